@@ -1,0 +1,275 @@
+/*
+ * gs.h — C ABI of libgsmi: one partition's 3D Gaussian Splatting training
+ * step on an MI355X (gfx950).
+ *
+ * The paper (Han et al., "Distributed 3D Gaussian Splatting for
+ * High-Resolution Isosurface Visualization", Sec. II, "Parallel Training")
+ * trains each data partition independently with the 3D-GS method of Kerbl
+ * et al.; the calls below are the steps of that training step:
+ *
+ *   gs_project     -> 3D Gaussian to 2D conic (EWA splatting Jacobian)
+ *   gs_bin_sort    -> tile binning + stable radix sort on (image, tile, depth)
+ *   gs_raster_fwd  -> front-to-back alpha compositing per pixel
+ *   gs_loss        -> background-masked L1 + D-SSIM loss and its image gradient
+ *                     (masks: Sec. II "Image Rendering and Masking", Sec. III-A)
+ *   gs_raster_bwd  -> reverse-order replay of the compositing (gradients)
+ *   gs_project_bwd -> chain rule back to the Gaussian parameters
+ *   gs_adam        -> Adam update of all parameters
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns gs_status (GS_OK = 0, negative = error) and never
+ *   aborts.  gs_last_error() returns a thread-local message for the last
+ *   failure on the calling thread.
+ * - Argument validation happens on the host before anything is enqueued: a
+ *   call that returns GS_ERR_ARG has launched nothing.
+ * - All buffers marked "device" are caller-owned device memory.  The library
+ *   allocates no device memory in any call; calls that need scratch space
+ *   take a caller-owned workspace sized by the matching *_workspace_bytes().
+ * - Every call enqueues its kernels on `stream` (a hipStream_t; NULL = the
+ *   null stream) and returns without synchronising.  Only gs_check_status()
+ *   synchronises the stream.
+ * - Float arrays are fp32.  Per-Gaussian arrays are planar SoA "[C][n]":
+ *   component c of Gaussian i lives at ptr[c*n + i].
+ * - Images are planar [S][3][H][W] fp32, masks [S][H][W] u8 (0 = background),
+ *   per-pixel state [S][H][W].  Pixel (x, y) has its centre at (x+0.5, y+0.5).
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GS_OK = 0,
+  GS_ERR_ARG = -1,         /* invalid argument; nothing was enqueued            */
+  GS_ERR_HIP = -2,         /* a HIP runtime call or kernel launch failed        */
+  GS_ERR_CAPACITY = -3,    /* the duplicate list outgrew dup_capacity           */
+  GS_ERR_NONFINITE = -4,   /* a loss value or parameter update was not finite   */
+  GS_ERR_UNSUPPORTED = -5  /* the request is valid but not implemented          */
+} gs_status;
+
+/* Pinhole camera in OpenCV axes (x right, y down, z forward).
+ * A world point X maps to camera space as x_c = R X + t (R row-major).
+ * Pixel coordinates: u = fx x_c/z_c + cx, v = fy y_c/z_c + cy.          */
+typedef struct {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float znear;              /* points with z_c <= znear are culled          */
+  int32_t width, height;    /* must equal the call's gs_tiling width/height */
+  int32_t reserved;
+} gs_camera;                /* 80 bytes */
+
+/* The Gaussians of one or more partitions, planar SoA, read-only.
+ *   mean [3][n], log_scale [3][n], quat [4][n] as (w, x, y, z) (any norm > 0),
+ *   opacity_logit [n], color [3][n] (degree-0 spherical-harmonic coefficient;
+ *   the rendered colour is max(0, C0*color + 1/2), C0 = 1/(2 sqrt(pi))).   */
+typedef struct {
+  const float* mean;
+  const float* log_scale;
+  const float* quat;
+  const float* opacity_logit;
+  const float* color;
+  int64_t n;
+} gs_gaussians;
+
+/* Gradients with respect to the gs_gaussians fields, same layout.         */
+typedef struct {
+  float* mean;
+  float* log_scale;
+  float* quat;
+  float* opacity_logit;
+  float* color;
+  int64_t n;
+} gs_grads;
+
+/* The images ("slots") one call renders.  Slot s draws Gaussians
+ * [gauss_offset[s], gauss_offset[s] + pair_offset[s+1] - pair_offset[s])
+ * through camera cams[s]; its (Gaussian, slot) pairs are numbered
+ * pair_offset[s] .. pair_offset[s+1]-1.  One partition seen from V views is
+ * pair_offset = {0, n, 2n, ..., Vn}, gauss_offset = {0, ..., 0}.  Several
+ * partitions of one concatenated Gaussian array batch by giving each slot its
+ * partition's offset.  All three arrays live in device memory; n_slots is
+ * at most GS_MAX_SLOTS and total_pairs must equal pair_offset[n_slots].   */
+#define GS_MAX_SLOTS 1024
+typedef struct {
+  int32_t n_slots;
+  int64_t total_pairs;
+  const int64_t* pair_offset;   /* device [n_slots + 1], pair_offset[0] = 0 */
+  const int64_t* gauss_offset;  /* device [n_slots]                         */
+  const gs_camera* cams;        /* device [n_slots]                         */
+} gs_views;
+
+/* Image geometry of a call: every slot is width x height pixels, binned in
+ * tile_w x tile_h tiles (tile_w * tile_h <= 1024; tiles_x = ceil(W/tile_w)).*/
+typedef struct {
+  int32_t width, height;
+  int32_t tile_w, tile_h;
+} gs_tiling;
+
+/* Projected record of one (Gaussian, slot) pair, 12 fp32 per pair
+ * ("rec[m][12]", 48 bytes, 16-byte aligned):
+ *   [0..1] mean2d (pixels)     [2..4] conic Q11, Q12, Q22 (inverse of the
+ *   dilated 2D covariance)     [5] opacity   [6..8] rgb   [9] depth (z_c)
+ *   [10] slot index (int32 bits)              [11] reserved (0)
+ * tile_bbox [m][4] u16 holds the inclusive tile range (tx0, ty0, tx1, ty1);
+ * n_tiles [m] is (tx1-tx0+1)(ty1-ty0+1), or 0 for a culled pair.           */
+#define GS_REC_STRIDE 12
+typedef struct {
+  float* rec;
+  uint16_t* tile_bbox;
+  int32_t* n_tiles;
+  int64_t m;
+} gs_projected;
+
+/* Gradient of the loss with respect to each pair's projected record,
+ * 9 fp32 per pair ("d_rec[m][9]"): d mean2d (2), d conic (3) in the same
+ * Q11, Q12, Q22 parameterisation, d opacity, d rgb (3).                    */
+#define GS_DREC_STRIDE 9
+
+/* Device status block written by gs_bin_sort / gs_loss / gs_adam:
+ *   status[0]  bit flags: 1 = duplicate overflow, 2 = non-finite loss
+ *   status[1]  duplicates required by the last gs_bin_sort
+ *   status[2..3] reserved.  The caller zeroes it once (gs_zero).           */
+#define GS_STATUS_WORDS 4
+#define GS_FLAG_CAPACITY 1
+#define GS_FLAG_NONFINITE 2
+
+/* ------------------------------------------------------------------------ */
+
+/* Project every (Gaussian, slot) pair of `views` (3D-GS method cited in
+ * Sec. I/II; EWA splatting).  Per pair:
+ *   s = exp(log_scale), q^ = q/|q|, o = sigmoid(opacity_logit),
+ *   rgb = max(0, C0 color + 1/2);  Sigma = R(q^) diag(s)^2 R(q^)^T;
+ *   t = R_v mu + t_v (culled if t_z <= znear);  mean2d = (fx t_x/t_z + cx,
+ *   fy t_y/t_z + cy);  Jacobian J of the perspective map with t_x/t_z and
+ *   t_y/t_z clamped to 1.3 * W/(2 fx) resp. 1.3 * H/(2 fy);
+ *   Sigma2 = J R_v Sigma R_v^T J^T + 0.3 I;  conic = Sigma2^{-1};
+ *   support = {d : d^T conic d <= 2 ln(255 o)} (where alpha >= 1/255),
+ *   culled if 255 o <= 1;  pixel bbox = [floor(m -/+ h) -/+ 1] clamped to
+ *   the image, h = sqrt(2 ln(255 o) diag(Sigma2));  tile bbox from it.
+ * out->m must equal views->total_pairs.  Culled pairs get n_tiles = 0.     */
+gs_status gs_project(const gs_gaussians* g, const gs_views* views,
+                     const gs_tiling* tiling, gs_projected* out, void* stream);
+
+/* Workspace for gs_bin_sort with m pairs and room for dup_capacity
+ * duplicates (one per (pair, overlapped tile)).                            */
+size_t gs_bin_sort_workspace_bytes(int64_t m, int64_t dup_capacity,
+                                   const gs_tiling* tiling, int32_t n_slots);
+
+/* Tile binning and sorting.  Each pair emits one entry per tile of its tile
+ * bbox with key ((slot * tiles_per_slot + ty * tiles_x + tx) << 32) |
+ * bits(depth) and value = pair index; entries are sorted stably by key, so
+ * equal keys keep ascending pair index.  Outputs (device):
+ *   keys_out [dup_capacity] u64, ids_out [dup_capacity] u32 (sorted),
+ *   tile_ranges [n_slots * tiles_per_slot][2] u32: [start, end) into ids_out
+ *   (start = end = 0 for an empty tile).
+ * The true duplicate count is written to status[1]; when it exceeds
+ * dup_capacity, GS_FLAG_CAPACITY is set, the list is truncated to the first
+ * dup_capacity entries in pair order and the ranges are NOT meaningful: the
+ * caller detects it with gs_check_status, grows the buffers and reruns.    */
+gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views,
+                      const gs_tiling* tiling, int64_t dup_capacity,
+                      void* ws, size_t ws_bytes, uint64_t* keys_out,
+                      uint32_t* ids_out, uint32_t* tile_ranges,
+                      int64_t* status, void* stream);
+
+/* Front-to-back compositing (3D-GS rasteriser).  For each pixel p of each
+ * slot, over its tile's sorted list: power = -1/2 d^T conic d with
+ * d = p - mean2d (skipped if power > 0); alpha = min(0.99, o e^power),
+ * skipped if alpha < 1/255; the loop stops before a Gaussian whose blend
+ * would take the transmittance T below 1e-4; C += rgb alpha T,
+ * T *= (1 - alpha).  image = C + T bg.
+ * Outputs (device): image [S][3][H][W]; T_final [S][H][W] and n_contrib
+ * [S][H][W] (list position after the last blended entry), both optional
+ * (NULL) when the backward will run in recompute mode.  bg: 3 host floats. */
+gs_status gs_raster_fwd(const gs_projected* proj, const gs_views* views,
+                        const gs_tiling* tiling, const uint32_t* ids,
+                        const uint32_t* tile_ranges, const float bg[3],
+                        float* image, float* T_final, int32_t* n_contrib,
+                        void* stream);
+
+#define GS_BWD_STORED 0     /* use T_final / n_contrib from the forward      */
+#define GS_BWD_RECOMPUTE 1  /* replay the forward per tile to recover them   */
+
+/* Reverse-order replay of the compositing: the exact derivative of
+ * gs_raster_fwd with every skip/stop/clamp decision held fixed (the
+ * derivative through a clamped alpha is zero).  d_image [S][3][H][W] is
+ * dL/d(image).  Accumulates (+=) into d_rec [m][9] (caller zeroes it).
+ * mode GS_BWD_STORED needs T_final and n_contrib; GS_BWD_RECOMPUTE ignores
+ * them (may be NULL).                                                      */
+gs_status gs_raster_bwd(const gs_projected* proj, const gs_views* views,
+                        const gs_tiling* tiling, const uint32_t* ids,
+                        const uint32_t* tile_ranges, const float bg[3],
+                        const float* T_final, const int32_t* n_contrib,
+                        const float* d_image, int32_t mode, float* d_rec,
+                        void* stream);
+
+/* Chain rule from d_rec back to the Gaussian parameters (sum over every
+ * slot that draws the Gaussian), accumulating (+=) into grads.  Depth, the
+ * support and the bboxes carry no gradient.  Deterministic (no atomics).   */
+gs_status gs_project_bwd(const gs_gaussians* g, const gs_views* views,
+                         const gs_tiling* tiling, const gs_projected* proj,
+                         const float* d_rec, gs_grads* grads, void* stream);
+
+size_t gs_loss_workspace_bytes(int32_t S, int32_t H, int32_t W);
+
+/* Background-masked photometric loss per image s (Sec. II masks):
+ *   I^ = M image, G^ = M target (M broadcast over rgb; mask NULL = all 1),
+ *   L1 = mean |I^ - G^| over 3HW,  SSIM = mean over 3HW of the SSIM map with
+ *   an 11x11 Gaussian window (sigma 1.5), zero padding, C1 = 0.01^2,
+ *   C2 = 0.03^2;  loss[s] = (1 - lambda) L1 + lambda (1 - SSIM).
+ * Writes loss_out [S] (device) and d_image [S][3][H][W] = grad_scale *
+ * dloss[s]/d(image) (sign(0) = 0 in the L1 subgradient).  A non-finite loss
+ * sets GS_FLAG_NONFINITE in status (may be NULL).                          */
+gs_status gs_loss(const float* image, const float* target,
+                  const uint8_t* mask, int32_t S, int32_t H, int32_t W,
+                  float lambda_dssim, float grad_scale, void* ws,
+                  size_t ws_bytes, float* loss_out, float* d_image,
+                  int64_t* status, void* stream);
+
+/* One parameter group of gs_adam: count fp32 elements at param/grad/m/v.  */
+typedef struct {
+  float* param;
+  float* grad;
+  float* m;
+  float* v;
+  int64_t count;
+  float lr;
+} gs_adam_group;
+#define GS_MAX_ADAM_GROUPS 8
+
+/* Adam with bias correction, dense over every element (step counts from 1):
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   param -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * groups: host array of n_groups (<= GS_MAX_ADAM_GROUPS).  zero_grad != 0
+ * clears each grad after reading it.                                      */
+gs_status gs_adam(const gs_adam_group* groups, int32_t n_groups, float beta1,
+                  float beta2, float eps, int32_t step, int32_t zero_grad,
+                  void* stream);
+
+/* Fill `bytes` bytes at device pointer `ptr` with zero using a kernel (safe
+ * to capture in a HIP graph).  bytes must be a multiple of 4.             */
+gs_status gs_zero(void* ptr, size_t bytes, void* stream);
+
+/* Synchronise `stream`, read the status block and report:
+ * GS_ERR_CAPACITY (required duplicates in *required_out), GS_ERR_NONFINITE,
+ * or GS_OK.  required_out may be NULL.                                    */
+gs_status gs_check_status(const int64_t* status, void* stream,
+                          int64_t* required_out);
+
+/* Thread-local text of the last error ("" if none).                        */
+const char* gs_last_error(void);
+
+/* Library version string.                                                  */
+const char* gs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GS_H */

@@ -1,0 +1,301 @@
+"""FP64 CPU oracle of one 3D Gaussian Splatting training step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package.  It shares no
+code with the GPU library ``paper_2509_12138_amd`` and never imports it.
+
+The heavy definitions (projection, per-pixel compositing and its analytic
+backward, projection backward, tile binning + sort, masked L1 + D-SSIM, brute
+force k-NN) are plain C in ``gs_oracle.c``; Adam and the initialisation MLP
+are plain numpy below.  Everything is FP64.  Which passage each function
+follows is stated in its docstring; the paper itself (Sec. II) delegates the
+training step to the 3D-GS method it cites, so the oracle restates that
+method's standard definitions.
+
+Parity pins: every function here is pinned by a CPU test against closed
+forms, finite differences, brute force or library routines; the MLP
+(``mlp_*``) is pinned by finite differences and the zero-weight special case.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gs_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+C0 = 0.28209479177387814  # degree-0 SH basis constant 1/(2 sqrt(pi))
+
+
+def build(force: bool = False) -> str:
+    """Compile gs_oracle.c with gcc (FP64, OpenMP) into liboracle.so."""
+    if force or not os.path.exists(_LIB_PATH) or (
+        os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)
+    ):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+               "-Wall", "-Wno-misleading-indentation", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_LIB_PATH)
+            lib.or_bin_sort.restype = ctypes.c_int64
+            lib.or_max_threads.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def max_threads() -> int:
+    return int(_load().or_max_threads())
+
+
+def camera_vector(cam):
+    """(16 doubles R, t, fx, fy, cx, cy; znear; W; H) from a camera record."""
+    v = np.concatenate([np.asarray(cam["R"], np.float64).ravel(),
+                        np.asarray(cam["t"], np.float64).ravel(),
+                        np.array([cam["fx"], cam["fy"], cam["cx"], cam["cy"]],
+                                 np.float64)])
+    return v, float(cam["znear"]), int(cam["width"]), int(cam["height"])
+
+
+# --------------------------------------------------------------------------
+# Projection (EWA splatting step of the 3D-GS method)
+# --------------------------------------------------------------------------
+
+def project(params, cam, tile=(16, 16)):
+    """Project every Gaussian through one camera (3D-GS projection step).
+
+    params: dict of planar SoA arrays mean [3,n], log_scale [3,n], quat [4,n],
+    opacity_logit [n], color [3,n].  Returns a dict of FP64 SoA outputs plus
+    integer pixel/tile bboxes [4,n] (tx0, ty0, tx1, ty1), n_tiles and valid.
+    """
+    lib = _load()
+    mean = _f64(params["mean"]); n = mean.shape[1]
+    ls = _f64(params["log_scale"]); q = _f64(params["quat"])
+    ol = _f64(params["opacity_logit"]); col = _f64(params["color"])
+    cv, znear, W, H = camera_vector(cam)
+    out = dict(mean2d=np.zeros((2, n)), conic=np.zeros((3, n)), depth=np.zeros(n),
+               opacity=np.zeros(n), rgb=np.zeros((3, n)), cov2d=np.zeros((3, n)),
+               pix_bbox=np.zeros((4, n), np.int32), tile_bbox=np.zeros((4, n), np.int32),
+               n_tiles=np.zeros(n, np.int32), valid=np.zeros(n, np.int32))
+    lib.or_project(ctypes.c_int64(n), _p(mean), _p(ls), _p(q), _p(ol), _p(col), _p(cv),
+                   ctypes.c_double(znear), ctypes.c_int(W), ctypes.c_int(H),
+                   ctypes.c_int(tile[0]), ctypes.c_int(tile[1]),
+                   _p(out["mean2d"]), _p(out["conic"]), _p(out["depth"]), _p(out["opacity"]),
+                   _p(out["rgb"]), _p(out["cov2d"]), _p(out["pix_bbox"]), _p(out["tile_bbox"]),
+                   _p(out["n_tiles"]), _p(out["valid"]))
+    return out
+
+
+def _proj_arrays(proj):
+    n = proj["depth"].shape[0]
+    valid = np.ascontiguousarray(proj.get("valid", proj["n_tiles"] > 0), dtype=np.int32)
+    tb = np.ascontiguousarray(proj["tile_bbox"], dtype=np.int32)
+    if tb.shape == (n, 4) and n != 4:
+        tb = np.ascontiguousarray(tb.T)
+    return (n, _f64(proj["mean2d"]), _f64(proj["conic"]), _f64(proj["depth"]),
+            _f64(proj["opacity"]), _f64(proj["rgb"]), tb, valid)
+
+
+def render(proj, W, H, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None):
+    """Composite every pixel front to back (3D-GS rasteriser definition).
+
+    proj holds SoA mean2d [2,n], conic [3,n], depth, opacity, rgb [3,n],
+    tile_bbox [4,n] and valid (or n_tiles).  window = (x0, y0, x1, y1).
+    Returns image [3,H,W], T_final, n_contrib, n_blended, ambiguous ([H,W]);
+    pixels outside the window are left zero.
+    """
+    lib = _load()
+    n, m2, cn, dp, op, rgb, tb, valid = _proj_arrays(proj)
+    x0, y0, x1, y1 = window if window is not None else (0, 0, W, H)
+    img = np.zeros((3, H, W)); T = np.zeros((H, W)); nc = np.zeros((H, W), np.int32)
+    nb = np.zeros((H, W), np.int32); amb = np.zeros((H, W), np.uint8)
+    bgv = _f64(bg)
+    lib.or_render(ctypes.c_int64(n), _p(m2), _p(cn), _p(dp), _p(op), _p(rgb), _p(tb), _p(valid),
+                  W, H, tile[0], tile[1], _p(bgv), x0, y0, x1, y1, _p(img), _p(T), _p(nc),
+                  _p(nb), _p(amb))
+    return dict(image=img, T_final=T, n_contrib=nc, n_blended=nb, ambiguous=amb.astype(bool))
+
+
+def render_bwd(proj, W, H, d_image, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None):
+    """Analytic backward of ``render`` with all decisions held fixed.
+
+    Returns per-Gaussian SoA gradients d_mean2d [2,n], d_conic [3,n],
+    d_opacity [n], d_rgb [3,n] and abs_mass / amb_mass [9,n] (sum of absolute
+    per-pixel contributions, all pixels / ambiguous pixels only).
+    """
+    lib = _load()
+    n, m2, cn, dp, op, rgb, tb, valid = _proj_arrays(proj)
+    x0, y0, x1, y1 = window if window is not None else (0, 0, W, H)
+    dI = _f64(d_image)
+    out = dict(d_mean2d=np.zeros((2, n)), d_conic=np.zeros((3, n)), d_opacity=np.zeros(n),
+               d_rgb=np.zeros((3, n)), abs_mass=np.zeros((9, n)), amb_mass=np.zeros((9, n)))
+    bgv = _f64(bg)
+    lib.or_render_bwd(ctypes.c_int64(n), _p(m2), _p(cn), _p(dp), _p(op), _p(rgb), _p(tb),
+                      _p(valid), W, H, tile[0], tile[1], _p(bgv), x0, y0, x1, y1, _p(dI),
+                      _p(out["d_mean2d"]), _p(out["d_conic"]), _p(out["d_opacity"]),
+                      _p(out["d_rgb"]), _p(out["abs_mass"]), _p(out["amb_mass"]))
+    return out
+
+
+def project_bwd(params, cam, grads2d, tile=(16, 16)):
+    """Chain rule from the projected outputs back to the parameters."""
+    lib = _load()
+    mean = _f64(params["mean"]); n = mean.shape[1]
+    ls = _f64(params["log_scale"]); q = _f64(params["quat"])
+    ol = _f64(params["opacity_logit"]); col = _f64(params["color"])
+    cv, znear, W, H = camera_vector(cam)
+    g = dict(mean=np.zeros((3, n)), log_scale=np.zeros((3, n)), quat=np.zeros((4, n)),
+             opacity_logit=np.zeros(n), color=np.zeros((3, n)))
+    lib.or_project_bwd(ctypes.c_int64(n), _p(mean), _p(ls), _p(q), _p(ol), _p(col), _p(cv),
+                       ctypes.c_double(znear), W, H, tile[0], tile[1],
+                       _p(_f64(grads2d["d_mean2d"])), _p(_f64(grads2d["d_conic"])),
+                       _p(_f64(grads2d["d_opacity"])), _p(_f64(grads2d["d_rgb"])),
+                       _p(g["mean"]), _p(g["log_scale"]), _p(g["quat"]), _p(g["opacity_logit"]),
+                       _p(g["color"]))
+    return g
+
+
+# --------------------------------------------------------------------------
+# Binning + sort
+# --------------------------------------------------------------------------
+
+def bin_sort(tile_bbox, n_tiles, depth_f32, slot, tiles_x, tiles_per_slot, n_slots):
+    """Emit (tile, depth) keys per pair and sort them stably (plain definition).
+
+    tile_bbox [m,4] pair-major (tx0, ty0, tx1, ty1); depth_f32 float32 [m]
+    (its raw bits form the low key word).  Returns keys u64, ids u32 and
+    ranges u32 [n_slots*tiles_per_slot, 2].
+    """
+    lib = _load()
+    tb = np.ascontiguousarray(tile_bbox, dtype=np.int32).reshape(-1, 4)
+    m = tb.shape[0]
+    nt = np.ascontiguousarray(n_tiles, dtype=np.int32)
+    db = np.ascontiguousarray(np.asarray(depth_f32, dtype=np.float32).view(np.uint32))
+    sl = np.ascontiguousarray(slot, dtype=np.int32)
+    total = int(np.maximum(nt, 0).sum())
+    keys = np.zeros(max(total, 1), np.uint64); ids = np.zeros(max(total, 1), np.uint32)
+    ranges = np.zeros((n_slots * tiles_per_slot, 2), np.uint32)
+    got = lib.or_bin_sort(ctypes.c_int64(m), _p(tb), _p(nt), _p(db), _p(sl), tiles_x,
+                          tiles_per_slot, n_slots, ctypes.c_int64(total), _p(keys), _p(ids),
+                          _p(ranges))
+    assert got == total
+    return keys[:total], ids[:total], ranges
+
+
+# --------------------------------------------------------------------------
+# Loss
+# --------------------------------------------------------------------------
+
+def loss(image, target, mask=None, lam=0.2):
+    """Masked (1-lam) L1 + lam (1 - SSIM) of one [3,H,W] image and its gradient."""
+    lib = _load()
+    img = _f64(image); tgt = _f64(target)
+    H, W = img.shape[1], img.shape[2]
+    mk = _f64(mask) if mask is not None else None
+    L = ctypes.c_double(); l1 = ctypes.c_double(); ss = ctypes.c_double()
+    dI = np.zeros_like(img); smap = np.zeros_like(img)
+    lib.or_loss(_p(img), _p(tgt), _p(mk), H, W, ctypes.c_double(lam), ctypes.byref(L),
+                ctypes.byref(l1), ctypes.byref(ss), _p(dI), _p(smap))
+    return dict(loss=L.value, l1=l1.value, ssim=ss.value, d_image=dI, ssim_map=smap)
+
+
+# --------------------------------------------------------------------------
+# Adam (dense, bias-corrected)
+# --------------------------------------------------------------------------
+
+def adam(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15):
+    """One Adam step (Kingma & Ba, Alg. 1) in FP64; returns new (param, m, v)."""
+    param = np.asarray(param, np.float64); grad = np.asarray(grad, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * grad
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * grad * grad
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    return param - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+# --------------------------------------------------------------------------
+# k nearest neighbours
+# --------------------------------------------------------------------------
+
+def knn(points, k):
+    """Brute-force k nearest other points of each point, sorted by (distance, index).
+
+    points [3,n]; returns idx [n,k] int32 and dist [n,k] float64.
+    """
+    if not 1 <= k <= 64:
+        raise ValueError("k must be in [1, 64]")
+    lib = _load()
+    pts = _f64(points); n = pts.shape[1]
+    idx = np.zeros((n, k), np.int32); dist = np.zeros((n, k))
+    lib.or_knn(ctypes.c_int64(n), _p(pts), k, _p(idx), _p(dist))
+    return idx, dist
+
+
+# --------------------------------------------------------------------------
+# Initialisation MLP (plain numpy, FP64, optional bf16 rounding)
+# --------------------------------------------------------------------------
+
+def bf16_round(x):
+    """Round FP64 values to the nearest bfloat16 (ties to even), returned as FP64."""
+    f = np.asarray(x, np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(np.isnan(f), np.nan, out)
+
+
+def mlp_forward(x, W1, b1, W2, b2, W3, b3, quantize=True):
+    """y = W3^T relu(W2^T relu(W1^T x + b1) + b2) + b3, row-major batches.
+
+    x [n,96]; W1 [96,64], W2 [64,64], W3 [64,8]; biases FP32-valued.  With
+    quantize, x, the weights and both hidden activations are rounded to bf16
+    exactly where the GPU stores them in bf16.  Returns y and the cache.
+    """
+    q = bf16_round if quantize else (lambda a: np.asarray(a, np.float64))
+    xq = q(x); W1q = q(W1); W2q = q(W2); W3q = q(W3)
+    z1 = xq @ W1q + b1
+    h1 = q(np.maximum(z1, 0.0))
+    z2 = h1 @ W2q + b2
+    h2 = q(np.maximum(z2, 0.0))
+    y = h2 @ W3q + b3
+    return y, dict(x=xq, W1=W1q, W2=W2q, W3=W3q, z1=z1, h1=h1, z2=z2, h2=h2)
+
+
+def mlp_backward(cache, dy):
+    """Gradients of the MLP for upstream dy [n,8] (ReLU derivative 0 at 0)."""
+    dW3 = cache["h2"].T @ dy
+    db3 = dy.sum(0)
+    dh2 = dy @ cache["W3"].T
+    dz2 = dh2 * (cache["z2"] > 0)
+    dW2 = cache["h1"].T @ dz2
+    db2 = dz2.sum(0)
+    dh1 = dz2 @ cache["W2"].T
+    dz1 = dh1 * (cache["z1"] > 0)
+    dW1 = cache["x"].T @ dz1
+    db1 = dz1.sum(0)
+    dx = dz1 @ cache["W1"].T
+    return dict(W1=dW1, b1=db1, W2=dW2, b2=db2, W3=dW3, b3=db3, x=dx)

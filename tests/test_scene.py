@@ -1,0 +1,50 @@
+"""Input generators: surface samples lie on f = 0, cameras look at the origin."""
+import numpy as np
+
+from paper_2509_12138_amd import scene
+
+
+def test_sphere_sines_samples_on_surface():
+    pts, nrm = scene.sample_surface(scene.field_sphere_sines, 4096, 64, seed=1)
+    assert pts.shape == (4096, 3)
+    f, _ = scene.field_sphere_sines(pts)
+    assert np.max(np.abs(f)) <= 1e-6
+    np.testing.assert_allclose(np.linalg.norm(nrm, axis=1), 1.0, rtol=1e-12)
+    # outward normals on a sphere-like surface
+    assert np.mean(np.sum(nrm * pts, 1) > 0) > 0.99
+    # seeded: same seed, same points
+    pts2, _ = scene.sample_surface(scene.field_sphere_sines, 4096, 64, seed=1)
+    np.testing.assert_array_equal(pts, pts2)
+
+
+def test_box_restricted_sampling():
+    box = (np.array([0.0, 0.0, 0.0]), np.array([1.0, 1.0, 1.0]))
+    pts, _ = scene.sample_surface(scene.field_sphere_sines, 2000, 128, seed=3, box=box)
+    assert np.all(pts >= 0) and len(pts) == 2000
+
+
+def test_mixing_interface_samples():
+    mi = scene.MixingInterface(seed=2)
+    assert abs(mi.A.sum() - 0.25) < 1e-12 and len(mi.A) == 32
+    pts, nrm = mi.sample(20000, seed=4)
+    assert pts.shape == (20000, 3)
+    np.testing.assert_allclose(np.linalg.norm(nrm, axis=1), 1.0, rtol=1e-9)
+    layer = np.abs(pts[:, 2] - mi.height(pts[:, :2])) < 1e-12
+    assert layer.mean() > 0.5
+
+
+def test_orbit_cameras_look_at_origin():
+    cams = scene.orbit_cameras(16, 128, 96)
+    for c in cams:
+        R = c["R"].reshape(3, 3).astype(np.float64)
+        np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-6)
+        assert abs(np.linalg.det(R) - 1) < 1e-6
+        o = R @ np.zeros(3) + c["t"]             # origin in camera space
+        assert abs(o[0]) < 1e-5 and abs(o[1]) < 1e-5 and abs(o[2] - 2.5) < 1e-5
+    assert abs(cams[0]["fx"] - 64 / np.tan(np.radians(25))) < 1e-3
+
+
+def test_views_table():
+    po, go = scene.views_table([5, 3], 2)
+    np.testing.assert_array_equal(po, [0, 5, 10, 13, 16])
+    np.testing.assert_array_equal(go, [0, 0, 5, 5])
