@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark: one partition's 3D-GS training step on one MI355X.
+
+Workload (the realistic single-partition configuration): a
+Richtmyer-Meshkov-like mixing-layer isosurface with 1M FP32 Gaussians (SH
+degree 0), 64 orbital views at 1920x1080 with background masks, batch of one
+view per step.  A step runs the whole hot path through libgsmi:
+project -> bin/sort -> raster fwd -> masked L1 + D-SSIM -> raster bwd ->
+project bwd -> Adam.
+
+Prints ONE JSON line.  value = fwd+bwd raster Mpix/s (pixels of a step's
+image over the summed durations of the two rasteriser launches, HIP events
+on the launch stream); ms_per_step / iters_per_s cover the whole step.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd raster Mpix/s; train iters/s at 1080p; secs to 35 dB PSNR vs plain"
+PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9          # FP32 lane-ops/s without packed math
+PEAK_HBM = 8.0e12
+# algorithmic VALU issue slots per evaluated (pixel, list entry) pair
+# (transcendentals count 4); see the design notes for the derivation
+OPS_PER_EVAL_FWD = 22
+OPS_PER_EVAL_BWD = 50
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--recompute", action="store_true")
+    ap.add_argument("--small", action="store_true", help="tiny config (smoke use)")
+    return ap.parse_args()
+
+
+def cpu_baseline(params, cam, target_seconds):
+    """Time the FP64 oracle's raster forward + backward on a pixel window of
+    the same view (a bounded sample of the workload)."""
+    import oracle
+    from paper_2509_12138_amd import scene
+    camd = scene.camera_dict(cam)
+    W, H = int(cam["width"]), int(cam["height"])
+    t0 = time.perf_counter()
+    proj = oracle.project(params, camd)
+    t_proj = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    d_image = rng.normal(size=(3, H, W))
+
+    def run(side):
+        x0, y0 = W // 2 - side // 2, H // 2 - side // 2
+        win = (x0, y0, x0 + side, y0 + side)
+        t = time.perf_counter()
+        oracle.render(proj, W, H, window=win)
+        oracle.render_bwd(proj, W, H, d_image, window=win)
+        return time.perf_counter() - t
+
+    side = 16
+    dt = run(side)
+    # scale the window so the timed sample takes about target_seconds
+    per_px = dt / (side * side)
+    side = int(max(16, min(512, (target_seconds / max(per_px, 1e-9)) ** 0.5)))
+    dt = run(side)
+    return {
+        "value": (side * side) / dt / 1e6,
+        "unit": "Mpix/s",
+        "cores": oracle.max_threads(),
+        "kind": "oracle",
+        "sample": f"raster fwd+bwd of a {side}x{side} pixel window at the centre of view 0 "
+                  f"(1920x1080, all {params['opacity_logit'].shape[0]} Gaussians; "
+                  f"FP64 projection {t_proj:.2f}s not included), {dt:.1f}s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X (no GPU visible)", file=sys.stderr)
+        sys.exit(3)
+    from paper_2509_12138_amd import _lib, workloads
+    from paper_2509_12138_amd.train import PlainTrainer
+    _lib.load()
+    tile = tuple(int(x) for x in args.tile.split("x"))
+    cfg = dict(n=20000, n_ref=80000, views=8, width=320, height=180) if args.small else None
+    t0 = time.perf_counter()
+    wl = workloads.realistic_partition(cfg)
+    log(f"scene built in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    targets, masks = workloads.render_targets_gpu(wl["reference"], wl["cams"])
+    log(f"targets rendered in {time.perf_counter() - t0:.1f}s; mask coverage "
+        f"{float(masks.float().mean()):.3f}")
+    cfgd = wl["cfg"]
+    W, H = cfgd["width"], cfgd["height"]
+    tr = PlainTrainer(wl["params"], wl["cams"], targets, masks, tile=tile, stored=not args.recompute)
+    need = tr.fit_capacity()
+    log(f"max duplicates per view {need}, capacity {tr.bufs.dup_capacity}")
+    rng = np.random.default_rng(1000 + 2)
+    order = rng.permutation(np.arange(10 ** 6) % len(wl["cams"]))
+    for s in range(args.warmup):
+        tr.step(int(order[s]))
+    tr.check()
+    torch.cuda.synchronize()
+    tr.timing = {}
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        tr.step(int(order[args.warmup + s]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tr.check()
+    ev = tr.timing
+    names = ["project", "bin_sort", "raster_fwd", "loss", "zero", "raster_bwd", "project_bwd", "adam", "end"]
+    stage_ms = {}
+    for a, b in zip(names[:-1], names[1:]):
+        stage_ms[a] = float(np.mean([x.elapsed_time(y) for x, y in zip(ev[a], ev[b])]))
+    tr.timing = None
+    t_fwd, t_bwd = stage_ms["raster_fwd"], stage_ms["raster_bwd"]
+    ms_per_step = wall * 1000.0 / args.steps
+    mpix = W * H / ((t_fwd + t_bwd) * 1e-3) / 1e6
+
+    # algorithmic evaluation counts of the last step's view (replayed once, untimed)
+    last_view = int(order[args.warmup + args.steps - 1])
+    tr.views.use_cameras(tr.cams[last_view:last_view + 1])
+    tr.bufs.render_checked(tr.gst, tr.bg)
+    import torch as _t
+    nc = tr.bufs.n_contrib[0].to(_t.int64)
+    evals_bwd = float(nc.sum())
+    rng_t = tr.bufs.ranges.to(_t.int64)
+    tile_len = (rng_t[:, 1] - rng_t[:, 0])
+    tx = (_t.arange(W, device="cuda") // tile[0])
+    ty = (_t.arange(H, device="cuda") // tile[1])
+    tid = ty[:, None] * tr.bufs.tiles_x + tx[None, :]
+    T = tr.bufs.T_final[0]
+    # forward: pixels that stopped evaluated n_contrib+1 entries (at most the
+    # list), the others the whole tile list
+    stopped = T < 2e-4
+    evals_fwd = float(_t.where(stopped, _t.minimum(nc + 1, tile_len[tid]), tile_len[tid]).sum())
+    dom = "raster_bwd" if t_bwd >= max(v for k, v in stage_ms.items() if k != "raster_bwd") else \
+        max(stage_ms, key=stage_ms.get)
+    if dom == "raster_bwd":
+        achieved = evals_bwd * OPS_PER_EVAL_BWD / (t_bwd * 1e-3)
+        roof = {"kernel": "k_raster_bwd", "bound": "alu", "achieved": achieved / 1e12,
+                "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
+                "traffic": None, "units_per_launch": evals_bwd,
+                "unit_desc": f"{OPS_PER_EVAL_BWD} FP32 VALU issue slots per evaluated (pixel, entry)"}
+    else:
+        achieved = evals_fwd * OPS_PER_EVAL_FWD / (t_fwd * 1e-3)
+        roof = {"kernel": "k_raster_fwd", "bound": "alu", "achieved": achieved / 1e12,
+                "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
+                "traffic": None, "units_per_launch": evals_fwd,
+                "unit_desc": f"{OPS_PER_EVAL_FWD} FP32 VALU issue slots per evaluated (pixel, entry)"}
+    out = {
+        "metric": METRIC,
+        "value": round(mpix, 3),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "iters_per_s": round(1000.0 / ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"single partition: mixing-layer isosurface, {cfgd['n']} Gaussians (SH 0), "
+                        f"{cfgd['views']} orbital views at {W}x{H}, masks, batch 1 view",
+            "tile": f"{tile[0]}x{tile[1]}",
+            "backward": "recompute" if args.recompute else "stored",
+            "duplicates_per_view": need,
+        },
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "evals": {"fwd": evals_fwd, "bwd": evals_bwd},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(wl["params"], wl["cams"][0], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

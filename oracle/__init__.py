@@ -111,7 +111,8 @@ def project(params, cam, tile=(16, 16)):
 
 def _proj_arrays(proj):
     n = proj["depth"].shape[0]
-    valid = np.ascontiguousarray(proj.get("valid", proj["n_tiles"] > 0), dtype=np.int32)
+    valid = proj["valid"] if "valid" in proj else (np.asarray(proj["n_tiles"]) > 0)
+    valid = np.ascontiguousarray(valid, dtype=np.int32)
     tb = np.ascontiguousarray(proj["tile_bbox"], dtype=np.int32)
     if tb.shape == (n, 4) and n != 4:
         tb = np.ascontiguousarray(tb.T)
@@ -125,7 +126,9 @@ def render(proj, W, H, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None):
     proj holds SoA mean2d [2,n], conic [3,n], depth, opacity, rgb [3,n],
     tile_bbox [4,n] and valid (or n_tiles).  window = (x0, y0, x1, y1).
     Returns image [3,H,W], T_final, n_contrib, n_blended, ambiguous ([H,W]);
-    pixels outside the window are left zero.
+    pixels outside the window are left zero.  ``ambiguity`` holds the reason
+    bits of an ambiguous pixel: 1 power near 0, 2 alpha near 1/255, 4 alpha
+    near 0.99, 8 transmittance near the cut-off, 16 near-equal depths.
     """
     lib = _load()
     n, m2, cn, dp, op, rgb, tb, valid = _proj_arrays(proj)
@@ -136,15 +139,18 @@ def render(proj, W, H, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None):
     lib.or_render(ctypes.c_int64(n), _p(m2), _p(cn), _p(dp), _p(op), _p(rgb), _p(tb), _p(valid),
                   W, H, tile[0], tile[1], _p(bgv), x0, y0, x1, y1, _p(img), _p(T), _p(nc),
                   _p(nb), _p(amb))
-    return dict(image=img, T_final=T, n_contrib=nc, n_blended=nb, ambiguous=amb.astype(bool))
+    return dict(image=img, T_final=T, n_contrib=nc, n_blended=nb, ambiguous=amb.astype(bool),
+                ambiguity=amb)
 
 
-def render_bwd(proj, W, H, d_image, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None):
+def render_bwd(proj, W, H, d_image, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None,
+               amb_bits=31):
     """Analytic backward of ``render`` with all decisions held fixed.
 
     Returns per-Gaussian SoA gradients d_mean2d [2,n], d_conic [3,n],
     d_opacity [n], d_rgb [3,n] and abs_mass / amb_mass [9,n] (sum of absolute
-    per-pixel contributions, all pixels / ambiguous pixels only).
+    per-pixel contributions, all pixels / ambiguous pixels only; amb_bits
+    selects which ambiguity reasons of ``render`` count).
     """
     lib = _load()
     n, m2, cn, dp, op, rgb, tb, valid = _proj_arrays(proj)
@@ -156,7 +162,8 @@ def render_bwd(proj, W, H, d_image, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=No
     lib.or_render_bwd(ctypes.c_int64(n), _p(m2), _p(cn), _p(dp), _p(op), _p(rgb), _p(tb),
                       _p(valid), W, H, tile[0], tile[1], _p(bgv), x0, y0, x1, y1, _p(dI),
                       _p(out["d_mean2d"]), _p(out["d_conic"]), _p(out["d_opacity"]),
-                      _p(out["d_rgb"]), _p(out["abs_mass"]), _p(out["amb_mass"]))
+                      _p(out["d_rgb"]), _p(out["abs_mass"]), _p(out["amb_mass"]),
+                      ctypes.c_int(amb_bits))
     return out
 
 

@@ -224,21 +224,21 @@ static int64_t composite_pixel(int px, int py, int tw, int th, int64_t n, int64_
     double q11 = conic[g], q12 = conic[n + g], q22 = conic[2 * n + g];
     double qf = q11 * dx * dx + 2.0 * q12 * dx * dy + q22 * dy * dy;
     double qabs = fabs(q11 * dx * dx) + fabs(2.0 * q12 * dx * dy) + fabs(q22 * dy * dy);
-    if (qabs > 0 && fabs(qf) <= 1e-5 * qabs) amb = 1;
+    if (qabs > 0 && fabs(qf) <= 1e-5 * qabs) amb |= 1;
     double power = -0.5 * qf;
     if (power > 0) continue;
     double e = exp(power);
     double a = opacity[g] * e;
-    if (fabs(a - OR_ALPHA_MIN) <= 1e-5 * OR_ALPHA_MIN) amb = 1;
-    if (fabs(a - OR_ALPHA_MAX) <= 1e-5 * OR_ALPHA_MAX) amb = 1;
+    if (fabs(a - OR_ALPHA_MIN) <= 1e-5 * OR_ALPHA_MIN) amb |= 2;
+    if (fabs(a - OR_ALPHA_MAX) <= 1e-5 * OR_ALPHA_MAX) amb |= 4;
     double alpha = a < OR_ALPHA_MAX ? a : OR_ALPHA_MAX;
     if (alpha < OR_ALPHA_MIN) continue;
     double Tn = T * (1.0 - alpha);
     double band = 8.0 * (double)(nb + 1) * 5.9604644775390625e-08;  /* 8 n 2^-24 */
     if (band < 1e-5) band = 1e-5;
-    if (fabs(Tn - OR_T_MIN) <= band * OR_T_MIN) amb = 1;
+    if (fabs(Tn - OR_T_MIN) <= band * OR_T_MIN) amb |= 8;
     if (Tn < OR_T_MIN) break;
-    if (prev_depth >= 0 && fabs(depth[g] - prev_depth) <= 1e-6 * fabs(depth[g])) amb = 1;
+    if (prev_depth >= 0 && fabs(depth[g] - prev_depth) <= 5e-7 * fabs(depth[g])) amb |= 16;
     prev_depth = depth[g];
     if (rec) {
       rec[nb].g = g; rec[nb].alpha = alpha; rec[nb].a = a; rec[nb].e = e;
@@ -288,14 +288,15 @@ void or_render(int64_t n, const double* mean2d, const double* conic, const doubl
  * d_mean2d [2][n], d_conic [3][n], d_opacity [n], d_rgb [3][n].  abs_mass
  * [9][n] (may be NULL) receives the sum of |per-pixel contribution| of every
  * gradient element, amb_mass [9][n] (may be NULL) the same restricted to
- * ambiguous pixels; order of the 9: mean2d x,y, conic 11,12,22, opacity,
- * rgb.                                                                     */
+ * ambiguous pixels (those whose ambiguity reason bits intersect amb_bits,
+ * see composite_pixel); order of the 9: mean2d x,y, conic 11,12,22,
+ * opacity, rgb.                                                            */
 void or_render_bwd(int64_t n, const double* mean2d, const double* conic, const double* depth,
                    const double* opacity, const double* rgb, const int32_t* tile_bbox,
                    const int32_t* valid, int W, int H, int tw, int th, const double* bg, int x0,
                    int y0, int x1, int y1, const double* d_image, double* d_mean2d,
                    double* d_conic, double* d_opacity, double* d_rgb, double* abs_mass,
-                   double* amb_mass) {
+                   double* amb_mass, int amb_bits) {
   int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
   int64_t cnt = sorted_order(n, depth, valid, order);
   int64_t npix = (int64_t)(x1 - x0) * (y1 - y0);
@@ -346,7 +347,7 @@ void or_render_bwd(int64_t n, const double* mean2d, const double* conic, const d
 #pragma omp atomic
             abs_mass[k2 * n + g] += fabs(contrib[k2]);
           }
-          if (amb_mass && amb) {
+          if (amb_mass && (amb & amb_bits)) {
 #pragma omp atomic
             amb_mass[k2 * n + g] += fabs(contrib[k2]);
           }

@@ -1,0 +1,439 @@
+// binsort.hip — tile binning and stable sort on (slot*tiles + tile, depth)
+// keys for the 3D-GS rasteriser (the per-tile, depth-ordered Gaussian lists
+// of the method the paper's Sec. II trains with).
+//
+// Pipeline (all sizes that depend on data stay on the device, so the whole
+// call can be captured in a HIP graph):
+//   k_scan_reduce  per-block sums of n_tiles
+//   k_scan_top     exclusive scan of the block sums, total -> status[1],
+//                  overflow flag, clamped count
+//   k_emit         per block: local scan of n_tiles, then one thread per
+//                  duplicate (coalesced writes) finds its pair by binary
+//                  search in LDS and writes key / pair index
+//   k_radix_hist / k_radix_rowscan / k_radix_scatter   LSD radix passes on
+//                  8-bit digits over the significant key bits only; the
+//                  scatter ranks stably with wave64 ballots and stages the
+//                  block in LDS so global writes are runs per digit
+//   k_ranges       [start, end) per tile from the sorted keys
+#include "gs_device.h"
+
+namespace gsmi {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 8;
+constexpr int kScanItems = kScanThreads * kScanPer;   // pairs per scan/emit block
+constexpr int kSortThreads = 256;
+constexpr int kSortPer = 16;
+constexpr int kSortItems = kSortThreads * kSortPer;   // keys per radix block
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct BinSortLayout {
+  int64_t nb_scan, nb_sort;
+  size_t off_block_sums, off_count, off_keys_alt, off_vals_alt, off_hist, off_rowtot, total;
+};
+
+static BinSortLayout layout(int64_t m, int64_t cap) {
+  BinSortLayout L;
+  L.nb_scan = ceil_div(m > 0 ? m : 1, kScanItems);
+  L.nb_sort = ceil_div(cap > 0 ? cap : 1, kSortItems);
+  size_t o = 0;
+  L.off_block_sums = o; o += align256(sizeof(int64_t) * (size_t)L.nb_scan);
+  L.off_count = o; o += align256(sizeof(int64_t) * 2);
+  L.off_keys_alt = o; o += align256(sizeof(uint64_t) * (size_t)(cap > 0 ? cap : 1));
+  L.off_vals_alt = o; o += align256(sizeof(uint32_t) * (size_t)(cap > 0 ? cap : 1));
+  L.off_hist = o; o += align256(sizeof(uint32_t) * (size_t)kRadix * (size_t)L.nb_sort);
+  L.off_rowtot = o; o += align256(sizeof(uint32_t) * kRadix);
+  L.total = o;
+  return L;
+}
+
+// ------------------------------------------------------------ block scans
+
+// Inclusive prefix sum over a wave64 with cross-lane shuffles.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// Exclusive prefix sum over a 256-thread block; `total` receives the sum.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* sm_waves /*[4]*/, T& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T inc = wave_inclusive_scan(v);
+  if (lane == 63) sm_waves[wave] = inc;
+  __syncthreads();
+  T base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    T x = sm_waves[w];
+    if (w < wave) base += x;
+    tot += x;
+  }
+  __syncthreads();
+  total = tot;
+  return base + inc - v;
+}
+
+// ------------------------------------------------------------ scan of n_tiles
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __restrict__ n_tiles,
+                                                              int64_t m,
+                                                              int64_t* __restrict__ block_sums) {
+  __shared__ int64_t sm[4];
+  int64_t base = (int64_t)blockIdx.x * kScanItems;
+  int64_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    int64_t i = base + k * kScanThreads + threadIdx.x;
+    if (i < m) sum += max(n_tiles[i], 0);
+  }
+  int64_t total;
+  block_exclusive_scan<int64_t>(sum, sm, total);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// Single workgroup: exclusive scan of nb block sums in place; writes the
+// true total to status[1] and min(total, cap) to count[0].
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t* __restrict__ block_sums,
+                                                           int64_t nb, int64_t cap,
+                                                           int64_t* __restrict__ status,
+                                                           int64_t* __restrict__ count) {
+  __shared__ int64_t sm[4];
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += kScanThreads) {
+    int64_t i = c0 + threadIdx.x;
+    int64_t v = i < nb ? block_sums[i] : 0;
+    int64_t total;
+    int64_t ex = block_exclusive_scan<int64_t>(v, sm, total);
+    if (i < nb) block_sums[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    if (status) {
+      status[1] = carry;
+      if (carry > cap) status[0] |= GS_FLAG_CAPACITY;
+    }
+    count[0] = carry < cap ? carry : cap;
+  }
+}
+
+// ------------------------------------------------------------ emit
+
+__global__ __launch_bounds__(kScanThreads) void k_emit(
+    const int32_t* __restrict__ n_tiles, const uint2* __restrict__ tile_bbox,
+    const float* __restrict__ rec, int64_t m, const int64_t* __restrict__ block_offsets,
+    int64_t cap, int tiles_x, int tiles_per_slot, uint64_t* __restrict__ keys,
+    uint32_t* __restrict__ vals) {
+  __shared__ uint32_t s_off[kScanItems + 1];
+  __shared__ uint2 s_bbox[kScanItems];
+  __shared__ uint32_t s_depth[kScanItems];
+  __shared__ uint32_t s_slot[kScanItems];
+  __shared__ uint32_t s_w[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanItems;
+  const int t = threadIdx.x;
+  // stage the block's pairs (striped, coalesced) ...
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    int li = k * kScanThreads + t;
+    int64_t i = base + li;
+    int nt = 0;
+    if (i < m) {
+      nt = max(n_tiles[i], 0);
+      if (nt > 0) {
+        s_bbox[li] = tile_bbox[i];
+        s_depth[li] = __float_as_uint(rec[i * GS_REC_STRIDE + 9]);
+        s_slot[li] = __float_as_uint(rec[i * GS_REC_STRIDE + 10]);
+      }
+    }
+    s_off[li] = (uint32_t)nt;
+  }
+  __syncthreads();
+  // ... then scan them in blocked order (thread t owns items t*8 .. t*8+7)
+  uint32_t v[kScanPer], run = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = s_off[t * kScanPer + k];
+    run += v[k];
+  }
+  uint32_t total;
+  uint32_t ex = block_exclusive_scan<uint32_t>(run, s_w, total);
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    s_off[t * kScanPer + k] = ex;
+    ex += v[k];
+  }
+  if (t == 0) s_off[kScanItems] = total;
+  __syncthreads();
+  const int64_t gbase = block_offsets[blockIdx.x];
+  for (uint32_t j = t; j < total; j += kScanThreads) {
+    int64_t dst = gbase + j;
+    if (dst >= cap) break;
+    // last local pair whose offset <= j (pairs with zero tiles are skipped
+    // because their successor shares the offset)
+    int lo = 0, hi = kScanItems - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (s_off[mid] <= j) lo = mid;
+      else hi = mid - 1;
+    }
+    uint32_t k = j - s_off[lo];
+    uint2 bb = s_bbox[lo];
+    int tx0 = bb.x & 0xffff, ty0 = bb.x >> 16, tx1 = bb.y & 0xffff;
+    int span = tx1 - tx0 + 1;
+    int ty = ty0 + (int)(k / span), tx = tx0 + (int)(k % span);
+    uint64_t tile = (uint64_t)s_slot[lo] * (uint64_t)tiles_per_slot + (uint64_t)(ty * tiles_x + tx);
+    keys[dst] = (tile << 32) | (uint64_t)s_depth[lo];
+    vals[dst] = (uint32_t)(base + lo);
+  }
+}
+
+// ------------------------------------------------------------ radix sort
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys,
+                                                             const int64_t* __restrict__ count,
+                                                             int shift, int64_t nb,
+                                                             uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kRadix];
+  const int t = threadIdx.x;
+  h[t] = 0;
+  __syncthreads();
+  const int64_t n = count[0];
+  const int64_t base = (int64_t)blockIdx.x * kSortItems;
+  if (base < n) {
+#pragma unroll 4
+    for (int k = 0; k < kSortPer; ++k) {
+      int64_t i = base + k * kSortThreads + t;
+      if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (kRadix - 1)], 1u);
+    }
+  }
+  __syncthreads();
+  hist[(int64_t)t * nb + blockIdx.x] = h[t];
+}
+
+// One workgroup per digit: exclusive scan of that digit's per-block counts.
+__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ hist, int64_t nb,
+                                                       uint32_t* __restrict__ row_tot) {
+  __shared__ uint32_t sm[4];
+  uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+  const int64_t seg = ceil_div(nb, 256);
+  const int64_t b0 = threadIdx.x * seg, b1 = min(b0 + seg, nb);
+  uint32_t s = 0;
+  for (int64_t b = b0; b < b1; ++b) s += row[b];
+  uint32_t total;
+  uint32_t ex = block_exclusive_scan<uint32_t>(s, sm, total);
+  for (int64_t b = b0; b < b1; ++b) {
+    uint32_t x = row[b];
+    row[b] = ex;
+    ex += x;
+  }
+  if (threadIdx.x == 0) row_tot[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, const int64_t* __restrict__ count,
+    int shift, int64_t nb, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ row_tot) {
+  // LDS: per (round, wave, digit) counts; staging of the block's items
+  __shared__ uint16_t s_cnt[kSortPer][4][kRadix];   // 32 KB
+  __shared__ uint64_t s_key[kSortItems];             // 32 KB
+  __shared__ uint32_t s_val[kSortItems];             // 16 KB
+  __shared__ uint32_t s_dstart[kRadix];              // local digit starts
+  __shared__ uint32_t s_gbase[kRadix];               // global digit base of this block
+  __shared__ uint32_t s_w[4];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t n = count[0];
+  const int64_t base = (int64_t)blockIdx.x * kSortItems;
+  if (base >= n) return;
+  // global base per digit = sum of all row totals of smaller digits + this
+  // block's exclusive prefix within the digit's row
+  {
+    uint32_t rt = row_tot[t];
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan<uint32_t>(rt, s_w, tot);
+    s_gbase[t] = ex + hist[(int64_t)t * nb + blockIdx.x];
+  }
+  {
+    uint32_t* z = reinterpret_cast<uint32_t*>(&s_cnt[0][0][0]);
+    for (int i = t; i < kSortPer * 4 * kRadix / 2; i += kSortThreads) z[i] = 0u;
+  }
+  __syncthreads();
+  uint64_t key[kSortPer];
+  uint32_t val[kSortPer];
+  uint32_t wrank[kSortPer];
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int r = 0; r < kSortPer; ++r) {
+    int64_t i = base + r * kSortThreads + t;
+    bool valid = i < n;
+    key[r] = valid ? kin[i] : 0ull;
+    val[r] = valid ? vin[i] : 0u;
+    uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < kRadixBits; ++bit) {
+      uint64_t b = __ballot((d >> bit) & 1u);
+      peers &= ((d >> bit) & 1u) ? b : ~b;
+    }
+    wrank[r] = (uint32_t)__popcll(peers & lt_mask);
+    if (valid && wrank[r] == 0) s_cnt[r][wave][d] = (uint16_t)__popcll(peers);
+  }
+  __syncthreads();
+  // thread t owns digit t: exclusive scan over (round, wave) in index order
+  {
+    uint32_t run = 0;
+#pragma unroll
+    for (int r = 0; r < kSortPer; ++r)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        uint32_t c = s_cnt[r][w][t];
+        s_cnt[r][w][t] = (uint16_t)run;
+        run += c;
+      }
+    uint32_t tot;
+    uint32_t ex = block_exclusive_scan<uint32_t>(run, s_w, tot);
+    s_dstart[t] = ex;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortPer; ++r) {
+    int64_t i = base + r * kSortThreads + t;
+    if (i < n) {
+      uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+      uint32_t pos = s_dstart[d] + s_cnt[r][wave][d] + wrank[r];
+      s_key[pos] = key[r];
+      s_val[pos] = val[r];
+    }
+  }
+  __syncthreads();
+  const int64_t nloc = min((int64_t)kSortItems, n - base);
+#pragma unroll 4
+  for (int r = 0; r < kSortPer; ++r) {
+    int li = r * kSortThreads + t;
+    if (li < nloc) {
+      uint64_t k = s_key[li];
+      uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
+      int64_t dst = (int64_t)s_gbase[d] + (li - (int64_t)s_dstart[d]);
+      kout[dst] = k;
+      vout[dst] = s_val[li];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint64_t* __restrict__ keys,
+                                                const int64_t* __restrict__ count,
+                                                uint32_t* __restrict__ ranges) {
+  const int64_t n = count[0];
+  int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  uint32_t tile = (uint32_t)(keys[j] >> 32);
+  if (j == 0 || (uint32_t)(keys[j - 1] >> 32) != tile) ranges[2 * (int64_t)tile] = (uint32_t)j;
+  if (j == n - 1 || (uint32_t)(keys[j + 1] >> 32) != tile)
+    ranges[2 * (int64_t)tile + 1] = (uint32_t)(j + 1);
+}
+
+}  // namespace gsmi
+
+using namespace gsmi;
+
+extern "C" {
+
+size_t gs_bin_sort_workspace_bytes(int64_t m, int64_t dup_capacity, const gs_tiling* tiling,
+                                   int32_t n_slots) {
+  (void)tiling;
+  (void)n_slots;
+  if (m < 0 || dup_capacity < 0) return 0;
+  return layout(m, dup_capacity).total;
+}
+
+gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_tiling* tiling,
+                      int64_t dup_capacity, void* ws, size_t ws_bytes, uint64_t* keys_out,
+                      uint32_t* ids_out, uint32_t* tile_ranges, int64_t* status, void* stream) {
+  clear_error();
+  GS_REQUIRE(proj != nullptr, "gs_bin_sort: NULL proj");
+  gs_status st = check_views(views, tiling, "gs_bin_sort");
+  if (st != GS_OK) return st;
+  GS_REQUIRE(proj->m == views->total_pairs, "gs_bin_sort: proj->m != total_pairs");
+  GS_REQUIRE(dup_capacity >= 1 && dup_capacity <= (int64_t)0xFFFFFFFFll,
+             "gs_bin_sort: dup_capacity=%lld outside [1, 2^32-1]", (long long)dup_capacity);
+  GS_REQUIRE(keys_out && ids_out && tile_ranges && ws, "gs_bin_sort: NULL output/workspace");
+  const int64_t m = proj->m;
+  GS_REQUIRE(m == 0 || (proj->rec && proj->tile_bbox && proj->n_tiles),
+             "gs_bin_sort: NULL projected arrays");
+  BinSortLayout L = layout(m, dup_capacity);
+  GS_REQUIRE(ws_bytes >= L.total, "gs_bin_sort: workspace %zu < required %zu", ws_bytes, L.total);
+  GS_REQUIRE(((uintptr_t)ws & 255) == 0, "gs_bin_sort: workspace must be 256-byte aligned");
+  hipStream_t s = as_stream(stream);
+  char* w = (char*)ws;
+  int64_t* block_sums = (int64_t*)(w + L.off_block_sums);
+  int64_t* count = (int64_t*)(w + L.off_count);
+  uint64_t* keys_alt = (uint64_t*)(w + L.off_keys_alt);
+  uint32_t* vals_alt = (uint32_t*)(w + L.off_vals_alt);
+  uint32_t* hist = (uint32_t*)(w + L.off_hist);
+  uint32_t* rowtot = (uint32_t*)(w + L.off_rowtot);
+  const int tiles_x = (int)ceil_div(tiling->width, tiling->tile_w);
+  const int tiles_y = (int)ceil_div(tiling->height, tiling->tile_h);
+  const int64_t tiles_per_slot = (int64_t)tiles_x * tiles_y;
+  const int64_t n_tiles_all = tiles_per_slot * views->n_slots;
+  // key bits: 32 depth bits + enough bits for the largest tile index
+  int tile_bits = 0;
+  while ((int64_t(1) << tile_bits) < n_tiles_all) ++tile_bits;
+  const int passes = (32 + tile_bits + kRadixBits - 1) / kRadixBits;
+  // emit into the buffer that the last pass will not overwrite
+  uint64_t* k0 = (passes % 2 == 0) ? keys_out : keys_alt;
+  uint32_t* v0 = (passes % 2 == 0) ? ids_out : vals_alt;
+  uint64_t* k1 = (passes % 2 == 0) ? keys_alt : keys_out;
+  uint32_t* v1 = (passes % 2 == 0) ? vals_alt : ids_out;
+
+  st = gs_zero(tile_ranges, sizeof(uint32_t) * 2 * (size_t)n_tiles_all, stream);
+  if (st != GS_OK) return st;
+  if (m == 0) {
+    st = gs_zero(count, sizeof(int64_t) * 2, stream);
+    if (st != GS_OK) return st;
+    if (status) {
+      // status[1] = 0 duplicates; flags untouched
+      st = gs_zero(status + 1, sizeof(int64_t), stream);
+      if (st != GS_OK) return st;
+    }
+    return GS_OK;
+  }
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s,
+                     proj->n_tiles, m, block_sums);
+  GS_LAUNCH_CHECK("gs_bin_sort/scan_reduce");
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, block_sums, L.nb_scan,
+                     dup_capacity, status, count);
+  GS_LAUNCH_CHECK("gs_bin_sort/scan_top");
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s, proj->n_tiles,
+                     (const uint2*)proj->tile_bbox, proj->rec, m, block_sums, dup_capacity, tiles_x,
+                     (int)tiles_per_slot, k0, v0);
+  GS_LAUNCH_CHECK("gs_bin_sort/emit");
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * kRadixBits;
+    const uint64_t* kin = (p % 2 == 0) ? k0 : k1;
+    const uint32_t* vin = (p % 2 == 0) ? v0 : v1;
+    uint64_t* kout = (p % 2 == 0) ? k1 : k0;
+    uint32_t* vout = (p % 2 == 0) ? v1 : v0;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)L.nb_sort), dim3(kSortThreads), 0, s, kin,
+                       count, shift, L.nb_sort, hist);
+    GS_LAUNCH_CHECK("gs_bin_sort/radix_hist");
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, L.nb_sort, rowtot);
+    GS_LAUNCH_CHECK("gs_bin_sort/radix_rowscan");
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)L.nb_sort), dim3(kSortThreads), 0, s, kin,
+                       vin, kout, vout, count, shift, L.nb_sort, hist, rowtot);
+    GS_LAUNCH_CHECK("gs_bin_sort/radix_scatter");
+  }
+  hipLaunchKernelGGL(k_ranges, dim3((unsigned)ceil_div(dup_capacity, 256)), dim3(256), 0, s,
+                     keys_out, count, tile_ranges);
+  GS_LAUNCH_CHECK("gs_bin_sort/ranges");
+  return GS_OK;
+}
+
+}  // extern "C"

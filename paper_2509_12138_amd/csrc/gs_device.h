@@ -1,0 +1,117 @@
+// gs_device.h — internal helpers of libgsmi (gfx950 / CDNA4, wave64).
+//
+// Host side: thread-local error text, argument checks, launch checks.
+// Device side: wave64 DPP reductions, the splat evaluation shared by the
+// forward and backward rasterisers (so both take bit-identical decisions),
+// and the method's constants in FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include "gs.h"
+
+namespace gsmi {
+
+// ----------------------------------------------------------------- host side
+
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define GS_REQUIRE(cond, ...)            \
+  do {                                   \
+    if (!(cond)) {                       \
+      ::gsmi::set_error(__VA_ARGS__);    \
+      return GS_ERR_ARG;                 \
+    }                                    \
+  } while (0)
+
+#define GS_LAUNCH_CHECK(what)                                                   \
+  do {                                                                          \
+    hipError_t _e = hipGetLastError();                                          \
+    if (_e != hipSuccess) {                                                     \
+      ::gsmi::set_error("%s: %s", (what), hipGetErrorString(_e));               \
+      return GS_ERR_HIP;                                                        \
+    }                                                                           \
+  } while (0)
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Validates a gs_views / gs_tiling pair; returns GS_OK or GS_ERR_ARG.
+gs_status check_views(const gs_views* v, const gs_tiling* t, const char* who);
+
+// Number of compute units of the current device (cached per device).
+int device_cu_count();
+
+// ----------------------------------------------------------------- constants
+
+constexpr float kC0 = 0.28209479177387814f;      // degree-0 SH basis 1/(2 sqrt(pi))
+constexpr float kDilate = 0.3f;                  // 2D covariance low-pass (px^2)
+constexpr float kFrustum = 1.3f;                 // Jacobian clamp factor
+constexpr float kAlphaMax = 0.99f;
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// ----------------------------------------------------------------- device side
+
+// DPP lane moves within a wave64 (GFX9 DPP controls).  Lanes that read an
+// invalid source or whose row is masked off receive 0.
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK,
+                                         BANK_MASK, false));
+}
+
+constexpr int kDppQuadSwap1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppRowRor4 = 0x124;    // row_ror:4
+constexpr int kDppRowRor8 = 0x128;    // row_ror:8
+constexpr int kDppRowBcast15 = 0x142; // row_bcast:15
+constexpr int kDppRowBcast31 = 0x143; // row_bcast:31
+
+// Sum over the 64 lanes of a wave; the total is valid in lane 63.
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+  v += dpp_f<kDppQuadSwap1>(v);
+  v += dpp_f<kDppQuadSwap2>(v);
+  v += dpp_f<kDppRowRor4>(v);
+  v += dpp_f<kDppRowRor8>(v);
+  v += dpp_f<kDppRowBcast15, 0xa>(v);
+  v += dpp_f<kDppRowBcast31, 0xc>(v);
+  return v;
+}
+
+__device__ __forceinline__ float lane63(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+__device__ __forceinline__ float wave_sum(float v) { return lane63(wave_sum_to_lane63(v)); }
+
+// A Gaussian as staged in LDS for the rasterisers: mean, log2-scaled conic
+// (A, B, C) so that log2 of the Gaussian falloff is A dx^2 + B dx dy + C dy^2,
+// opacity and colour.
+struct alignas(16) Splat {
+  float mx, my, A, B, C, o, r, g, b, pad0, pad1, pad2;
+};
+
+// log2-domain falloff exponent at offset (dx, dy).  Written with explicit
+// fused operations so that the forward and backward kernels evaluate it
+// bit-identically (their skip/stop decisions must agree).
+__device__ __forceinline__ float splat_p2(float A, float B, float C, float dx, float dy) {
+  float u = __fmul_rn(A, dx);
+  u = __fmaf_rn(B, dy, u);           // A dx + B dy
+  float v = __fmul_rn(C, dy);        // C dy
+  float w = __fmul_rn(v, dy);        // C dy^2
+  return __fmaf_rn(u, dx, w);        // A dx^2 + B dx dy + C dy^2
+}
+
+// Unclamped alpha o * 2^p2 (the clamp and the 1/255 skip are applied by the
+// caller).  __builtin_amdgcn_exp2f is the hardware v_exp_f32.
+__device__ __forceinline__ float splat_gauss(float p2) { return __builtin_amdgcn_exp2f(p2); }
+
+}  // namespace gsmi

@@ -1,0 +1,416 @@
+// project.hip — EWA projection of 3D Gaussians and its backward (3D-GS
+// method that the paper's Sec. II "Parallel Training" runs per partition).
+//
+// Forward: one thread per (Gaussian, slot) pair; planar SoA parameter loads
+// are coalesced, the 48-byte record goes out as three 16-byte stores.
+// Backward: one thread per Gaussian that loops over the slots drawing it, so
+// gradients summed over views need no atomics and are deterministic.
+#include "gs_device.h"
+
+namespace gsmi {
+
+struct Params {
+  const float* mean;
+  const float* ls;
+  const float* quat;
+  const float* ol;
+  const float* col;
+  int64_t n;
+};
+
+struct GradPtrs {
+  float* mean;
+  float* ls;
+  float* quat;
+  float* ol;
+  float* col;
+};
+
+// Everything the projection of one pair computes (FP32).
+struct ProjState {
+  float s[3], qn[4], qinv;
+  float R[9];          // rotation of the Gaussian
+  float Sig[6];        // 3D covariance xx, xy, xz, yy, yz, zz
+  float t[3];
+  float mean2d[2];
+  float xc, yc;        // clamped tx, ty used by the Jacobian
+  bool xcl, ycl;
+  float T[6];          // J * Rv (2x3, row-major)
+  float a, b, c, det;  // dilated 2D covariance
+  float conic[3];
+  float o, pre_rgb[3], rgb[3];
+  int bbox[4];         // inclusive tile range
+  int n_tiles;
+  bool valid;
+};
+
+__device__ __forceinline__ void load_gaussian(const Params& P, int64_t g, float mu[3], float ls[3],
+                                              float q[4], float& ol, float col[3]) {
+  const int64_t n = P.n;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    mu[k] = P.mean[k * n + g];
+    ls[k] = P.ls[k * n + g];
+    col[k] = P.col[k * n + g];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = P.quat[k * n + g];
+  ol = P.ol[g];
+}
+
+__device__ __forceinline__ void project_core(const float mu[3], const float ls[3], const float q[4],
+                                             float ol, const float col[3], const gs_camera& cam,
+                                             int W, int H, int tw, int th, ProjState& S) {
+  S.valid = false;
+  S.n_tiles = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) S.s[k] = expf(ls[k]);
+  float qq = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+  float qnorm = sqrtf(qq);
+  S.qinv = 1.0f / qnorm;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) S.qn[k] = q[k] * S.qinv;
+  float w = S.qn[0], x = S.qn[1], y = S.qn[2], z = S.qn[3];
+  float* R = S.R;
+  R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z); R[2] = 2.f * (x * z + w * y);
+  R[3] = 2.f * (x * y + w * z); R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+  R[6] = 2.f * (x * z - w * y); R[7] = 2.f * (y * z + w * x); R[8] = 1.f - 2.f * (x * x + y * y);
+  float M[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M[r * 3 + k] = R[r * 3 + k] * S.s[k];
+  // Sigma = M M^T
+  S.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  S.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+  S.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+  S.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+  S.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+  S.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+  S.o = 1.0f / (1.0f + expf(-ol));
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    S.pre_rgb[k] = kC0 * col[k] + 0.5f;
+    S.rgb[k] = fmaxf(S.pre_rgb[k], 0.0f);
+  }
+  const float* Rv = cam.R;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    S.t[i] = Rv[i * 3 + 0] * mu[0] + Rv[i * 3 + 1] * mu[1] + Rv[i * 3 + 2] * mu[2] + cam.t[i];
+  float tx = S.t[0], ty = S.t[1], tz = S.t[2];
+  if (!(tz > cam.znear)) return;
+  float itz = 1.0f / tz;
+  S.mean2d[0] = cam.fx * tx * itz + cam.cx;
+  S.mean2d[1] = cam.fy * ty * itz + cam.cy;
+  float limx = kFrustum * 0.5f * (float)W / cam.fx;
+  float limy = kFrustum * 0.5f * (float)H / cam.fy;
+  float rx = tx * itz, ry = ty * itz;
+  S.xcl = (rx < -limx) || (rx > limx);
+  S.ycl = (ry < -limy) || (ry > limy);
+  rx = fminf(fmaxf(rx, -limx), limx);
+  ry = fminf(fmaxf(ry, -limy), limy);
+  S.xc = rx * tz;
+  S.yc = ry * tz;
+  float j00 = cam.fx * itz, j02 = -cam.fx * S.xc * itz * itz;
+  float j11 = cam.fy * itz, j12 = -cam.fy * S.yc * itz * itz;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    S.T[k] = j00 * Rv[0 * 3 + k] + j02 * Rv[2 * 3 + k];
+    S.T[3 + k] = j11 * Rv[1 * 3 + k] + j12 * Rv[2 * 3 + k];
+  }
+  // V = T Sigma T^T
+  const float* Sg = S.Sig;
+  float u0[3], u1[3];  // Sigma T_row^T
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const float* Tr = S.T + 3 * r;
+    float* u = r ? u1 : u0;
+    u[0] = Sg[0] * Tr[0] + Sg[1] * Tr[1] + Sg[2] * Tr[2];
+    u[1] = Sg[1] * Tr[0] + Sg[3] * Tr[1] + Sg[4] * Tr[2];
+    u[2] = Sg[2] * Tr[0] + Sg[4] * Tr[1] + Sg[5] * Tr[2];
+  }
+  S.a = S.T[0] * u0[0] + S.T[1] * u0[1] + S.T[2] * u0[2] + kDilate;
+  S.b = S.T[0] * u1[0] + S.T[1] * u1[1] + S.T[2] * u1[2];
+  S.c = S.T[3] * u1[0] + S.T[4] * u1[1] + S.T[5] * u1[2] + kDilate;
+  S.det = S.a * S.c - S.b * S.b;
+  if (!(S.det > 0.0f)) return;
+  float idet = 1.0f / S.det;
+  S.conic[0] = S.c * idet;
+  S.conic[1] = -S.b * idet;
+  S.conic[2] = S.a * idet;
+  if (!(255.0f * S.o > 1.0f)) return;
+  float kappa = 2.0f * logf(255.0f * S.o);
+  float hx = sqrtf(kappa * S.a), hy = sqrtf(kappa * S.c);
+  float xl = S.mean2d[0] - hx, xh = S.mean2d[0] + hx;
+  float yl = S.mean2d[1] - hy, yh = S.mean2d[1] + hy;
+  float Wf = (float)W + 4.0f, Hf = (float)H + 4.0f;
+  xl = (xl > -4.0f) ? fminf(xl, Wf) : -4.0f;
+  xh = (xh > -4.0f) ? fminf(xh, Wf) : -4.0f;
+  yl = (yl > -4.0f) ? fminf(yl, Hf) : -4.0f;
+  yh = (yh > -4.0f) ? fminf(yh, Hf) : -4.0f;
+  int x0 = max((int)floorf(xl) - 1, 0), x1 = min((int)floorf(xh) + 1, W - 1);
+  int y0 = max((int)floorf(yl) - 1, 0), y1 = min((int)floorf(yh) + 1, H - 1);
+  if (x0 > x1 || y0 > y1) return;
+  S.bbox[0] = x0 / tw;
+  S.bbox[1] = y0 / th;
+  S.bbox[2] = x1 / tw;
+  S.bbox[3] = y1 / th;
+  S.n_tiles = (S.bbox[2] - S.bbox[0] + 1) * (S.bbox[3] - S.bbox[1] + 1);
+  S.valid = true;
+}
+
+__device__ __forceinline__ int find_slot(const int64_t* __restrict__ pair_offset, int n_slots,
+                                         int64_t p) {
+  int lo = 0, hi = n_slots - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pair_offset[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_project(Params P, const int64_t* __restrict__ pair_offset,
+                                                 const int64_t* __restrict__ gauss_offset,
+                                                 const gs_camera* __restrict__ cams, int n_slots,
+                                                 int64_t m, int W, int H, int tw, int th,
+                                                 float4* __restrict__ rec,
+                                                 uint2* __restrict__ tile_bbox,
+                                                 int32_t* __restrict__ n_tiles) {
+  int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= m) return;
+  int s = find_slot(pair_offset, n_slots, p);
+  int64_t g = gauss_offset[s] + (p - pair_offset[s]);
+  ProjState S;
+  S.valid = false;
+  S.n_tiles = 0;
+  S.t[2] = 0.0f;
+  if (g >= 0 && g < P.n) {
+    float mu[3], ls[3], q[4], ol, col[3];
+    load_gaussian(P, g, mu, ls, q, ol, col);
+    project_core(mu, ls, q, ol, col, cams[s], W, H, tw, th, S);
+  }
+  float4* r = rec + 3 * p;
+  if (S.valid) {
+    r[0] = make_float4(S.mean2d[0], S.mean2d[1], S.conic[0], S.conic[1]);
+    r[1] = make_float4(S.conic[2], S.o, S.rgb[0], S.rgb[1]);
+    r[2] = make_float4(S.rgb[2], S.t[2], __int_as_float(s), 0.0f);
+    tile_bbox[p] = make_uint2((uint32_t)S.bbox[0] | ((uint32_t)S.bbox[1] << 16),
+                              (uint32_t)S.bbox[2] | ((uint32_t)S.bbox[3] << 16));
+    n_tiles[p] = S.n_tiles;
+  } else {
+    r[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    r[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    r[2] = make_float4(0.f, S.t[2], __int_as_float(s), 0.0f);
+    tile_bbox[p] = make_uint2(0u, 0u);
+    n_tiles[p] = 0;
+  }
+}
+
+// Backward of project_core for one pair: accumulates the parameter gradients
+// of the pair into the per-thread sums.
+__device__ __forceinline__ void project_bwd_core(const ProjState& S, const gs_camera& cam,
+                                                 const float* __restrict__ dr, float gmu[3],
+                                                 float gls[3], float gq[4], float& gol,
+                                                 float gcol[3]) {
+  float dmx = dr[0], dmy = dr[1], dq11 = dr[2], dq12 = dr[3], dq22 = dr[4];
+  float dop = dr[5];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (S.pre_rgb[k] >= 0.0f) gcol[k] += kC0 * dr[6 + k];
+  gol += S.o * (1.0f - S.o) * dop;
+  // conic (c, -b, a)/det as a function of (a, b, c)
+  float a = S.a, b = S.b, c = S.c;
+  float idet = 1.0f / S.det, id2 = idet * idet;
+  float da = (-c * c * dq11 + b * c * dq12 - b * b * dq22) * id2;
+  float db = (2.f * b * c * dq11 - (S.det + 2.f * b * b) * dq12 + 2.f * a * b * dq22) * id2;
+  float dc = (-b * b * dq11 + a * b * dq12 - a * a * dq22) * id2;
+  float G00 = da, G01 = 0.5f * db, G11 = dc;
+  const float* T = S.T;
+  // dSigma = T^T G T  (symmetric 3x3: xx, xy, xz, yy, yz, zz)
+  float gt0[3], gt1[3];  // rows of G T
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    gt0[k] = G00 * T[k] + G01 * T[3 + k];
+    gt1[k] = G01 * T[k] + G11 * T[3 + k];
+  }
+  float dS[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dS[i * 3 + j] = T[i] * gt0[j] + T[3 + i] * gt1[j];
+  // dT = 2 G T Sigma
+  const float* Sg = S.Sig;
+  float Sf[9] = {Sg[0], Sg[1], Sg[2], Sg[1], Sg[3], Sg[4], Sg[2], Sg[4], Sg[5]};
+  float dT[6];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    dT[l] = 2.f * (gt0[0] * Sf[0 * 3 + l] + gt0[1] * Sf[1 * 3 + l] + gt0[2] * Sf[2 * 3 + l]);
+    dT[3 + l] = 2.f * (gt1[0] * Sf[0 * 3 + l] + gt1[1] * Sf[1 * 3 + l] + gt1[2] * Sf[2 * 3 + l]);
+  }
+  // T = J Rv: dJ = dT Rv^T (only the non-constant entries of J)
+  const float* Rv = cam.R;
+  float dj00 = dT[0] * Rv[0] + dT[1] * Rv[1] + dT[2] * Rv[2];
+  float dj02 = dT[0] * Rv[6] + dT[1] * Rv[7] + dT[2] * Rv[8];
+  float dj11 = dT[3] * Rv[3] + dT[4] * Rv[4] + dT[5] * Rv[5];
+  float dj12 = dT[3] * Rv[6] + dT[4] * Rv[7] + dT[5] * Rv[8];
+  float tx = S.t[0], ty = S.t[1], tz = S.t[2];
+  float itz = 1.0f / tz, itz2 = itz * itz, itz3 = itz2 * itz;
+  float fx = cam.fx, fy = cam.fy;
+  float dtx = 0.f, dty = 0.f, dtz = 0.f;
+  dtz += -fx * itz2 * dj00 - fy * itz2 * dj11;
+  if (!S.xcl) {
+    dtx += -fx * itz2 * dj02;
+    dtz += 2.f * fx * tx * itz3 * dj02;
+  } else {
+    dtz += fx * S.xc * itz3 * dj02;
+  }
+  if (!S.ycl) {
+    dty += -fy * itz2 * dj12;
+    dtz += 2.f * fy * ty * itz3 * dj12;
+  } else {
+    dtz += fy * S.yc * itz3 * dj12;
+  }
+  dtx += dmx * fx * itz;
+  dty += dmy * fy * itz;
+  dtz += -(dmx * fx * tx + dmy * fy * ty) * itz2;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gmu[k] += Rv[k] * dtx + Rv[3 + k] * dty + Rv[6 + k] * dtz;
+  // Sigma = M M^T, M = R diag(s): dM = 2 dSigma M
+  const float* R = S.R;
+  float M[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) M[r * 3 + k] = R[r * 3 + k] * S.s[k];
+  float dM[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      dM[r * 3 + k] =
+          2.f * (dS[r * 3 + 0] * M[0 * 3 + k] + dS[r * 3 + 1] * M[1 * 3 + k] + dS[r * 3 + 2] * M[2 * 3 + k]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float ds = dM[0 * 3 + k] * R[0 * 3 + k] + dM[1 * 3 + k] * R[1 * 3 + k] + dM[2 * 3 + k] * R[2 * 3 + k];
+    gls[k] += ds * S.s[k];
+  }
+  float dR[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dR[r * 3 + k] = dM[r * 3 + k] * S.s[k];
+  float w = S.qn[0], x = S.qn[1], y = S.qn[2], z = S.qn[3];
+  float dw = 2.f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+  float dx = 2.f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.f * x * dR[4] - w * dR[5] + z * dR[6] +
+                    w * dR[7] - 2.f * x * dR[8]);
+  float dy = 2.f * (-2.f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] +
+                    z * dR[7] - 2.f * y * dR[8]);
+  float dz = 2.f * (-2.f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.f * z * dR[4] +
+                    y * dR[5] + x * dR[6] + y * dR[7]);
+  float dot = w * dw + x * dx + y * dy + z * dz;
+  gq[0] += (dw - w * dot) * S.qinv;
+  gq[1] += (dx - x * dot) * S.qinv;
+  gq[2] += (dy - y * dot) * S.qinv;
+  gq[3] += (dz - z * dot) * S.qinv;
+}
+
+__global__ __launch_bounds__(256) void k_project_bwd(
+    Params P, GradPtrs Gr, const int64_t* __restrict__ pair_offset,
+    const int64_t* __restrict__ gauss_offset, const gs_camera* __restrict__ cams, int n_slots,
+    int W, int H, int tw, int th, const int32_t* __restrict__ n_tiles,
+    const float* __restrict__ d_rec) {
+  int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= P.n) return;
+  float mu[3], ls[3], q[4], ol, col[3];
+  load_gaussian(P, g, mu, ls, q, ol, col);
+  float gmu[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
+  float gol = 0.f, gcol[3] = {0.f, 0.f, 0.f};
+  bool any = false;
+  for (int s = 0; s < n_slots; ++s) {
+    int64_t g0 = gauss_offset[s];
+    int64_t cnt = pair_offset[s + 1] - pair_offset[s];
+    if (g < g0 || g >= g0 + cnt) continue;
+    int64_t p = pair_offset[s] + (g - g0);
+    if (n_tiles[p] <= 0) continue;
+    ProjState S;
+    project_core(mu, ls, q, ol, col, cams[s], W, H, tw, th, S);
+    if (!S.valid) continue;
+    float dr[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) dr[k] = d_rec[p * GS_DREC_STRIDE + k];
+    project_bwd_core(S, cams[s], dr, gmu, gls, gq, gol, gcol);
+    any = true;
+  }
+  if (!any) return;
+  const int64_t n = P.n;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    Gr.mean[k * n + g] += gmu[k];
+    Gr.ls[k * n + g] += gls[k];
+    Gr.col[k * n + g] += gcol[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Gr.quat[k * n + g] += gq[k];
+  Gr.ol[g] += gol;
+}
+
+}  // namespace gsmi
+
+using namespace gsmi;
+
+extern "C" {
+
+gs_status gs_project(const gs_gaussians* g, const gs_views* views, const gs_tiling* tiling,
+                     gs_projected* out, void* stream) {
+  clear_error();
+  GS_REQUIRE(g && out, "gs_project: NULL argument");
+  gs_status st = check_views(views, tiling, "gs_project");
+  if (st != GS_OK) return st;
+  GS_REQUIRE(g->n >= 0, "gs_project: n=%lld < 0", (long long)g->n);
+  GS_REQUIRE(out->m == views->total_pairs, "gs_project: out->m=%lld != total_pairs=%lld",
+             (long long)out->m, (long long)views->total_pairs);
+  if (out->m == 0) return GS_OK;
+  GS_REQUIRE(g->n > 0 && g->mean && g->log_scale && g->quat && g->opacity_logit && g->color,
+             "gs_project: Gaussian arrays must not be NULL");
+  GS_REQUIRE(out->rec && out->tile_bbox && out->n_tiles, "gs_project: output arrays NULL");
+  GS_REQUIRE(((uintptr_t)out->rec & 15) == 0 && ((uintptr_t)out->tile_bbox & 7) == 0,
+             "gs_project: rec must be 16-byte and tile_bbox 8-byte aligned");
+  Params P{g->mean, g->log_scale, g->quat, g->opacity_logit, g->color, g->n};
+  int64_t blocks = ceil_div(out->m, 256);
+  hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), P,
+                     views->pair_offset, views->gauss_offset, views->cams, views->n_slots, out->m,
+                     tiling->width, tiling->height, tiling->tile_w, tiling->tile_h,
+                     (float4*)out->rec, (uint2*)out->tile_bbox, out->n_tiles);
+  GS_LAUNCH_CHECK("gs_project");
+  return GS_OK;
+}
+
+gs_status gs_project_bwd(const gs_gaussians* g, const gs_views* views, const gs_tiling* tiling,
+                         const gs_projected* proj, const float* d_rec, gs_grads* grads,
+                         void* stream) {
+  clear_error();
+  GS_REQUIRE(g && proj && grads, "gs_project_bwd: NULL argument");
+  gs_status st = check_views(views, tiling, "gs_project_bwd");
+  if (st != GS_OK) return st;
+  GS_REQUIRE(proj->m == views->total_pairs, "gs_project_bwd: proj->m != total_pairs");
+  GS_REQUIRE(grads->n == g->n, "gs_project_bwd: grads->n=%lld != n=%lld", (long long)grads->n,
+             (long long)g->n);
+  if (g->n == 0 || proj->m == 0) return GS_OK;
+  GS_REQUIRE(g->mean && g->log_scale && g->quat && g->opacity_logit && g->color,
+             "gs_project_bwd: Gaussian arrays must not be NULL");
+  GS_REQUIRE(grads->mean && grads->log_scale && grads->quat && grads->opacity_logit &&
+                 grads->color && d_rec && proj->n_tiles,
+             "gs_project_bwd: gradient arrays must not be NULL");
+  Params P{g->mean, g->log_scale, g->quat, g->opacity_logit, g->color, g->n};
+  GradPtrs G{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->color};
+  int64_t blocks = ceil_div(g->n, 256);
+  hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), P, G,
+                     views->pair_offset, views->gauss_offset, views->cams, views->n_slots,
+                     tiling->width, tiling->height, tiling->tile_w, tiling->tile_h, proj->n_tiles,
+                     d_rec);
+  GS_LAUNCH_CHECK("gs_project_bwd");
+  return GS_OK;
+}
+
+}  // extern "C"

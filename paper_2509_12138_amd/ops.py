@@ -1,0 +1,304 @@
+"""PyTorch-facing wrappers of libgsmi: buffers, calls and autograd Functions.
+
+PyTorch supplies device memory and the stream only; every computation runs
+in the library's HIP kernels through the C ABI (include/gs.h).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import call
+
+PARAM_NAMES = ("mean", "log_scale", "quat", "opacity_logit", "color")
+PARAM_ROWS = {"mean": 3, "log_scale": 3, "quat": 4, "opacity_logit": 1, "color": 3}
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def stream_handle(device=None):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_f32(t, name):
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+
+
+# --------------------------------------------------------------------------
+# Structures
+# --------------------------------------------------------------------------
+
+def gaussians_struct(params, n=None):
+    for k in PARAM_NAMES:
+        _check_f32(params[k], k)
+    n = params["opacity_logit"].shape[-1] if n is None else n
+    return _lib.gs_gaussians(*[params[k].data_ptr() for k in PARAM_NAMES], n)
+
+
+def grads_struct(grads, n):
+    for k in PARAM_NAMES:
+        _check_f32(grads[k], "grad " + k)
+    return _lib.gs_grads(*[grads[k].data_ptr() for k in PARAM_NAMES], n)
+
+
+class Views:
+    """Device-side slot table: which Gaussians each image draws and with
+    which camera.  Camera records are the 80-byte gs_camera layout."""
+
+    def __init__(self, pair_offset, gauss_offset, cams_u8, device):
+        self.device = device
+        self.pair_offset_host = np.asarray(pair_offset, np.int64)
+        self.n_slots = len(self.pair_offset_host) - 1
+        self.total_pairs = int(self.pair_offset_host[-1])
+        self.pair_offset = torch.as_tensor(self.pair_offset_host, device=device)
+        self.gauss_offset = torch.as_tensor(np.asarray(gauss_offset, np.int64), device=device)
+        self.cams = cams_u8
+        self.struct = _lib.gs_views(self.n_slots, self.total_pairs, self.pair_offset.data_ptr(),
+                                    self.gauss_offset.data_ptr(), self.cams.data_ptr())
+
+    @staticmethod
+    def cams_to_device(cams_np, device):
+        raw = np.ascontiguousarray(cams_np).view(np.uint8).reshape(len(cams_np), 80)
+        return torch.as_tensor(raw, device=device)
+
+    @classmethod
+    def single(cls, n, cams_np, device="cuda"):
+        """One partition of n Gaussians seen through every camera in cams_np."""
+        V = len(cams_np)
+        po = np.arange(V + 1, dtype=np.int64) * n
+        return cls(po, np.zeros(V, np.int64), cls.cams_to_device(cams_np, device), device)
+
+    @classmethod
+    def batch(cls, counts, views_per_part, cams_dev_u8, device="cuda"):
+        """Partitions stored back to back (counts[p] Gaussians each), each
+        seen from views_per_part slots; cams_dev_u8 holds one record per slot."""
+        from .scene import views_table
+        po, go = views_table(counts, views_per_part)
+        return cls(po, go, cams_dev_u8, device)
+
+    def use_cameras(self, cams_u8):
+        """Point the slots at other camera records (device uint8 [S, 80])."""
+        assert cams_u8.shape[0] >= self.n_slots and cams_u8.dtype == torch.uint8
+        self.cams = cams_u8
+        self.struct.cams = cams_u8.data_ptr()
+
+
+def tiling_struct(width, height, tile=(16, 16)):
+    return _lib.gs_tiling(width, height, tile[0], tile[1])
+
+
+# --------------------------------------------------------------------------
+# Buffers of one rasterisation configuration
+# --------------------------------------------------------------------------
+
+class RasterBuffers:
+    """All device buffers one (views, tiling) configuration needs.
+
+    dup_capacity grows on overflow (see ``ensure_capacity``)."""
+
+    def __init__(self, views: Views, width, height, tile=(16, 16), dup_capacity=None,
+                 store_state=True):
+        dev = views.device
+        self.views = views
+        self.W, self.H, self.tile = width, height, tuple(tile)
+        self.tiling = tiling_struct(width, height, tile)
+        self.tiles_x = math.ceil(width / tile[0])
+        self.tiles_y = math.ceil(height / tile[1])
+        self.tiles_per_slot = self.tiles_x * self.tiles_y
+        S, m = views.n_slots, views.total_pairs
+        self.S, self.m = S, m
+        self.rec = torch.empty((max(m, 1), 12), dtype=torch.float32, device=dev)
+        self.tile_bbox = torch.empty((max(m, 1), 4), dtype=torch.int16, device=dev)
+        self.n_tiles = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+        self.proj = _lib.gs_projected(self.rec.data_ptr(), self.tile_bbox.data_ptr(),
+                                      self.n_tiles.data_ptr(), m)
+        self.ranges = torch.empty((S * self.tiles_per_slot, 2), dtype=torch.int32, device=dev)
+        self.image = torch.empty((S, 3, height, width), dtype=torch.float32, device=dev)
+        self.store_state = store_state
+        if store_state:
+            self.T_final = torch.empty((S, height, width), dtype=torch.float32, device=dev)
+            self.n_contrib = torch.empty((S, height, width), dtype=torch.int32, device=dev)
+        else:
+            self.T_final = self.n_contrib = None
+        self.d_rec = torch.zeros((max(m, 1), 9), dtype=torch.float32, device=dev)
+        self.status = torch.zeros(4, dtype=torch.int64, device=dev)
+        self.keys = self.ids = self.ws = None
+        self.dup_capacity = 0
+        self.ensure_capacity(dup_capacity or max(4 * m, 1024))
+
+    def ensure_capacity(self, cap):
+        cap = int(min(max(cap, 1024), 0xFFFFFFFF))
+        if cap <= self.dup_capacity:
+            return
+        dev = self.views.device
+        self.dup_capacity = cap
+        self.keys = torch.empty(cap, dtype=torch.int64, device=dev)
+        self.ids = torch.empty(cap, dtype=torch.int32, device=dev)
+        nbytes = _lib.load().gs_bin_sort_workspace_bytes(self.m, cap, C.byref(self.tiling),
+                                                         self.S)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+    # ---------------------------------------------------------- the calls
+
+    def project(self, gstruct, stream=None):
+        s = stream or stream_handle()
+        call("gs_project", C.byref(gstruct), C.byref(self.views.struct), C.byref(self.tiling),
+             C.byref(self.proj), s)
+
+    def bin_sort(self, stream=None):
+        s = stream or stream_handle()
+        call("gs_bin_sort", C.byref(self.proj), C.byref(self.views.struct), C.byref(self.tiling),
+             self.dup_capacity, _ptr(self.ws), self.ws.numel(), _ptr(self.keys), _ptr(self.ids),
+             _ptr(self.ranges), _ptr(self.status), s)
+
+    def raster_fwd(self, bg=(0.0, 0.0, 0.0), stream=None):
+        s = stream or stream_handle()
+        call("gs_raster_fwd", C.byref(self.proj), C.byref(self.views.struct),
+             C.byref(self.tiling), _ptr(self.ids), _ptr(self.ranges), _lib.F3(*bg),
+             _ptr(self.image), _ptr(self.T_final), _ptr(self.n_contrib), s)
+
+    def raster_bwd(self, d_image, bg=(0.0, 0.0, 0.0), mode=None, stream=None):
+        s = stream or stream_handle()
+        if mode is None:
+            mode = _lib.GS_BWD_STORED if self.store_state else _lib.GS_BWD_RECOMPUTE
+        _check_f32(d_image, "d_image")
+        call("gs_raster_bwd", C.byref(self.proj), C.byref(self.views.struct),
+             C.byref(self.tiling), _ptr(self.ids), _ptr(self.ranges), _lib.F3(*bg),
+             _ptr(self.T_final), _ptr(self.n_contrib), _ptr(d_image), int(mode),
+             _ptr(self.d_rec), s)
+
+    def project_bwd(self, gstruct, grads_struct_, stream=None):
+        s = stream or stream_handle()
+        call("gs_project_bwd", C.byref(gstruct), C.byref(self.views.struct),
+             C.byref(self.tiling), C.byref(self.proj), _ptr(self.d_rec),
+             C.byref(grads_struct_), s)
+
+    def zero_d_rec(self, stream=None):
+        s = stream or stream_handle()
+        call("gs_zero", _ptr(self.d_rec), self.d_rec.numel() * 4, s)
+
+    def check(self, stream=None):
+        """Synchronise and report (status, required duplicates)."""
+        s = stream or stream_handle()
+        req = C.c_int64(0)
+        st = _lib.load().gs_check_status(_ptr(self.status), s, C.byref(req))
+        return st, int(req.value)
+
+    def clear_status(self, stream=None):
+        call("gs_zero", _ptr(self.status), self.status.numel() * 8, stream or stream_handle())
+
+    def render_checked(self, gstruct, bg=(0.0, 0.0, 0.0), max_retry=3):
+        """project + bin_sort (+ capacity growth on overflow) + raster_fwd."""
+        for _ in range(max_retry + 1):
+            self.clear_status()
+            self.project(gstruct)
+            self.bin_sort()
+            st, req = self.check()
+            if st == _lib.GS_ERR_CAPACITY:
+                self.ensure_capacity(int(req * 1.25) + 1024)
+                continue
+            if st not in (_lib.GS_OK,):
+                raise _lib.GSError("gs_bin_sort", st, _lib.last_error())
+            self.raster_fwd(bg)
+            return req
+        raise RuntimeError("duplicate capacity could not be satisfied")
+
+
+# --------------------------------------------------------------------------
+# Loss and optimiser
+# --------------------------------------------------------------------------
+
+class LossBuffers:
+    def __init__(self, S, H, W, device="cuda"):
+        self.S, self.H, self.W = S, H, W
+        nbytes = _lib.load().gs_loss_workspace_bytes(S, H, W)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.loss = torch.zeros(S, dtype=torch.float32, device=device)
+        self.d_image = torch.empty((S, 3, H, W), dtype=torch.float32, device=device)
+
+    def __call__(self, image, target, mask=None, lam=0.2, grad_scale=1.0, status=None,
+                 stream=None):
+        _check_f32(image, "image"); _check_f32(target, "target")
+        if mask is not None and (mask.dtype != torch.uint8 or not mask.is_contiguous()):
+            raise ValueError("mask must be a contiguous uint8 tensor")
+        call("gs_loss", _ptr(image), _ptr(target), _ptr(mask), self.S, self.H, self.W,
+             float(lam), float(grad_scale), _ptr(self.ws), self.ws.numel(), _ptr(self.loss),
+             _ptr(self.d_image), _ptr(status), stream or stream_handle())
+        return self.loss, self.d_image
+
+
+def adam_groups(params, grads, m, v, lrs):
+    arr = (_lib.gs_adam_group * len(PARAM_NAMES))()
+    for i, k in enumerate(PARAM_NAMES):
+        arr[i] = _lib.gs_adam_group(params[k].data_ptr(), grads[k].data_ptr(), m[k].data_ptr(),
+                                    v[k].data_ptr(), params[k].numel(), float(lrs[k]))
+    return arr
+
+
+def adam_step(groups, step, beta1=0.9, beta2=0.999, eps=1e-15, zero_grad=True, stream=None):
+    call("gs_adam", groups, len(groups), beta1, beta2, eps, int(step), int(bool(zero_grad)),
+         stream or stream_handle())
+
+
+# --------------------------------------------------------------------------
+# autograd
+# --------------------------------------------------------------------------
+
+class RenderFn(torch.autograd.Function):
+    """image = render(Gaussians) through the library's projection, binning,
+    sort and compositing; backward runs the hand-written reverse replay and
+    the projection backward."""
+
+    @staticmethod
+    def forward(ctx, mean, log_scale, quat, opacity_logit, color, bufs: RasterBuffers, bg,
+                mode):
+        params = dict(mean=mean, log_scale=log_scale, quat=quat, opacity_logit=opacity_logit,
+                      color=color)
+        gst = gaussians_struct(params)
+        bufs.render_checked(gst, bg)
+        ctx.bufs, ctx.bg, ctx.mode = bufs, bg, mode
+        ctx.save_for_backward(mean, log_scale, quat, opacity_logit, color)
+        return bufs.image.clone()
+
+    @staticmethod
+    def backward(ctx, d_image):
+        mean, log_scale, quat, opacity_logit, color = ctx.saved_tensors
+        params = dict(mean=mean, log_scale=log_scale, quat=quat, opacity_logit=opacity_logit,
+                      color=color)
+        bufs = ctx.bufs
+        grads = {k: torch.zeros_like(v) for k, v in params.items()}
+        bufs.zero_d_rec()
+        bufs.raster_bwd(d_image.contiguous(), ctx.bg, ctx.mode)
+        n = opacity_logit.shape[-1]
+        bufs.project_bwd(gaussians_struct(params), grads_struct(grads, n))
+        return (grads["mean"], grads["log_scale"], grads["quat"], grads["opacity_logit"],
+                grads["color"], None, None, None)
+
+
+def render(params, bufs: RasterBuffers, bg=(0.0, 0.0, 0.0), mode=None):
+    if mode is None:
+        mode = _lib.GS_BWD_STORED if bufs.store_state else _lib.GS_BWD_RECOMPUTE
+    return RenderFn.apply(params["mean"], params["log_scale"], params["quat"],
+                          params["opacity_logit"], params["color"], bufs, tuple(bg), mode)
+
+
+class LossFn(torch.autograd.Function):
+    """Masked (1 - lam) L1 + lam D-SSIM per image (gs_loss); returns [S]."""
+
+    @staticmethod
+    def forward(ctx, image, target, mask, lam, lbufs: LossBuffers):
+        loss, d_image = lbufs(image.contiguous(), target, mask, lam, 1.0)
+        ctx.save_for_backward(d_image.clone())
+        return loss.clone()
+
+    @staticmethod
+    def backward(ctx, d_loss):
+        (d_image,) = ctx.saved_tensors
+        return d_image * d_loss.view(-1, 1, 1, 1), None, None, None, None

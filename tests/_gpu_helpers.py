@@ -1,0 +1,54 @@
+"""Shared helpers of the GPU parity tests (inputs from the scene module,
+expected values from the oracle)."""
+import math
+import sys
+
+import numpy as np
+
+import oracle
+from paper_2509_12138_amd import scene
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(params, torch):
+    return {k: torch.as_tensor(np.ascontiguousarray(v, np.float32)).cuda() for k, v in params.items()}
+
+
+def rec_to_oracle(rec, tile_bbox, n_tiles):
+    """Oracle-side SoA view of FP32 projected records [m, 12] (+ bboxes)."""
+    rec = np.asarray(rec, np.float64)
+    tb = np.asarray(tile_bbox, np.int64).astype(np.int32) & 0xFFFF
+    return dict(mean2d=rec[:, 0:2].T.copy(), conic=rec[:, 2:5].T.copy(), depth=rec[:, 9].copy(),
+                opacity=rec[:, 5].copy(), rgb=rec[:, 6:9].T.copy(),
+                tile_bbox=np.ascontiguousarray(tb.T), valid=(np.asarray(n_tiles) > 0).astype(np.int32))
+
+
+def grad_tolerance_check(g, r, abs_mass, amb_mass, rel=1e-3, floor=0.01):
+    """|g - r| <= rel * max(|r|, floor * A) + A_amb per element (A = sum of the
+    absolute per-pixel contributions); returns (ok, worst ratio)."""
+    bound = rel * np.maximum(np.abs(r), floor * abs_mass) + amb_mass + 1e-12
+    ratio = np.abs(g - r) / bound
+    return bool(np.all(ratio <= 1.0)), float(ratio.max(initial=0.0))
+
+
+def surface_scene(n, seed, opacity=0.1):
+    """n Gaussians on the bumpy-sphere isosurface with k-NN isotropic scales."""
+    pts, nrm = scene.sample_surface(scene.field_sphere_sines, n, 64, seed=seed)
+    d = scene.knn_mean_distance(pts, 3)
+    return scene.gaussians_from_points(pts, nrm, d, opacity=opacity)
+
+
+def perturbed(params, seed, amount=0.3):
+    """Anisotropic, rotated, varied-opacity version of surface Gaussians."""
+    rng = np.random.default_rng(seed)
+    p = {k: v.copy() for k, v in params.items()}
+    n = p["opacity_logit"].shape[0]
+    p["log_scale"] = (p["log_scale"] + rng.normal(0, amount, (3, n))).astype(np.float32)
+    p["quat"] = (p["quat"] + rng.normal(0, 0.5, (4, n))).astype(np.float32)
+    p["opacity_logit"] = rng.normal(-0.5, 1.5, n).astype(np.float32)
+    p["color"] = (p["color"] + rng.normal(0, 0.5, (3, n))).astype(np.float32)
+    return p

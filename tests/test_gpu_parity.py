@@ -1,0 +1,351 @@
+"""GPU parity: every hot-path call of libgsmi (through the C ABI) against the
+FP64 oracle on the same seeded inputs.
+
+Tolerances: tile ids / sorted lists / ranges bit-exact; projection 1e-5
+relative; images max-abs 1e-4 outside ambiguous pixels (decisions within
+their guard band, see the oracle); gradients 1e-3 relative with a
+condition-aware floor; loss and Adam 1e-5 / 1e-6 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_12138_amd import scene
+from _gpu_helpers import (grad_tolerance_check, perturbed, rec_to_oracle, say, surface_scene,
+                          to_dev)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SAME_RECORD_BITS = 1 | 2 | 4 | 8      # oracle ambiguity reasons other than depth ties
+
+
+@pytest.fixture(scope="module")
+def ops(gpu):
+    from paper_2509_12138_amd import ops as _ops
+    return _ops
+
+
+def make_bufs(ops, params, cams, W, H, tile=(16, 16), cap=None, store=True):
+    n = params["opacity_logit"].shape[0]
+    views = ops.Views.single(n, cams)
+    return ops.RasterBuffers(views, W, H, tile, dup_capacity=cap, store_state=store)
+
+
+# ------------------------------------------------------------------ projection
+
+@pytest.mark.parametrize("seed,W,H", [(11, 160, 120), (12, 333, 197)])
+def test_project_matches_oracle(ops, seed, W, H):
+    say("project", seed, W, H)
+    params = perturbed(surface_scene(3000, seed), seed)
+    cams = scene.orbit_cameras(5, W, H)
+    bufs = make_bufs(ops, params, cams, W, H)
+    bufs.project(ops.gaussians_struct(to_dev(params, torch)))
+    torch.cuda.synchronize()
+    rec = bufs.rec.cpu().numpy(); tb = bufs.tile_bbox.cpu().numpy().astype(np.int64) & 0xFFFF
+    nt = bufs.n_tiles.cpu().numpy()
+    n = 3000
+    amb_total = 0
+    for v in range(5):
+        o = oracle.project(params, scene.camera_dict(cams[v]))
+        sl = slice(v * n, (v + 1) * n)
+        r, t_, ntv = rec[sl], tb[sl], nt[sl]
+        valid = o["valid"].astype(bool)
+        # near-boundary decisions may legitimately differ: bbox edges within
+        # 1e-4 px of an integer (FP32 error of m +/- h is below 1e-4 px at
+        # these image sizes) and opacities at the 1/255 support threshold
+        kappa = 2 * np.log(np.maximum(255 * o["opacity"], 1e-300))
+        hx = np.sqrt(np.maximum(kappa, 0) * o["cov2d"][0]); hy = np.sqrt(np.maximum(kappa, 0) * o["cov2d"][2])
+        edges = np.stack([o["mean2d"][0] - hx, o["mean2d"][0] + hx, o["mean2d"][1] - hy, o["mean2d"][1] + hy])
+        near = np.any(np.abs(edges - np.round(edges)) < 1e-4, axis=0) | (np.abs(255 * o["opacity"] - 1) < 1e-4)
+        amb_total += int(near.sum())
+        ok = ~near
+        np.testing.assert_array_equal(ntv[ok] > 0, valid[ok])
+        both = ok & valid
+        assert both.sum() > 500
+        np.testing.assert_array_equal(t_[both], o["tile_bbox"].T[both])
+        np.testing.assert_array_equal(ntv[both], o["n_tiles"][both])
+        np.testing.assert_allclose(r[both, 0:2], o["mean2d"].T[both], rtol=1e-5, atol=1e-4)
+        cscale = np.abs(o["conic"]).max(0)[both][:, None]
+        assert np.all(np.abs(r[both, 2:5] - o["conic"].T[both]) <= 1e-5 * cscale + 1e-9)
+        np.testing.assert_allclose(r[both, 5], o["opacity"][both], rtol=1e-5)
+        np.testing.assert_allclose(r[both, 6:9], o["rgb"].T[both], rtol=1e-5, atol=1e-6)
+        np.testing.assert_allclose(r[both, 9], o["depth"][both], rtol=1e-6)
+        assert np.all(r[:, 10].view(np.int32) == v)
+    assert amb_total <= 5 * n * 2e-3
+
+
+# ------------------------------------------------------------------ bin + sort
+
+def synthetic_pairs(m, tiles_x, tiles_y, S, seed, zero_frac=0.2, max_span=4):
+    rng = np.random.default_rng(seed)
+    tx0 = rng.integers(0, tiles_x, m); ty0 = rng.integers(0, tiles_y, m)
+    tx1 = np.minimum(tx0 + rng.integers(0, max_span, m), tiles_x - 1)
+    ty1 = np.minimum(ty0 + rng.integers(0, max_span, m), tiles_y - 1)
+    tb = np.stack([tx0, ty0, tx1, ty1], 1).astype(np.int32)
+    nt = ((tx1 - tx0 + 1) * (ty1 - ty0 + 1)).astype(np.int32)
+    nt[rng.uniform(size=m) < zero_frac] = 0
+    tb[nt == 0] = 0
+    depth = rng.uniform(0.3, 6.0, m).astype(np.float32)
+    depth[: m // 10] = depth[m // 10: 2 * (m // 10)]              # exact ties
+    per = m // S
+    slot = np.minimum(np.arange(m) // per, S - 1).astype(np.int32)
+    return tb, nt, depth, slot
+
+
+def run_binsort(ops, tb, nt, depth, slot, W, H, tile, S, cap):
+    m = len(nt)
+    counts = [int((slot == s).sum()) for s in range(S)]
+    po = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    cams = scene.orbit_cameras(S, W, H)
+    views = ops.Views(po, np.zeros(S, np.int64), ops.Views.cams_to_device(cams, "cuda"), "cuda")
+    bufs = ops.RasterBuffers(views, W, H, tile, dup_capacity=cap)
+    rec = np.zeros((m, 12), np.float32)
+    rec[:, 9] = depth
+    rec[:, 10] = slot.view(np.float32)
+    bufs.rec.copy_(torch.as_tensor(rec))
+    bufs.tile_bbox.copy_(torch.as_tensor(tb.astype(np.uint16).view(np.int16)))
+    bufs.n_tiles.copy_(torch.as_tensor(nt))
+    bufs.clear_status()
+    bufs.bin_sort()
+    st, req = bufs.check()
+    return bufs, st, req
+
+
+@pytest.mark.parametrize("m,S,tile,W,H,seed", [
+    (5000, 1, (16, 16), 300, 200, 0),        # several scan blocks, one slot
+    (9000, 3, (8, 8), 130, 75, 1),           # ragged tiles, three slots
+    (300000, 2, (16, 16), 1920, 1080, 2),    # many radix blocks, 1080p tiles
+])
+def test_bin_sort_bit_exact(ops, m, S, tile, W, H, seed):
+    say("bin_sort", m, S, tile, W, H)
+    tx, ty = math.ceil(W / tile[0]), math.ceil(H / tile[1])
+    tb, nt, depth, slot = synthetic_pairs(m, tx, ty, S, seed)
+    K = int(nt.sum())
+    bufs, st, req = run_binsort(ops, tb, nt, depth, slot, W, H, tile, S, cap=K + 17)
+    assert st == 0 and req == K
+    keys, ids, ranges = oracle.bin_sort(tb, nt, depth, slot, tx, tx * ty, S)
+    gk = bufs.keys[:K].cpu().numpy().view(np.uint64)
+    gi = bufs.ids[:K].cpu().numpy().view(np.uint32)
+    gr = bufs.ranges.cpu().numpy().view(np.uint32)
+    np.testing.assert_array_equal(gk, keys)
+    np.testing.assert_array_equal(gi, ids)
+    np.testing.assert_array_equal(gr, ranges)
+
+
+def test_bin_sort_overflow_and_empty(ops):
+    say("bin_sort overflow/empty")
+    tb, nt, depth, slot = synthetic_pairs(4000, 20, 12, 1, 5)
+    K = int(nt.sum())
+    bufs, st, req = run_binsort(ops, tb, nt, depth, slot, 320, 192, (16, 16), 1, cap=K // 2)
+    assert st == -3 and req == K                      # GS_ERR_CAPACITY, true count reported
+    bufs.ensure_capacity(req)
+    bufs.clear_status(); bufs.bin_sort()
+    st, req2 = bufs.check()
+    assert st == 0 and req2 == K
+    keys, ids, _ = oracle.bin_sort(tb, nt, depth, slot, 20, 240, 1)
+    np.testing.assert_array_equal(bufs.ids[:K].cpu().numpy().view(np.uint32), ids)
+    # all pairs culled: no duplicates, all ranges empty
+    nt0 = np.zeros_like(nt)
+    bufs, st, req = run_binsort(ops, tb * 0, nt0, depth, slot, 320, 192, (16, 16), 1, cap=100)
+    assert st == 0 and req == 0
+    assert int(bufs.ranges.abs().sum()) == 0
+
+
+# ------------------------------------------------------------------ rasteriser
+
+def projected_inputs(ops, params, cams, W, H, tile, store=True):
+    bufs = make_bufs(ops, params, cams, W, H, tile, store=store)
+    gst = ops.gaussians_struct(to_dev(params, torch))
+    bufs.render_checked(gst, bg=(0.0, 0.0, 0.0))
+    torch.cuda.synchronize()
+    return bufs, gst
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8), (16, 32)])
+def test_raster_fwd_matches_oracle_on_same_records(ops, tile):
+    say("raster_fwd", tile)
+    W, H = 150, 110                                      # ragged tail on both axes
+    params = perturbed(surface_scene(6000, 21), 21)
+    cams = scene.orbit_cameras(3, W, H)
+    bg = (0.1, 0.3, 0.2)
+    bufs = make_bufs(ops, params, cams, W, H, tile)
+    gst = ops.gaussians_struct(to_dev(params, torch))
+    bufs.render_checked(gst, bg=bg)
+    torch.cuda.synchronize()
+    rec, tb, nt = bufs.rec.cpu().numpy(), bufs.tile_bbox.cpu().numpy(), bufs.n_tiles.cpu().numpy()
+    img = bufs.image.cpu().numpy(); Tf = bufs.T_final.cpu().numpy(); nc = bufs.n_contrib.cpu().numpy()
+    n = 6000
+    for v in range(3):
+        sl = slice(v * n, (v + 1) * n)
+        o = oracle.render(rec_to_oracle(rec[sl], tb[sl], nt[sl]), W, H, tile=tile, bg=bg)
+        # both sides sort the same FP32 depths, so near-equal depths are not
+        # ambiguous here: only the alpha / power / cut-off guard bands count
+        amb = (o["ambiguity"] & SAME_RECORD_BITS) != 0
+        assert amb.mean() <= 1e-3
+        ok = ~amb
+        err = np.abs(img[v] - o["image"])[:, ok]
+        assert err.max() <= 1e-4, err.max()
+        assert np.abs(Tf[v] - o["T_final"])[ok].max() <= 1e-4
+        np.testing.assert_array_equal(nc[v][ok], o["n_contrib"][ok])
+        assert (o["n_blended"] > 0).mean() > 0.2
+
+
+def test_image_independent_of_tile_shape(ops):
+    say("tile-shape invariance")
+    W, H = 128, 96
+    params = perturbed(surface_scene(4000, 31), 31)
+    cams = scene.orbit_cameras(2, W, H)
+    imgs = []
+    for tile in [(16, 16), (8, 8), (32, 16)]:
+        bufs, _ = projected_inputs(ops, params, cams, W, H, tile)
+        imgs.append(bufs.image.cpu().numpy())
+    for im in imgs[1:]:
+        np.testing.assert_array_equal(im, imgs[0])
+
+
+def test_end_to_end_image_matches_fp64_oracle(ops):
+    say("end-to-end image")
+    W, H = 128, 128
+    params = surface_scene(4096, 1)
+    cams = scene.orbit_cameras(4, W, H)
+    bufs, _ = projected_inputs(ops, params, cams, W, H, (16, 16))
+    img = bufs.image.cpu().numpy()
+    for v in range(4):
+        o = oracle.render(oracle.project(params, scene.camera_dict(cams[v])), W, H)
+        amb = o["ambiguous"]
+        # near-equal depths of neighbouring surface Gaussians dominate the
+        # ambiguous set (their FP32 order may differ from FP64)
+        assert amb.mean() <= 1e-2
+        err = np.abs(img[v] - o["image"])[:, ~amb]
+        assert err.max() <= 1e-4, err.max()
+
+
+def test_permutation_invariance_gpu(ops):
+    say("permutation invariance")
+    W, H = 96, 80
+    params = perturbed(surface_scene(3000, 41), 41)
+    perm = np.random.default_rng(0).permutation(3000)
+    pp = {k: np.ascontiguousarray(v[..., perm]) for k, v in params.items()}
+    cams = scene.orbit_cameras(2, W, H)
+    a, _ = projected_inputs(ops, params, cams, W, H, (16, 16))
+    b, _ = projected_inputs(ops, pp, cams, W, H, (16, 16))
+    np.testing.assert_array_equal(a.image.cpu().numpy(), b.image.cpu().numpy())
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_raster_bwd_matches_oracle(ops, mode, tile):
+    say("raster_bwd mode", mode, tile)
+    W, H = 120, 90
+    params = perturbed(surface_scene(4000, 51), 51)
+    cams = scene.orbit_cameras(2, W, H)
+    bg = (0.2, 0.1, 0.05)
+    bufs = make_bufs(ops, params, cams, W, H, tile, store=(mode == 0))
+    gst = ops.gaussians_struct(to_dev(params, torch))
+    bufs.render_checked(gst, bg=bg)
+    rng = np.random.default_rng(7)
+    dI = rng.normal(size=(2, 3, H, W)).astype(np.float32)
+    bufs.zero_d_rec()
+    bufs.raster_bwd(torch.as_tensor(dI).cuda(), bg=bg, mode=mode)
+    torch.cuda.synchronize()
+    rec, tb, nt = bufs.rec.cpu().numpy(), bufs.tile_bbox.cpu().numpy(), bufs.n_tiles.cpu().numpy()
+    drec = bufs.d_rec.cpu().numpy().astype(np.float64)
+    n = 4000
+    for v in range(2):
+        sl = slice(v * n, (v + 1) * n)
+        po = rec_to_oracle(rec[sl], tb[sl], nt[sl])
+        o = oracle.render_bwd(po, W, H, dI[v], tile=tile, bg=bg, amb_bits=SAME_RECORD_BITS)
+        ref = np.concatenate([o["d_mean2d"], o["d_conic"], o["d_opacity"][None], o["d_rgb"]]).T
+        ok, worst = grad_tolerance_check(drec[sl], ref, o["abs_mass"].T, o["amb_mass"].T)
+        assert ok, worst
+        for c in range(9):
+            nr = np.linalg.norm(drec[sl][:, c] - ref[:, c]) / max(np.linalg.norm(ref[:, c]), 1e-30)
+            assert nr <= 1e-3, (c, nr)
+
+
+def test_project_bwd_matches_oracle(ops):
+    say("project_bwd")
+    W, H = 200, 150
+    params = perturbed(surface_scene(5000, 61), 61)
+    cams = scene.orbit_cameras(3, W, H)
+    bufs = make_bufs(ops, params, cams, W, H)
+    dp = to_dev(params, torch)
+    gst = ops.gaussians_struct(dp)
+    bufs.project(gst)
+    rng = np.random.default_rng(3)
+    m = 3 * 5000
+    drec = rng.normal(size=(m, 9)).astype(np.float32)
+    bufs.d_rec.copy_(torch.as_tensor(drec))
+    grads = {k: torch.zeros_like(v) for k, v in dp.items()}
+    bufs.project_bwd(gst, ops.grads_struct(grads, 5000))
+    torch.cuda.synchronize()
+    nt = bufs.n_tiles.cpu().numpy()
+    ref = {k: np.zeros(v.shape) for k, v in params.items()}
+    for v in range(3):
+        sl = slice(v * 5000, (v + 1) * 5000)
+        d = drec[sl].astype(np.float64) * (nt[sl] > 0)[:, None]
+        g = oracle.project_bwd(params, scene.camera_dict(cams[v]),
+                               dict(d_mean2d=d[:, 0:2].T, d_conic=d[:, 2:5].T, d_opacity=d[:, 5],
+                                    d_rgb=d[:, 6:9].T))
+        for k in ref:
+            ref[k] += g[k]
+    for k in ref:
+        got = grads[k].cpu().numpy().astype(np.float64)
+        r = ref[k]
+        nr = np.linalg.norm(got - r) / max(np.linalg.norm(r), 1e-30)
+        assert nr <= 1e-4, (k, nr)
+        scale = np.abs(r).max()
+        assert np.all(np.abs(got - r) <= 1e-3 * np.abs(r) + 1e-5 * scale), k
+
+
+# ------------------------------------------------------------------ loss, Adam
+
+@pytest.mark.parametrize("S,H,W,lam", [(2, 70, 95, 0.2), (1, 33, 40, 0.5)])
+def test_loss_matches_oracle(ops, S, H, W, lam):
+    say("loss", S, H, W)
+    rng = np.random.default_rng(9)
+    img = rng.uniform(0, 1, (S, 3, H, W)).astype(np.float32)
+    tgt = np.clip(img + rng.normal(0, 0.2, img.shape), 0, 1).astype(np.float32)
+    mask = (rng.uniform(size=(S, H, W)) > 0.3).astype(np.uint8)
+    L = ops.LossBuffers(S, H, W)
+    status = torch.zeros(4, dtype=torch.int64, device="cuda")
+    loss, dI = L(torch.as_tensor(img).cuda(), torch.as_tensor(tgt).cuda(),
+                 torch.as_tensor(mask).cuda(), lam=lam, grad_scale=0.5, status=status)
+    torch.cuda.synchronize()
+    loss = loss.cpu().numpy(); dI = dI.cpu().numpy()
+    for s in range(S):
+        o = oracle.loss(img[s], tgt[s], mask[s], lam=lam)
+        assert abs(loss[s] - o["loss"]) <= 1e-5 * abs(o["loss"]), (loss[s], o["loss"])
+        r = 0.5 * o["d_image"]
+        assert np.abs(dI[s] - r).max() <= 1e-5 * np.abs(r).max() + 1e-12
+    assert int(status[0]) == 0
+
+
+def test_adam_matches_oracle(ops):
+    say("adam")
+    rng = np.random.default_rng(10)
+    sizes = {"mean": (3, 1001), "log_scale": (3, 1001), "quat": (4, 1001), "opacity_logit": (1001,),
+             "color": (3, 1001)}
+    p = {k: rng.normal(size=s).astype(np.float32) for k, s in sizes.items()}
+    lrs = {"mean": 1e-3, "log_scale": 5e-3, "quat": 1e-3, "opacity_logit": 5e-2, "color": 2.5e-3}
+    dp = {k: torch.as_tensor(v).cuda() for k, v in p.items()}
+    dm = {k: torch.zeros_like(v) for k, v in dp.items()}
+    dv = {k: torch.zeros_like(v) for k, v in dp.items()}
+    dg = {k: torch.zeros_like(v) for k, v in dp.items()}
+    groups = ops.adam_groups(dp, dg, dm, dv, lrs)
+    ref = {k: (v.astype(np.float64), np.zeros(v.shape), np.zeros(v.shape)) for k, v in p.items()}
+    for step in range(1, 6):
+        g = {k: rng.normal(size=s).astype(np.float32) for k, s in sizes.items()}
+        for k in g:
+            dg[k].copy_(torch.as_tensor(g[k]))
+        ops.adam_step(groups, step, zero_grad=True)
+        for k in g:
+            ref[k] = oracle.adam(ref[k][0], g[k], ref[k][1], ref[k][2], lrs[k], step)
+        torch.cuda.synchronize()
+        for k in g:
+            assert float(dg[k].abs().max()) == 0.0
+            np.testing.assert_allclose(dp[k].cpu().numpy(), ref[k][0], rtol=2e-6, atol=2e-7)
+            np.testing.assert_allclose(dm[k].cpu().numpy(), ref[k][1], rtol=1e-5, atol=1e-7)
