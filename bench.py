@@ -74,11 +74,12 @@ def cpu_baseline(params, cam, target_seconds):
         oracle.render_bwd(proj, W, H, d_image, window=win)
         return time.perf_counter() - t
 
-    side = 16
-    dt = run(side)
-    # scale the window so the timed sample takes about target_seconds
-    per_px = dt / (side * side)
-    side = int(max(16, min(512, (target_seconds / max(per_px, 1e-9)) ** 0.5)))
+    # fixed cost (sorting) + per-pixel cost from two small windows, then a
+    # window sized so that the timed sample takes about target_seconds
+    t16, t32 = run(16), run(32)
+    per_px = max((t32 - t16) / (32 * 32 - 16 * 16), 1e-9)
+    fixed = max(t16 - per_px * 256, 0.0)
+    side = int(max(16, min(768, ((target_seconds - fixed) / per_px) ** 0.5)))
     dt = run(side)
     return {
         "value": (side * side) / dt / 1e6,

@@ -94,24 +94,34 @@ __device__ __forceinline__ float wave_sum(float v) { return lane63(wave_sum_to_l
 
 // A Gaussian as staged in LDS for the rasterisers: mean, log2-scaled conic
 // (A, B, C) so that log2 of the Gaussian falloff is A dx^2 + B dx dy + C dy^2,
-// opacity and colour.
+// opacity, colour and the log2-domain skip threshold thr = -log2(255 o):
+// o 2^p2 < 1/255 exactly when p2 < thr, so skipped entries never reach exp.
 struct alignas(16) Splat {
-  float mx, my, A, B, C, o, r, g, b, pad0, pad1, pad2;
+  float mx, my, A, B, C, o, r, g, b, thr, pad1, pad2;
 };
 
-// log2-domain falloff exponent at offset (dx, dy).  Written with explicit
-// fused operations so that the forward and backward kernels evaluate it
-// bit-identically (their skip/stop decisions must agree).
-__device__ __forceinline__ float splat_p2(float A, float B, float C, float dx, float dy) {
-  float u = __fmul_rn(A, dx);
-  u = __fmaf_rn(B, dy, u);           // A dx + B dy
-  float v = __fmul_rn(C, dy);        // C dy
-  float w = __fmul_rn(v, dy);        // C dy^2
-  return __fmaf_rn(u, dx, w);        // A dx^2 + B dx dy + C dy^2
+// log2-domain falloff exponents of the PX pixels a lane owns in one column
+// (same dx, rows fy[k]).  Explicit rounded operations keep the forward and
+// backward kernels bit-identical, so their skip/stop decisions agree.
+template <int PX>
+__device__ __forceinline__ void splat_p2_column(const Splat& s, float dx, const float* fy,
+                                                float* p2) {
+  const float adx2 = __fmul_rn(__fmul_rn(s.A, dx), dx);
+  const float bdx = __fmul_rn(s.B, dx);
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    const float dy = __fsub_rn(fy[k], s.my);
+    const float t = __fmaf_rn(s.C, dy, bdx);     // C dy + B dx
+    p2[k] = __fmaf_rn(dy, t, adx2);              // A dx^2 + B dx dy + C dy^2
+  }
 }
 
-// Unclamped alpha o * 2^p2 (the clamp and the 1/255 skip are applied by the
-// caller).  __builtin_amdgcn_exp2f is the hardware v_exp_f32.
+// Entry passes the skip tests: falloff exponent <= 0 and alpha >= 1/255.
+__device__ __forceinline__ bool splat_pass(const Splat& s, float p2) {
+  return (p2 <= 0.0f) && (p2 >= s.thr);
+}
+
+// Unclamped alpha o * 2^p2; __builtin_amdgcn_exp2f is the hardware v_exp_f32.
 __device__ __forceinline__ float splat_gauss(float p2) { return __builtin_amdgcn_exp2f(p2); }
 
 }  // namespace gsmi

@@ -30,7 +30,7 @@ __device__ __forceinline__ Splat load_splat(const float* __restrict__ rec, uint3
   const float4* r = reinterpret_cast<const float4*>(rec + (int64_t)id * GS_REC_STRIDE);
   float4 a = r[0], b = r[1], c = r[2];
   Splat s;
-  s.pad0 = s.pad1 = s.pad2 = 0.0f;
+  s.pad1 = s.pad2 = 0.0f;
   s.mx = a.x;
   s.my = a.y;
   s.A = -0.5f * kLog2e * a.z;
@@ -40,6 +40,7 @@ __device__ __forceinline__ Splat load_splat(const float* __restrict__ rec, uint3
   s.r = b.z;
   s.g = b.w;
   s.b = c.x;
+  s.thr = -__builtin_amdgcn_logf(255.0f * b.y);   // -log2(255 o)
   return s;
 }
 
@@ -79,16 +80,21 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
     __syncthreads();
     for (int j = 0; j < n; ++j) {
       const Splat sp = s_splat[j];
-      const float dx = fx - sp.mx;
+      const float dx = __fsub_rn(fx, sp.mx);
+      float p2[PX];
+      splat_p2_column<PX>(sp, dx, fy, p2);
+      bool pass[PX], any = false;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        pass[k] = !done[k] && splat_pass(sp, p2[k]);
+        any = any || pass[k];
+      }
+      if (!__any(any)) continue;                    // whole wave skips this entry
       const int pos = (int)(b0 - start) + j + 1;
 #pragma unroll
       for (int k = 0; k < PX; ++k) {
-        if (done[k]) continue;
-        const float dy = fy[k] - sp.my;
-        const float p2 = splat_p2(sp.A, sp.B, sp.C, dx, dy);
-        if (p2 > 0.0f) continue;
-        const float alpha = fminf(kAlphaMax, sp.o * splat_gauss(p2));
-        if (alpha < kAlphaMin) continue;
+        if (!pass[k]) continue;
+        const float alpha = fminf(kAlphaMax, sp.o * splat_gauss(p2[k]));
         const float Tn = T[k] * (1.0f - alpha);
         if (Tn < kTMin) {
           done[k] = true;
@@ -198,7 +204,8 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd(
       last[k] = inside[k] ? n_contrib[o] : 0;
     }
   }
-  float dI[PX][3], acc[PX][3];
+  // dIacc = dI . (sum of the colour blended behind + bg T_final), per pixel
+  float dI[PX][3], dIacc[PX];
   const float* dimg = d_image + (int64_t)slot * 3 * HW;
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
@@ -206,9 +213,7 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd(
     dI[k][0] = inside[k] ? dimg[o] : 0.0f;
     dI[k][1] = inside[k] ? dimg[HW + o] : 0.0f;
     dI[k][2] = inside[k] ? dimg[2 * HW + o] : 0.0f;
-    acc[k][0] = bg0 * T[k];
-    acc[k][1] = bg1 * T[k];
-    acc[k][2] = bg2 * T[k];
+    dIacc[k] = T[k] * (dI[k][0] * bg0 + dI[k][1] * bg1 + dI[k][2] * bg2);
   }
   int lmax = 0;
 #pragma unroll
@@ -227,54 +232,61 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd(
     for (int j = n - 1; j >= 0; --j) {
       const Splat sp = s_splat[j];
       const int pos = lo + j + 1;
-      const float dx = fx - sp.mx;
-      float g_mx = 0.f, g_my = 0.f, g_q11 = 0.f, g_q12 = 0.f, g_q22 = 0.f, g_o = 0.f;
-      float g_r = 0.f, g_g = 0.f, g_b = 0.f;
-      bool any = false;
+      const float dx = __fsub_rn(fx, sp.mx);
+      float p2[PX];
+      splat_p2_column<PX>(sp, dx, fy, p2);
+      bool pass[PX], any = false;
 #pragma unroll
       for (int k = 0; k < PX; ++k) {
-        if (pos > last[k]) continue;
-        const float dy = fy[k] - sp.my;
-        const float p2 = splat_p2(sp.A, sp.B, sp.C, dx, dy);
-        if (p2 > 0.0f) continue;
-        const float gss = splat_gauss(p2);
-        const float a = sp.o * gss;
-        const float alpha = fminf(kAlphaMax, a);
-        if (alpha < kAlphaMin) continue;
-        any = true;
-        const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
-        const float Tb = T[k] * inv;             // transmittance before this Gaussian
-        const float w = alpha * Tb;
-        g_r = fmaf(dI[k][0], w, g_r);
-        g_g = fmaf(dI[k][1], w, g_g);
-        g_b = fmaf(dI[k][2], w, g_b);
-        float dLda = dI[k][0] * (sp.r * Tb - acc[k][0] * inv);
-        dLda = fmaf(dI[k][1], sp.g * Tb - acc[k][1] * inv, dLda);
-        dLda = fmaf(dI[k][2], sp.b * Tb - acc[k][2] * inv, dLda);
-        acc[k][0] = fmaf(sp.r, w, acc[k][0]);
-        acc[k][1] = fmaf(sp.g, w, acc[k][1]);
-        acc[k][2] = fmaf(sp.b, w, acc[k][2]);
-        T[k] = Tb;
-        if (a < kAlphaMax) {
-          const float G = dLda * alpha;          // dL/d(power)
-          g_o = fmaf(dLda, gss, g_o);
-          g_mx = fmaf(G, 2.0f * sp.A * dx + sp.B * dy, g_mx);
-          g_my = fmaf(G, 2.0f * sp.C * dy + sp.B * dx, g_my);
-          g_q11 = fmaf(G, dx * dx, g_q11);
-          g_q12 = fmaf(G, dx * dy, g_q12);
-          g_q22 = fmaf(G, dy * dy, g_q22);
-        }
+        pass[k] = (pos <= last[k]) && splat_pass(sp, p2[k]);
+        any = any || pass[k];
       }
       if (!__any(any)) continue;
+      // per-lane sums over the lane's pixels; the geometric gradients of the
+      // lane follow from sG = sum G, sGdy = sum G dy, sGdy2 = sum G dy^2 with
+      // G = dL/d(power) (dx is shared by the lane's column)
+      float sG = 0.f, sGdy = 0.f, sGdy2 = 0.f, so = 0.f, sr = 0.f, sg = 0.f, sb = 0.f;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        if (!pass[k]) continue;
+        const float gss = splat_gauss(p2[k]);
+        const float a = sp.o * gss;
+        const float alpha = fminf(kAlphaMax, a);
+        const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+        const float Tb = T[k] * inv;                 // transmittance in front of it
+        const float w = alpha * Tb;
+        const float dIc = fmaf(dI[k][2], sp.b, fmaf(dI[k][1], sp.g, dI[k][0] * sp.r));
+        const float dLda = fmaf(Tb, dIc, -inv * dIacc[k]);
+        dIacc[k] = fmaf(w, dIc, dIacc[k]);
+        T[k] = Tb;
+        sr = fmaf(dI[k][0], w, sr);
+        sg = fmaf(dI[k][1], w, sg);
+        sb = fmaf(dI[k][2], w, sb);
+        if (a < kAlphaMax) {
+          const float G = dLda * alpha;
+          const float dy = __fsub_rn(fy[k], sp.my);
+          const float Gdy = G * dy;
+          so = fmaf(dLda, gss, so);
+          sG += G;
+          sGdy += Gdy;
+          sGdy2 = fmaf(Gdy, dy, sGdy2);
+        }
+      }
+      const float bdx = sp.B * dx;
+      float g_mx = fmaf(2.0f * sp.A * dx, sG, sp.B * sGdy);   // x -ln2 below
+      float g_my = fmaf(2.0f * sp.C, sGdy, bdx * sG);         // x -ln2 below
+      float g_q11 = dx * dx * sG;                             // x -1/2 below
+      float g_q12 = dx * sGdy;                                // x -1 below
+      float g_q22 = sGdy2;                                    // x -1/2 below
       g_mx = wave_sum_to_lane63(g_mx);
       g_my = wave_sum_to_lane63(g_my);
       g_q11 = wave_sum_to_lane63(g_q11);
       g_q12 = wave_sum_to_lane63(g_q12);
       g_q22 = wave_sum_to_lane63(g_q22);
-      g_o = wave_sum_to_lane63(g_o);
-      g_r = wave_sum_to_lane63(g_r);
-      g_g = wave_sum_to_lane63(g_g);
-      g_b = wave_sum_to_lane63(g_b);
+      so = wave_sum_to_lane63(so);
+      sr = wave_sum_to_lane63(sr);
+      sg = wave_sum_to_lane63(sg);
+      sb = wave_sum_to_lane63(sb);
       if (lane == 63) {
         float* dst = d_rec + (int64_t)s_id[j] * GS_DREC_STRIDE;
         atomicAdd(dst + 0, -kLn2 * g_mx);
@@ -282,10 +294,10 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd(
         atomicAdd(dst + 2, -0.5f * g_q11);
         atomicAdd(dst + 3, -g_q12);
         atomicAdd(dst + 4, -0.5f * g_q22);
-        atomicAdd(dst + 5, g_o);
-        atomicAdd(dst + 6, g_r);
-        atomicAdd(dst + 7, g_g);
-        atomicAdd(dst + 8, g_b);
+        atomicAdd(dst + 5, so);
+        atomicAdd(dst + 6, sr);
+        atomicAdd(dst + 7, sg);
+        atomicAdd(dst + 8, sb);
       }
     }
   }

@@ -1,0 +1,64 @@
+"""Summarise a rocprofv3 kernel trace of ``bench.py`` over its timed steps.
+
+    python -m paper_2509_12138_amd.profsum <kernel_trace.csv> --steps K [--pmc <counter.csv> ...]
+
+bench.py launches one k_project per training step and one more afterwards
+(the untimed replay that counts evaluations), so the timed window is the
+K steps that precede the last k_project dispatch.  Prints per-kernel
+dispatch counts, mean durations and share of the step, as Markdown.  With
+--pmc, adds per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) averaged over the
+same kernels in a counter-collection run's CSV.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import re
+
+
+def short(name):
+    n = re.sub(r"\(.*", "", name)
+    n = n.replace("void ", "").replace("gsmi::", "")
+    return n
+
+
+def timed_window(rows, steps):
+    proj = [r for r in rows if short(r["Kernel_Name"]) == "k_project"]
+    if len(proj) < steps + 1:
+        raise SystemExit(f"only {len(proj)} k_project dispatches; need {steps + 1}")
+    t0 = int(proj[-steps - 1]["Start_Timestamp"])
+    t1 = int(proj[-1]["Start_Timestamp"])
+    return t0, t1
+
+
+def summarise(trace, steps):
+    rows = list(csv.DictReader(open(trace)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    t0, t1 = timed_window(rows, steps)
+    dur = collections.defaultdict(list)
+    for r in rows:
+        s, e = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        if t0 <= s < t1:
+            dur[short(r["Kernel_Name"])].append(e - s)
+    total = sum(sum(v) for v in dur.values())
+    return dur, total, (t1 - t0) / steps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("trace")
+    ap.add_argument("--steps", type=int, required=True)
+    args = ap.parse_args()
+    dur, total, wall = summarise(args.trace, args.steps)
+    print(f"Timed window: {args.steps} steps, {wall / 1e3:.1f} us per step (first k_project to "
+          f"the next step's), kernels busy {total / args.steps / 1e3:.1f} us per step\n")
+    print("| kernel | dispatches/step | mean us | us/step | share |")
+    print("|---|---:|---:|---:|---:|")
+    for k, v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
+        print(f"| {k} | {len(v) / args.steps:.0f} | {sum(v) / len(v) / 1e3:.2f} | "
+              f"{sum(v) / args.steps / 1e3:.2f} | {100.0 * sum(v) / total:.1f}% |")
+
+
+if __name__ == "__main__":
+    main()
