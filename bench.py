@@ -50,7 +50,22 @@ def parse():
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--recompute", action="store_true")
     ap.add_argument("--small", action="store_true", help="tiny config (smoke use)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device copy 5 times (HBM counter scale)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy of known size: 512 MiB read + 512 MiB written per launch,
+    used to scale the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                      "launches": 5}))
 
 
 def cpu_baseline(params, cam, target_seconds):
@@ -102,6 +117,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs an MI355X (no GPU visible)", file=sys.stderr)
         sys.exit(3)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     from paper_2509_12138_amd import _lib, workloads
     from paper_2509_12138_amd.train import PlainTrainer
     _lib.load()
