@@ -179,6 +179,53 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views,
                       uint32_t* ids_out, uint32_t* tile_ranges,
                       int64_t* status, void* stream);
 
+/* How the rasterisers walk the tiles of a call (optional; NULL = one
+ * work-group per tile in an XCD-aware order).
+ *   tile_order       device [S * tiles] permutation of the tiles (e.g. the
+ *                    longest-first order from gs_tile_order), or NULL
+ *   queue            device u32 work counter: when set, a persistent grid of
+ *                    persistent_waves work-groups (0 = 16 per CU) pulls tiles
+ *                    atomically in tile_order order; the call resets it.
+ * Chunked backward (STORED mode only): with chunk > 0 (a multiple of 64) the
+ * backward cuts every tile list into `chunk`-entry work items that run in
+ * parallel; the forward then stores each pixel's (T, C) after every `chunk`
+ * entries into checkpoints [max_items][tile_w*tile_h] float4 and the
+ * backward reads them (and the forward's image) to start each item.
+ *   chunk_offset [n_tiles + 1], chunk_items [max_items]: from gs_chunk_items
+ *   after gs_bin_sort (the same plan must be passed to both raster calls).
+ * Results do not depend on the plan (up to FP32 atomic ordering in the
+ * gradients).                                                              */
+typedef struct {
+  const uint32_t* tile_order;
+  uint32_t* queue;
+  int32_t persistent_waves;
+  int32_t chunk;
+  const uint32_t* chunk_offset;
+  const uint32_t* chunk_items;
+  float* checkpoints;
+  const float* image;
+  int64_t max_items;
+} gs_raster_plan;
+
+/* Upper bound on the work items of gs_chunk_items for a duplicate capacity. */
+int64_t gs_chunk_max_items(int64_t n_tiles, int64_t dup_capacity, int32_t chunk);
+
+/* Work items of the chunked backward: chunk_offset[t] = first item of tile t
+ * (chunk_offset[n_tiles] = item count = sum of ceil(len_t / chunk)),
+ * chunk_items[i] = tile of item i.  Device arrays, no host sync.           */
+gs_status gs_chunk_items(const uint32_t* tile_ranges, int64_t n_tiles, int32_t chunk,
+                         int64_t max_items, uint32_t* chunk_offset, uint32_t* chunk_items,
+                         void* stream);
+
+size_t gs_tile_order_workspace_bytes(int64_t n_tiles);
+
+/* Longest-first order of the tiles of a call by list length (bucketed by
+ * floor(log2(length + 1)), descending), for load balance of batched,
+ * uneven partitions.  tile_ranges as written by gs_bin_sort; order [n_tiles]
+ * device output.  The order inside a bucket is unspecified.                */
+gs_status gs_tile_order(const uint32_t* tile_ranges, int64_t n_tiles, void* ws,
+                        size_t ws_bytes, uint32_t* order, void* stream);
+
 /* Front-to-back compositing (3D-GS rasteriser).  For each pixel p of each
  * slot, over its tile's sorted list: power = -1/2 d^T conic d with
  * d = p - mean2d (skipped if power > 0); alpha = min(0.99, o e^power),
@@ -192,7 +239,7 @@ gs_status gs_raster_fwd(const gs_projected* proj, const gs_views* views,
                         const gs_tiling* tiling, const uint32_t* ids,
                         const uint32_t* tile_ranges, const float bg[3],
                         float* image, float* T_final, int32_t* n_contrib,
-                        void* stream);
+                        const gs_raster_plan* plan, void* stream);
 
 #define GS_BWD_STORED 0     /* use T_final / n_contrib from the forward      */
 #define GS_BWD_RECOMPUTE 1  /* replay the forward per tile to recover them   */
@@ -208,7 +255,7 @@ gs_status gs_raster_bwd(const gs_projected* proj, const gs_views* views,
                         const uint32_t* tile_ranges, const float bg[3],
                         const float* T_final, const int32_t* n_contrib,
                         const float* d_image, int32_t mode, float* d_rec,
-                        void* stream);
+                        const gs_raster_plan* plan, void* stream);
 
 /* Chain rule from d_rec back to the Gaussian parameters (sum over every
  * slot that draws the Gaussian), accumulating (+=) into grads.  Depth, the
@@ -252,6 +299,22 @@ typedef struct {
 gs_status gs_adam(const gs_adam_group* groups, int32_t n_groups, float beta1,
                   float beta2, float eps, int32_t step, int32_t zero_grad,
                   void* stream);
+
+/* Workspace for gs_knn on n points.                                         */
+size_t gs_knn_workspace_bytes(int64_t n, int32_t k);
+
+/* Exact k nearest neighbours of every point among the other points
+ * (Euclidean, FP32), used by the initialisation: the plain one sets a
+ * Gaussian's isotropic scale to the mean distance to its 3 nearest
+ * neighbours, the learned one reads 16-NN offsets (isosurface points,
+ * Sec. II "Isosurface Extraction").
+ *   pts [3][n] device (planar x, y, z); idx [n][k] i32 and dist [n][k] f32
+ *   device outputs sorted by (distance, index); missing neighbours (n <= k)
+ *   are -1 / +inf.  1 <= k <= 32, n < 2^31.  ws: gs_knn_workspace_bytes,
+ *   256-byte aligned.  Uniform grid + shell search with an exact stopping
+ *   bound; no host synchronisation.                                        */
+gs_status gs_knn(const float* pts, int64_t n, int32_t k, void* ws, size_t ws_bytes,
+                 int32_t* idx, float* dist, void* stream);
 
 /* Fill `bytes` bytes at device pointer `ptr` with zero using a kernel (safe
  * to capture in a HIP graph).  bytes must be a multiple of 4.             */

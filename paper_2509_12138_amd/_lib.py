@@ -50,6 +50,12 @@ class gs_projected(C.Structure):
     _fields_ = [("rec", vp), ("tile_bbox", vp), ("n_tiles", vp), ("m", i64)]
 
 
+class gs_raster_plan(C.Structure):
+    _fields_ = [("tile_order", vp), ("queue", vp), ("persistent_waves", i32), ("chunk", i32),
+                ("chunk_offset", vp), ("chunk_items", vp), ("checkpoints", vp), ("image", vp),
+                ("max_items", i64)]
+
+
 class gs_adam_group(C.Structure):
     _fields_ = [("param", vp), ("grad", vp), ("m", vp), ("v", vp), ("count", i64), ("lr", f32)]
 
@@ -73,9 +79,13 @@ SIGNATURES = {
     "gs_bin_sort": (i32, [P(gs_projected), P(gs_views), P(gs_tiling), i64, vp, sz, vp, vp, vp,
                           vp, vp]),
     "gs_raster_fwd": (i32, [P(gs_projected), P(gs_views), P(gs_tiling), vp, vp, P(f32), vp, vp,
-                            vp, vp]),
+                            vp, P(gs_raster_plan), vp]),
     "gs_raster_bwd": (i32, [P(gs_projected), P(gs_views), P(gs_tiling), vp, vp, P(f32), vp, vp,
-                            vp, i32, vp, vp]),
+                            vp, i32, vp, P(gs_raster_plan), vp]),
+    "gs_tile_order_workspace_bytes": (sz, [i64]),
+    "gs_chunk_max_items": (i64, [i64, i64, i32]),
+    "gs_chunk_items": (i32, [vp, i64, i32, i64, vp, vp, vp]),
+    "gs_tile_order": (i32, [vp, i64, vp, sz, vp, vp]),
     "gs_project_bwd": (i32, [P(gs_gaussians), P(gs_views), P(gs_tiling), P(gs_projected), vp,
                              P(gs_grads), vp]),
     "gs_loss_workspace_bytes": (sz, [i32, i32, i32]),

@@ -12,6 +12,8 @@
 // (1 - alpha) in reverse order (STORED) or first replays the forward for its
 // tile (RECOMPUTE).  Per (tile, Gaussian) the 9 gradient components are
 // summed over the wave with DPP and added with one FP32 atomic each.
+#include <algorithm>
+
 #include "gs_device.h"
 
 namespace gsmi {
@@ -53,12 +55,16 @@ struct TileGeom {
 
 // Forward pass of one tile for one lane's PX pixels.  WITH_COLOR=false is the
 // replay used by the backward in RECOMPUTE mode.
+// With `ck` set (WITH_COLOR only), the per-pixel state (T, C) after every
+// `chunk` list entries is stored for the chunked backward: boundary c (after
+// entry (c+1)*chunk) goes to ck[c * TW*TH + pixel].
 template <int TW, int TH, bool WITH_COLOR>
 __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
                                              const uint32_t* __restrict__ ids, uint32_t start,
                                              uint32_t end, const float fx, const float* fy,
                                              const bool* inside, Splat* s_splat, float* T,
-                                             float (*C)[3], int* last) {
+                                             float (*C)[3], int* last, float4* ck = nullptr,
+                                             int chunk = 0) {
   constexpr int PX = TileGeom<TW, TH>::PX;
   const int lane = threadIdx.x;
   bool done[PX];
@@ -110,22 +116,74 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
         last[k] = pos;
       }
     }
+    if (WITH_COLOR && ck) {
+      const uint32_t done_n = b0 + (uint32_t)n - start;
+      if (done_n % (uint32_t)chunk == 0 && b0 + (uint32_t)n < end) {
+        float4* dst = ck + (int64_t)(done_n / chunk - 1) * (TW * TH);
+#pragma unroll
+        for (int k = 0; k < PX; ++k)
+          dst[lane + k * kRasterWave] = make_float4(T[k], C[k][0], C[k][1], C[k][2]);
+      }
+    }
+  }
+}
+
+// Per-call arguments shared by the forward and backward rasterisers.
+struct RasterDev {
+  const float* rec;
+  const uint32_t* ids;
+  const uint32_t* ranges;
+  int W, H, tiles_x, tiles_per_slot;
+  int64_t n_tiles;
+  float bg0, bg1, bg2;
+};
+
+// Which tile a work-group processes: default XCD-aware order, a precomputed
+// (longest-first) order, or a persistent grid pulling from an atomic queue.
+struct TileSched {
+  const uint32_t* order;   // NULL: XCD-aware default order
+  uint32_t* queue;         // non-NULL: persistent launch, items pulled atomically
+};
+
+// Chunked backward: every tile list is cut into `chunk`-entry work items;
+// offset[t] is the first item of tile t (offset[n_tiles] = item count),
+// items[i] the tile of item i; ck the forward checkpoints, one TW*TH float4
+// block per item; image the forward's output.
+struct ChunkDev {
+  int chunk;
+  const uint32_t* offset;
+  const uint32_t* items;
+  float4* ck;
+  const float* image;
+};
+
+template <typename F>
+__device__ __forceinline__ void for_each_tile(const TileSched& sch, int64_t n_tiles, F&& body) {
+  if (sch.queue) {
+    for (;;) {
+      uint32_t item = 0;
+      if (threadIdx.x == 0) item = atomicAdd(sch.queue, 1u);
+      item = __builtin_amdgcn_readfirstlane(item);
+      if ((int64_t)item >= n_tiles) break;
+      body((int64_t)(sch.order ? sch.order[item] : item));
+    }
+  } else {
+    const int64_t tile = sch.order ? ((int64_t)blockIdx.x < n_tiles ? (int64_t)sch.order[blockIdx.x] : n_tiles)
+                                   : tile_of_block(n_tiles);
+    if (tile < n_tiles) body(tile);
   }
 }
 
 template <int TW, int TH>
-__global__ __launch_bounds__(kRasterWave) void k_raster_fwd(
-    const float* __restrict__ rec, const uint32_t* __restrict__ ids,
-    const uint32_t* __restrict__ ranges, int W, int H, int tiles_x, int tiles_per_slot,
-    int64_t n_tiles, float bg0, float bg1, float bg2, float* __restrict__ image,
-    float* __restrict__ T_final, int32_t* __restrict__ n_contrib) {
+__device__ __forceinline__ void fwd_tile(const RasterDev& a, const ChunkDev& ch, int64_t tile,
+                                         Splat* s_splat, float* __restrict__ image,
+                                         float* __restrict__ T_final,
+                                         int32_t* __restrict__ n_contrib) {
   constexpr int PX = TileGeom<TW, TH>::PX, RSTEP = TileGeom<TW, TH>::RSTEP;
-  __shared__ Splat s_splat[kRasterWave];
-  const int64_t tile = tile_of_block(n_tiles);
-  if (tile >= n_tiles) return;
-  const int slot = (int)(tile / tiles_per_slot);
-  const int t = (int)(tile - (int64_t)slot * tiles_per_slot);
-  const int ty = t / tiles_x, tx = t - ty * tiles_x;
+  const int W = a.W, H = a.H;
+  const int slot = (int)(tile / a.tiles_per_slot);
+  const int t = (int)(tile - (int64_t)slot * a.tiles_per_slot);
+  const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
   const int lane = threadIdx.x;
   const int px = tx * TW + (lane % TW);
   const int py0 = ty * TH + lane / TW;
@@ -138,22 +196,35 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_fwd(
     fy[k] = (float)py + 0.5f;
     inside[k] = (px < W) && (py < H);
   }
-  const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+  const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
   float T[PX], C[PX][3];
   int last[PX];
-  tile_forward<TW, TH, true>(rec, ids, start, end, fx, fy, inside, s_splat, T, C, last);
+  float4* ck = ch.ck ? ch.ck + (int64_t)ch.offset[tile] * (TW * TH) : nullptr;
+  tile_forward<TW, TH, true>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T, C, last, ck,
+                             ch.chunk);
   const int64_t HW = (int64_t)H * W;
   float* img = image + (int64_t)slot * 3 * HW;
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     if (!inside[k]) continue;
     const int64_t o = (int64_t)(py0 + k * RSTEP) * W + px;
-    img[o] = C[k][0] + T[k] * bg0;
-    img[HW + o] = C[k][1] + T[k] * bg1;
-    img[2 * HW + o] = C[k][2] + T[k] * bg2;
+    img[o] = C[k][0] + T[k] * a.bg0;
+    img[HW + o] = C[k][1] + T[k] * a.bg1;
+    img[2 * HW + o] = C[k][2] + T[k] * a.bg2;
     if (T_final) T_final[(int64_t)slot * HW + o] = T[k];
     if (n_contrib) n_contrib[(int64_t)slot * HW + o] = last[k];
   }
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(kRasterWave) void k_raster_fwd(RasterDev a, TileSched sch, ChunkDev ch,
+                                                            float* __restrict__ image,
+                                                            float* __restrict__ T_final,
+                                                            int32_t* __restrict__ n_contrib) {
+  __shared__ Splat s_splat[kRasterWave];
+  for_each_tile(sch, a.n_tiles, [&](int64_t tile) {
+    fwd_tile<TW, TH>(a, ch, tile, s_splat, image, T_final, n_contrib);
+  });
 }
 
 __device__ __forceinline__ int wave_max_int(int v) {
@@ -162,76 +233,30 @@ __device__ __forceinline__ int wave_max_int(int v) {
   return v;
 }
 
-template <int TW, int TH, bool RECOMPUTE>
-__global__ __launch_bounds__(kRasterWave) void k_raster_bwd(
-    const float* __restrict__ rec, const uint32_t* __restrict__ ids,
-    const uint32_t* __restrict__ ranges, int W, int H, int tiles_x, int tiles_per_slot,
-    int64_t n_tiles, float bg0, float bg1, float bg2, const float* __restrict__ T_final,
-    const int32_t* __restrict__ n_contrib, const float* __restrict__ d_image,
-    float* __restrict__ d_rec) {
-  constexpr int PX = TileGeom<TW, TH>::PX, RSTEP = TileGeom<TW, TH>::RSTEP;
-  __shared__ Splat s_splat[kRasterWave];
-  __shared__ uint32_t s_id[kRasterWave];
-  const int64_t tile = tile_of_block(n_tiles);
-  if (tile >= n_tiles) return;
-  const int slot = (int)(tile / tiles_per_slot);
-  const int t = (int)(tile - (int64_t)slot * tiles_per_slot);
-  const int ty = t / tiles_x, tx = t - ty * tiles_x;
+// Reverse replay of list positions (lo, hi] of one tile (entries start+lo ..
+// start+hi-1, last first).  Per pixel k on entry: T[k] = transmittance after
+// position hi, dIacc[k] = dI . (colour blended behind position hi + bg T_final).
+template <int TW, int TH>
+__device__ __forceinline__ void reverse_pass(const RasterDev& a, uint32_t start, int lo, int hi,
+                                             const float fx, const float* fy, const int* last,
+                                             float* T, float (*dI)[3], float* dIacc,
+                                             Splat* s_splat, uint32_t* s_id,
+                                             float* __restrict__ d_rec) {
+  constexpr int PX = TileGeom<TW, TH>::PX;
   const int lane = threadIdx.x;
-  const int px = tx * TW + (lane % TW);
-  const int py0 = ty * TH + lane / TW;
-  const float fx = (float)px + 0.5f;
-  float fy[PX];
-  bool inside[PX];
-#pragma unroll
-  for (int k = 0; k < PX; ++k) {
-    const int py = py0 + k * RSTEP;
-    fy[k] = (float)py + 0.5f;
-    inside[k] = (px < W) && (py < H);
-  }
-  const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-  if (start >= end) return;
-  const int64_t HW = (int64_t)H * W;
-  float T[PX];
-  int last[PX];
-  if (RECOMPUTE) {
-    tile_forward<TW, TH, false>(rec, ids, start, end, fx, fy, inside, s_splat, T, nullptr, last);
-  } else {
-#pragma unroll
-    for (int k = 0; k < PX; ++k) {
-      const int64_t o = (int64_t)slot * HW + (int64_t)(py0 + k * RSTEP) * W + px;
-      T[k] = inside[k] ? T_final[o] : 1.0f;
-      last[k] = inside[k] ? n_contrib[o] : 0;
-    }
-  }
-  // dIacc = dI . (sum of the colour blended behind + bg T_final), per pixel
-  float dI[PX][3], dIacc[PX];
-  const float* dimg = d_image + (int64_t)slot * 3 * HW;
-#pragma unroll
-  for (int k = 0; k < PX; ++k) {
-    const int64_t o = (int64_t)(py0 + k * RSTEP) * W + px;
-    dI[k][0] = inside[k] ? dimg[o] : 0.0f;
-    dI[k][1] = inside[k] ? dimg[HW + o] : 0.0f;
-    dI[k][2] = inside[k] ? dimg[2 * HW + o] : 0.0f;
-    dIacc[k] = T[k] * (dI[k][0] * bg0 + dI[k][1] * bg1 + dI[k][2] * bg2);
-  }
-  int lmax = 0;
-#pragma unroll
-  for (int k = 0; k < PX; ++k) lmax = max(lmax, last[k]);
-  lmax = min(wave_max_int(lmax), (int)(end - start));
-  for (int hi = lmax; hi > 0; hi -= kRasterWave) {
-    const int lo = max(0, hi - kRasterWave);
-    const int n = hi - lo;
+  for (int top = hi; top > lo; top -= kRasterWave) {
+    const int bot = max(lo, top - kRasterWave);
+    const int n = top - bot;
     __syncthreads();
     if (lane < n) {
-      const uint32_t id = ids[start + lo + lane];
+      const uint32_t id = a.ids[start + bot + lane];
       s_id[lane] = id;
-      s_splat[lane] = load_splat(rec, id);
+      s_splat[lane] = load_splat(a.rec, id);
     }
     __syncthreads();
     for (int j = n - 1; j >= 0; --j) {
       const Splat sp = s_splat[j];
-      const int pos = lo + j + 1;
+      const int pos = bot + j + 1;
       const float dx = __fsub_rn(fx, sp.mx);
       float p2[PX];
       splat_p2_column<PX>(sp, dx, fy, p2);
@@ -250,8 +275,8 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd(
       for (int k = 0; k < PX; ++k) {
         if (!pass[k]) continue;
         const float gss = splat_gauss(p2[k]);
-        const float a = sp.o * gss;
-        const float alpha = fminf(kAlphaMax, a);
+        const float aa = sp.o * gss;
+        const float alpha = fminf(kAlphaMax, aa);
         const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
         const float Tb = T[k] * inv;                 // transmittance in front of it
         const float w = alpha * Tb;
@@ -262,7 +287,7 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd(
         sr = fmaf(dI[k][0], w, sr);
         sg = fmaf(dI[k][1], w, sg);
         sb = fmaf(dI[k][2], w, sb);
-        if (a < kAlphaMax) {
+        if (aa < kAlphaMax) {
           const float G = dLda * alpha;
           const float dy = __fsub_rn(fy[k], sp.my);
           const float Gdy = G * dy;
@@ -303,38 +328,296 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd(
   }
 }
 
-// ---------------------------------------------------------------- dispatch
-
-struct RasterArgs {
-  const float* rec;
-  const uint32_t* ids;
-  const uint32_t* ranges;
-  int W, H, tiles_x, tiles_per_slot;
-  int64_t n_tiles;
-  float bg[3];
+// Pixel geometry of one tile for the calling lane.
+template <int TW, int TH>
+struct LanePixels {
+  static constexpr int PX = TileGeom<TW, TH>::PX, RSTEP = TileGeom<TW, TH>::RSTEP;
+  int slot, px, py0;
+  float fx, fy[PX];
+  bool inside[PX];
+  __device__ __forceinline__ LanePixels(const RasterDev& a, int64_t tile) {
+    slot = (int)(tile / a.tiles_per_slot);
+    const int t = (int)(tile - (int64_t)slot * a.tiles_per_slot);
+    const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
+    const int lane = threadIdx.x;
+    px = tx * TW + (lane % TW);
+    py0 = ty * TH + lane / TW;
+    fx = (float)px + 0.5f;
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      const int py = py0 + k * RSTEP;
+      fy[k] = (float)py + 0.5f;
+      inside[k] = (px < a.W) && (py < a.H);
+    }
+  }
+  __device__ __forceinline__ int64_t offset(const RasterDev& a, int k) const {
+    return (int64_t)(py0 + k * RSTEP) * a.W + px;
+  }
 };
 
+template <int TW, int TH, bool RECOMPUTE>
+__device__ __forceinline__ void bwd_tile(const RasterDev& a, int64_t tile, Splat* s_splat,
+                                         uint32_t* s_id, const float* __restrict__ T_final,
+                                         const int32_t* __restrict__ n_contrib,
+                                         const float* __restrict__ d_image,
+                                         float* __restrict__ d_rec) {
+  constexpr int PX = TileGeom<TW, TH>::PX;
+  const LanePixels<TW, TH> L(a, tile);
+  const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+  if (start >= end) return;
+  const int64_t HW = (int64_t)a.H * a.W;
+  float T[PX];
+  int last[PX];
+  if (RECOMPUTE) {
+    tile_forward<TW, TH, false>(a.rec, a.ids, start, end, L.fx, L.fy, L.inside, s_splat, T,
+                                nullptr, last);
+  } else {
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      const int64_t o = (int64_t)L.slot * HW + L.offset(a, k);
+      T[k] = L.inside[k] ? T_final[o] : 1.0f;
+      last[k] = L.inside[k] ? n_contrib[o] : 0;
+    }
+  }
+  // dIacc = dI . (sum of the colour blended behind + bg T_final), per pixel
+  float dI[PX][3], dIacc[PX];
+  const float* dimg = d_image + (int64_t)L.slot * 3 * HW;
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    const int64_t o = L.offset(a, k);
+    dI[k][0] = L.inside[k] ? dimg[o] : 0.0f;
+    dI[k][1] = L.inside[k] ? dimg[HW + o] : 0.0f;
+    dI[k][2] = L.inside[k] ? dimg[2 * HW + o] : 0.0f;
+    dIacc[k] = T[k] * (dI[k][0] * a.bg0 + dI[k][1] * a.bg1 + dI[k][2] * a.bg2);
+  }
+  int lmax = 0;
+#pragma unroll
+  for (int k = 0; k < PX; ++k) lmax = max(lmax, last[k]);
+  lmax = min(wave_max_int(lmax), (int)(end - start));
+  reverse_pass<TW, TH>(a, start, 0, lmax, L.fx, L.fy, last, T, dI, dIacc, s_splat, s_id, d_rec);
+}
+
+template <int TW, int TH, bool RECOMPUTE>
+__global__ __launch_bounds__(kRasterWave) void k_raster_bwd(RasterDev a, TileSched sch,
+                                                            const float* __restrict__ T_final,
+                                                            const int32_t* __restrict__ n_contrib,
+                                                            const float* __restrict__ d_image,
+                                                            float* __restrict__ d_rec) {
+  __shared__ Splat s_splat[kRasterWave];
+  __shared__ uint32_t s_id[kRasterWave];
+  for_each_tile(sch, a.n_tiles, [&](int64_t tile) {
+    bwd_tile<TW, TH, RECOMPUTE>(a, tile, s_splat, s_id, T_final, n_contrib, d_image, d_rec);
+  });
+}
+
+// Chunked backward: one work-group per (tile, chunk) item.  Chunk c covers
+// list positions (c*chunk, min((c+1)*chunk, len)]; the state after its last
+// position is the forward's final state for pixels whose last blended entry
+// lies at or before it, else the checkpoint the forward stored there.
 template <int TW, int TH>
-static void launch_fwd(const RasterArgs& a, float* image, float* T_final, int32_t* n_contrib,
-                       hipStream_t s) {
-  const int64_t blocks = 8 * ((a.n_tiles + 7) / 8);
-  hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3((unsigned)blocks), dim3(kRasterWave), 0, s,
-                     a.rec, a.ids, a.ranges, a.W, a.H, a.tiles_x, a.tiles_per_slot, a.n_tiles,
-                     a.bg[0], a.bg[1], a.bg[2], image, T_final, n_contrib);
+__global__ __launch_bounds__(kRasterWave) void k_raster_bwd_chunked(
+    RasterDev a, ChunkDev ch, const float* __restrict__ T_final,
+    const int32_t* __restrict__ n_contrib, const float* __restrict__ d_image,
+    float* __restrict__ d_rec) {
+  constexpr int PX = TileGeom<TW, TH>::PX;
+  __shared__ Splat s_splat[kRasterWave];
+  __shared__ uint32_t s_id[kRasterWave];
+  const uint32_t item = blockIdx.x;
+  if (item >= ch.offset[a.n_tiles]) return;
+  const int64_t tile = ch.items[item];
+  const int c = (int)(item - ch.offset[tile]);
+  const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+  const int len = (int)(end - start);
+  const int lo = c * ch.chunk, hi_pos = min(lo + ch.chunk, len);
+  const LanePixels<TW, TH> L(a, tile);
+  const int64_t HW = (int64_t)a.H * a.W;
+  int last[PX];
+  int lmax = 0;
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    last[k] = L.inside[k] ? n_contrib[(int64_t)L.slot * HW + L.offset(a, k)] : 0;
+    lmax = max(lmax, last[k]);
+  }
+  const int hi = min(wave_max_int(lmax), hi_pos);
+  if (hi <= lo) return;
+  const float4* ck = ch.ck + ((int64_t)ch.offset[tile] + c) * (TW * TH);
+  float T[PX], dI[PX][3], dIacc[PX];
+  const float* dimg = d_image + (int64_t)L.slot * 3 * HW;
+  const float* img = ch.image + (int64_t)L.slot * 3 * HW;
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    const int64_t o = L.offset(a, k);
+    dI[k][0] = L.inside[k] ? dimg[o] : 0.0f;
+    dI[k][1] = L.inside[k] ? dimg[HW + o] : 0.0f;
+    dI[k][2] = L.inside[k] ? dimg[2 * HW + o] : 0.0f;
+    if (!L.inside[k] || last[k] <= hi_pos) {
+      // nothing blended after this chunk: final state, I - C_final = bg T_final
+      T[k] = L.inside[k] ? T_final[(int64_t)L.slot * HW + o] : 1.0f;
+      dIacc[k] = T[k] * (dI[k][0] * a.bg0 + dI[k][1] * a.bg1 + dI[k][2] * a.bg2);
+    } else {
+      const float4 s = ck[threadIdx.x + k * kRasterWave];
+      T[k] = s.x;
+      dIacc[k] = dI[k][0] * (img[o] - s.y) + dI[k][1] * (img[HW + o] - s.z) +
+                 dI[k][2] * (img[2 * HW + o] - s.w);
+    }
+  }
+  reverse_pass<TW, TH>(a, start, lo, hi, L.fx, L.fy, last, T, dI, dIacc, s_splat, s_id, d_rec);
+}
+
+// ---------------------------------------------------------------- tile order
+
+// Longest-first (LPT) order of the tiles by list length, bucketed by
+// floor(log2(len + 1)): 32 buckets, block-local LDS counts, one global
+// atomic per (block, bucket), so tiles of one block stay together inside a
+// bucket.
+constexpr int kOrderThreads = 256;
+constexpr int kOrderBuckets = 32;
+
+__device__ __forceinline__ int len_bucket(uint32_t len) {
+  return 31 - __clz(len + 1u);    // 0 for empty tiles
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_order_count(const uint32_t* __restrict__ ranges,
+                                                               int64_t n_tiles,
+                                                               uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * kOrderThreads + threadIdx.x;
+  if (t < n_tiles) atomicAdd(&h[len_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_order_scan(uint32_t* __restrict__ hist, uint32_t* __restrict__ start) {
+  if (threadIdx.x != 0) return;
+  uint32_t run = 0;
+  for (int b = kOrderBuckets - 1; b >= 0; --b) {   // descending cost
+    start[b] = run;
+    run += hist[b];
+  }
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_order_scatter(const uint32_t* __restrict__ ranges,
+                                                                 int64_t n_tiles,
+                                                                 const uint32_t* __restrict__ start,
+                                                                 uint32_t* __restrict__ cursor,
+                                                                 uint32_t* __restrict__ order) {
+  __shared__ uint32_t h[kOrderBuckets], base[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * kOrderThreads + threadIdx.x;
+  int b = 0;
+  uint32_t local = 0;
+  if (t < n_tiles) {
+    b = len_bucket(ranges[2 * t + 1] - ranges[2 * t]);
+    local = atomicAdd(&h[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets && h[threadIdx.x])
+    base[threadIdx.x] = start[threadIdx.x] + atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]);
+  __syncthreads();
+  if (t < n_tiles) order[base[b] + local] = (uint32_t)t;
+}
+
+__global__ void k_reset_queue(uint32_t* q) {
+  if (threadIdx.x == 0) q[0] = 0u;
+}
+
+// ---------------------------------------------------------------- chunk items
+
+// offset[t] = ceil(len(t) / chunk); then an exclusive scan over n_tiles + 1
+// entries; then items[offset[t] + c] = t.
+__global__ __launch_bounds__(256) void k_chunk_count(const uint32_t* __restrict__ ranges,
+                                                     int64_t n_tiles, int chunk,
+                                                     uint32_t* __restrict__ offset) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n_tiles) offset[t] = (ranges[2 * t + 1] - ranges[2 * t] + chunk - 1) / chunk;
+  if (t == n_tiles) offset[t] = 0;
+}
+
+// single work-group exclusive scan of n entries in place (n up to a few 1e5)
+__global__ __launch_bounds__(1024) void k_scan_small(uint32_t* __restrict__ v, int64_t n) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b0 = t * per, b1 = min(b0 + per, n);
+  uint32_t s = 0;
+  for (int64_t i = b0; i < b1; ++i) s += v[i];
+  part[t] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    uint32_t x = t >= d ? part[t - d] : 0u;
+    __syncthreads();
+    part[t] += x;
+    __syncthreads();
+  }
+  uint32_t run = t > 0 ? part[t - 1] : 0u;
+  for (int64_t i = b0; i < b1; ++i) {
+    const uint32_t x = v[i];
+    v[i] = run;
+    run += x;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_chunk_items(const uint32_t* __restrict__ offset,
+                                                     int64_t n_tiles, int64_t max_items,
+                                                     uint32_t* __restrict__ items) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_tiles) return;
+  for (uint32_t i = offset[t]; i < offset[t + 1] && (int64_t)i < max_items; ++i) items[i] = (uint32_t)t;
+}
+
+// ---------------------------------------------------------------- dispatch
+
+struct Launch {
+  unsigned blocks;
+  TileSched sch;
+  ChunkDev ch;
+  int64_t max_items;
+};
+
+static Launch make_launch(const RasterDev& a, const gs_raster_plan* plan) {
+  Launch L;
+  L.sch.order = plan ? plan->tile_order : nullptr;
+  L.sch.queue = plan ? plan->queue : nullptr;
+  L.ch.chunk = plan ? plan->chunk : 0;
+  L.ch.offset = plan ? plan->chunk_offset : nullptr;
+  L.ch.items = plan ? plan->chunk_items : nullptr;
+  L.ch.ck = plan ? reinterpret_cast<float4*>(plan->checkpoints) : nullptr;
+  L.ch.image = plan ? plan->image : nullptr;
+  L.max_items = plan ? plan->max_items : 0;
+  if (L.sch.queue) {
+    int64_t w = plan->persistent_waves > 0 ? plan->persistent_waves : (int64_t)device_cu_count() * 16;
+    L.blocks = (unsigned)std::min<int64_t>(w, std::max<int64_t>(a.n_tiles, 1));
+  } else if (L.sch.order) {
+    L.blocks = (unsigned)std::max<int64_t>(a.n_tiles, 1);
+  } else {
+    L.blocks = (unsigned)(8 * ((a.n_tiles + 7) / 8));
+  }
+  return L;
 }
 
 template <int TW, int TH>
-static void launch_bwd(const RasterArgs& a, const float* T_final, const int32_t* n_contrib,
-                       const float* d_image, int mode, float* d_rec, hipStream_t s) {
-  const int64_t blocks = 8 * ((a.n_tiles + 7) / 8);
-  if (mode == GS_BWD_RECOMPUTE)
-    hipLaunchKernelGGL((k_raster_bwd<TW, TH, true>), dim3((unsigned)blocks), dim3(kRasterWave), 0,
-                       s, a.rec, a.ids, a.ranges, a.W, a.H, a.tiles_x, a.tiles_per_slot,
-                       a.n_tiles, a.bg[0], a.bg[1], a.bg[2], T_final, n_contrib, d_image, d_rec);
+static void launch_fwd(const RasterDev& a, const Launch& L, float* image, float* T_final,
+                       int32_t* n_contrib, hipStream_t s) {
+  hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3(L.blocks), dim3(kRasterWave), 0, s, a, L.sch,
+                     L.ch, image, T_final, n_contrib);
+}
+
+template <int TW, int TH>
+static void launch_bwd(const RasterDev& a, const Launch& L, const float* T_final,
+                       const int32_t* n_contrib, const float* d_image, int mode, float* d_rec,
+                       hipStream_t s) {
+  if (mode == GS_BWD_STORED && L.ch.chunk > 0)
+    hipLaunchKernelGGL((k_raster_bwd_chunked<TW, TH>), dim3((unsigned)L.max_items),
+                       dim3(kRasterWave), 0, s, a, L.ch, T_final, n_contrib, d_image, d_rec);
+  else if (mode == GS_BWD_RECOMPUTE)
+    hipLaunchKernelGGL((k_raster_bwd<TW, TH, true>), dim3(L.blocks), dim3(kRasterWave), 0, s, a,
+                       L.sch, T_final, n_contrib, d_image, d_rec);
   else
-    hipLaunchKernelGGL((k_raster_bwd<TW, TH, false>), dim3((unsigned)blocks), dim3(kRasterWave), 0,
-                       s, a.rec, a.ids, a.ranges, a.W, a.H, a.tiles_x, a.tiles_per_slot,
-                       a.n_tiles, a.bg[0], a.bg[1], a.bg[2], T_final, n_contrib, d_image, d_rec);
+    hipLaunchKernelGGL((k_raster_bwd<TW, TH, false>), dim3(L.blocks), dim3(kRasterWave), 0, s, a,
+                       L.sch, T_final, n_contrib, d_image, d_rec);
 }
 
 // Tile shapes with a compiled rasteriser (one wave per tile).
@@ -350,7 +633,7 @@ static bool raster_shape_supported(int tw, int th) {
 static gs_status raster_prepare(const gs_projected* proj, const gs_views* views,
                                 const gs_tiling* tiling, const uint32_t* ids,
                                 const uint32_t* tile_ranges, const float bg[3], const char* who,
-                                RasterArgs& a) {
+                                RasterDev& a) {
   GS_REQUIRE(proj != nullptr && bg != nullptr, "%s: NULL argument", who);
   gs_status st = check_views(views, tiling, who);
   if (st != GS_OK) return st;
@@ -367,9 +650,27 @@ static gs_status raster_prepare(const gs_projected* proj, const gs_views* views,
   a.tiles_x = (int)ceil_div(tiling->width, tiling->tile_w);
   a.tiles_per_slot = a.tiles_x * (int)ceil_div(tiling->height, tiling->tile_h);
   a.n_tiles = (int64_t)a.tiles_per_slot * views->n_slots;
-  a.bg[0] = bg[0];
-  a.bg[1] = bg[1];
-  a.bg[2] = bg[2];
+  a.bg0 = bg[0];
+  a.bg1 = bg[1];
+  a.bg2 = bg[2];
+  return GS_OK;
+}
+
+static gs_status plan_prepare(const gs_raster_plan* plan, hipStream_t s, const char* who) {
+  if (!plan) return GS_OK;
+  GS_REQUIRE(plan->persistent_waves >= 0, "%s: persistent_waves < 0", who);
+  if (plan->chunk > 0) {
+    GS_REQUIRE(plan->chunk % kRasterWave == 0, "%s: chunk %d is not a multiple of 64", who,
+               plan->chunk);
+    GS_REQUIRE(plan->chunk_offset && plan->chunk_items && plan->checkpoints && plan->image &&
+                   plan->max_items > 0 && plan->max_items < (int64_t(1) << 31),
+               "%s: chunked plan needs chunk_offset, chunk_items, checkpoints, image, max_items",
+               who);
+  }
+  if (plan->queue) {
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, plan->queue);
+    GS_LAUNCH_CHECK(who);
+  }
   return GS_OK;
 }
 
@@ -379,20 +680,80 @@ using namespace gsmi;
 
 extern "C" {
 
+size_t gs_tile_order_workspace_bytes(int64_t n_tiles) {
+  (void)n_tiles;
+  return 3 * kOrderBuckets * sizeof(uint32_t);
+}
+
+gs_status gs_tile_order(const uint32_t* tile_ranges, int64_t n_tiles, void* ws, size_t ws_bytes,
+                        uint32_t* order, void* stream) {
+  clear_error();
+  GS_REQUIRE(n_tiles >= 0 && n_tiles < (int64_t(1) << 32), "gs_tile_order: bad n_tiles");
+  if (n_tiles == 0) return GS_OK;
+  GS_REQUIRE(tile_ranges && ws && order, "gs_tile_order: NULL argument");
+  GS_REQUIRE(ws_bytes >= gs_tile_order_workspace_bytes(n_tiles), "gs_tile_order: workspace too small");
+  uint32_t* hist = (uint32_t*)ws;
+  uint32_t* start = hist + kOrderBuckets;
+  uint32_t* cursor = start + kOrderBuckets;
+  hipStream_t s = as_stream(stream);
+  gs_status st = gs_zero(ws, 3 * kOrderBuckets * sizeof(uint32_t), stream);
+  if (st != GS_OK) return st;
+  const unsigned blocks = (unsigned)ceil_div(n_tiles, kOrderThreads);
+  hipLaunchKernelGGL(k_order_count, dim3(blocks), dim3(kOrderThreads), 0, s, tile_ranges, n_tiles,
+                     hist);
+  GS_LAUNCH_CHECK("gs_tile_order/count");
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, s, hist, start);
+  GS_LAUNCH_CHECK("gs_tile_order/scan");
+  hipLaunchKernelGGL(k_order_scatter, dim3(blocks), dim3(kOrderThreads), 0, s, tile_ranges,
+                     n_tiles, start, cursor, order);
+  GS_LAUNCH_CHECK("gs_tile_order/scatter");
+  return GS_OK;
+}
+
+int64_t gs_chunk_max_items(int64_t n_tiles, int64_t dup_capacity, int32_t chunk) {
+  if (n_tiles < 0 || dup_capacity < 0 || chunk <= 0) return 0;
+  return n_tiles + dup_capacity / chunk + 1;
+}
+
+gs_status gs_chunk_items(const uint32_t* tile_ranges, int64_t n_tiles, int32_t chunk,
+                         int64_t max_items, uint32_t* chunk_offset, uint32_t* chunk_items,
+                         void* stream) {
+  clear_error();
+  GS_REQUIRE(n_tiles >= 0 && n_tiles < (int64_t(1) << 31), "gs_chunk_items: bad n_tiles");
+  GS_REQUIRE(chunk > 0 && chunk % kRasterWave == 0, "gs_chunk_items: chunk %d not a positive multiple of 64", chunk);
+  GS_REQUIRE(tile_ranges && chunk_offset && chunk_items, "gs_chunk_items: NULL argument");
+  GS_REQUIRE(max_items > 0, "gs_chunk_items: max_items must be positive");
+  hipStream_t s = as_stream(stream);
+  const unsigned blocks = (unsigned)ceil_div(n_tiles + 1, 256);
+  hipLaunchKernelGGL(k_chunk_count, dim3(blocks), dim3(256), 0, s, tile_ranges, n_tiles, chunk,
+                     chunk_offset);
+  GS_LAUNCH_CHECK("gs_chunk_items/count");
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, chunk_offset, n_tiles + 1);
+  GS_LAUNCH_CHECK("gs_chunk_items/scan");
+  hipLaunchKernelGGL(k_chunk_items, dim3(blocks), dim3(256), 0, s, chunk_offset, n_tiles, max_items,
+                     chunk_items);
+  GS_LAUNCH_CHECK("gs_chunk_items/items");
+  return GS_OK;
+}
+
 gs_status gs_raster_fwd(const gs_projected* proj, const gs_views* views, const gs_tiling* tiling,
                         const uint32_t* ids, const uint32_t* tile_ranges, const float bg[3],
-                        float* image, float* T_final, int32_t* n_contrib, void* stream) {
+                        float* image, float* T_final, int32_t* n_contrib,
+                        const gs_raster_plan* plan, void* stream) {
   clear_error();
-  RasterArgs a;
+  RasterDev a;
   gs_status st = raster_prepare(proj, views, tiling, ids, tile_ranges, bg, "gs_raster_fwd", a);
   if (st != GS_OK) return st;
   GS_REQUIRE(image != nullptr, "gs_raster_fwd: NULL image");
   GS_REQUIRE((T_final == nullptr) == (n_contrib == nullptr),
              "gs_raster_fwd: T_final and n_contrib must both be set or both be NULL");
   hipStream_t s = as_stream(stream);
+  st = plan_prepare(plan, s, "gs_raster_fwd");
+  if (st != GS_OK) return st;
+  const Launch L = make_launch(a, plan);
 #define GS_FWD_CASE(a_, b_)                                              \
   if (tiling->tile_w == a_ && tiling->tile_h == b_)                      \
-    launch_fwd<a_, b_>(a, image, T_final, n_contrib, s);                 \
+    launch_fwd<a_, b_>(a, L, image, T_final, n_contrib, s);              \
   else
   GS_RASTER_SHAPES(GS_FWD_CASE) {}
 #undef GS_FWD_CASE
@@ -403,9 +764,9 @@ gs_status gs_raster_fwd(const gs_projected* proj, const gs_views* views, const g
 gs_status gs_raster_bwd(const gs_projected* proj, const gs_views* views, const gs_tiling* tiling,
                         const uint32_t* ids, const uint32_t* tile_ranges, const float bg[3],
                         const float* T_final, const int32_t* n_contrib, const float* d_image,
-                        int32_t mode, float* d_rec, void* stream) {
+                        int32_t mode, float* d_rec, const gs_raster_plan* plan, void* stream) {
   clear_error();
-  RasterArgs a;
+  RasterDev a;
   gs_status st = raster_prepare(proj, views, tiling, ids, tile_ranges, bg, "gs_raster_bwd", a);
   if (st != GS_OK) return st;
   GS_REQUIRE(mode == GS_BWD_STORED || mode == GS_BWD_RECOMPUTE, "gs_raster_bwd: bad mode %d",
@@ -414,9 +775,12 @@ gs_status gs_raster_bwd(const gs_projected* proj, const gs_views* views, const g
   GS_REQUIRE(mode == GS_BWD_RECOMPUTE || (T_final && n_contrib),
              "gs_raster_bwd: STORED mode needs T_final and n_contrib");
   hipStream_t s = as_stream(stream);
+  st = plan_prepare(plan, s, "gs_raster_bwd");
+  if (st != GS_OK) return st;
+  const Launch L = make_launch(a, plan);
 #define GS_BWD_CASE(a_, b_)                                                   \
   if (tiling->tile_w == a_ && tiling->tile_h == b_)                           \
-    launch_bwd<a_, b_>(a, T_final, n_contrib, d_image, mode, d_rec, s);       \
+    launch_bwd<a_, b_>(a, L, T_final, n_contrib, d_image, mode, d_rec, s);    \
   else
   GS_RASTER_SHAPES(GS_BWD_CASE) {}
 #undef GS_BWD_CASE

@@ -132,6 +132,9 @@ class RasterBuffers:
         self.keys = self.ids = self.ws = None
         self.dup_capacity = 0
         self.ensure_capacity(dup_capacity or max(4 * m, 1024))
+        self.plan = None
+        self.schedule = "default"
+        self.chunk = 0
 
     def ensure_capacity(self, cap):
         cap = int(min(max(cap, 1024), 0xFFFFFFFF))
@@ -144,6 +147,8 @@ class RasterBuffers:
         nbytes = _lib.load().gs_bin_sort_workspace_bytes(self.m, cap, C.byref(self.tiling),
                                                          self.S)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        if getattr(self, "chunk", 0):
+            self._alloc_chunks()
 
     # ---------------------------------------------------------- the calls
 
@@ -158,11 +163,68 @@ class RasterBuffers:
              self.dup_capacity, _ptr(self.ws), self.ws.numel(), _ptr(self.keys), _ptr(self.ids),
              _ptr(self.ranges), _ptr(self.status), s)
 
+    # ---------------------------------------------------------- tile schedule
+
+    def set_schedule(self, mode="default", persistent_waves=0, chunk=0):
+        """How the rasterisers walk the tiles: "default" (XCD-aware order, one
+        work-group per tile), "lpt" (longest tile lists first) or "persistent"
+        (longest first, pulled from an atomic queue by a persistent grid).
+        chunk > 0 (a multiple of 64) cuts the backward's tile lists into
+        chunk-entry work items (stored mode), using forward checkpoints."""
+        dev = self.views.device
+        self.schedule = mode
+        self.chunk = int(chunk) if self.store_state else 0
+        n = self.S * self.tiles_per_slot
+        self.plan = _lib.gs_raster_plan()
+        if mode != "default":
+            self.tile_order = torch.empty(n, dtype=torch.int32, device=dev)
+            nb = _lib.load().gs_tile_order_workspace_bytes(n)
+            self.order_ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev)
+            self.queue = torch.zeros(1, dtype=torch.int32, device=dev) if mode == "persistent" else None
+            self.plan.tile_order = self.tile_order.data_ptr()
+            self.plan.queue = self.queue.data_ptr() if self.queue is not None else None
+            self.plan.persistent_waves = int(persistent_waves)
+        if self.chunk:
+            self.chunk_offset = torch.empty(n + 1, dtype=torch.int32, device=dev)
+            self._alloc_chunks()
+        if mode == "default" and not self.chunk:
+            self.plan = None
+
+    def _alloc_chunks(self):
+        dev = self.views.device
+        n = self.S * self.tiles_per_slot
+        self.max_items = int(_lib.load().gs_chunk_max_items(n, self.dup_capacity, self.chunk))
+        self.chunk_items = torch.empty(self.max_items, dtype=torch.int32, device=dev)
+        self.checkpoints = torch.empty((self.max_items, self.tile[0] * self.tile[1], 4),
+                                       dtype=torch.float32, device=dev)
+        self.plan.chunk = self.chunk
+        self.plan.chunk_offset = self.chunk_offset.data_ptr()
+        self.plan.chunk_items = self.chunk_items.data_ptr()
+        self.plan.checkpoints = self.checkpoints.data_ptr()
+        self.plan.image = self.image.data_ptr()
+        self.plan.max_items = self.max_items
+
+    def order_tiles(self, stream=None):
+        """Per-step plan inputs that depend on the sorted lists."""
+        if self.plan is None:
+            return
+        s = stream or stream_handle()
+        n = self.S * self.tiles_per_slot
+        if self.schedule != "default":
+            call("gs_tile_order", _ptr(self.ranges), n, _ptr(self.order_ws), self.order_ws.numel(),
+                 _ptr(self.tile_order), s)
+        if self.chunk:
+            call("gs_chunk_items", _ptr(self.ranges), n, self.chunk, self.max_items,
+                 _ptr(self.chunk_offset), _ptr(self.chunk_items), s)
+
+    def _plan_ref(self):
+        return C.byref(self.plan) if self.plan is not None else None
+
     def raster_fwd(self, bg=(0.0, 0.0, 0.0), stream=None):
         s = stream or stream_handle()
         call("gs_raster_fwd", C.byref(self.proj), C.byref(self.views.struct),
              C.byref(self.tiling), _ptr(self.ids), _ptr(self.ranges), _lib.F3(*bg),
-             _ptr(self.image), _ptr(self.T_final), _ptr(self.n_contrib), s)
+             _ptr(self.image), _ptr(self.T_final), _ptr(self.n_contrib), self._plan_ref(), s)
 
     def raster_bwd(self, d_image, bg=(0.0, 0.0, 0.0), mode=None, stream=None):
         s = stream or stream_handle()
@@ -172,7 +234,7 @@ class RasterBuffers:
         call("gs_raster_bwd", C.byref(self.proj), C.byref(self.views.struct),
              C.byref(self.tiling), _ptr(self.ids), _ptr(self.ranges), _lib.F3(*bg),
              _ptr(self.T_final), _ptr(self.n_contrib), _ptr(d_image), int(mode),
-             _ptr(self.d_rec), s)
+             _ptr(self.d_rec), self._plan_ref(), s)
 
     def project_bwd(self, gstruct, grads_struct_, stream=None):
         s = stream or stream_handle()
@@ -206,6 +268,7 @@ class RasterBuffers:
                 continue
             if st not in (_lib.GS_OK,):
                 raise _lib.GSError("gs_bin_sort", st, _lib.last_error())
+            self.order_tiles()
             self.raster_fwd(bg)
             return req
         raise RuntimeError("duplicate capacity could not be satisfied")
@@ -302,3 +365,29 @@ class LossFn(torch.autograd.Function):
     def backward(ctx, d_loss):
         (d_image,) = ctx.saved_tensors
         return d_image * d_loss.view(-1, 1, 1, 1), None, None, None, None
+
+
+# --------------------------------------------------------------------------
+# k nearest neighbours
+# --------------------------------------------------------------------------
+
+def knn(points, k):
+    """Exact k-NN of device points [3, n] (gs_knn); returns (idx [n,k] int32,
+    dist [n,k] float32) sorted by (distance, index)."""
+    _check_f32(points, "points")
+    n = points.shape[1]
+    idx = torch.empty((n, k), dtype=torch.int32, device=points.device)
+    dist = torch.empty((n, k), dtype=torch.float32, device=points.device)
+    if n == 0:
+        return idx, dist
+    nbytes = _lib.load().gs_knn_workspace_bytes(n, k)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=points.device)
+    call("gs_knn", _ptr(points), n, int(k), _ptr(ws), nbytes, _ptr(idx), _ptr(dist),
+         stream_handle())
+    return idx, dist
+
+
+def knn_mean_distance(points, k=3):
+    """Mean distance to the k nearest neighbours of each device point."""
+    _, d = knn(points, k)
+    return d.mean(dim=1)

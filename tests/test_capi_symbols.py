@@ -56,7 +56,7 @@ def test_host_only_calls(lib):
     v = _lib.gs_views(0, 0, None, None, None)
     p = _lib.gs_projected(None, None, None, 0)
     st = lib.gs_raster_fwd(ctypes.byref(p), ctypes.byref(v), ctypes.byref(t), None, None,
-                           _lib.F3(0, 0, 0), None, None, None, None)
+                           _lib.F3(0, 0, 0), None, None, None, None, None)
     assert st == _lib.GS_ERR_ARG and b"n_slots" in lib.gs_last_error()
     st = lib.gs_adam(None, 1, 0.9, 0.999, 1e-15, 0, 1, None)
     assert st == _lib.GS_ERR_ARG

@@ -349,3 +349,71 @@ def test_adam_matches_oracle(ops):
             assert float(dg[k].abs().max()) == 0.0
             np.testing.assert_allclose(dp[k].cpu().numpy(), ref[k][0], rtol=2e-6, atol=2e-7)
             np.testing.assert_allclose(dm[k].cpu().numpy(), ref[k][1], rtol=1e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("sched", ["lpt", "persistent"])
+def test_schedules_give_identical_results(ops, sched):
+    """Tile order and persistent launches change only the order of work:
+    images are bit-identical, gradients equal up to FP32 atomic ordering."""
+    say("schedule", sched)
+    W, H = 200, 120
+    params = perturbed(surface_scene(5000, 71), 71)
+    cams = scene.orbit_cameras(3, W, H)
+    dev = to_dev(params, torch)
+    out = {}
+    for mode in ("default", sched):
+        bufs = make_bufs(ops, params, cams, W, H, (16, 16))
+        bufs.set_schedule(mode, persistent_waves=37)
+        bufs.render_checked(ops.gaussians_struct(dev))
+        dI = torch.as_tensor(np.random.default_rng(2).normal(size=(3, 3, H, W)).astype(np.float32)).cuda()
+        bufs.zero_d_rec()
+        bufs.raster_bwd(dI)
+        torch.cuda.synchronize()
+        out[mode] = (bufs.image.cpu().numpy(), bufs.n_contrib.cpu().numpy(), bufs.d_rec.cpu().numpy())
+    a, b = out["default"], out[sched]
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    nr = np.linalg.norm(a[2] - b[2]) / np.linalg.norm(a[2])
+    assert nr <= 1e-5, nr
+
+
+@pytest.mark.parametrize("chunk,sched", [(64, "default"), (128, "lpt"), (64, "persistent")])
+def test_chunked_backward_matches_oracle(ops, chunk, sched):
+    """Tile lists cut into chunk-entry work items (forward checkpoints of T and
+    C) give the oracle's gradients; the image is unchanged."""
+    say("chunked bwd", chunk, sched)
+    W, H = 112, 80
+    params = perturbed(surface_scene(20000, 81), 81, amount=0.2)
+    cams = scene.orbit_cameras(2, W, H)
+    bg = (0.05, 0.1, 0.2)
+    dev = to_dev(params, torch)
+    rng = np.random.default_rng(3)
+    dI = rng.normal(size=(2, 3, H, W)).astype(np.float32)
+    res = {}
+    for c in (0, chunk):
+        bufs = make_bufs(ops, params, cams, W, H, (16, 16))
+        bufs.set_schedule(sched if c else "default", persistent_waves=29, chunk=c)
+        bufs.render_checked(ops.gaussians_struct(dev), bg=bg)
+        bufs.zero_d_rec()
+        bufs.raster_bwd(torch.as_tensor(dI).cuda(), bg=bg)
+        torch.cuda.synchronize()
+        res[c] = (bufs.image.cpu().numpy(), bufs.d_rec.cpu().numpy().astype(np.float64),
+                  bufs.ranges.cpu().numpy())
+        if c:
+            n_items = int(bufs.chunk_offset[-1])
+            assert n_items > bufs.S * bufs.tiles_per_slot // 2
+            lens = (res[c][2][:, 1] - res[c][2][:, 0]).astype(np.int64)
+            assert lens.max() > 3 * chunk                      # several chunks per long tile
+            assert n_items == int(np.sum((lens + chunk - 1) // chunk))
+    np.testing.assert_array_equal(res[0][0], res[chunk][0])
+    nr = np.linalg.norm(res[0][1] - res[chunk][1]) / np.linalg.norm(res[0][1])
+    assert nr <= 1e-4, nr
+    rec, tb, nt = bufs.rec.cpu().numpy(), bufs.tile_bbox.cpu().numpy(), bufs.n_tiles.cpu().numpy()
+    n = 20000
+    for v in range(2):
+        sl = slice(v * n, (v + 1) * n)
+        o = oracle.render_bwd(rec_to_oracle(rec[sl], tb[sl], nt[sl]), W, H, dI[v], bg=bg,
+                              amb_bits=SAME_RECORD_BITS)
+        ref = np.concatenate([o["d_mean2d"], o["d_conic"], o["d_opacity"][None], o["d_rgb"]]).T
+        ok, worst = grad_tolerance_check(res[chunk][1][sl], ref, o["abs_mass"].T, o["amb_mass"].T)
+        assert ok, worst
