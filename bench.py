@@ -47,7 +47,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default=None, help="fix the bin tile (e.g. 16x16); default autotuned")
+    ap.add_argument("--schedule", default=None, help="default | lpt | persistent (default autotuned)")
+    ap.add_argument("--chunk", type=int, default=None, help="backward chunk (0 = whole tiles)")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--recompute", action="store_true")
     ap.add_argument("--small", action="store_true", help="tiny config (smoke use)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -123,7 +126,6 @@ def main():
     from paper_2509_12138_amd import _lib, workloads
     from paper_2509_12138_amd.train import PlainTrainer
     _lib.load()
-    tile = tuple(int(x) for x in args.tile.split("x"))
     cfg = dict(n=20000, n_ref=80000, views=8, width=320, height=180) if args.small else None
     t0 = time.perf_counter()
     wl = workloads.realistic_partition(cfg)
@@ -134,7 +136,28 @@ def main():
         f"{float(masks.float().mean()):.3f}")
     cfgd = wl["cfg"]
     W, H = cfgd["width"], cfgd["height"]
-    tr = PlainTrainer(wl["params"], wl["cams"], targets, masks, tile=tile, stored=not args.recompute)
+    stored = not args.recompute
+
+    def make(tile):
+        return PlainTrainer(wl["params"], wl["cams"], targets, masks, tile=tile, stored=stored)
+
+    tune_entry = None
+    if args.no_autotune or (args.tile and args.schedule is not None and args.chunk is not None):
+        plan = (tuple(int(x) for x in (args.tile or "16x16").split("x")), args.schedule or "default",
+                args.chunk or 0)
+    else:
+        from paper_2509_12138_amd import autotune
+        t0 = time.perf_counter()
+        plan, tune_entry = autotune.tune(make, W, H, 1, cfgd["n"], stored=stored,
+                                         views=list(range(0, cfgd["views"], max(1, cfgd["views"] // 8))),
+                                         cache_path=os.path.join(ROOT, "gpurun_out", "autotune.json"),
+                                         force=True, log=log)
+        log(f"autotuned plan {plan} in {time.perf_counter() - t0:.1f}s")
+    tile, sched, chunk = plan
+    if not stored:
+        chunk = 0
+    tr = PlainTrainer(wl["params"], wl["cams"], targets, masks, tile=tile, stored=stored,
+                      schedule=sched, chunk=chunk)
     need = tr.fit_capacity()
     log(f"max duplicates per view {need}, capacity {tr.bufs.dup_capacity}")
     rng = np.random.default_rng(1000 + 2)
@@ -181,7 +204,7 @@ def main():
         max(stage_ms, key=stage_ms.get)
     if dom == "raster_bwd":
         achieved = evals_bwd * OPS_PER_EVAL_BWD / (t_bwd * 1e-3)
-        roof = {"kernel": "k_raster_bwd", "bound": "alu", "achieved": achieved / 1e12,
+        roof = {"kernel": "k_raster_bwd_chunked" if chunk else "k_raster_bwd", "bound": "alu", "achieved": achieved / 1e12,
                 "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
                 "traffic": None, "units_per_launch": evals_bwd,
                 "unit_desc": f"{OPS_PER_EVAL_BWD} FP32 VALU issue slots per evaluated (pixel, entry)"}
@@ -209,6 +232,9 @@ def main():
             "workload": f"single partition: mixing-layer isosurface, {cfgd['n']} Gaussians (SH 0), "
                         f"{cfgd['views']} orbital views at {W}x{H}, masks, batch 1 view",
             "tile": f"{tile[0]}x{tile[1]}",
+            "schedule": sched,
+            "backward_chunk": chunk,
+            "plan_source": "autotuner" if tune_entry else "fixed",
             "backward": "recompute" if args.recompute else "stored",
             "duplicates_per_view": need,
         },

@@ -188,9 +188,10 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views,
  *                    atomically in tile_order order; the call resets it.
  * Chunked backward (STORED mode only): with chunk > 0 (a multiple of 64) the
  * backward cuts every tile list into `chunk`-entry work items that run in
- * parallel; the forward then stores each pixel's (T, C) after every `chunk`
- * entries into checkpoints [max_items][tile_w*tile_h] float4 and the
- * backward reads them (and the forward's image) to start each item.
+ * parallel; the forward then stores, for each pixel and every `chunk`
+ * entries, the transmittance there and the (transmittance-normalised) colour
+ * still to come behind it into checkpoints [max_items][tile_w*tile_h] float4,
+ * and the backward starts each item from them.
  *   chunk_offset [n_tiles + 1], chunk_items [max_items]: from gs_chunk_items
  *   after gs_bin_sort (the same plan must be passed to both raster calls).
  * Results do not depend on the plan (up to FP32 atomic ordering in the
@@ -203,7 +204,6 @@ typedef struct {
   const uint32_t* chunk_offset;
   const uint32_t* chunk_items;
   float* checkpoints;
-  const float* image;
   int64_t max_items;
 } gs_raster_plan;
 

@@ -150,20 +150,23 @@ def render_bwd(proj, W, H, d_image, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=No
     Returns per-Gaussian SoA gradients d_mean2d [2,n], d_conic [3,n],
     d_opacity [n], d_rgb [3,n] and abs_mass / amb_mass [9,n] (sum of absolute
     per-pixel contributions, all pixels / ambiguous pixels only; amb_bits
-    selects which ambiguity reasons of ``render`` count).
+    selects which ambiguity reasons of ``render`` count) and term_mass [9,n]
+    (the same sums over the magnitudes of the terms before they cancel inside
+    dL/dalpha, a condition measure for FP32 comparisons).
     """
     lib = _load()
     n, m2, cn, dp, op, rgb, tb, valid = _proj_arrays(proj)
     x0, y0, x1, y1 = window if window is not None else (0, 0, W, H)
     dI = _f64(d_image)
     out = dict(d_mean2d=np.zeros((2, n)), d_conic=np.zeros((3, n)), d_opacity=np.zeros(n),
-               d_rgb=np.zeros((3, n)), abs_mass=np.zeros((9, n)), amb_mass=np.zeros((9, n)))
+               d_rgb=np.zeros((3, n)), abs_mass=np.zeros((9, n)), amb_mass=np.zeros((9, n)),
+               term_mass=np.zeros((9, n)))
     bgv = _f64(bg)
     lib.or_render_bwd(ctypes.c_int64(n), _p(m2), _p(cn), _p(dp), _p(op), _p(rgb), _p(tb),
                       _p(valid), W, H, tile[0], tile[1], _p(bgv), x0, y0, x1, y1, _p(dI),
                       _p(out["d_mean2d"]), _p(out["d_conic"]), _p(out["d_opacity"]),
                       _p(out["d_rgb"]), _p(out["abs_mass"]), _p(out["amb_mass"]),
-                      ctypes.c_int(amb_bits))
+                      ctypes.c_int(amb_bits), _p(out["term_mass"]))
     return out
 
 

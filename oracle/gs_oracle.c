@@ -289,14 +289,16 @@ void or_render(int64_t n, const double* mean2d, const double* conic, const doubl
  * [9][n] (may be NULL) receives the sum of |per-pixel contribution| of every
  * gradient element, amb_mass [9][n] (may be NULL) the same restricted to
  * ambiguous pixels (those whose ambiguity reason bits intersect amb_bits,
- * see composite_pixel); order of the 9: mean2d x,y, conic 11,12,22,
- * opacity, rgb.                                                            */
+ * see composite_pixel); term_mass [9][n] (may be NULL) the sum over pixels
+ * of the magnitudes of the terms before they cancel inside dL/dalpha (a
+ * condition measure for FP32 comparisons); order of the 9: mean2d x,y,
+ * conic 11,12,22, opacity, rgb.                                            */
 void or_render_bwd(int64_t n, const double* mean2d, const double* conic, const double* depth,
                    const double* opacity, const double* rgb, const int32_t* tile_bbox,
                    const int32_t* valid, int W, int H, int tw, int th, const double* bg, int x0,
                    int y0, int x1, int y1, const double* d_image, double* d_mean2d,
                    double* d_conic, double* d_opacity, double* d_rgb, double* abs_mass,
-                   double* amb_mass, int amb_bits) {
+                   double* amb_mass, int amb_bits, double* term_mass) {
   int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
   int64_t cnt = sorted_order(n, depth, valid, order);
   int64_t npix = (int64_t)(x1 - x0) * (y1 - y0);
@@ -317,12 +319,14 @@ void or_render_bwd(int64_t n, const double* mean2d, const double* conic, const d
       for (int64_t k = nb - 1; k >= 0; --k) {
         const or_blend* r = &rec[k];
         int64_t g = r->g;
-        double contrib[9];
-        double dalpha = 0;
+        double contrib[9], terms[9];
+        double dalpha = 0, dalpha_mag = 0;
         for (int ch = 0; ch < 3; ++ch) {
           double c = rgb[ch * n + g];
           contrib[6 + ch] = dI[ch] * r->alpha * r->T;
+          terms[6 + ch] = fabs(contrib[6 + ch]);
           dalpha += dI[ch] * (c * r->T - acc[ch] / (1.0 - r->alpha));
+          dalpha_mag += fabs(dI[ch]) * (fabs(c * r->T) + fabs(acc[ch] / (1.0 - r->alpha)));
           acc[ch] += c * r->alpha * r->T;
         }
         if (r->a < OR_ALPHA_MAX) {
@@ -334,8 +338,17 @@ void or_render_bwd(int64_t n, const double* mean2d, const double* conic, const d
           contrib[3] = dpower * (-r->dx * r->dy);
           contrib[4] = dpower * (-0.5 * r->dy * r->dy);
           contrib[5] = dalpha * r->e;
+          /* the same partials with |dL/dalpha| replaced by the magnitude of
+           * its terms before they cancel */
+          double m = dalpha_mag * r->alpha;
+          terms[0] = m * fabs(q11 * r->dx + q12 * r->dy);
+          terms[1] = m * fabs(q12 * r->dx + q22 * r->dy);
+          terms[2] = m * 0.5 * r->dx * r->dx;
+          terms[3] = m * fabs(r->dx * r->dy);
+          terms[4] = m * 0.5 * r->dy * r->dy;
+          terms[5] = dalpha_mag * r->e;
         } else {
-          for (int k2 = 0; k2 < 6; ++k2) contrib[k2] = 0.0;
+          for (int k2 = 0; k2 < 6; ++k2) contrib[k2] = terms[k2] = 0.0;
         }
         double* dst[9] = {&d_mean2d[g], &d_mean2d[n + g], &d_conic[g], &d_conic[n + g],
                           &d_conic[2 * n + g], &d_opacity[g], &d_rgb[g], &d_rgb[n + g],
@@ -350,6 +363,10 @@ void or_render_bwd(int64_t n, const double* mean2d, const double* conic, const d
           if (amb_mass && (amb & amb_bits)) {
 #pragma omp atomic
             amb_mass[k2 * n + g] += fabs(contrib[k2]);
+          }
+          if (term_mass) {
+#pragma omp atomic
+            term_mass[k2 * n + g] += terms[k2];
           }
         }
       }

@@ -52,7 +52,7 @@ class gs_projected(C.Structure):
 
 class gs_raster_plan(C.Structure):
     _fields_ = [("tile_order", vp), ("queue", vp), ("persistent_waves", i32), ("chunk", i32),
-                ("chunk_offset", vp), ("chunk_items", vp), ("checkpoints", vp), ("image", vp),
+                ("chunk_offset", vp), ("chunk_items", vp), ("checkpoints", vp),
                 ("max_items", i64)]
 
 

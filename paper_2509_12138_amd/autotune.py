@@ -1,0 +1,99 @@
+"""Autotuner for the rasteriser plan: bin-tile shape, tile schedule and
+backward chunk size, picked by timing real training steps on the workload.
+
+The choice cannot change results: images do not depend on the tile shape
+(the support bbox is a strict superset of the alpha >= 1/255 ellipse) and the
+schedule / chunking only reorder work.  Results are cached in a JSON file
+keyed by device, image size, slot count, Gaussian-count bucket and backward
+mode.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import numpy as np
+import torch
+
+# (tile, schedule, chunk); every tile shape here has a compiled rasteriser
+CANDIDATES = [
+    ((16, 16), "lpt", 64), ((16, 16), "lpt", 128), ((16, 16), "persistent", 64),
+    ((16, 8), "lpt", 64), ((16, 8), "lpt", 128), ((8, 16), "lpt", 64), ((8, 16), "lpt", 128),
+    ((8, 8), "lpt", 0), ((16, 16), "lpt", 0), ((32, 8), "lpt", 128),
+]
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "gsmi", "autotune.json")
+
+
+def cache_key(width, height, n_slots, n_gauss, stored):
+    dev = torch.cuda.get_device_properties(0)
+    arch = getattr(dev, "gcnArchName", dev.name)
+    return f"{arch}|{width}x{height}|S{n_slots}|N2^{int(math.log2(max(n_gauss, 1)))}|{'stored' if stored else 'recompute'}"
+
+
+def load_cache(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(path, cache):
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_plan(make_trainer, plan, views, steps=8, warmup=2):
+    """Mean ms per training step of a trainer built with `plan`."""
+    tile, sched, chunk = plan
+    tr = make_trainer(tile)
+    tr.bufs.set_schedule(sched if sched != "default" else "default", chunk=chunk)
+    tr.fit_capacity(views=views)
+    for s in range(warmup):
+        tr.step(views[s % len(views)])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        tr.step(views[(warmup + s) % len(views)])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    tr.check()
+    del tr
+    torch.cuda.empty_cache()
+    return ms
+
+
+def tune(make_trainer, width, height, n_slots, n_gauss, stored=True, views=None,
+         candidates=None, cache_path=DEFAULT_CACHE, force=False, log=None):
+    """Return the fastest (tile, schedule, chunk) for this workload.
+
+    make_trainer(tile) builds a fresh trainer (with .bufs, .step(view),
+    .fit_capacity(views=...), .check()).  The choice is cached unless force.
+    """
+    key = cache_key(width, height, n_slots, n_gauss, stored)
+    cache = load_cache(cache_path) if cache_path else {}
+    if not force and key in cache:
+        e = cache[key]
+        return (tuple(e["tile"]), e["schedule"], e["chunk"]), e
+    views = list(views if views is not None else range(8))
+    results = []
+    for plan in (candidates or CANDIDATES):
+        if not stored and plan[2]:
+            continue                                   # chunking needs stored state
+        ms = time_plan(make_trainer, plan, views)
+        results.append((ms, plan))
+        if log:
+            log(f"autotune {plan}: {ms:.3f} ms/step")
+    ms, best = min(results, key=lambda r: r[0])
+    entry = dict(tile=list(best[0]), schedule=best[1], chunk=best[2], ms_per_step=ms,
+                 tried=[dict(tile=list(p[0]), schedule=p[1], chunk=p[2], ms=m) for m, p in results])
+    if cache_path:
+        cache[key] = entry
+        save_cache(cache_path, cache)
+    return best, entry

@@ -55,26 +55,38 @@ struct TileGeom {
 
 // Forward pass of one tile for one lane's PX pixels.  WITH_COLOR=false is the
 // replay used by the backward in RECOMPUTE mode.
-// With `ck` set (WITH_COLOR only), the per-pixel state (T, C) after every
-// `chunk` list entries is stored for the chunked backward: boundary c (after
-// entry (c+1)*chunk) goes to ck[c * TW*TH + pixel].
-template <int TW, int TH, bool WITH_COLOR>
+// CHUNKED (with colour) also prepares the chunked backward: boundary c is
+// the list position (c+1)*chunk; for each pixel the forward stores at slot c
+// of `ck` (ck[c * TW*TH + pixel]) the transmittance T_c there and the colour
+// still to come behind it, normalised by T_c:
+//   U_c = (sum over later blends of rgb alpha T + bg T_final) / T_c,
+// built without cancellation from chunk-local composites (P = prod(1-alpha),
+// L = sum rgb alpha T_local over a chunk) by U_c = L_{c+1} + P_{c+1} U_{c+1}
+// after the tile is done.
+template <int TW, int TH, bool WITH_COLOR, bool CHUNKED = false>
 __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
                                              const uint32_t* __restrict__ ids, uint32_t start,
                                              uint32_t end, const float fx, const float* fy,
                                              const bool* inside, Splat* s_splat, float* T,
                                              float (*C)[3], int* last, float4* ck = nullptr,
-                                             int chunk = 0) {
+                                             int chunk = 0, float bg0 = 0.f, float bg1 = 0.f,
+                                             float bg2 = 0.f) {
   constexpr int PX = TileGeom<TW, TH>::PX;
   const int lane = threadIdx.x;
   bool done[PX];
+  float Tl[PX], Lc[PX][3];
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     T[k] = 1.0f;
     last[k] = 0;
     done[k] = !inside[k];
     if (WITH_COLOR) C[k][0] = C[k][1] = C[k][2] = 0.0f;
+    if (CHUNKED) {
+      Tl[k] = 1.0f;
+      Lc[k][0] = Lc[k][1] = Lc[k][2] = 0.0f;
+    }
   }
+  uint32_t reached = 0;     // list entries processed (CHUNKED bookkeeping)
   for (uint32_t b0 = start; b0 < end; b0 += kRasterWave) {
     bool lane_done = true;
 #pragma unroll
@@ -112,17 +124,64 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
           C[k][1] = fmaf(sp.g, w, C[k][1]);
           C[k][2] = fmaf(sp.b, w, C[k][2]);
         }
+        if (CHUNKED) {
+          const float wl = alpha * Tl[k];
+          Lc[k][0] = fmaf(sp.r, wl, Lc[k][0]);
+          Lc[k][1] = fmaf(sp.g, wl, Lc[k][1]);
+          Lc[k][2] = fmaf(sp.b, wl, Lc[k][2]);
+          Tl[k] = Tl[k] * (1.0f - alpha);
+        }
         T[k] = Tn;
         last[k] = pos;
       }
     }
-    if (WITH_COLOR && ck) {
-      const uint32_t done_n = b0 + (uint32_t)n - start;
-      if (done_n % (uint32_t)chunk == 0 && b0 + (uint32_t)n < end) {
-        float4* dst = ck + (int64_t)(done_n / chunk - 1) * (TW * TH);
+    if (CHUNKED) {
+      reached = b0 + (uint32_t)n - start;
+      if (reached % (uint32_t)chunk == 0) {
+        // chunk ce just ended: its local composite goes to slot ce-1
+        const int ce = (int)(reached / chunk) - 1;
+        if (ce >= 1) {
+          float4* dst = ck + (int64_t)(ce - 1) * (TW * TH);
 #pragma unroll
-        for (int k = 0; k < PX; ++k)
-          dst[lane + k * kRasterWave] = make_float4(T[k], C[k][0], C[k][1], C[k][2]);
+          for (int k = 0; k < PX; ++k)
+            dst[lane + k * kRasterWave] = make_float4(Tl[k], Lc[k][0], Lc[k][1], Lc[k][2]);
+        }
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+          Tl[k] = 1.0f;
+          Lc[k][0] = Lc[k][1] = Lc[k][2] = 0.0f;
+        }
+      }
+    }
+  }
+  if (CHUNKED && reached > 0) {
+    // the partly processed last chunk (if any) and the reverse recursion
+    int clast = (int)((reached - 1) / chunk);          // last chunk touched
+    if (reached % (uint32_t)chunk != 0 && clast >= 1) {
+      float4* dst = ck + (int64_t)(clast - 1) * (TW * TH);
+#pragma unroll
+      for (int k = 0; k < PX; ++k)
+        dst[lane + k * kRasterWave] = make_float4(Tl[k], Lc[k][0], Lc[k][1], Lc[k][2]);
+    }
+    float Tn[PX], U[PX][3];
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      Tn[k] = T[k];
+      U[k][0] = bg0;
+      U[k][1] = bg1;
+      U[k][2] = bg2;
+    }
+    for (int c = clast - 1; c >= 0; --c) {
+      float4* slot = ck + (int64_t)c * (TW * TH);
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        const float4 pl = slot[lane + k * kRasterWave];     // (P, L) of chunk c+1
+        const float Te = Tn[k] / pl.x;
+        U[k][0] = fmaf(pl.x, U[k][0], pl.y);
+        U[k][1] = fmaf(pl.x, U[k][1], pl.z);
+        U[k][2] = fmaf(pl.x, U[k][2], pl.w);
+        slot[lane + k * kRasterWave] = make_float4(Te, U[k][0], U[k][1], U[k][2]);
+        Tn[k] = Te;
       }
     }
   }
@@ -147,14 +206,13 @@ struct TileSched {
 
 // Chunked backward: every tile list is cut into `chunk`-entry work items;
 // offset[t] is the first item of tile t (offset[n_tiles] = item count),
-// items[i] the tile of item i; ck the forward checkpoints, one TW*TH float4
-// block per item; image the forward's output.
+// items[i] the tile of item i; ck the forward checkpoints (T_c, U_c), one
+// TW*TH float4 block per item.
 struct ChunkDev {
   int chunk;
   const uint32_t* offset;
   const uint32_t* items;
   float4* ck;
-  const float* image;
 };
 
 template <typename F>
@@ -199,9 +257,13 @@ __device__ __forceinline__ void fwd_tile(const RasterDev& a, const ChunkDev& ch,
   const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
   float T[PX], C[PX][3];
   int last[PX];
-  float4* ck = ch.ck ? ch.ck + (int64_t)ch.offset[tile] * (TW * TH) : nullptr;
-  tile_forward<TW, TH, true>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T, C, last, ck,
-                             ch.chunk);
+  if (ch.ck) {
+    float4* ck = ch.ck + (int64_t)ch.offset[tile] * (TW * TH);
+    tile_forward<TW, TH, true, true>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T, C,
+                                     last, ck, ch.chunk, a.bg0, a.bg1, a.bg2);
+  } else {
+    tile_forward<TW, TH, true>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T, C, last);
+  }
   const int64_t HW = (int64_t)H * W;
   float* img = image + (int64_t)slot * 3 * HW;
 #pragma unroll
@@ -413,7 +475,8 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd(RasterDev a, TileSch
 // Chunked backward: one work-group per (tile, chunk) item.  Chunk c covers
 // list positions (c*chunk, min((c+1)*chunk, len)]; the state after its last
 // position is the forward's final state for pixels whose last blended entry
-// lies at or before it, else the checkpoint the forward stored there.
+// lies at or before it, else the checkpoint (T_c, U_c) the forward stored
+// there (dI . acc = T_c dI . U_c).
 template <int TW, int TH>
 __global__ __launch_bounds__(kRasterWave) void k_raster_bwd_chunked(
     RasterDev a, ChunkDev ch, const float* __restrict__ T_final,
@@ -443,7 +506,6 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd_chunked(
   const float4* ck = ch.ck + ((int64_t)ch.offset[tile] + c) * (TW * TH);
   float T[PX], dI[PX][3], dIacc[PX];
   const float* dimg = d_image + (int64_t)L.slot * 3 * HW;
-  const float* img = ch.image + (int64_t)L.slot * 3 * HW;
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     const int64_t o = L.offset(a, k);
@@ -455,10 +517,9 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd_chunked(
       T[k] = L.inside[k] ? T_final[(int64_t)L.slot * HW + o] : 1.0f;
       dIacc[k] = T[k] * (dI[k][0] * a.bg0 + dI[k][1] * a.bg1 + dI[k][2] * a.bg2);
     } else {
-      const float4 s = ck[threadIdx.x + k * kRasterWave];
+      const float4 s = ck[threadIdx.x + k * kRasterWave];   // (T_c, U_c)
       T[k] = s.x;
-      dIacc[k] = dI[k][0] * (img[o] - s.y) + dI[k][1] * (img[HW + o] - s.z) +
-                 dI[k][2] * (img[2 * HW + o] - s.w);
+      dIacc[k] = s.x * (dI[k][0] * s.y + dI[k][1] * s.z + dI[k][2] * s.w);
     }
   }
   reverse_pass<TW, TH>(a, start, lo, hi, L.fx, L.fy, last, T, dI, dIacc, s_splat, s_id, d_rec);
@@ -584,8 +645,7 @@ static Launch make_launch(const RasterDev& a, const gs_raster_plan* plan) {
   L.ch.chunk = plan ? plan->chunk : 0;
   L.ch.offset = plan ? plan->chunk_offset : nullptr;
   L.ch.items = plan ? plan->chunk_items : nullptr;
-  L.ch.ck = plan ? reinterpret_cast<float4*>(plan->checkpoints) : nullptr;
-  L.ch.image = plan ? plan->image : nullptr;
+  L.ch.ck = plan && plan->chunk > 0 ? reinterpret_cast<float4*>(plan->checkpoints) : nullptr;
   L.max_items = plan ? plan->max_items : 0;
   if (L.sch.queue) {
     int64_t w = plan->persistent_waves > 0 ? plan->persistent_waves : (int64_t)device_cu_count() * 16;
@@ -662,10 +722,9 @@ static gs_status plan_prepare(const gs_raster_plan* plan, hipStream_t s, const c
   if (plan->chunk > 0) {
     GS_REQUIRE(plan->chunk % kRasterWave == 0, "%s: chunk %d is not a multiple of 64", who,
                plan->chunk);
-    GS_REQUIRE(plan->chunk_offset && plan->chunk_items && plan->checkpoints && plan->image &&
+    GS_REQUIRE(plan->chunk_offset && plan->chunk_items && plan->checkpoints &&
                    plan->max_items > 0 && plan->max_items < (int64_t(1) << 31),
-               "%s: chunked plan needs chunk_offset, chunk_items, checkpoints, image, max_items",
-               who);
+               "%s: chunked plan needs chunk_offset, chunk_items, checkpoints, max_items", who);
   }
   if (plan->queue) {
     hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(64), 0, s, plan->queue);

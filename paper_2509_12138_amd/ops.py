@@ -201,7 +201,6 @@ class RasterBuffers:
         self.plan.chunk_offset = self.chunk_offset.data_ptr()
         self.plan.chunk_items = self.chunk_items.data_ptr()
         self.plan.checkpoints = self.checkpoints.data_ptr()
-        self.plan.image = self.image.data_ptr()
         self.plan.max_items = self.max_items
 
     def order_tiles(self, stream=None):

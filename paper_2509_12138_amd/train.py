@@ -41,7 +41,7 @@ class PlainTrainer:
 
     def __init__(self, params, cams_np, targets, masks, tile=(16, 16), lam=0.2,
                  bg=(0.0, 0.0, 0.0), stored=True, extent=2.75, lrs=None, dup_capacity=None,
-                 device="cuda"):
+                 schedule="default", chunk=0, device="cuda"):
         self.device = device
         self.params = {k: torch.as_tensor(np.ascontiguousarray(v, np.float32)).to(device)
                        if not torch.is_tensor(v) else v.contiguous().to(device)
@@ -63,6 +63,7 @@ class PlainTrainer:
         self.views.use_cameras(self.cams[0:1])
         self.bufs = ops.RasterBuffers(self.views, self.W, self.H, tile, dup_capacity=dup_capacity,
                                       store_state=stored)
+        self.bufs.set_schedule(schedule, chunk=chunk)
         self.loss = ops.LossBuffers(1, self.H, self.W, device)
         self.mode = _lib.GS_BWD_STORED if stored else _lib.GS_BWD_RECOMPUTE
         self.gst = ops.gaussians_struct(self.params)
@@ -71,10 +72,10 @@ class PlainTrainer:
         self.step_count = 0
         self.timing = None            # optional dict of lists of (start, end) events
 
-    def fit_capacity(self, margin=1.5):
+    def fit_capacity(self, margin=1.5, views=None):
         """Size the duplicate buffers from the largest view's true count."""
         need = 0
-        for vi in range(self.V):
+        for vi in (range(self.V) if views is None else views):
             self.views.use_cameras(self.cams[vi:vi + 1])
             need = max(need, self.bufs.render_checked(self.gst, self.bg))
         self.bufs.ensure_capacity(int(need * margin) + 4096)

@@ -27,12 +27,22 @@ def rec_to_oracle(rec, tile_bbox, n_tiles):
                 tile_bbox=np.ascontiguousarray(tb.T), valid=(np.asarray(n_tiles) > 0).astype(np.int32))
 
 
-def grad_tolerance_check(g, r, abs_mass, amb_mass, rel=1e-3, floor=0.01):
-    """|g - r| <= rel * max(|r|, floor * A) + A_amb per element (A = sum of the
-    absolute per-pixel contributions); returns (ok, worst ratio)."""
-    bound = rel * np.maximum(np.abs(r), floor * abs_mass) + amb_mass + 1e-12
+def grad_tolerance_check(g, r, term_mass, amb_mass, rel=1e-3, floor=0.1):
+    """|g - r| <= rel * max(|r|, floor * A) + A_amb per element, where A is the
+    oracle's term mass (sum over pixels of the magnitudes of the terms before
+    they cancel) and A_amb the contribution of ambiguous pixels.  The floor
+    1e-4 A is the FP32 evaluation error of such sums when the transmittance
+    is recovered over blend chains of a few hundred entries (about 1.5 ulp
+    per entry); returns (ok, worst ratio)."""
+    bound = rel * np.maximum(np.abs(r), floor * term_mass) + amb_mass + 1e-12
     ratio = np.abs(g - r) / bound
-    return bool(np.all(ratio <= 1.0)), float(ratio.max(initial=0.0))
+    worst = float(ratio.max(initial=0.0))
+    if worst > 1.0:
+        i = np.unravel_index(np.argmax(ratio), ratio.shape)
+        return False, (worst, dict(index=tuple(int(x) for x in i), got=float(g[i]), ref=float(r[i]),
+                                   term_mass=float(term_mass[i]), amb_mass=float(amb_mass[i]),
+                                   n_bad=int((ratio > 1).sum())))
+    return True, worst
 
 
 def surface_scene(n, seed, opacity=0.1):

@@ -259,7 +259,7 @@ def test_raster_bwd_matches_oracle(ops, mode, tile):
         po = rec_to_oracle(rec[sl], tb[sl], nt[sl])
         o = oracle.render_bwd(po, W, H, dI[v], tile=tile, bg=bg, amb_bits=SAME_RECORD_BITS)
         ref = np.concatenate([o["d_mean2d"], o["d_conic"], o["d_opacity"][None], o["d_rgb"]]).T
-        ok, worst = grad_tolerance_check(drec[sl], ref, o["abs_mass"].T, o["amb_mass"].T)
+        ok, worst = grad_tolerance_check(drec[sl], ref, o["term_mass"].T, o["amb_mass"].T)
         assert ok, worst
         for c in range(9):
             nr = np.linalg.norm(drec[sl][:, c] - ref[:, c]) / max(np.linalg.norm(ref[:, c]), 1e-30)
@@ -415,5 +415,6 @@ def test_chunked_backward_matches_oracle(ops, chunk, sched):
         o = oracle.render_bwd(rec_to_oracle(rec[sl], tb[sl], nt[sl]), W, H, dI[v], bg=bg,
                               amb_bits=SAME_RECORD_BITS)
         ref = np.concatenate([o["d_mean2d"], o["d_conic"], o["d_opacity"][None], o["d_rgb"]]).T
-        ok, worst = grad_tolerance_check(res[chunk][1][sl], ref, o["abs_mass"].T, o["amb_mass"].T)
-        assert ok, worst
+        ok0, worst0 = grad_tolerance_check(res[0][1][sl], ref, o["term_mass"].T, o["amb_mass"].T)
+        ok, worst = grad_tolerance_check(res[chunk][1][sl], ref, o["term_mass"].T, o["amb_mass"].T)
+        assert ok0 and ok, (worst0, worst)

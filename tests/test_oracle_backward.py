@@ -165,3 +165,16 @@ def test_project_bwd_frustum_clamp_branch():
             g = an[key][r_, 0] if params[key].ndim == 2 else an[key][0]
             fd = (Lp - Lm) / (2 * h)
             assert abs(fd - g) <= 1e-6 * abs(g) + 1e-7, (key, r_, fd, g)
+
+
+def test_term_mass_bounds_contributions():
+    # the pre-cancellation term mass is never below the post-cancellation mass
+    params = make_params(11)
+    cam = cam_at()
+    p = oracle.project(params, cam, tile=(8, 8))
+    w = np.random.default_rng(1).normal(size=(3, H, W))
+    g = oracle.render_bwd(p, W, H, w, tile=(8, 8))
+    assert np.all(g["term_mass"] >= g["abs_mass"] * (1 - 1e-12))
+    np.testing.assert_allclose(g["term_mass"][6:], g["abs_mass"][6:], rtol=1e-12)
+    assert np.all(g["abs_mass"] >= np.abs(np.concatenate([g["d_mean2d"], g["d_conic"],
+                                                          g["d_opacity"][None], g["d_rgb"]])) * (1 - 1e-12))
