@@ -316,6 +316,16 @@ size_t gs_knn_workspace_bytes(int64_t n, int32_t k);
 gs_status gs_knn(const float* pts, int64_t n, int32_t k, void* ws, size_t ws_bytes,
                  int32_t* idx, float* dist, void* stream);
 
+/* gs_adam with the step count on the device, so that a captured HIP graph
+ * can replay training steps unchanged: the kernels use t = step_dev[0] + 1
+ * for the bias corrections and, for group g with lr_final[g] > 0 (host
+ * array, may be NULL), the log-linear decay lr_g (lr_final[g]/lr_g)^min(t /
+ * decay_steps, 1) (the 3D-GS position schedule); a last kernel stores
+ * step_dev[0] = t.  step_dev: one device int32, 0 before the first step.   */
+gs_status gs_adam_dev(const gs_adam_group* groups, int32_t n_groups, const float* lr_final,
+                      int32_t decay_steps, float beta1, float beta2, float eps,
+                      int32_t* step_dev, int32_t zero_grad, void* stream);
+
 /* Fill `bytes` bytes at device pointer `ptr` with zero using a kernel (safe
  * to capture in a HIP graph).  bytes must be a multiple of 4.             */
 gs_status gs_zero(void* ptr, size_t bytes, void* stream);

@@ -309,6 +309,25 @@ def adam_step(groups, step, beta1=0.9, beta2=0.999, eps=1e-15, zero_grad=True, s
          stream or stream_handle())
 
 
+class DeviceAdam:
+    """Adam whose step count and position-lr decay live on the device
+    (gs_adam_dev), so that captured graphs replay whole training steps."""
+
+    def __init__(self, groups, lr_final=None, decay_steps=30000, beta1=0.9, beta2=0.999,
+                 eps=1e-15, device="cuda"):
+        self.groups = groups
+        n = len(groups)
+        self.lr_final = (_lib.f32 * n)(*([0.0] * n if lr_final is None else lr_final))
+        self.decay_steps = int(decay_steps)
+        self.betas = (beta1, beta2, eps)
+        self.step_dev = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def __call__(self, zero_grad=True, stream=None):
+        call("gs_adam_dev", self.groups, len(self.groups), self.lr_final, self.decay_steps,
+             self.betas[0], self.betas[1], self.betas[2], _ptr(self.step_dev),
+             int(bool(zero_grad)), stream or stream_handle())
+
+
 # --------------------------------------------------------------------------
 # autograd
 # --------------------------------------------------------------------------

@@ -164,3 +164,135 @@ class PlainTrainer:
         self.check()
         hist.append((steps, train_time, None))
         return hist
+
+
+class BatchedTrainer:
+    """Uneven, ghost-padded partitions trained together: every step renders
+    ``views_per_part`` views of every partition (S = partitions x views slots)
+    through ONE launch per stage, and each stage's work is balanced by the
+    longest-first tile order (and the chunked backward).  The views are cut
+    into fixed groups (a seeded permutation of the orbit); each group's step
+    is captured once in a HIP graph (through torch.cuda.CUDAGraph) and then
+    replayed: the step count and the position-lr decay live on the device.
+
+    parts: list of dicts with params (planar SoA arrays), targets [V,3,H,W]
+    float32 and masks [V,H,W] uint8 on the device, all seen from cams_np.
+    The loss of a slot is scaled by 1/views_per_part, so each partition's
+    gradient is the mean over its views; one Adam step per batch.
+    """
+
+    def __init__(self, parts, cams_np, views_per_part=4, tile=(16, 16), schedule="lpt",
+                 chunk=64, stored=True, lam=0.2, bg=(0.0, 0.0, 0.0), extent=2.75, lrs=None,
+                 order_seed=0, graphs=True, dup_capacity=None, device="cuda"):
+        from .scene import concat_params
+        self.device = device
+        self.P = len(parts)
+        self.vpp = views_per_part
+        self.counts = [int(p["params"]["opacity_logit"].shape[-1]) for p in parts]
+        cat = concat_params([{k: np.asarray(v, np.float32) for k, v in p["params"].items()}
+                             for p in parts])
+        self.params = {k: torch.as_tensor(v).to(device) for k, v in cat.items()}
+        self.n = sum(self.counts)
+        self.grads = {k: torch.zeros_like(v) for k, v in self.params.items()}
+        self.m = {k: torch.zeros_like(v) for k, v in self.params.items()}
+        self.v = {k: torch.zeros_like(v) for k, v in self.params.items()}
+        self.V = len(cams_np)
+        assert self.V % views_per_part == 0, "the orbit must split into whole view groups"
+        self.G = self.V // views_per_part
+        self.S = self.P * views_per_part
+        self.W, self.H = int(cams_np[0]["width"]), int(cams_np[0]["height"])
+        rng = np.random.default_rng(order_seed)
+        perm = rng.permutation(self.V)
+        self.group_views = [perm[g * views_per_part:(g + 1) * views_per_part] for g in range(self.G)]
+        cams_all = ops.Views.cams_to_device(cams_np, device)
+        # per group: slot s = p * vpp + j sees view group_views[g][j]
+        self.cams_g = torch.stack([torch.cat([cams_all[self.group_views[g]]] * self.P)
+                                   for g in range(self.G)]).contiguous()
+        self.targets_g = torch.empty((self.G, self.S, 3, self.H, self.W), dtype=torch.float32,
+                                     device=device)
+        self.masks_g = torch.empty((self.G, self.S, self.H, self.W), dtype=torch.uint8, device=device)
+        for g in range(self.G):
+            for p, part in enumerate(parts):
+                idx = torch.as_tensor(self.group_views[g], device=part["targets"].device)
+                self.targets_g[g, p * self.vpp:(p + 1) * self.vpp] = part["targets"][idx]
+                self.masks_g[g, p * self.vpp:(p + 1) * self.vpp] = part["masks"][idx]
+        self.bg, self.lam, self.extent = tuple(bg), lam, extent
+        self.lrs = dict(DEFAULT_LR if lrs is None else lrs)
+        self.lrs["mean"] = self.lrs["mean"] * extent
+        self.views = ops.Views.batch(self.counts, views_per_part, self.cams_g[0], device)
+        self.bufs = ops.RasterBuffers(self.views, self.W, self.H, tile, dup_capacity=dup_capacity,
+                                      store_state=stored)
+        self.bufs.set_schedule(schedule, chunk=chunk)
+        self.mode = _lib.GS_BWD_STORED if stored else _lib.GS_BWD_RECOMPUTE
+        self.loss = ops.LossBuffers(self.S, self.H, self.W, device)
+        self.gst = ops.gaussians_struct(self.params)
+        self.grst = ops.grads_struct(self.grads, self.n)
+        self.groups = ops.adam_groups(self.params, self.grads, self.m, self.v, self.lrs)
+        self.adam = ops.DeviceAdam(self.groups, lr_final=[1.6e-6 * extent, 0, 0, 0, 0],
+                                   decay_steps=30000, device=device)
+        self.use_graphs = graphs
+        self.graphs = {}
+        self._warm = set()
+        self.steps_done = 0
+
+    def fit_capacity(self, margin=1.3):
+        need = 0
+        for g in range(self.G):
+            self.views.use_cameras(self.cams_g[g])
+            need = max(need, self.bufs.render_checked(self.gst, self.bg))
+        self.bufs.ensure_capacity(int(need * margin) + 4096)
+        self.graphs = {}
+        return need
+
+    def _step_body(self, g):
+        b = self.bufs
+        self.views.use_cameras(self.cams_g[g])
+        b.project(self.gst)
+        b.bin_sort()
+        b.order_tiles()
+        b.raster_fwd(self.bg)
+        self.loss(b.image, self.targets_g[g], self.masks_g[g], self.lam, 1.0 / self.vpp, b.status)
+        b.zero_d_rec()
+        b.raster_bwd(self.loss.d_image, self.bg, self.mode)
+        b.project_bwd(self.gst, self.grst)
+        self.adam(zero_grad=True)
+
+    def step(self, g):
+        """One batched step on view group g (graph replay after the first)."""
+        if not self.use_graphs or g not in self._warm:
+            # eager (also the first time, so every kernel is loaded before capture)
+            self._step_body(g)
+            self._warm.add(g)
+        else:
+            graph = self.graphs.get(g)
+            if graph is None:
+                # capture; the capture itself does not execute the work
+                torch.cuda.synchronize()
+                graph = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(graph):
+                    self._step_body(g)
+                self.graphs[g] = graph
+            graph.replay()
+        self.steps_done += 1
+
+    def check(self):
+        st, req = self.bufs.check()
+        if st != _lib.GS_OK:
+            raise _lib.GSError("batched step", st, _lib.last_error())
+        return req
+
+    def evaluate(self):
+        """Masked PSNR per partition (mean over its views); evaluation only."""
+        ps = torch.zeros((self.P, self.V), device=self.device)
+        for g in range(self.G):
+            self.views.use_cameras(self.cams_g[g])
+            self.bufs.render_checked(self.gst, self.bg)
+            pv = masked_psnr(self.bufs.image, self.targets_g[g], self.masks_g[g])
+            for p in range(self.P):
+                for j in range(self.vpp):
+                    ps[p, self.group_views[g][j]] = pv[p * self.vpp + j]
+        return ps.mean(dim=1).cpu().numpy()
+
+    def partition_params(self, p):
+        o = sum(self.counts[:p])
+        return {k: v[..., o:o + self.counts[p]] for k, v in self.params.items()}

@@ -1,0 +1,111 @@
+"""Batched uneven partitions in one launch, graph replay and the device-side
+Adam schedule."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_12138_amd import scene
+from _gpu_helpers import perturbed, say, surface_scene, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+W, H = 96, 72
+
+
+@pytest.fixture(scope="module")
+def parts(gpu):
+    """Three uneven slabs of the bumpy sphere (x-slabs with 0.02 ghost
+    overlap), each with its own targets/masks rendered by the oracle."""
+    pts, nrm = scene.sample_surface(scene.field_sphere_sines, 9000, 64, seed=5)
+    edges = [-1.0, -0.1, 0.25, 1.0]
+    cams = scene.orbit_cameras(8, W, H)
+    out = []
+    for i in range(3):
+        sel = (pts[:, 0] >= edges[i] - 0.02) & (pts[:, 0] <= edges[i + 1] + 0.02)
+        d = scene.knn_mean_distance(pts[sel], 3)
+        prm = scene.gaussians_from_points(pts[sel], nrm[sel], d, opacity=0.3)
+        ref = scene.gaussians_from_points(pts[sel], nrm[sel], d, opacity=0.9, thin=0.2)
+        tg, mk = [], []
+        for cam in cams:
+            r = oracle.render(oracle.project(ref, scene.camera_dict(cam)), W, H)
+            tg.append(r["image"]); mk.append(r["T_final"] <= 0.5)
+        out.append(dict(params=prm, targets=torch.as_tensor(np.stack(tg).astype(np.float32)).cuda(),
+                        masks=torch.as_tensor(np.stack(mk).astype(np.uint8)).cuda()))
+    assert len({p["params"]["opacity_logit"].shape[0] for p in out}) == 3     # uneven
+    return out, cams
+
+
+def test_batched_images_equal_single_renders(parts):
+    say("batched images")
+    from paper_2509_12138_amd import ops
+    from paper_2509_12138_amd.train import BatchedTrainer
+    prts, cams = parts
+    bt = BatchedTrainer(prts, cams, views_per_part=2, graphs=False)
+    bt.views.use_cameras(bt.cams_g[1])
+    bt.bufs.render_checked(bt.gst)
+    torch.cuda.synchronize()
+    got = bt.bufs.image.cpu().numpy()
+    for p in range(3):
+        prm = bt.partition_params(p)
+        single = ops.RasterBuffers(ops.Views.single(bt.counts[p], cams[bt.group_views[1]]), W, H)
+        single.render_checked(ops.gaussians_struct({k: v.contiguous() for k, v in prm.items()}))
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got[2 * p:2 * p + 2], single.image.cpu().numpy())
+
+
+def test_graph_replay_matches_eager(parts):
+    say("graph replay")
+    from paper_2509_12138_amd.train import BatchedTrainer
+    prts, cams = parts
+    runs = {}
+    for graphs in (False, True):
+        bt = BatchedTrainer(prts, cams, views_per_part=2, graphs=graphs, order_seed=3)
+        bt.fit_capacity()
+        losses, m1 = [], None
+        for s in range(10):
+            g = s % bt.G
+            bt.step(g)
+            torch.cuda.synchronize()
+            losses.append(bt.loss.loss.cpu().numpy().copy())
+            if s == 0:
+                m1 = {k: v.cpu().numpy().copy() for k, v in bt.m.items()}
+            # eager work between replays
+            _ = (bt.params["mean"] * 2).sum().item()
+        bt.check()
+        runs[graphs] = (np.array(losses), m1, int(bt.adam.step_dev.item()))
+    le, lg = runs[False][0], runs[True][0]
+    np.testing.assert_allclose(lg, le, rtol=2e-4, atol=1e-7)
+    assert runs[True][2] == runs[False][2] == 10
+    for k in runs[False][1]:
+        a, b = runs[False][1][k], runs[True][1][k]
+        assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a) + 1e-12, k
+
+
+def test_device_adam_schedule_matches_oracle(gpu):
+    say("device adam")
+    from paper_2509_12138_amd import ops
+    rng = np.random.default_rng(1)
+    p0 = rng.normal(size=(3, 500)).astype(np.float32)
+    p = torch.as_tensor(p0).cuda(); g = torch.zeros_like(p)
+    m = torch.zeros_like(p); v = torch.zeros_like(p)
+    groups = ops.adam_groups(dict(mean=p, log_scale=p[:0], quat=p[:0], opacity_logit=p[0, :0],
+                                  color=p[:0]),
+                             dict(mean=g, log_scale=g[:0], quat=g[:0], opacity_logit=g[0, :0],
+                                  color=g[:0]),
+                             dict(mean=m, log_scale=m[:0], quat=m[:0], opacity_logit=m[0, :0],
+                                  color=m[:0]),
+                             dict(mean=v, log_scale=v[:0], quat=v[:0], opacity_logit=v[0, :0],
+                                  color=v[:0]),
+                             dict(mean=1e-2, log_scale=1, quat=1, opacity_logit=1, color=1))
+    adam = ops.DeviceAdam(groups, lr_final=[1e-4, 0, 0, 0, 0], decay_steps=7)
+    ref = (p0.astype(np.float64), np.zeros(p0.shape), np.zeros(p0.shape))
+    for t in range(1, 11):
+        gr = rng.normal(size=p0.shape).astype(np.float32)
+        g.copy_(torch.as_tensor(gr))
+        adam()
+        lr = 1e-2 * (1e-4 / 1e-2) ** min(t / 7, 1.0)
+        ref = oracle.adam(ref[0], gr, ref[1], ref[2], lr, t)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(p.cpu().numpy(), ref[0], rtol=2e-6, atol=2e-6)
+    assert int(adam.step_dev.item()) == 10
