@@ -326,6 +326,112 @@ gs_status gs_adam_dev(const gs_adam_group* groups, int32_t n_groups, const float
                       int32_t decay_steps, float beta1, float beta2, float eps,
                       int32_t* step_dev, int32_t zero_grad, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned initialisation.  The paper places one Gaussian at every point of
+ * the extracted isosurface (Sec. II, "Isosurface Extraction") and leaves its
+ * starting shape to the 3D-GS default (isotropic, scale from the 3 nearest
+ * neighbours, see gs_knn).  These calls add a small network that predicts
+ * the starting log-scale, rotation and opacity of each Gaussian from its 16
+ * nearest isosurface points, trained on Gaussians the training step itself
+ * has fitted:
+ *   inference: gs_knn(k=16) -> gs_mlp_features -> gs_mlp_fwd -> gs_mlp_apply
+ *   training:  gs_mlp_targets (once) then per step gs_mlp_fwd ->
+ *              gs_mlp_loss -> gs_mlp_bwd -> gs_adam
+ * Network: y = W3^T relu(W2^T relu(W1^T x + b1) + b2) + b3, 96 -> 64 -> 64 -> 8,
+ * bf16 MFMA products with fp32 accumulation.  The bf16 roundings are:
+ * x (stored bf16), the weights (rounded from the fp32 masters when loaded),
+ * both hidden activations after bias + ReLU; in the backward also dy, dZ2
+ * and dZ1 (after the ReLU mask).  Biases, pre-activations and outputs fp32.
+ * Per point: y[0:3] log-scale offset, y[3:7] quaternion (w, x, y, z) in the
+ * point's local frame (unnormalised), y[7] opacity logit.
+ *
+ * Local frame of a point with unit normal n: z = n, x = normalise(n x e)
+ * with e the world axis least aligned with n (lowest index on ties),
+ * y = z x x.  F = the 3x3 matrix whose rows are x, y, z (world -> local).
+ * ------------------------------------------------------------------------ */
+
+/* fp32 master weights, all device, row-major (input index first):
+ *   w1 [96][64], w2 [64][64], w3 [64][8], b1 [64], b2 [64], b3 [8].         */
+typedef struct {
+  const float* w1;
+  const float* w2;
+  const float* w3;
+  const float* b1;
+  const float* b2;
+  const float* b3;
+} gs_mlp;
+
+/* Gradient outputs of gs_mlp_bwd, same shapes as gs_mlp; they are ADDED to.
+ * dx: [n][96] fp32 gradient of the features, overwritten; may be NULL.   */
+typedef struct {
+  float* dw1;
+  float* dw2;
+  float* dw3;
+  float* db1;
+  float* db2;
+  float* db3;
+  float* dx;
+} gs_mlp_grads;
+
+/* Features of n isosurface points from their 16 nearest neighbours
+ * (gs_knn with k = 16: idx/dist [n][16], sorted, -1 = missing).
+ *   pts, normals [3][n] device (normals need not be unit length).
+ *   x_bf16 [n][96] device out, 16-byte aligned: for neighbour k,
+ *     x[6k..6k+2] = F (p_j - p) / dbar,  x[6k+3..6k+5] = F n_j
+ *     (zero for a missing neighbour), rounded to bf16 (nearest even).
+ *   dbar [n] device out: mean distance over the present neighbours (1 if
+ *     none).  n < 2^31.                                                   */
+gs_status gs_mlp_features(const float* pts, const float* normals, int64_t n,
+                          const int32_t* knn_idx, const float* knn_dist,
+                          uint16_t* x_bf16, float* dbar, void* stream);
+
+/* Forward: y [n][8] fp32 device out for x_bf16 [n][96] (16-byte aligned).
+ * w: host struct of device pointers.  n = 0 is a no-op.                   */
+gs_status gs_mlp_fwd(const uint16_t* x_bf16, int64_t n, const gs_mlp* w,
+                     float* y, void* stream);
+
+/* Workspace for gs_mlp_bwd on n points (per-work-group partial sums).     */
+size_t gs_mlp_bwd_workspace_bytes(int64_t n);
+
+/* Backward for upstream dy [n][8] fp32: recomputes the forward and adds the
+ * parameter gradients to g (host struct of device pointers); writes g->dx
+ * if it is not NULL.  ws: gs_mlp_bwd_workspace_bytes(n), 256-byte aligned.
+ * The reduction order is fixed: results are deterministic.                */
+gs_status gs_mlp_bwd(const uint16_t* x_bf16, int64_t n, const gs_mlp* w,
+                     const float* dy, gs_mlp_grads* g, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Training targets from fitted Gaussians (same identity as the points):
+ *   target[i][0:3] = log_scale[:, i] - log dbar[i],
+ *   target[i][3:7] = unit quaternion of F R(quat[:, i]) with w >= 0,
+ *   target[i][7]   = opacity_logit[i].
+ * log_scale [3][n], quat [4][n], opacity_logit [n], normals [3][n],
+ * dbar [n] device in; target [n][8] device out.                            */
+gs_status gs_mlp_targets(const float* log_scale, const float* quat,
+                         const float* opacity_logit, const float* normals,
+                         const float* dbar, int64_t n, float* target,
+                         void* stream);
+
+/* Workspace for gs_mlp_loss on n points.                                   */
+size_t gs_mlp_loss_workspace_bytes(int64_t n);
+
+/* Loss = (1/n) sum_i [ sum_{a<3} (y_a - t_a)^2 + (y_7 - t_7)^2
+ *                      + 1 - |<y[3:7]/|y[3:7]|, t[3:7]>| ]
+ * (the rotation term is blind to the sign of the quaternion).  Writes
+ * dy = dLoss/dy [n][8] and the loss to loss_out (one device float).  n >= 1.
+ * ws: gs_mlp_loss_workspace_bytes(n).                                      */
+gs_status gs_mlp_loss(const float* y, const float* target, int64_t n, float* dy,
+                      void* ws, size_t ws_bytes, float* loss_out, void* stream);
+
+/* Initial Gaussians from network outputs y [n][8]:
+ *   log_scale[a][i] = log dbar[i] + y[i][a],
+ *   quat[:, i] = unit quaternion (w >= 0) of F^T R(y[i][3:7]),
+ *   opacity_logit[i] = y[i][7].
+ * The inverse of gs_mlp_targets.  All device; outputs planar SoA.          */
+gs_status gs_mlp_apply(const float* y, const float* normals, const float* dbar,
+                       int64_t n, float* log_scale, float* quat,
+                       float* opacity_logit, void* stream);
+
 /* Fill `bytes` bytes at device pointer `ptr` with zero using a kernel (safe
  * to capture in a HIP graph).  bytes must be a multiple of 4.             */
 gs_status gs_zero(void* ptr, size_t bytes, void* stream);

@@ -295,17 +295,126 @@ def mlp_forward(x, W1, b1, W2, b2, W3, b3, quantize=True):
     return y, dict(x=xq, W1=W1q, W2=W2q, W3=W3q, z1=z1, h1=h1, z2=z2, h2=h2)
 
 
-def mlp_backward(cache, dy):
-    """Gradients of the MLP for upstream dy [n,8] (ReLU derivative 0 at 0)."""
+def mlp_backward(cache, dy, quantize=False):
+    """Gradients of the MLP for upstream dy [n,8] (ReLU derivative 0 at 0).
+
+    With quantize, dy and the masked hidden gradients dZ2, dZ1 are rounded to
+    bf16 where the GPU keeps them in bf16 (the products use the bf16 weights
+    and activations of a quantised forward's cache)."""
+    q = bf16_round if quantize else (lambda a: np.asarray(a, np.float64))
+    dy = q(dy)
     dW3 = cache["h2"].T @ dy
     db3 = dy.sum(0)
     dh2 = dy @ cache["W3"].T
-    dz2 = dh2 * (cache["z2"] > 0)
+    dz2 = q(dh2 * (cache["z2"] > 0))
     dW2 = cache["h1"].T @ dz2
     db2 = dz2.sum(0)
     dh1 = dz2 @ cache["W2"].T
-    dz1 = dh1 * (cache["z1"] > 0)
+    dz1 = q(dh1 * (cache["z1"] > 0))
     dW1 = cache["x"].T @ dz1
     db1 = dz1.sum(0)
     dx = dz1 @ cache["W1"].T
     return dict(W1=dW1, b1=db1, W2=dW2, b2=db2, W3=dW3, b3=db3, x=dx)
+
+
+# --------------------------------------------------------------------------
+# Learned initialisation: features, targets, loss, apply (plain numpy, FP64)
+#
+# One Gaussian per isosurface point (Sec. II, "Isosurface Extraction"); the
+# network reads the point's 16 nearest neighbours in its local frame and
+# predicts the starting log-scale, rotation and opacity.  Rotations are
+# converted with scipy.spatial.transform (a library routine).
+# --------------------------------------------------------------------------
+
+def local_frames(normals):
+    """[n,3,3] world->local frames: rows x, y, z with z = unit normal,
+    x = normalise(z x e), e the world axis least aligned with z (lowest
+    index on ties), y = z x x."""
+    nz = _f64(normals).T
+    nz = nz / np.linalg.norm(nz, axis=1, keepdims=True)
+    e = np.zeros_like(nz)
+    e[np.arange(len(nz)), np.argmin(np.abs(nz), axis=1)] = 1.0   # argmin: first minimum
+    xa = np.cross(nz, e)
+    xa /= np.linalg.norm(xa, axis=1, keepdims=True)
+    ya = np.cross(nz, xa)
+    return np.stack([xa, ya, nz], axis=1)
+
+
+def mlp_features(points, normals, idx, dist, quantize=True):
+    """Features [n,96] and mean neighbour distance dbar [n].
+
+    For neighbour k of point p (idx/dist [n,16] sorted, -1 = missing):
+    x[6k:6k+3] = F (p_j - p) / dbar, x[6k+3:6k+6] = F n_j (zero if missing);
+    dbar = mean distance over the present neighbours (1 if none)."""
+    P = _f64(points).T
+    N = _f64(normals).T
+    idx = np.asarray(idx)
+    dist = np.asarray(dist, np.float64)
+    n, k = idx.shape
+    F = local_frames(normals)
+    present = idx >= 0
+    cnt = present.sum(1)
+    dbar = np.where(cnt > 0, np.where(present, dist, 0.0).sum(1) / np.maximum(cnt, 1), 1.0)
+    x = np.zeros((n, 6 * k))
+    for kk in range(k):
+        j = idx[:, kk]
+        ok = j >= 0
+        js = np.where(ok, j, 0)
+        off = (P[js] - P) / dbar[:, None]
+        x[:, 6 * kk:6 * kk + 3] = np.where(ok[:, None], np.einsum("nab,nb->na", F, off), 0.0)
+        x[:, 6 * kk + 3:6 * kk + 6] = np.where(ok[:, None], np.einsum("nab,nb->na", F, N[js]), 0.0)
+    return (bf16_round(x) if quantize else x), dbar
+
+
+def _rot_from_wxyz(q):
+    from scipy.spatial.transform import Rotation
+    q = np.asarray(q, np.float64)
+    return Rotation.from_quat(np.column_stack([q[:, 1], q[:, 2], q[:, 3], q[:, 0]])).as_matrix()
+
+
+def _wxyz_from_rot(R):
+    from scipy.spatial.transform import Rotation
+    xyzw = Rotation.from_matrix(R).as_quat()
+    q = np.column_stack([xyzw[:, 3], xyzw[:, 0], xyzw[:, 1], xyzw[:, 2]])
+    return q * np.where(q[:, :1] < 0, -1.0, 1.0)
+
+
+def mlp_targets(log_scale, quat, opacity_logit, normals, dbar):
+    """Targets [n,8] of fitted Gaussians: log-scale minus log dbar, the unit
+    quaternion (w >= 0) of F R(quat), and the opacity logit."""
+    F = local_frames(normals)
+    Rg = _rot_from_wxyz(_f64(quat).T)
+    t = np.zeros((len(dbar), 8))
+    t[:, 0:3] = _f64(log_scale).T - np.log(dbar)[:, None]
+    t[:, 3:7] = _wxyz_from_rot(F @ Rg)
+    t[:, 7] = _f64(opacity_logit)
+    return t
+
+
+def mlp_apply(y, normals, dbar):
+    """Initial Gaussians from outputs y [n,8]: log_scale [3,n] = log dbar +
+    y[:,0:3], quat [4,n] = unit quaternion (w >= 0) of F^T R(y[:,3:7]),
+    opacity_logit [n] = y[:,7]; the inverse of mlp_targets."""
+    y = _f64(y)
+    F = local_frames(normals)
+    R = np.transpose(F, (0, 2, 1)) @ _rot_from_wxyz(y[:, 3:7])
+    return dict(log_scale=(np.log(dbar)[:, None] + y[:, 0:3]).T.copy(),
+                quat=_wxyz_from_rot(R).T.copy(), opacity_logit=y[:, 7].copy())
+
+
+def mlp_loss(y, t):
+    """Mean over points of the squared error of log-scale (3) and opacity
+    logit plus 1 - |<q/|q|, q*>| for the rotation; returns (loss, dL/dy)."""
+    y = _f64(y); t = _f64(t)
+    n = len(y)
+    d = np.zeros_like(y)
+    r = y[:, [0, 1, 2, 7]] - t[:, [0, 1, 2, 7]]
+    d[:, [0, 1, 2, 7]] = 2.0 * r / n
+    q = y[:, 3:7]
+    qn = np.linalg.norm(q, axis=1)
+    qh = q / np.maximum(qn, 1e-300)[:, None]
+    c = np.sum(qh * t[:, 3:7], axis=1)
+    L = np.sum(r * r) + np.sum(1.0 - np.abs(c))
+    # derivative of |c| through the normalisation q -> q/|q|
+    d[:, 3:7] = -np.sign(c)[:, None] * (t[:, 3:7] - qh * c[:, None]) / qn[:, None] / n
+    return L / n, d

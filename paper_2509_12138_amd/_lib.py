@@ -98,8 +98,14 @@ SIGNATURES = {
     "gs_version": (C.c_char_p, []),
     "gs_knn_workspace_bytes": (sz, [i64, i32]),
     "gs_knn": (i32, [vp, i64, i32, vp, sz, vp, vp, vp]),
-    "gs_mlp_fwd": (i32, [vp, i64, P(gs_mlp), vp, vp, vp]),
-    "gs_mlp_bwd": (i32, [vp, i64, P(gs_mlp), vp, vp, P(gs_mlp_grads), vp]),
+    "gs_mlp_features": (i32, [vp, vp, i64, vp, vp, vp, vp, vp]),
+    "gs_mlp_fwd": (i32, [vp, i64, P(gs_mlp), vp, vp]),
+    "gs_mlp_bwd_workspace_bytes": (sz, [i64]),
+    "gs_mlp_bwd": (i32, [vp, i64, P(gs_mlp), vp, P(gs_mlp_grads), vp, sz, vp]),
+    "gs_mlp_targets": (i32, [vp, vp, vp, vp, vp, i64, vp, vp]),
+    "gs_mlp_loss_workspace_bytes": (sz, [i64]),
+    "gs_mlp_loss": (i32, [vp, vp, i64, vp, vp, sz, vp, vp]),
+    "gs_mlp_apply": (i32, [vp, vp, vp, i64, vp, vp, vp, vp]),
 }
 
 _lock = threading.Lock()

@@ -71,7 +71,7 @@ def tiny_partition(cfg=None):
                                   seed=100 + cfg["seed"])
     ref = reference_discs(rp, rn, scene.knn_mean_distance(rp, 3))
     cams = scene.orbit_cameras(cfg["views"], cfg["width"], cfg["height"])
-    return dict(params=params, reference=ref, cams=cams, cfg=cfg)
+    return dict(params=params, reference=ref, cams=cams, cfg=cfg, points=pts, normals=nrm)
 
 
 def render_targets_gpu(reference, cams, tile=(16, 16), device="cuda"):
