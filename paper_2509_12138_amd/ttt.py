@@ -1,0 +1,330 @@
+"""Time to a masked-PSNR target on one GPU.
+
+Three arms on the same partitions, views and targets:
+
+* plain    - each partition trained on its own by the plain trainer (one
+             view per step, the method's per-partition training, Sec. II
+             "Parallel Training"), partitions one after another;
+* batched  - all partitions x ``views_per_part`` views per step in one launch
+             per stage (LPT tile order, chunked backward) with captured steps;
+* learned  - the plain trainer started from the learned initialisation.
+
+Partitions are x-slabs of the bumpy-sphere field with ghost margins (Sec. II
+"Data Partitioning": the dataset is cut into partitions padded with ghost
+cells); every partition sees the same orbital cameras (Sec. II "Camera
+Setup") and gets targets and background masks rendered from its own
+reference set (Sec. II "Image Rendering and Masking").
+
+Timing: the training wall clock, evaluation excluded (the clock pauses while
+the mean masked PSNR over all views is computed every ``eval_every`` steps),
+initialisation (k-NN, features, network) included in every arm.  A
+partition's time is taken at its first evaluation at or above the target.
+
+    python -m paper_2509_12138_amd.ttt probe   [--scale S]
+    python -m paper_2509_12138_amd.ttt batched [--scale S] [--target 35]
+    python -m paper_2509_12138_amd.ttt learned [--scale S] [--target 35]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import scene, workloads
+
+SLAB_COUNTS = (500_000, 800_000, 1_200_000, 1_500_000, 2_000_000, 2_500_000, 3_000_000, 4_500_000)
+GRID = 512               # sampling grid over [-1, 1]^3
+GHOST_VOXELS = 2
+
+
+def log(*a):
+    print("[ttt]", *a, flush=True)
+
+
+SURFACE_EXTENT = 0.56    # the isosurface |x| = 0.5 +- 0.05 lies inside [-0.56, 0.56]^3
+
+
+def slab_partitions(counts=SLAB_COUNTS, seed=4, ref_factor=2.0, grid=GRID):
+    """The bumpy-sphere isosurface cut into len(counts) equal-width x-slabs
+    over its extent, each padded by a ghost margin of GHOST_VOXELS voxels
+    beyond its faces and sampled at exactly its listed point count (so the
+    partitions' densities and workloads are uneven), plus a reference set
+    ref_factor times denser in the same padded slab.  Returns per partition
+    points / normals / ref_points / ref_normals ([n,3] float64)."""
+    P = len(counts)
+    ghost = GHOST_VOXELS * 2.0 / grid
+    edges = np.linspace(-SURFACE_EXTENT, SURFACE_EXTENT, P + 1)
+    parts = []
+    for p in range(P):
+        box = ((edges[p] - ghost, -1.0, -1.0), (edges[p + 1] + ghost, 1.0, 1.0))
+        pts, nrm = scene.sample_surface(scene.field_sphere_sines, int(counts[p]), grid,
+                                        seed=seed * 100 + p, box=box)
+        rp, rn = scene.sample_surface(scene.field_sphere_sines, int(counts[p] * ref_factor), grid,
+                                      seed=seed * 100 + 50 + p, box=box)
+        parts.append(dict(points=pts, normals=nrm, ref_points=rp, ref_normals=rn,
+                          x_range=(float(edges[p]), float(edges[p + 1]))))
+    return parts
+
+
+def prepare(parts, cams, device="cuda"):
+    """Reference discs -> targets and masks on the device, per partition."""
+    for part in parts:
+        d = scene.knn_mean_distance(part["ref_points"], 3)
+        ref = workloads.reference_discs(part["ref_points"], part["ref_normals"], d)
+        part["targets"], part["masks"] = workloads.render_targets_gpu(ref, cams, device=device)
+        part["n"] = len(part["points"])
+    return parts
+
+
+def plain_params(part, device="cuda"):
+    """Plain initialisation on the device (timed by the caller)."""
+    from . import learned_init
+    pts = torch.as_tensor(np.ascontiguousarray(part["points"].T, np.float32)).to(device)
+    nrm = torch.as_tensor(np.ascontiguousarray(part["normals"].T, np.float32)).to(device)
+    return learned_init.plain_init(pts, nrm), pts, nrm
+
+
+def run_plain(part, cams, target, max_steps, eval_every, init="plain", mlp=None, plan=None,
+              seed=0, device="cuda"):
+    """Train one partition with the plain trainer until the target.
+    Returns dict(seconds, steps, psnr, history, init_seconds, init_kind)."""
+    from . import learned_init
+    from .train import PlainTrainer
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if init == "learned":
+        pts = torch.as_tensor(np.ascontiguousarray(part["points"].T, np.float32)).to(device)
+        nrm = torch.as_tensor(np.ascontiguousarray(part["normals"].T, np.float32)).to(device)
+        params, kind = learned_init.choose_init(mlp, pts, nrm)
+    else:
+        params, _, _ = plain_params(part, device)
+        kind = "plain"
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    tile, sched, chunk = plan or ((16, 16), "lpt", 64)
+    tr = PlainTrainer(params, cams, part["targets"], part["masks"], tile=tile, schedule=sched,
+                      chunk=chunk)
+    tr.fit_capacity(views=range(0, len(cams), max(1, len(cams) // 8)))
+    hist = tr.train(max_steps, order_seed=1000 + seed, eval_every=eval_every, target_psnr=target)
+    reached = [h for h in hist if h[2] is not None and h[2] >= target]
+    last = [h for h in hist if h[2] is not None]
+    out = dict(init_seconds=t_init, init_kind=kind,
+               history=[(int(s), float(t), float(p)) for s, t, p in last])
+    if reached:
+        out.update(seconds=t_init + reached[0][1], steps=reached[0][0], psnr=reached[0][2])
+    else:
+        out.update(seconds=None, steps=max_steps, psnr=last[-1][2] if last else None)
+    out["trainer"] = tr
+    return out
+
+
+def run_batched(parts, cams, target, max_steps, eval_every, views_per_part=4, plan=None,
+                device="cuda"):
+    """All partitions in one batched trainer until every one reaches the
+    target; per partition the time of its first evaluation at the target."""
+    from .train import BatchedTrainer
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    inits = [plain_params(p, device)[0] for p in parts]
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    tile, sched, chunk = plan or ((16, 16), "lpt", 64)
+    bp = [dict(params={k: v.cpu().numpy() for k, v in ini.items()}, targets=p["targets"],
+               masks=p["masks"]) for ini, p in zip(inits, parts)]
+    tr = BatchedTrainer(bp, cams, views_per_part=views_per_part, tile=tile, schedule=sched,
+                        chunk=chunk, order_seed=7)
+    tr.fit_capacity()
+    P = len(parts)
+    reached = [None] * P
+    hist = []
+    train_time = 0.0
+    rng = np.random.default_rng(11)
+    order = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in range(max_steps):
+        if not order:
+            order = list(rng.permutation(tr.G))
+        tr.step(order.pop())
+        if (s + 1) % eval_every == 0:
+            torch.cuda.synchronize()
+            train_time += time.perf_counter() - t1
+            tr.check()
+            ps = tr.evaluate()
+            hist.append((s + 1, train_time, [float(x) for x in ps]))
+            log(f"batched step {s + 1}: {train_time:.2f} s, psnr min {ps.min():.2f} "
+                f"mean {ps.mean():.2f}")
+            for p in range(P):
+                if reached[p] is None and ps[p] >= target:
+                    reached[p] = (s + 1, t_init + train_time, float(ps[p]))
+            if all(r is not None for r in reached):
+                break
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+    return dict(init_seconds=t_init, reached=reached, history=hist, trainer=tr)
+
+
+def _cams(views, width, height):
+    return scene.orbit_cameras(views, width, height)
+
+
+def cmd_probe(a):
+    """PSNR against steps on the 1M-Gaussian 1080p partition (plain)."""
+    wl = workloads.realistic_partition(dict(n=int(1_000_000 * a.scale), n_ref=int(4_000_000 * a.scale)))
+    part = dict(points=wl["points"], normals=wl["normals"])
+    tg, mk = workloads.render_targets_gpu(wl["reference"], wl["cams"])
+    part.update(targets=tg, masks=mk, n=len(wl["points"]))
+    r = run_plain(part, wl["cams"], a.target, a.steps, a.eval_every, plan=a.plan)
+    for s, t, p in r["history"]:
+        log(f"plain step {s}: {t:.2f} s psnr {p:.2f}")
+    print(json.dumps(dict(experiment="probe", n=part["n"], target=a.target, seconds=r["seconds"],
+                          steps=r["steps"], history=r["history"])), flush=True)
+
+
+def cmd_batched(a):
+    counts = [int(c * a.scale) for c in SLAB_COUNTS]
+    cams = _cams(a.views, a.width, a.height)
+    log(f"sampling slabs {counts}")
+    parts = prepare(slab_partitions(counts, ref_factor=a.ref_factor), cams)
+    log("targets ready: " + ", ".join(str(p["n"]) for p in parts))
+    rb = run_batched(parts, cams, a.target, a.steps, a.eval_every, a.vpp, plan=a.plan)
+    del rb["trainer"]
+    torch.cuda.empty_cache()
+    plain = []
+    for i, part in enumerate(parts):
+        r = run_plain(part, cams, a.target, a.steps * a.vpp, a.eval_every * a.vpp, plan=a.plan,
+                      seed=i)
+        del r["trainer"]
+        torch.cuda.empty_cache()
+        log(f"plain partition {i} (n={part['n']}): {r['seconds']} s, {r['steps']} steps, "
+            f"psnr {r['psnr']}")
+        plain.append(r)
+    res = dict(experiment="batched_vs_plain", counts=[p["n"] for p in parts], target=a.target,
+               views=a.views, width=a.width, height=a.height, views_per_part=a.vpp,
+               batched=dict(init_seconds=rb["init_seconds"], reached=rb["reached"],
+                            history=rb["history"]),
+               plain=[{k: v for k, v in r.items()} for r in plain])
+    tb = [r[1] for r in rb["reached"]] if all(rb["reached"]) else None
+    tp = [r["seconds"] for r in plain]
+    res["batched_seconds_all"] = max(tb) if tb else None
+    res["plain_seconds_all"] = sum(tp) if all(t is not None for t in tp) else None
+    print(json.dumps(res), flush=True)
+
+
+def octant_partition(n, seed, ref_factor=2.0, grid=GRID):
+    """The octant x, y, z >= 0 of the bumpy-sphere field padded by the ghost
+    margin across its three internal faces (one of eight partitions)."""
+    ghost = GHOST_VOXELS * 2.0 / grid
+    box = ((-ghost, -ghost, -ghost), (1.0, 1.0, 1.0))
+    pts, nrm = scene.sample_surface(scene.field_sphere_sines, int(n), grid, seed=seed, box=box)
+    rp, rn = scene.sample_surface(scene.field_sphere_sines, int(n * ref_factor), grid,
+                                  seed=seed + 100, box=box)
+    return dict(points=pts, normals=nrm, ref_points=rp, ref_normals=rn)
+
+
+def fitted_examples(part, cams, steps, plan, seed):
+    """Fit a partition with the plain trainer, return (features, targets,
+    plain-initialisation outputs, final psnr) of its Gaussians."""
+    from . import learned_init
+    r = run_plain(part, cams, 1e9, steps, steps, plan=plan, seed=seed)
+    tr = r["trainer"]
+    pts = torch.as_tensor(np.ascontiguousarray(part["points"].T, np.float32)).cuda()
+    nrm = torch.as_tensor(np.ascontiguousarray(part["normals"].T, np.float32)).cuda()
+    x, dbar = learned_init.features(pts, nrm)
+    p = tr.params
+    t = learned_init.targets(p["log_scale"], p["quat"], p["opacity_logit"], nrm, dbar)
+    q = learned_init.plain_init(pts, nrm)
+    y_plain = learned_init.targets(q["log_scale"], q["quat"], q["opacity_logit"], nrm, dbar)
+    psnr = r["history"][-1][2] if r["history"] else None
+    del tr, r
+    torch.cuda.empty_cache()
+    return x, t, y_plain, psnr
+
+
+def cmd_learned(a):
+    from . import learned_init
+    cams = _cams(a.views, a.width, a.height)
+    # training data: Gaussians fitted on the tiny configuration (4,096
+    # Gaussians, 16 views at 128^2) and on an octant partition of the field
+    tiny = workloads.tiny_partition()
+    tiny_part = dict(points=tiny["points"], normals=tiny["normals"], n=len(tiny["points"]))
+    tiny_part["targets"], tiny_part["masks"] = workloads.render_targets_gpu(tiny["reference"],
+                                                                            tiny["cams"])
+    xs, ts, ys = [], [], []
+    x, t, yp, ps = fitted_examples(tiny_part, tiny["cams"], a.fit_steps, ((16, 16), "lpt", 64), 1)
+    xs.append(x); ts.append(t); ys.append(yp)
+    log(f"tiny fitted: psnr {ps}")
+    src = prepare([octant_partition(int(a.scale * 13_300_000), seed=3, ref_factor=a.ref_factor)],
+                  cams)[0]
+    x, t, yp, ps = fitted_examples(src, cams, a.fit_steps, a.plan, 3)
+    xs.append(x); ts.append(t); ys.append(yp)
+    log(f"octant fitted (n={src['n']}): psnr {ps}")
+    del src
+    x = torch.cat(xs); t = torch.cat(ts); yp = torch.cat(ys)
+    # held-out tenth for the fallback rule
+    nh = max(1, x.shape[0] // 10)
+    g = torch.Generator(device="cpu").manual_seed(505)
+    perm = torch.randperm(x.shape[0], generator=g).cuda()
+    xh, th = x[perm[:nh]].contiguous(), t[perm[:nh]].contiguous()
+    xt, tt = x[perm[nh:]], t[perm[nh:]]
+    mlp = learned_init.InitMLP.random(seed=505, out_bias=tt.mean(0).cpu().numpy())
+    mt = learned_init.MLPTrainer(mlp, xt, tt, lr=2e-3, batch=65536)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = mt.train(a.mlp_steps, log_every=max(1, a.mlp_steps // 5), log=log)
+    torch.cuda.synchronize()
+    mlp_seconds = time.perf_counter() - t0
+    held = learned_init.evaluate_loss(mlp, xh, th)
+    held_plain = float(learned_init.loss(yp[perm[:nh]].contiguous(), th)[0].item())
+    use_mlp = math.isfinite(held) and held < held_plain
+    log(f"network: {mlp_seconds:.1f} s, held-out loss {held:.4f} vs plain init {held_plain:.4f}"
+        f" -> {'learned' if use_mlp else 'fallback to plain'}")
+    # a new partition of the same field (other seed): learned vs plain
+    tgt = prepare([octant_partition(int(a.scale * 4_000_000), seed=5, ref_factor=a.ref_factor)],
+                  cams)[0]
+    out = dict(experiment="learned_vs_plain", n=tgt["n"], target=a.target,
+               mlp_train_seconds=mlp_seconds, mlp_history=hist, mlp_heldout_loss=held,
+               plain_heldout_loss=held_plain)
+    for arm in ("plain", "learned"):
+        init = arm if use_mlp else "plain"
+        r = run_plain(tgt, cams, a.target, a.steps, a.eval_every, init=init, mlp=mlp, plan=a.plan,
+                      seed=99)
+        del r["trainer"]
+        torch.cuda.empty_cache()
+        log(f"{arm}: {r['seconds']} s, {r['steps']} steps, psnr {r['psnr']}, init {r['init_kind']}")
+        out[arm] = r
+    print(json.dumps(out), flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("experiment", choices=["probe", "batched", "learned"])
+    ap.add_argument("--scale", type=float, default=1.0, help="multiplies every Gaussian count")
+    ap.add_argument("--target", type=float, default=35.0)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--eval-every", type=int, default=100)
+    ap.add_argument("--views", type=int, default=64)
+    ap.add_argument("--width", type=int, default=1920)
+    ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--vpp", type=int, default=4)
+    ap.add_argument("--ref-factor", type=float, default=2.0)
+    ap.add_argument("--fit-steps", type=int, default=2000)
+    ap.add_argument("--mlp-steps", type=int, default=2000)
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--schedule", default="lpt")
+    ap.add_argument("--chunk", type=int, default=64)
+    a = ap.parse_args(argv)
+    tw, th = (int(v) for v in a.tile.split("x"))
+    a.plan = ((tw, th), a.schedule, a.chunk)
+    if not torch.cuda.is_available():
+        sys.exit("ttt needs a GPU")
+    dict(probe=cmd_probe, batched=cmd_batched, learned=cmd_learned)[a.experiment](a)
+
+
+if __name__ == "__main__":
+    main()

@@ -62,3 +62,46 @@ def perturbed(params, seed, amount=0.3):
     p["opacity_logit"] = rng.normal(-0.5, 1.5, n).astype(np.float32)
     p["color"] = (p["color"] + rng.normal(0, 0.5, (3, n))).astype(np.float32)
     return p
+
+
+def oracle_records(params, cams, W, H, tile):
+    """Projected records of every view built by the oracle (its FP64
+    projection rounded to FP32) in the library's record layout
+    (mean2d, conic, opacity, rgb, depth, slot bits, 0; culled pairs zero but
+    depth and slot), slot-major, plus per view the oracle-side dict of the
+    same FP32 values.  Both sides then rasterise identical inputs, none of
+    which comes from the GPU."""
+    recs, tbs, nts, views = [], [], [], []
+    for s, cam in enumerate(cams):
+        o = oracle.project(params, scene.camera_dict(cam), tile)
+        n = o["depth"].shape[0]
+        valid = o["valid"].astype(bool) & (o["n_tiles"] > 0)
+        rec = np.zeros((n, 12), np.float32)
+        rec[:, 0:2] = o["mean2d"].T
+        rec[:, 2:5] = o["conic"].T
+        rec[:, 5] = o["opacity"]
+        rec[:, 6:9] = o["rgb"].T
+        rec[~valid, 0:9] = 0.0
+        rec[:, 9] = o["depth"]
+        rec[:, 10] = np.full(n, s, np.int32).view(np.float32)
+        tb = np.ascontiguousarray(np.where(valid[None], o["tile_bbox"], 0).T
+                                  .astype(np.uint16).view(np.int16))
+        nt = np.where(valid, o["n_tiles"], 0).astype(np.int32)
+        recs.append(rec); tbs.append(tb); nts.append(nt)
+        views.append(rec_to_oracle(rec, tb, nt))
+    return np.concatenate(recs), np.concatenate(tbs), np.concatenate(nts), views
+
+
+def raster_records(bufs, rec, tb, nt, bg, torch):
+    """Load given records into the buffers, then bin/sort and rasterise."""
+    bufs.ensure_capacity(int(nt.astype(np.int64).sum()) + 1024)
+    bufs.rec.copy_(torch.as_tensor(rec))
+    bufs.tile_bbox.copy_(torch.as_tensor(tb))
+    bufs.n_tiles.copy_(torch.as_tensor(nt))
+    bufs.clear_status()
+    bufs.bin_sort()
+    st, req = bufs.check()
+    assert st == 0 and req == int(nt.astype(np.int64).sum()), (st, req)
+    bufs.order_tiles()
+    bufs.raster_fwd(bg)
+    torch.cuda.synchronize()

@@ -1,0 +1,205 @@
+"""Parity at the benchmark workload's full size: the 1M-Gaussian mixing-layer
+partition at 1920x1080, in every rasteriser launch configuration the
+autotuner can pick (bench.py times the one it picks).
+
+* projection of all 1M Gaussians for two views against the oracle;
+* bin/sort of the oracle's records, bit-exact against the oracle's sort;
+* images on sampled 32x32 pixel windows (the densest tile, the image
+  centre, the bottom-right corner with its ragged tiles) within 1e-4 of the
+  oracle's window render;
+* gradients from an image gradient that is non-zero only inside those
+  windows, so that the oracle's window backward is the complete answer.
+
+Both sides rasterise the same FP32 records, built by the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_12138_amd import scene, workloads
+from _gpu_helpers import (grad_tolerance_check, oracle_records, perturbed, raster_records, say,
+                          to_dev)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+W, H = 1920, 1080
+VIEWS = [0, 37]
+SAME_RECORD_BITS = 1 | 2 | 4 | 8
+WIN = 32
+
+
+@pytest.fixture(scope="module")
+def big(gpu):
+    say("building the 1M-Gaussian 1080p partition")
+    wl = workloads.realistic_partition(with_reference=False)
+    assert wl["cfg"]["width"] == W and wl["cfg"]["height"] == H
+    params = perturbed(wl["params"], 7, amount=0.2)
+    cams = wl["cams"][VIEWS]
+    return params, cams
+
+
+def test_fullsize_projection_matches_oracle(big):
+    from paper_2509_12138_amd import ops
+    params, cams = big
+    n = params["opacity_logit"].shape[0]
+    say(f"full-size projection n={n}")
+    views = ops.Views.single(n, cams)
+    bufs = ops.RasterBuffers(views, W, H, (16, 16), dup_capacity=1024)
+    bufs.project(ops.gaussians_struct(to_dev(params, torch)))
+    torch.cuda.synchronize()
+    rec = bufs.rec.cpu().numpy()
+    tb = bufs.tile_bbox.cpu().numpy().astype(np.int64) & 0xFFFF
+    nt = bufs.n_tiles.cpu().numpy()
+    for v in range(len(cams)):
+        o = oracle.project(params, scene.camera_dict(cams[v]))
+        sl = slice(v * n, (v + 1) * n)
+        r, t_, ntv = rec[sl], tb[sl], nt[sl]
+        kappa = 2 * np.log(np.maximum(255 * o["opacity"], 1e-300))
+        hx = np.sqrt(np.maximum(kappa, 0) * o["cov2d"][0])
+        hy = np.sqrt(np.maximum(kappa, 0) * o["cov2d"][2])
+        edges = np.stack([o["mean2d"][0] - hx, o["mean2d"][0] + hx,
+                          o["mean2d"][1] - hy, o["mean2d"][1] + hy])
+        # FP32 error of m +/- h stays below 2e-4 px at 1080p coordinates
+        near = np.any(np.abs(edges - np.round(edges)) < 2e-4, axis=0) | \
+            (np.abs(255 * o["opacity"] - 1) < 1e-4)
+        assert near.mean() < 2e-3
+        ok = ~near
+        valid = o["valid"].astype(bool) & (o["n_tiles"] > 0)
+        np.testing.assert_array_equal(ntv[ok] > 0, valid[ok])
+        both = ok & valid
+        assert both.sum() > n // 4
+        np.testing.assert_array_equal(t_[both], o["tile_bbox"].T[both])
+        np.testing.assert_allclose(r[both, 0:2], o["mean2d"].T[both], rtol=1e-5, atol=2e-4)
+        cscale = np.abs(o["conic"]).max(0)[both][:, None]
+        assert np.all(np.abs(r[both, 2:5] - o["conic"].T[both]) <= 1e-5 * cscale + 1e-9)
+        np.testing.assert_allclose(r[both, 5], o["opacity"][both], rtol=1e-5)
+        np.testing.assert_allclose(r[both, 9], o["depth"][both], rtol=1e-6)
+
+
+_records = {}
+
+
+def records(big, tile):
+    if tile not in _records:
+        params, cams = big
+        _records[tile] = oracle_records(params, cams, W, H, tile)
+    return _records[tile]
+
+
+def windows_for(big, v):
+    """Three windows of view v: around the tile with the longest list, the
+    image centre, the bottom-right corner (ragged for 16-row tiles)."""
+    rec, tb, nt, _ = records(big, (16, 16))
+    n = big[0]["opacity_logit"].shape[0]
+    t = tb[v * n:(v + 1) * n].astype(np.int64) & 0xFFFF
+    k = nt[v * n:(v + 1) * n] > 0
+    cnt = np.zeros((math.ceil(H / 16), W // 16), np.int64)
+    for i in np.flatnonzero(k)[::7]:                 # a subsample finds the dense area
+        cnt[t[i, 1]:t[i, 3] + 1, t[i, 0]:t[i, 2] + 1] += 1
+    ty, tx = np.unravel_index(np.argmax(cnt), cnt.shape)
+    x0 = int(min(max(16 * tx - 8, 0), W - WIN)); y0 = int(min(max(16 * ty - 8, 0), H - WIN))
+    return [(x0, y0, x0 + WIN, y0 + WIN), (W // 2 - 16, H // 2 - 16, W // 2 + 16, H // 2 + 16),
+            (W - WIN, H - WIN, W, H)]
+
+
+_oracle_out = {}
+
+
+def oracle_windows(big, dI):
+    """The oracle's window renders and backward, once: records of other tile
+    shapes differ only in their tile bboxes, and neither the images nor the
+    gradients depend on the tile shape (the support ellipse lies inside the
+    padded bbox for every shape)."""
+    tile = (16, 16)
+    if tile not in _oracle_out:
+        _, _, _, views = records(big, tile)
+        out = []
+        for v in range(len(VIEWS)):
+            per = []
+            for win in windows_for(big, v):
+                f = oracle.render(views[v], W, H, tile=tile, window=win)
+                b = oracle.render_bwd(views[v], W, H, dI[v], tile=tile, window=win,
+                                      amb_bits=SAME_RECORD_BITS)
+                per.append((win, f, b))
+            out.append(per)
+        _oracle_out[tile] = out
+    return _oracle_out[tile]
+
+
+def image_gradient(big):
+    rng = np.random.default_rng(11)
+    dI = np.zeros((len(VIEWS), 3, H, W), np.float32)
+    for v in range(len(VIEWS)):
+        for (x0, y0, x1, y1) in windows_for(big, v):
+            dI[v, :, y0:y1, x0:x1] = rng.normal(size=(3, y1 - y0, x1 - x0))
+    return dI
+
+
+def test_fullsize_bin_sort_bit_exact(big):
+    from paper_2509_12138_amd import ops
+    params, cams = big
+    n = params["opacity_logit"].shape[0]
+    for tile in [(16, 16), (8, 16)]:
+        say(f"full-size bin/sort tile={tile}")
+        rec, tb, nt, _ = records(big, tile)
+        bufs = ops.RasterBuffers(ops.Views.single(n, cams), W, H, tile, dup_capacity=1024)
+        raster_records(bufs, rec, tb, nt, (0.0, 0.0, 0.0), torch)
+        K = int(nt.astype(np.int64).sum())
+        tx, ty = math.ceil(W / tile[0]), math.ceil(H / tile[1])
+        slot = np.repeat(np.arange(len(cams), dtype=np.int32), n)
+        keys, ids, ranges = oracle.bin_sort(tb.astype(np.int32) & 0xFFFF, nt, rec[:, 9], slot,
+                                            tx, tx * ty, len(cams))
+        np.testing.assert_array_equal(bufs.keys[:K].cpu().numpy().view(np.uint64), keys)
+        np.testing.assert_array_equal(bufs.ids[:K].cpu().numpy().view(np.uint32), ids)
+        np.testing.assert_array_equal(bufs.ranges.cpu().numpy().view(np.uint32), ranges)
+
+
+def _plans():
+    from paper_2509_12138_amd.autotune import CANDIDATES
+    plans = [(t, s, c, True) for (t, s, c) in CANDIDATES]
+    plans.append(((16, 16), "lpt", 0, False))              # transmittance recompute
+    return plans
+
+
+@pytest.mark.parametrize("tile,sched,chunk,stored", _plans())
+def test_fullsize_raster_matches_oracle_windows(big, tile, sched, chunk, stored):
+    from paper_2509_12138_amd import ops
+    params, cams = big
+    n = params["opacity_logit"].shape[0]
+    say(f"full-size raster tile={tile} {sched} chunk={chunk} stored={stored}")
+    rec, tb, nt, _ = records(big, tile)
+    dI = image_gradient(big)
+    bufs = ops.RasterBuffers(ops.Views.single(n, cams), W, H, tile, dup_capacity=1024,
+                             store_state=stored)
+    bufs.set_schedule(sched, chunk=chunk)
+    raster_records(bufs, rec, tb, nt, (0.0, 0.0, 0.0), torch)
+    bufs.zero_d_rec()
+    bufs.raster_bwd(torch.as_tensor(dI).cuda())
+    torch.cuda.synchronize()
+    img = bufs.image.cpu().numpy()
+    drec = bufs.d_rec.cpu().numpy().astype(np.float64)
+    for v, per in enumerate(oracle_windows(big, dI)):
+        grad = np.zeros((n, 9)); term = np.zeros((n, 9)); amb_m = np.zeros((n, 9))
+        for (x0, y0, x1, y1), f, b in per:
+            amb = ((f["ambiguity"] & SAME_RECORD_BITS) != 0)[y0:y1, x0:x1]
+            assert amb.mean() <= 1e-2
+            err = np.abs(img[v][:, y0:y1, x0:x1] - f["image"][:, y0:y1, x0:x1])[:, ~amb]
+            assert err.max() <= 1e-4, ((x0, y0), err.max())
+            if stored:
+                nc = bufs.n_contrib[v].cpu().numpy()[y0:y1, x0:x1]
+                np.testing.assert_array_equal(nc[~amb], f["n_contrib"][y0:y1, x0:x1][~amb])
+            grad += np.concatenate([b["d_mean2d"], b["d_conic"], b["d_opacity"][None],
+                                    b["d_rgb"]]).T
+            term += b["term_mass"].T
+            amb_m += b["amb_mass"].T
+        sl = slice(v * n, (v + 1) * n)
+        touched = np.any(grad != 0, axis=1)
+        assert touched.sum() > 1000
+        np.testing.assert_array_equal(drec[sl][~touched & (term.sum(1) == 0)], 0.0)
+        ok, worst = grad_tolerance_check(drec[sl], grad, term, amb_m)
+        assert ok, worst
+        for c in range(9):
+            nr = np.linalg.norm(drec[sl][:, c] - grad[:, c]) / max(np.linalg.norm(grad[:, c]), 1e-30)
+            assert nr <= 1e-3, (c, nr)

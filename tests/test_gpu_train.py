@@ -51,7 +51,7 @@ def test_training_step_matches_oracle_step(tiny):
     tr = PlainTrainer(wl["params"], wl["cams"], targets, masks)
     tr.fit_capacity()
     v = 3
-    before = {k: t.detach().cpu().numpy().astype(np.float64) for k, t in tr.params.items()}
+    before = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in wl["params"].items()}
     tr.step(v)
     torch.cuda.synchronize()
     after = {k: t.detach().cpu().numpy().astype(np.float64) for k, t in tr.params.items()}
