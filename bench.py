@@ -50,7 +50,10 @@ def parse():
     ap.add_argument("--tile", default=None, help="fix the bin tile (e.g. 16x16); default autotuned")
     ap.add_argument("--schedule", default=None, help="default | lpt | persistent (default autotuned)")
     ap.add_argument("--chunk", type=int, default=None, help="backward chunk (0 = whole tiles)")
+    ap.add_argument("--fwd-waves", type=int, default=None, help="forward waves per tile (1, 2, 4)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--cached-plan", action="store_true",
+                    help="reuse the plan the autotuner cached for this workload (no re-tuning)")
     ap.add_argument("--recompute", action="store_true")
     ap.add_argument("--small", action="store_true", help="tiny config (smoke use)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -144,20 +147,20 @@ def main():
     tune_entry = None
     if args.no_autotune or (args.tile and args.schedule is not None and args.chunk is not None):
         plan = (tuple(int(x) for x in (args.tile or "16x16").split("x")), args.schedule or "default",
-                args.chunk or 0)
+                args.chunk or 0, args.fwd_waves or 1)
     else:
         from paper_2509_12138_amd import autotune
         t0 = time.perf_counter()
         plan, tune_entry = autotune.tune(make, W, H, 1, cfgd["n"], stored=stored,
                                          views=list(range(0, cfgd["views"], max(1, cfgd["views"] // 8))),
                                          cache_path=os.path.join(ROOT, "gpurun_out", "autotune.json"),
-                                         force=True, log=log)
+                                         force=not args.cached_plan, log=log)
         log(f"autotuned plan {plan} in {time.perf_counter() - t0:.1f}s")
-    tile, sched, chunk = plan
+    tile, sched, chunk, fwd_waves = plan
     if not stored:
         chunk = 0
     tr = PlainTrainer(wl["params"], wl["cams"], targets, masks, tile=tile, stored=stored,
-                      schedule=sched, chunk=chunk)
+                      schedule=sched, chunk=chunk, fwd_waves=fwd_waves)
     need = tr.fit_capacity()
     log(f"max duplicates per view {need}, capacity {tr.bufs.dup_capacity}")
     rng = np.random.default_rng(1000 + 2)
@@ -234,6 +237,7 @@ def main():
             "tile": f"{tile[0]}x{tile[1]}",
             "schedule": sched,
             "backward_chunk": chunk,
+            "fwd_waves": fwd_waves,
             "plan_source": "autotuner" if tune_entry else "fixed",
             "backward": "recompute" if args.recompute else "stored",
             "duplicates_per_view": need,

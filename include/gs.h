@@ -194,6 +194,10 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views,
  * and the backward starts each item from them.
  *   chunk_offset [n_tiles + 1], chunk_items [max_items]: from gs_chunk_items
  *   after gs_bin_sort (the same plan must be passed to both raster calls).
+ * fwd_waves: waves per tile in the forward (0 or 1 = one wave per tile; 2 or
+ * 4 split the tile's pixels over that many waves of one work-group, which
+ * shortens the longest tiles; must divide tile_w * tile_h / 64; not with a
+ * queue).
  * Results do not depend on the plan (up to FP32 atomic ordering in the
  * gradients).                                                              */
 typedef struct {
@@ -205,6 +209,8 @@ typedef struct {
   const uint32_t* chunk_items;
   float* checkpoints;
   int64_t max_items;
+  int32_t fwd_waves;
+  int32_t reserved;
 } gs_raster_plan;
 
 /* Upper bound on the work items of gs_chunk_items for a duplicate capacity. */

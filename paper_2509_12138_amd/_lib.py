@@ -53,7 +53,7 @@ class gs_projected(C.Structure):
 class gs_raster_plan(C.Structure):
     _fields_ = [("tile_order", vp), ("queue", vp), ("persistent_waves", i32), ("chunk", i32),
                 ("chunk_offset", vp), ("chunk_items", vp), ("checkpoints", vp),
-                ("max_items", i64)]
+                ("max_items", i64), ("fwd_waves", i32), ("reserved", i32)]
 
 
 class gs_adam_group(C.Structure):

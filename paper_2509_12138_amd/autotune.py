@@ -3,7 +3,7 @@ backward chunk size, picked by timing real training steps on the workload.
 
 The choice cannot change results: images do not depend on the tile shape
 (the support bbox is a strict superset of the alpha >= 1/255 ellipse) and the
-schedule / chunking only reorder work.  Results are cached in a JSON file
+schedule, chunking and waves per tile only reorder or split work.  Results are cached in a JSON file
 keyed by device, image size, slot count, Gaussian-count bucket and backward
 mode.
 """
@@ -17,11 +17,13 @@ import time
 import numpy as np
 import torch
 
-# (tile, schedule, chunk); every tile shape here has a compiled rasteriser
+# (tile, schedule, backward chunk, forward waves per tile); every tile shape
+# here has a compiled rasteriser
 CANDIDATES = [
-    ((16, 16), "lpt", 64), ((16, 16), "lpt", 128), ((16, 16), "persistent", 64),
-    ((16, 8), "lpt", 64), ((16, 8), "lpt", 128), ((8, 16), "lpt", 64), ((8, 16), "lpt", 128),
-    ((8, 8), "lpt", 0), ((16, 16), "lpt", 0), ((32, 8), "lpt", 128),
+    ((16, 16), "lpt", 64, 1), ((16, 16), "lpt", 64, 2), ((16, 16), "lpt", 64, 4),
+    ((16, 16), "lpt", 128, 4), ((16, 16), "persistent", 64, 1),
+    ((16, 8), "lpt", 64, 2), ((8, 16), "lpt", 64, 1), ((8, 16), "lpt", 64, 2),
+    ((8, 8), "lpt", 0, 1), ((16, 16), "lpt", 0, 4), ((32, 8), "lpt", 128, 4),
 ]
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "gsmi", "autotune.json")
@@ -51,9 +53,9 @@ def save_cache(path, cache):
 
 def time_plan(make_trainer, plan, views, steps=8, warmup=2):
     """Mean ms per training step of a trainer built with `plan`."""
-    tile, sched, chunk = plan
+    tile, sched, chunk, nw = plan
     tr = make_trainer(tile)
-    tr.bufs.set_schedule(sched if sched != "default" else "default", chunk=chunk)
+    tr.bufs.set_schedule(sched, chunk=chunk, fwd_waves=nw)
     tr.fit_capacity(views=views)
     for s in range(warmup):
         tr.step(views[s % len(views)])
@@ -71,7 +73,7 @@ def time_plan(make_trainer, plan, views, steps=8, warmup=2):
 
 def tune(make_trainer, width, height, n_slots, n_gauss, stored=True, views=None,
          candidates=None, cache_path=DEFAULT_CACHE, force=False, log=None):
-    """Return the fastest (tile, schedule, chunk) for this workload.
+    """Return the fastest (tile, schedule, chunk, fwd_waves) for this workload.
 
     make_trainer(tile) builds a fresh trainer (with .bufs, .step(view),
     .fit_capacity(views=...), .check()).  The choice is cached unless force.
@@ -80,7 +82,7 @@ def tune(make_trainer, width, height, n_slots, n_gauss, stored=True, views=None,
     cache = load_cache(cache_path) if cache_path else {}
     if not force and key in cache:
         e = cache[key]
-        return (tuple(e["tile"]), e["schedule"], e["chunk"]), e
+        return (tuple(e["tile"]), e["schedule"], e["chunk"], e.get("fwd_waves", 1)), e
     views = list(views if views is not None else range(8))
     results = []
     for plan in (candidates or CANDIDATES):
@@ -91,8 +93,10 @@ def tune(make_trainer, width, height, n_slots, n_gauss, stored=True, views=None,
         if log:
             log(f"autotune {plan}: {ms:.3f} ms/step")
     ms, best = min(results, key=lambda r: r[0])
-    entry = dict(tile=list(best[0]), schedule=best[1], chunk=best[2], ms_per_step=ms,
-                 tried=[dict(tile=list(p[0]), schedule=p[1], chunk=p[2], ms=m) for m, p in results])
+    entry = dict(tile=list(best[0]), schedule=best[1], chunk=best[2], fwd_waves=best[3],
+                 ms_per_step=ms,
+                 tried=[dict(tile=list(p[0]), schedule=p[1], chunk=p[2], fwd_waves=p[3], ms=m)
+                        for m, p in results])
     if cache_path:
         cache[key] = entry
         save_cache(cache_path, cache)

@@ -4,16 +4,21 @@
 //
 // Pipeline (all sizes that depend on data stay on the device, so the whole
 // call can be captured in a HIP graph):
-//   k_scan_reduce  per-block sums of n_tiles
+//   k_depth_keys + 4 radix passes   the m pairs sorted stably by depth bits
+//                  (ties by pair index): the depth order is sorted once per
+//                  pair instead of once per duplicate
+//   k_scan_reduce  per-block sums of n_tiles, in depth order
 //   k_scan_top     exclusive scan of the block sums, total -> status[1],
 //                  overflow flag, clamped count
-//   k_emit         per block: local scan of n_tiles, then one thread per
-//                  duplicate (coalesced writes) finds its pair by binary
-//                  search in LDS and writes key / pair index
+//   k_emit         per block of depth-ordered pairs: local scan of n_tiles,
+//                  then one thread per duplicate (coalesced writes) finds its
+//                  pair by binary search in LDS and writes key / pair index
 //   k_radix_hist / k_radix_rowscan / k_radix_scatter   LSD radix passes on
-//                  8-bit digits over the significant key bits only; the
-//                  scatter ranks stably with wave64 ballots and stages the
-//                  block in LDS so global writes are runs per digit
+//                  8-bit digits over the tile bits of the keys only (the
+//                  emission is already in (depth, pair) order and the passes
+//                  are stable); the scatter ranks stably with wave64 ballots
+//                  and stages the block in LDS so global writes are runs per
+//                  digit
 //   k_ranges       [start, end) per tile from the sorted keys
 #include "gs_device.h"
 
@@ -31,21 +36,29 @@ constexpr int kRadix = 1 << kRadixBits;
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct BinSortLayout {
-  int64_t nb_scan, nb_sort;
-  size_t off_block_sums, off_count, off_keys_alt, off_vals_alt, off_hist, off_rowtot, total;
+  int64_t nb_scan, nb_sort, nb_pairs;
+  size_t off_block_sums, off_count, off_keys_alt, off_vals_alt, off_hist, off_rowtot;
+  size_t off_pkeys[2], off_pvals[2], total;
 };
 
 static BinSortLayout layout(int64_t m, int64_t cap) {
   BinSortLayout L;
+  const size_t mm = (size_t)(m > 0 ? m : 1);
   L.nb_scan = ceil_div(m > 0 ? m : 1, kScanItems);
   L.nb_sort = ceil_div(cap > 0 ? cap : 1, kSortItems);
+  L.nb_pairs = ceil_div(m > 0 ? m : 1, kSortItems);
+  const int64_t nb_hist = L.nb_sort > L.nb_pairs ? L.nb_sort : L.nb_pairs;
   size_t o = 0;
   L.off_block_sums = o; o += align256(sizeof(int64_t) * (size_t)L.nb_scan);
   L.off_count = o; o += align256(sizeof(int64_t) * 2);
   L.off_keys_alt = o; o += align256(sizeof(uint64_t) * (size_t)(cap > 0 ? cap : 1));
   L.off_vals_alt = o; o += align256(sizeof(uint32_t) * (size_t)(cap > 0 ? cap : 1));
-  L.off_hist = o; o += align256(sizeof(uint32_t) * (size_t)kRadix * (size_t)L.nb_sort);
+  L.off_hist = o; o += align256(sizeof(uint32_t) * (size_t)kRadix * (size_t)nb_hist);
   L.off_rowtot = o; o += align256(sizeof(uint32_t) * kRadix);
+  for (int b = 0; b < 2; ++b) {
+    L.off_pkeys[b] = o; o += align256(sizeof(uint64_t) * mm);
+    L.off_pvals[b] = o; o += align256(sizeof(uint32_t) * mm);
+  }
   L.total = o;
   return L;
 }
@@ -85,7 +98,9 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sm_waves /*[4]*/, T& t
 
 // ------------------------------------------------------------ scan of n_tiles
 
+// Pairs are visited in the order perm[0..m) (the depth order).
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __restrict__ n_tiles,
+                                                              const uint32_t* __restrict__ perm,
                                                               int64_t m,
                                                               int64_t* __restrict__ block_sums) {
   __shared__ int64_t sm[4];
@@ -94,7 +109,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __r
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
     int64_t i = base + k * kScanThreads + threadIdx.x;
-    if (i < m) sum += max(n_tiles[i], 0);
+    if (i < m) sum += max(n_tiles[perm[i]], 0);
   }
   int64_t total;
   block_exclusive_scan<int64_t>(sum, sm, total);
@@ -128,15 +143,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t* __restrict__
 
 // ------------------------------------------------------------ emit
 
+// Block b handles depth-ordered positions b*kScanItems ...: pair perm[i]
+// with presorted key pkey[i] = (slot << 32) | depth bits.
 __global__ __launch_bounds__(kScanThreads) void k_emit(
     const int32_t* __restrict__ n_tiles, const uint2* __restrict__ tile_bbox,
-    const float* __restrict__ rec, int64_t m, const int64_t* __restrict__ block_offsets,
-    int64_t cap, int tiles_x, int tiles_per_slot, uint64_t* __restrict__ keys,
-    uint32_t* __restrict__ vals) {
+    const uint64_t* __restrict__ pkey, const uint32_t* __restrict__ perm, int64_t m,
+    const int64_t* __restrict__ block_offsets, int64_t cap, int tiles_x, int tiles_per_slot,
+    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
   __shared__ uint32_t s_off[kScanItems + 1];
   __shared__ uint2 s_bbox[kScanItems];
   __shared__ uint32_t s_depth[kScanItems];
   __shared__ uint32_t s_slot[kScanItems];
+  __shared__ uint32_t s_pair[kScanItems];
   __shared__ uint32_t s_w[4];
   const int64_t base = (int64_t)blockIdx.x * kScanItems;
   const int t = threadIdx.x;
@@ -147,11 +165,14 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
     int64_t i = base + li;
     int nt = 0;
     if (i < m) {
-      nt = max(n_tiles[i], 0);
+      const uint32_t p = perm[i];
+      nt = max(n_tiles[p], 0);
       if (nt > 0) {
-        s_bbox[li] = tile_bbox[i];
-        s_depth[li] = __float_as_uint(rec[i * GS_REC_STRIDE + 9]);
-        s_slot[li] = __float_as_uint(rec[i * GS_REC_STRIDE + 10]);
+        const uint64_t key = pkey[i];
+        s_bbox[li] = tile_bbox[p];
+        s_depth[li] = (uint32_t)key;
+        s_slot[li] = (uint32_t)(key >> 32);
+        s_pair[li] = p;
       }
     }
     s_off[li] = (uint32_t)nt;
@@ -192,8 +213,24 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
     int ty = ty0 + (int)(k / span), tx = tx0 + (int)(k % span);
     uint64_t tile = (uint64_t)s_slot[lo] * (uint64_t)tiles_per_slot + (uint64_t)(ty * tiles_x + tx);
     keys[dst] = (tile << 32) | (uint64_t)s_depth[lo];
-    vals[dst] = (uint32_t)(base + lo);
+    vals[dst] = s_pair[lo];
   }
+}
+
+// ------------------------------------------------------------ depth presort
+
+// key = (slot << 32) | depth bits, value = pair index; count[0] = m.
+// Depths of visible pairs are positive, so their bits order as the floats.
+__global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ rec, int64_t m,
+                                                   uint64_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals,
+                                                   int64_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i == 0) count[0] = m;
+  if (i >= m) return;
+  keys[i] = ((uint64_t)__float_as_uint(rec[i * GS_REC_STRIDE + 10]) << 32) |
+            (uint64_t)__float_as_uint(rec[i * GS_REC_STRIDE + 9]);
+  vals[i] = (uint32_t)i;
 }
 
 // ------------------------------------------------------------ radix sort
@@ -383,10 +420,11 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   const int tiles_y = (int)ceil_div(tiling->height, tiling->tile_h);
   const int64_t tiles_per_slot = (int64_t)tiles_x * tiles_y;
   const int64_t n_tiles_all = tiles_per_slot * views->n_slots;
-  // key bits: 32 depth bits + enough bits for the largest tile index
+  // passes over the tile bits of the keys (the depth order comes from the
+  // presort of the pairs)
   int tile_bits = 0;
   while ((int64_t(1) << tile_bits) < n_tiles_all) ++tile_bits;
-  const int passes = (32 + tile_bits + kRadixBits - 1) / kRadixBits;
+  const int passes = (tile_bits + kRadixBits - 1) / kRadixBits;
   // emit into the buffer that the last pass will not overwrite
   uint64_t* k0 = (passes % 2 == 0) ? keys_out : keys_alt;
   uint32_t* v0 = (passes % 2 == 0) ? ids_out : vals_alt;
@@ -405,18 +443,39 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
     }
     return GS_OK;
   }
+  // depth presort of the m pairs: 4 stable passes over the depth bits,
+  // ping-pong ending in buffer 0
+  uint64_t* pk[2] = {(uint64_t*)(w + L.off_pkeys[0]), (uint64_t*)(w + L.off_pkeys[1])};
+  uint32_t* pv[2] = {(uint32_t*)(w + L.off_pvals[0]), (uint32_t*)(w + L.off_pvals[1])};
+  int64_t* count_pairs = count + 1;
+  hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, proj->rec, m,
+                     pk[0], pv[0], count_pairs);
+  GS_LAUNCH_CHECK("gs_bin_sort/depth_keys");
+  for (int p = 0; p < 4; ++p) {
+    const int shift = p * kRadixBits;
+    const int a = p & 1, b = a ^ 1;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)L.nb_pairs), dim3(kSortThreads), 0, s, pk[a],
+                       count_pairs, shift, L.nb_pairs, hist);
+    GS_LAUNCH_CHECK("gs_bin_sort/depth_hist");
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, L.nb_pairs, rowtot);
+    GS_LAUNCH_CHECK("gs_bin_sort/depth_rowscan");
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)L.nb_pairs), dim3(kSortThreads), 0, s,
+                       pk[a], pv[a], pk[b], pv[b], count_pairs, shift, L.nb_pairs, hist, rowtot);
+    GS_LAUNCH_CHECK("gs_bin_sort/depth_scatter");
+  }
+  // duplicates in depth order, then stable passes over the tile bits only
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s,
-                     proj->n_tiles, m, block_sums);
+                     proj->n_tiles, pv[0], m, block_sums);
   GS_LAUNCH_CHECK("gs_bin_sort/scan_reduce");
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, block_sums, L.nb_scan,
                      dup_capacity, status, count);
   GS_LAUNCH_CHECK("gs_bin_sort/scan_top");
   hipLaunchKernelGGL(k_emit, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s, proj->n_tiles,
-                     (const uint2*)proj->tile_bbox, proj->rec, m, block_sums, dup_capacity, tiles_x,
-                     (int)tiles_per_slot, k0, v0);
+                     (const uint2*)proj->tile_bbox, pk[0], pv[0], m, block_sums, dup_capacity,
+                     tiles_x, (int)tiles_per_slot, k0, v0);
   GS_LAUNCH_CHECK("gs_bin_sort/emit");
   for (int p = 0; p < passes; ++p) {
-    const int shift = p * kRadixBits;
+    const int shift = 32 + p * kRadixBits;
     const uint64_t* kin = (p % 2 == 0) ? k0 : k1;
     const uint32_t* vin = (p % 2 == 0) ? v0 : v1;
     uint64_t* kout = (p % 2 == 0) ? k1 : k0;

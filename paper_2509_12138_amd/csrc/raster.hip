@@ -5,6 +5,10 @@
 // pixels of one column, so every Gaussian staged in LDS is read once per 4
 // evaluations and the backward's wave reduction is amortised over 256
 // pixels.  Gaussians are staged 64 at a time (one gathered record per lane).
+// The forward can also split a tile's pixels over 2 or 4 waves of one
+// work-group (each wave walks the whole list for its rows, with its own LDS
+// batch): all tiles of a 1080p view are resident at once, so the forward's
+// time is set by its longest lists, and more waves per tile shorten them.
 // Work-group ids are remapped so that neighbouring tiles run on the same
 // XCD and share its L2.
 //
@@ -53,8 +57,16 @@ struct TileGeom {
   static_assert(TW * TH % kRasterWave == 0 && kRasterWave % TW == 0, "tile shape");
 };
 
-// Forward pass of one tile for one lane's PX pixels.  WITH_COLOR=false is the
-// replay used by the backward in RECOMPUTE mode.
+// Orders one wave's LDS accesses: the wave's staged batch is private to it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Forward pass of one tile for one lane's PX pixels (pixel slots lane +
+// 64 (kbase + k) of the tile).  WITH_COLOR=false is the replay used by the
+// backward in RECOMPUTE mode.  s_splat: this wave's 64-entry LDS batch.
 // CHUNKED (with colour) also prepares the chunked backward: boundary c is
 // the list position (c+1)*chunk; for each pixel the forward stores at slot c
 // of `ck` (ck[c * TW*TH + pixel]) the transmittance T_c there and the colour
@@ -63,16 +75,15 @@ struct TileGeom {
 // built without cancellation from chunk-local composites (P = prod(1-alpha),
 // L = sum rgb alpha T_local over a chunk) by U_c = L_{c+1} + P_{c+1} U_{c+1}
 // after the tile is done.
-template <int TW, int TH, bool WITH_COLOR, bool CHUNKED = false>
+template <int TW, int TH, int PX, bool WITH_COLOR, bool CHUNKED = false>
 __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
                                              const uint32_t* __restrict__ ids, uint32_t start,
                                              uint32_t end, const float fx, const float* fy,
                                              const bool* inside, Splat* s_splat, float* T,
                                              float (*C)[3], int* last, float4* ck = nullptr,
                                              int chunk = 0, float bg0 = 0.f, float bg1 = 0.f,
-                                             float bg2 = 0.f) {
-  constexpr int PX = TileGeom<TW, TH>::PX;
-  const int lane = threadIdx.x;
+                                             float bg2 = 0.f, int kbase = 0) {
+  const int lane = threadIdx.x & (kRasterWave - 1);
   bool done[PX];
   float Tl[PX], Lc[PX][3];
 #pragma unroll
@@ -93,9 +104,9 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
     for (int k = 0; k < PX; ++k) lane_done = lane_done && done[k];
     if (__all(lane_done)) break;
     const int n = (int)min((uint32_t)kRasterWave, end - b0);
-    __syncthreads();
+    wave_sync();
     if (lane < n) s_splat[lane] = load_splat(rec, ids[b0 + lane]);
-    __syncthreads();
+    wave_sync();
     for (int j = 0; j < n; ++j) {
       const Splat sp = s_splat[j];
       const float dx = __fsub_rn(fx, sp.mx);
@@ -144,7 +155,7 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
           float4* dst = ck + (int64_t)(ce - 1) * (TW * TH);
 #pragma unroll
           for (int k = 0; k < PX; ++k)
-            dst[lane + k * kRasterWave] = make_float4(Tl[k], Lc[k][0], Lc[k][1], Lc[k][2]);
+            dst[lane + (kbase + k) * kRasterWave] = make_float4(Tl[k], Lc[k][0], Lc[k][1], Lc[k][2]);
         }
 #pragma unroll
         for (int k = 0; k < PX; ++k) {
@@ -161,7 +172,7 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
       float4* dst = ck + (int64_t)(clast - 1) * (TW * TH);
 #pragma unroll
       for (int k = 0; k < PX; ++k)
-        dst[lane + k * kRasterWave] = make_float4(Tl[k], Lc[k][0], Lc[k][1], Lc[k][2]);
+        dst[lane + (kbase + k) * kRasterWave] = make_float4(Tl[k], Lc[k][0], Lc[k][1], Lc[k][2]);
     }
     float Tn[PX], U[PX][3];
 #pragma unroll
@@ -175,12 +186,13 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
       float4* slot = ck + (int64_t)c * (TW * TH);
 #pragma unroll
       for (int k = 0; k < PX; ++k) {
-        const float4 pl = slot[lane + k * kRasterWave];     // (P, L) of chunk c+1
+        const int q = lane + (kbase + k) * kRasterWave;
+        const float4 pl = slot[q];                          // (P, L) of chunk c+1
         const float Te = Tn[k] / pl.x;
         U[k][0] = fmaf(pl.x, U[k][0], pl.y);
         U[k][1] = fmaf(pl.x, U[k][1], pl.z);
         U[k][2] = fmaf(pl.x, U[k][2], pl.w);
-        slot[lane + k * kRasterWave] = make_float4(Te, U[k][0], U[k][1], U[k][2]);
+        slot[q] = make_float4(Te, U[k][0], U[k][1], U[k][2]);
         Tn[k] = Te;
       }
     }
@@ -232,19 +244,23 @@ __device__ __forceinline__ void for_each_tile(const TileSched& sch, int64_t n_ti
   }
 }
 
-template <int TW, int TH>
+// Forward of one tile by wave (threadIdx.x / 64) of NW: the wave owns pixel
+// slots lane + 64 k for k in [wave PX, (wave + 1) PX), PX = TW TH / (64 NW).
+template <int TW, int TH, int NW>
 __device__ __forceinline__ void fwd_tile(const RasterDev& a, const ChunkDev& ch, int64_t tile,
                                          Splat* s_splat, float* __restrict__ image,
                                          float* __restrict__ T_final,
                                          int32_t* __restrict__ n_contrib) {
-  constexpr int PX = TileGeom<TW, TH>::PX, RSTEP = TileGeom<TW, TH>::RSTEP;
+  constexpr int PX = TileGeom<TW, TH>::PX / NW, RSTEP = TileGeom<TW, TH>::RSTEP;
+  static_assert(PX >= 1 && TileGeom<TW, TH>::PX % NW == 0, "waves per tile");
   const int W = a.W, H = a.H;
   const int slot = (int)(tile / a.tiles_per_slot);
   const int t = (int)(tile - (int64_t)slot * a.tiles_per_slot);
   const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kRasterWave - 1);
+  const int kbase = (threadIdx.x / kRasterWave) * PX;
   const int px = tx * TW + (lane % TW);
-  const int py0 = ty * TH + lane / TW;
+  const int py0 = ty * TH + lane / TW + kbase * RSTEP;
   const float fx = (float)px + 0.5f;
   float fy[PX];
   bool inside[PX];
@@ -259,10 +275,10 @@ __device__ __forceinline__ void fwd_tile(const RasterDev& a, const ChunkDev& ch,
   int last[PX];
   if (ch.ck) {
     float4* ck = ch.ck + (int64_t)ch.offset[tile] * (TW * TH);
-    tile_forward<TW, TH, true, true>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T, C,
-                                     last, ck, ch.chunk, a.bg0, a.bg1, a.bg2);
+    tile_forward<TW, TH, PX, true, true>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T, C,
+                                         last, ck, ch.chunk, a.bg0, a.bg1, a.bg2, kbase);
   } else {
-    tile_forward<TW, TH, true>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T, C, last);
+    tile_forward<TW, TH, PX, true>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T, C, last);
   }
   const int64_t HW = (int64_t)H * W;
   float* img = image + (int64_t)slot * 3 * HW;
@@ -278,14 +294,16 @@ __device__ __forceinline__ void fwd_tile(const RasterDev& a, const ChunkDev& ch,
   }
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(kRasterWave) void k_raster_fwd(RasterDev a, TileSched sch, ChunkDev ch,
-                                                            float* __restrict__ image,
-                                                            float* __restrict__ T_final,
-                                                            int32_t* __restrict__ n_contrib) {
-  __shared__ Splat s_splat[kRasterWave];
+template <int TW, int TH, int NW>
+__global__ __launch_bounds__(kRasterWave * NW) void k_raster_fwd(RasterDev a, TileSched sch,
+                                                                 ChunkDev ch,
+                                                                 float* __restrict__ image,
+                                                                 float* __restrict__ T_final,
+                                                                 int32_t* __restrict__ n_contrib) {
+  __shared__ Splat s_splat[kRasterWave * NW];
+  Splat* mine = s_splat + (threadIdx.x / kRasterWave) * kRasterWave;
   for_each_tile(sch, a.n_tiles, [&](int64_t tile) {
-    fwd_tile<TW, TH>(a, ch, tile, s_splat, image, T_final, n_contrib);
+    fwd_tile<TW, TH, NW>(a, ch, tile, mine, image, T_final, n_contrib);
   });
 }
 
@@ -431,8 +449,8 @@ __device__ __forceinline__ void bwd_tile(const RasterDev& a, int64_t tile, Splat
   float T[PX];
   int last[PX];
   if (RECOMPUTE) {
-    tile_forward<TW, TH, false>(a.rec, a.ids, start, end, L.fx, L.fy, L.inside, s_splat, T,
-                                nullptr, last);
+    tile_forward<TW, TH, PX, false>(a.rec, a.ids, start, end, L.fx, L.fy, L.inside, s_splat, T,
+                                    nullptr, last);
   } else {
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
@@ -636,6 +654,7 @@ struct Launch {
   TileSched sch;
   ChunkDev ch;
   int64_t max_items;
+  int fwd_waves;
 };
 
 static Launch make_launch(const RasterDev& a, const gs_raster_plan* plan) {
@@ -647,6 +666,7 @@ static Launch make_launch(const RasterDev& a, const gs_raster_plan* plan) {
   L.ch.items = plan ? plan->chunk_items : nullptr;
   L.ch.ck = plan && plan->chunk > 0 ? reinterpret_cast<float4*>(plan->checkpoints) : nullptr;
   L.max_items = plan ? plan->max_items : 0;
+  L.fwd_waves = plan && plan->fwd_waves > 1 ? plan->fwd_waves : 1;
   if (L.sch.queue) {
     int64_t w = plan->persistent_waves > 0 ? plan->persistent_waves : (int64_t)device_cu_count() * 16;
     L.blocks = (unsigned)std::min<int64_t>(w, std::max<int64_t>(a.n_tiles, 1));
@@ -661,7 +681,22 @@ static Launch make_launch(const RasterDev& a, const gs_raster_plan* plan) {
 template <int TW, int TH>
 static void launch_fwd(const RasterDev& a, const Launch& L, float* image, float* T_final,
                        int32_t* n_contrib, hipStream_t s) {
-  hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3(L.blocks), dim3(kRasterWave), 0, s, a, L.sch,
+  constexpr int PXT = TileGeom<TW, TH>::PX;
+  if constexpr (PXT % 4 == 0) {
+    if (L.fwd_waves == 4) {
+      hipLaunchKernelGGL((k_raster_fwd<TW, TH, 4>), dim3(L.blocks), dim3(4 * kRasterWave), 0, s,
+                         a, L.sch, L.ch, image, T_final, n_contrib);
+      return;
+    }
+  }
+  if constexpr (PXT % 2 == 0) {
+    if (L.fwd_waves == 2) {
+      hipLaunchKernelGGL((k_raster_fwd<TW, TH, 2>), dim3(L.blocks), dim3(2 * kRasterWave), 0, s,
+                         a, L.sch, L.ch, image, T_final, n_contrib);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_raster_fwd<TW, TH, 1>), dim3(L.blocks), dim3(kRasterWave), 0, s, a, L.sch,
                      L.ch, image, T_final, n_contrib);
 }
 
@@ -716,9 +751,18 @@ static gs_status raster_prepare(const gs_projected* proj, const gs_views* views,
   return GS_OK;
 }
 
-static gs_status plan_prepare(const gs_raster_plan* plan, hipStream_t s, const char* who) {
+static gs_status plan_prepare(const gs_raster_plan* plan, const gs_tiling* tiling, hipStream_t s,
+                              const char* who) {
   if (!plan) return GS_OK;
   GS_REQUIRE(plan->persistent_waves >= 0, "%s: persistent_waves < 0", who);
+  const int nw = plan->fwd_waves;
+  GS_REQUIRE(nw == 0 || nw == 1 || nw == 2 || nw == 4, "%s: fwd_waves %d not in {0, 1, 2, 4}",
+             who, nw);
+  GS_REQUIRE(nw <= 1 || (tiling->tile_w * tiling->tile_h / kRasterWave) % nw == 0,
+             "%s: fwd_waves %d does not divide the %dx%d tile's %d pixels per lane", who, nw,
+             tiling->tile_w, tiling->tile_h, tiling->tile_w * tiling->tile_h / kRasterWave);
+  GS_REQUIRE(nw <= 1 || plan->queue == nullptr, "%s: fwd_waves > 1 needs a non-persistent plan",
+             who);
   if (plan->chunk > 0) {
     GS_REQUIRE(plan->chunk % kRasterWave == 0, "%s: chunk %d is not a multiple of 64", who,
                plan->chunk);
@@ -807,7 +851,7 @@ gs_status gs_raster_fwd(const gs_projected* proj, const gs_views* views, const g
   GS_REQUIRE((T_final == nullptr) == (n_contrib == nullptr),
              "gs_raster_fwd: T_final and n_contrib must both be set or both be NULL");
   hipStream_t s = as_stream(stream);
-  st = plan_prepare(plan, s, "gs_raster_fwd");
+  st = plan_prepare(plan, tiling, s, "gs_raster_fwd");
   if (st != GS_OK) return st;
   const Launch L = make_launch(a, plan);
 #define GS_FWD_CASE(a_, b_)                                              \
@@ -834,7 +878,7 @@ gs_status gs_raster_bwd(const gs_projected* proj, const gs_views* views, const g
   GS_REQUIRE(mode == GS_BWD_RECOMPUTE || (T_final && n_contrib),
              "gs_raster_bwd: STORED mode needs T_final and n_contrib");
   hipStream_t s = as_stream(stream);
-  st = plan_prepare(plan, s, "gs_raster_bwd");
+  st = plan_prepare(plan, tiling, s, "gs_raster_bwd");
   if (st != GS_OK) return st;
   const Launch L = make_launch(a, plan);
 #define GS_BWD_CASE(a_, b_)                                                   \

@@ -135,6 +135,7 @@ class RasterBuffers:
         self.plan = None
         self.schedule = "default"
         self.chunk = 0
+        self.fwd_waves = 1
 
     def ensure_capacity(self, cap):
         cap = int(min(max(cap, 1024), 0xFFFFFFFF))
@@ -165,17 +166,21 @@ class RasterBuffers:
 
     # ---------------------------------------------------------- tile schedule
 
-    def set_schedule(self, mode="default", persistent_waves=0, chunk=0):
+    def set_schedule(self, mode="default", persistent_waves=0, chunk=0, fwd_waves=1):
         """How the rasterisers walk the tiles: "default" (XCD-aware order, one
         work-group per tile), "lpt" (longest tile lists first) or "persistent"
         (longest first, pulled from an atomic queue by a persistent grid).
         chunk > 0 (a multiple of 64) cuts the backward's tile lists into
-        chunk-entry work items (stored mode), using forward checkpoints."""
+        chunk-entry work items (stored mode), using forward checkpoints.
+        fwd_waves (1, 2, 4) splits each tile's pixels over that many waves in
+        the forward."""
         dev = self.views.device
         self.schedule = mode
         self.chunk = int(chunk) if self.store_state else 0
+        self.fwd_waves = int(fwd_waves)
         n = self.S * self.tiles_per_slot
         self.plan = _lib.gs_raster_plan()
+        self.plan.fwd_waves = self.fwd_waves
         if mode != "default":
             self.tile_order = torch.empty(n, dtype=torch.int32, device=dev)
             nb = _lib.load().gs_tile_order_workspace_bytes(n)
@@ -187,7 +192,7 @@ class RasterBuffers:
         if self.chunk:
             self.chunk_offset = torch.empty(n + 1, dtype=torch.int32, device=dev)
             self._alloc_chunks()
-        if mode == "default" and not self.chunk:
+        if mode == "default" and not self.chunk and self.fwd_waves <= 1:
             self.plan = None
 
     def _alloc_chunks(self):

@@ -49,6 +49,17 @@ def log(*a):
 SURFACE_EXTENT = 0.56    # the isosurface |x| = 0.5 +- 0.05 lies inside [-0.56, 0.56]^3
 
 
+def slab_part(x0, x1, n, seed, ref_factor=2.0, grid=GRID):
+    """One x-slab [x0, x1) of the bumpy-sphere isosurface padded by the ghost
+    margin, sampled at n points, plus its ref_factor-denser reference."""
+    ghost = GHOST_VOXELS * 2.0 / grid
+    box = ((x0 - ghost, -1.0, -1.0), (x1 + ghost, 1.0, 1.0))
+    pts, nrm = scene.sample_surface(scene.field_sphere_sines, int(n), grid, seed=seed, box=box)
+    rp, rn = scene.sample_surface(scene.field_sphere_sines, int(n * ref_factor), grid,
+                                  seed=seed + 50, box=box)
+    return dict(points=pts, normals=nrm, ref_points=rp, ref_normals=rn, x_range=(x0, x1))
+
+
 def slab_partitions(counts=SLAB_COUNTS, seed=4, ref_factor=2.0, grid=GRID):
     """The bumpy-sphere isosurface cut into len(counts) equal-width x-slabs
     over its extent, each padded by a ghost margin of GHOST_VOXELS voxels
@@ -57,18 +68,9 @@ def slab_partitions(counts=SLAB_COUNTS, seed=4, ref_factor=2.0, grid=GRID):
     ref_factor times denser in the same padded slab.  Returns per partition
     points / normals / ref_points / ref_normals ([n,3] float64)."""
     P = len(counts)
-    ghost = GHOST_VOXELS * 2.0 / grid
     edges = np.linspace(-SURFACE_EXTENT, SURFACE_EXTENT, P + 1)
-    parts = []
-    for p in range(P):
-        box = ((edges[p] - ghost, -1.0, -1.0), (edges[p + 1] + ghost, 1.0, 1.0))
-        pts, nrm = scene.sample_surface(scene.field_sphere_sines, int(counts[p]), grid,
-                                        seed=seed * 100 + p, box=box)
-        rp, rn = scene.sample_surface(scene.field_sphere_sines, int(counts[p] * ref_factor), grid,
-                                      seed=seed * 100 + 50 + p, box=box)
-        parts.append(dict(points=pts, normals=nrm, ref_points=rp, ref_normals=rn,
-                          x_range=(float(edges[p]), float(edges[p + 1]))))
-    return parts
+    return [slab_part(float(edges[p]), float(edges[p + 1]), counts[p], seed * 100 + p,
+                      ref_factor, grid) for p in range(P)]
 
 
 def prepare(parts, cams, device="cuda"):
@@ -106,9 +108,9 @@ def run_plain(part, cams, target, max_steps, eval_every, init="plain", mlp=None,
         kind = "plain"
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
-    tile, sched, chunk = plan or ((16, 16), "lpt", 64)
+    tile, sched, chunk, nw = plan or ((16, 16), "lpt", 64, 1)
     tr = PlainTrainer(params, cams, part["targets"], part["masks"], tile=tile, schedule=sched,
-                      chunk=chunk)
+                      chunk=chunk, fwd_waves=nw)
     tr.fit_capacity(views=range(0, len(cams), max(1, len(cams) // 8)))
     hist = tr.train(max_steps, order_seed=1000 + seed, eval_every=eval_every, target_psnr=target)
     reached = [h for h in hist if h[2] is not None and h[2] >= target]
@@ -133,11 +135,11 @@ def run_batched(parts, cams, target, max_steps, eval_every, views_per_part=4, pl
     inits = [plain_params(p, device)[0] for p in parts]
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
-    tile, sched, chunk = plan or ((16, 16), "lpt", 64)
+    tile, sched, chunk, nw = plan or ((16, 16), "lpt", 64, 1)
     bp = [dict(params={k: v.cpu().numpy() for k, v in ini.items()}, targets=p["targets"],
                masks=p["masks"]) for ini, p in zip(inits, parts)]
     tr = BatchedTrainer(bp, cams, views_per_part=views_per_part, tile=tile, schedule=sched,
-                        chunk=chunk, order_seed=7)
+                        chunk=chunk, fwd_waves=nw, order_seed=7)
     tr.fit_capacity()
     P = len(parts)
     reached = [None] * P
@@ -174,16 +176,26 @@ def _cams(views, width, height):
 
 
 def cmd_probe(a):
-    """PSNR against steps on the 1M-Gaussian 1080p partition (plain)."""
-    wl = workloads.realistic_partition(dict(n=int(1_000_000 * a.scale), n_ref=int(4_000_000 * a.scale)))
-    part = dict(points=wl["points"], normals=wl["normals"])
-    tg, mk = workloads.render_targets_gpu(wl["reference"], wl["cams"])
-    part.update(targets=tg, masks=mk, n=len(wl["points"]))
-    r = run_plain(part, wl["cams"], a.target, a.steps, a.eval_every, plan=a.plan)
+    """Masked PSNR against training steps of the plain trainer: the octant
+    partition of the bumpy-sphere field (scale x 4M Gaussians) or the
+    1M-Gaussian mixing-layer partition (--field mixing)."""
+    if a.field == "mixing":
+        wl = workloads.realistic_partition(dict(n=int(1_000_000 * a.scale),
+                                                n_ref=int(4_000_000 * a.scale)))
+        cams = wl["cams"]
+        part = dict(points=wl["points"], normals=wl["normals"], n=len(wl["points"]))
+        part["targets"], part["masks"] = workloads.render_targets_gpu(wl["reference"], cams)
+    else:
+        cams = _cams(a.views, a.width, a.height)
+        part = prepare([octant_partition(int(4_000_000 * a.scale), seed=5,
+                                         ref_factor=a.ref_factor)], cams)[0]
+    log(f"probe: {a.field} partition, n={part['n']}")
+    r = run_plain(part, cams, a.target, a.steps, a.eval_every, plan=a.plan)
     for s, t, p in r["history"]:
         log(f"plain step {s}: {t:.2f} s psnr {p:.2f}")
-    print(json.dumps(dict(experiment="probe", n=part["n"], target=a.target, seconds=r["seconds"],
-                          steps=r["steps"], history=r["history"])), flush=True)
+    print(json.dumps(dict(experiment="probe", field=a.field, n=part["n"], target=a.target,
+                          seconds=r["seconds"], steps=r["steps"], history=r["history"])),
+          flush=True)
 
 
 def cmd_batched(a):
@@ -256,7 +268,8 @@ def cmd_learned(a):
     tiny_part["targets"], tiny_part["masks"] = workloads.render_targets_gpu(tiny["reference"],
                                                                             tiny["cams"])
     xs, ts, ys = [], [], []
-    x, t, yp, ps = fitted_examples(tiny_part, tiny["cams"], a.fit_steps, ((16, 16), "lpt", 64), 1)
+    x, t, yp, ps = fitted_examples(tiny_part, tiny["cams"], a.fit_steps, ((16, 16), "lpt", 64, 1),
+                                   1)
     xs.append(x); ts.append(t); ys.append(yp)
     log(f"tiny fitted: psnr {ps}")
     src = prepare([octant_partition(int(a.scale * 13_300_000), seed=3, ref_factor=a.ref_factor)],
@@ -284,9 +297,10 @@ def cmd_learned(a):
     use_mlp = math.isfinite(held) and held < held_plain
     log(f"network: {mlp_seconds:.1f} s, held-out loss {held:.4f} vs plain init {held_plain:.4f}"
         f" -> {'learned' if use_mlp else 'fallback to plain'}")
-    # a new partition of the same field (other seed): learned vs plain
-    tgt = prepare([octant_partition(int(a.scale * 4_000_000), seed=5, ref_factor=a.ref_factor)],
-                  cams)[0]
+    # a new partition of the same field: an x-slab whose extent matches none
+    # of the slab partitions, other seed; learned vs plain
+    tgt = prepare([slab_part(-0.21, 0.26, int(a.scale * 4_000_000), seed=5,
+                             ref_factor=a.ref_factor)], cams)[0]
     out = dict(experiment="learned_vs_plain", n=tgt["n"], target=a.target,
                mlp_train_seconds=mlp_seconds, mlp_history=hist, mlp_heldout_loss=held,
                plain_heldout_loss=held_plain)
@@ -313,14 +327,16 @@ def main(argv=None):
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--vpp", type=int, default=4)
     ap.add_argument("--ref-factor", type=float, default=2.0)
+    ap.add_argument("--field", choices=["sphere", "mixing"], default="sphere")
     ap.add_argument("--fit-steps", type=int, default=2000)
     ap.add_argument("--mlp-steps", type=int, default=2000)
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--schedule", default="lpt")
     ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--fwd-waves", type=int, default=1)
     a = ap.parse_args(argv)
     tw, th = (int(v) for v in a.tile.split("x"))
-    a.plan = ((tw, th), a.schedule, a.chunk)
+    a.plan = ((tw, th), a.schedule, a.chunk, a.fwd_waves)
     if not torch.cuda.is_available():
         sys.exit("ttt needs a GPU")
     dict(probe=cmd_probe, batched=cmd_batched, learned=cmd_learned)[a.experiment](a)

@@ -128,6 +128,19 @@ def oracle_windows(big, dI):
     return _oracle_out[tile]
 
 
+_ncontrib = {}
+
+
+def oracle_ncontrib(big, tile):
+    """n_contrib of the oracle's window renders with this tile shape's
+    records (a position in the tile's list, so it depends on the shape)."""
+    if tile not in _ncontrib:
+        _, _, _, views = records(big, tile)
+        _ncontrib[tile] = [[oracle.render(views[v], W, H, tile=tile, window=win)["n_contrib"]
+                            for win in windows_for(big, v)] for v in range(len(VIEWS))]
+    return _ncontrib[tile]
+
+
 def image_gradient(big):
     rng = np.random.default_rng(11)
     dI = np.zeros((len(VIEWS), 3, H, W), np.float32)
@@ -158,38 +171,39 @@ def test_fullsize_bin_sort_bit_exact(big):
 
 def _plans():
     from paper_2509_12138_amd.autotune import CANDIDATES
-    plans = [(t, s, c, True) for (t, s, c) in CANDIDATES]
-    plans.append(((16, 16), "lpt", 0, False))              # transmittance recompute
+    plans = [(t, s, c, w, True) for (t, s, c, w) in CANDIDATES]
+    plans.append(((16, 16), "lpt", 0, 1, False))           # transmittance recompute
     return plans
 
 
-@pytest.mark.parametrize("tile,sched,chunk,stored", _plans())
-def test_fullsize_raster_matches_oracle_windows(big, tile, sched, chunk, stored):
+@pytest.mark.parametrize("tile,sched,chunk,fwd_waves,stored", _plans())
+def test_fullsize_raster_matches_oracle_windows(big, tile, sched, chunk, fwd_waves, stored):
     from paper_2509_12138_amd import ops
     params, cams = big
     n = params["opacity_logit"].shape[0]
-    say(f"full-size raster tile={tile} {sched} chunk={chunk} stored={stored}")
+    say(f"full-size raster tile={tile} {sched} chunk={chunk} fwd_waves={fwd_waves} stored={stored}")
     rec, tb, nt, _ = records(big, tile)
     dI = image_gradient(big)
     bufs = ops.RasterBuffers(ops.Views.single(n, cams), W, H, tile, dup_capacity=1024,
                              store_state=stored)
-    bufs.set_schedule(sched, chunk=chunk)
+    bufs.set_schedule(sched, chunk=chunk, fwd_waves=fwd_waves)
     raster_records(bufs, rec, tb, nt, (0.0, 0.0, 0.0), torch)
     bufs.zero_d_rec()
     bufs.raster_bwd(torch.as_tensor(dI).cuda())
     torch.cuda.synchronize()
     img = bufs.image.cpu().numpy()
     drec = bufs.d_rec.cpu().numpy().astype(np.float64)
+    ncs = oracle_ncontrib(big, tile) if stored else None
     for v, per in enumerate(oracle_windows(big, dI)):
         grad = np.zeros((n, 9)); term = np.zeros((n, 9)); amb_m = np.zeros((n, 9))
-        for (x0, y0, x1, y1), f, b in per:
+        for w_i, ((x0, y0, x1, y1), f, b) in enumerate(per):
             amb = ((f["ambiguity"] & SAME_RECORD_BITS) != 0)[y0:y1, x0:x1]
             assert amb.mean() <= 1e-2
             err = np.abs(img[v][:, y0:y1, x0:x1] - f["image"][:, y0:y1, x0:x1])[:, ~amb]
             assert err.max() <= 1e-4, ((x0, y0), err.max())
             if stored:
                 nc = bufs.n_contrib[v].cpu().numpy()[y0:y1, x0:x1]
-                np.testing.assert_array_equal(nc[~amb], f["n_contrib"][y0:y1, x0:x1][~amb])
+                np.testing.assert_array_equal(nc[~amb], ncs[v][w_i][y0:y1, x0:x1][~amb])
             grad += np.concatenate([b["d_mean2d"], b["d_conic"], b["d_opacity"][None],
                                     b["d_rgb"]]).T
             term += b["term_mass"].T

@@ -422,3 +422,34 @@ def test_chunked_backward_matches_oracle(ops, chunk, sched):
         ok0, worst0 = grad_tolerance_check(res[0][1][sl], ref, o["term_mass"].T, o["amb_mass"].T)
         ok, worst = grad_tolerance_check(res[chunk][1][sl], ref, o["term_mass"].T, o["amb_mass"].T)
         assert ok0 and ok, (worst0, worst)
+
+
+@pytest.mark.parametrize("tile,fwd_waves", [((16, 16), 2), ((16, 16), 4), ((8, 16), 2),
+                                            ((32, 16), 4)])
+def test_forward_waves_give_identical_results(ops, tile, fwd_waves):
+    """Splitting a tile's pixels over several waves of the forward changes
+    only who computes each pixel: images, T_final and n_contrib are
+    bit-identical, and the chunked backward (which reads the checkpoints the
+    forward wrote) gives the same gradients up to atomic ordering."""
+    say("fwd waves", tile, fwd_waves)
+    W, H = 150, 110
+    params = perturbed(surface_scene(8000, 91), 91, amount=0.2)
+    cams = scene.orbit_cameras(2, W, H)
+    bg = (0.1, 0.2, 0.3)
+    rec, tb, nt, _ = oracle_records(params, cams, W, H, tile)
+    dI = torch.as_tensor(np.random.default_rng(4).normal(size=(2, 3, H, W)).astype(np.float32)).cuda()
+    out = {}
+    for nw in (1, fwd_waves):
+        bufs = make_bufs(ops, params, cams, W, H, tile)
+        bufs.set_schedule("lpt", chunk=64, fwd_waves=nw)
+        raster_records(bufs, rec, tb, nt, bg, torch)
+        bufs.zero_d_rec()
+        bufs.raster_bwd(dI, bg=bg)
+        torch.cuda.synchronize()
+        out[nw] = (bufs.image.cpu().numpy(), bufs.T_final.cpu().numpy(),
+                   bufs.n_contrib.cpu().numpy(), bufs.d_rec.cpu().numpy())
+    a, b = out[1], out[fwd_waves]
+    for i in range(3):
+        np.testing.assert_array_equal(a[i], b[i])
+    nr = np.linalg.norm(a[3] - b[3]) / np.linalg.norm(a[3])
+    assert nr <= 1e-5, nr
