@@ -217,6 +217,12 @@ def main():
                 "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
                 "traffic": None, "units_per_launch": evals_fwd,
                 "unit_desc": f"{OPS_PER_EVAL_FWD} FP32 VALU issue slots per evaluated (pixel, entry)"}
+    # HBM traffic of the dominant kernel from committed counter runs, only
+    # while its source is unchanged since they were taken
+    from paper_2509_12138_amd import traffic as _traffic
+    plan_str = f"{tile[0]}x{tile[1]},{sched},{chunk},{fwd_waves}"
+    roof["traffic"] = _traffic.lookup(os.path.join(ROOT, "paper_2509_12138_amd", "hbm_traffic.json"),
+                                      roof["kernel"], plan_str)
     out = {
         "metric": METRIC,
         "value": round(mpix, 3),

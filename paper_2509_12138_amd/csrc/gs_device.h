@@ -72,6 +72,7 @@ constexpr int kDppQuadSwap1 = 0xB1;   // quad_perm [1,0,3,2]
 constexpr int kDppQuadSwap2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int kDppRowRor4 = 0x124;    // row_ror:4
 constexpr int kDppRowRor8 = 0x128;    // row_ror:8
+constexpr int kDppRowHalfMirror = 0x141;  // row_half_mirror (l <-> 7 - l in 8 lanes)
 constexpr int kDppRowBcast15 = 0x142; // row_bcast:15
 constexpr int kDppRowBcast31 = 0x143; // row_bcast:31
 

@@ -313,6 +313,81 @@ __device__ __forceinline__ int wave_max_int(int v) {
   return v;
 }
 
+// Reduce-scatter of the 9 gradient components of one list entry over the
+// wave.  Stage 1 pairs lanes l and l ^ 32 with v_permlane32_swap, stage 2
+// pairs l and l ^ 16 with v_permlane16_swap: swapping the halves of two
+// component registers and adding gives, in every lane, one component summed
+// over the lane pair, with no selects.  Stages 3-4 (partners l ^ 8 via
+// row_ror:8, and l <-> 7 - (l mod 8) via row_half_mirror) keep one of two
+// components per lane, and two quad_perm steps finish the sum.  Afterwards
+// each group of 4 lanes holds the wave total of one component: 9 of the 16
+// groups hold one each, and lanes 4k issue a single 9-lane atomic.
+struct Scatter9 {
+  int slot;       // component this lane's group holds (-1: none)
+  float scale;    // its constant factor in d_rec
+};
+
+__device__ __forceinline__ Scatter9 scatter9_setup() {
+  const int lane = threadIdx.x & (kRasterWave - 1);
+  // which operand a lane keeps after each swap: push 0 / 1 through it
+  const auto p32 = __builtin_amdgcn_permlane32_swap(0u, 1u, false, false);
+  const auto p16 = __builtin_amdgcn_permlane16_swap(0u, 1u, false, false);
+  const bool first32 = p32[0] == 0u, first16 = p16[0] == 0u;
+  const int b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+  const int u = b2 == 0 ? (b3 ? 2 : 0) : (b3 ? -1 : 1);           // after stage 2
+  const int w = u < 0 ? -1 : (first16 ? u : (u + 3 <= 4 ? u + 3 : -1));   // after stage 1
+  const int v = w < 0 ? -1 : (first32 ? w : (w + 5 <= 8 ? w + 5 : -1));  // component
+  // d mean2d (x2) carry -ln2, d Q11 and d Q22 -1/2, d Q12 -1 (log2-scaled
+  // falloff); opacity and colour 1
+  const float sc[9] = {-kLn2, -kLn2, -0.5f, -1.0f, -0.5f, 1.0f, 1.0f, 1.0f, 1.0f};
+  Scatter9 r;
+  r.slot = ((lane & 3) == 0) ? v : -1;
+  r.scale = v >= 0 ? sc[v] : 0.0f;
+  return r;
+}
+
+__device__ __forceinline__ float swap_add32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float swap_add16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// v[0..8]: this lane's partial components; returns the wave total of the
+// component named by scatter9_setup().slot (valid in every lane of its group).
+__device__ __forceinline__ float reduce_scatter9(const float (&v)[9]) {
+  const int lane = threadIdx.x & (kRasterWave - 1);
+  // stage 1: 9 -> 5 (pairs (i, i + 5), v[9] = 0)
+  const float w0 = swap_add32(v[0], v[5]);
+  const float w1 = swap_add32(v[1], v[6]);
+  const float w2 = swap_add32(v[2], v[7]);
+  const float w3 = swap_add32(v[3], v[8]);
+  const float w4 = swap_add32(v[4], 0.0f);
+  // stage 2: 5 -> 3 (pairs (i, i + 3), w[5] = 0)
+  const float u0 = swap_add16(w0, w3);
+  const float u1 = swap_add16(w1, w4);
+  const float u2 = swap_add16(w2, 0.0f);
+  // stage 3: 3 -> 2 across l ^ 8: bit 3 clear keeps (u0, u1), set keeps (u2, -)
+  const bool b3 = (lane >> 3) & 1;
+  const float k0 = b3 ? u2 : u0, s0 = b3 ? u0 : u2;
+  const float k1 = b3 ? 0.0f : u1, s1 = b3 ? u1 : 0.0f;
+  const float t0 = k0 + dpp_f<kDppRowRor8>(s0);
+  const float t1 = k1 + dpp_f<kDppRowRor8>(s1);
+  // stage 4: 2 -> 1 across l <-> 7 - (l mod 8): bit 2 clear keeps t0
+  const bool b2 = (lane >> 2) & 1;
+  const float kk = b2 ? t1 : t0, ss = b2 ? t0 : t1;
+  float z = kk + dpp_f<kDppRowHalfMirror>(ss);
+  // stages 5-6: sum over the quad
+  z += dpp_f<kDppQuadSwap1>(z);
+  z += dpp_f<kDppQuadSwap2>(z);
+  return z;
+}
+
 // Reverse replay of list positions (lo, hi] of one tile (entries start+lo ..
 // start+hi-1, last first).  Per pixel k on entry: T[k] = transmittance after
 // position hi, dIacc[k] = dI . (colour blended behind position hi + bg T_final).
@@ -321,7 +396,7 @@ __device__ __forceinline__ void reverse_pass(const RasterDev& a, uint32_t start,
                                              const float fx, const float* fy, const int* last,
                                              float* T, float (*dI)[3], float* dIacc,
                                              Splat* s_splat, uint32_t* s_id,
-                                             float* __restrict__ d_rec) {
+                                             float* __restrict__ d_rec, const Scatter9& red) {
   constexpr int PX = TileGeom<TW, TH>::PX;
   const int lane = threadIdx.x;
   for (int top = hi; top > lo; top -= kRasterWave) {
@@ -378,32 +453,17 @@ __device__ __forceinline__ void reverse_pass(const RasterDev& a, uint32_t start,
         }
       }
       const float bdx = sp.B * dx;
-      float g_mx = fmaf(2.0f * sp.A * dx, sG, sp.B * sGdy);   // x -ln2 below
-      float g_my = fmaf(2.0f * sp.C, sGdy, bdx * sG);         // x -ln2 below
-      float g_q11 = dx * dx * sG;                             // x -1/2 below
-      float g_q12 = dx * sGdy;                                // x -1 below
-      float g_q22 = sGdy2;                                    // x -1/2 below
-      g_mx = wave_sum_to_lane63(g_mx);
-      g_my = wave_sum_to_lane63(g_my);
-      g_q11 = wave_sum_to_lane63(g_q11);
-      g_q12 = wave_sum_to_lane63(g_q12);
-      g_q22 = wave_sum_to_lane63(g_q22);
-      so = wave_sum_to_lane63(so);
-      sr = wave_sum_to_lane63(sr);
-      sg = wave_sum_to_lane63(sg);
-      sb = wave_sum_to_lane63(sb);
-      if (lane == 63) {
-        float* dst = d_rec + (int64_t)s_id[j] * GS_DREC_STRIDE;
-        atomicAdd(dst + 0, -kLn2 * g_mx);
-        atomicAdd(dst + 1, -kLn2 * g_my);
-        atomicAdd(dst + 2, -0.5f * g_q11);
-        atomicAdd(dst + 3, -g_q12);
-        atomicAdd(dst + 4, -0.5f * g_q22);
-        atomicAdd(dst + 5, so);
-        atomicAdd(dst + 6, sr);
-        atomicAdd(dst + 7, sg);
-        atomicAdd(dst + 8, sb);
-      }
+      // geometric gradients of the lane (constant factors applied per
+      // component after the reduction)
+      const float comp[9] = {fmaf(2.0f * sp.A * dx, sG, sp.B * sGdy),   // d mx / -ln2
+                             fmaf(2.0f * sp.C, sGdy, bdx * sG),         // d my / -ln2
+                             dx * dx * sG,                              // d Q11 / -1/2
+                             dx * sGdy,                                 // d Q12 / -1
+                             sGdy2,                                     // d Q22 / -1/2
+                             so, sr, sg, sb};
+      const float tot = reduce_scatter9(comp);
+      if (red.slot >= 0)
+        atomicAdd(d_rec + (int64_t)s_id[j] * GS_DREC_STRIDE + red.slot, red.scale * tot);
     }
   }
 }
@@ -474,7 +534,8 @@ __device__ __forceinline__ void bwd_tile(const RasterDev& a, int64_t tile, Splat
 #pragma unroll
   for (int k = 0; k < PX; ++k) lmax = max(lmax, last[k]);
   lmax = min(wave_max_int(lmax), (int)(end - start));
-  reverse_pass<TW, TH>(a, start, 0, lmax, L.fx, L.fy, last, T, dI, dIacc, s_splat, s_id, d_rec);
+  reverse_pass<TW, TH>(a, start, 0, lmax, L.fx, L.fy, last, T, dI, dIacc, s_splat, s_id, d_rec,
+                       scatter9_setup());
 }
 
 template <int TW, int TH, bool RECOMPUTE>
@@ -540,7 +601,8 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd_chunked(
       dIacc[k] = s.x * (dI[k][0] * s.y + dI[k][1] * s.z + dI[k][2] * s.w);
     }
   }
-  reverse_pass<TW, TH>(a, start, lo, hi, L.fx, L.fy, last, T, dI, dIacc, s_splat, s_id, d_rec);
+  reverse_pass<TW, TH>(a, start, lo, hi, L.fx, L.fy, last, T, dI, dIacc, s_splat, s_id, d_rec,
+                       scatter9_setup());
 }
 
 // ---------------------------------------------------------------- tile order
@@ -715,7 +777,7 @@ static void launch_bwd(const RasterDev& a, const Launch& L, const float* T_final
                        L.sch, T_final, n_contrib, d_image, d_rec);
 }
 
-// Tile shapes with a compiled rasteriser (one wave per tile).
+// Tile shapes with a compiled rasteriser.
 #define GS_RASTER_SHAPES(X) X(16, 16) X(8, 8) X(16, 8) X(32, 8) X(8, 16) X(32, 16) X(16, 32)
 
 static bool raster_shape_supported(int tw, int th) {
