@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--schedule", default=None, help="default | lpt | persistent (default autotuned)")
     ap.add_argument("--chunk", type=int, default=None, help="backward chunk (0 = whole tiles)")
     ap.add_argument("--fwd-waves", type=int, default=None, help="forward waves per tile (1, 2, 4)")
+    ap.add_argument("--deterministic", type=int, default=None,
+                    help="1: per-entry gradient slots summed per pair instead of atomics")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cached-plan", action="store_true",
                     help="reuse the plan the autotuner cached for this workload (no re-tuning)")
@@ -147,7 +149,7 @@ def main():
     tune_entry = None
     if args.no_autotune or (args.tile and args.schedule is not None and args.chunk is not None):
         plan = (tuple(int(x) for x in (args.tile or "16x16").split("x")), args.schedule or "default",
-                args.chunk or 0, args.fwd_waves or 1)
+                args.chunk or 0, args.fwd_waves or 1, bool(args.deterministic))
     else:
         from paper_2509_12138_amd import autotune
         t0 = time.perf_counter()
@@ -156,11 +158,12 @@ def main():
                                          cache_path=os.path.join(ROOT, "gpurun_out", "autotune.json"),
                                          force=not args.cached_plan, log=log)
         log(f"autotuned plan {plan} in {time.perf_counter() - t0:.1f}s")
-    tile, sched, chunk, fwd_waves = plan
+    tile, sched, chunk, fwd_waves, deterministic = plan
     if not stored:
         chunk = 0
     tr = PlainTrainer(wl["params"], wl["cams"], targets, masks, tile=tile, stored=stored,
-                      schedule=sched, chunk=chunk, fwd_waves=fwd_waves)
+                      schedule=sched, chunk=chunk, fwd_waves=fwd_waves,
+                      deterministic=deterministic)
     need = tr.fit_capacity()
     log(f"max duplicates per view {need}, capacity {tr.bufs.dup_capacity}")
     rng = np.random.default_rng(1000 + 2)
@@ -220,7 +223,7 @@ def main():
     # HBM traffic of the dominant kernel from committed counter runs, only
     # while its source is unchanged since they were taken
     from paper_2509_12138_amd import traffic as _traffic
-    plan_str = f"{tile[0]}x{tile[1]},{sched},{chunk},{fwd_waves}"
+    plan_str = f"{tile[0]}x{tile[1]},{sched},{chunk},{fwd_waves},{int(deterministic)}"
     roof["traffic"] = _traffic.lookup(os.path.join(ROOT, "paper_2509_12138_amd", "hbm_traffic.json"),
                                       roof["kernel"], plan_str)
     out = {
@@ -244,6 +247,7 @@ def main():
             "schedule": sched,
             "backward_chunk": chunk,
             "fwd_waves": fwd_waves,
+            "deterministic_gradients": deterministic,
             "plan_source": "autotuner" if tune_entry else "fixed",
             "backward": "recompute" if args.recompute else "stored",
             "duplicates_per_view": need,

@@ -17,14 +17,23 @@ import time
 import numpy as np
 import torch
 
-# (tile, schedule, backward chunk, forward waves per tile); every tile shape
-# here has a compiled rasteriser
+# (tile, schedule, backward chunk, forward waves per tile, deterministic
+# gradients); every tile shape here has a compiled rasteriser
 CANDIDATES = [
-    ((16, 16), "lpt", 64, 1), ((16, 16), "lpt", 64, 2), ((16, 16), "lpt", 64, 4),
-    ((16, 16), "lpt", 128, 4), ((16, 16), "persistent", 64, 1),
-    ((16, 8), "lpt", 64, 2), ((8, 16), "lpt", 64, 1), ((8, 16), "lpt", 64, 2),
-    ((8, 8), "lpt", 0, 1), ((16, 16), "lpt", 0, 4), ((32, 8), "lpt", 128, 4),
+    ((16, 16), "lpt", 64, 4, True), ((16, 16), "lpt", 64, 4, False),
+    ((16, 16), "lpt", 128, 4, True), ((16, 16), "lpt", 64, 2, True),
+    ((16, 16), "lpt", 64, 1, False), ((16, 16), "persistent", 64, 1, True),
+    ((16, 8), "lpt", 64, 2, True), ((8, 16), "lpt", 64, 2, True), ((8, 16), "lpt", 64, 1, False),
+    ((8, 8), "lpt", 0, 1, True), ((16, 16), "lpt", 0, 4, True), ((32, 8), "lpt", 128, 4, True),
 ]
+
+
+def normalize(plan):
+    """Plans of older caches lack the trailing fields: fill the defaults."""
+    tile, sched, chunk = plan[0], plan[1], plan[2]
+    nw = plan[3] if len(plan) > 3 else 1
+    det = bool(plan[4]) if len(plan) > 4 else False
+    return (tuple(tile), sched, int(chunk), int(nw), det)
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "gsmi", "autotune.json")
 
@@ -53,9 +62,9 @@ def save_cache(path, cache):
 
 def time_plan(make_trainer, plan, views, steps=8, warmup=2):
     """Mean ms per training step of a trainer built with `plan`."""
-    tile, sched, chunk, nw = plan
+    tile, sched, chunk, nw, det = normalize(plan)
     tr = make_trainer(tile)
-    tr.bufs.set_schedule(sched, chunk=chunk, fwd_waves=nw)
+    tr.bufs.set_schedule(sched, chunk=chunk, fwd_waves=nw, deterministic=det)
     tr.fit_capacity(views=views)
     for s in range(warmup):
         tr.step(views[s % len(views)])
@@ -73,7 +82,8 @@ def time_plan(make_trainer, plan, views, steps=8, warmup=2):
 
 def tune(make_trainer, width, height, n_slots, n_gauss, stored=True, views=None,
          candidates=None, cache_path=DEFAULT_CACHE, force=False, log=None):
-    """Return the fastest (tile, schedule, chunk, fwd_waves) for this workload.
+    """Return the fastest (tile, schedule, chunk, fwd_waves, deterministic)
+    for this workload.
 
     make_trainer(tile) builds a fresh trainer (with .bufs, .step(view),
     .fit_capacity(views=...), .check()).  The choice is cached unless force.
@@ -82,10 +92,12 @@ def tune(make_trainer, width, height, n_slots, n_gauss, stored=True, views=None,
     cache = load_cache(cache_path) if cache_path else {}
     if not force and key in cache:
         e = cache[key]
-        return (tuple(e["tile"]), e["schedule"], e["chunk"], e.get("fwd_waves", 1)), e
+        return normalize((e["tile"], e["schedule"], e["chunk"], e.get("fwd_waves", 1),
+                          e.get("deterministic", False))), e
     views = list(views if views is not None else range(8))
     results = []
     for plan in (candidates or CANDIDATES):
+        plan = normalize(plan)
         if not stored and plan[2]:
             continue                                   # chunking needs stored state
         ms = time_plan(make_trainer, plan, views)
@@ -94,9 +106,9 @@ def tune(make_trainer, width, height, n_slots, n_gauss, stored=True, views=None,
             log(f"autotune {plan}: {ms:.3f} ms/step")
     ms, best = min(results, key=lambda r: r[0])
     entry = dict(tile=list(best[0]), schedule=best[1], chunk=best[2], fwd_waves=best[3],
-                 ms_per_step=ms,
-                 tried=[dict(tile=list(p[0]), schedule=p[1], chunk=p[2], fwd_waves=p[3], ms=m)
-                        for m, p in results])
+                 deterministic=best[4], ms_per_step=ms,
+                 tried=[dict(tile=list(p[0]), schedule=p[1], chunk=p[2], fwd_waves=p[3],
+                             deterministic=p[4], ms=m) for m, p in results])
     if cache_path:
         cache[key] = entry
         save_cache(cache_path, cache)

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
     const int32_t* __restrict__ n_tiles, const uint2* __restrict__ tile_bbox,
     const uint64_t* __restrict__ pkey, const uint32_t* __restrict__ perm, int64_t m,
     const int64_t* __restrict__ block_offsets, int64_t cap, int tiles_x, int tiles_per_slot,
-    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ pair_first) {
   __shared__ uint32_t s_off[kScanItems + 1];
   __shared__ uint2 s_bbox[kScanItems];
   __shared__ uint32_t s_depth[kScanItems];
@@ -195,6 +195,14 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
   if (t == 0) s_off[kScanItems] = total;
   __syncthreads();
   const int64_t gbase = block_offsets[blockIdx.x];
+  if (pair_first) {
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const int li = k * kScanThreads + t;
+      const int64_t i = base + li;
+      if (i < m && s_off[li + 1] > s_off[li]) pair_first[s_pair[li]] = (uint32_t)(gbase + s_off[li]);
+    }
+  }
   for (uint32_t j = t; j < total; j += kScanThreads) {
     int64_t dst = gbase + j;
     if (dst >= cap) break;
@@ -393,7 +401,8 @@ size_t gs_bin_sort_workspace_bytes(int64_t m, int64_t dup_capacity, const gs_til
 
 gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_tiling* tiling,
                       int64_t dup_capacity, void* ws, size_t ws_bytes, uint64_t* keys_out,
-                      uint32_t* ids_out, uint32_t* tile_ranges, int64_t* status, void* stream) {
+                      uint32_t* ids_out, uint32_t* tile_ranges, uint32_t* pair_first,
+                      int64_t* status, void* stream) {
   clear_error();
   GS_REQUIRE(proj != nullptr, "gs_bin_sort: NULL proj");
   gs_status st = check_views(views, tiling, "gs_bin_sort");
@@ -472,7 +481,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   GS_LAUNCH_CHECK("gs_bin_sort/scan_top");
   hipLaunchKernelGGL(k_emit, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s, proj->n_tiles,
                      (const uint2*)proj->tile_bbox, pk[0], pv[0], m, block_sums, dup_capacity,
-                     tiles_x, (int)tiles_per_slot, k0, v0);
+                     tiles_x, (int)tiles_per_slot, k0, v0, pair_first);
   GS_LAUNCH_CHECK("gs_bin_sort/emit");
   for (int p = 0; p < passes; ++p) {
     const int shift = 32 + p * kRadixBits;

@@ -207,7 +207,34 @@ struct RasterDev {
   int W, H, tiles_x, tiles_per_slot;
   int64_t n_tiles;
   float bg0, bg1, bg2;
+  // deterministic backward (NULL dup_grads: atomics into d_rec)
+  const uint2* tile_bbox;
+  const uint32_t* pair_first;
+  float* dup_grads;
+  int64_t dup_cap;
 };
+
+// Emission index of pair `id`'s entry for tile (tx, ty): its tiles are
+// emitted row-major over its tile bbox starting at pair_first[id].
+__device__ __forceinline__ uint32_t emission_index(const RasterDev& a, uint32_t id, int tx, int ty) {
+  const uint2 bb = a.tile_bbox[id];
+  const int tx0 = (int)(bb.x & 0xffffu), ty0 = (int)(bb.x >> 16), tx1 = (int)(bb.y & 0xffffu);
+  return a.pair_first[id] + (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+}
+
+// Deterministic mode: zero the gradient slots of list indices [lo, hi) of a
+// tile (entries no pixel reaches), one entry per lane.
+__device__ __forceinline__ void zero_dup_slots(const RasterDev& a, uint32_t start, int lo, int hi,
+                                               int tx, int ty) {
+  const int lane = threadIdx.x & (kRasterWave - 1);
+  for (int q = lo + lane; q < hi; q += kRasterWave) {
+    const uint32_t e = emission_index(a, a.ids[start + q], tx, ty);
+    if ((int64_t)e >= a.dup_cap) continue;
+    float* g = a.dup_grads + (int64_t)e * GS_DREC_STRIDE;
+#pragma unroll
+    for (int c = 0; c < GS_DREC_STRIDE; ++c) g[c] = 0.0f;
+  }
+}
 
 // Which tile a work-group processes: default XCD-aware order, a precomputed
 // (longest-first) order, or a persistent grid pulling from an atomic queue.
@@ -391,21 +418,26 @@ __device__ __forceinline__ float reduce_scatter9(const float (&v)[9]) {
 // Reverse replay of list positions (lo, hi] of one tile (entries start+lo ..
 // start+hi-1, last first).  Per pixel k on entry: T[k] = transmittance after
 // position hi, dIacc[k] = dI . (colour blended behind position hi + bg T_final).
+// With a.dup_grads the entry's components go to its emission slot (s_id then
+// holds the slot index), else they are added atomically to d_rec.
 template <int TW, int TH>
 __device__ __forceinline__ void reverse_pass(const RasterDev& a, uint32_t start, int lo, int hi,
                                              const float fx, const float* fy, const int* last,
                                              float* T, float (*dI)[3], float* dIacc,
                                              Splat* s_splat, uint32_t* s_id,
-                                             float* __restrict__ d_rec, const Scatter9& red) {
+                                             float* __restrict__ d_rec, const Scatter9& red,
+                                             int tx, int ty) {
   constexpr int PX = TileGeom<TW, TH>::PX;
   const int lane = threadIdx.x;
+  const bool det = a.dup_grads != nullptr;
+  float* const gbase = det ? a.dup_grads : d_rec;
   for (int top = hi; top > lo; top -= kRasterWave) {
     const int bot = max(lo, top - kRasterWave);
     const int n = top - bot;
     __syncthreads();
     if (lane < n) {
       const uint32_t id = a.ids[start + bot + lane];
-      s_id[lane] = id;
+      s_id[lane] = det ? emission_index(a, id, tx, ty) : id;
       s_splat[lane] = load_splat(a.rec, id);
     }
     __syncthreads();
@@ -421,7 +453,11 @@ __device__ __forceinline__ void reverse_pass(const RasterDev& a, uint32_t start,
         pass[k] = (pos <= last[k]) && splat_pass(sp, p2[k]);
         any = any || pass[k];
       }
-      if (!__any(any)) continue;
+      if (!__any(any)) {
+        if (det && red.slot >= 0 && (int64_t)s_id[j] < a.dup_cap)
+          gbase[(int64_t)s_id[j] * GS_DREC_STRIDE + red.slot] = 0.0f;
+        continue;
+      }
       // per-lane sums over the lane's pixels; the geometric gradients of the
       // lane follow from sG = sum G, sGdy = sum G dy, sGdy2 = sum G dy^2 with
       // G = dL/d(power) (dx is shared by the lane's column)
@@ -462,8 +498,11 @@ __device__ __forceinline__ void reverse_pass(const RasterDev& a, uint32_t start,
                              sGdy2,                                     // d Q22 / -1/2
                              so, sr, sg, sb};
       const float tot = reduce_scatter9(comp);
-      if (red.slot >= 0)
-        atomicAdd(d_rec + (int64_t)s_id[j] * GS_DREC_STRIDE + red.slot, red.scale * tot);
+      if (red.slot >= 0) {
+        float* dst = gbase + (int64_t)s_id[j] * GS_DREC_STRIDE + red.slot;
+        if (!det) atomicAdd(dst, red.scale * tot);
+        else if ((int64_t)s_id[j] < a.dup_cap) *dst = red.scale * tot;
+      }
     }
   }
 }
@@ -472,13 +511,14 @@ __device__ __forceinline__ void reverse_pass(const RasterDev& a, uint32_t start,
 template <int TW, int TH>
 struct LanePixels {
   static constexpr int PX = TileGeom<TW, TH>::PX, RSTEP = TileGeom<TW, TH>::RSTEP;
-  int slot, px, py0;
+  int slot, px, py0, tx, ty;
   float fx, fy[PX];
   bool inside[PX];
   __device__ __forceinline__ LanePixels(const RasterDev& a, int64_t tile) {
     slot = (int)(tile / a.tiles_per_slot);
     const int t = (int)(tile - (int64_t)slot * a.tiles_per_slot);
-    const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
+    ty = t / a.tiles_x;
+    tx = t - ty * a.tiles_x;
     const int lane = threadIdx.x;
     px = tx * TW + (lane % TW);
     py0 = ty * TH + lane / TW;
@@ -535,7 +575,8 @@ __device__ __forceinline__ void bwd_tile(const RasterDev& a, int64_t tile, Splat
   for (int k = 0; k < PX; ++k) lmax = max(lmax, last[k]);
   lmax = min(wave_max_int(lmax), (int)(end - start));
   reverse_pass<TW, TH>(a, start, 0, lmax, L.fx, L.fy, last, T, dI, dIacc, s_splat, s_id, d_rec,
-                       scatter9_setup());
+                       scatter9_setup(), L.tx, L.ty);
+  if (a.dup_grads) zero_dup_slots(a, start, lmax, (int)(end - start), L.tx, L.ty);
 }
 
 template <int TW, int TH, bool RECOMPUTE>
@@ -581,7 +622,10 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd_chunked(
     lmax = max(lmax, last[k]);
   }
   const int hi = min(wave_max_int(lmax), hi_pos);
-  if (hi <= lo) return;
+  if (hi <= lo) {
+    if (a.dup_grads) zero_dup_slots(a, start, lo, hi_pos, L.tx, L.ty);
+    return;
+  }
   const float4* ck = ch.ck + ((int64_t)ch.offset[tile] + c) * (TW * TH);
   float T[PX], dI[PX][3], dIacc[PX];
   const float* dimg = d_image + (int64_t)L.slot * 3 * HW;
@@ -602,7 +646,8 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd_chunked(
     }
   }
   reverse_pass<TW, TH>(a, start, lo, hi, L.fx, L.fy, last, T, dI, dIacc, s_splat, s_id, d_rec,
-                       scatter9_setup());
+                       scatter9_setup(), L.tx, L.ty);
+  if (a.dup_grads) zero_dup_slots(a, start, hi, hi_pos, L.tx, L.ty);
 }
 
 // ---------------------------------------------------------------- tile order
@@ -709,6 +754,31 @@ __global__ __launch_bounds__(256) void k_chunk_items(const uint32_t* __restrict_
   for (uint32_t i = offset[t]; i < offset[t + 1] && (int64_t)i < max_items; ++i) items[i] = (uint32_t)t;
 }
 
+// ---------------------------------------------------------------- deterministic sum
+
+// d_rec[p] += sum of pair p's emission slots, in emission order.
+__global__ __launch_bounds__(256) void k_dup_reduce(const int32_t* __restrict__ n_tiles,
+                                                    const uint32_t* __restrict__ pair_first,
+                                                    int64_t m, const float* __restrict__ dup,
+                                                    int64_t dup_cap, float* __restrict__ d_rec) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= m) return;
+  const int nt = n_tiles[p];
+  if (nt <= 0) return;
+  const int64_t e0 = pair_first[p];
+  if (e0 + nt > dup_cap) return;
+  const float* g = dup + e0 * GS_DREC_STRIDE;
+  float acc[GS_DREC_STRIDE];
+#pragma unroll
+  for (int c = 0; c < GS_DREC_STRIDE; ++c) acc[c] = 0.0f;
+  for (int k = 0; k < nt; ++k)
+#pragma unroll
+    for (int c = 0; c < GS_DREC_STRIDE; ++c) acc[c] += g[k * GS_DREC_STRIDE + c];
+  float* d = d_rec + p * GS_DREC_STRIDE;
+#pragma unroll
+  for (int c = 0; c < GS_DREC_STRIDE; ++c) d[c] += acc[c];
+}
+
 // ---------------------------------------------------------------- dispatch
 
 struct Launch {
@@ -810,6 +880,10 @@ static gs_status raster_prepare(const gs_projected* proj, const gs_views* views,
   a.bg0 = bg[0];
   a.bg1 = bg[1];
   a.bg2 = bg[2];
+  a.tile_bbox = reinterpret_cast<const uint2*>(proj->tile_bbox);
+  a.pair_first = nullptr;
+  a.dup_grads = nullptr;
+  a.dup_cap = 0;
   return GS_OK;
 }
 
@@ -940,6 +1014,14 @@ gs_status gs_raster_bwd(const gs_projected* proj, const gs_views* views, const g
   GS_REQUIRE(mode == GS_BWD_RECOMPUTE || (T_final && n_contrib),
              "gs_raster_bwd: STORED mode needs T_final and n_contrib");
   hipStream_t s = as_stream(stream);
+  const bool det = plan && plan->dup_grads;
+  if (det) {
+    GS_REQUIRE(plan->pair_first && plan->dup_capacity > 0 && proj->tile_bbox && proj->n_tiles,
+               "gs_raster_bwd: deterministic mode needs pair_first, dup_capacity, tile_bbox, n_tiles");
+    a.pair_first = plan->pair_first;
+    a.dup_grads = plan->dup_grads;
+    a.dup_cap = plan->dup_capacity;
+  }
   st = plan_prepare(plan, tiling, s, "gs_raster_bwd");
   if (st != GS_OK) return st;
   const Launch L = make_launch(a, plan);
@@ -950,6 +1032,12 @@ gs_status gs_raster_bwd(const gs_projected* proj, const gs_views* views, const g
   GS_RASTER_SHAPES(GS_BWD_CASE) {}
 #undef GS_BWD_CASE
   GS_LAUNCH_CHECK("gs_raster_bwd");
+  if (det && proj->m > 0) {
+    hipLaunchKernelGGL(k_dup_reduce, dim3((unsigned)ceil_div(proj->m, 256)), dim3(256), 0, s,
+                       proj->n_tiles, plan->pair_first, proj->m, plan->dup_grads,
+                       plan->dup_capacity, d_rec);
+    GS_LAUNCH_CHECK("gs_raster_bwd/reduce");
+  }
   return GS_OK;
 }
 

@@ -128,14 +128,17 @@ class RasterBuffers:
         else:
             self.T_final = self.n_contrib = None
         self.d_rec = torch.zeros((max(m, 1), 9), dtype=torch.float32, device=dev)
+        self.pair_first = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
         self.status = torch.zeros(4, dtype=torch.int64, device=dev)
         self.keys = self.ids = self.ws = None
-        self.dup_capacity = 0
-        self.ensure_capacity(dup_capacity or max(4 * m, 1024))
+        self.dup_grads = None
+        self.deterministic = False
         self.plan = None
         self.schedule = "default"
         self.chunk = 0
         self.fwd_waves = 1
+        self.dup_capacity = 0
+        self.ensure_capacity(dup_capacity or max(4 * m, 1024))
 
     def ensure_capacity(self, cap):
         cap = int(min(max(cap, 1024), 0xFFFFFFFF))
@@ -148,8 +151,10 @@ class RasterBuffers:
         nbytes = _lib.load().gs_bin_sort_workspace_bytes(self.m, cap, C.byref(self.tiling),
                                                          self.S)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-        if getattr(self, "chunk", 0):
+        if self.chunk:
             self._alloc_chunks()
+        if self.deterministic:
+            self._alloc_dup_grads()
 
     # ---------------------------------------------------------- the calls
 
@@ -162,22 +167,25 @@ class RasterBuffers:
         s = stream or stream_handle()
         call("gs_bin_sort", C.byref(self.proj), C.byref(self.views.struct), C.byref(self.tiling),
              self.dup_capacity, _ptr(self.ws), self.ws.numel(), _ptr(self.keys), _ptr(self.ids),
-             _ptr(self.ranges), _ptr(self.status), s)
+             _ptr(self.ranges), _ptr(self.pair_first), _ptr(self.status), s)
 
     # ---------------------------------------------------------- tile schedule
 
-    def set_schedule(self, mode="default", persistent_waves=0, chunk=0, fwd_waves=1):
+    def set_schedule(self, mode="default", persistent_waves=0, chunk=0, fwd_waves=1,
+                     deterministic=False):
         """How the rasterisers walk the tiles: "default" (XCD-aware order, one
         work-group per tile), "lpt" (longest tile lists first) or "persistent"
         (longest first, pulled from an atomic queue by a persistent grid).
         chunk > 0 (a multiple of 64) cuts the backward's tile lists into
         chunk-entry work items (stored mode), using forward checkpoints.
         fwd_waves (1, 2, 4) splits each tile's pixels over that many waves in
-        the forward."""
+        the forward.  deterministic: per-entry gradient slots summed per pair
+        instead of atomics (bitwise reproducible gradients)."""
         dev = self.views.device
         self.schedule = mode
         self.chunk = int(chunk) if self.store_state else 0
         self.fwd_waves = int(fwd_waves)
+        self.deterministic = bool(deterministic)
         n = self.S * self.tiles_per_slot
         self.plan = _lib.gs_raster_plan()
         self.plan.fwd_waves = self.fwd_waves
@@ -192,8 +200,19 @@ class RasterBuffers:
         if self.chunk:
             self.chunk_offset = torch.empty(n + 1, dtype=torch.int32, device=dev)
             self._alloc_chunks()
-        if mode == "default" and not self.chunk and self.fwd_waves <= 1:
+        if self.deterministic:
+            self._alloc_dup_grads()
+        else:
+            self.dup_grads = None
+        if mode == "default" and not self.chunk and self.fwd_waves <= 1 and not self.deterministic:
             self.plan = None
+
+    def _alloc_dup_grads(self):
+        self.dup_grads = torch.empty((self.dup_capacity, 9), dtype=torch.float32,
+                                     device=self.views.device)
+        self.plan.dup_grads = self.dup_grads.data_ptr()
+        self.plan.pair_first = self.pair_first.data_ptr()
+        self.plan.dup_capacity = self.dup_capacity
 
     def _alloc_chunks(self):
         dev = self.views.device

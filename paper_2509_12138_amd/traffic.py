@@ -7,7 +7,7 @@ of each counter: factor = bytes the copy moved / bytes the counter reported.
 
     python -m paper_2509_12138_amd.traffic --kernel k_raster_bwd_chunked \
         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \
-        --plan 8x16,lpt,64,1 --out paper_2509_12138_amd/hbm_traffic.json
+        --plan 16x16,lpt,64,4,1 --out paper_2509_12138_amd/hbm_traffic.json
 
 The entry records the kernel, the plan and a hash of the kernel's source
 file; bench.py reports the traffic only while that hash still matches.
@@ -57,7 +57,8 @@ def main(argv=None):
     ap.add_argument("--write", required=True)
     ap.add_argument("--copy-fetch", required=True)
     ap.add_argument("--copy-write", required=True)
-    ap.add_argument("--plan", required=True, help="tile,schedule,chunk,fwd_waves e.g. 8x16,lpt,64,1")
+    ap.add_argument("--plan", required=True,
+                    help="tile,schedule,chunk,fwd_waves,deterministic e.g. 16x16,lpt,64,4,1")
     ap.add_argument("--command", default="", help="the command the counters were taken on")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)

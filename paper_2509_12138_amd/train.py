@@ -41,7 +41,7 @@ class PlainTrainer:
 
     def __init__(self, params, cams_np, targets, masks, tile=(16, 16), lam=0.2,
                  bg=(0.0, 0.0, 0.0), stored=True, extent=2.75, lrs=None, dup_capacity=None,
-                 schedule="default", chunk=0, fwd_waves=1, device="cuda"):
+                 schedule="default", chunk=0, fwd_waves=1, deterministic=False, device="cuda"):
         self.device = device
         self.params = {k: torch.as_tensor(np.ascontiguousarray(v, np.float32)).to(device)
                        if not torch.is_tensor(v) else v.contiguous().to(device)
@@ -63,7 +63,8 @@ class PlainTrainer:
         self.views.use_cameras(self.cams[0:1])
         self.bufs = ops.RasterBuffers(self.views, self.W, self.H, tile, dup_capacity=dup_capacity,
                                       store_state=stored)
-        self.bufs.set_schedule(schedule, chunk=chunk, fwd_waves=fwd_waves)
+        self.bufs.set_schedule(schedule, chunk=chunk, fwd_waves=fwd_waves,
+                               deterministic=deterministic)
         self.loss = ops.LossBuffers(1, self.H, self.W, device)
         self.mode = _lib.GS_BWD_STORED if stored else _lib.GS_BWD_RECOMPUTE
         self.gst = ops.gaussians_struct(self.params)
@@ -183,7 +184,8 @@ class BatchedTrainer:
 
     def __init__(self, parts, cams_np, views_per_part=4, tile=(16, 16), schedule="lpt",
                  chunk=64, stored=True, lam=0.2, bg=(0.0, 0.0, 0.0), extent=2.75, lrs=None,
-                 order_seed=0, graphs=True, dup_capacity=None, fwd_waves=1, device="cuda"):
+                 order_seed=0, graphs=True, dup_capacity=None, fwd_waves=1, deterministic=False,
+                 device="cuda"):
         from .scene import concat_params
         self.device = device
         self.P = len(parts)
@@ -222,7 +224,8 @@ class BatchedTrainer:
         self.views = ops.Views.batch(self.counts, views_per_part, self.cams_g[0], device)
         self.bufs = ops.RasterBuffers(self.views, self.W, self.H, tile, dup_capacity=dup_capacity,
                                       store_state=stored)
-        self.bufs.set_schedule(schedule, chunk=chunk, fwd_waves=fwd_waves)
+        self.bufs.set_schedule(schedule, chunk=chunk, fwd_waves=fwd_waves,
+                               deterministic=deterministic)
         self.mode = _lib.GS_BWD_STORED if stored else _lib.GS_BWD_RECOMPUTE
         self.loss = ops.LossBuffers(self.S, self.H, self.W, device)
         self.gst = ops.gaussians_struct(self.params)

@@ -108,9 +108,9 @@ def run_plain(part, cams, target, max_steps, eval_every, init="plain", mlp=None,
         kind = "plain"
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
-    tile, sched, chunk, nw = plan or ((16, 16), "lpt", 64, 1)
+    tile, sched, chunk, nw, det = plan or ((16, 16), "lpt", 64, 4, True)
     tr = PlainTrainer(params, cams, part["targets"], part["masks"], tile=tile, schedule=sched,
-                      chunk=chunk, fwd_waves=nw)
+                      chunk=chunk, fwd_waves=nw, deterministic=det)
     tr.fit_capacity(views=range(0, len(cams), max(1, len(cams) // 8)))
     hist = tr.train(max_steps, order_seed=1000 + seed, eval_every=eval_every, target_psnr=target)
     reached = [h for h in hist if h[2] is not None and h[2] >= target]
@@ -135,11 +135,11 @@ def run_batched(parts, cams, target, max_steps, eval_every, views_per_part=4, pl
     inits = [plain_params(p, device)[0] for p in parts]
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t0
-    tile, sched, chunk, nw = plan or ((16, 16), "lpt", 64, 1)
+    tile, sched, chunk, nw, det = plan or ((16, 16), "lpt", 64, 4, True)
     bp = [dict(params={k: v.cpu().numpy() for k, v in ini.items()}, targets=p["targets"],
                masks=p["masks"]) for ini, p in zip(inits, parts)]
     tr = BatchedTrainer(bp, cams, views_per_part=views_per_part, tile=tile, schedule=sched,
-                        chunk=chunk, fwd_waves=nw, order_seed=7)
+                        chunk=chunk, fwd_waves=nw, deterministic=det, order_seed=7)
     tr.fit_capacity()
     P = len(parts)
     reached = [None] * P
@@ -268,8 +268,8 @@ def cmd_learned(a):
     tiny_part["targets"], tiny_part["masks"] = workloads.render_targets_gpu(tiny["reference"],
                                                                             tiny["cams"])
     xs, ts, ys = [], [], []
-    x, t, yp, ps = fitted_examples(tiny_part, tiny["cams"], a.fit_steps, ((16, 16), "lpt", 64, 1),
-                                   1)
+    x, t, yp, ps = fitted_examples(tiny_part, tiny["cams"], a.fit_steps,
+                                   ((16, 16), "lpt", 64, 1, True), 1)
     xs.append(x); ts.append(t); ys.append(yp)
     log(f"tiny fitted: psnr {ps}")
     src = prepare([octant_partition(int(a.scale * 13_300_000), seed=3, ref_factor=a.ref_factor)],
@@ -333,10 +333,11 @@ def main(argv=None):
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--schedule", default="lpt")
     ap.add_argument("--chunk", type=int, default=64)
-    ap.add_argument("--fwd-waves", type=int, default=1)
+    ap.add_argument("--fwd-waves", type=int, default=4)
+    ap.add_argument("--deterministic", type=int, default=1)
     a = ap.parse_args(argv)
     tw, th = (int(v) for v in a.tile.split("x"))
-    a.plan = ((tw, th), a.schedule, a.chunk, a.fwd_waves)
+    a.plan = ((tw, th), a.schedule, a.chunk, a.fwd_waves, bool(a.deterministic))
     if not torch.cuda.is_available():
         sys.exit("ttt needs a GPU")
     dict(probe=cmd_probe, batched=cmd_batched, learned=cmd_learned)[a.experiment](a)

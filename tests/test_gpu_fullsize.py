@@ -171,22 +171,24 @@ def test_fullsize_bin_sort_bit_exact(big):
 
 def _plans():
     from paper_2509_12138_amd.autotune import CANDIDATES
-    plans = [(t, s, c, w, True) for (t, s, c, w) in CANDIDATES]
-    plans.append(((16, 16), "lpt", 0, 1, False))           # transmittance recompute
+    plans = [(t, s, c, w, d, True) for (t, s, c, w, d) in CANDIDATES]
+    plans.append(((16, 16), "lpt", 0, 1, False, False))    # transmittance recompute
+    plans.append(((16, 16), "lpt", 0, 4, True, False))
     return plans
 
 
-@pytest.mark.parametrize("tile,sched,chunk,fwd_waves,stored", _plans())
-def test_fullsize_raster_matches_oracle_windows(big, tile, sched, chunk, fwd_waves, stored):
+@pytest.mark.parametrize("tile,sched,chunk,fwd_waves,det,stored", _plans())
+def test_fullsize_raster_matches_oracle_windows(big, tile, sched, chunk, fwd_waves, det, stored):
     from paper_2509_12138_amd import ops
     params, cams = big
     n = params["opacity_logit"].shape[0]
-    say(f"full-size raster tile={tile} {sched} chunk={chunk} fwd_waves={fwd_waves} stored={stored}")
+    say(f"full-size raster tile={tile} {sched} chunk={chunk} fwd_waves={fwd_waves} det={det} "
+        f"stored={stored}")
     rec, tb, nt, _ = records(big, tile)
     dI = image_gradient(big)
     bufs = ops.RasterBuffers(ops.Views.single(n, cams), W, H, tile, dup_capacity=1024,
                              store_state=stored)
-    bufs.set_schedule(sched, chunk=chunk, fwd_waves=fwd_waves)
+    bufs.set_schedule(sched, chunk=chunk, fwd_waves=fwd_waves, deterministic=det)
     raster_records(bufs, rec, tb, nt, (0.0, 0.0, 0.0), torch)
     bufs.zero_d_rec()
     bufs.raster_bwd(torch.as_tensor(dI).cuda())

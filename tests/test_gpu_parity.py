@@ -231,16 +231,19 @@ def test_permutation_invariance_gpu(ops):
     np.testing.assert_array_equal(a.image.cpu().numpy(), b.image.cpu().numpy())
 
 
+@pytest.mark.parametrize("det", [False, True])
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
-def test_raster_bwd_matches_oracle(ops, mode, tile):
-    say("raster_bwd mode", mode, tile)
+def test_raster_bwd_matches_oracle(ops, mode, tile, det):
+    say("raster_bwd mode", mode, tile, "deterministic" if det else "atomic")
     W, H = 120, 90
     params = perturbed(surface_scene(4000, 51), 51)
     cams = scene.orbit_cameras(2, W, H)
     bg = (0.2, 0.1, 0.05)
     rec, tb, nt, views = oracle_records(params, cams, W, H, tile)
     bufs = make_bufs(ops, params, cams, W, H, tile, store=(mode == 0))
+    if det:
+        bufs.set_schedule("default", deterministic=True)
     raster_records(bufs, rec, tb, nt, bg, torch)
     rng = np.random.default_rng(7)
     dI = rng.normal(size=(2, 3, H, W)).astype(np.float32)
@@ -383,8 +386,10 @@ def test_schedules_give_identical_results(ops, sched):
     assert nr <= 1e-5, nr
 
 
-@pytest.mark.parametrize("chunk,sched", [(64, "default"), (128, "lpt"), (64, "persistent")])
-def test_chunked_backward_matches_oracle(ops, chunk, sched):
+@pytest.mark.parametrize("chunk,sched,det", [(64, "default", False), (128, "lpt", False),
+                                             (64, "persistent", False), (64, "lpt", True),
+                                             (128, "default", True)])
+def test_chunked_backward_matches_oracle(ops, chunk, sched, det):
     """Tile lists cut into chunk-entry work items (forward checkpoints of T and
     C) give the oracle's gradients; the image is unchanged."""
     say("chunked bwd", chunk, sched)
@@ -398,7 +403,8 @@ def test_chunked_backward_matches_oracle(ops, chunk, sched):
     res = {}
     for c in (0, chunk):
         bufs = make_bufs(ops, params, cams, W, H, (16, 16))
-        bufs.set_schedule(sched if c else "default", persistent_waves=29, chunk=c)
+        bufs.set_schedule(sched if c else "default", persistent_waves=29, chunk=c,
+                          deterministic=det)
         raster_records(bufs, rec, tb, nt, bg, torch)
         bufs.zero_d_rec()
         bufs.raster_bwd(torch.as_tensor(dI).cuda(), bg=bg)
@@ -452,4 +458,39 @@ def test_forward_waves_give_identical_results(ops, tile, fwd_waves):
     for i in range(3):
         np.testing.assert_array_equal(a[i], b[i])
     nr = np.linalg.norm(a[3] - b[3]) / np.linalg.norm(a[3])
+    assert nr <= 1e-5, nr
+
+
+@pytest.mark.parametrize("chunk", [0, 64])
+def test_deterministic_gradients_are_reproducible(ops, chunk):
+    """Per-entry gradient slots summed per pair: two runs give bitwise equal
+    gradients, equal to the atomic accumulation up to summation order, and
+    the emission order of gs_bin_sort's pair_first matches its duplicates."""
+    say("deterministic gradients", chunk)
+    W, H = 160, 100
+    params = perturbed(surface_scene(9000, 93), 93, amount=0.2)
+    cams = scene.orbit_cameras(3, W, H)
+    rec, tb, nt, _ = oracle_records(params, cams, W, H, (16, 16))
+    dI = torch.as_tensor(np.random.default_rng(5).normal(size=(3, 3, H, W)).astype(np.float32)).cuda()
+    out = []
+    for det in (True, True, False):
+        bufs = make_bufs(ops, params, cams, W, H, (16, 16))
+        bufs.set_schedule("lpt", chunk=chunk, fwd_waves=2, deterministic=det)
+        raster_records(bufs, rec, tb, nt, (0.0, 0.0, 0.0), torch)
+        bufs.zero_d_rec()
+        bufs.raster_bwd(dI)
+        torch.cuda.synchronize()
+        out.append(bufs.d_rec.cpu().numpy())
+        if det:
+            # every emitted entry of a visible pair sits at pair_first + k
+            K = int(nt.astype(np.int64).sum())
+            pf = bufs.pair_first.cpu().numpy().astype(np.int64)
+            vis = nt > 0
+            order = np.argsort(pf[vis], kind="stable")
+            starts = pf[vis][order]
+            lens = nt[vis][order].astype(np.int64)
+            assert starts[0] == 0 and np.all(starts[1:] == starts[:-1] + lens[:-1])
+            assert starts[-1] + lens[-1] == K
+    np.testing.assert_array_equal(out[0], out[1])
+    nr = np.linalg.norm(out[0] - out[2]) / np.linalg.norm(out[2])
     assert nr <= 1e-5, nr
