@@ -210,7 +210,10 @@ def main():
         max(stage_ms, key=stage_ms.get)
     if dom == "raster_bwd":
         achieved = evals_bwd * OPS_PER_EVAL_BWD / (t_bwd * 1e-3)
-        roof = {"kernel": "k_raster_bwd_chunked" if chunk else "k_raster_bwd", "bound": "alu", "achieved": achieved / 1e12,
+        kname = "k_raster_bwd_chunked" if chunk else "k_raster_bwd"
+        if deterministic:
+            kname += "+k_dup_reduce"          # both run inside the timed gs_raster_bwd call
+        roof = {"kernel": kname, "bound": "alu", "achieved": achieved / 1e12,
                 "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
                 "traffic": None, "units_per_launch": evals_bwd,
                 "unit_desc": f"{OPS_PER_EVAL_BWD} FP32 VALU issue slots per evaluated (pixel, entry)"}

@@ -173,7 +173,9 @@ size_t gs_bin_sort_workspace_bytes(int64_t m, int64_t dup_capacity,
  *   pair's first entry.  Entries are emitted pair by pair in ascending
  *   (depth bits, pair index) order, each pair's tiles row-major over its tile
  *   bbox, so pair p's entries are emission indices pair_first[p] ..
- *   pair_first[p] + n_tiles[p] - 1 (unspecified when n_tiles[p] = 0).
+ *   pair_first[p] + n_tiles[p] - 1 (unspecified when n_tiles[p] = 0),
+ *   emit_out [dup_capacity] u32 (optional, may be NULL): the emission index
+ *   of each sorted entry (aligned with ids_out).
  * The true duplicate count is written to status[1]; when it exceeds
  * dup_capacity, GS_FLAG_CAPACITY is set, the list is truncated to the first
  * dup_capacity entries in emission order and the ranges are NOT meaningful:
@@ -182,7 +184,8 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views,
                       const gs_tiling* tiling, int64_t dup_capacity,
                       void* ws, size_t ws_bytes, uint64_t* keys_out,
                       uint32_t* ids_out, uint32_t* tile_ranges,
-                      uint32_t* pair_first, int64_t* status, void* stream);
+                      uint32_t* pair_first, uint32_t* emit_out, int64_t* status,
+                      void* stream);
 
 /* How the rasterisers walk the tiles of a call (optional; NULL = one
  * work-group per tile in an XCD-aware order).
@@ -204,11 +207,11 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views,
  * shortens the longest tiles; must divide tile_w * tile_h / 64; not with a
  * queue).
  * Deterministic gradients: with dup_grads ([dup_capacity][9] f32 device
- * workspace; dup_capacity as passed to gs_bin_sort) and pair_first (from
- * gs_bin_sort of the same step) set, the
- * backward writes each (tile, pair) entry's 9 gradient components into the
- * slot of its emission index instead of adding them atomically, then sums
- * every pair's slots in emission order into d_rec: no atomics, and
+ * workspace; dup_capacity as passed to gs_bin_sort), pair_first and
+ * emit_idx (pair_first and emit_out of gs_bin_sort of the same step) set,
+ * the backward writes each (tile, pair) entry's 9 gradient components into
+ * the slot of its emission index instead of adding them atomically, then
+ * sums every pair's slots in emission order into d_rec: no atomics, and
  * gradients are bitwise reproducible.
  * Images do not depend on the plan; gradients only up to FP32 summation
  * order.                                                                   */
@@ -226,6 +229,7 @@ typedef struct {
   float* dup_grads;
   const uint32_t* pair_first;
   int64_t dup_capacity;
+  const uint32_t* emit_idx;
 } gs_raster_plan;
 
 /* Upper bound on the work items of gs_chunk_items for a duplicate capacity. */

@@ -54,7 +54,8 @@ class gs_raster_plan(C.Structure):
     _fields_ = [("tile_order", vp), ("queue", vp), ("persistent_waves", i32), ("chunk", i32),
                 ("chunk_offset", vp), ("chunk_items", vp), ("checkpoints", vp),
                 ("max_items", i64), ("fwd_waves", i32), ("reserved", i32),
-                ("dup_grads", vp), ("pair_first", vp), ("dup_capacity", i64)]
+                ("dup_grads", vp), ("pair_first", vp), ("dup_capacity", i64),
+                ("emit_idx", vp)]
 
 
 class gs_adam_group(C.Structure):
@@ -78,7 +79,7 @@ SIGNATURES = {
     "gs_project": (i32, [P(gs_gaussians), P(gs_views), P(gs_tiling), P(gs_projected), vp]),
     "gs_bin_sort_workspace_bytes": (sz, [i64, i64, P(gs_tiling), i32]),
     "gs_bin_sort": (i32, [P(gs_projected), P(gs_views), P(gs_tiling), i64, vp, sz, vp, vp, vp,
-                          vp, vp, vp]),
+                          vp, vp, vp, vp]),
     "gs_raster_fwd": (i32, [P(gs_projected), P(gs_views), P(gs_tiling), vp, vp, P(f32), vp, vp,
                             vp, P(gs_raster_plan), vp]),
     "gs_raster_bwd": (i32, [P(gs_projected), P(gs_views), P(gs_tiling), vp, vp, P(f32), vp, vp,

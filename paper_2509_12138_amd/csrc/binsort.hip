@@ -37,7 +37,7 @@ static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct BinSortLayout {
   int64_t nb_scan, nb_sort, nb_pairs;
-  size_t off_block_sums, off_count, off_keys_alt, off_vals_alt, off_hist, off_rowtot;
+  size_t off_block_sums, off_count, off_keys_alt, off_vals_alt, off_emit_alt, off_hist, off_rowtot;
   size_t off_pkeys[2], off_pvals[2], total;
 };
 
@@ -53,6 +53,7 @@ static BinSortLayout layout(int64_t m, int64_t cap) {
   L.off_count = o; o += align256(sizeof(int64_t) * 2);
   L.off_keys_alt = o; o += align256(sizeof(uint64_t) * (size_t)(cap > 0 ? cap : 1));
   L.off_vals_alt = o; o += align256(sizeof(uint32_t) * (size_t)(cap > 0 ? cap : 1));
+  L.off_emit_alt = o; o += align256(sizeof(uint32_t) * (size_t)(cap > 0 ? cap : 1));
   L.off_hist = o; o += align256(sizeof(uint32_t) * (size_t)kRadix * (size_t)nb_hist);
   L.off_rowtot = o; o += align256(sizeof(uint32_t) * kRadix);
   for (int b = 0; b < 2; ++b) {
@@ -149,7 +150,8 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
     const int32_t* __restrict__ n_tiles, const uint2* __restrict__ tile_bbox,
     const uint64_t* __restrict__ pkey, const uint32_t* __restrict__ perm, int64_t m,
     const int64_t* __restrict__ block_offsets, int64_t cap, int tiles_x, int tiles_per_slot,
-    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ pair_first) {
+    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ pair_first,
+    uint32_t* __restrict__ emit) {
   __shared__ uint32_t s_off[kScanItems + 1];
   __shared__ uint2 s_bbox[kScanItems];
   __shared__ uint32_t s_depth[kScanItems];
@@ -222,6 +224,7 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
     uint64_t tile = (uint64_t)s_slot[lo] * (uint64_t)tiles_per_slot + (uint64_t)(ty * tiles_x + tx);
     keys[dst] = (tile << 32) | (uint64_t)s_depth[lo];
     vals[dst] = s_pair[lo];
+    if (emit) emit[dst] = (uint32_t)dst;
   }
 }
 
@@ -283,14 +286,17 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ hi
   if (threadIdx.x == 0) row_tot[blockIdx.x] = total;
 }
 
+// vin2 / vout2 (may be NULL): a second value carried along.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, const int64_t* __restrict__ count,
-    int shift, int64_t nb, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ row_tot) {
+    int shift, int64_t nb, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ row_tot,
+    const uint32_t* __restrict__ vin2, uint32_t* __restrict__ vout2) {
   // LDS: per (round, wave, digit) counts; staging of the block's items
   __shared__ uint16_t s_cnt[kSortPer][4][kRadix];   // 32 KB
   __shared__ uint64_t s_key[kSortItems];             // 32 KB
   __shared__ uint32_t s_val[kSortItems];             // 16 KB
+  __shared__ uint32_t s_val2[kSortItems];            // 16 KB
   __shared__ uint32_t s_dstart[kRadix];              // local digit starts
   __shared__ uint32_t s_gbase[kRadix];               // global digit base of this block
   __shared__ uint32_t s_w[4];
@@ -312,7 +318,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   }
   __syncthreads();
   uint64_t key[kSortPer];
-  uint32_t val[kSortPer];
+  uint32_t val[kSortPer], val2[kSortPer];
+  const bool two = vin2 != nullptr;
   uint32_t wrank[kSortPer];
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
@@ -321,6 +328,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     bool valid = i < n;
     key[r] = valid ? kin[i] : 0ull;
     val[r] = valid ? vin[i] : 0u;
+    val2[r] = (valid && two) ? vin2[i] : 0u;
     uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -356,6 +364,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       uint32_t pos = s_dstart[d] + s_cnt[r][wave][d] + wrank[r];
       s_key[pos] = key[r];
       s_val[pos] = val[r];
+      s_val2[pos] = val2[r];
     }
   }
   __syncthreads();
@@ -369,6 +378,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       int64_t dst = (int64_t)s_gbase[d] + (li - (int64_t)s_dstart[d]);
       kout[dst] = k;
       vout[dst] = s_val[li];
+      if (two) vout2[dst] = s_val2[li];
     }
   }
 }
@@ -402,7 +412,7 @@ size_t gs_bin_sort_workspace_bytes(int64_t m, int64_t dup_capacity, const gs_til
 gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_tiling* tiling,
                       int64_t dup_capacity, void* ws, size_t ws_bytes, uint64_t* keys_out,
                       uint32_t* ids_out, uint32_t* tile_ranges, uint32_t* pair_first,
-                      int64_t* status, void* stream) {
+                      uint32_t* emit_out, int64_t* status, void* stream) {
   clear_error();
   GS_REQUIRE(proj != nullptr, "gs_bin_sort: NULL proj");
   gs_status st = check_views(views, tiling, "gs_bin_sort");
@@ -439,6 +449,9 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   uint32_t* v0 = (passes % 2 == 0) ? ids_out : vals_alt;
   uint64_t* k1 = (passes % 2 == 0) ? keys_alt : keys_out;
   uint32_t* v1 = (passes % 2 == 0) ? vals_alt : ids_out;
+  uint32_t* emit_alt = (uint32_t*)(w + L.off_emit_alt);
+  uint32_t* e0 = emit_out ? ((passes % 2 == 0) ? emit_out : emit_alt) : nullptr;
+  uint32_t* e1 = emit_out ? ((passes % 2 == 0) ? emit_alt : emit_out) : nullptr;
 
   st = gs_zero(tile_ranges, sizeof(uint32_t) * 2 * (size_t)n_tiles_all, stream);
   if (st != GS_OK) return st;
@@ -469,7 +482,8 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
     hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, L.nb_pairs, rowtot);
     GS_LAUNCH_CHECK("gs_bin_sort/depth_rowscan");
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)L.nb_pairs), dim3(kSortThreads), 0, s,
-                       pk[a], pv[a], pk[b], pv[b], count_pairs, shift, L.nb_pairs, hist, rowtot);
+                       pk[a], pv[a], pk[b], pv[b], count_pairs, shift, L.nb_pairs, hist, rowtot,
+                       (const uint32_t*)nullptr, (uint32_t*)nullptr);
     GS_LAUNCH_CHECK("gs_bin_sort/depth_scatter");
   }
   // duplicates in depth order, then stable passes over the tile bits only
@@ -481,7 +495,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   GS_LAUNCH_CHECK("gs_bin_sort/scan_top");
   hipLaunchKernelGGL(k_emit, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s, proj->n_tiles,
                      (const uint2*)proj->tile_bbox, pk[0], pv[0], m, block_sums, dup_capacity,
-                     tiles_x, (int)tiles_per_slot, k0, v0, pair_first);
+                     tiles_x, (int)tiles_per_slot, k0, v0, pair_first, e0);
   GS_LAUNCH_CHECK("gs_bin_sort/emit");
   for (int p = 0; p < passes; ++p) {
     const int shift = 32 + p * kRadixBits;
@@ -489,13 +503,15 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
     const uint32_t* vin = (p % 2 == 0) ? v0 : v1;
     uint64_t* kout = (p % 2 == 0) ? k1 : k0;
     uint32_t* vout = (p % 2 == 0) ? v1 : v0;
+    const uint32_t* ein = (p % 2 == 0) ? e0 : e1;
+    uint32_t* eout = (p % 2 == 0) ? e1 : e0;
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)L.nb_sort), dim3(kSortThreads), 0, s, kin,
                        count, shift, L.nb_sort, hist);
     GS_LAUNCH_CHECK("gs_bin_sort/radix_hist");
     hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, L.nb_sort, rowtot);
     GS_LAUNCH_CHECK("gs_bin_sort/radix_rowscan");
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)L.nb_sort), dim3(kSortThreads), 0, s, kin,
-                       vin, kout, vout, count, shift, L.nb_sort, hist, rowtot);
+                       vin, kout, vout, count, shift, L.nb_sort, hist, rowtot, ein, eout);
     GS_LAUNCH_CHECK("gs_bin_sort/radix_scatter");
   }
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)ceil_div(dup_capacity, 256)), dim3(256), 0, s,

@@ -207,28 +207,19 @@ struct RasterDev {
   int W, H, tiles_x, tiles_per_slot;
   int64_t n_tiles;
   float bg0, bg1, bg2;
-  // deterministic backward (NULL dup_grads: atomics into d_rec)
-  const uint2* tile_bbox;
-  const uint32_t* pair_first;
+  // deterministic backward (NULL dup_grads: atomics into d_rec): emit[q]
+  // is the emission index (gradient slot) of sorted entry q
+  const uint32_t* emit;
   float* dup_grads;
   int64_t dup_cap;
 };
 
-// Emission index of pair `id`'s entry for tile (tx, ty): its tiles are
-// emitted row-major over its tile bbox starting at pair_first[id].
-__device__ __forceinline__ uint32_t emission_index(const RasterDev& a, uint32_t id, int tx, int ty) {
-  const uint2 bb = a.tile_bbox[id];
-  const int tx0 = (int)(bb.x & 0xffffu), ty0 = (int)(bb.x >> 16), tx1 = (int)(bb.y & 0xffffu);
-  return a.pair_first[id] + (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
-}
-
 // Deterministic mode: zero the gradient slots of list indices [lo, hi) of a
 // tile (entries no pixel reaches), one entry per lane.
-__device__ __forceinline__ void zero_dup_slots(const RasterDev& a, uint32_t start, int lo, int hi,
-                                               int tx, int ty) {
+__device__ __forceinline__ void zero_dup_slots(const RasterDev& a, uint32_t start, int lo, int hi) {
   const int lane = threadIdx.x & (kRasterWave - 1);
   for (int q = lo + lane; q < hi; q += kRasterWave) {
-    const uint32_t e = emission_index(a, a.ids[start + q], tx, ty);
+    const uint32_t e = a.emit[start + q];
     if ((int64_t)e >= a.dup_cap) continue;
     float* g = a.dup_grads + (int64_t)e * GS_DREC_STRIDE;
 #pragma unroll
@@ -425,8 +416,7 @@ __device__ __forceinline__ void reverse_pass(const RasterDev& a, uint32_t start,
                                              const float fx, const float* fy, const int* last,
                                              float* T, float (*dI)[3], float* dIacc,
                                              Splat* s_splat, uint32_t* s_id,
-                                             float* __restrict__ d_rec, const Scatter9& red,
-                                             int tx, int ty) {
+                                             float* __restrict__ d_rec, const Scatter9& red) {
   constexpr int PX = TileGeom<TW, TH>::PX;
   const int lane = threadIdx.x;
   const bool det = a.dup_grads != nullptr;
@@ -437,7 +427,7 @@ __device__ __forceinline__ void reverse_pass(const RasterDev& a, uint32_t start,
     __syncthreads();
     if (lane < n) {
       const uint32_t id = a.ids[start + bot + lane];
-      s_id[lane] = det ? emission_index(a, id, tx, ty) : id;
+      s_id[lane] = det ? a.emit[start + bot + lane] : id;
       s_splat[lane] = load_splat(a.rec, id);
     }
     __syncthreads();
@@ -575,8 +565,8 @@ __device__ __forceinline__ void bwd_tile(const RasterDev& a, int64_t tile, Splat
   for (int k = 0; k < PX; ++k) lmax = max(lmax, last[k]);
   lmax = min(wave_max_int(lmax), (int)(end - start));
   reverse_pass<TW, TH>(a, start, 0, lmax, L.fx, L.fy, last, T, dI, dIacc, s_splat, s_id, d_rec,
-                       scatter9_setup(), L.tx, L.ty);
-  if (a.dup_grads) zero_dup_slots(a, start, lmax, (int)(end - start), L.tx, L.ty);
+                       scatter9_setup());
+  if (a.dup_grads) zero_dup_slots(a, start, lmax, (int)(end - start));
 }
 
 template <int TW, int TH, bool RECOMPUTE>
@@ -623,7 +613,7 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd_chunked(
   }
   const int hi = min(wave_max_int(lmax), hi_pos);
   if (hi <= lo) {
-    if (a.dup_grads) zero_dup_slots(a, start, lo, hi_pos, L.tx, L.ty);
+    if (a.dup_grads) zero_dup_slots(a, start, lo, hi_pos);
     return;
   }
   const float4* ck = ch.ck + ((int64_t)ch.offset[tile] + c) * (TW * TH);
@@ -646,8 +636,8 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd_chunked(
     }
   }
   reverse_pass<TW, TH>(a, start, lo, hi, L.fx, L.fy, last, T, dI, dIacc, s_splat, s_id, d_rec,
-                       scatter9_setup(), L.tx, L.ty);
-  if (a.dup_grads) zero_dup_slots(a, start, hi, hi_pos, L.tx, L.ty);
+                       scatter9_setup());
+  if (a.dup_grads) zero_dup_slots(a, start, hi, hi_pos);
 }
 
 // ---------------------------------------------------------------- tile order
@@ -756,27 +746,25 @@ __global__ __launch_bounds__(256) void k_chunk_items(const uint32_t* __restrict_
 
 // ---------------------------------------------------------------- deterministic sum
 
-// d_rec[p] += sum of pair p's emission slots, in emission order.
+// d_rec[p][c] += sum over pair p's emission slots of component c, in
+// emission order; one thread per (pair, component), so the 9 threads of a
+// pair read its slots' 36-byte records together.
 __global__ __launch_bounds__(256) void k_dup_reduce(const int32_t* __restrict__ n_tiles,
                                                     const uint32_t* __restrict__ pair_first,
                                                     int64_t m, const float* __restrict__ dup,
                                                     int64_t dup_cap, float* __restrict__ d_rec) {
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t p = i / GS_DREC_STRIDE;
+  const int c = (int)(i - p * GS_DREC_STRIDE);
   if (p >= m) return;
   const int nt = n_tiles[p];
   if (nt <= 0) return;
   const int64_t e0 = pair_first[p];
   if (e0 + nt > dup_cap) return;
-  const float* g = dup + e0 * GS_DREC_STRIDE;
-  float acc[GS_DREC_STRIDE];
-#pragma unroll
-  for (int c = 0; c < GS_DREC_STRIDE; ++c) acc[c] = 0.0f;
-  for (int k = 0; k < nt; ++k)
-#pragma unroll
-    for (int c = 0; c < GS_DREC_STRIDE; ++c) acc[c] += g[k * GS_DREC_STRIDE + c];
-  float* d = d_rec + p * GS_DREC_STRIDE;
-#pragma unroll
-  for (int c = 0; c < GS_DREC_STRIDE; ++c) d[c] += acc[c];
+  const float* g = dup + e0 * GS_DREC_STRIDE + c;
+  float acc = 0.0f;
+  for (int k = 0; k < nt; ++k) acc += g[k * GS_DREC_STRIDE];
+  d_rec[p * GS_DREC_STRIDE + c] += acc;
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -880,8 +868,7 @@ static gs_status raster_prepare(const gs_projected* proj, const gs_views* views,
   a.bg0 = bg[0];
   a.bg1 = bg[1];
   a.bg2 = bg[2];
-  a.tile_bbox = reinterpret_cast<const uint2*>(proj->tile_bbox);
-  a.pair_first = nullptr;
+  a.emit = nullptr;
   a.dup_grads = nullptr;
   a.dup_cap = 0;
   return GS_OK;
@@ -1016,9 +1003,9 @@ gs_status gs_raster_bwd(const gs_projected* proj, const gs_views* views, const g
   hipStream_t s = as_stream(stream);
   const bool det = plan && plan->dup_grads;
   if (det) {
-    GS_REQUIRE(plan->pair_first && plan->dup_capacity > 0 && proj->tile_bbox && proj->n_tiles,
-               "gs_raster_bwd: deterministic mode needs pair_first, dup_capacity, tile_bbox, n_tiles");
-    a.pair_first = plan->pair_first;
+    GS_REQUIRE(plan->pair_first && plan->emit_idx && plan->dup_capacity > 0 && proj->n_tiles,
+               "gs_raster_bwd: deterministic mode needs pair_first, emit_idx, dup_capacity, n_tiles");
+    a.emit = plan->emit_idx;
     a.dup_grads = plan->dup_grads;
     a.dup_cap = plan->dup_capacity;
   }
@@ -1033,7 +1020,8 @@ gs_status gs_raster_bwd(const gs_projected* proj, const gs_views* views, const g
 #undef GS_BWD_CASE
   GS_LAUNCH_CHECK("gs_raster_bwd");
   if (det && proj->m > 0) {
-    hipLaunchKernelGGL(k_dup_reduce, dim3((unsigned)ceil_div(proj->m, 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_dup_reduce, dim3((unsigned)ceil_div(proj->m * GS_DREC_STRIDE, 256)),
+                       dim3(256), 0, s,
                        proj->n_tiles, plan->pair_first, proj->m, plan->dup_grads,
                        plan->dup_capacity, d_rec);
     GS_LAUNCH_CHECK("gs_raster_bwd/reduce");

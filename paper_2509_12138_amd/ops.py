@@ -148,6 +148,7 @@ class RasterBuffers:
         self.dup_capacity = cap
         self.keys = torch.empty(cap, dtype=torch.int64, device=dev)
         self.ids = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.emit = torch.empty(cap, dtype=torch.int32, device=dev)
         nbytes = _lib.load().gs_bin_sort_workspace_bytes(self.m, cap, C.byref(self.tiling),
                                                          self.S)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -167,7 +168,8 @@ class RasterBuffers:
         s = stream or stream_handle()
         call("gs_bin_sort", C.byref(self.proj), C.byref(self.views.struct), C.byref(self.tiling),
              self.dup_capacity, _ptr(self.ws), self.ws.numel(), _ptr(self.keys), _ptr(self.ids),
-             _ptr(self.ranges), _ptr(self.pair_first), _ptr(self.status), s)
+             _ptr(self.ranges), _ptr(self.pair_first),
+             _ptr(self.emit) if self.deterministic else None, _ptr(self.status), s)
 
     # ---------------------------------------------------------- tile schedule
 
@@ -213,6 +215,7 @@ class RasterBuffers:
         self.plan.dup_grads = self.dup_grads.data_ptr()
         self.plan.pair_first = self.pair_first.data_ptr()
         self.plan.dup_capacity = self.dup_capacity
+        self.plan.emit_idx = self.emit.data_ptr()
 
     def _alloc_chunks(self):
         dev = self.views.device

@@ -22,14 +22,17 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {"k_raster_bwd_chunked": "raster.hip", "k_raster_bwd": "raster.hip",
-                  "k_raster_fwd": "raster.hip"}
+                  "k_raster_fwd": "raster.hip", "k_dup_reduce": "raster.hip"}
 COPY_BYTES = 512 * 1024 * 1024
 
 
-def source_hash(kernel):
-    path = os.path.join(HERE, "csrc", KERNEL_SOURCES[kernel])
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_hash(kernels):
+    """Hash of the source files of a '+'-joined list of kernels."""
+    h = hashlib.sha256()
+    for src in sorted({KERNEL_SOURCES[k] for k in kernels.split("+")}):
+        with open(os.path.join(HERE, "csrc", src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def counter_kib(path, kernel_prefix, counter):
@@ -52,7 +55,8 @@ def copy_factor(path, counter):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--kernel", required=True,
+                    help="kernel name, or several joined by '+' (bytes are summed per launch)")
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
     ap.add_argument("--copy-fetch", required=True)
@@ -62,8 +66,15 @@ def main(argv=None):
     ap.add_argument("--command", default="", help="the command the counters were taken on")
     ap.add_argument("--out", required=True)
     a = ap.parse_args(argv)
-    f_kib, nf = counter_kib(a.fetch, a.kernel, "FETCH_SIZE")
-    w_kib, nw = counter_kib(a.write, a.kernel, "WRITE_SIZE")
+    f_kib = w_kib = 0.0
+    nf = nw = []
+    for k in a.kernel.split("+"):
+        fk, n1 = counter_kib(a.fetch, k, "FETCH_SIZE")
+        wk, n2 = counter_kib(a.write, k, "WRITE_SIZE")
+        f_kib += fk
+        w_kib += wk
+        nf = nf + [n1]
+        nw = nw + [n2]
     ff = copy_factor(a.copy_fetch, "FETCH_SIZE")
     fw = copy_factor(a.copy_write, "WRITE_SIZE")
     entry = dict(kernel=a.kernel, plan=a.plan, source_sha256_16=source_hash(a.kernel),
