@@ -210,7 +210,8 @@ def main():
         max(stage_ms, key=stage_ms.get)
     if dom == "raster_bwd":
         achieved = evals_bwd * OPS_PER_EVAL_BWD / (t_bwd * 1e-3)
-        kname = "k_raster_bwd_chunked" if chunk else "k_raster_bwd"
+        kname = (f"k_raster_bwd_chunked<{tile[0]}, {tile[1]}>" if chunk else
+                 f"k_raster_bwd<{tile[0]}, {tile[1]}, {'true' if args.recompute else 'false'}>")
         if deterministic:
             kname += "+k_dup_reduce"          # both run inside the timed gs_raster_bwd call
         roof = {"kernel": kname, "bound": "alu", "achieved": achieved / 1e12,
@@ -219,7 +220,8 @@ def main():
                 "unit_desc": f"{OPS_PER_EVAL_BWD} FP32 VALU issue slots per evaluated (pixel, entry)"}
     else:
         achieved = evals_fwd * OPS_PER_EVAL_FWD / (t_fwd * 1e-3)
-        roof = {"kernel": "k_raster_fwd", "bound": "alu", "achieved": achieved / 1e12,
+        roof = {"kernel": f"k_raster_fwd<{tile[0]}, {tile[1]}, {fwd_waves}>", "bound": "alu",
+                "achieved": achieved / 1e12,
                 "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
                 "traffic": None, "units_per_launch": evals_fwd,
                 "unit_desc": f"{OPS_PER_EVAL_FWD} FP32 VALU issue slots per evaluated (pixel, entry)"}

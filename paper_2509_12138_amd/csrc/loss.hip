@@ -2,6 +2,7 @@
 // gradient (masks: the paper's Sec. II "Image Rendering and Masking" and
 // Sec. III-A; L1 + D-SSIM: the 3D-GS training loss it trains with).
 //
+// One work-group per (image, channel, 32x32 output tile).
 // k_ssim_fwd  per 32x32 output tile and channel: stage the masked image and
 //             target (+5 px halo, zero outside the image) in LDS, blur the
 //             five moment maps with the separable 11-tap window, form the
@@ -52,7 +53,7 @@ static LossLayout loss_layout(int S, int H, int W) {
   L.off_maps = 0;
   size_t maps = sizeof(float) * 9 * (size_t)S * H * W;
   L.off_part = (maps + 255) & ~size_t(255);
-  size_t part = sizeof(float) * 2 * (size_t)S * L.blocks_per_img;
+  size_t part = sizeof(float) * 2 * 3 * (size_t)S * L.blocks_per_img;
   L.total = L.off_part + ((part + 255) & ~size_t(255));
   return L;
 }
@@ -65,14 +66,16 @@ __global__ __launch_bounds__(kLThreads) void k_ssim_fwd(
   __shared__ float s_y[kLIn][kLIn + 1];
   __shared__ float s_h[5][kLIn][kLT + 1];
   __shared__ float s_red[2][4];
-  const int64_t img = blockIdx.x / blocks_per_img;
-  const int64_t b = blockIdx.x - img * blocks_per_img;
+  const int64_t ic = blockIdx.x / blocks_per_img;          // image * 3 + channel
+  const int64_t img = ic / 3;
+  const int ch = (int)(ic - img * 3);
+  const int64_t b = blockIdx.x - ic * blocks_per_img;
   const int ty = (int)(b / tiles_x), tx = (int)(b - (int64_t)ty * tiles_x);
   const int x0 = tx * kLT - kLR, y0 = ty * kLT - kLR;
   const int t = threadIdx.x;
   const int64_t HW = (int64_t)H * W;
   float ssum = 0.f, l1sum = 0.f;
-  for (int ch = 0; ch < 3; ++ch) {
+  {
     const float* I = image + (img * 3 + ch) * HW;
     const float* G = target + (img * 3 + ch) * HW;
     for (int i = t; i < kLIn * kLIn; i += kLThreads) {
@@ -138,7 +141,6 @@ __global__ __launch_bounds__(kLThreads) void k_ssim_fwd(
         mp[2 * HW + o] = 2.f * A1 * iB;
       }
     }
-    __syncthreads();
   }
   // block sums
   ssum = wave_sum(ssum);
@@ -161,13 +163,15 @@ __global__ __launch_bounds__(kLThreads) void k_ssim_bwd(
     float* __restrict__ d_image) {
   __shared__ float s_m[3][kLIn][kLIn + 1];
   __shared__ float s_h[3][kLIn][kLT + 1];
-  const int64_t img = blockIdx.x / blocks_per_img;
-  const int64_t b = blockIdx.x - img * blocks_per_img;
+  const int64_t ic = blockIdx.x / blocks_per_img;          // image * 3 + channel
+  const int64_t img = ic / 3;
+  const int ch = (int)(ic - img * 3);
+  const int64_t b = blockIdx.x - ic * blocks_per_img;
   const int ty = (int)(b / tiles_x), tx = (int)(b - (int64_t)ty * tiles_x);
   const int x0 = tx * kLT - kLR, y0 = ty * kLT - kLR;
   const int t = threadIdx.x;
   const int64_t HW = (int64_t)H * W;
-  for (int ch = 0; ch < 3; ++ch) {
+  {
     const float* mp = maps + (img * 9 + ch * 3) * HW;
     for (int i = t; i < kLIn * kLIn; i += kLThreads) {
       const int r = i / kLIn, c = i - r * kLIn;
@@ -219,7 +223,6 @@ __global__ __launch_bounds__(kLThreads) void k_ssim_bwd(
       const float sg = diff > 0.f ? 1.f : (diff < 0.f ? -1.f : 0.f);
       D[o] = mk * (l1_coef * sg - ssim_coef * gs);
     }
-    __syncthreads();
   }
 }
 
@@ -230,9 +233,9 @@ __global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ pa
   __shared__ double sm[2][256];
   const int64_t img = blockIdx.x;
   double s = 0.0, l = 0.0;
-  for (int64_t b = threadIdx.x; b < blocks_per_img; b += 256) {
-    s += (double)part[2 * (img * blocks_per_img + b)];
-    l += (double)part[2 * (img * blocks_per_img + b) + 1];
+  for (int64_t b = threadIdx.x; b < 3 * blocks_per_img; b += 256) {
+    s += (double)part[2 * (img * 3 * blocks_per_img + b)];
+    l += (double)part[2 * (img * 3 * blocks_per_img + b) + 1];
   }
   sm[0][threadIdx.x] = s;
   sm[1][threadIdx.x] = l;
@@ -279,7 +282,7 @@ gs_status gs_loss(const float* image, const float* target, const uint8_t* mask, 
   float* maps = (float*)(w + L.off_maps);
   float* part = (float*)(w + L.off_part);
   const Window win = ssim_window();
-  const int64_t blocks = (int64_t)S * L.blocks_per_img;
+  const int64_t blocks = (int64_t)S * 3 * L.blocks_per_img;
   hipStream_t s = as_stream(stream);
   hipLaunchKernelGGL(k_ssim_fwd, dim3((unsigned)blocks), dim3(kLThreads), 0, s, image, target,
                      mask, H, W, L.tiles_x, L.blocks_per_img, win, maps, part);

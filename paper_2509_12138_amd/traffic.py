@@ -29,19 +29,24 @@ COPY_BYTES = 512 * 1024 * 1024
 def source_hash(kernels):
     """Hash of the source files of a '+'-joined list of kernels."""
     h = hashlib.sha256()
-    for src in sorted({KERNEL_SOURCES[k] for k in kernels.split("+")}):
+    for src in sorted({KERNEL_SOURCES[k.split("<")[0]] for k in kernels.split("+")}):
         with open(os.path.join(HERE, "csrc", src), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def counter_kib(path, kernel_prefix, counter):
+def counter_kib(path, kernel, counter):
+    """Mean counter value over the dispatches of `kernel`: a plain name
+    matches every instantiation, a name with template arguments (e.g.
+    "k_raster_fwd<16, 16, 4>") only that one."""
     vals = []
+    want = kernel.replace(" ", "")
     with open(path) as f:
         for r in csv.DictReader(f):
             name = r["Kernel_Name"].split("(")[0].replace("void ", "").strip()
-            base = name.split("::")[-1].split("<")[0]
-            if base == kernel_prefix and r["Counter_Name"] == counter:
+            full = name.split("::")[-1].replace(" ", "")
+            base = full.split("<")[0]
+            if (full == want if "<" in want else base == want) and r["Counter_Name"] == counter:
                 vals.append(float(r["Counter_Value"]))
     if not vals:
         raise SystemExit(f"no {counter} samples for {kernel_prefix} in {path}")
