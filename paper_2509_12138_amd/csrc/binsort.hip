@@ -28,9 +28,12 @@ constexpr int kScanThreads = 256;
 constexpr int kScanPer = 8;
 constexpr int kScanItems = kScanThreads * kScanPer;   // pairs per scan/emit block
 constexpr int kSortThreads = 256;
-constexpr int kSortPer = 16;
+constexpr int kSortPer = 8;
 constexpr int kSortItems = kSortThreads * kSortPer;   // keys per radix block
 constexpr int kRadixBits = 8;
+// presort key fields: depth bits 0-31, slot 32-41, tile count 42-63
+constexpr int kKeySlotShift = 32, kKeyTilesShift = 42;
+constexpr uint64_t kKeySlotMask = (1ull << (kKeyTilesShift - kKeySlotShift)) - 1;
 constexpr int kRadix = 1 << kRadixBits;
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -99,9 +102,9 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sm_waves /*[4]*/, T& t
 
 // ------------------------------------------------------------ scan of n_tiles
 
-// Pairs are visited in the order perm[0..m) (the depth order).
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __restrict__ n_tiles,
-                                                              const uint32_t* __restrict__ perm,
+// Pairs in depth order: their tile counts are the top bits of the presorted
+// keys.
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint64_t* __restrict__ pkey,
                                                               int64_t m,
                                                               int64_t* __restrict__ block_sums) {
   __shared__ int64_t sm[4];
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __r
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
     int64_t i = base + k * kScanThreads + threadIdx.x;
-    if (i < m) sum += max(n_tiles[perm[i]], 0);
+    if (i < m) sum += (int64_t)(pkey[i] >> kKeyTilesShift);
   }
   int64_t total;
   block_exclusive_scan<int64_t>(sum, sm, total);
@@ -145,9 +148,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t* __restrict__
 // ------------------------------------------------------------ emit
 
 // Block b handles depth-ordered positions b*kScanItems ...: pair perm[i]
-// with presorted key pkey[i] = (slot << 32) | depth bits.
+// with presorted key pkey[i] = (n_tiles << 42) | (slot << 32) | depth bits.
 __global__ __launch_bounds__(kScanThreads) void k_emit(
-    const int32_t* __restrict__ n_tiles, const uint2* __restrict__ tile_bbox,
+    const uint2* __restrict__ tile_bbox,
     const uint64_t* __restrict__ pkey, const uint32_t* __restrict__ perm, int64_t m,
     const int64_t* __restrict__ block_offsets, int64_t cap, int tiles_x, int tiles_per_slot,
     uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ pair_first,
@@ -167,13 +170,13 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
     int64_t i = base + li;
     int nt = 0;
     if (i < m) {
-      const uint32_t p = perm[i];
-      nt = max(n_tiles[p], 0);
+      const uint64_t key = pkey[i];
+      nt = (int)(key >> kKeyTilesShift);
       if (nt > 0) {
-        const uint64_t key = pkey[i];
+        const uint32_t p = perm[i];
         s_bbox[li] = tile_bbox[p];
         s_depth[li] = (uint32_t)key;
-        s_slot[li] = (uint32_t)(key >> 32);
+        s_slot[li] = (uint32_t)((key >> kKeySlotShift) & kKeySlotMask);
         s_pair[li] = p;
       }
     }
@@ -230,16 +233,21 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
 
 // ------------------------------------------------------------ depth presort
 
-// key = (slot << 32) | depth bits, value = pair index; count[0] = m.
-// Depths of visible pairs are positive, so their bits order as the floats.
-__global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ rec, int64_t m,
+// key = (n_tiles << 42) | (slot << 32) | depth bits, value = pair index;
+// count[0] = m.  Depths of visible pairs are positive, so their bits order
+// as the floats; the passes sort the low 32 bits only, the pair's tile count
+// and slot ride along for the scan and the emission.
+__global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ rec,
+                                                   const int32_t* __restrict__ n_tiles, int64_t m,
                                                    uint64_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals,
                                                    int64_t* __restrict__ count) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i == 0) count[0] = m;
   if (i >= m) return;
-  keys[i] = ((uint64_t)__float_as_uint(rec[i * GS_REC_STRIDE + 10]) << 32) |
+  const uint64_t nt = (uint64_t)max(n_tiles[i], 0);
+  keys[i] = (nt << kKeyTilesShift) |
+            ((uint64_t)__float_as_uint(rec[i * GS_REC_STRIDE + 10]) << kKeySlotShift) |
             (uint64_t)__float_as_uint(rec[i * GS_REC_STRIDE + 9]);
   vals[i] = (uint32_t)i;
 }
@@ -293,10 +301,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     int shift, int64_t nb, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ row_tot,
     const uint32_t* __restrict__ vin2, uint32_t* __restrict__ vout2) {
   // LDS: per (round, wave, digit) counts; staging of the block's items
-  __shared__ uint16_t s_cnt[kSortPer][4][kRadix];   // 32 KB
-  __shared__ uint64_t s_key[kSortItems];             // 32 KB
-  __shared__ uint32_t s_val[kSortItems];             // 16 KB
-  __shared__ uint32_t s_val2[kSortItems];            // 16 KB
+  __shared__ uint16_t s_cnt[kSortPer][4][kRadix];   // 16 KB
+  __shared__ uint64_t s_key[kSortItems];             // 16 KB
+  __shared__ uint32_t s_val[kSortItems];             // 8 KB
+  __shared__ uint32_t s_val2[kSortItems];            // 8 KB
   __shared__ uint32_t s_dstart[kRadix];              // local digit starts
   __shared__ uint32_t s_gbase[kRadix];               // global digit base of this block
   __shared__ uint32_t s_w[4];
@@ -439,6 +447,9 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   const int tiles_y = (int)ceil_div(tiling->height, tiling->tile_h);
   const int64_t tiles_per_slot = (int64_t)tiles_x * tiles_y;
   const int64_t n_tiles_all = tiles_per_slot * views->n_slots;
+  GS_REQUIRE(tiles_per_slot < (int64_t(1) << (64 - kKeyTilesShift)) && views->n_slots <= (int)kKeySlotMask + 1,
+             "gs_bin_sort: %lld tiles per slot or %d slots exceed the key fields",
+             (long long)tiles_per_slot, views->n_slots);
   // passes over the tile bits of the keys (the depth order comes from the
   // presort of the pairs)
   int tile_bits = 0;
@@ -470,8 +481,8 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   uint64_t* pk[2] = {(uint64_t*)(w + L.off_pkeys[0]), (uint64_t*)(w + L.off_pkeys[1])};
   uint32_t* pv[2] = {(uint32_t*)(w + L.off_pvals[0]), (uint32_t*)(w + L.off_pvals[1])};
   int64_t* count_pairs = count + 1;
-  hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, proj->rec, m,
-                     pk[0], pv[0], count_pairs);
+  hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, proj->rec,
+                     proj->n_tiles, m, pk[0], pv[0], count_pairs);
   GS_LAUNCH_CHECK("gs_bin_sort/depth_keys");
   for (int p = 0; p < 4; ++p) {
     const int shift = p * kRadixBits;
@@ -487,13 +498,13 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
     GS_LAUNCH_CHECK("gs_bin_sort/depth_scatter");
   }
   // duplicates in depth order, then stable passes over the tile bits only
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s,
-                     proj->n_tiles, pv[0], m, block_sums);
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s, pk[0], m,
+                     block_sums);
   GS_LAUNCH_CHECK("gs_bin_sort/scan_reduce");
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, block_sums, L.nb_scan,
                      dup_capacity, status, count);
   GS_LAUNCH_CHECK("gs_bin_sort/scan_top");
-  hipLaunchKernelGGL(k_emit, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s, proj->n_tiles,
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s,
                      (const uint2*)proj->tile_bbox, pk[0], pv[0], m, block_sums, dup_capacity,
                      tiles_x, (int)tiles_per_slot, k0, v0, pair_first, e0);
   GS_LAUNCH_CHECK("gs_bin_sort/emit");

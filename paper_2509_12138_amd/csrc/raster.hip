@@ -6,10 +6,9 @@
 // evaluations and the backward's wave reduction is amortised over 256
 // pixels.  Gaussians are staged 64 at a time (one gathered record per lane).
 // The forward can also split a tile's pixels over 2 or 4 waves of one
-// work-group (the waves walk the list together on one shared LDS batch, each
-// compositing its own rows): all tiles of a 1080p view are resident at once,
-// so the forward's time is set by its longest lists, and more waves per tile
-// shorten them.
+// work-group (each wave walks the whole list for its rows, with its own LDS
+// batch): all tiles of a 1080p view are resident at once, so the forward's
+// time is set by its longest lists, and more waves per tile shorten them.
 // Work-group ids are remapped so that neighbouring tiles run on the same
 // XCD and share its L2.
 //
@@ -76,21 +75,15 @@ __device__ __forceinline__ void wave_sync() {
 // built without cancellation from chunk-local composites (P = prod(1-alpha),
 // L = sum rgb alpha T_local over a chunk) by U_c = L_{c+1} + P_{c+1} U_{c+1}
 // after the tile is done.
-// NW > 1: the NW waves of the work-group walk the list together, sharing one
-// LDS batch that each wave loads a 64/NW-entry part of; a wave whose pixels
-// are all done skips the compositing and the block stops when all are done
-// (s_done: NW flags in LDS).
-template <int TW, int TH, int PX, bool WITH_COLOR, bool CHUNKED = false, int NW = 1>
+template <int TW, int TH, int PX, bool WITH_COLOR, bool CHUNKED = false>
 __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
                                              const uint32_t* __restrict__ ids, uint32_t start,
                                              uint32_t end, const float fx, const float* fy,
                                              const bool* inside, Splat* s_splat, float* T,
                                              float (*C)[3], int* last, float4* ck = nullptr,
                                              int chunk = 0, float bg0 = 0.f, float bg1 = 0.f,
-                                             float bg2 = 0.f, int kbase = 0,
-                                             int* s_done = nullptr) {
+                                             float bg2 = 0.f, int kbase = 0) {
   const int lane = threadIdx.x & (kRasterWave - 1);
-  const int wave = threadIdx.x / kRasterWave;
   bool done[PX];
   float Tl[PX], Lc[PX][3];
 #pragma unroll
@@ -109,27 +102,12 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
     bool lane_done = true;
 #pragma unroll
     for (int k = 0; k < PX; ++k) lane_done = lane_done && done[k];
-    const bool wave_done = __all(lane_done);
+    if (__all(lane_done)) break;
     const int n = (int)min((uint32_t)kRasterWave, end - b0);
-    if constexpr (NW > 1) {
-      if (lane == 0) s_done[wave] = wave_done;
-      __syncthreads();
-      bool all_done = true;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) all_done = all_done && s_done[w];
-      if (all_done) break;
-      __syncthreads();
-      constexpr int PART = kRasterWave / NW;
-      const int e = wave * PART + lane;
-      if (lane < PART && e < n) s_splat[e] = load_splat(rec, ids[b0 + e]);
-      __syncthreads();
-    } else {
-      if (wave_done) break;
-      wave_sync();
-      if (lane < n) s_splat[lane] = load_splat(rec, ids[b0 + lane]);
-      wave_sync();
-    }
-    for (int j = 0; j < (wave_done ? 0 : n); ++j) {
+    wave_sync();
+    if (lane < n) s_splat[lane] = load_splat(rec, ids[b0 + lane]);
+    wave_sync();
+    for (int j = 0; j < n; ++j) {
       const Splat sp = s_splat[j];
       const float dx = __fsub_rn(fx, sp.mx);
       float p2[PX];
@@ -288,7 +266,7 @@ __device__ __forceinline__ void for_each_tile(const TileSched& sch, int64_t n_ti
 // slots lane + 64 k for k in [wave PX, (wave + 1) PX), PX = TW TH / (64 NW).
 template <int TW, int TH, int NW>
 __device__ __forceinline__ void fwd_tile(const RasterDev& a, const ChunkDev& ch, int64_t tile,
-                                         Splat* s_splat, int* s_done, float* __restrict__ image,
+                                         Splat* s_splat, float* __restrict__ image,
                                          float* __restrict__ T_final,
                                          int32_t* __restrict__ n_contrib) {
   constexpr int PX = TileGeom<TW, TH>::PX / NW, RSTEP = TileGeom<TW, TH>::RSTEP;
@@ -315,12 +293,10 @@ __device__ __forceinline__ void fwd_tile(const RasterDev& a, const ChunkDev& ch,
   int last[PX];
   if (ch.ck) {
     float4* ck = ch.ck + (int64_t)ch.offset[tile] * (TW * TH);
-    tile_forward<TW, TH, PX, true, true, NW>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T,
-                                             C, last, ck, ch.chunk, a.bg0, a.bg1, a.bg2, kbase,
-                                             s_done);
+    tile_forward<TW, TH, PX, true, true>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T, C,
+                                         last, ck, ch.chunk, a.bg0, a.bg1, a.bg2, kbase);
   } else {
-    tile_forward<TW, TH, PX, true, false, NW>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T,
-                                              C, last, nullptr, 0, 0.f, 0.f, 0.f, kbase, s_done);
+    tile_forward<TW, TH, PX, true>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T, C, last);
   }
   const int64_t HW = (int64_t)H * W;
   float* img = image + (int64_t)slot * 3 * HW;
@@ -342,10 +318,10 @@ __global__ __launch_bounds__(kRasterWave * NW) void k_raster_fwd(RasterDev a, Ti
                                                                  float* __restrict__ image,
                                                                  float* __restrict__ T_final,
                                                                  int32_t* __restrict__ n_contrib) {
-  __shared__ Splat s_splat[kRasterWave];
-  __shared__ int s_done[NW];
+  __shared__ Splat s_splat[kRasterWave * NW];
+  Splat* mine = s_splat + (threadIdx.x / kRasterWave) * kRasterWave;
   for_each_tile(sch, a.n_tiles, [&](int64_t tile) {
-    fwd_tile<TW, TH, NW>(a, ch, tile, s_splat, s_done, image, T_final, n_contrib);
+    fwd_tile<TW, TH, NW>(a, ch, tile, mine, image, T_final, n_contrib);
   });
 }
 

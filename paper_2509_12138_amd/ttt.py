@@ -208,8 +208,12 @@ def cmd_batched(a):
     del rb["trainer"]
     torch.cuda.empty_cache()
     plain = []
+    # the plain arm: one partition after another, one view per step; by
+    # default with the same rasteriser plan, --plain-plan default gives it the
+    # untuned one-work-group-per-tile plan
+    plain_plan = ((16, 16), "default", 0, 1, False) if a.plain_plan == "default" else a.plan
     for i, part in enumerate(parts):
-        r = run_plain(part, cams, a.target, a.steps * a.vpp, a.eval_every * a.vpp, plan=a.plan,
+        r = run_plain(part, cams, a.target, a.steps * a.vpp, a.eval_every * a.vpp, plan=plain_plan,
                       seed=i)
         del r["trainer"]
         torch.cuda.empty_cache()
@@ -217,6 +221,7 @@ def cmd_batched(a):
             f"psnr {r['psnr']}")
         plain.append(r)
     res = dict(experiment="batched_vs_plain", counts=[p["n"] for p in parts], target=a.target,
+               plan=list(a.plan), plain_plan=list(plain_plan),
                views=a.views, width=a.width, height=a.height, views_per_part=a.vpp,
                batched=dict(init_seconds=rb["init_seconds"], reached=rb["reached"],
                             history=rb["history"]),
@@ -328,6 +333,7 @@ def main(argv=None):
     ap.add_argument("--vpp", type=int, default=4)
     ap.add_argument("--ref-factor", type=float, default=2.0)
     ap.add_argument("--field", choices=["sphere", "mixing"], default="sphere")
+    ap.add_argument("--plain-plan", choices=["same", "default"], default="same")
     ap.add_argument("--fit-steps", type=int, default=2000)
     ap.add_argument("--mlp-steps", type=int, default=2000)
     ap.add_argument("--tile", default="16x16")
