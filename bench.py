@@ -30,8 +30,9 @@ sys.path.insert(0, ROOT)
 METRIC = "fwd+bwd raster Mpix/s; train iters/s at 1080p; secs to 35 dB PSNR vs plain"
 PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9          # FP32 lane-ops/s without packed math
 PEAK_HBM = 8.0e12
-# algorithmic VALU issue slots per evaluated (pixel, list entry) pair
-# (transcendentals count 4); see the design notes for the derivation
+# algorithmic VALU issue slots per blended (pixel, Gaussian) pair, the work
+# an exact rasteriser cannot avoid (transcendentals count 4); see the design
+# notes for the derivation
 OPS_PER_EVAL_FWD = 22
 OPS_PER_EVAL_BWD = 50
 
@@ -189,23 +190,24 @@ def main():
     ms_per_step = wall * 1000.0 / args.steps
     mpix = W * H / ((t_fwd + t_bwd) * 1e-3) / 1e6
 
-    # algorithmic evaluation counts of the last step's view (replayed once, untimed)
+    # algorithmic work of the last step's view (replayed once, untimed): the
+    # blended (pixel, Gaussian) pairs, counted with the forward's decisions
     last_view = int(order[args.warmup + args.steps - 1])
     tr.views.use_cameras(tr.cams[last_view:last_view + 1])
     tr.bufs.render_checked(tr.gst, tr.bg)
     import torch as _t
+    blended = float(tr.bufs.count_blended()[0].to(_t.int64).sum())
+    evals_fwd = evals_bwd = blended
+    # list positions visited before each pixel stops (what a rasteriser with
+    # no culling below the tile evaluates), reported beside it
     nc = tr.bufs.n_contrib[0].to(_t.int64)
-    evals_bwd = float(nc.sum())
     rng_t = tr.bufs.ranges.to(_t.int64)
     tile_len = (rng_t[:, 1] - rng_t[:, 0])
     tx = (_t.arange(W, device="cuda") // tile[0])
     ty = (_t.arange(H, device="cuda") // tile[1])
     tid = ty[:, None] * tr.bufs.tiles_x + tx[None, :]
-    T = tr.bufs.T_final[0]
-    # forward: pixels that stopped evaluated n_contrib+1 entries (at most the
-    # list), the others the whole tile list
-    stopped = T < 2e-4
-    evals_fwd = float(_t.where(stopped, _t.minimum(nc + 1, tile_len[tid]), tile_len[tid]).sum())
+    stopped = tr.bufs.T_final[0] < 2e-4
+    list_pairs = float(_t.where(stopped, _t.minimum(nc + 1, tile_len[tid]), tile_len[tid]).sum())
     dom = "raster_bwd" if t_bwd >= max(v for k, v in stage_ms.items() if k != "raster_bwd") else \
         max(stage_ms, key=stage_ms.get)
     if dom == "raster_bwd":
@@ -217,14 +219,14 @@ def main():
         roof = {"kernel": kname, "bound": "alu", "achieved": achieved / 1e12,
                 "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
                 "traffic": None, "units_per_launch": evals_bwd,
-                "unit_desc": f"{OPS_PER_EVAL_BWD} FP32 VALU issue slots per evaluated (pixel, entry)"}
+                "unit_desc": f"{OPS_PER_EVAL_BWD} FP32 VALU issue slots per blended (pixel, Gaussian)"}
     else:
         achieved = evals_fwd * OPS_PER_EVAL_FWD / (t_fwd * 1e-3)
         roof = {"kernel": f"k_raster_fwd<{tile[0]}, {tile[1]}, {fwd_waves}>", "bound": "alu",
                 "achieved": achieved / 1e12,
                 "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
                 "traffic": None, "units_per_launch": evals_fwd,
-                "unit_desc": f"{OPS_PER_EVAL_FWD} FP32 VALU issue slots per evaluated (pixel, entry)"}
+                "unit_desc": f"{OPS_PER_EVAL_FWD} FP32 VALU issue slots per blended (pixel, Gaussian)"}
     # HBM traffic of the dominant kernel from committed counter runs, only
     # while its source is unchanged since they were taken
     from paper_2509_12138_amd import traffic as _traffic
@@ -258,7 +260,7 @@ def main():
             "duplicates_per_view": need,
         },
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "evals": {"fwd": evals_fwd, "bwd": evals_bwd},
+        "pairs": {"blended": blended, "list_positions": list_pairs},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

@@ -282,6 +282,17 @@ gs_status gs_raster_bwd(const gs_projected* proj, const gs_views* views,
                         const float* d_image, int32_t mode, float* d_rec,
                         const gs_raster_plan* plan, void* stream);
 
+/* Measurement helper, not part of the training step: per pixel, the number
+ * of list entries the front-to-back compositing of gs_raster_fwd blends
+ * (alpha test passed, transmittance still at or above 1e-4 after it), with
+ * the same FP32 decisions.  These (pixel, Gaussian) pairs are the work an
+ * exact rasteriser cannot avoid, which prices the rasteriser's roofline.
+ * n_blend [S][H][W] int32 (device, caller-owned, fully written).  Tiles of
+ * at most 512 pixels.  Errors as gs_raster_fwd.                            */
+gs_status gs_raster_count(const gs_projected* proj, const gs_views* views,
+                          const gs_tiling* tiling, const uint32_t* ids,
+                          const uint32_t* tile_ranges, int32_t* n_blend, void* stream);
+
 /* Chain rule from d_rec back to the Gaussian parameters (sum over every
  * slot that draws the Gaussian), accumulating (+=) into grads.  Depth, the
  * support and the bboxes carry no gradient.  Deterministic (no atomics).   */

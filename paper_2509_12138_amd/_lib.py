@@ -84,6 +84,7 @@ SIGNATURES = {
                             vp, P(gs_raster_plan), vp]),
     "gs_raster_bwd": (i32, [P(gs_projected), P(gs_views), P(gs_tiling), vp, vp, P(f32), vp, vp,
                             vp, i32, vp, P(gs_raster_plan), vp]),
+    "gs_raster_count": (i32, [P(gs_projected), P(gs_views), P(gs_tiling), vp, vp, vp, vp]),
     "gs_tile_order_workspace_bytes": (sz, [i64]),
     "gs_chunk_max_items": (i64, [i64, i64, i32]),
     "gs_chunk_items": (i32, [vp, i64, i32, i64, vp, vp, vp]),

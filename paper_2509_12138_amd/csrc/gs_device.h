@@ -122,6 +122,35 @@ __device__ __forceinline__ bool splat_pass(const Splat& s, float p2) {
   return (p2 <= 0.0f) && (p2 >= s.thr);
 }
 
+// Conservative cull of a splat against the pixel centres of the box
+// [x0, x1] x [y0, y1]: false only when every centre certainly fails the
+// alpha test.  p2 is concave (A, C < 0), so its maximum over the box is 0
+// when the mean lies inside, else the largest of the four edge maxima, each
+// taken at the edge's stationary point clamped to the edge.  The margin
+// 0.02 + 4e-6 M, with M bounding the magnitudes of the three terms of p2
+// over the box, exceeds the FP32 rounding of this bound and of the
+// per-pixel p2 together, so culling never changes a pixel's decision.
+__device__ __forceinline__ bool splat_may_hit(const Splat& s, float x0, float x1, float y0,
+                                              float y1) {
+  const float dx0 = x0 - s.mx, dx1 = x1 - s.mx, dy0 = y0 - s.my, dy1 = y1 - s.my;
+  if (dx0 <= 0.0f && dx1 >= 0.0f && dy0 <= 0.0f && dy1 >= 0.0f) return true;
+  const float iA = -0.5f * __builtin_amdgcn_rcpf(s.A);    // -1 / (2A) > 0
+  const float iC = -0.5f * __builtin_amdgcn_rcpf(s.C);
+  float best = -INFINITY;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const float dy = e ? dy1 : dy0;                        // edge y = const
+    const float dx = fminf(fmaxf(s.B * dy * iA, dx0), dx1);
+    best = fmaxf(best, fmaf(fmaf(s.A, dx, s.B * dy), dx, s.C * dy * dy));
+    const float ex = e ? dx1 : dx0;                        // edge x = const
+    const float ey = fminf(fmaxf(s.B * ex * iC, dy0), dy1);
+    best = fmaxf(best, fmaf(fmaf(s.C, ey, s.B * ex), ey, s.A * ex * ex));
+  }
+  const float X = fmaxf(fabsf(dx0), fabsf(dx1)), Y = fmaxf(fabsf(dy0), fabsf(dy1));
+  const float M = fmaf(-s.A * X, X, fmaf(fabsf(s.B) * X, Y, -s.C * Y * Y));
+  return best >= s.thr - fmaf(4e-6f, M, 0.02f);
+}
+
 // Unclamped alpha o * 2^p2; __builtin_amdgcn_exp2f is the hardware v_exp_f32.
 __device__ __forceinline__ float splat_gauss(float p2) { return __builtin_amdgcn_exp2f(p2); }
 

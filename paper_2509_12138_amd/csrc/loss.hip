@@ -2,47 +2,61 @@
 // gradient (masks: the paper's Sec. II "Image Rendering and Masking" and
 // Sec. III-A; L1 + D-SSIM: the 3D-GS training loss it trains with).
 //
-// One work-group per (image, channel, 32x32 output tile).
-// k_ssim_fwd  per 32x32 output tile and channel: stage the masked image and
-//             target (+5 px halo, zero outside the image) in LDS, blur the
-//             five moment maps with the separable 11-tap window, form the
-//             SSIM map and the three per-pixel partials dS/dmu_x, dS/dE[x^2],
-//             dS/dE[xy]; write the partials, block sums of S and |x - y|.
-// k_ssim_bwd  per tile: blur the partials with the same (symmetric) window,
-//             which is the adjoint of the forward blur, and combine them
-//             with the L1 subgradient into d loss / d image.
-// k_loss_final one work-group per image: deterministic FP64 sum of the block
-//             partials -> loss[s]; non-finite losses raise the status flag.
+// One work-group per (image, channel, 32x32 output tile), one kernel for
+// the loss terms and the gradient: the masked image and target are staged
+// with a 10-pixel halo (zero outside the image); the five moment maps are
+// blurred with the separable 11-tap window over the 42x42 positions whose
+// SSIM terms reach the tile's pixels; the three per-position partials
+// dS/dmu_x, dS/dE[x^2], dS/dE[xy] (zero outside the image) are blurred again
+// with the same symmetric window, which is the adjoint of the forward blur,
+// and combined with the L1 subgradient into d loss / d image.  The block
+// sums of S and |x - y| over the tile go to a partials array;
+// k_loss_final sums them per image in FP64.  Every blur pass keeps several
+// outputs per thread in registers, so each staged value is read from LDS
+// once per thread rather than once per tap.
 #include <math.h>
 
 #include "gs_device.h"
 
 namespace gsmi {
 
-constexpr int kLT = 32;              // output tile edge
-constexpr int kLR = 5;               // window radius
-constexpr int kLIn = kLT + 2 * kLR;  // 42: staged edge
+constexpr int kLT = 32;               // output tile edge
+constexpr int kLR = 5;                // window radius
+constexpr int kLTaps = 2 * kLR + 1;
+constexpr int kLM = kLT + 2 * kLR;    // 42: positions with SSIM terms reaching the tile
+constexpr int kLS = kLM + 2 * kLR;    // 52: staged edge
 constexpr int kLThreads = 256;
+// LDS row strides (odd: consecutive rows start in different banks)
+constexpr int kLSs = kLS + 1;         // staged image / target
+constexpr int kLMs = kLM + 1;         // horizontal moments, partials
+constexpr int kLTs = kLT + 1;         // horizontal pass of the partials
+// register blocking of the four passes
+constexpr int kH1 = 3;                // moments, horizontal: 3 columns per item
+constexpr int kV1 = 7;                // moments, vertical: 7 rows per item
+constexpr int kH2 = 4;                // partials, horizontal: 4 columns per item
+constexpr int kV2 = 4;                // partials, vertical: 4 rows per item
+static_assert(kLM % kH1 == 0 && kLM % kV1 == 0 && kLT % kH2 == 0 && kLT % kV2 == 0, "blocking");
+static_assert((kLM / kV1) * kLM <= kLThreads && (kLT / kV2) * kLT == kLThreads, "blocking");
 
 struct Window {
-  float w[2 * kLR + 1];
+  float w[kLTaps];
 };
 
 static Window ssim_window() {
-  double w[2 * kLR + 1], s = 0;
-  for (int k = 0; k <= 2 * kLR; ++k) {
+  double w[kLTaps], s = 0;
+  for (int k = 0; k < kLTaps; ++k) {
     double d = k - kLR;
     w[k] = exp(-d * d / (2.0 * 1.5 * 1.5));
     s += w[k];
   }
   Window W;
-  for (int k = 0; k <= 2 * kLR; ++k) W.w[k] = (float)(w[k] / s);
+  for (int k = 0; k < kLTaps; ++k) W.w[k] = (float)(w[k] / s);
   return W;
 }
 
 struct LossLayout {
   int64_t tiles_x, tiles_y, blocks_per_img;
-  size_t off_maps, off_part, total;
+  size_t off_part, total;
 };
 
 static LossLayout loss_layout(int S, int H, int W) {
@@ -50,98 +64,238 @@ static LossLayout loss_layout(int S, int H, int W) {
   L.tiles_x = ceil_div(W, kLT);
   L.tiles_y = ceil_div(H, kLT);
   L.blocks_per_img = L.tiles_x * L.tiles_y;
-  L.off_maps = 0;
-  size_t maps = sizeof(float) * 9 * (size_t)S * H * W;
-  L.off_part = (maps + 255) & ~size_t(255);
+  L.off_part = 0;
   size_t part = sizeof(float) * 2 * 3 * (size_t)S * L.blocks_per_img;
-  L.total = L.off_part + ((part + 255) & ~size_t(255));
+  L.total = (part + 255) & ~size_t(255);
   return L;
 }
 
-__global__ __launch_bounds__(kLThreads) void k_ssim_fwd(
+// LDS: region A holds the staged image and target, later the partials;
+// region B the horizontal moment sums, later the horizontal pass of the
+// partials.
+constexpr int kLRegionA = (2 * kLS * kLSs > 3 * kLM * kLMs) ? 2 * kLS * kLSs : 3 * kLM * kLMs;
+constexpr int kLRegionB = (5 * kLS * kLMs > 3 * kLM * kLTs) ? 5 * kLS * kLMs : 3 * kLM * kLTs;
+
+template <bool MASK>
+__global__ __launch_bounds__(kLThreads) void k_ssim(
     const float* __restrict__ image, const float* __restrict__ target,
     const uint8_t* __restrict__ mask, int H, int W, int64_t tiles_x, int64_t blocks_per_img,
-    Window win, float* __restrict__ maps, float* __restrict__ part) {
-  __shared__ float s_x[kLIn][kLIn + 1];
-  __shared__ float s_y[kLIn][kLIn + 1];
-  __shared__ float s_h[5][kLIn][kLT + 1];
-  __shared__ float s_red[2][4];
+    Window win, float l1_coef, float ssim_coef, float* __restrict__ d_image,
+    float* __restrict__ part) {
+  __shared__ float sA[kLRegionA];
+  __shared__ float sB[kLRegionB];
+  __shared__ float s_red[2][kLThreads / 64];
   const int64_t ic = blockIdx.x / blocks_per_img;          // image * 3 + channel
   const int64_t img = ic / 3;
-  const int ch = (int)(ic - img * 3);
   const int64_t b = blockIdx.x - ic * blocks_per_img;
   const int ty = (int)(b / tiles_x), tx = (int)(b - (int64_t)ty * tiles_x);
-  const int x0 = tx * kLT - kLR, y0 = ty * kLT - kLR;
+  const int ox = tx * kLT, oy = ty * kLT;                  // tile origin
   const int t = threadIdx.x;
   const int64_t HW = (int64_t)H * W;
-  float ssum = 0.f, l1sum = 0.f;
+  const float* I = image + ic * HW;
+  const float* G = target + ic * HW;
+  const uint8_t* Mk = MASK ? mask + img * HW : nullptr;
+  float* s_x = sA;                  // [kLS][kLSs], staged row r = image row oy - 10 + r
+  float* s_y = sA + kLS * kLSs;
+  float* s_h = sB;                  // [5][kLS][kLMs]
+  float* s_p = sA;                  // [3][kLM][kLMs], position row r = image row oy - 5 + r
+  float* s_g = sB;                  // [3][kLM][kLTs]
+
+  // stage the masked image and target (zero outside the image).  Every
+  // load reads a clamped, valid address and the value is dropped afterwards
+  // if it lies outside, so all loads of a thread are in flight together.
+  constexpr int kStage = kLS * kLS;
+  constexpr int kStageQ = (kStage + kLThreads - 1) / kLThreads;
   {
-    const float* I = image + (img * 3 + ch) * HW;
-    const float* G = target + (img * 3 + ch) * HW;
-    for (int i = t; i < kLIn * kLIn; i += kLThreads) {
-      const int r = i / kLIn, c = i - r * kLIn;
-      const int y = y0 + r, x = x0 + c;
-      float xv = 0.f, yv = 0.f;
-      if (x >= 0 && x < W && y >= 0 && y < H) {
-        const int64_t o = (int64_t)y * W + x;
-        const float mk = mask ? (float)(mask[img * HW + o] != 0) : 1.0f;
-        xv = mk * I[o];
-        yv = mk * G[o];
-      }
-      s_x[r][c] = xv;
-      s_y[r][c] = yv;
+    float iv[kStageQ], gv[kStageQ];
+    uint8_t mv[kStageQ];
+    bool ok[kStageQ];
+#pragma unroll
+    for (int q = 0; q < kStageQ; ++q) {
+      const int i = min(t + q * kLThreads, kStage - 1);
+      const int r = i / kLS, c = i - r * kLS;
+      const int y = oy - 2 * kLR + r, x = ox - 2 * kLR + c;
+      ok[q] = x >= 0 && x < W && y >= 0 && y < H;
+      const int64_t o = (int64_t)min(max(y, 0), H - 1) * W + min(max(x, 0), W - 1);
+      mv[q] = MASK ? Mk[o] : (uint8_t)1;
+      iv[q] = I[o];
+      gv[q] = G[o];
     }
-    __syncthreads();
-    // horizontal pass: 42 rows x 32 columns, five moments
-    for (int i = t; i < kLIn * kLT; i += kLThreads) {
-      const int r = i / kLT, c = i - r * kLT;
-      float mx = 0.f, my = 0.f, xx = 0.f, yy = 0.f, xy = 0.f;
 #pragma unroll
-      for (int k = 0; k <= 2 * kLR; ++k) {
-        const float xv = s_x[r][c + k], yv = s_y[r][c + k], w = win.w[k];
-        mx = fmaf(w, xv, mx);
-        my = fmaf(w, yv, my);
-        xx = fmaf(w, xv * xv, xx);
-        yy = fmaf(w, yv * yv, yy);
-        xy = fmaf(w, xv * yv, xy);
-      }
-      s_h[0][r][c] = mx;
-      s_h[1][r][c] = my;
-      s_h[2][r][c] = xx;
-      s_h[3][r][c] = yy;
-      s_h[4][r][c] = xy;
-    }
-    __syncthreads();
-    for (int i = t; i < kLT * kLT; i += kLThreads) {
-      const int r = i / kLT, c = i - r * kLT;
-      const int y = ty * kLT + r, x = tx * kLT + c;
-      float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int k = 0; k <= 2 * kLR; ++k) {
-        const float w = win.w[k];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) m[q] = fmaf(w, s_h[q][r + k][c], m[q]);
-      }
-      if (x < W && y < H) {
-        const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
-        const float mx = m[0], my = m[1];
-        const float A1 = 2.f * mx * my + C1;
-        const float A2 = 2.f * (m[4] - mx * my) + C2;
-        const float B1 = mx * mx + my * my + C1;
-        const float B2 = (m[2] - mx * mx) + (m[3] - my * my) + C2;
-        const float iB = 1.0f / (B1 * B2);
-        const float S = A1 * A2 * iB;
-        ssum += S;
-        const float xv = s_x[r + kLR][c + kLR], yv = s_y[r + kLR][c + kLR];
-        l1sum += fabsf(xv - yv);
-        const int64_t o = (int64_t)y * W + x;
-        float* mp = maps + (img * 9 + ch * 3) * HW;
-        mp[o] = 2.f * my * (A2 - A1) * iB - 2.f * mx * S * (1.0f / B1 - 1.0f / B2);
-        mp[HW + o] = -S / B2;
-        mp[2 * HW + o] = 2.f * A1 * iB;
-      }
+    for (int q = 0; q < kStageQ; ++q) {
+      const int i = t + q * kLThreads;
+      if (i >= kStage) continue;
+      const int r = i / kLS, c = i - r * kLS;
+      const float mk = (ok[q] && mv[q] != 0) ? 1.0f : 0.0f;
+      s_x[r * kLSs + c] = mk * iv[q];
+      s_y[r * kLSs + c] = mk * gv[q];
     }
   }
+  __syncthreads();
+
+  // moments, horizontal: staged row r, positions c0 .. c0 + kH1 - 1
+  constexpr int kItems1 = kLS * (kLM / kH1);
+  for (int it = t; it < kItems1; it += kLThreads) {
+    const int r = it / (kLM / kH1), c0 = (it - r * (kLM / kH1)) * kH1;
+    float acc[kH1][5];
+#pragma unroll
+    for (int u = 0; u < kH1; ++u)
+#pragma unroll
+      for (int q = 0; q < 5; ++q) acc[u][q] = 0.f;
+#pragma unroll
+    for (int j = 0; j < kH1 + 2 * kLR; ++j) {
+      const float xv = s_x[r * kLSs + c0 + j], yv = s_y[r * kLSs + c0 + j];
+      const float xx = xv * xv, yy = yv * yv, xy = xv * yv;
+#pragma unroll
+      for (int u = 0; u < kH1; ++u) {
+        const int k = j - u;
+        if (k < 0 || k > 2 * kLR) continue;
+        const float w = win.w[k];
+        acc[u][0] = fmaf(w, xv, acc[u][0]);
+        acc[u][1] = fmaf(w, yv, acc[u][1]);
+        acc[u][2] = fmaf(w, xx, acc[u][2]);
+        acc[u][3] = fmaf(w, yy, acc[u][3]);
+        acc[u][4] = fmaf(w, xy, acc[u][4]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kH1; ++u)
+#pragma unroll
+      for (int q = 0; q < 5; ++q) s_h[(q * kLS + r) * kLMs + c0 + u] = acc[u][q];
+  }
+  __syncthreads();
+
+  // moments, vertical, then SSIM and its partials at positions (r0 + u, c)
+  float ssum = 0.f;
+  if (t < (kLM / kV1) * kLM) {
+    const int c = t % kLM, r0 = (t / kLM) * kV1;
+    float m[kV1][5];
+#pragma unroll
+    for (int u = 0; u < kV1; ++u)
+#pragma unroll
+      for (int q = 0; q < 5; ++q) m[u][q] = 0.f;
+#pragma unroll
+    for (int j = 0; j < kV1 + 2 * kLR; ++j) {
+      float h[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) h[q] = s_h[(q * kLS + r0 + j) * kLMs + c];
+#pragma unroll
+      for (int u = 0; u < kV1; ++u) {
+        const int k = j - u;
+        if (k < 0 || k > 2 * kLR) continue;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) m[u][q] = fmaf(win.w[k], h[q], m[u][q]);
+      }
+    }
+    const int x = ox - kLR + c;
+    const bool colin = x >= 0 && x < W;
+    const bool colc = c >= kLR && c < kLR + kLT;
+    float P[kV1][3];
+#pragma unroll
+    for (int u = 0; u < kV1; ++u) {
+      const int y = oy - kLR + r0 + u;
+      const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
+      const float mx = m[u][0], my = m[u][1];
+      const float A1 = 2.f * mx * my + C1;
+      const float A2 = 2.f * (m[u][4] - mx * my) + C2;
+      const float B1 = mx * mx + my * my + C1;
+      const float B2 = (m[u][2] - mx * mx) + (m[u][3] - my * my) + C2;
+      // B1, B2 >= C1, C2 > 0: hardware reciprocals (1 ulp) suffice
+      const float iB1 = __builtin_amdgcn_rcpf(B1), iB2 = __builtin_amdgcn_rcpf(B2);
+      const float iB = iB1 * iB2;
+      const float S = A1 * A2 * iB;
+      const bool in = colin && y >= 0 && y < H;
+      if (in && colc && r0 + u >= kLR && r0 + u < kLR + kLT) ssum += S;
+      P[u][0] = in ? 2.f * my * (A2 - A1) * iB - 2.f * mx * S * (iB1 - iB2) : 0.f;
+      P[u][1] = in ? -S * iB2 : 0.f;
+      P[u][2] = in ? 2.f * A1 * iB : 0.f;
+    }
+    // region A (the staged images) is free once every thread is past the
+    // horizontal pass, which the barrier above guarantees
+#pragma unroll
+    for (int u = 0; u < kV1; ++u)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) s_p[(q * kLM + r0 + u) * kLMs + c] = P[u][q];
+  }
+  __syncthreads();
+
+  // this thread's output pixels (column cx, rows ry0 .. ry0 + kV2 - 1):
+  // fetch image, target and mask now, consumed after two more passes
+  const int cx = t % kLT, ry0 = (t / kLT) * kV2;
+  float xo[kV2], yo[kV2], mo[kV2];
+#pragma unroll
+  for (int u = 0; u < kV2; ++u) {
+    const int y = oy + ry0 + u, x = ox + cx;
+    const int64_t o = (int64_t)min(y, H - 1) * W + min(x, W - 1);
+    const uint8_t mb = MASK ? Mk[o] : (uint8_t)1;
+    const float iv = I[o], gv = G[o];
+    mo[u] = (x < W && y < H && mb != 0) ? 1.0f : 0.0f;
+    xo[u] = mo[u] * iv;
+    yo[u] = mo[u] * gv;
+  }
+
+  // partials, horizontal: position row r, output columns c0 .. c0 + kH2 - 1
+  constexpr int kItems2 = kLM * (kLT / kH2);
+  for (int it = t; it < kItems2; it += kLThreads) {
+    const int r = it / (kLT / kH2), c0 = (it - r * (kLT / kH2)) * kH2;
+    float acc[kH2][3];
+#pragma unroll
+    for (int u = 0; u < kH2; ++u)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[u][q] = 0.f;
+#pragma unroll
+    for (int j = 0; j < kH2 + 2 * kLR; ++j) {
+      float p[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) p[q] = s_p[(q * kLM + r) * kLMs + c0 + j];
+#pragma unroll
+      for (int u = 0; u < kH2; ++u) {
+        const int k = j - u;
+        if (k < 0 || k > 2 * kLR) continue;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[u][q] = fmaf(win.w[k], p[q], acc[u][q]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kH2; ++u)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) s_g[(q * kLM + r) * kLTs + c0 + u] = acc[u][q];
+  }
+  __syncthreads();
+
+  // partials, vertical, and d loss / d image
+  float g[kV2][3];
+#pragma unroll
+  for (int u = 0; u < kV2; ++u)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) g[u][q] = 0.f;
+#pragma unroll
+  for (int j = 0; j < kV2 + 2 * kLR; ++j) {
+    float h[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) h[q] = s_g[(q * kLM + ry0 + j) * kLTs + cx];
+#pragma unroll
+    for (int u = 0; u < kV2; ++u) {
+      const int k = j - u;
+      if (k < 0 || k > 2 * kLR) continue;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) g[u][q] = fmaf(win.w[k], h[q], g[u][q]);
+    }
+  }
+  float l1sum = 0.f;
+  float* D = d_image + ic * HW;
+#pragma unroll
+  for (int u = 0; u < kV2; ++u) {
+    const int y = oy + ry0 + u, x = ox + cx;
+    if (x >= W || y >= H) continue;
+    const float xv = xo[u], yv = yo[u];
+    l1sum += fabsf(xv - yv);
+    const float gs = g[u][0] + 2.f * xv * g[u][1] + yv * g[u][2];
+    const float diff = xv - yv;
+    const float sg = diff > 0.f ? 1.f : (diff < 0.f ? -1.f : 0.f);
+    D[(int64_t)y * W + x] = mo[u] * (l1_coef * sg - ssim_coef * gs);
+  }
+
   // block sums
   ssum = wave_sum(ssum);
   l1sum = wave_sum(l1sum);
@@ -151,78 +305,14 @@ __global__ __launch_bounds__(kLThreads) void k_ssim_fwd(
   }
   __syncthreads();
   if (t == 0) {
-    part[2 * blockIdx.x] = s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3];
-    part[2 * blockIdx.x + 1] = s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3];
-  }
-}
-
-__global__ __launch_bounds__(kLThreads) void k_ssim_bwd(
-    const float* __restrict__ image, const float* __restrict__ target,
-    const uint8_t* __restrict__ mask, int H, int W, int64_t tiles_x, int64_t blocks_per_img,
-    Window win, const float* __restrict__ maps, float l1_coef, float ssim_coef,
-    float* __restrict__ d_image) {
-  __shared__ float s_m[3][kLIn][kLIn + 1];
-  __shared__ float s_h[3][kLIn][kLT + 1];
-  const int64_t ic = blockIdx.x / blocks_per_img;          // image * 3 + channel
-  const int64_t img = ic / 3;
-  const int ch = (int)(ic - img * 3);
-  const int64_t b = blockIdx.x - ic * blocks_per_img;
-  const int ty = (int)(b / tiles_x), tx = (int)(b - (int64_t)ty * tiles_x);
-  const int x0 = tx * kLT - kLR, y0 = ty * kLT - kLR;
-  const int t = threadIdx.x;
-  const int64_t HW = (int64_t)H * W;
-  {
-    const float* mp = maps + (img * 9 + ch * 3) * HW;
-    for (int i = t; i < kLIn * kLIn; i += kLThreads) {
-      const int r = i / kLIn, c = i - r * kLIn;
-      const int y = y0 + r, x = x0 + c;
-      float a = 0.f, bb = 0.f, cc = 0.f;
-      if (x >= 0 && x < W && y >= 0 && y < H) {
-        const int64_t o = (int64_t)y * W + x;
-        a = mp[o];
-        bb = mp[HW + o];
-        cc = mp[2 * HW + o];
-      }
-      s_m[0][r][c] = a;
-      s_m[1][r][c] = bb;
-      s_m[2][r][c] = cc;
+    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+    for (int w = 0; w < kLThreads / 64; ++w) {
+      a0 += s_red[0][w];
+      a1 += s_red[1][w];
     }
-    __syncthreads();
-    for (int i = t; i < kLIn * kLT; i += kLThreads) {
-      const int r = i / kLT, c = i - r * kLT;
-      float acc[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-      for (int k = 0; k <= 2 * kLR; ++k) {
-        const float w = win.w[k];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) acc[q] = fmaf(w, s_m[q][r][c + k], acc[q]);
-      }
-#pragma unroll
-      for (int q = 0; q < 3; ++q) s_h[q][r][c] = acc[q];
-    }
-    __syncthreads();
-    const float* I = image + (img * 3 + ch) * HW;
-    const float* G = target + (img * 3 + ch) * HW;
-    float* D = d_image + (img * 3 + ch) * HW;
-    for (int i = t; i < kLT * kLT; i += kLThreads) {
-      const int r = i / kLT, c = i - r * kLT;
-      const int y = ty * kLT + r, x = tx * kLT + c;
-      if (x >= W || y >= H) continue;
-      float g[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-      for (int k = 0; k <= 2 * kLR; ++k) {
-        const float w = win.w[k];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) g[q] = fmaf(w, s_h[q][r + k][c], g[q]);
-      }
-      const int64_t o = (int64_t)y * W + x;
-      const float mk = mask ? (float)(mask[img * HW + o] != 0) : 1.0f;
-      const float xv = mk * I[o], yv = mk * G[o];
-      const float gs = g[0] + 2.f * xv * g[1] + yv * g[2];
-      const float diff = xv - yv;
-      const float sg = diff > 0.f ? 1.f : (diff < 0.f ? -1.f : 0.f);
-      D[o] = mk * (l1_coef * sg - ssim_coef * gs);
-    }
+    part[2 * blockIdx.x] = a0;
+    part[2 * blockIdx.x + 1] = a1;
   }
 }
 
@@ -278,22 +368,22 @@ gs_status gs_loss(const float* image, const float* target, const uint8_t* mask, 
   LossLayout L = loss_layout(S, H, W);
   GS_REQUIRE(ws_bytes >= L.total, "gs_loss: workspace %zu < required %zu", ws_bytes, L.total);
   GS_REQUIRE(((uintptr_t)ws & 255) == 0, "gs_loss: workspace must be 256-byte aligned");
-  char* w = (char*)ws;
-  float* maps = (float*)(w + L.off_maps);
-  float* part = (float*)(w + L.off_part);
+  float* part = (float*)((char*)ws + L.off_part);
   const Window win = ssim_window();
   const int64_t blocks = (int64_t)S * 3 * L.blocks_per_img;
   hipStream_t s = as_stream(stream);
-  hipLaunchKernelGGL(k_ssim_fwd, dim3((unsigned)blocks), dim3(kLThreads), 0, s, image, target,
-                     mask, H, W, L.tiles_x, L.blocks_per_img, win, maps, part);
-  GS_LAUNCH_CHECK("gs_loss/ssim_fwd");
   const double N = 3.0 * (double)H * (double)W;
   const float l1_coef = (float)((1.0 - lambda_dssim) * grad_scale / N);
   const float ssim_coef = (float)(lambda_dssim * grad_scale / N);
-  hipLaunchKernelGGL(k_ssim_bwd, dim3((unsigned)blocks), dim3(kLThreads), 0, s, image, target,
-                     mask, H, W, L.tiles_x, L.blocks_per_img, win, maps, l1_coef, ssim_coef,
-                     d_image);
-  GS_LAUNCH_CHECK("gs_loss/ssim_bwd");
+  if (mask)
+    hipLaunchKernelGGL(k_ssim<true>, dim3((unsigned)blocks), dim3(kLThreads), 0, s, image, target,
+                       mask, H, W, L.tiles_x, L.blocks_per_img, win, l1_coef, ssim_coef, d_image,
+                       part);
+  else
+    hipLaunchKernelGGL(k_ssim<false>, dim3((unsigned)blocks), dim3(kLThreads), 0, s, image, target,
+                       mask, H, W, L.tiles_x, L.blocks_per_img, win, l1_coef, ssim_coef, d_image,
+                       part);
+  GS_LAUNCH_CHECK("gs_loss/ssim");
   hipLaunchKernelGGL(k_loss_final, dim3((unsigned)S), dim3(256), 0, s, part, L.blocks_per_img,
                      1.0 / N, lambda_dssim, loss_out, status);
   GS_LAUNCH_CHECK("gs_loss/final");

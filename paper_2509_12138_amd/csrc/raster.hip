@@ -32,9 +32,18 @@ __device__ __forceinline__ int64_t tile_of_block(int64_t n_tiles) {
   return (i & 7) * chunk + (i >> 3);
 }
 
-__device__ __forceinline__ Splat load_splat(const float* __restrict__ rec, uint32_t id) {
+// A projected record as three 16-byte words (mean, conic, opacity, rgb).
+struct RawSplat {
+  float4 a, b, c;
+};
+
+__device__ __forceinline__ RawSplat fetch_splat(const float* __restrict__ rec, uint32_t id) {
   const float4* r = reinterpret_cast<const float4*>(rec + (int64_t)id * GS_REC_STRIDE);
-  float4 a = r[0], b = r[1], c = r[2];
+  return RawSplat{r[0], r[1], r[2]};
+}
+
+__device__ __forceinline__ Splat make_splat(const RawSplat& raw) {
+  const float4 a = raw.a, b = raw.b, c = raw.c;
   Splat s;
   s.pad1 = s.pad2 = 0.0f;
   s.mx = a.x;
@@ -48,6 +57,10 @@ __device__ __forceinline__ Splat load_splat(const float* __restrict__ rec, uint3
   s.b = c.x;
   s.thr = -__builtin_amdgcn_logf(255.0f * b.y);   // -log2(255 o)
   return s;
+}
+
+__device__ __forceinline__ Splat load_splat(const float* __restrict__ rec, uint32_t id) {
+  return make_splat(fetch_splat(rec, id));
 }
 
 template <int TW, int TH>
@@ -84,38 +97,53 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
                                              int chunk = 0, float bg0 = 0.f, float bg1 = 0.f,
                                              float bg2 = 0.f, int kbase = 0) {
   const int lane = threadIdx.x & (kRasterWave - 1);
-  bool done[PX];
+  // a pixel that is done (outside the image, or stopped) gets a NaN row
+  // coordinate: its falloff exponent is NaN and fails both skip tests, so
+  // no separate flag is tested per entry
+  float fyk[PX];
   float Tl[PX], Lc[PX][3];
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     T[k] = 1.0f;
     last[k] = 0;
-    done[k] = !inside[k];
+    fyk[k] = inside[k] ? fy[k] : __builtin_nanf("");
     if (WITH_COLOR) C[k][0] = C[k][1] = C[k][2] = 0.0f;
     if (CHUNKED) {
       Tl[k] = 1.0f;
       Lc[k][0] = Lc[k][1] = Lc[k][2] = 0.0f;
     }
   }
+  // the wave's pixel box: the tile's columns, rows of its PX strips
+  const float bx0 = fx - (float)(lane % TW), by0 = fy[0] - (float)(lane / TW);
+  const float bx1 = bx0 + (float)(TW - 1), by1 = by0 + (float)(PX * (kRasterWave / TW) - 1);
   uint32_t reached = 0;     // list entries processed (CHUNKED bookkeeping)
   for (uint32_t b0 = start; b0 < end; b0 += kRasterWave) {
     bool lane_done = true;
 #pragma unroll
-    for (int k = 0; k < PX; ++k) lane_done = lane_done && done[k];
+    for (int k = 0; k < PX; ++k) lane_done = lane_done && (fyk[k] != fyk[k]);
     if (__all(lane_done)) break;
     const int n = (int)min((uint32_t)kRasterWave, end - b0);
     wave_sync();
-    if (lane < n) s_splat[lane] = load_splat(rec, ids[b0 + lane]);
+    bool hit = false;
+    if (lane < n) {
+      const Splat s = load_splat(rec, ids[b0 + lane]);
+      hit = splat_may_hit(s, bx0, bx1, by0, by1);
+      s_splat[lane] = s;
+    }
+    // entries that cannot reach the wave's box are never visited
+    uint64_t todo = __ballot(hit);
     wave_sync();
-    for (int j = 0; j < n; ++j) {
+    while (todo) {
+      const int j = (int)__builtin_ctzll(todo);
+      todo &= todo - 1;
       const Splat sp = s_splat[j];
       const float dx = __fsub_rn(fx, sp.mx);
       float p2[PX];
-      splat_p2_column<PX>(sp, dx, fy, p2);
+      splat_p2_column<PX>(sp, dx, fyk, p2);
       bool pass[PX], any = false;
 #pragma unroll
       for (int k = 0; k < PX; ++k) {
-        pass[k] = !done[k] && splat_pass(sp, p2[k]);
+        pass[k] = splat_pass(sp, p2[k]);
         any = any || pass[k];
       }
       if (!__any(any)) continue;                    // whole wave skips this entry
@@ -126,7 +154,7 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
         const float alpha = fminf(kAlphaMax, sp.o * splat_gauss(p2[k]));
         const float Tn = T[k] * (1.0f - alpha);
         if (Tn < kTMin) {
-          done[k] = true;
+          fyk[k] = __builtin_nanf("");
           continue;
         }
         if (WITH_COLOR) {
@@ -421,17 +449,33 @@ __device__ __forceinline__ void reverse_pass(const RasterDev& a, uint32_t start,
   const int lane = threadIdx.x;
   const bool det = a.dup_grads != nullptr;
   float* const gbase = det ? a.dup_grads : d_rec;
+  // the tile's pixel box
+  const float bx0 = fx - (float)(lane % TW), by0 = fy[0] - (float)(lane / TW);
+  const float bx1 = bx0 + (float)(TW - 1), by1 = by0 + (float)(TH - 1);
   for (int top = hi; top > lo; top -= kRasterWave) {
     const int bot = max(lo, top - kRasterWave);
     const int n = top - bot;
     __syncthreads();
+    bool hit = false;
     if (lane < n) {
       const uint32_t id = a.ids[start + bot + lane];
-      s_id[lane] = det ? a.emit[start + bot + lane] : id;
-      s_splat[lane] = load_splat(a.rec, id);
+      const uint32_t e = det ? a.emit[start + bot + lane] : id;
+      s_id[lane] = e;
+      const Splat s = load_splat(a.rec, id);
+      hit = splat_may_hit(s, bx0, bx1, by0, by1);
+      s_splat[lane] = s;
+      // an entry that cannot reach the tile gets zero gradients
+      if (!hit && det && (int64_t)e < a.dup_cap) {
+        float* g = gbase + (int64_t)e * GS_DREC_STRIDE;
+#pragma unroll
+        for (int c = 0; c < GS_DREC_STRIDE; ++c) g[c] = 0.0f;
+      }
     }
+    uint64_t todo = __ballot(hit);
     __syncthreads();
-    for (int j = n - 1; j >= 0; --j) {
+    while (todo) {
+      const int j = 63 - (int)__builtin_clzll(todo);         // last first
+      todo &= ~(1ull << j);
       const Splat sp = s_splat[j];
       const int pos = bot + j + 1;
       const float dx = __fsub_rn(fx, sp.mx);
@@ -638,6 +682,73 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd_chunked(
   reverse_pass<TW, TH>(a, start, lo, hi, L.fx, L.fy, last, T, dI, dIacc, s_splat, s_id, d_rec,
                        scatter9_setup());
   if (a.dup_grads) zero_dup_slots(a, start, hi, hi_pos);
+}
+
+// ---------------------------------------------------------------- support count
+
+// Per pixel, the number of list entries it blends (alpha test passed,
+// transmittance still at or above the cut-off), with the forward's
+// decisions: one work-group of 256 threads per tile, up to 2 pixels per
+// thread, entries staged 256 at a time.  A measurement of the method's work
+// (the pairs an exact rasteriser must composite), not part of the training
+// step.
+constexpr int kCountThreads = 256;
+
+__global__ __launch_bounds__(kCountThreads) void k_raster_count(RasterDev a, int TW, int TH,
+                                                                int32_t* __restrict__ n_blend) {
+  __shared__ Splat s_sp[kCountThreads];
+  const int64_t tile = blockIdx.x;
+  const int slot = (int)(tile / a.tiles_per_slot);
+  const int tt = (int)(tile - (int64_t)slot * a.tiles_per_slot);
+  const int ty = tt / a.tiles_x, tx = tt - ty * a.tiles_x;
+  const int t = threadIdx.x;
+  float fx[2], fy[2], T[2];
+  int cnt[2];
+  bool live[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int p = t + k * kCountThreads;
+    const int px = tx * TW + p % TW, py = ty * TH + p / TW;
+    fx[k] = (float)px + 0.5f;
+    fy[k] = (float)py + 0.5f;
+    live[k] = p < TW * TH && px < a.W && py < a.H;
+    T[k] = 1.0f;
+    cnt[k] = 0;
+  }
+  const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+  for (uint32_t b0 = start; b0 < end; b0 += kCountThreads) {
+    if (__syncthreads_count(live[0] || live[1]) == 0) break;
+    if (b0 + t < end) s_sp[t] = load_splat(a.rec, a.ids[b0 + t]);
+    __syncthreads();
+    const int n = (int)min((uint32_t)kCountThreads, end - b0);
+    for (int j = 0; j < n; ++j) {
+      const Splat sp = s_sp[j];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (!live[k]) continue;
+        float p2;
+        splat_p2_column<1>(sp, __fsub_rn(fx[k], sp.mx), &fy[k], &p2);
+        if (!splat_pass(sp, p2)) continue;
+        const float alpha = fminf(kAlphaMax, sp.o * splat_gauss(p2));
+        const float Tn = T[k] * (1.0f - alpha);
+        if (Tn < kTMin) {
+          live[k] = false;
+          continue;
+        }
+        T[k] = Tn;
+        ++cnt[k];
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t HW = (int64_t)a.H * a.W;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int p = t + k * kCountThreads;
+    const int px = tx * TW + p % TW, py = ty * TH + p / TW;
+    if (p < TW * TH && px < a.W && py < a.H)
+      n_blend[(int64_t)slot * HW + (int64_t)py * a.W + px] = cnt[k];
+  }
 }
 
 // ---------------------------------------------------------------- tile order
@@ -1026,6 +1137,25 @@ gs_status gs_raster_bwd(const gs_projected* proj, const gs_views* views, const g
                        plan->dup_capacity, d_rec);
     GS_LAUNCH_CHECK("gs_raster_bwd/reduce");
   }
+  return GS_OK;
+}
+
+gs_status gs_raster_count(const gs_projected* proj, const gs_views* views,
+                          const gs_tiling* tiling, const uint32_t* ids,
+                          const uint32_t* tile_ranges, int32_t* n_blend, void* stream) {
+  clear_error();
+  RasterDev a;
+  const float bg[3] = {0.f, 0.f, 0.f};
+  gs_status st = raster_prepare(proj, views, tiling, ids, tile_ranges, bg, "gs_raster_count", a);
+  if (st != GS_OK) return st;
+  GS_REQUIRE(n_blend != nullptr, "gs_raster_count: NULL n_blend");
+  GS_REQUIRE(tiling->tile_w * tiling->tile_h <= 2 * kCountThreads,
+             "gs_raster_count: tile of %d pixels (at most %d)", tiling->tile_w * tiling->tile_h,
+             2 * kCountThreads);
+  if (a.n_tiles == 0) return GS_OK;
+  hipLaunchKernelGGL(k_raster_count, dim3((unsigned)a.n_tiles), dim3(kCountThreads), 0,
+                     as_stream(stream), a, tiling->tile_w, tiling->tile_h, n_blend);
+  GS_LAUNCH_CHECK("gs_raster_count");
   return GS_OK;
 }
 

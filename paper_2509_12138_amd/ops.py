@@ -252,6 +252,15 @@ class RasterBuffers:
              C.byref(self.tiling), _ptr(self.ids), _ptr(self.ranges), _lib.F3(*bg),
              _ptr(self.image), _ptr(self.T_final), _ptr(self.n_contrib), self._plan_ref(), s)
 
+    def count_blended(self, stream=None):
+        """Per-pixel number of blended list entries (gs_raster_count) of the
+        current lists, as a new [S, H, W] int32 tensor."""
+        out = torch.empty_like(self.n_contrib)
+        call("gs_raster_count", C.byref(self.proj), C.byref(self.views.struct),
+             C.byref(self.tiling), _ptr(self.ids), _ptr(self.ranges), _ptr(out),
+             stream or stream_handle())
+        return out
+
     def raster_bwd(self, d_image, bg=(0.0, 0.0, 0.0), mode=None, stream=None):
         s = stream or stream_handle()
         if mode is None:

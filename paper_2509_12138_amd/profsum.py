@@ -6,8 +6,8 @@ bench.py launches one k_project per training step and one more afterwards
 (the untimed replay that counts evaluations), so the timed window is the
 K steps that precede the last k_project dispatch.  Prints per-kernel
 dispatch counts, mean durations and share of the step, as Markdown.  With
---pmc, adds per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) averaged over the
-same kernels in a counter-collection run's CSV.
+--pmc, adds per-dispatch FETCH_SIZE / WRITE_SIZE (KiB, raw counter values) averaged
+over the dispatches of each kernel in counter-collection CSVs.
 """
 from __future__ import annotations
 
@@ -45,19 +45,42 @@ def summarise(trace, steps):
     return dur, total, (t1 - t0) / steps
 
 
+def counters(paths):
+    """Mean value per (kernel, counter) over every dispatch in the
+    counter-collection CSVs."""
+    acc = collections.defaultdict(list)
+    for p in paths:
+        for r in csv.DictReader(open(p)):
+            acc[(short(r["Kernel_Name"]), r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("trace")
     ap.add_argument("--steps", type=int, required=True)
+    ap.add_argument("--pmc", nargs="*", default=[],
+                    help="counter-collection CSVs with FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     dur, total, wall = summarise(args.trace, args.steps)
+    pmc = counters(args.pmc)
     print(f"Timed window: {args.steps} steps, {wall / 1e3:.1f} us per step (first k_project to "
           f"the next step's), kernels busy {total / args.steps / 1e3:.1f} us per step\n")
-    print("| kernel | dispatches/step | mean us | us/step | share |")
-    print("|---|---:|---:|---:|---:|")
+    head = "| kernel | dispatches/step | mean us | us/step | share |"
+    rule = "|---|---:|---:|---:|---:|"
+    if pmc:
+        head += " FETCH_SIZE KiB | WRITE_SIZE KiB |"
+        rule += "---:|---:|"
+    print(head)
+    print(rule)
     for k, v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
-        print(f"| {k} | {len(v) / args.steps:.0f} | {sum(v) / len(v) / 1e3:.2f} | "
-              f"{sum(v) / args.steps / 1e3:.2f} | {100.0 * sum(v) / total:.1f}% |")
+        line = (f"| {k} | {len(v) / args.steps:.0f} | {sum(v) / len(v) / 1e3:.2f} | "
+                f"{sum(v) / args.steps / 1e3:.2f} | {100.0 * sum(v) / total:.1f}% |")
+        if pmc:
+            f, w = pmc.get((k, "FETCH_SIZE")), pmc.get((k, "WRITE_SIZE"))
+            line += (f" {f:.0f} |" if f is not None else " – |") + \
+                    (f" {w:.0f} |" if w is not None else " – |")
+        print(line)
 
 
 if __name__ == "__main__":

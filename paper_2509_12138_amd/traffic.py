@@ -49,7 +49,7 @@ def counter_kib(path, kernel, counter):
             if (full == want if "<" in want else base == want) and r["Counter_Name"] == counter:
                 vals.append(float(r["Counter_Value"]))
     if not vals:
-        raise SystemExit(f"no {counter} samples for {kernel_prefix} in {path}")
+        raise SystemExit(f"no {counter} samples for {kernel} in {path}")
     return sum(vals) / len(vals), len(vals)
 
 

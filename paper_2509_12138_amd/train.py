@@ -284,6 +284,33 @@ class BatchedTrainer:
             raise _lib.GSError("batched step", st, _lib.last_error())
         return req
 
+    def prepare(self):
+        """Capture every view group's step before training (set-up, not
+        training): one eager step loads the kernels, its effect on the
+        parameters and optimiser state is undone, then each group's step is
+        captured (capturing does not run it)."""
+        if not self.use_graphs:
+            return
+        saved = [t.clone() for d in (self.params, self.m, self.v) for t in d.values()]
+        step0 = self.adam.step_dev.clone()
+        self._step_body(0)
+        torch.cuda.synchronize()
+        i = 0
+        for d in (self.params, self.m, self.v):
+            for t in d.values():
+                t.copy_(saved[i])
+                i += 1
+        self.adam.step_dev.copy_(step0)
+        for g in range(self.G):
+            if g not in self.graphs:
+                torch.cuda.synchronize()
+                graph = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(graph):
+                    self._step_body(g)
+                self.graphs[g] = graph
+            self._warm.add(g)
+        torch.cuda.synchronize()
+
     def evaluate(self):
         """Masked PSNR per partition (mean over its views); evaluation only."""
         ps = torch.zeros((self.P, self.V), device=self.device)

@@ -141,6 +141,7 @@ def run_batched(parts, cams, target, max_steps, eval_every, views_per_part=4, pl
     tr = BatchedTrainer(bp, cams, views_per_part=views_per_part, tile=tile, schedule=sched,
                         chunk=chunk, fwd_waves=nw, deterministic=det, order_seed=7)
     tr.fit_capacity()
+    tr.prepare()                  # graph capture is set-up, outside the clock
     P = len(parts)
     reached = [None] * P
     hist = []

@@ -109,3 +109,27 @@ def test_device_adam_schedule_matches_oracle(gpu):
         torch.cuda.synchronize()
         np.testing.assert_allclose(p.cpu().numpy(), ref[0], rtol=2e-6, atol=2e-6)
     assert int(adam.step_dev.item()) == 10
+
+
+def test_prepare_captures_without_training(parts):
+    """prepare() captures every group's step and leaves the state as it was;
+    the replayed training then matches an eager run."""
+    say("prepare + replay")
+    from paper_2509_12138_amd.train import BatchedTrainer
+    prts, cams = parts
+    bt = BatchedTrainer(prts, cams, views_per_part=2, graphs=True, order_seed=3)
+    bt.fit_capacity()
+    before = {k: v.cpu().numpy().copy() for k, v in bt.params.items()}
+    bt.prepare()
+    assert len(bt.graphs) == bt.G
+    assert int(bt.adam.step_dev.item()) == 0
+    for k, v in bt.params.items():
+        np.testing.assert_array_equal(v.cpu().numpy(), before[k])
+    ref = BatchedTrainer(prts, cams, views_per_part=2, graphs=False, order_seed=3)
+    ref.fit_capacity()
+    for s in range(6):
+        bt.step(s % bt.G)
+        ref.step(s % ref.G)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(bt.loss.loss.cpu().numpy(), ref.loss.loss.cpu().numpy(),
+                                   rtol=2e-4, atol=1e-7)

@@ -175,6 +175,7 @@ def test_raster_fwd_matches_oracle_on_same_records(ops, tile):
     bufs = make_bufs(ops, params, cams, W, H, tile)
     raster_records(bufs, rec, tb, nt, bg, torch)
     img = bufs.image.cpu().numpy(); Tf = bufs.T_final.cpu().numpy(); nc = bufs.n_contrib.cpu().numpy()
+    nb = bufs.count_blended().cpu().numpy()
     for v in range(3):
         o = oracle.render(views[v], W, H, tile=tile, bg=bg)
         # both sides sort the same FP32 depths, so near-equal depths are not
@@ -186,6 +187,7 @@ def test_raster_fwd_matches_oracle_on_same_records(ops, tile):
         assert err.max() <= 1e-4, err.max()
         assert np.abs(Tf[v] - o["T_final"])[ok].max() <= 1e-4
         np.testing.assert_array_equal(nc[v][ok], o["n_contrib"][ok])
+        np.testing.assert_array_equal(nb[v][ok], o["n_blended"][ok])   # gs_raster_count
         assert (o["n_blended"] > 0).mean() > 0.2
 
 
@@ -312,7 +314,7 @@ def test_project_bwd_matches_oracle(ops):
 
 # ------------------------------------------------------------------ loss, Adam
 
-@pytest.mark.parametrize("S,H,W,lam", [(2, 70, 95, 0.2), (1, 33, 40, 0.5)])
+@pytest.mark.parametrize("S,H,W,lam", [(2, 70, 95, 0.2), (1, 33, 40, 0.5), (1, 100, 170, 0.2), (1, 1, 1, 0.2)])
 def test_loss_matches_oracle(ops, S, H, W, lam):
     say("loss", S, H, W)
     rng = np.random.default_rng(9)
