@@ -97,24 +97,33 @@ __device__ __forceinline__ float wave_sum(float v) { return lane63(wave_sum_to_l
 // (A, B, C) so that log2 of the Gaussian falloff is A dx^2 + B dx dy + C dy^2,
 // opacity, colour and the log2-domain skip threshold thr = -log2(255 o):
 // o 2^p2 < 1/255 exactly when p2 < thr, so skipped entries never reach exp.
+// The first six words are what the skip test reads.
 struct alignas(16) Splat {
-  float mx, my, A, B, C, o, r, g, b, thr, pad1, pad2;
+  float mx, my, A, B, C, thr, o, r, g, b, pad1, pad2;
 };
 
 // log2-domain falloff exponents of the PX pixels a lane owns in one column
 // (same dx, rows fy[k]).  Explicit rounded operations keep the forward and
 // backward kernels bit-identical, so their skip/stop decisions agree.
+// Column terms of p2 shared by a lane's pixels: A dx^2 and B dx.
+__device__ __forceinline__ float splat_adx2(const Splat& s, float dx) {
+  return __fmul_rn(__fmul_rn(s.A, dx), dx);
+}
+__device__ __forceinline__ float splat_bdx(const Splat& s, float dx) { return __fmul_rn(s.B, dx); }
+
+// p2 of one pixel of the column (row centre fy).
+__device__ __forceinline__ float splat_p2_row(const Splat& s, float adx2, float bdx, float fy) {
+  const float dy = __fsub_rn(fy, s.my);
+  const float t = __fmaf_rn(s.C, dy, bdx);       // C dy + B dx
+  return __fmaf_rn(dy, t, adx2);                 // A dx^2 + B dx dy + C dy^2
+}
+
 template <int PX>
 __device__ __forceinline__ void splat_p2_column(const Splat& s, float dx, const float* fy,
                                                 float* p2) {
-  const float adx2 = __fmul_rn(__fmul_rn(s.A, dx), dx);
-  const float bdx = __fmul_rn(s.B, dx);
+  const float adx2 = splat_adx2(s, dx), bdx = splat_bdx(s, dx);
 #pragma unroll
-  for (int k = 0; k < PX; ++k) {
-    const float dy = __fsub_rn(fy[k], s.my);
-    const float t = __fmaf_rn(s.C, dy, bdx);     // C dy + B dx
-    p2[k] = __fmaf_rn(dy, t, adx2);              // A dx^2 + B dx dy + C dy^2
-  }
+  for (int k = 0; k < PX; ++k) p2[k] = splat_p2_row(s, adx2, bdx, fy[k]);
 }
 
 // Entry passes the skip tests: falloff exponent <= 0 and alpha >= 1/255.

@@ -132,11 +132,27 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
     }
     // entries that cannot reach the wave's box are never visited
     uint64_t todo = __ballot(hit);
+    const bool hit_any = todo != 0;
     wave_sync();
-    while (todo) {
-      const int j = (int)__builtin_ctzll(todo);
+    // the skip-test words of the next entry are read from LDS while the
+    // current one is processed
+    int j = todo ? (int)__builtin_ctzll(todo) : 0;
+    todo &= todo - 1;
+    float4 geo = *reinterpret_cast<const float4*>(&s_splat[j]);          // mx, my, A, B
+    float2 geo2 = *reinterpret_cast<const float2*>(&s_splat[j].C);       // C, thr
+    for (bool more = hit_any; more;) {
+      more = todo != 0;
+      const int jn = more ? (int)__builtin_ctzll(todo) : j;
+      const float4 geon = *reinterpret_cast<const float4*>(&s_splat[jn]);
+      const float2 geon2 = *reinterpret_cast<const float2*>(&s_splat[jn].C);
       todo &= todo - 1;
-      const Splat sp = s_splat[j];
+      Splat sp;
+      sp.mx = geo.x;
+      sp.my = geo.y;
+      sp.A = geo.z;
+      sp.B = geo.w;
+      sp.C = geo2.x;
+      sp.thr = geo2.y;
       const float dx = __fsub_rn(fx, sp.mx);
       float p2[PX];
       splat_p2_column<PX>(sp, dx, fyk, p2);
@@ -146,33 +162,38 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
         pass[k] = splat_pass(sp, p2[k]);
         any = any || pass[k];
       }
-      if (!__any(any)) continue;                    // whole wave skips this entry
-      const int pos = (int)(b0 - start) + j + 1;
+      if (__any(any)) {
+        const float4 col = *reinterpret_cast<const float4*>(&s_splat[j].o);   // o, r, g, b
+        const int pos = (int)(b0 - start) + j + 1;
 #pragma unroll
-      for (int k = 0; k < PX; ++k) {
-        if (!pass[k]) continue;
-        const float alpha = fminf(kAlphaMax, sp.o * splat_gauss(p2[k]));
-        const float Tn = T[k] * (1.0f - alpha);
-        if (Tn < kTMin) {
-          fyk[k] = __builtin_nanf("");
-          continue;
+        for (int k = 0; k < PX; ++k) {
+          if (!pass[k]) continue;
+          const float alpha = fminf(kAlphaMax, col.x * splat_gauss(p2[k]));
+          const float Tn = T[k] * (1.0f - alpha);
+          if (Tn < kTMin) {
+            fyk[k] = __builtin_nanf("");
+            continue;
+          }
+          if (WITH_COLOR) {
+            const float w = alpha * T[k];
+            C[k][0] = fmaf(col.y, w, C[k][0]);
+            C[k][1] = fmaf(col.z, w, C[k][1]);
+            C[k][2] = fmaf(col.w, w, C[k][2]);
+          }
+          if (CHUNKED) {
+            const float wl = alpha * Tl[k];
+            Lc[k][0] = fmaf(col.y, wl, Lc[k][0]);
+            Lc[k][1] = fmaf(col.z, wl, Lc[k][1]);
+            Lc[k][2] = fmaf(col.w, wl, Lc[k][2]);
+            Tl[k] = Tl[k] * (1.0f - alpha);
+          }
+          T[k] = Tn;
+          last[k] = pos;
         }
-        if (WITH_COLOR) {
-          const float w = alpha * T[k];
-          C[k][0] = fmaf(sp.r, w, C[k][0]);
-          C[k][1] = fmaf(sp.g, w, C[k][1]);
-          C[k][2] = fmaf(sp.b, w, C[k][2]);
-        }
-        if (CHUNKED) {
-          const float wl = alpha * Tl[k];
-          Lc[k][0] = fmaf(sp.r, wl, Lc[k][0]);
-          Lc[k][1] = fmaf(sp.g, wl, Lc[k][1]);
-          Lc[k][2] = fmaf(sp.b, wl, Lc[k][2]);
-          Tl[k] = Tl[k] * (1.0f - alpha);
-        }
-        T[k] = Tn;
-        last[k] = pos;
       }
+      geo = geon;
+      geo2 = geon2;
+      j = jn;
     }
     if (CHUNKED) {
       reached = b0 + (uint32_t)n - start;
