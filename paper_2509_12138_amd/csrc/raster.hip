@@ -77,9 +77,15 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Forward pass of one tile for one lane's PX pixels (pixel slots lane +
-// 64 (kbase + k) of the tile).  WITH_COLOR=false is the replay used by the
-// backward in RECOMPUTE mode.  s_splat: this wave's 64-entry LDS batch.
+// Pixel-centre box of the pixels a wave owns (for the entry cull).
+struct PixBox {
+  float x0, x1, y0, y1;
+};
+
+// Forward pass of one tile for one lane's PX pixels (pixel slots q0 + 64 k
+// of the tile, slot = row * TW + column), which lie in the wave's box.
+// WITH_COLOR=false is the replay used by the backward in RECOMPUTE mode.
+// s_splat: this wave's 64-entry LDS batch.
 // CHUNKED (with colour) also prepares the chunked backward: boundary c is
 // the list position (c+1)*chunk; for each pixel the forward stores at slot c
 // of `ck` (ck[c * TW*TH + pixel]) the transmittance T_c there and the colour
@@ -93,9 +99,9 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
                                              const uint32_t* __restrict__ ids, uint32_t start,
                                              uint32_t end, const float fx, const float* fy,
                                              const bool* inside, Splat* s_splat, float* T,
-                                             float (*C)[3], int* last, float4* ck = nullptr,
-                                             int chunk = 0, float bg0 = 0.f, float bg1 = 0.f,
-                                             float bg2 = 0.f, int kbase = 0) {
+                                             float (*C)[3], int* last, const PixBox& box,
+                                             float4* ck = nullptr, int chunk = 0, float bg0 = 0.f,
+                                             float bg1 = 0.f, float bg2 = 0.f, int q0 = 0) {
   const int lane = threadIdx.x & (kRasterWave - 1);
   // a pixel that is done (outside the image, or stopped) gets a NaN row
   // coordinate: its falloff exponent is NaN and fails both skip tests, so
@@ -113,9 +119,6 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
       Lc[k][0] = Lc[k][1] = Lc[k][2] = 0.0f;
     }
   }
-  // the wave's pixel box: the tile's columns, rows of its PX strips
-  const float bx0 = fx - (float)(lane % TW), by0 = fy[0] - (float)(lane / TW);
-  const float bx1 = bx0 + (float)(TW - 1), by1 = by0 + (float)(PX * (kRasterWave / TW) - 1);
   uint32_t reached = 0;     // list entries processed (CHUNKED bookkeeping)
   for (uint32_t b0 = start; b0 < end; b0 += kRasterWave) {
     bool lane_done = true;
@@ -127,7 +130,7 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
     bool hit = false;
     if (lane < n) {
       const Splat s = load_splat(rec, ids[b0 + lane]);
-      hit = splat_may_hit(s, bx0, bx1, by0, by1);
+      hit = splat_may_hit(s, box.x0, box.x1, box.y0, box.y1);
       s_splat[lane] = s;
     }
     // entries that cannot reach the wave's box are never visited
@@ -204,7 +207,7 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
           float4* dst = ck + (int64_t)(ce - 1) * (TW * TH);
 #pragma unroll
           for (int k = 0; k < PX; ++k)
-            dst[lane + (kbase + k) * kRasterWave] = make_float4(Tl[k], Lc[k][0], Lc[k][1], Lc[k][2]);
+            dst[q0 + k * kRasterWave] = make_float4(Tl[k], Lc[k][0], Lc[k][1], Lc[k][2]);
         }
 #pragma unroll
         for (int k = 0; k < PX; ++k) {
@@ -221,7 +224,7 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
       float4* dst = ck + (int64_t)(clast - 1) * (TW * TH);
 #pragma unroll
       for (int k = 0; k < PX; ++k)
-        dst[lane + (kbase + k) * kRasterWave] = make_float4(Tl[k], Lc[k][0], Lc[k][1], Lc[k][2]);
+        dst[q0 + k * kRasterWave] = make_float4(Tl[k], Lc[k][0], Lc[k][1], Lc[k][2]);
     }
     float Tn[PX], U[PX][3];
 #pragma unroll
@@ -235,7 +238,7 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
       float4* slot = ck + (int64_t)c * (TW * TH);
 #pragma unroll
       for (int k = 0; k < PX; ++k) {
-        const int q = lane + (kbase + k) * kRasterWave;
+        const int q = q0 + k * kRasterWave;
         const float4 pl = slot[q];                          // (P, L) of chunk c+1
         const float Te = Tn[k] / pl.x;
         U[k][0] = fmaf(pl.x, U[k][0], pl.y);
@@ -311,8 +314,11 @@ __device__ __forceinline__ void for_each_tile(const TileSched& sch, int64_t n_ti
   }
 }
 
-// Forward of one tile by wave (threadIdx.x / 64) of NW: the wave owns pixel
-// slots lane + 64 k for k in [wave PX, (wave + 1) PX), PX = TW TH / (64 NW).
+// Forward of one tile by wave w = threadIdx.x / 64 of NW; PX = TW TH / (64 NW)
+// pixels per lane.  With one pixel per lane the wave owns an 8x8 block of
+// the tile (blocks in row-major order), the most compact box for the entry
+// cull; otherwise the rows ty TH + (w PX + k) RSTEP + lane / TW of column
+// lane % TW.
 template <int TW, int TH, int NW>
 __device__ __forceinline__ void fwd_tile(const RasterDev& a, const ChunkDev& ch, int64_t tile,
                                          Splat* s_splat, float* __restrict__ image,
@@ -320,14 +326,22 @@ __device__ __forceinline__ void fwd_tile(const RasterDev& a, const ChunkDev& ch,
                                          int32_t* __restrict__ n_contrib) {
   constexpr int PX = TileGeom<TW, TH>::PX / NW, RSTEP = TileGeom<TW, TH>::RSTEP;
   static_assert(PX >= 1 && TileGeom<TW, TH>::PX % NW == 0, "waves per tile");
+  constexpr bool kBlock8 = PX == 1 && TW % 8 == 0 && TH % 8 == 0;
   const int W = a.W, H = a.H;
   const int slot = (int)(tile / a.tiles_per_slot);
   const int t = (int)(tile - (int64_t)slot * a.tiles_per_slot);
   const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
   const int lane = threadIdx.x & (kRasterWave - 1);
-  const int kbase = (threadIdx.x / kRasterWave) * PX;
-  const int px = tx * TW + (lane % TW);
-  const int py0 = ty * TH + lane / TW + kbase * RSTEP;
+  const int w = threadIdx.x / kRasterWave;
+  // the lane's column and first row inside the tile, and the wave's box
+  const int lx = kBlock8 ? (w % (TW / 8)) * 8 + lane % 8 : lane % TW;
+  const int ly0 = kBlock8 ? (w / (TW / 8)) * 8 + lane / 8 : lane / TW + w * PX * RSTEP;
+  const int bxo = kBlock8 ? (w % (TW / 8)) * 8 : 0, bw = kBlock8 ? 8 : TW;
+  const int byo = kBlock8 ? (w / (TW / 8)) * 8 : w * PX * RSTEP, bh = kBlock8 ? 8 : PX * RSTEP;
+  const PixBox box{(float)(tx * TW + bxo) + 0.5f, (float)(tx * TW + bxo + bw - 1) + 0.5f,
+                   (float)(ty * TH + byo) + 0.5f, (float)(ty * TH + byo + bh - 1) + 0.5f};
+  const int px = tx * TW + lx;
+  const int py0 = ty * TH + ly0;
   const float fx = (float)px + 0.5f;
   float fy[PX];
   bool inside[PX];
@@ -343,9 +357,11 @@ __device__ __forceinline__ void fwd_tile(const RasterDev& a, const ChunkDev& ch,
   if (ch.ck) {
     float4* ck = ch.ck + (int64_t)ch.offset[tile] * (TW * TH);
     tile_forward<TW, TH, PX, true, true>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T, C,
-                                         last, ck, ch.chunk, a.bg0, a.bg1, a.bg2, kbase);
+                                         last, box, ck, ch.chunk, a.bg0, a.bg1, a.bg2,
+                                         ly0 * TW + lx);
   } else {
-    tile_forward<TW, TH, PX, true>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T, C, last);
+    tile_forward<TW, TH, PX, true>(a.rec, a.ids, start, end, fx, fy, inside, s_splat, T, C, last,
+                                   box);
   }
   const int64_t HW = (int64_t)H * W;
   float* img = image + (int64_t)slot * 3 * HW;
@@ -368,7 +384,8 @@ __global__ __launch_bounds__(kRasterWave * NW) void k_raster_fwd(RasterDev a, Ti
                                                                  float* __restrict__ T_final,
                                                                  int32_t* __restrict__ n_contrib) {
   __shared__ Splat s_splat[kRasterWave * NW];
-  Splat* mine = s_splat + (threadIdx.x / kRasterWave) * kRasterWave;
+  // wave-uniform base (scalar), so per-entry LDS addresses stay scalar too
+  Splat* mine = s_splat + __builtin_amdgcn_readfirstlane(threadIdx.x / kRasterWave) * kRasterWave;
   for_each_tile(sch, a.n_tiles, [&](int64_t tile) {
     fwd_tile<TW, TH, NW>(a, ch, tile, mine, image, T_final, n_contrib);
   });
@@ -604,8 +621,10 @@ __device__ __forceinline__ void bwd_tile(const RasterDev& a, int64_t tile, Splat
   float T[PX];
   int last[PX];
   if (RECOMPUTE) {
+    const PixBox box{(float)(L.tx * TW) + 0.5f, (float)(L.tx * TW + TW - 1) + 0.5f,
+                     (float)(L.ty * TH) + 0.5f, (float)(L.ty * TH + TH - 1) + 0.5f};
     tile_forward<TW, TH, PX, false>(a.rec, a.ids, start, end, L.fx, L.fy, L.inside, s_splat, T,
-                                    nullptr, last);
+                                    nullptr, last, box);
   } else {
 #pragma unroll
     for (int k = 0; k < PX; ++k) {
