@@ -98,8 +98,8 @@ class PlainTrainer:
         b.project(self.gst)
         self._ev("bin_sort")
         b.bin_sort()
-        self._ev("raster_fwd")
         b.order_tiles()
+        self._ev("raster_fwd")
         b.raster_fwd(self.bg)
         self._ev("loss")
         self.loss(b.image, self.targets[vi:vi + 1], self.masks[vi:vi + 1] if self.masks is not None

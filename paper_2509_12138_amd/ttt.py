@@ -49,10 +49,11 @@ def log(*a):
 SURFACE_EXTENT = 0.56    # the isosurface |x| = 0.5 +- 0.05 lies inside [-0.56, 0.56]^3
 
 
-def slab_part(x0, x1, n, seed, ref_factor=2.0, grid=GRID):
-    """One x-slab [x0, x1) of the bumpy-sphere isosurface padded by the ghost
-    margin, sampled at n points, plus its ref_factor-denser reference."""
-    ghost = GHOST_VOXELS * 2.0 / grid
+def slab_part(x0, x1, n, seed, ref_factor=2.0, grid=GRID, ghost_voxels=GHOST_VOXELS):
+    """One x-slab [x0, x1) of the bumpy-sphere isosurface padded by a ghost
+    margin of ghost_voxels grid voxels, sampled at n points, plus its
+    ref_factor-denser reference."""
+    ghost = ghost_voxels * 2.0 / grid
     box = ((x0 - ghost, -1.0, -1.0), (x1 + ghost, 1.0, 1.0))
     pts, nrm = scene.sample_surface(scene.field_sphere_sines, int(n), grid, seed=seed, box=box)
     rp, rn = scene.sample_surface(scene.field_sphere_sines, int(n * ref_factor), grid,
@@ -60,7 +61,8 @@ def slab_part(x0, x1, n, seed, ref_factor=2.0, grid=GRID):
     return dict(points=pts, normals=nrm, ref_points=rp, ref_normals=rn, x_range=(x0, x1))
 
 
-def slab_partitions(counts=SLAB_COUNTS, seed=4, ref_factor=2.0, grid=GRID):
+def slab_partitions(counts=SLAB_COUNTS, seed=4, ref_factor=2.0, grid=GRID,
+                    ghost_voxels=GHOST_VOXELS):
     """The bumpy-sphere isosurface cut into len(counts) equal-width x-slabs
     over its extent, each padded by a ghost margin of GHOST_VOXELS voxels
     beyond its faces and sampled at exactly its listed point count (so the
@@ -70,15 +72,21 @@ def slab_partitions(counts=SLAB_COUNTS, seed=4, ref_factor=2.0, grid=GRID):
     P = len(counts)
     edges = np.linspace(-SURFACE_EXTENT, SURFACE_EXTENT, P + 1)
     return [slab_part(float(edges[p]), float(edges[p + 1]), counts[p], seed * 100 + p,
-                      ref_factor, grid) for p in range(P)]
+                      ref_factor, grid, ghost_voxels) for p in range(P)]
 
 
-def prepare(parts, cams, device="cuda"):
+def slab_faces(P):
+    """x of the P - 1 interior faces between the equal-width slabs."""
+    return np.linspace(-SURFACE_EXTENT, SURFACE_EXTENT, P + 1)[1:-1]
+
+
+def prepare(parts, cams, device="cuda", bg=(0.0, 0.0, 0.0)):
     """Reference discs -> targets and masks on the device, per partition."""
     for part in parts:
         d = scene.knn_mean_distance(part["ref_points"], 3)
         ref = workloads.reference_discs(part["ref_points"], part["ref_normals"], d)
-        part["targets"], part["masks"] = workloads.render_targets_gpu(ref, cams, device=device)
+        part["targets"], part["masks"] = workloads.render_targets_gpu(ref, cams, device=device,
+                                                                      bg=bg)
         part["n"] = len(part["points"])
     return parts
 

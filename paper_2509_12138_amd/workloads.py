@@ -74,9 +74,10 @@ def tiny_partition(cfg=None):
     return dict(params=params, reference=ref, cams=cams, cfg=cfg, points=pts, normals=nrm)
 
 
-def render_targets_gpu(reference, cams, tile=(16, 16), device="cuda"):
-    """Render every view of a reference set with the library's forward pass.
-    Returns (targets [V,3,H,W] f32, masks [V,H,W] u8) on the device."""
+def render_targets_gpu(reference, cams, tile=(16, 16), device="cuda", bg=(0.0, 0.0, 0.0)):
+    """Render every view of a reference set with the library's forward pass
+    over background colour bg.  Returns (targets [V,3,H,W] f32, masks [V,H,W]
+    u8) on the device."""
     import torch
     from . import ops
     n = reference["opacity_logit"].shape[0]
@@ -91,7 +92,7 @@ def render_targets_gpu(reference, cams, tile=(16, 16), device="cuda"):
     masks = torch.empty((len(cams), H, W), dtype=torch.uint8, device=device)
     for v in range(len(cams)):
         views.use_cameras(cams_dev[v:v + 1])
-        bufs.render_checked(gst)
+        bufs.render_checked(gst, tuple(bg))
         targets[v].copy_(bufs.image[0])
         masks[v].copy_((bufs.T_final[0] <= 0.5).to(torch.uint8))
     torch.cuda.synchronize()
