@@ -137,25 +137,16 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
     uint64_t todo = __ballot(hit);
     const bool hit_any = todo != 0;
     wave_sync();
-    // the skip-test words of the next entry are read from LDS while the
-    // current one is processed
-    int j = todo ? (int)__builtin_ctzll(todo) : 0;
-    todo &= todo - 1;
-    float4 geo = *reinterpret_cast<const float4*>(&s_splat[j]);          // mx, my, A, B
-    float2 geo2 = *reinterpret_cast<const float2*>(&s_splat[j].C);       // C, thr
-    for (bool more = hit_any; more;) {
-      more = todo != 0;
-      const int jn = more ? (int)__builtin_ctzll(todo) : j;
-      const float4 geon = *reinterpret_cast<const float4*>(&s_splat[jn]);
-      const float2 geon2 = *reinterpret_cast<const float2*>(&s_splat[jn].C);
-      todo &= todo - 1;
+    // composite entry j of the batch (skip-test words g = mx, my, A, B and
+    // h = C, thr already read)
+    auto composite = [&](const float4& g, const float2& h, int j) {
       Splat sp;
-      sp.mx = geo.x;
-      sp.my = geo.y;
-      sp.A = geo.z;
-      sp.B = geo.w;
-      sp.C = geo2.x;
-      sp.thr = geo2.y;
+      sp.mx = g.x;
+      sp.my = g.y;
+      sp.A = g.z;
+      sp.B = g.w;
+      sp.C = h.x;
+      sp.thr = h.y;
       const float dx = __fsub_rn(fx, sp.mx);
       float p2[PX];
       splat_p2_column<PX>(sp, dx, fyk, p2);
@@ -165,38 +156,57 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
         pass[k] = splat_pass(sp, p2[k]);
         any = any || pass[k];
       }
-      if (__any(any)) {
-        const float4 col = *reinterpret_cast<const float4*>(&s_splat[j].o);   // o, r, g, b
-        const int pos = (int)(b0 - start) + j + 1;
+      if (!__any(any)) return;
+      const float4 col = *reinterpret_cast<const float4*>(&s_splat[j].o);   // o, r, g, b
+      const int pos = (int)(b0 - start) + j + 1;
 #pragma unroll
-        for (int k = 0; k < PX; ++k) {
-          if (!pass[k]) continue;
-          const float alpha = fminf(kAlphaMax, col.x * splat_gauss(p2[k]));
-          const float Tn = T[k] * (1.0f - alpha);
-          if (Tn < kTMin) {
-            fyk[k] = __builtin_nanf("");
-            continue;
-          }
-          if (WITH_COLOR) {
-            const float w = alpha * T[k];
-            C[k][0] = fmaf(col.y, w, C[k][0]);
-            C[k][1] = fmaf(col.z, w, C[k][1]);
-            C[k][2] = fmaf(col.w, w, C[k][2]);
-          }
-          if (CHUNKED) {
-            const float wl = alpha * Tl[k];
-            Lc[k][0] = fmaf(col.y, wl, Lc[k][0]);
-            Lc[k][1] = fmaf(col.z, wl, Lc[k][1]);
-            Lc[k][2] = fmaf(col.w, wl, Lc[k][2]);
-            Tl[k] = Tl[k] * (1.0f - alpha);
-          }
-          T[k] = Tn;
-          last[k] = pos;
+      for (int k = 0; k < PX; ++k) {
+        if (!pass[k]) continue;
+        const float alpha = fminf(kAlphaMax, col.x * splat_gauss(p2[k]));
+        const float Tn = T[k] * (1.0f - alpha);
+        const bool stop = Tn < kTMin;
+        fyk[k] = stop ? __builtin_nanf("") : fyk[k];
+        if (stop) continue;
+        if (WITH_COLOR) {
+          const float w = alpha * T[k];
+          C[k][0] = fmaf(col.y, w, C[k][0]);
+          C[k][1] = fmaf(col.z, w, C[k][1]);
+          C[k][2] = fmaf(col.w, w, C[k][2]);
         }
+        if (CHUNKED) {
+          const float wl = alpha * Tl[k];
+          Lc[k][0] = fmaf(col.y, wl, Lc[k][0]);
+          Lc[k][1] = fmaf(col.z, wl, Lc[k][1]);
+          Lc[k][2] = fmaf(col.w, wl, Lc[k][2]);
+          Tl[k] = Tl[k] * (1.0f - alpha);
+        }
+        T[k] = Tn;
+        last[k] = pos;
       }
-      geo = geon;
-      geo2 = geon2;
-      j = jn;
+    };
+    // the skip-test words of the next entry are read from LDS while the
+    // current one is composited; two register sets alternate
+    if (hit_any) {
+      int ja = (int)__builtin_ctzll(todo);
+      todo &= todo - 1;
+      float4 ga = *reinterpret_cast<const float4*>(&s_splat[ja]);     // mx, my, A, B
+      float2 ha = *reinterpret_cast<const float2*>(&s_splat[ja].C);   // C, thr
+      for (;;) {
+        const bool more_a = todo != 0;
+        const int jb = more_a ? (int)__builtin_ctzll(todo) : ja;
+        const float4 gb = *reinterpret_cast<const float4*>(&s_splat[jb]);
+        const float2 hb = *reinterpret_cast<const float2*>(&s_splat[jb].C);
+        todo &= todo - 1;
+        composite(ga, ha, ja);
+        if (!more_a) break;
+        const bool more_b = todo != 0;
+        ja = more_b ? (int)__builtin_ctzll(todo) : jb;
+        ga = *reinterpret_cast<const float4*>(&s_splat[ja]);
+        ha = *reinterpret_cast<const float2*>(&s_splat[ja].C);
+        todo &= todo - 1;
+        composite(gb, hb, jb);
+        if (!more_b) break;
+      }
     }
     if (CHUNKED) {
       reached = b0 + (uint32_t)n - start;
