@@ -362,6 +362,22 @@ gs_status gs_adam_dev(const gs_adam_group* groups, int32_t n_groups, const float
                       int32_t decay_steps, float beta1, float beta2, float eps,
                       int32_t* step_dev, int32_t zero_grad, void* stream);
 
+/* gs_project_bwd into zeroed gradients followed by gs_adam_dev, in one pass
+ * over the Gaussians (the 3D-GS step's last two stages): each Gaussian's
+ * gradient, summed over its pairs of `views`, stays in registers and updates
+ * its 14 parameters, m and v in place at once, so the gradient arrays are
+ * neither written nor read.  Bitwise equal to the two calls.
+ *   groups: 5 groups in the order mean, log_scale, quat, opacity_logit,
+ *   color whose param arrays are g's (counts 3n, 3n, 4n, n, 3n) with their
+ *   m, v and lr; grad pointers are not used.  lr_final (5 or NULL),
+ *   decay_steps, betas, eps and step_dev as gs_adam_dev (step_dev is
+ *   incremented).  Gaussians drawn by no pair get a zero gradient.         */
+gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
+                              const gs_tiling* tiling, const gs_projected* proj,
+                              const float* d_rec, const gs_adam_group* groups,
+                              const float* lr_final, int32_t decay_steps, float beta1,
+                              float beta2, float eps, int32_t* step_dev, void* stream);
+
 /* ------------------------------------------------------------------------
  * Learned initialisation.  The paper places one Gaussian at every point of
  * the extracted isosurface (Sec. II, "Isosurface Extraction") and leaves its

@@ -95,6 +95,8 @@ SIGNATURES = {
     "gs_loss": (i32, [vp, vp, vp, i32, i32, i32, f32, f32, vp, sz, vp, vp, vp, vp]),
     "gs_adam": (i32, [P(gs_adam_group), i32, f32, f32, f32, i32, i32, vp]),
     "gs_adam_dev": (i32, [P(gs_adam_group), i32, P(f32), i32, f32, f32, f32, vp, i32, vp]),
+    "gs_project_bwd_adam": (i32, [P(gs_gaussians), P(gs_views), P(gs_tiling), P(gs_projected),
+                                  vp, P(gs_adam_group), P(f32), i32, f32, f32, f32, vp, vp]),
     "gs_zero": (i32, [vp, sz, vp]),
     "gs_check_status": (i32, [vp, vp, P(i64)]),
     "gs_last_error": (C.c_char_p, []),

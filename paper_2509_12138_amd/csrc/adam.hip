@@ -32,24 +32,13 @@ struct AdamArgs {
 // Learning rate and bias corrections of the step the device counter names.
 __device__ __forceinline__ void device_schedule(const AdamArgs& A, const AdamGroupDev& G,
                                                 float& lr, float& ibc1, float& ibc2) {
-  const int t = A.step_dev[0] + 1;
-  ibc1 = 1.0f / (1.0f - powf(A.b1, (float)t));
-  ibc2 = 1.0f / (1.0f - powf(A.b2, (float)t));
-  lr = G.lr;
-  const float lf = A.lr_final[blockIdx.y];
-  if (lf > 0.0f && A.decay_steps > 0) {
-    const float u = fminf((float)t / (float)A.decay_steps, 1.0f);
-    lr = G.lr * expf(u * logf(lf / G.lr));
-  }
+  adam_schedule(A.step_dev[0] + 1, A.b1, A.b2, G.lr, A.lr_final[blockIdx.y], A.decay_steps, lr,
+                ibc1, ibc2);
 }
 
 __device__ __forceinline__ void adam_one(float& p, float& g, float& m, float& v, float lr,
                                          float ibc1, float ibc2, const AdamArgs& A) {
-  m = A.b1 * m + (1.0f - A.b1) * g;
-  v = A.b2 * v + (1.0f - A.b2) * g * g;
-  const float mh = m * ibc1;
-  const float vh = v * ibc2;
-  p -= lr * mh / (sqrtf(vh) + A.eps);
+  adam_update(p, g, m, v, lr, ibc1, ibc2, A.b1, A.b2, A.eps);
 }
 
 __global__ __launch_bounds__(256) void k_adam(AdamArgs A) {

@@ -7,6 +7,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdarg.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -162,5 +163,34 @@ __device__ __forceinline__ bool splat_may_hit(const Splat& s, float x0, float x1
 
 // Unclamped alpha o * 2^p2; __builtin_amdgcn_exp2f is the hardware v_exp_f32.
 __device__ __forceinline__ float splat_gauss(float p2) { return __builtin_amdgcn_exp2f(p2); }
+
+// ----------------------------------------------------------------- Adam
+
+// Learning rate and bias-correction factors of Adam step t (from 1): lr0
+// decayed log-linearly towards lr_final over decay_steps when lr_final > 0
+// (the 3D-GS position schedule).  Shared by every Adam kernel so that fused
+// and separate updates agree bit for bit.
+__device__ __forceinline__ void adam_schedule(int t, float b1, float b2, float lr0,
+                                              float lr_final, int decay_steps, float& lr,
+                                              float& ibc1, float& ibc2) {
+  ibc1 = 1.0f / (1.0f - powf(b1, (float)t));
+  ibc2 = 1.0f / (1.0f - powf(b2, (float)t));
+  lr = lr0;
+  if (lr_final > 0.0f && decay_steps > 0) {
+    const float u = fminf((float)t / (float)decay_steps, 1.0f);
+    lr = lr0 * expf(u * logf(lr_final / lr0));
+  }
+}
+
+// One bias-corrected Adam update of a parameter p with gradient g.
+__device__ __forceinline__ void adam_update(float& p, float g, float& m, float& v, float lr,
+                                            float ibc1, float ibc2, float b1, float b2,
+                                            float eps) {
+  m = b1 * m + (1.0f - b1) * g;
+  v = b2 * v + (1.0f - b2) * g * g;
+  const float mh = m * ibc1;
+  const float vh = v * ibc2;
+  p -= lr * mh / (sqrtf(vh) + eps);
+}
 
 }  // namespace gsmi

@@ -355,6 +355,84 @@ __global__ __launch_bounds__(256) void k_project_bwd(
   Gr.ol[g] += gol;
 }
 
+// gs_project_bwd and one Adam step in a single pass: a thread owns a
+// Gaussian, sums its gradient over its pairs in registers (the same
+// arithmetic as k_project_bwd) and applies the update to its 14 parameters,
+// reading and writing m and v once.  Gaussians drawn by no pair get a zero
+// gradient (dense Adam).
+struct AdamFused {
+  float* p[5];            // mean, log_scale, quat, opacity_logit, colour (planar)
+  float* m[5];
+  float* v[5];
+  float lr[5], lr_final[5];
+  int decay_steps;
+  float b1, b2, eps;
+  const int32_t* step_dev;
+};
+
+__global__ __launch_bounds__(256) void k_project_bwd_adam(
+    Params P, AdamFused A, const int64_t* __restrict__ pair_offset,
+    const int64_t* __restrict__ gauss_offset, const gs_camera* __restrict__ cams, int n_slots,
+    int W, int H, int tw, int th, const int32_t* __restrict__ n_tiles,
+    const float* __restrict__ d_rec) {
+  __shared__ float s_lr[5], s_ibc[2];
+  if (threadIdx.x < 5) {
+    float lr, ibc1, ibc2;
+    adam_schedule(A.step_dev[0] + 1, A.b1, A.b2, A.lr[threadIdx.x], A.lr_final[threadIdx.x],
+                  A.decay_steps, lr, ibc1, ibc2);
+    s_lr[threadIdx.x] = lr;
+    if (threadIdx.x == 0) {
+      s_ibc[0] = ibc1;
+      s_ibc[1] = ibc2;
+    }
+  }
+  __syncthreads();
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= P.n) return;
+  float mu[3], ls[3], q[4], ol, col[3];
+  load_gaussian(P, g, mu, ls, q, ol, col);
+  float gmu[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
+  float gol = 0.f, gcol[3] = {0.f, 0.f, 0.f};
+  for (int s = 0; s < n_slots; ++s) {
+    const int64_t g0 = gauss_offset[s];
+    const int64_t cnt = pair_offset[s + 1] - pair_offset[s];
+    if (g < g0 || g >= g0 + cnt) continue;
+    const int64_t p = pair_offset[s] + (g - g0);
+    if (n_tiles[p] <= 0) continue;
+    ProjState S;
+    project_core(mu, ls, q, ol, col, cams[s], W, H, tw, th, S);
+    if (!S.valid) continue;
+    float dr[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) dr[k] = d_rec[p * GS_DREC_STRIDE + k];
+    project_bwd_core(S, cams[s], dr, gmu, gls, gq, gol, gcol);
+  }
+  // the gradient a separate pass would add to zeroed arrays
+  const float G[14] = {0.f + gmu[0], 0.f + gmu[1], 0.f + gmu[2], 0.f + gls[0], 0.f + gls[1],
+                       0.f + gls[2], 0.f + gq[0],  0.f + gq[1],  0.f + gq[2],  0.f + gq[3],
+                       0.f + gol,    0.f + gcol[0], 0.f + gcol[1], 0.f + gcol[2]};
+  float par[14] = {mu[0], mu[1], mu[2], ls[0], ls[1], ls[2], q[0], q[1], q[2], q[3], ol,
+                   col[0], col[1], col[2]};
+  constexpr int kGroup[14] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 2, 3, 4, 4, 4};
+  constexpr int kRow[14] = {0, 1, 2, 0, 1, 2, 0, 1, 2, 3, 0, 0, 1, 2};
+  const int64_t n = P.n;
+  const float ibc1 = s_ibc[0], ibc2 = s_ibc[1];
+#pragma unroll
+  for (int e = 0; e < 14; ++e) {
+    const int gr = kGroup[e];
+    const int64_t o = (int64_t)kRow[e] * n + g;
+    float m = A.m[gr][o], v = A.v[gr][o];
+    adam_update(par[e], G[e], m, v, s_lr[gr], ibc1, ibc2, A.b1, A.b2, A.eps);
+    A.p[gr][o] = par[e];
+    A.m[gr][o] = m;
+    A.v[gr][o] = v;
+  }
+}
+
+__global__ void k_adam_step_inc(int32_t* step_dev) {
+  if (threadIdx.x == 0) step_dev[0] += 1;
+}
+
 }  // namespace gsmi
 
 using namespace gsmi;
@@ -410,6 +488,59 @@ gs_status gs_project_bwd(const gs_gaussians* g, const gs_views* views, const gs_
                      tiling->width, tiling->height, tiling->tile_w, tiling->tile_h, proj->n_tiles,
                      d_rec);
   GS_LAUNCH_CHECK("gs_project_bwd");
+  return GS_OK;
+}
+
+gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
+                              const gs_tiling* tiling, const gs_projected* proj,
+                              const float* d_rec, const gs_adam_group* groups,
+                              const float* lr_final, int32_t decay_steps, float beta1,
+                              float beta2, float eps, int32_t* step_dev, void* stream) {
+  clear_error();
+  GS_REQUIRE(g && proj && groups && step_dev, "gs_project_bwd_adam: NULL argument");
+  gs_status st = check_views(views, tiling, "gs_project_bwd_adam");
+  if (st != GS_OK) return st;
+  GS_REQUIRE(proj->m == views->total_pairs, "gs_project_bwd_adam: proj->m != total_pairs");
+  GS_REQUIRE(decay_steps >= 0, "gs_project_bwd_adam: decay_steps < 0");
+  GS_REQUIRE(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f,
+             "gs_project_bwd_adam: bad betas");
+  const float* arrays[5] = {g->mean, g->log_scale, g->quat, g->opacity_logit, g->color};
+  const int rows[5] = {3, 3, 4, 1, 3};
+  AdamFused A;
+  for (int i = 0; i < 5; ++i) {
+    GS_REQUIRE(groups[i].param == arrays[i] && groups[i].count == rows[i] * g->n,
+               "gs_project_bwd_adam: group %d must be the Gaussians' array %d (%d x n elements)",
+               i, i, rows[i]);
+    GS_REQUIRE(g->n == 0 || (groups[i].m && groups[i].v), "gs_project_bwd_adam: group %d NULL m/v",
+               i);
+    const float lf = lr_final ? lr_final[i] : 0.0f;
+    GS_REQUIRE(!(lf > 0.0f) || groups[i].lr > 0.0f,
+               "gs_project_bwd_adam: decay needs lr > 0 (group %d)", i);
+    A.p[i] = groups[i].param;
+    A.m[i] = groups[i].m;
+    A.v[i] = groups[i].v;
+    A.lr[i] = groups[i].lr;
+    A.lr_final[i] = lf;
+  }
+  A.decay_steps = decay_steps;
+  A.b1 = beta1;
+  A.b2 = beta2;
+  A.eps = eps;
+  A.step_dev = step_dev;
+  hipStream_t s = as_stream(stream);
+  if (g->n > 0) {
+    GS_REQUIRE(g->mean && g->log_scale && g->quat && g->opacity_logit && g->color &&
+                   (proj->m == 0 || (d_rec && proj->n_tiles)),
+               "gs_project_bwd_adam: arrays must not be NULL");
+    Params P{g->mean, g->log_scale, g->quat, g->opacity_logit, g->color, g->n};
+    hipLaunchKernelGGL(k_project_bwd_adam, dim3((unsigned)ceil_div(g->n, 256)), dim3(256), 0, s,
+                       P, A, views->pair_offset, views->gauss_offset, views->cams, views->n_slots,
+                       tiling->width, tiling->height, tiling->tile_w, tiling->tile_h,
+                       proj->n_tiles, d_rec);
+    GS_LAUNCH_CHECK("gs_project_bwd_adam");
+  }
+  hipLaunchKernelGGL(k_adam_step_inc, dim3(1), dim3(64), 0, s, step_dev);
+  GS_LAUNCH_CHECK("gs_project_bwd_adam/step");
   return GS_OK;
 }
 

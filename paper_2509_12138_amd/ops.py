@@ -277,6 +277,15 @@ class RasterBuffers:
              C.byref(self.tiling), C.byref(self.proj), _ptr(self.d_rec),
              C.byref(grads_struct_), s)
 
+    def project_bwd_adam(self, gstruct, adam, stream=None):
+        """gs_project_bwd_adam: projection backward and the DeviceAdam step
+        `adam` in one pass (gradient arrays untouched)."""
+        s = stream or stream_handle()
+        call("gs_project_bwd_adam", C.byref(gstruct), C.byref(self.views.struct),
+             C.byref(self.tiling), C.byref(self.proj), _ptr(self.d_rec), adam.groups,
+             adam.lr_final, adam.decay_steps, adam.betas[0], adam.betas[1], adam.betas[2],
+             _ptr(adam.step_dev), s)
+
     def zero_d_rec(self, stream=None):
         s = stream or stream_handle()
         call("gs_zero", _ptr(self.d_rec), self.d_rec.numel() * 4, s)

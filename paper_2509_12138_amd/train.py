@@ -41,7 +41,8 @@ class PlainTrainer:
 
     def __init__(self, params, cams_np, targets, masks, tile=(16, 16), lam=0.2,
                  bg=(0.0, 0.0, 0.0), stored=True, extent=2.75, lrs=None, dup_capacity=None,
-                 schedule="default", chunk=0, fwd_waves=1, deterministic=False, device="cuda"):
+                 schedule="default", chunk=0, fwd_waves=1, deterministic=False, fused_adam=True,
+                 device="cuda"):
         self.device = device
         self.params = {k: torch.as_tensor(np.ascontiguousarray(v, np.float32)).to(device)
                        if not torch.is_tensor(v) else v.contiguous().to(device)
@@ -70,6 +71,14 @@ class PlainTrainer:
         self.gst = ops.gaussians_struct(self.params)
         self.grst = ops.grads_struct(self.grads, self.n)
         self.groups = ops.adam_groups(self.params, self.grads, self.m, self.v, self.lrs)
+        # fused projection backward + Adam: the step count and the position
+        # lr decay live on the device
+        self.fused_adam = fused_adam
+        if fused_adam:
+            lrs_dev = dict(self.lrs, mean=self.lrs["mean"] * extent)
+            self.dev_adam = ops.DeviceAdam(
+                ops.adam_groups(self.params, self.grads, self.m, self.v, lrs_dev),
+                lr_final=[1.6e-6 * extent, 0, 0, 0, 0], decay_steps=30000, device=device)
         self.step_count = 0
         self.timing = None            # optional dict of lists of (start, end) events
 
@@ -109,11 +118,15 @@ class PlainTrainer:
         self._ev("raster_bwd")
         b.raster_bwd(self.loss.d_image, self.bg, self.mode)
         self._ev("project_bwd")
-        b.project_bwd(self.gst, self.grst)
-        self._ev("adam")
         self.step_count += 1
-        self.groups[0].lr = mean_lr(self.step_count, self.extent, self.lrs["mean"])
-        ops.adam_step(self.groups, self.step_count, zero_grad=True)
+        if self.fused_adam:
+            b.project_bwd_adam(self.gst, self.dev_adam)
+            self._ev("adam")
+        else:
+            b.project_bwd(self.gst, self.grst)
+            self._ev("adam")
+            self.groups[0].lr = mean_lr(self.step_count, self.extent, self.lrs["mean"])
+            ops.adam_step(self.groups, self.step_count, zero_grad=True)
         self._ev("end")
 
     def check(self):
@@ -185,7 +198,7 @@ class BatchedTrainer:
     def __init__(self, parts, cams_np, views_per_part=4, tile=(16, 16), schedule="lpt",
                  chunk=64, stored=True, lam=0.2, bg=(0.0, 0.0, 0.0), extent=2.75, lrs=None,
                  order_seed=0, graphs=True, dup_capacity=None, fwd_waves=1, deterministic=False,
-                 device="cuda"):
+                 fused_adam=True, device="cuda"):
         from .scene import concat_params
         self.device = device
         self.P = len(parts)
@@ -233,6 +246,7 @@ class BatchedTrainer:
         self.groups = ops.adam_groups(self.params, self.grads, self.m, self.v, self.lrs)
         self.adam = ops.DeviceAdam(self.groups, lr_final=[1.6e-6 * extent, 0, 0, 0, 0],
                                    decay_steps=30000, device=device)
+        self.fused_adam = fused_adam
         self.use_graphs = graphs
         self.graphs = {}
         self._warm = set()
@@ -257,8 +271,11 @@ class BatchedTrainer:
         self.loss(b.image, self.targets_g[g], self.masks_g[g], self.lam, 1.0 / self.vpp, b.status)
         b.zero_d_rec()
         b.raster_bwd(self.loss.d_image, self.bg, self.mode)
-        b.project_bwd(self.gst, self.grst)
-        self.adam(zero_grad=True)
+        if self.fused_adam:
+            b.project_bwd_adam(self.gst, self.adam)
+        else:
+            b.project_bwd(self.gst, self.grst)
+            self.adam(zero_grad=True)
 
     def step(self, g):
         """One batched step on view group g (graph replay after the first)."""

@@ -312,6 +312,49 @@ def test_project_bwd_matches_oracle(ops):
         assert np.all(np.abs(got - r) <= 1e-3 * np.abs(r) + 1e-5 * scale), k
 
 
+def test_fused_projection_backward_adam_is_bitwise_equal(ops):
+    """gs_project_bwd_adam equals gs_project_bwd into zeroed gradients
+    followed by gs_adam_dev, bit for bit, over three steps (3 slots per
+    step, position-lr decay, some Gaussians drawn by no pair)."""
+    say("project_bwd + adam fused")
+    W, H = 200, 150
+    n = 5000
+    params = perturbed(surface_scene(n, 62), 62)
+    cams = scene.orbit_cameras(3, W, H)
+    lrs = {"mean": 1.6e-4 * 2.75, "log_scale": 5e-3, "quat": 1e-3, "opacity_logit": 5e-2,
+           "color": 2.5e-3}
+    runs = []
+    for fused in (False, True):
+        bufs = make_bufs(ops, params, cams, W, H)
+        dp = to_dev(params, torch)
+        gst = ops.gaussians_struct(dp)
+        dm = {k: torch.zeros_like(v) for k, v in dp.items()}
+        dv = {k: torch.zeros_like(v) for k, v in dp.items()}
+        dg = {k: torch.zeros_like(v) for k, v in dp.items()}
+        adam = ops.DeviceAdam(ops.adam_groups(dp, dg, dm, dv, lrs),
+                              lr_final=[1.6e-6 * 2.75, 0, 0, 0, 0], decay_steps=7)
+        rng = np.random.default_rng(4)
+        for step in range(3):
+            bufs.project(gst)
+            drec = rng.normal(size=(3 * n, 9)).astype(np.float32)
+            drec[rng.uniform(size=3 * n) < 0.3] = 0.0
+            bufs.d_rec.copy_(torch.as_tensor(drec))
+            if fused:
+                bufs.project_bwd_adam(gst, adam)
+            else:
+                bufs.project_bwd(gst, ops.grads_struct(dg, n))
+                adam(zero_grad=True)
+        torch.cuda.synchronize()
+        runs.append(({k: v.cpu().numpy() for k, v in dp.items()},
+                     {k: v.cpu().numpy() for k, v in dm.items()},
+                     {k: v.cpu().numpy() for k, v in dv.items()}, int(adam.step_dev.item())))
+    for a, b in zip(runs[0][:3], runs[1][:3]):
+        for k in a:
+            np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    assert runs[0][3] == runs[1][3] == 3
+    assert not np.array_equal(runs[1][0]["mean"], params["mean"])
+
+
 # ------------------------------------------------------------------ loss, Adam
 
 @pytest.mark.parametrize("S,H,W,lam", [(2, 70, 95, 0.2), (1, 33, 40, 0.5), (1, 100, 170, 0.2), (1, 1, 1, 0.2)])
