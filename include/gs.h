@@ -379,6 +379,71 @@ gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
                               float beta2, float eps, int32_t* step_dev, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Adaptive density control of the 3D-GS method each partition is trained
+ * with (Sec. II "Parallel Training"; the paper keeps its defaults): every
+ * few hundred steps, Gaussians whose mean screen-space position gradient is
+ * large are cloned (small ones) or split in two (large ones), faint or
+ * oversized ones are pruned, and opacities are periodically clamped.
+ *   per step:   gs_densify_stats after gs_raster_bwd
+ *   densify:    gs_densify_select -> (host reads n_out) -> gs_densify_apply
+ *               into arrays of n_out Gaussians; the caller resets the
+ *               statistics (gs_zero)
+ * A Gaussian's state: parameters in the planar layouts of gs_gaussians and
+ * its Adam moments in the same layouts, in the order mean, log_scale, quat,
+ * opacity_logit, color (m and v of a group may both be NULL).             */
+typedef struct {
+  float* param[5];
+  float* m[5];
+  float* v[5];
+  int64_t n;
+} gs_gaussian_state;
+
+/* accum[g] += sum over g's visible pairs (n_tiles > 0) of |(dL/dmean2d_x W/2,
+ * dL/dmean2d_y H/2)| (the gradient of the projected mean in normalised
+ * device coordinates; FP32, one correctly rounded operation at a time);
+ * denom[g] += their count.  d_rec as gs_raster_bwd writes it; accum, denom [n] device.      */
+gs_status gs_densify_stats(const gs_views* views, const gs_tiling* tiling,
+                           const gs_projected* proj, const float* d_rec, int64_t n,
+                           float* accum, float* denom, void* stream);
+
+size_t gs_densify_workspace_bytes(int64_t n);
+
+/* Per Gaussian (FP32 comparisons of the inputs with the thresholds):
+ * faint = opacity_logit < min_opacity_logit; grow = denom > 0 and
+ * accum >= grad_threshold x denom (exact); L = max log-scale.  Action:
+ *   faint                              -> dropped
+ *   grow, L <= max_log_scale_clone     -> kept and cloned (2 outputs)
+ *   grow, L >  max_log_scale_clone     -> split into 2 children with
+ *                                         log-scales minus log_split
+ *   otherwise                          -> kept
+ * and any output whose largest log-scale exceeds max_log_scale is dropped.
+ * action [n] i32 device (0 drop, 1 keep, 2 clone, 3 split); n_out: one
+ * device i64, the number of outputs; ws (gs_densify_workspace_bytes, 8-byte
+ * aligned) keeps the per-block output offsets for gs_densify_apply.        */
+gs_status gs_densify_select(const gs_gaussian_state* state, const float* accum,
+                            const float* denom, float grad_threshold,
+                            float max_log_scale_clone, float min_opacity_logit,
+                            float max_log_scale, float log_split, void* ws,
+                            size_t ws_bytes, int32_t* action, int64_t* n_out,
+                            void* stream);
+
+/* Writes the outputs in input order: a kept Gaussian once with its moments;
+ * a clone twice, the copy with zero moments; a split Gaussian as two
+ * children c = 0, 1 at mean + R(q/|q|) (exp(log_scale) * z[g][c]) with
+ * log_scale - log_split, the rest of its parameters copied, zero moments.
+ * z [n][2][3] device standard normal samples (the random draws of the
+ * split, passed in).  in / action / ws from gs_densify_select; out->n must
+ * be its n_out (outputs past out->n are not written).  in and out must not
+ * overlap.                                                                  */
+gs_status gs_densify_apply(const gs_gaussian_state* in, const int32_t* action,
+                           const void* ws, const float* z, float log_split,
+                           gs_gaussian_state* out, void* stream);
+
+/* opacity_logit = min(opacity_logit, max_opacity_logit); the opacity
+ * group's moments (if given) are cleared.                                   */
+gs_status gs_opacity_reset(gs_gaussian_state* state, float max_opacity_logit, void* stream);
+
+/* ------------------------------------------------------------------------
  * Learned initialisation.  The paper places one Gaussian at every point of
  * the extracted isosurface (Sec. II, "Isosurface Extraction") and leaves its
  * starting shape to the 3D-GS default (isotropic, scale from the 3 nearest

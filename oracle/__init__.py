@@ -6,8 +6,10 @@ code with the GPU library ``paper_2509_12138_amd`` and never imports it.
 
 The heavy definitions (projection, per-pixel compositing and its analytic
 backward, projection backward, tile binning + sort, masked L1 + D-SSIM, brute
-force k-NN) are plain C in ``gs_oracle.c``; Adam and the initialisation MLP
-are plain numpy below.  Everything is FP64.  Which passage each function
+force k-NN) are plain C in ``gs_oracle.c``; Adam, the initialisation MLP and
+the adaptive density control are plain numpy below.  Everything is FP64,
+except the density statistics and decisions, which are FP32 integers-by-
+comparison (see that section).  Which passage each function
 follows is stated in its docstring; the paper itself (Sec. II) delegates the
 training step to the 3D-GS method it cites, so the oracle restates that
 method's standard definitions.
@@ -418,3 +420,120 @@ def mlp_loss(y, t):
     # derivative of |c| through the normalisation q -> q/|q|
     d[:, 3:7] = -np.sign(c)[:, None] * (t[:, 3:7] - qh * c[:, None]) / qn[:, None] / n
     return L / n, d
+
+
+# --------------------------------------------------------------------------
+# Adaptive density control (clone / split / prune / opacity reset) of the
+# 3D-GS method the partitions are trained with.  The statistics and the
+# decisions are integers decided by FP32 values, so they are computed in
+# FP32 with the device's operation order (one IEEE operation at a time);
+# the new parameters are FP64.
+# --------------------------------------------------------------------------
+
+ACT_DROP, ACT_KEEP, ACT_CLONE, ACT_SPLIT = 0, 1, 2, 3
+
+
+def densify_stats(d_rec, n_tiles, n, W, H, accum, denom):
+    """Add one step's statistics: for every slot s (pairs s*n .. s*n+n-1 of
+    a single-partition view set) and visible pair (n_tiles > 0), the norm of
+    (dL/dx W/2, dL/dy H/2) (the gradient of the projected mean in normalised
+    device coordinates) to accum and 1 to denom.  FP32 throughout."""
+    f = np.float32
+    d_rec = np.asarray(d_rec, f).reshape(-1, 9)
+    n_tiles = np.asarray(n_tiles).reshape(-1)
+    a = np.array(accum, f, copy=True)
+    d = np.array(denom, f, copy=True)
+    hw, hh = f(0.5 * W), f(0.5 * H)
+    for s in range(len(n_tiles) // n):
+        vis = n_tiles[s * n:(s + 1) * n] > 0
+        gx = d_rec[s * n:(s + 1) * n, 0] * hw
+        gy = d_rec[s * n:(s + 1) * n, 1] * hh
+        norm = np.sqrt(gx * gx + gy * gy)
+        a = np.where(vis, a + norm, a).astype(f)
+        d = np.where(vis, d + f(1.0), d).astype(f)
+    return a, d
+
+
+def densify_select(log_scale, opacity_logit, accum, denom, grad_threshold, max_log_scale_clone,
+                   min_opacity_logit, max_log_scale, log_split):
+    """Action per Gaussian: dropped when faint (opacity logit below the
+    threshold); cloned when its mean gradient norm accum / denom reaches the
+    threshold (decided exactly, as accum >= threshold x denom)
+    and its largest log-scale is at most max_log_scale_clone; split when
+    the gradient reaches it and the Gaussian is larger; kept otherwise; an
+    output whose largest log-scale exceeds max_log_scale is dropped (split
+    children are log_split smaller).  Returns (action [n], n_out)."""
+    f = np.float32
+    ls = np.asarray(log_scale, f).max(axis=0)
+    acc = np.asarray(accum, f)
+    den = np.asarray(denom, f)
+    # mean >= threshold decided exactly (FP64 products of FP32 values are exact)
+    grow = (den > 0) & (acc.astype(np.float64) >= np.float64(f(grad_threshold)) * den.astype(np.float64))
+    faint = np.asarray(opacity_logit, f) < f(min_opacity_logit)
+    small = ls <= f(max_log_scale_clone)
+    act = np.full(len(ls), ACT_KEEP, np.int32)
+    act[grow & small] = ACT_CLONE
+    act[grow & ~small] = ACT_SPLIT
+    too_big = np.where(act == ACT_SPLIT, (ls - f(log_split)).astype(f), ls) > f(max_log_scale)
+    act[too_big | faint] = ACT_DROP
+    counts = np.select([act == ACT_KEEP, act == ACT_CLONE, act == ACT_SPLIT], [1, 2, 2], 0)
+    return act, int(counts.sum())
+
+
+def _rot_wxyz(q):
+    q = np.asarray(q, np.float64)
+    q = q / np.linalg.norm(q, axis=0, keepdims=True)
+    w, x, y, z = q
+    return np.stack([np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)]),
+                     np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)]),
+                     np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)])])
+
+
+def densify_apply(params, m, v, action, z, log_split):
+    """The new Gaussians in input order: kept ones with their moments; a
+    clone as the original then a copy with zero moments; a split Gaussian
+    as two children c = 0, 1 at mean + R(q) (exp(log_scale) * z[g, c]) with
+    log-scale - log_split and zero moments.  params / m / v: dicts of planar
+    [rows][n] arrays; z [n, 2, 3].  Returns (params, m, v) dicts, FP64."""
+    names = ("mean", "log_scale", "quat", "opacity_logit", "color")
+    P = {k: np.atleast_2d(np.asarray(params[k], np.float64)) for k in names}
+    M = {k: np.atleast_2d(np.asarray(m[k], np.float64)) for k in names}
+    Vv = {k: np.atleast_2d(np.asarray(v[k], np.float64)) for k in names}
+    z = np.asarray(z, np.float64)
+    outs = {k: [] for k in names}
+    om = {k: [] for k in names}
+    ov = {k: [] for k in names}
+    R = _rot_wxyz(P["quat"])                      # [3, 3, n]
+    s = np.exp(P["log_scale"])
+    for g, a in enumerate(np.asarray(action)):
+        if a == ACT_DROP:
+            continue
+        if a in (ACT_KEEP, ACT_CLONE):
+            for c in range(1 if a == ACT_KEEP else 2):
+                for k in names:
+                    outs[k].append(P[k][:, g])
+                    om[k].append(M[k][:, g] if c == 0 else np.zeros(len(M[k])))
+                    ov[k].append(Vv[k][:, g] if c == 0 else np.zeros(len(Vv[k])))
+            continue
+        for c in range(2):
+            child = {k: P[k][:, g].copy() for k in names}
+            child["mean"] = P["mean"][:, g] + R[:, :, g] @ (s[:, g] * z[g, c])
+            child["log_scale"] = P["log_scale"][:, g] - log_split
+            for k in names:
+                outs[k].append(child[k])
+                om[k].append(np.zeros(len(M[k])))
+                ov[k].append(np.zeros(len(Vv[k])))
+
+    def stack(lst, rows):
+        return np.stack(lst, axis=1) if lst else np.zeros((rows, 0))
+    res = []
+    for d in (outs, om, ov):
+        r = {k: stack(d[k], len(P[k])) for k in names}
+        r["opacity_logit"] = r["opacity_logit"][0]
+        res.append(r)
+    return tuple(res)
+
+
+def opacity_reset(opacity_logit, max_opacity_logit):
+    """Opacity clamp of the periodic reset: min(logit, threshold)."""
+    return np.minimum(np.asarray(opacity_logit, np.float64), max_opacity_logit)

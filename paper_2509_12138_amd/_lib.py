@@ -71,6 +71,10 @@ class gs_mlp_grads(C.Structure):
                 ("dx", vp)]
 
 
+class gs_gaussian_state(C.Structure):
+    _fields_ = [("param", vp * 5), ("m", vp * 5), ("v", vp * 5), ("n", i64)]
+
+
 P = C.POINTER
 F3 = f32 * 3
 
@@ -97,6 +101,12 @@ SIGNATURES = {
     "gs_adam_dev": (i32, [P(gs_adam_group), i32, P(f32), i32, f32, f32, f32, vp, i32, vp]),
     "gs_project_bwd_adam": (i32, [P(gs_gaussians), P(gs_views), P(gs_tiling), P(gs_projected),
                                   vp, P(gs_adam_group), P(f32), i32, f32, f32, f32, vp, vp]),
+    "gs_densify_stats": (i32, [P(gs_views), P(gs_tiling), P(gs_projected), vp, i64, vp, vp, vp]),
+    "gs_densify_workspace_bytes": (sz, [i64]),
+    "gs_densify_select": (i32, [P(gs_gaussian_state), vp, vp, f32, f32, f32, f32, f32, vp, sz,
+                                vp, vp, vp]),
+    "gs_densify_apply": (i32, [P(gs_gaussian_state), vp, vp, vp, f32, P(gs_gaussian_state), vp]),
+    "gs_opacity_reset": (i32, [P(gs_gaussian_state), f32, vp]),
     "gs_zero": (i32, [vp, sz, vp]),
     "gs_check_status": (i32, [vp, vp, P(i64)]),
     "gs_last_error": (C.c_char_p, []),

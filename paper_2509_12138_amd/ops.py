@@ -454,3 +454,73 @@ def knn_mean_distance(points, k=3):
     """Mean distance to the k nearest neighbours of each device point."""
     _, d = knn(points, k)
     return d.mean(dim=1)
+
+
+# --------------------------------------------------------------------------
+# adaptive density control
+# --------------------------------------------------------------------------
+
+def gaussian_state(params, m=None, v=None):
+    """gs_gaussian_state over planar parameter tensors (and Adam moments)."""
+    st = _lib.gs_gaussian_state()
+    for i, k in enumerate(PARAM_NAMES):
+        st.param[i] = params[k].data_ptr()
+        st.m[i] = m[k].data_ptr() if m is not None else None
+        st.v[i] = v[k].data_ptr() if v is not None else None
+    st.n = params["opacity_logit"].shape[-1]
+    return st
+
+
+class Densifier:
+    """Statistics and the clone / split / prune / opacity-reset calls of
+    the 3D-GS density control for n Gaussians."""
+
+    def __init__(self, n, device="cuda"):
+        self.device = device
+        self.resize(n)
+
+    def resize(self, n):
+        self.n = int(n)
+        self.accum = torch.zeros(max(self.n, 1), dtype=torch.float32, device=self.device)
+        self.denom = torch.zeros(max(self.n, 1), dtype=torch.float32, device=self.device)
+        self.action = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)
+        nb = _lib.load().gs_densify_workspace_bytes(self.n)
+        self.ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+        self.n_out = torch.zeros(1, dtype=torch.int64, device=self.device)
+
+    def reset_stats(self, stream=None):
+        s = stream or stream_handle()
+        call("gs_zero", _ptr(self.accum), self.accum.numel() * 4, s)
+        call("gs_zero", _ptr(self.denom), self.denom.numel() * 4, s)
+
+    def stats(self, bufs: RasterBuffers, stream=None):
+        call("gs_densify_stats", C.byref(bufs.views.struct), C.byref(bufs.tiling),
+             C.byref(bufs.proj), _ptr(bufs.d_rec), self.n, _ptr(self.accum), _ptr(self.denom),
+             stream or stream_handle())
+
+    def select(self, params, m, v, grad_threshold, max_log_scale_clone, min_opacity_logit,
+               max_log_scale, log_split, stream=None):
+        """Actions on the device; returns the output count (synchronises)."""
+        st = gaussian_state(params, m, v)
+        call("gs_densify_select", C.byref(st), _ptr(self.accum), _ptr(self.denom),
+             float(grad_threshold), float(max_log_scale_clone), float(min_opacity_logit),
+             float(max_log_scale), float(log_split), _ptr(self.ws), self.ws.numel(),
+             _ptr(self.action), _ptr(self.n_out), stream or stream_handle())
+        return int(self.n_out.item())
+
+    def apply(self, params, m, v, n_out, z, log_split, stream=None):
+        """New (params, m, v) dicts of n_out Gaussians (after select)."""
+        P = {k: torch.empty(t.shape[:-1] + (n_out,), dtype=torch.float32, device=self.device)
+             for k, t in params.items()}
+        M = {k: torch.empty_like(t) for k, t in P.items()} if m is not None else None
+        V = {k: torch.empty_like(t) for k, t in P.items()} if v is not None else None
+        sin = gaussian_state(params, m, v)
+        sout = gaussian_state(P, M, V)
+        call("gs_densify_apply", C.byref(sin), _ptr(self.action), _ptr(self.ws), _ptr(z),
+             float(log_split), C.byref(sout), stream or stream_handle())
+        return P, M, V
+
+    @staticmethod
+    def opacity_reset(params, m, v, max_opacity_logit, stream=None):
+        st = gaussian_state(params, m, v)
+        call("gs_opacity_reset", C.byref(st), float(max_opacity_logit), stream or stream_handle())

@@ -5,11 +5,15 @@ each partition):
     gs_project -> gs_bin_sort -> gs_raster_fwd -> gs_loss -> gs_raster_bwd
     -> gs_project_bwd -> gs_adam (clears the gradients)
 Everything stays on the device; the duplicate-capacity status is read back
-only every ``check_every`` steps (the one host synchronisation).
+only every ``check_every`` steps (the one host synchronisation).  With a
+DensityControl, the 3D-GS adaptive density control runs between steps
+(statistics every step, clone / split / prune every ``interval`` steps,
+opacity reset every ``reset_interval`` steps).
 """
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
 import math
 import time
 
@@ -20,6 +24,27 @@ from . import _lib
 from . import ops
 
 DEFAULT_LR = dict(mean=1.6e-4, log_scale=5e-3, quat=1e-3, opacity_logit=5e-2, color=2.5e-3)
+
+
+@dataclasses.dataclass
+class DensityControl:
+    """Adaptive density control schedule and thresholds (the 3D-GS defaults):
+    statistics from `start` until `until`, densification every `interval`
+    steps after `start`, opacity reset every `reset_interval` steps; clone
+    when the largest scale is at most percent_dense x extent, else split
+    into two children with scales / split_divisor; prune opacity below
+    min_opacity and, after the first opacity reset, scales above
+    max_world_scale x extent."""
+    start: int = 500
+    until: int = 15000
+    interval: int = 100
+    grad_threshold: float = 2e-4
+    percent_dense: float = 0.01
+    reset_interval: int = 3000
+    min_opacity: float = 0.005
+    max_world_scale: float = 0.1
+    split_divisor: float = 1.6
+    seed: int = 0
 
 
 def mean_lr(step, extent, lr0=1.6e-4, lr1=1.6e-6, total=30000):
@@ -42,17 +67,11 @@ class PlainTrainer:
     def __init__(self, params, cams_np, targets, masks, tile=(16, 16), lam=0.2,
                  bg=(0.0, 0.0, 0.0), stored=True, extent=2.75, lrs=None, dup_capacity=None,
                  schedule="default", chunk=0, fwd_waves=1, deterministic=False, fused_adam=True,
-                 device="cuda"):
+                 density=None, device="cuda"):
         self.device = device
-        self.params = {k: torch.as_tensor(np.ascontiguousarray(v, np.float32)).to(device)
-                       if not torch.is_tensor(v) else v.contiguous().to(device)
-                       for k, v in params.items()}
-        self.n = self.params["opacity_logit"].shape[-1]
-        self.grads = {k: torch.zeros_like(v) for k, v in self.params.items()}
-        self.m = {k: torch.zeros_like(v) for k, v in self.params.items()}
-        self.v = {k: torch.zeros_like(v) for k, v in self.params.items()}
         self.V = len(cams_np)
         self.W, self.H = int(cams_np[0]["width"]), int(cams_np[0]["height"])
+        self.cams_np = cams_np
         self.cams = ops.Views.cams_to_device(cams_np, device)
         self.targets = targets
         self.masks = masks
@@ -60,27 +79,78 @@ class PlainTrainer:
         self.lam = lam
         self.extent = extent
         self.lrs = dict(DEFAULT_LR if lrs is None else lrs)
-        self.views = ops.Views.single(self.n, cams_np[:1], device)
-        self.views.use_cameras(self.cams[0:1])
-        self.bufs = ops.RasterBuffers(self.views, self.W, self.H, tile, dup_capacity=dup_capacity,
-                                      store_state=stored)
-        self.bufs.set_schedule(schedule, chunk=chunk, fwd_waves=fwd_waves,
-                               deterministic=deterministic)
+        self.tile, self.stored = tuple(tile), stored
+        self.plan = dict(mode=schedule, chunk=chunk, fwd_waves=fwd_waves,
+                         deterministic=deterministic)
         self.loss = ops.LossBuffers(1, self.H, self.W, device)
         self.mode = _lib.GS_BWD_STORED if stored else _lib.GS_BWD_RECOMPUTE
-        self.gst = ops.gaussians_struct(self.params)
-        self.grst = ops.grads_struct(self.grads, self.n)
-        self.groups = ops.adam_groups(self.params, self.grads, self.m, self.v, self.lrs)
         # fused projection backward + Adam: the step count and the position
         # lr decay live on the device
         self.fused_adam = fused_adam
-        if fused_adam:
-            lrs_dev = dict(self.lrs, mean=self.lrs["mean"] * extent)
-            self.dev_adam = ops.DeviceAdam(
-                ops.adam_groups(self.params, self.grads, self.m, self.v, lrs_dev),
-                lr_final=[1.6e-6 * extent, 0, 0, 0, 0], decay_steps=30000, device=device)
+        self.density = density
+        self.dev_adam = None
+        self.densifier = None
+        p = {k: torch.as_tensor(np.ascontiguousarray(v, np.float32)).to(device)
+             if not torch.is_tensor(v) else v.contiguous().to(device) for k, v in params.items()}
+        self._bind(p, {k: torch.zeros_like(v) for k, v in p.items()},
+                   {k: torch.zeros_like(v) for k, v in p.items()}, dup_capacity)
+        if density is not None:
+            self.gen = torch.Generator(device=device).manual_seed(int(density.seed))
         self.step_count = 0
         self.timing = None            # optional dict of lists of (start, end) events
+
+    def _bind(self, params, m, v, dup_capacity=None):
+        """Point every buffer and call structure at a (new) set of Gaussians
+        with their Adam moments; the device step count carries over."""
+        self.params, self.m, self.v = params, m, v
+        self.n = self.params["opacity_logit"].shape[-1]
+        self.grads = {k: torch.zeros_like(t) for k, t in self.params.items()}
+        self.views = ops.Views.single(self.n, self.cams_np[:1], self.device)
+        self.views.use_cameras(self.cams[0:1])
+        self.bufs = ops.RasterBuffers(self.views, self.W, self.H, self.tile,
+                                      dup_capacity=dup_capacity, store_state=self.stored)
+        self.bufs.set_schedule(self.plan["mode"], chunk=self.plan["chunk"],
+                               fwd_waves=self.plan["fwd_waves"],
+                               deterministic=self.plan["deterministic"])
+        self.gst = ops.gaussians_struct(self.params)
+        self.grst = ops.grads_struct(self.grads, self.n)
+        self.groups = ops.adam_groups(self.params, self.grads, self.m, self.v, self.lrs)
+        if self.fused_adam:
+            step_dev = self.dev_adam.step_dev if self.dev_adam is not None else None
+            lrs_dev = dict(self.lrs, mean=self.lrs["mean"] * self.extent)
+            self.dev_adam = ops.DeviceAdam(
+                ops.adam_groups(self.params, self.grads, self.m, self.v, lrs_dev),
+                lr_final=[1.6e-6 * self.extent, 0, 0, 0, 0], decay_steps=30000,
+                device=self.device)
+            if step_dev is not None:
+                self.dev_adam.step_dev = step_dev
+        if self.density is not None:
+            if self.densifier is None:
+                self.densifier = ops.Densifier(self.n, self.device)
+            else:
+                self.densifier.resize(self.n)
+
+    def densify(self):
+        """Clone / split / prune from the statistics gathered since the last
+        call (one host synchronisation for the new count); returns it."""
+        c = self.density
+        big = (math.log(c.max_world_scale * self.extent) if self.step_count > c.reset_interval
+               else float("inf"))
+        log_split = math.log(c.split_divisor)
+        n_out = self.densifier.select(self.params, self.m, self.v, c.grad_threshold,
+                                      math.log(c.percent_dense * self.extent),
+                                      math.log(c.min_opacity / (1.0 - c.min_opacity)), big,
+                                      log_split)
+        z = torch.randn((self.n, 2, 3), generator=self.gen, device=self.device)
+        P, M, V = self.densifier.apply(self.params, self.m, self.v, n_out, z, log_split)
+        per_gauss = self.bufs.dup_capacity / max(self.n, 1)
+        self._bind(P, M, V, dup_capacity=int(per_gauss * max(n_out, 1) * 1.2) + 4096)
+        self.densifier.reset_stats()
+        return n_out
+
+    def opacity_reset(self):
+        """Clamp every opacity to 0.01 and clear its Adam moments."""
+        ops.Densifier.opacity_reset(self.params, self.m, self.v, math.log(0.01 / 0.99))
 
     def fit_capacity(self, margin=1.5, views=None):
         """Size the duplicate buffers from the largest view's true count."""
@@ -117,6 +187,9 @@ class PlainTrainer:
         b.zero_d_rec()
         self._ev("raster_bwd")
         b.raster_bwd(self.loss.d_image, self.bg, self.mode)
+        c = self.density
+        if c is not None and self.step_count < c.until:
+            self.densifier.stats(b)
         self._ev("project_bwd")
         self.step_count += 1
         if self.fused_adam:
@@ -128,10 +201,24 @@ class PlainTrainer:
             self.groups[0].lr = mean_lr(self.step_count, self.extent, self.lrs["mean"])
             ops.adam_step(self.groups, self.step_count, zero_grad=True)
         self._ev("end")
+        if c is not None and self.step_count < c.until:
+            t = self.step_count
+            if t > c.start and t % c.interval == 0:
+                self.densify()
+            if t % c.reset_interval == 0:
+                self.opacity_reset()
 
-    def check(self):
-        """Synchronise and raise on duplicate overflow / non-finite loss."""
+    def check(self, grow=False):
+        """Synchronise and raise on duplicate overflow / non-finite loss.
+        With grow, an overflow instead enlarges the duplicate buffers to
+        1.25 x the count needed and training goes on (the steps since the
+        last check rasterised truncated lists); returns the count."""
         st, req = self.bufs.check()
+        if st == _lib.GS_ERR_CAPACITY and grow:
+            self.bufs.ensure_capacity(int(req * 1.25) + 4096)
+            self.bufs.clear_status()
+            self.capacity_grown = getattr(self, "capacity_grown", 0) + 1
+            return req
         if st != _lib.GS_OK:
             raise _lib.GSError("training step", st, _lib.last_error())
         return req
@@ -147,9 +234,9 @@ class PlainTrainer:
         return float(torch.stack(ps).mean())
 
     def train(self, steps, order_seed=0, eval_every=0, target_psnr=None, check_every=50,
-              log=None):
+              log=None, grow=False):
         """Run `steps` steps over a seeded view order.  Returns a history of
-        (step, wall seconds excluding evaluation, psnr)."""
+        (step, wall seconds excluding evaluation, psnr).  grow: see check()."""
         rng = np.random.default_rng(order_seed)
         order = []
         hist = []
@@ -161,7 +248,7 @@ class PlainTrainer:
                 order = list(rng.permutation(self.V))
             self.step(order.pop())
             if check_every and (s + 1) % check_every == 0:
-                self.check()
+                self.check(grow=grow)
             if eval_every and (s + 1) % eval_every == 0:
                 torch.cuda.synchronize()
                 train_time += time.perf_counter() - t0

@@ -23,6 +23,7 @@ partition's time is taken at its first evaluation at or above the target.
     python -m paper_2509_12138_amd.ttt probe   [--scale S]
     python -m paper_2509_12138_amd.ttt batched [--scale S] [--target 35]
     python -m paper_2509_12138_amd.ttt learned [--scale S] [--target 35]
+    python -m paper_2509_12138_amd.ttt adc     [--scale S] [--steps K]
 """
 from __future__ import annotations
 
@@ -242,6 +243,52 @@ def cmd_batched(a):
     print(json.dumps(res), flush=True)
 
 
+def cmd_adc(a):
+    """The 3D-GS adaptive density control (clone / split / prune / opacity
+    reset) on the mixing-layer partition: the plain trainer from a sparse
+    initialisation (scale x 1M Gaussians on the surface), with and without
+    density control, same views, targets and steps; masked PSNR and the
+    number of Gaussians against steps and training time."""
+    from .train import DensityControl, PlainTrainer
+    wl = workloads.realistic_partition(dict(n=int(1_000_000 * a.scale)))
+    cams = wl["cams"]
+    targets, masks = workloads.render_targets_gpu(wl["reference"], cams)
+    tile, sched, chunk, nw, det = a.plan
+    out = dict(experiment="density_control", n0=int(len(wl["points"])), steps=a.steps,
+               views=len(cams), arms={})
+    for arm in ("plain", "density"):
+        dc = DensityControl(seed=1) if arm == "density" else None
+        tr = PlainTrainer(wl["params"], cams, targets, masks, tile=tile, schedule=sched,
+                          chunk=chunk, fwd_waves=nw, deterministic=det, density=dc)
+        tr.fit_capacity(views=range(0, len(cams), max(1, len(cams) // 8)))
+        dens_t = []
+        if dc is not None:
+            plain_densify = tr.densify
+
+            def timed():
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = plain_densify()
+                torch.cuda.synchronize()
+                dens_t.append(time.perf_counter() - t0)
+                return r
+            tr.densify = timed
+        hist = []
+
+        def record(s, t, p):
+            hist.append((int(s), float(t), float(p), int(tr.n)))
+            log(f"{arm} step {s}: {t:.2f} s, psnr {p:.2f}, n {tr.n}")
+        # Gaussians grow during training: buffers grow on overflow instead of failing
+        tr.train(a.steps, order_seed=77, eval_every=a.eval_every, log=record, check_every=10,
+                 grow=True)
+        out["arms"][arm] = dict(history=hist, densify_calls=len(dens_t),
+                                densify_seconds_mean=float(np.mean(dens_t)) if dens_t else None,
+                                capacity_grown=getattr(tr, "capacity_grown", 0))
+        del tr
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def octant_partition(n, seed, ref_factor=2.0, grid=GRID):
     """The octant x, y, z >= 0 of the bumpy-sphere field padded by the ghost
     margin across its three internal faces (one of eight partitions)."""
@@ -331,7 +378,7 @@ def cmd_learned(a):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("experiment", choices=["probe", "batched", "learned"])
+    ap.add_argument("experiment", choices=["probe", "batched", "learned", "adc"])
     ap.add_argument("--scale", type=float, default=1.0, help="multiplies every Gaussian count")
     ap.add_argument("--target", type=float, default=35.0)
     ap.add_argument("--steps", type=int, default=2000)
@@ -355,7 +402,7 @@ def main(argv=None):
     a.plan = ((tw, th), a.schedule, a.chunk, a.fwd_waves, bool(a.deterministic))
     if not torch.cuda.is_available():
         sys.exit("ttt needs a GPU")
-    dict(probe=cmd_probe, batched=cmd_batched, learned=cmd_learned)[a.experiment](a)
+    dict(probe=cmd_probe, batched=cmd_batched, learned=cmd_learned, adc=cmd_adc)[a.experiment](a)
 
 
 if __name__ == "__main__":

@@ -1,0 +1,132 @@
+"""GPU parity of the adaptive density control calls (gs_densify_stats,
+gs_densify_select, gs_densify_apply, gs_opacity_reset) against the oracle:
+statistics and actions bit-exact (FP32 decisions on both sides), new
+parameters to 1e-6, moments exact."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_12138_amd import scene
+from _gpu_helpers import say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NAMES = ("mean", "log_scale", "quat", "opacity_logit", "color")
+
+
+@pytest.fixture(scope="module")
+def ops(gpu):
+    from paper_2509_12138_amd import ops as _ops
+    return _ops
+
+
+def _params(n, rng):
+    return dict(mean=rng.normal(size=(3, n)).astype(np.float32),
+                log_scale=rng.normal(-3.0, 0.8, (3, n)).astype(np.float32),
+                quat=rng.normal(size=(4, n)).astype(np.float32),
+                opacity_logit=rng.normal(0.0, 3.0, n).astype(np.float32),
+                color=rng.normal(size=(3, n)).astype(np.float32))
+
+
+def _dev(d):
+    return {k: torch.as_tensor(v).cuda().contiguous() for k, v in d.items()}
+
+
+@pytest.mark.parametrize("S", [1, 3])
+def test_stats_bit_exact(ops, S):
+    say("densify stats", S)
+    n, W, H = 3001, 320, 180
+    rng = np.random.default_rng(50 + S)
+    views = ops.Views.single(n, scene.orbit_cameras(S, W, H))
+    bufs = ops.RasterBuffers(views, W, H, (16, 16))
+    drec = rng.normal(0, 1e-3, (S * n, 9)).astype(np.float32)
+    nt = rng.integers(0, 4, S * n).astype(np.int32)
+    bufs.d_rec.copy_(torch.as_tensor(drec))
+    bufs.n_tiles.copy_(torch.as_tensor(nt))
+    den = ops.Densifier(n)
+    a0 = rng.uniform(0, 1e-3, n).astype(np.float32)
+    c0 = rng.integers(0, 5, n).astype(np.float32)
+    den.accum.copy_(torch.as_tensor(a0))
+    den.denom.copy_(torch.as_tensor(c0))
+    den.stats(bufs)
+    torch.cuda.synchronize()
+    ra, rc = oracle.densify_stats(drec, nt, n, W, H, a0, c0)
+    np.testing.assert_array_equal(den.accum.cpu().numpy(), ra)
+    np.testing.assert_array_equal(den.denom.cpu().numpy(), rc)
+
+
+@pytest.mark.parametrize("n", [1, 255, 4099])
+def test_select_and_apply_match_oracle(ops, n):
+    say("densify select/apply", n)
+    rng = np.random.default_rng(n)
+    p = _params(n, rng)
+    m = {k: rng.normal(size=v.shape).astype(np.float32) for k, v in p.items()}
+    v = {k: rng.uniform(size=x.shape).astype(np.float32) for k, x in p.items()}
+    acc = rng.uniform(0, 4e-4, n).astype(np.float32)
+    cnt = rng.integers(0, 3, n).astype(np.float32)
+    th = dict(grad_threshold=2e-4, max_log_scale_clone=-3.0, min_opacity_logit=-4.6,
+              max_log_scale=-1.5, log_split=math.log(1.6))
+    act_ref, n_ref = oracle.densify_select(p["log_scale"], p["opacity_logit"], acc, cnt, **th)
+    den = ops.Densifier(n)
+    den.accum.copy_(torch.as_tensor(acc))
+    den.denom.copy_(torch.as_tensor(cnt))
+    P, M, V = _dev(p), _dev(m), _dev(v)
+    n_out = den.select(P, M, V, **th)
+    assert n_out == n_ref
+    np.testing.assert_array_equal(den.action[:n].cpu().numpy(), act_ref)
+    if n >= 255:
+        assert len(set(act_ref.tolist())) == 4          # every action occurs
+    z = rng.normal(size=(n, 2, 3)).astype(np.float32)
+    zd = torch.as_tensor(z).cuda()
+    P2, M2, V2 = den.apply(P, M, V, n_out, zd, th["log_split"])
+    torch.cuda.synchronize()
+    rp, rm, rv = oracle.densify_apply(p, m, v, act_ref, z, th["log_split"])
+    for k in NAMES:
+        got = P2[k].cpu().numpy().astype(np.float64)
+        np.testing.assert_allclose(got, rp[k], rtol=1e-6, atol=1e-6, err_msg=k)
+        np.testing.assert_array_equal(M2[k].cpu().numpy(), rm[k].astype(np.float32), err_msg=k)
+        np.testing.assert_array_equal(V2[k].cpu().numpy(), rv[k].astype(np.float32), err_msg=k)
+    # copies that are not split children are bit-exact
+    keep = np.repeat(act_ref, np.select([act_ref == 1, act_ref == 2, act_ref == 3], [1, 2, 2], 0))
+    exact = keep != oracle.ACT_SPLIT
+    for k in ("quat", "opacity_logit", "color"):
+        np.testing.assert_array_equal(np.atleast_2d(P2[k].cpu().numpy())[:, exact],
+                                      np.atleast_2d(rp[k])[:, exact].astype(np.float32))
+
+
+def test_apply_into_short_arrays_writes_only_what_fits(ops):
+    say("densify apply short")
+    n = 600
+    rng = np.random.default_rng(7)
+    p = _params(n, rng)
+    den = ops.Densifier(n)
+    den.accum.fill_(1.0)
+    den.denom.fill_(1.0)
+    P = _dev(p)
+    n_out = den.select(P, None, None, 0.5, -3.0, -1e9, 1e9, math.log(1.6))
+    assert n_out == 2 * n
+    z = torch.zeros((n, 2, 3), device="cuda")
+    full, _, _ = den.apply(P, None, None, n_out, z, math.log(1.6))
+    short, _, _ = den.apply(P, None, None, n_out - 5, z, math.log(1.6))
+    torch.cuda.synchronize()
+    for k in NAMES:
+        torch.testing.assert_close(short[k], full[k][..., :n_out - 5], rtol=0, atol=0)
+
+
+def test_opacity_reset_matches_oracle(ops):
+    say("opacity reset")
+    n = 1000
+    rng = np.random.default_rng(8)
+    p = _params(n, rng)
+    m = {k: rng.normal(size=v.shape).astype(np.float32) for k, v in p.items()}
+    P, M, V = _dev(p), _dev(m), _dev(m)
+    thr = math.log(0.01 / 0.99)
+    ops.Densifier.opacity_reset(P, M, V, thr)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(P["opacity_logit"].cpu().numpy(),
+                                  oracle.opacity_reset(p["opacity_logit"], np.float32(thr)).astype(np.float32))
+    assert float(M["opacity_logit"].abs().max()) == 0.0 and float(V["opacity_logit"].abs().max()) == 0.0
+    np.testing.assert_array_equal(M["mean"].cpu().numpy(), m["mean"])

@@ -77,3 +77,36 @@ def test_training_step_matches_oracle_step(tiny):
         agree = np.mean(np.sign(step_got[big]) == np.sign(step_ref[big]))
         assert agree > 0.995, (k, agree)
         np.testing.assert_allclose(np.abs(step_got[big]), lrs[k], rtol=1e-3)
+
+
+def test_density_control_changes_the_model_and_keeps_training(tiny):
+    """The trainer's adaptive density control on the tiny configuration: the
+    densifications change the number of Gaussians, every buffer follows the
+    new count, training continues on the new set and improves PSNR (the
+    selection and the new parameters themselves are checked against the
+    oracle in test_gpu_density)."""
+    say("density control")
+    from paper_2509_12138_amd.train import DensityControl, PlainTrainer
+    wl, targets, masks = tiny
+    # no opacity reset inside the run (it empties the image for a while;
+    # the reset itself is checked against the oracle in test_gpu_density)
+    dc = DensityControl(start=10, until=60, interval=10, grad_threshold=1e-4,
+                        reset_interval=1000, seed=3)
+    tr = PlainTrainer(wl["params"], wl["cams"], targets, masks, density=dc)
+    tr.fit_capacity()
+    p0 = tr.evaluate()
+    n_seen = [tr.n]
+    rng = np.random.default_rng(5)
+    for s in range(60):
+        tr.step(int(rng.integers(tr.V)))
+        if tr.n != n_seen[-1]:
+            n_seen.append(tr.n)
+    tr.check()
+    assert len(n_seen) > 1
+    p1 = tr.evaluate()
+    say(f"psnr {p0:.2f} -> {p1:.2f}, n {n_seen}")
+    assert np.isfinite(p1) and p1 > p0
+    for k, v in tr.params.items():
+        assert torch.isfinite(v).all(), k
+        assert v.shape[-1] == tr.n, k
+    assert tr.views.struct.total_pairs == tr.n and tr.dev_adam.groups[0].count == 3 * tr.n
