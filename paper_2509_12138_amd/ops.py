@@ -168,7 +168,7 @@ class RasterBuffers:
         s = stream or stream_handle()
         call("gs_bin_sort", C.byref(self.proj), C.byref(self.views.struct), C.byref(self.tiling),
              self.dup_capacity, _ptr(self.ws), self.ws.numel(), _ptr(self.keys), _ptr(self.ids),
-             _ptr(self.ranges), _ptr(self.pair_first),
+             _ptr(self.ranges), _ptr(self.pair_first) if self.deterministic else None,
              _ptr(self.emit) if self.deterministic else None, _ptr(self.status), s)
 
     # ---------------------------------------------------------- tile schedule
