@@ -86,23 +86,51 @@ def camera_vector(cam):
 # Projection (EWA splatting step of the 3D-GS method)
 # --------------------------------------------------------------------------
 
+def sh_degree_of(color):
+    """Spherical-harmonic degree D of a colour array with 3 (D+1)^2 rows."""
+    rows = np.shape(color)[0]
+    D = int(round(np.sqrt(rows / 3.0))) - 1
+    if D < 0 or D > SH_MAX or 3 * (D + 1) ** 2 != rows:
+        raise ValueError(f"colour array has {rows} rows; expected 3 (D+1)^2, D <= {SH_MAX}")
+    return D
+
+
+SH_MAX = 3
+
+
+def sh_basis(D, dirs):
+    """Real spherical harmonics (Condon-Shortley phase, index l*l + l + m) of
+    degree <= D at unit vectors dirs [p, 3]: returns Y [p, K] and the
+    gradient of their Cartesian polynomials [p, K, 3], K = (D+1)^2."""
+    lib = _load()
+    d = np.ascontiguousarray(np.asarray(dirs, np.float64).reshape(-1, 3))
+    K = (D + 1) ** 2
+    Y = np.zeros((len(d), K)); G = np.zeros((len(d), K, 3))
+    lib.or_sh_basis(ctypes.c_int(D), ctypes.c_int64(len(d)), _p(d), _p(Y), _p(G))
+    return Y, G
+
+
 def project(params, cam, tile=(16, 16)):
     """Project every Gaussian through one camera (3D-GS projection step).
 
     params: dict of planar SoA arrays mean [3,n], log_scale [3,n], quat [4,n],
-    opacity_logit [n], color [3,n].  Returns a dict of FP64 SoA outputs plus
-    integer pixel/tile bboxes [4,n] (tx0, ty0, tx1, ty1), n_tiles and valid.
+    opacity_logit [n], color [3(D+1)^2, n] (spherical-harmonic coefficient k
+    of channel c in row 3k + c; D = 0 is the plain colour).  Returns a dict
+    of FP64 SoA outputs plus integer pixel/tile bboxes [4,n] (tx0, ty0, tx1,
+    ty1), n_tiles and valid.
     """
     lib = _load()
     mean = _f64(params["mean"]); n = mean.shape[1]
     ls = _f64(params["log_scale"]); q = _f64(params["quat"])
     ol = _f64(params["opacity_logit"]); col = _f64(params["color"])
+    D = sh_degree_of(col)
     cv, znear, W, H = camera_vector(cam)
     out = dict(mean2d=np.zeros((2, n)), conic=np.zeros((3, n)), depth=np.zeros(n),
                opacity=np.zeros(n), rgb=np.zeros((3, n)), cov2d=np.zeros((3, n)),
                pix_bbox=np.zeros((4, n), np.int32), tile_bbox=np.zeros((4, n), np.int32),
                n_tiles=np.zeros(n, np.int32), valid=np.zeros(n, np.int32))
-    lib.or_project(ctypes.c_int64(n), _p(mean), _p(ls), _p(q), _p(ol), _p(col), _p(cv),
+    lib.or_project(ctypes.c_int64(n), _p(mean), _p(ls), _p(q), _p(ol), _p(col), ctypes.c_int(D),
+                   _p(cv),
                    ctypes.c_double(znear), ctypes.c_int(W), ctypes.c_int(H),
                    ctypes.c_int(tile[0]), ctypes.c_int(tile[1]),
                    _p(out["mean2d"]), _p(out["conic"]), _p(out["depth"]), _p(out["opacity"]),
@@ -178,10 +206,12 @@ def project_bwd(params, cam, grads2d, tile=(16, 16)):
     mean = _f64(params["mean"]); n = mean.shape[1]
     ls = _f64(params["log_scale"]); q = _f64(params["quat"])
     ol = _f64(params["opacity_logit"]); col = _f64(params["color"])
+    D = sh_degree_of(col)
     cv, znear, W, H = camera_vector(cam)
     g = dict(mean=np.zeros((3, n)), log_scale=np.zeros((3, n)), quat=np.zeros((4, n)),
-             opacity_logit=np.zeros(n), color=np.zeros((3, n)))
-    lib.or_project_bwd(ctypes.c_int64(n), _p(mean), _p(ls), _p(q), _p(ol), _p(col), _p(cv),
+             opacity_logit=np.zeros(n), color=np.zeros(col.shape))
+    lib.or_project_bwd(ctypes.c_int64(n), _p(mean), _p(ls), _p(q), _p(ol), _p(col),
+                       ctypes.c_int(D), _p(cv),
                        ctypes.c_double(znear), W, H, tile[0], tile[1],
                        _p(_f64(grads2d["d_mean2d"])), _p(_f64(grads2d["d_conic"])),
                        _p(_f64(grads2d["d_opacity"])), _p(_f64(grads2d["d_rgb"])),

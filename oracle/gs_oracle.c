@@ -26,7 +26,6 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define OR_C0 0.28209479177387814   /* degree-0 SH basis: 1 / (2 sqrt(pi)) */
 #define OR_DILATE 0.3               /* low-pass added to the 2D covariance  */
 #define OR_FRUSTUM 1.3              /* Jacobian clamp, x tan(fov/2)         */
 #define OR_ALPHA_MAX 0.99
@@ -45,10 +44,117 @@ static void quat_to_rot(const double q[4], double R[9]) {
   R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
 }
 
+/* ---------------------------------------------------------------------- */
+/* View-dependent colour: real spherical harmonics                          */
+/* ---------------------------------------------------------------------- */
+
+#define OR_SH_MAX 3                 /* highest degree of the colour model   */
+#define OR_SH_K ((OR_SH_MAX + 1) * (OR_SH_MAX + 1))
+
+/* Coefficients c[0..l] of the Legendre polynomial P_l (Bonnet recurrence
+ * (j+1) P_{j+1} = (2j+1) z P_j - j P_{j-1}).                               */
+static void legendre_coeffs(int l, double c[OR_SH_MAX + 1]) {
+  double pm[OR_SH_MAX + 2] = {0}, p[OR_SH_MAX + 2] = {0}, nx[OR_SH_MAX + 2];
+  p[0] = 1.0;                                          /* P_0 */
+  for (int j = 0; j < l; ++j) {
+    for (int i = 0; i <= OR_SH_MAX + 1; ++i) {
+      double zp = i > 0 ? p[i - 1] : 0.0;
+      nx[i] = ((2 * j + 1) * zp - j * pm[i]) / (j + 1);
+    }
+    memcpy(pm, p, sizeof(p));
+    memcpy(p, nx, sizeof(p));
+  }
+  for (int i = 0; i <= OR_SH_MAX; ++i) c[i] = p[i];
+}
+
+/* Value at z of the m-th derivative of the polynomial c[0..deg].           */
+static double poly_deriv_eval(const double* c, int deg, int m, double z) {
+  double r = 0.0;
+  for (int i = deg; i >= m; --i) {
+    double f = 1.0;
+    for (int j = 0; j < m; ++j) f *= (double)(i - j);
+    r = r * z + f * c[i];
+  }
+  return r;
+}
+
+static double factorial(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= i;
+  return f;
+}
+
+/* Real spherical harmonics of degree <= D at the unit vector d, Condon-
+ * Shortley phase included, index l*l + l + m (m = -l..l).  With P_l the
+ * Legendre polynomial, D^m P_l its m-th derivative and
+ * K_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!):
+ *   Y_l0  = K_l0 P_l(z)
+ *   Y_lm  = (-1)^m sqrt(2) K_lm D^m P_l(z) Re((x + i y)^m)     (m > 0)
+ *   Y_l-m = (-1)^m sqrt(2) K_lm D^m P_l(z) Im((x + i y)^m)
+ * which is the textbook definition written with
+ * sin^m(theta) e^{i m phi} = (x + i y)^m on the sphere.  grad[k] is the
+ * gradient of the k-th expression as a polynomial in (x, y, z); its part
+ * tangent to the sphere is the derivative of Y_k along the sphere, the only
+ * part the chain rule through d = v / |v| keeps.                           */
+static void sh_basis(int D, const double d[3], double* Y, double (*grad)[3]) {
+  double x = d[0], y = d[1], z = d[2];
+  for (int l = 0; l <= D; ++l) {
+    double P[OR_SH_MAX + 1];
+    legendre_coeffs(l, P);
+    for (int m = 0; m <= l; ++m) {
+      double K = sqrt((2.0 * l + 1.0) / (4.0 * acos(-1.0)) * factorial(l - m) / factorial(l + m));
+      double q = poly_deriv_eval(P, l, m, z);
+      double qz = poly_deriv_eval(P, l, m + 1, z);
+      /* w = (x + i y)^m, w1 = (x + i y)^(m-1) */
+      double wr = 1.0, wi = 0.0, w1r = 0.0, w1i = 0.0;
+      for (int j = 0; j < m; ++j) {
+        w1r = wr; w1i = wi;
+        double tr = wr * x - wi * y, ti = wr * y + wi * x;
+        wr = tr; wi = ti;
+      }
+      if (m == 0) {
+        Y[l * l + l] = K * q;
+        grad[l * l + l][0] = 0.0;
+        grad[l * l + l][1] = 0.0;
+        grad[l * l + l][2] = K * qz;
+        continue;
+      }
+      double s = ((m & 1) ? -1.0 : 1.0) * sqrt(2.0) * K;
+      int kp = l * l + l + m, kn = l * l + l - m;
+      /* d/dx (x+iy)^m = m w1, d/dy (x+iy)^m = i m w1 */
+      Y[kp] = s * q * wr;
+      grad[kp][0] = s * q * m * w1r;
+      grad[kp][1] = -s * q * m * w1i;
+      grad[kp][2] = s * qz * wr;
+      Y[kn] = s * q * wi;
+      grad[kn][0] = s * q * m * w1i;
+      grad[kn][1] = s * q * m * w1r;
+      grad[kn][2] = s * qz * wi;
+    }
+  }
+}
+
+/* sh_basis at npts unit vectors d [npts][3]: Y [npts][(D+1)^2],
+ * grad [npts][(D+1)^2][3].                                                 */
+void or_sh_basis(int D, int64_t npts, const double* d, double* Y, double* grad) {
+  int K = (D + 1) * (D + 1);
+  for (int64_t p = 0; p < npts; ++p) {
+    double y[OR_SH_K], g[OR_SH_K][3];
+    sh_basis(D, d + 3 * p, y, g);
+    for (int k = 0; k < K; ++k) {
+      Y[p * K + k] = y[k];
+      for (int j = 0; j < 3; ++j) grad[(p * K + k) * 3 + j] = g[k][j];
+    }
+  }
+}
+
 /* Everything the projection computes for one Gaussian in one view, kept so
  * that the backward pass can reuse the forward's intermediate values.      */
 typedef struct {
   double s[3], qn[4], qnorm, o, rgb[3], pre_rgb[3];
+  int sh_deg;
+  double dir[3], vlen;        /* unit vector camera centre -> mean, |v|   */
+  double Y[OR_SH_K], dY[OR_SH_K][3];
   double R[9], Sigma[9];
   double t[3], mean2d[2];
   double J[6], xclamp, yclamp; int xclamped, yclamped;
@@ -59,9 +165,13 @@ typedef struct {
   int pix[4], tile[4], n_tiles, valid;
 } or_proj;
 
-/* cam: R[9], t[3], fx, fy, cx, cy (16 doubles)                            */
+/* cam: R[9], t[3], fx, fy, cx, cy (16 doubles).  color: the (D+1)^2 x 3
+ * spherical-harmonic coefficients of one Gaussian, coefficient-major
+ * (color[k*3 + channel]), D = sh_deg.  The colour seen from the camera is
+ * max(0, sum_k Y_k(d) color[k] + 1/2) with d the unit vector from the camera
+ * centre -R^T t to the mean (3D-GS colour model).                          */
 static void project_one(const double* mean, const double* ls, const double* quat,
-                        double opac_logit, const double* color, const double* cam,
+                        double opac_logit, const double* color, int sh_deg, const double* cam,
                         double znear, int W, int H, int tw, int th, or_proj* P) {
   memset(P, 0, sizeof(*P));
   for (int k = 0; k < 3; ++k) P->s[k] = exp(ls[k]);
@@ -69,8 +179,21 @@ static void project_one(const double* mean, const double* ls, const double* quat
   P->qnorm = qn;
   for (int k = 0; k < 4; ++k) P->qn[k] = quat[k] / qn;
   P->o = 1.0 / (1.0 + exp(-opac_logit));
+  P->sh_deg = sh_deg;
+  {
+    const double* Rc = cam; const double* tc = cam + 9;
+    double v[3];
+    for (int i = 0; i < 3; ++i)        /* mean - (-R^T t) */
+      v[i] = mean[i] + Rc[0 * 3 + i] * tc[0] + Rc[1 * 3 + i] * tc[1] + Rc[2 * 3 + i] * tc[2];
+    P->vlen = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int i = 0; i < 3; ++i) P->dir[i] = P->vlen > 0 ? v[i] / P->vlen : (i == 2);
+  }
+  sh_basis(sh_deg, P->dir, P->Y, P->dY);
+  int K = (sh_deg + 1) * (sh_deg + 1);
   for (int k = 0; k < 3; ++k) {
-    P->pre_rgb[k] = OR_C0 * color[k] + 0.5;
+    double acc = 0.0;
+    for (int j = 0; j < K; ++j) acc += P->Y[j] * color[j * 3 + k];
+    P->pre_rgb[k] = acc + 0.5;
     P->rgb[k] = P->pre_rgb[k] > 0 ? P->pre_rgb[k] : 0.0;
   }
   quat_to_rot(P->qn, P->R);
@@ -139,9 +262,11 @@ static void project_one(const double* mean, const double* ls, const double* quat
   P->valid = 1;
 }
 
-/* Project n Gaussians (planar SoA inputs) through one camera.              */
+/* Project n Gaussians (planar SoA inputs) through one camera.  color is
+ * [(D+1)^2][3][n] (coefficient k of channel c in row 3k + c), D = sh_deg.  */
 void or_project(int64_t n, const double* mean, const double* log_scale, const double* quat,
-                const double* opac_logit, const double* color, const double* cam, double znear,
+                const double* opac_logit, const double* color, int sh_deg, const double* cam,
+                double znear,
                 int W, int H, int tw, int th, double* out_mean2d, double* out_conic,
                 double* out_depth, double* out_opacity, double* out_rgb, double* out_cov2d,
                 int32_t* out_pix_bbox, int32_t* out_tile_bbox, int32_t* out_n_tiles,
@@ -151,9 +276,10 @@ void or_project(int64_t n, const double* mean, const double* log_scale, const do
     double mu[3] = {mean[i], mean[n + i], mean[2 * n + i]};
     double ls[3] = {log_scale[i], log_scale[n + i], log_scale[2 * n + i]};
     double q[4] = {quat[i], quat[n + i], quat[2 * n + i], quat[3 * n + i]};
-    double f[3] = {color[i], color[n + i], color[2 * n + i]};
+    double f[3 * OR_SH_K];
+    for (int r = 0; r < 3 * (sh_deg + 1) * (sh_deg + 1); ++r) f[r] = color[r * n + i];
     or_proj P;
-    project_one(mu, ls, q, opac_logit[i], f, cam, znear, W, H, tw, th, &P);
+    project_one(mu, ls, q, opac_logit[i], f, sh_deg, cam, znear, W, H, tw, th, &P);
     out_mean2d[i] = P.mean2d[0]; out_mean2d[n + i] = P.mean2d[1];
     for (int k = 0; k < 3; ++k) out_conic[k * n + i] = P.conic[k];
     out_depth[i] = P.t[2];
@@ -384,7 +510,7 @@ void or_render_bwd(int64_t n, const double* mean2d, const double* conic, const d
  * gradients w.r.t. or_project's outputs; accumulates (+=) into the SoA
  * parameter gradients.  Invalid (culled) Gaussians receive nothing.        */
 void or_project_bwd(int64_t n, const double* mean, const double* log_scale, const double* quat,
-                    const double* opac_logit, const double* color, const double* cam,
+                    const double* opac_logit, const double* color, int sh_deg, const double* cam,
                     double znear, int W, int H, int tw, int th, const double* d_mean2d,
                     const double* d_conic, const double* d_opacity, const double* d_rgb,
                     double* g_mean, double* g_log_scale, double* g_quat, double* g_opac_logit,
@@ -396,14 +522,24 @@ void or_project_bwd(int64_t n, const double* mean, const double* log_scale, cons
     double mu[3] = {mean[i], mean[n + i], mean[2 * n + i]};
     double ls[3] = {log_scale[i], log_scale[n + i], log_scale[2 * n + i]};
     double q[4] = {quat[i], quat[n + i], quat[2 * n + i], quat[3 * n + i]};
-    double f[3] = {color[i], color[n + i], color[2 * n + i]};
+    double f[3 * OR_SH_K];
+    int K = (sh_deg + 1) * (sh_deg + 1);
+    for (int r = 0; r < 3 * K; ++r) f[r] = color[r * n + i];
     or_proj P;
-    project_one(mu, ls, q, opac_logit[i], f, cam, znear, W, H, tw, th, &P);
+    project_one(mu, ls, q, opac_logit[i], f, sh_deg, cam, znear, W, H, tw, th, &P);
     if (!P.valid) continue;
-    /* colour: rgb = max(0, C0 f + 1/2); the derivative passes where the
-     * argument is >= 0 */
-    for (int k = 0; k < 3; ++k)
-      if (P.pre_rgb[k] >= 0) g_color[k * n + i] += OR_C0 * d_rgb[k * n + i];
+    /* colour: rgb_c = max(0, sum_k Y_k(d) f_kc + 1/2); the derivative passes
+     * where the argument is >= 0.  d = v/|v| moves with the mean:
+     * dd/dv = (I - d d^T) / |v|.                                            */
+    double gc[3], gdir[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < 3; ++c) gc[c] = P.pre_rgb[c] >= 0 ? d_rgb[c * n + i] : 0.0;
+    for (int k = 0; k < K; ++k)
+      for (int c = 0; c < 3; ++c) {
+        g_color[(k * 3 + c) * n + i] += P.Y[k] * gc[c];
+        for (int j = 0; j < 3; ++j) gdir[j] += gc[c] * f[k * 3 + c] * P.dY[k][j];
+      }
+    double dd = gdir[0] * P.dir[0] + gdir[1] * P.dir[1] + gdir[2] * P.dir[2];
+    for (int j = 0; j < 3; ++j) g_mean[j * n + i] += (gdir[j] - P.dir[j] * dd) / P.vlen;
     /* opacity: o = sigmoid(w) */
     g_opac_logit[i] += P.o * (1.0 - P.o) * d_opacity[i];
     /* conic (Q11, Q12, Q22) = (c, -b, a) / det as functions of (a, b, c)   */
