@@ -67,8 +67,16 @@ typedef struct {
 
 /* The Gaussians of one or more partitions, planar SoA, read-only.
  *   mean [3][n], log_scale [3][n], quat [4][n] as (w, x, y, z) (any norm > 0),
- *   opacity_logit [n], color [3][n] (degree-0 spherical-harmonic coefficient;
- *   the rendered colour is max(0, C0*color + 1/2), C0 = 1/(2 sqrt(pi))).   */
+ *   opacity_logit [n], color [3 (D+1)^2][n]: real spherical-harmonic
+ *   coefficients of degree D = sh_degree (0..GS_SH_MAX_DEGREE), coefficient k
+ *   (index l*l + l + m, Condon-Shortley phase) of channel c in row 3k + c.
+ * The colour a camera sees is max(0, sum_k Y_k(d) color_k + 1/2) with d the
+ * unit vector from the camera centre -R^T t to the mean (the view-dependent
+ * colour of 3D-GS, whose images the paper fits, Sec. I); at D = 0 this is
+ * max(0, C0 color + 1/2), C0 = 1/(2 sqrt(pi)).  Arrays stored at a higher
+ * degree may be drawn at a lower one: the rows are coefficient-major, so
+ * the first 3 (D+1)^2 rows are the lower-degree model.                     */
+#define GS_SH_MAX_DEGREE 3
 typedef struct {
   const float* mean;
   const float* log_scale;
@@ -76,9 +84,12 @@ typedef struct {
   const float* opacity_logit;
   const float* color;
   int64_t n;
+  int32_t sh_degree;
+  int32_t reserved;
 } gs_gaussians;
 
-/* Gradients with respect to the gs_gaussians fields, same layout.         */
+/* Gradients with respect to the gs_gaussians fields, same layout (color:
+ * the 3 (D+1)^2 rows of the call's degree).                              */
 typedef struct {
   float* mean;
   float* log_scale;
@@ -365,11 +376,15 @@ gs_status gs_adam_dev(const gs_adam_group* groups, int32_t n_groups, const float
 /* gs_project_bwd into zeroed gradients followed by gs_adam_dev, in one pass
  * over the Gaussians (the 3D-GS step's last two stages): each Gaussian's
  * gradient, summed over its pairs of `views`, stays in registers and updates
- * its 14 parameters, m and v in place at once, so the gradient arrays are
- * neither written nor read.  Bitwise equal to the two calls.
+ * its parameters (11 + the colour rows), m and v in place at once, so the
+ * gradient arrays are neither written nor read.  Bitwise equal to the two
+ * calls.
  *   groups: 5 groups in the order mean, log_scale, quat, opacity_logit,
- *   color whose param arrays are g's (counts 3n, 3n, 4n, n, 3n) with their
- *   m, v and lr; grad pointers are not used.  lr_final (5 or NULL),
+ *   color whose param arrays are g's (counts 3n, 3n, 4n, n, rows x n) with
+ *   their m, v and lr; rows is a multiple of 3 from 3 (D+1)^2 (D =
+ *   g->sh_degree) to 48: stored rows past the active degree are updated with
+ *   a zero gradient, as a dense gs_adam_dev would.  grad pointers are not
+ *   used.  lr_final (5 or NULL),
  *   decay_steps, betas, eps and step_dev as gs_adam_dev (step_dev is
  *   incremented).  Gaussians drawn by no pair get a zero gradient.         */
 gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
@@ -396,6 +411,8 @@ typedef struct {
   float* m[5];
   float* v[5];
   int64_t n;
+  int32_t color_rows;   /* rows of the colour arrays, 3 (D+1)^2; 0 means 3 */
+  int32_t reserved;
 } gs_gaussian_state;
 
 /* accum[g] += sum over g's visible pairs (n_tiles > 0) of |(dL/dmean2d_x W/2,

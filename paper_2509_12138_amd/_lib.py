@@ -29,7 +29,7 @@ i32, i64, f32, sz = C.c_int32, C.c_int64, C.c_float, C.c_size_t
 
 class gs_gaussians(C.Structure):
     _fields_ = [("mean", vp), ("log_scale", vp), ("quat", vp), ("opacity_logit", vp),
-                ("color", vp), ("n", i64)]
+                ("color", vp), ("n", i64), ("sh_degree", i32), ("reserved", i32)]
 
 
 class gs_grads(C.Structure):
@@ -72,7 +72,8 @@ class gs_mlp_grads(C.Structure):
 
 
 class gs_gaussian_state(C.Structure):
-    _fields_ = [("param", vp * 5), ("m", vp * 5), ("v", vp * 5), ("n", i64)]
+    _fields_ = [("param", vp * 5), ("m", vp * 5), ("v", vp * 5), ("n", i64),
+                ("color_rows", i32), ("reserved", i32)]
 
 
 P = C.POINTER

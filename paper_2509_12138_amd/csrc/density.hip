@@ -163,9 +163,8 @@ struct DenState {
   float* m[5];
   float* v[5];
   int64_t n;
+  int rows[5];   // 3, 3, 4, 1 and the colour rows 3 (D+1)^2
 };
-
-__device__ constexpr int kDenRows[5] = {3, 3, 4, 1, 3};
 
 // R(q / |q|) column-major application: out = R (s * z).
 __device__ __forceinline__ void rotate_scaled(const float q[4], const float s[3], const float z[3],
@@ -197,7 +196,7 @@ __global__ __launch_bounds__(kDenThreads) void k_densify_apply(
     const int copies = (act == kActClone && o + 1 < no) ? 2 : 1;
 #pragma unroll
     for (int grp = 0; grp < 5; ++grp)
-      for (int r = 0; r < kDenRows[grp]; ++r) {
+      for (int r = 0; r < in.rows[grp]; ++r) {
         const float pv = in.p[grp][r * n + g];
         const float mv = in.m[grp] ? in.m[grp][r * n + g] : 0.0f;
         const float vv = in.v[grp] ? in.v[grp][r * n + g] : 0.0f;
@@ -233,11 +232,10 @@ __global__ __launch_bounds__(kDenThreads) void k_densify_apply(
 #pragma unroll
     for (int r = 0; r < 4; ++r) out.p[2][r * no + oc] = q[r];
     out.p[3][oc] = in.p[3][g];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) out.p[4][r * no + oc] = in.p[4][r * n + g];
+    for (int r = 0; r < in.rows[4]; ++r) out.p[4][r * no + oc] = in.p[4][r * n + g];
 #pragma unroll
     for (int grp = 0; grp < 5; ++grp)
-      for (int r = 0; r < kDenRows[grp]; ++r) {
+      for (int r = 0; r < in.rows[grp]; ++r) {
         if (out.m[grp]) out.m[grp][r * no + oc] = 0.0f;
         if (out.v[grp]) out.v[grp][r * no + oc] = 0.0f;
       }
@@ -263,11 +261,16 @@ static DenState den_state(const gs_gaussian_state* s) {
     d.v[i] = s->v[i];
   }
   d.n = s->n;
+  const int rows[5] = {3, 3, 4, 1, s->color_rows > 0 ? s->color_rows : 3};
+  for (int i = 0; i < 5; ++i) d.rows[i] = rows[i];
   return d;
 }
 
 static bool state_ok(const gs_gaussian_state* s) {
   if (!s || s->n < 0) return false;
+  if (s->color_rows < 0 || s->color_rows % 3 != 0 ||
+      s->color_rows > 3 * (GS_SH_MAX_DEGREE + 1) * (GS_SH_MAX_DEGREE + 1))
+    return false;
   if (s->n == 0) return true;
   for (int i = 0; i < 5; ++i)
     if (!s->param[i] || ((s->m[i] == nullptr) != (s->v[i] == nullptr))) return false;
@@ -341,6 +344,9 @@ gs_status gs_densify_apply(const gs_gaussian_state* in, const int32_t* action, c
   clear_error();
   GS_REQUIRE(state_ok(in) && state_ok(out), "gs_densify_apply: bad state (NULL arrays or n < 0)");
   GS_REQUIRE(in->n == 0 || (action && ws && z), "gs_densify_apply: NULL action/workspace/z");
+  GS_REQUIRE((in->color_rows > 0 ? in->color_rows : 3) == (out->color_rows > 0 ? out->color_rows : 3),
+             "gs_densify_apply: colour rows differ (%d in, %d out)", in->color_rows,
+             out->color_rows);
   for (int i = 0; i < 5; ++i)
     GS_REQUIRE(out->n == 0 || in->n == 0 || ((in->m[i] == nullptr) == (out->m[i] == nullptr)),
                "gs_densify_apply: moments given on one side only (group %d)", i);

@@ -5,6 +5,8 @@
 // are coalesced, the 48-byte record goes out as three 16-byte stores.
 // Backward: one thread per Gaussian that loops over the slots drawing it, so
 // gradients summed over views need no atomics and are deterministic.
+#include <type_traits>
+
 #include "gs_device.h"
 
 namespace gsmi {
@@ -39,27 +41,170 @@ struct ProjState {
   float a, b, c, det;  // dilated 2D covariance
   float conic[3];
   float o, pre_rgb[3], rgb[3];
+  float dir[3], ivlen; // unit vector camera centre -> mean, 1/|mean - centre|
   int bbox[4];         // inclusive tile range
   int n_tiles;
   bool valid;
 };
 
 __device__ __forceinline__ void load_gaussian(const Params& P, int64_t g, float mu[3], float ls[3],
-                                              float q[4], float& ol, float col[3]) {
+                                              float q[4], float& ol) {
   const int64_t n = P.n;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     mu[k] = P.mean[k * n + g];
     ls[k] = P.ls[k * n + g];
-    col[k] = P.col[k * n + g];
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) q[k] = P.quat[k * n + g];
   ol = P.ol[g];
 }
 
+// ---------------------------------------------------------------------------
+// View-dependent colour (3D-GS colour model): rgb_c = max(0, sum_k Y_k(d)
+// f_kc + 1/2) over the real spherical harmonics of degree <= D, Condon-
+// Shortley phase, index l*l + l + m, d the unit vector from the camera centre
+// to the mean.  Y_k is written out as a polynomial of d's components.
+// Colour coefficients are planar: coefficient k of channel c in row 3k + c.
+// ---------------------------------------------------------------------------
+constexpr float kSH1 = 0.4886025119029199f;  // sqrt(3 / (4 pi))
+constexpr float kSH2a = 1.0925484305920792f; // sqrt(15 / (4 pi))
+constexpr float kSH2b = 0.31539156525252005f;// sqrt(5 / (16 pi))
+constexpr float kSH2c = 0.5462742152960396f; // sqrt(15 / (16 pi))
+constexpr float kSH3a = 0.5900435899266435f; // sqrt(35 / (32 pi))
+constexpr float kSH3b = 2.890611442640554f;  // sqrt(105 / (4 pi))
+constexpr float kSH3c = 0.4570457994644658f; // sqrt(21 / (32 pi))
+constexpr float kSH3d = 0.3731763325901154f; // sqrt(7 / (16 pi))
+constexpr float kSH3e = 1.445305721320277f;  // sqrt(105 / (16 pi))
+
+// f(k, Y_k, dY_k/dx, dY_k/dy, dY_k/dz) for k = 0 .. (D+1)^2 - 1 at the unit
+// vector d; each term is made where it is consumed, so no table of basis
+// values stays live.
+template <int D, class F>
+__device__ __forceinline__ void sh_for_each(const float d[3], F&& f) {
+  f(0, kC0, 0.f, 0.f, 0.f);
+  if constexpr (D >= 1) {
+    const float x = d[0], y = d[1], z = d[2];
+    f(1, -kSH1 * y, 0.f, -kSH1, 0.f);
+    f(2, kSH1 * z, 0.f, 0.f, kSH1);
+    f(3, -kSH1 * x, -kSH1, 0.f, 0.f);
+    if constexpr (D >= 2) {
+      const float xx = x * x, yy = y * y, zz = z * z;
+      f(4, kSH2a * x * y, kSH2a * y, kSH2a * x, 0.f);
+      f(5, -kSH2a * y * z, 0.f, -kSH2a * z, -kSH2a * y);
+      f(6, kSH2b * (2.f * zz - xx - yy), -2.f * kSH2b * x, -2.f * kSH2b * y, 4.f * kSH2b * z);
+      f(7, -kSH2a * x * z, -kSH2a * z, 0.f, -kSH2a * x);
+      f(8, kSH2c * (xx - yy), 2.f * kSH2c * x, -2.f * kSH2c * y, 0.f);
+      if constexpr (D >= 3) {
+        f(9, -kSH3a * y * (3.f * xx - yy), -6.f * kSH3a * x * y, -kSH3a * (3.f * xx - 3.f * yy),
+          0.f);
+        f(10, kSH3b * x * y * z, kSH3b * y * z, kSH3b * x * z, kSH3b * x * y);
+        f(11, -kSH3c * y * (4.f * zz - xx - yy), 2.f * kSH3c * x * y,
+          -kSH3c * (4.f * zz - xx - 3.f * yy), -8.f * kSH3c * y * z);
+        f(12, kSH3d * z * (2.f * zz - 3.f * xx - 3.f * yy), -6.f * kSH3d * x * z,
+          -6.f * kSH3d * y * z, kSH3d * (6.f * zz - 3.f * xx - 3.f * yy));
+        f(13, -kSH3c * x * (4.f * zz - xx - yy), -kSH3c * (4.f * zz - 3.f * xx - yy),
+          2.f * kSH3c * x * y, -8.f * kSH3c * x * z);
+        f(14, kSH3e * z * (xx - yy), 2.f * kSH3e * x * z, -2.f * kSH3e * y * z, kSH3e * (xx - yy));
+        f(15, -kSH3a * x * (xx - 3.f * yy), -kSH3a * (3.f * xx - 3.f * yy), 6.f * kSH3a * x * y,
+          0.f);
+      }
+    }
+  }
+}
+
+// S.pre_rgb / S.rgb of Gaussian g from its colour coefficients.
+template <int D>
+__device__ __forceinline__ void colour_fwd(const float* __restrict__ col, int64_t n, int64_t g,
+                                           ProjState& S) {
+  float acc[3] = {0.f, 0.f, 0.f};
+  sh_for_each<D>(S.dir, [&](int k, float Y, float, float, float) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] += Y * col[(3 * k + c) * n + g];
+  });
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    S.pre_rgb[c] = acc[c] + 0.5f;
+    S.rgb[c] = fmaxf(S.pre_rgb[c], 0.0f);
+  }
+}
+
+// Per-thread colour-gradient accumulators of a 256-thread block: registers
+// at degree 0; above it an LDS array [rows][256] (48 KB at degree 3), which
+// keeps up to 48 running sums out of the registers the projection needs.
+template <int D>
+struct ColourAcc {
+  static constexpr int NC = 3 * (D + 1) * (D + 1);
+  static constexpr int STRIDE = D == 0 ? 1 : 256;
+  float reg[D == 0 ? NC : 1];
+  float* lds;
+  __device__ __forceinline__ void init(float* block_lds) {
+    lds = block_lds + threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) ptr()[r * STRIDE] = 0.f;
+  }
+  __device__ __forceinline__ float* ptr() {
+    if constexpr (D == 0) return reg;
+    else return lds;
+  }
+  __device__ __forceinline__ float get(int r) { return ptr()[r * STRIDE]; }
+};
+
+// Colour of one pair and its backward: rgb_c = max(0, sum_k Y_k(d) f_kc +
+// 1/2) (sets S.pre_rgb / S.rgb); dL/df_kc = Y_k dL/drgb_c where the clamp
+// passes, and the mean moves the direction: dL/dmean += (I - d d^T) dL/dd /
+// |v| with dL/dd = sum_c gc_c sum_k f_kc grad Y_k.  One pass over the
+// coefficients makes both the colour and the per-channel direction
+// gradients; a second pass over the basis alone adds the coefficient
+// gradients into gcol (element r at gcol[r * STRIDE]).
+template <int D, int STRIDE>
+__device__ __forceinline__ void colour_bwd(const float* __restrict__ col, int64_t n, int64_t g,
+                                           ProjState& S, const float* __restrict__ drgb,
+                                           float* gcol, float gmu[3]) {
+  float acc[3] = {0.f, 0.f, 0.f};
+  float gdc[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  // walk the rows from a pointer the compiler cannot see through, so the
+  // row addresses are made here and not kept live across the caller's loop
+  const float* cp = col + g;
+  if constexpr (D >= 1) asm volatile("" : "+v"(cp));
+  sh_for_each<D>(S.dir, [&](int k, float Y, float gx, float gy, float gz) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float f = *cp;
+      cp += n;
+      acc[c] += Y * f;
+      if (k > 0) {
+        gdc[c][0] += f * gx;
+        gdc[c][1] += f * gy;
+        gdc[c][2] += f * gz;
+      }
+    }
+  });
+  float gc[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    S.pre_rgb[c] = acc[c] + 0.5f;
+    S.rgb[c] = fmaxf(S.pre_rgb[c], 0.0f);
+    gc[c] = S.pre_rgb[c] >= 0.0f ? drgb[c] : 0.0f;
+  }
+  sh_for_each<D>(S.dir, [&](int k, float Y, float, float, float) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gcol[(3 * k + c) * STRIDE] += Y * gc[c];
+  });
+  if constexpr (D >= 1) {
+    float gd[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) gd[j] = gc[0] * gdc[0][j] + gc[1] * gdc[1][j] + gc[2] * gdc[2][j];
+    const float x = S.dir[0], y = S.dir[1], z = S.dir[2];
+    const float dd = gd[0] * x + gd[1] * y + gd[2] * z;
+    gmu[0] += (gd[0] - x * dd) * S.ivlen;
+    gmu[1] += (gd[1] - y * dd) * S.ivlen;
+    gmu[2] += (gd[2] - z * dd) * S.ivlen;
+  }
+}
+
 __device__ __forceinline__ void project_core(const float mu[3], const float ls[3], const float q[4],
-                                             float ol, const float col[3], const gs_camera& cam,
+                                             float ol, const gs_camera& cam,
                                              int W, int H, int tw, int th, ProjState& S) {
   S.valid = false;
   S.n_tiles = 0;
@@ -88,12 +233,18 @@ __device__ __forceinline__ void project_core(const float mu[3], const float ls[3
   S.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
   S.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
   S.o = 1.0f / (1.0f + expf(-ol));
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    S.pre_rgb[k] = kC0 * col[k] + 0.5f;
-    S.rgb[k] = fmaxf(S.pre_rgb[k], 0.0f);
-  }
   const float* Rv = cam.R;
+  {
+    // v = mean - camera centre, centre = -Rv^T t
+    float v[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      v[i] = mu[i] + Rv[0 * 3 + i] * cam.t[0] + Rv[1 * 3 + i] * cam.t[1] + Rv[2 * 3 + i] * cam.t[2];
+    const float vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    S.ivlen = vv > 0.0f ? rsqrtf(vv) : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) S.dir[i] = v[i] * S.ivlen;
+  }
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     S.t[i] = Rv[i * 3 + 0] * mu[0] + Rv[i * 3 + 1] * mu[1] + Rv[i * 3 + 2] * mu[2] + cam.t[i];
@@ -170,6 +321,7 @@ __device__ __forceinline__ int find_slot(const int64_t* __restrict__ pair_offset
   return lo;
 }
 
+template <int D>
 __global__ __launch_bounds__(256) void k_project(Params P, const int64_t* __restrict__ pair_offset,
                                                  const int64_t* __restrict__ gauss_offset,
                                                  const gs_camera* __restrict__ cams, int n_slots,
@@ -186,9 +338,10 @@ __global__ __launch_bounds__(256) void k_project(Params P, const int64_t* __rest
   S.n_tiles = 0;
   S.t[2] = 0.0f;
   if (g >= 0 && g < P.n) {
-    float mu[3], ls[3], q[4], ol, col[3];
-    load_gaussian(P, g, mu, ls, q, ol, col);
-    project_core(mu, ls, q, ol, col, cams[s], W, H, tw, th, S);
+    float mu[3], ls[3], q[4], ol;
+    load_gaussian(P, g, mu, ls, q, ol);
+    project_core(mu, ls, q, ol, cams[s], W, H, tw, th, S);
+    if (S.valid) colour_fwd<D>(P.col, P.n, g, S);
   }
   float4* r = rec + 3 * p;
   if (S.valid) {
@@ -207,17 +360,13 @@ __global__ __launch_bounds__(256) void k_project(Params P, const int64_t* __rest
   }
 }
 
-// Backward of project_core for one pair: accumulates the parameter gradients
-// of the pair into the per-thread sums.
+// Backward of project_core for one pair (everything but the colour):
+// accumulates the parameter gradients of the pair into the per-thread sums.
 __device__ __forceinline__ void project_bwd_core(const ProjState& S, const gs_camera& cam,
                                                  const float* __restrict__ dr, float gmu[3],
-                                                 float gls[3], float gq[4], float& gol,
-                                                 float gcol[3]) {
+                                                 float gls[3], float gq[4], float& gol) {
   float dmx = dr[0], dmy = dr[1], dq11 = dr[2], dq12 = dr[3], dq22 = dr[4];
   float dop = dr[5];
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-    if (S.pre_rgb[k] >= 0.0f) gcol[k] += kC0 * dr[6 + k];
   gol += S.o * (1.0f - S.o) * dop;
   // conic (c, -b, a)/det as a function of (a, b, c)
   float a = S.a, b = S.b, c = S.c;
@@ -315,17 +464,26 @@ __device__ __forceinline__ void project_bwd_core(const ProjState& S, const gs_ca
   gq[3] += (dz - z * dot) * S.qinv;
 }
 
-__global__ __launch_bounds__(256) void k_project_bwd(
+// Above degree 0 the LDS accumulators allow 3 blocks per CU (3 waves per
+// SIMD); registers are capped to match, so the scheduler cannot hoist every
+// coefficient load at once.
+template <int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 0 ? 1 : 3))) void
+k_project_bwd(
     Params P, GradPtrs Gr, const int64_t* __restrict__ pair_offset,
     const int64_t* __restrict__ gauss_offset, const gs_camera* __restrict__ cams, int n_slots,
     int W, int H, int tw, int th, const int32_t* __restrict__ n_tiles,
     const float* __restrict__ d_rec) {
   int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (g >= P.n) return;
-  float mu[3], ls[3], q[4], ol, col[3];
-  load_gaussian(P, g, mu, ls, q, ol, col);
+  constexpr int NC = ColourAcc<D>::NC;
+  __shared__ float s_gcol[D == 0 ? 1 : NC * 256];
+  ColourAcc<D> gcol;
+  gcol.init(s_gcol);
+  float mu[3], ls[3], q[4], ol;
+  load_gaussian(P, g, mu, ls, q, ol);
   float gmu[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
-  float gol = 0.f, gcol[3] = {0.f, 0.f, 0.f};
+  float gol = 0.f;
   bool any = false;
   for (int s = 0; s < n_slots; ++s) {
     int64_t g0 = gauss_offset[s];
@@ -334,12 +492,14 @@ __global__ __launch_bounds__(256) void k_project_bwd(
     int64_t p = pair_offset[s] + (g - g0);
     if (n_tiles[p] <= 0) continue;
     ProjState S;
-    project_core(mu, ls, q, ol, col, cams[s], W, H, tw, th, S);
+    project_core(mu, ls, q, ol, cams[s], W, H, tw, th, S);
     if (!S.valid) continue;
     float dr[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) dr[k] = d_rec[p * GS_DREC_STRIDE + k];
-    project_bwd_core(S, cams[s], dr, gmu, gls, gq, gol, gcol);
+    project_bwd_core(S, cams[s], dr, gmu, gls, gq, gol);
+    // the colour last, so its coefficients are live only here
+    colour_bwd<D, ColourAcc<D>::STRIDE>(P.col, P.n, g, S, dr + 6, gcol.ptr(), gmu);
     any = true;
   }
   if (!any) return;
@@ -348,8 +508,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(
   for (int k = 0; k < 3; ++k) {
     Gr.mean[k * n + g] += gmu[k];
     Gr.ls[k * n + g] += gls[k];
-    Gr.col[k * n + g] += gcol[k];
   }
+#pragma unroll
+  for (int k = 0; k < NC; ++k) Gr.col[k * n + g] += gcol.get(k);
 #pragma unroll
   for (int k = 0; k < 4; ++k) Gr.quat[k * n + g] += gq[k];
   Gr.ol[g] += gol;
@@ -364,13 +525,16 @@ struct AdamFused {
   float* p[5];            // mean, log_scale, quat, opacity_logit, colour (planar)
   float* m[5];
   float* v[5];
+  int col_rows;           // rows of the colour arrays (>= 3 (D+1)^2)
   float lr[5], lr_final[5];
   int decay_steps;
   float b1, b2, eps;
   const int32_t* step_dev;
 };
 
-__global__ __launch_bounds__(256) void k_project_bwd_adam(
+template <int D>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 0 ? 1 : 3))) void
+k_project_bwd_adam(
     Params P, AdamFused A, const int64_t* __restrict__ pair_offset,
     const int64_t* __restrict__ gauss_offset, const gs_camera* __restrict__ cams, int n_slots,
     int W, int H, int tw, int th, const int32_t* __restrict__ n_tiles,
@@ -389,10 +553,14 @@ __global__ __launch_bounds__(256) void k_project_bwd_adam(
   __syncthreads();
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (g >= P.n) return;
-  float mu[3], ls[3], q[4], ol, col[3];
-  load_gaussian(P, g, mu, ls, q, ol, col);
+  constexpr int NC = ColourAcc<D>::NC;
+  __shared__ float s_gcol[D == 0 ? 1 : NC * 256];
+  ColourAcc<D> gcol;
+  gcol.init(s_gcol);
+  float mu[3], ls[3], q[4], ol;
+  load_gaussian(P, g, mu, ls, q, ol);
   float gmu[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
-  float gol = 0.f, gcol[3] = {0.f, 0.f, 0.f};
+  float gol = 0.f;
   for (int s = 0; s < n_slots; ++s) {
     const int64_t g0 = gauss_offset[s];
     const int64_t cnt = pair_offset[s + 1] - pair_offset[s];
@@ -400,25 +568,26 @@ __global__ __launch_bounds__(256) void k_project_bwd_adam(
     const int64_t p = pair_offset[s] + (g - g0);
     if (n_tiles[p] <= 0) continue;
     ProjState S;
-    project_core(mu, ls, q, ol, col, cams[s], W, H, tw, th, S);
+    project_core(mu, ls, q, ol, cams[s], W, H, tw, th, S);
     if (!S.valid) continue;
     float dr[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) dr[k] = d_rec[p * GS_DREC_STRIDE + k];
-    project_bwd_core(S, cams[s], dr, gmu, gls, gq, gol, gcol);
+    project_bwd_core(S, cams[s], dr, gmu, gls, gq, gol);
+    // the colour last, so its coefficients are live only here
+    colour_bwd<D, ColourAcc<D>::STRIDE>(P.col, P.n, g, S, dr + 6, gcol.ptr(), gmu);
   }
   // the gradient a separate pass would add to zeroed arrays
-  const float G[14] = {0.f + gmu[0], 0.f + gmu[1], 0.f + gmu[2], 0.f + gls[0], 0.f + gls[1],
+  const float G[11] = {0.f + gmu[0], 0.f + gmu[1], 0.f + gmu[2], 0.f + gls[0], 0.f + gls[1],
                        0.f + gls[2], 0.f + gq[0],  0.f + gq[1],  0.f + gq[2],  0.f + gq[3],
-                       0.f + gol,    0.f + gcol[0], 0.f + gcol[1], 0.f + gcol[2]};
-  float par[14] = {mu[0], mu[1], mu[2], ls[0], ls[1], ls[2], q[0], q[1], q[2], q[3], ol,
-                   col[0], col[1], col[2]};
-  constexpr int kGroup[14] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 2, 3, 4, 4, 4};
-  constexpr int kRow[14] = {0, 1, 2, 0, 1, 2, 0, 1, 2, 3, 0, 0, 1, 2};
+                       0.f + gol};
+  float par[11] = {mu[0], mu[1], mu[2], ls[0], ls[1], ls[2], q[0], q[1], q[2], q[3], ol};
+  constexpr int kGroup[11] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 2, 3};
+  constexpr int kRow[11] = {0, 1, 2, 0, 1, 2, 0, 1, 2, 3, 0};
   const int64_t n = P.n;
   const float ibc1 = s_ibc[0], ibc2 = s_ibc[1];
 #pragma unroll
-  for (int e = 0; e < 14; ++e) {
+  for (int e = 0; e < 11; ++e) {
     const int gr = kGroup[e];
     const int64_t o = (int64_t)kRow[e] * n + g;
     float m = A.m[gr][o], v = A.v[gr][o];
@@ -427,10 +596,48 @@ __global__ __launch_bounds__(256) void k_project_bwd_adam(
     A.m[gr][o] = m;
     A.v[gr][o] = v;
   }
+  // colour rows: the active coefficients, then any stored beyond the
+  // active degree (zero gradient)
+  float* cp = A.p[4] + g;
+  float* cm = A.m[4] + g;
+  float* cv = A.v[4] + g;
+  if constexpr (D >= 1) asm volatile("" : "+v"(cp), "+v"(cm), "+v"(cv));
+#pragma unroll
+  for (int r = 0; r < NC; ++r) {
+    float pv = *cp, m = *cm, v = *cv;
+    adam_update(pv, 0.f + gcol.get(r), m, v, s_lr[4], ibc1, ibc2, A.b1, A.b2, A.eps);
+    *cp = pv;
+    *cm = m;
+    *cv = v;
+    cp += n;
+    cm += n;
+    cv += n;
+  }
+  for (int r = NC; r < A.col_rows; ++r) {
+    float pv = *cp, m = *cm, v = *cv;
+    adam_update(pv, 0.f, m, v, s_lr[4], ibc1, ibc2, A.b1, A.b2, A.eps);
+    *cp = pv;
+    *cm = m;
+    *cv = v;
+    cp += n;
+    cm += n;
+    cv += n;
+  }
 }
 
 __global__ void k_adam_step_inc(int32_t* step_dev) {
   if (threadIdx.x == 0) step_dev[0] += 1;
+}
+
+// Calls f(std::integral_constant<int, D>) for the run-time degree d (0..3).
+template <class F>
+static void sh_dispatch(int d, F&& f) {
+  switch (d) {
+    case 0: f(std::integral_constant<int, 0>{}); break;
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    default: f(std::integral_constant<int, 3>{}); break;
+  }
 }
 
 }  // namespace gsmi
@@ -446,6 +653,8 @@ gs_status gs_project(const gs_gaussians* g, const gs_views* views, const gs_tili
   gs_status st = check_views(views, tiling, "gs_project");
   if (st != GS_OK) return st;
   GS_REQUIRE(g->n >= 0, "gs_project: n=%lld < 0", (long long)g->n);
+  GS_REQUIRE(g->sh_degree >= 0 && g->sh_degree <= GS_SH_MAX_DEGREE,
+             "gs_project: sh_degree=%d outside 0..%d", g->sh_degree, GS_SH_MAX_DEGREE);
   GS_REQUIRE(out->m == views->total_pairs, "gs_project: out->m=%lld != total_pairs=%lld",
              (long long)out->m, (long long)views->total_pairs);
   if (out->m == 0) return GS_OK;
@@ -456,10 +665,12 @@ gs_status gs_project(const gs_gaussians* g, const gs_views* views, const gs_tili
              "gs_project: rec must be 16-byte and tile_bbox 8-byte aligned");
   Params P{g->mean, g->log_scale, g->quat, g->opacity_logit, g->color, g->n};
   int64_t blocks = ceil_div(out->m, 256);
-  hipLaunchKernelGGL(k_project, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), P,
-                     views->pair_offset, views->gauss_offset, views->cams, views->n_slots, out->m,
-                     tiling->width, tiling->height, tiling->tile_w, tiling->tile_h,
-                     (float4*)out->rec, (uint2*)out->tile_bbox, out->n_tiles);
+  sh_dispatch(g->sh_degree, [&](auto D) {
+    hipLaunchKernelGGL(k_project<decltype(D)::value>, dim3((unsigned)blocks), dim3(256), 0,
+                       as_stream(stream), P, views->pair_offset, views->gauss_offset, views->cams,
+                       views->n_slots, out->m, tiling->width, tiling->height, tiling->tile_w,
+                       tiling->tile_h, (float4*)out->rec, (uint2*)out->tile_bbox, out->n_tiles);
+  });
   GS_LAUNCH_CHECK("gs_project");
   return GS_OK;
 }
@@ -474,6 +685,8 @@ gs_status gs_project_bwd(const gs_gaussians* g, const gs_views* views, const gs_
   GS_REQUIRE(proj->m == views->total_pairs, "gs_project_bwd: proj->m != total_pairs");
   GS_REQUIRE(grads->n == g->n, "gs_project_bwd: grads->n=%lld != n=%lld", (long long)grads->n,
              (long long)g->n);
+  GS_REQUIRE(g->sh_degree >= 0 && g->sh_degree <= GS_SH_MAX_DEGREE,
+             "gs_project_bwd: sh_degree=%d outside 0..%d", g->sh_degree, GS_SH_MAX_DEGREE);
   if (g->n == 0 || proj->m == 0) return GS_OK;
   GS_REQUIRE(g->mean && g->log_scale && g->quat && g->opacity_logit && g->color,
              "gs_project_bwd: Gaussian arrays must not be NULL");
@@ -483,10 +696,12 @@ gs_status gs_project_bwd(const gs_gaussians* g, const gs_views* views, const gs_
   Params P{g->mean, g->log_scale, g->quat, g->opacity_logit, g->color, g->n};
   GradPtrs G{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->color};
   int64_t blocks = ceil_div(g->n, 256);
-  hipLaunchKernelGGL(k_project_bwd, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), P, G,
-                     views->pair_offset, views->gauss_offset, views->cams, views->n_slots,
-                     tiling->width, tiling->height, tiling->tile_w, tiling->tile_h, proj->n_tiles,
-                     d_rec);
+  sh_dispatch(g->sh_degree, [&](auto D) {
+    hipLaunchKernelGGL(k_project_bwd<decltype(D)::value>, dim3((unsigned)blocks), dim3(256), 0,
+                       as_stream(stream), P, G, views->pair_offset, views->gauss_offset,
+                       views->cams, views->n_slots, tiling->width, tiling->height, tiling->tile_w,
+                       tiling->tile_h, proj->n_tiles, d_rec);
+  });
   GS_LAUNCH_CHECK("gs_project_bwd");
   return GS_OK;
 }
@@ -504,9 +719,23 @@ gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
   GS_REQUIRE(decay_steps >= 0, "gs_project_bwd_adam: decay_steps < 0");
   GS_REQUIRE(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f,
              "gs_project_bwd_adam: bad betas");
+  GS_REQUIRE(g->sh_degree >= 0 && g->sh_degree <= GS_SH_MAX_DEGREE,
+             "gs_project_bwd_adam: sh_degree=%d outside 0..%d", g->sh_degree, GS_SH_MAX_DEGREE);
   const float* arrays[5] = {g->mean, g->log_scale, g->quat, g->opacity_logit, g->color};
-  const int rows[5] = {3, 3, 4, 1, 3};
+  const int nc = 3 * (g->sh_degree + 1) * (g->sh_degree + 1);
+  int col_rows = nc;
+  if (g->n > 0) {
+    GS_REQUIRE(groups[4].count % g->n == 0 && groups[4].count / g->n >= nc &&
+                   (groups[4].count / g->n) % 3 == 0 &&
+                   groups[4].count / g->n <= 3 * (GS_SH_MAX_DEGREE + 1) * (GS_SH_MAX_DEGREE + 1),
+               "gs_project_bwd_adam: colour group count %lld must be 3k x n, k >= (D+1)^2 = %d, "
+               "k <= %d",
+               (long long)groups[4].count, nc / 3, (GS_SH_MAX_DEGREE + 1) * (GS_SH_MAX_DEGREE + 1));
+    col_rows = (int)(groups[4].count / g->n);
+  }
+  const int rows[5] = {3, 3, 4, 1, col_rows};
   AdamFused A;
+  A.col_rows = col_rows;
   for (int i = 0; i < 5; ++i) {
     GS_REQUIRE(groups[i].param == arrays[i] && groups[i].count == rows[i] * g->n,
                "gs_project_bwd_adam: group %d must be the Gaussians' array %d (%d x n elements)",
@@ -533,10 +762,13 @@ gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
                    (proj->m == 0 || (d_rec && proj->n_tiles)),
                "gs_project_bwd_adam: arrays must not be NULL");
     Params P{g->mean, g->log_scale, g->quat, g->opacity_logit, g->color, g->n};
-    hipLaunchKernelGGL(k_project_bwd_adam, dim3((unsigned)ceil_div(g->n, 256)), dim3(256), 0, s,
-                       P, A, views->pair_offset, views->gauss_offset, views->cams, views->n_slots,
-                       tiling->width, tiling->height, tiling->tile_w, tiling->tile_h,
-                       proj->n_tiles, d_rec);
+    sh_dispatch(g->sh_degree, [&](auto D) {
+      hipLaunchKernelGGL(k_project_bwd_adam<decltype(D)::value>,
+                         dim3((unsigned)ceil_div(g->n, 256)), dim3(256), 0, s, P, A,
+                         views->pair_offset, views->gauss_offset, views->cams, views->n_slots,
+                         tiling->width, tiling->height, tiling->tile_w, tiling->tile_h,
+                         proj->n_tiles, d_rec);
+    });
     GS_LAUNCH_CHECK("gs_project_bwd_adam");
   }
   hipLaunchKernelGGL(k_adam_step_inc, dim3(1), dim3(64), 0, s, step_dev);

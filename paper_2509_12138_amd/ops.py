@@ -35,11 +35,30 @@ def _check_f32(t, name):
 # Structures
 # --------------------------------------------------------------------------
 
-def gaussians_struct(params, n=None):
+SH_MAX_DEGREE = 3
+
+
+def sh_degree_of(color):
+    """Highest spherical-harmonic degree D whose 3 (D+1)^2 coefficient rows
+    a planar colour array [rows, n] holds."""
+    rows = color.shape[0]
+    D = int(round(math.sqrt(rows / 3.0))) - 1
+    if rows % 3 or D < 0 or D > SH_MAX_DEGREE or 3 * (D + 1) ** 2 != rows:
+        raise ValueError(f"colour has {rows} rows; expected 3 (D+1)^2 with D <= {SH_MAX_DEGREE}")
+    return D
+
+
+def gaussians_struct(params, n=None, sh_degree=None):
+    """gs_gaussians over planar tensors; sh_degree defaults to the degree the
+    colour rows hold (a lower one draws the leading coefficients only)."""
     for k in PARAM_NAMES:
         _check_f32(params[k], k)
     n = params["opacity_logit"].shape[-1] if n is None else n
-    return _lib.gs_gaussians(*[params[k].data_ptr() for k in PARAM_NAMES], n)
+    stored = sh_degree_of(params["color"])
+    D = stored if sh_degree is None else int(sh_degree)
+    if not 0 <= D <= stored:
+        raise ValueError(f"sh_degree {D} outside 0..{stored} (the degree the colour rows hold)")
+    return _lib.gs_gaussians(*[params[k].data_ptr() for k in PARAM_NAMES], n, D, 0)
 
 
 def grads_struct(grads, n):
@@ -468,6 +487,7 @@ def gaussian_state(params, m=None, v=None):
         st.m[i] = m[k].data_ptr() if m is not None else None
         st.v[i] = v[k].data_ptr() if v is not None else None
     st.n = params["opacity_logit"].shape[-1]
+    st.color_rows = params["color"].shape[0]
     return st
 
 

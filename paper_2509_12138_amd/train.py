@@ -67,7 +67,7 @@ class PlainTrainer:
     def __init__(self, params, cams_np, targets, masks, tile=(16, 16), lam=0.2,
                  bg=(0.0, 0.0, 0.0), stored=True, extent=2.75, lrs=None, dup_capacity=None,
                  schedule="default", chunk=0, fwd_waves=1, deterministic=False, fused_adam=True,
-                 density=None, device="cuda"):
+                 density=None, sh_degree=0, sh_up_every=1000, device="cuda"):
         self.device = device
         self.V = len(cams_np)
         self.W, self.H = int(cams_np[0]["width"]), int(cams_np[0]["height"])
@@ -92,6 +92,16 @@ class PlainTrainer:
         self.densifier = None
         p = {k: torch.as_tensor(np.ascontiguousarray(v, np.float32)).to(device)
              if not torch.is_tensor(v) else v.contiguous().to(device) for k, v in params.items()}
+        # view-dependent colour: coefficients up to sh_degree (the higher
+        # ones start at zero); the active degree starts at 0 and rises by
+        # one every sh_up_every steps (the 3D-GS schedule)
+        self.sh_degree, self.sh_up_every = int(sh_degree), int(sh_up_every)
+        rows = 3 * (self.sh_degree + 1) ** 2
+        if p["color"].shape[0] < rows:
+            pad = torch.zeros((rows - p["color"].shape[0], p["color"].shape[1]),
+                              dtype=p["color"].dtype, device=device)
+            p["color"] = torch.cat([p["color"], pad]).contiguous()
+        self.active_sh = 0
         self._bind(p, {k: torch.zeros_like(v) for k, v in p.items()},
                    {k: torch.zeros_like(v) for k, v in p.items()}, dup_capacity)
         if density is not None:
@@ -112,7 +122,7 @@ class PlainTrainer:
         self.bufs.set_schedule(self.plan["mode"], chunk=self.plan["chunk"],
                                fwd_waves=self.plan["fwd_waves"],
                                deterministic=self.plan["deterministic"])
-        self.gst = ops.gaussians_struct(self.params)
+        self.gst = ops.gaussians_struct(self.params, sh_degree=self.active_sh)
         self.grst = ops.grads_struct(self.grads, self.n)
         self.groups = ops.adam_groups(self.params, self.grads, self.m, self.v, self.lrs)
         if self.fused_adam:
@@ -172,6 +182,10 @@ class PlainTrainer:
     def step(self, vi):
         """One training step on view vi (asynchronous; no host sync)."""
         b = self.bufs
+        if (self.active_sh < self.sh_degree and self.step_count > 0
+                and self.step_count % self.sh_up_every == 0):
+            self.active_sh += 1
+            self.gst = ops.gaussians_struct(self.params, sh_degree=self.active_sh)
         self.views.use_cameras(self.cams[vi:vi + 1])
         self._ev("project")
         b.project(self.gst)

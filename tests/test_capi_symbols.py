@@ -61,3 +61,34 @@ def test_host_only_calls(lib):
     assert st == _lib.GS_ERR_ARG and b"n_slots" in lib.gs_last_error()
     st = lib.gs_adam(None, 1, 0.9, 0.999, 1e-15, 0, 1, None)
     assert st == _lib.GS_ERR_ARG
+
+
+def test_ctypes_structs_match_the_header_layout(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets (compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    from paper_2509_12138_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = [n for n in dir(_lib) if n.startswith("gs_") and isinstance(getattr(_lib, n), type)
+               and issubclass(getattr(_lib, n), ctypes.Structure)]
+    assert "gs_gaussians" in structs and "gs_gaussian_state" in structs
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gs.h"', 'int main(void) {']
+    for s in structs:
+        lines.append(f'  printf("{s} size %zu\\n", sizeof({s}));')
+        for f, _ in getattr(_lib, s)._fields_:
+            lines.append(f'  printf("{s} {f} %zu\\n", offsetof({s}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        s, f, v = line.split()
+        cls = getattr(_lib, s)
+        want = ctypes.sizeof(cls) if f == "size" else getattr(cls, f).offset
+        assert int(v) == want, (s, f, int(v), want)

@@ -23,12 +23,12 @@ def ops(gpu):
     return _ops
 
 
-def _params(n, rng):
+def _params(n, rng, color_rows=3):
     return dict(mean=rng.normal(size=(3, n)).astype(np.float32),
                 log_scale=rng.normal(-3.0, 0.8, (3, n)).astype(np.float32),
                 quat=rng.normal(size=(4, n)).astype(np.float32),
                 opacity_logit=rng.normal(0.0, 3.0, n).astype(np.float32),
-                color=rng.normal(size=(3, n)).astype(np.float32))
+                color=rng.normal(size=(color_rows, n)).astype(np.float32))
 
 
 def _dev(d):
@@ -58,11 +58,11 @@ def test_stats_bit_exact(ops, S):
     np.testing.assert_array_equal(den.denom.cpu().numpy(), rc)
 
 
-@pytest.mark.parametrize("n", [1, 255, 4099])
-def test_select_and_apply_match_oracle(ops, n):
-    say("densify select/apply", n)
+@pytest.mark.parametrize("n,color_rows", [(1, 3), (255, 3), (4099, 3), (1000, 48), (77, 12)])
+def test_select_and_apply_match_oracle(ops, n, color_rows):
+    say("densify select/apply", n, color_rows)
     rng = np.random.default_rng(n)
-    p = _params(n, rng)
+    p = _params(n, rng, color_rows)
     m = {k: rng.normal(size=v.shape).astype(np.float32) for k, v in p.items()}
     v = {k: rng.uniform(size=x.shape).astype(np.float32) for k, x in p.items()}
     acc = rng.uniform(0, 4e-4, n).astype(np.float32)

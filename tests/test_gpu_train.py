@@ -110,3 +110,38 @@ def test_density_control_changes_the_model_and_keeps_training(tiny):
         assert torch.isfinite(v).all(), k
         assert v.shape[-1] == tr.n, k
     assert tr.views.struct.total_pairs == tr.n and tr.dev_adam.groups[0].count == 3 * tr.n
+
+
+def test_view_dependent_targets_need_spherical_harmonics(gpu):
+    """Targets whose colours depend on the view (the reference discs carry
+    degree-1 coefficients, rendered by the oracle) are fitted better by a
+    trainer with view-dependent colour (degree 1, raised from 0 after 20
+    steps) than by the plain degree-0 trainer on the same steps."""
+    say("sh training")
+    from paper_2509_12138_amd.train import PlainTrainer
+    wl = workloads.tiny_partition()
+    W, H = wl["cfg"]["width"], wl["cfg"]["height"]
+    ref = dict(wl["reference"])
+    nr = ref["opacity_logit"].shape[0]
+    rng = np.random.default_rng(17)
+    col = np.zeros((12, nr))
+    col[:3] = ref["color"]
+    col[3:] = rng.normal(0, 0.8, (9, 1))      # one view-dependent tint for every disc
+    ref["color"] = col
+    tg, mk = [], []
+    for cam in wl["cams"]:
+        r = oracle.render(oracle.project(ref, scene.camera_dict(cam)), W, H)
+        tg.append(r["image"]); mk.append(r["T_final"] <= 0.5)
+    targets = torch.as_tensor(np.stack(tg).astype(np.float32)).cuda()
+    masks = torch.as_tensor(np.stack(mk).astype(np.uint8)).cuda()
+    psnr = {}
+    for D in (0, 1):
+        tr = PlainTrainer(wl["params"], wl["cams"], targets, masks, sh_degree=D, sh_up_every=20)
+        tr.fit_capacity()
+        tr.train(300, order_seed=1002, check_every=50)
+        assert tr.active_sh == D and tr.params["color"].shape[0] == 3 * (D + 1) ** 2
+        psnr[D] = tr.evaluate()
+        for k, v in tr.params.items():
+            assert torch.isfinite(v).all(), (D, k)
+    say(f"psnr degree 0 {psnr[0]:.2f}, degree 1 {psnr[1]:.2f}")
+    assert psnr[1] > psnr[0] + 1.0
