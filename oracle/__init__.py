@@ -268,14 +268,25 @@ def loss(image, target, mask=None, lam=0.2):
 # Adam (dense, bias-corrected)
 # --------------------------------------------------------------------------
 
-def adam(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15):
-    """One Adam step (Kingma & Ba, Alg. 1) in FP64; returns new (param, m, v)."""
-    param = np.asarray(param, np.float64); grad = np.asarray(grad, np.float64)
-    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * grad
-    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * grad * grad
-    mhat = m / (1.0 - beta1 ** step)
-    vhat = v / (1.0 - beta2 ** step)
-    return param - lr * mhat / (np.sqrt(vhat) + eps), m, v
+def adam(param, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-15, visible=None):
+    """One Adam step (Kingma & Ba, Alg. 1) in FP64; returns new (param, m, v).
+
+    visible: optional boolean mask over the last axis (the Gaussians).  The
+    sparse (visible-only) form of the 3D-GS optimiser updates only the
+    Gaussians the step's views draw; the others keep parameter and both
+    moments unchanged, while the step count (and so the bias correction)
+    stays global."""
+    p0 = np.asarray(param, np.float64); grad = np.asarray(grad, np.float64)
+    m0 = np.asarray(m, np.float64); v0 = np.asarray(v, np.float64)
+    m1 = beta1 * m0 + (1.0 - beta1) * grad
+    v1 = beta2 * v0 + (1.0 - beta2) * grad * grad
+    mhat = m1 / (1.0 - beta1 ** step)
+    vhat = v1 / (1.0 - beta2 ** step)
+    p1 = p0 - lr * mhat / (np.sqrt(vhat) + eps)
+    if visible is None:
+        return p1, m1, v1
+    keep = ~np.asarray(visible, bool)
+    return (np.where(keep, p0, p1), np.where(keep, m0, m1), np.where(keep, v0, v1))
 
 
 # --------------------------------------------------------------------------

@@ -97,6 +97,33 @@ def test_adam_constant_gradient_constant_step():
         p = p_new
 
 
+def test_sparse_adam_keeps_hidden_gaussians_and_uses_the_global_step():
+    # Gaussian 0 is drawn at every step, Gaussian 1 first at step k, Gaussian
+    # 2 never; gradients are constant in time
+    b1, b2, lr, k = 0.9, 0.999, 1e-3, 7
+    g = np.array([[0.5, -2.0, 0.7], [1e-3, 3.0, -0.2]])
+    p = np.array([[1.0, 2.0, 3.0], [4.0, 5.0, 6.0]])
+    m = np.zeros_like(p); v = np.zeros_like(p)
+    for step in range(1, k + 1):
+        vis = np.array([True, step == k, False])
+        p_new, m, v = oracle.adam(p, g, m, v, lr=lr, step=step, visible=vis)
+        assert np.array_equal(p_new[:, 2], p[:, 2]) and np.all(m[:, 2] == 0) and np.all(v[:, 2] == 0)
+        if step < k:
+            assert np.array_equal(p_new[:, 1], p[:, 1])
+        p_last = p
+        p = p_new
+    # constant gradient, seen at every step: the step is lr sign(g)
+    np.testing.assert_allclose(p[:, 0] - p_last[:, 0], -lr * np.sign(g[:, 0]), rtol=1e-9)
+    # first seen at step k: zero moments, bias correction of step k
+    ratio = (1 - b1) / (1 - b1 ** k) / np.sqrt((1 - b2) / (1 - b2 ** k))
+    np.testing.assert_allclose(p[:, 1] - p_last[:, 1], -lr * ratio * np.sign(g[:, 1]), rtol=1e-9)
+    # all visible is the dense step
+    d = oracle.adam(p, g, m, v, lr=lr, step=k + 1)
+    s_ = oracle.adam(p, g, m, v, lr=lr, step=k + 1, visible=np.ones(3, bool))
+    for a, b in zip(d, s_):
+        assert np.array_equal(a, b)
+
+
 # ---------------------------------------------------------------- binning + sort
 
 def brute_tile_lists(tb, nt, depth, slot, tiles_x, tiles_per_slot, n_slots):
