@@ -60,6 +60,11 @@ def parse():
                     help="reuse the plan the autotuner cached for this workload (no re-tuning)")
     ap.add_argument("--recompute", action="store_true")
     ap.add_argument("--small", action="store_true", help="tiny config (smoke use)")
+    ap.add_argument("--sh-degree", type=int, default=0,
+                    help="view-dependent colour of this degree, active from the first step "
+                         "(the headline workload is degree 0)")
+    ap.add_argument("--sparse-adam", action="store_true",
+                    help="visible-only Adam (the headline workload uses the dense step)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (HBM counter scale)")
     return ap.parse_args()
@@ -165,7 +170,8 @@ def main():
         chunk = 0
     tr = PlainTrainer(wl["params"], wl["cams"], targets, masks, tile=tile, stored=stored,
                       schedule=sched, chunk=chunk, fwd_waves=fwd_waves,
-                      deterministic=deterministic)
+                      deterministic=deterministic, sh_degree=args.sh_degree, sh_up_every=0,
+                      sparse_adam=args.sparse_adam)
     need = tr.fit_capacity()
     log(f"max duplicates per view {need}, capacity {tr.bufs.dup_capacity}")
     rng = np.random.default_rng(1000 + 2)
@@ -254,8 +260,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"single partition: mixing-layer isosurface, {cfgd['n']} Gaussians (SH 0), "
-                        f"{cfgd['views']} orbital views at {W}x{H}, masks, batch 1 view",
+            "workload": f"single partition: mixing-layer isosurface, {cfgd['n']} Gaussians "
+                        f"(SH {args.sh_degree}), {cfgd['views']} orbital views at {W}x{H}, masks, "
+                        f"batch 1 view",
+            "optimizer": "sparse adam" if args.sparse_adam else "adam",
             "tile": f"{tile[0]}x{tile[1]}",
             "schedule": sched,
             "backward_chunk": chunk,

@@ -384,14 +384,20 @@ gs_status gs_adam_dev(const gs_adam_group* groups, int32_t n_groups, const float
  *   their m, v and lr; rows is a multiple of 3 from 3 (D+1)^2 (D =
  *   g->sh_degree) to 48: stored rows past the active degree are updated with
  *   a zero gradient, as a dense gs_adam_dev would.  grad pointers are not
- *   used.  lr_final (5 or NULL),
+ *   used.
+ *   visible_only != 0: sparse Adam, the optimiser form that updates only the
+ *   Gaussians a step draws: a Gaussian with no pair of `views` whose n_tiles
+ *   is > 0 keeps its parameters, m and v unchanged (and none of them is
+ *   read); the step count and its bias corrections stay global.  With 0,
+ *   every Gaussian is updated (dense, the 3D-GS default).  lr_final (5 or NULL),
  *   decay_steps, betas, eps and step_dev as gs_adam_dev (step_dev is
  *   incremented).  Gaussians drawn by no pair get a zero gradient.         */
 gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
                               const gs_tiling* tiling, const gs_projected* proj,
                               const float* d_rec, const gs_adam_group* groups,
                               const float* lr_final, int32_t decay_steps, float beta1,
-                              float beta2, float eps, int32_t* step_dev, void* stream);
+                              float beta2, float eps, int32_t visible_only, int32_t* step_dev,
+                              void* stream);
 
 /* ------------------------------------------------------------------------
  * Adaptive density control of the 3D-GS method each partition is trained

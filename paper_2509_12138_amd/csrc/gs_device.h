@@ -182,10 +182,14 @@ __device__ __forceinline__ void adam_schedule(int t, float b1, float b2, float l
   }
 }
 
-// One bias-corrected Adam update of a parameter p with gradient g.
+// One bias-corrected Adam update of a parameter p with gradient g.  No
+// multiply-add contraction: which product a contraction would fuse depends
+// on the surrounding code, and every kernel that steps Adam (the plain one
+// and the fused projection backward) must round alike.
 __device__ __forceinline__ void adam_update(float& p, float g, float& m, float& v, float lr,
                                             float ibc1, float ibc2, float b1, float b2,
                                             float eps) {
+#pragma clang fp contract(off)
   m = b1 * m + (1.0f - b1) * g;
   v = b2 * v + (1.0f - b2) * g * g;
   const float mh = m * ibc1;

@@ -79,9 +79,11 @@ constexpr float kSH3e = 1.445305721320277f;  // sqrt(105 / (16 pi))
 
 // f(k, Y_k, dY_k/dx, dY_k/dy, dY_k/dz) for k = 0 .. (D+1)^2 - 1 at the unit
 // vector d; each term is made where it is consumed, so no table of basis
-// values stays live.
+// values stays live.  No multiply-add contraction here: every kernel that
+// evaluates the basis gets the same bits, wherever it is inlined.
 template <int D, class F>
 __device__ __forceinline__ void sh_for_each(const float d[3], F&& f) {
+#pragma clang fp contract(off)
   f(0, kC0, 0.f, 0.f, 0.f);
   if constexpr (D >= 1) {
     const float x = d[0], y = d[1], z = d[2];
@@ -129,38 +131,15 @@ __device__ __forceinline__ void colour_fwd(const float* __restrict__ col, int64_
   }
 }
 
-// Per-thread colour-gradient accumulators of a 256-thread block: registers
-// at degree 0; above it an LDS array [rows][256] (48 KB at degree 3), which
-// keeps up to 48 running sums out of the registers the projection needs.
-template <int D>
-struct ColourAcc {
-  static constexpr int NC = 3 * (D + 1) * (D + 1);
-  static constexpr int STRIDE = D == 0 ? 1 : 256;
-  float reg[D == 0 ? NC : 1];
-  float* lds;
-  __device__ __forceinline__ void init(float* block_lds) {
-    lds = block_lds + threadIdx.x;
-#pragma unroll
-    for (int r = 0; r < NC; ++r) ptr()[r * STRIDE] = 0.f;
-  }
-  __device__ __forceinline__ float* ptr() {
-    if constexpr (D == 0) return reg;
-    else return lds;
-  }
-  __device__ __forceinline__ float get(int r) { return ptr()[r * STRIDE]; }
-};
-
 // Colour of one pair and its backward: rgb_c = max(0, sum_k Y_k(d) f_kc +
-// 1/2) (sets S.pre_rgb / S.rgb); dL/df_kc = Y_k dL/drgb_c where the clamp
-// passes, and the mean moves the direction: dL/dmean += (I - d d^T) dL/dd /
-// |v| with dL/dd = sum_c gc_c sum_k f_kc grad Y_k.  One pass over the
-// coefficients makes both the colour and the per-channel direction
-// gradients; a second pass over the basis alone adds the coefficient
-// gradients into gcol (element r at gcol[r * STRIDE]).
-template <int D, int STRIDE>
+// 1/2) (sets S.pre_rgb / S.rgb); gc_c = dL/drgb_c where the clamp passes;
+// the mean moves the direction: dL/dmean += (I - d d^T) dL/dd / |v| with
+// dL/dd = sum_c gc_c sum_k f_kc grad Y_k.  One pass over the coefficients
+// makes both the colour and the per-channel direction gradients.
+template <int D>
 __device__ __forceinline__ void colour_bwd(const float* __restrict__ col, int64_t n, int64_t g,
                                            ProjState& S, const float* __restrict__ drgb,
-                                           float* gcol, float gmu[3]) {
+                                           float gc[3], float gmu[3]) {
   float acc[3] = {0.f, 0.f, 0.f};
   float gdc[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
   // walk the rows from a pointer the compiler cannot see through, so the
@@ -180,17 +159,12 @@ __device__ __forceinline__ void colour_bwd(const float* __restrict__ col, int64_
       }
     }
   });
-  float gc[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     S.pre_rgb[c] = acc[c] + 0.5f;
     S.rgb[c] = fmaxf(S.pre_rgb[c], 0.0f);
     gc[c] = S.pre_rgb[c] >= 0.0f ? drgb[c] : 0.0f;
   }
-  sh_for_each<D>(S.dir, [&](int k, float Y, float, float, float) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) gcol[(3 * k + c) * STRIDE] += Y * gc[c];
-  });
   if constexpr (D >= 1) {
     float gd[3];
 #pragma unroll
@@ -202,6 +176,37 @@ __device__ __forceinline__ void colour_bwd(const float* __restrict__ col, int64_
     gmu[2] += (gd[2] - z * dd) * S.ivlen;
   }
 }
+
+// add(r, Y_k(d) gc_c) for every coefficient row r = 3k + c: the pair's
+// gradient of the colour coefficients.
+template <int D, class Add>
+__device__ __forceinline__ void colour_coef_grads(const float d[3], const float gc[3], Add&& add) {
+  sh_for_each<D>(d, [&](int k, float Y, float, float, float) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) add(3 * k + c, Y * gc[c]);
+  });
+}
+
+// Colour-gradient running sums of the fused kernel over several slots:
+// registers at degree 0; above it an LDS array [rows][256] per block (48 KB
+// at degree 3), which keeps up to 48 sums out of the registers the
+// projection needs.
+template <int D>
+struct ColourAcc {
+  static constexpr int NC = 3 * (D + 1) * (D + 1);
+  static constexpr int STRIDE = D == 0 ? 1 : 256;
+  float reg[D == 0 ? NC : 1];
+  float* lds;
+  __device__ __forceinline__ void init(float* block_lds) {
+    lds = block_lds + threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) at(r) = 0.f;
+  }
+  __device__ __forceinline__ float& at(int r) {
+    if constexpr (D == 0) return reg[r];
+    else return lds[r * STRIDE];
+  }
+};
 
 __device__ __forceinline__ void project_core(const float mu[3], const float ls[3], const float q[4],
                                              float ol, const gs_camera& cam,
@@ -464,11 +469,12 @@ __device__ __forceinline__ void project_bwd_core(const ProjState& S, const gs_ca
   gq[3] += (dz - z * dot) * S.qinv;
 }
 
-// Above degree 0 the LDS accumulators allow 3 blocks per CU (3 waves per
-// SIMD); registers are capped to match, so the scheduler cannot hoist every
-// coefficient load at once.
+// A thread owns a Gaussian and loops over the slots drawing it.  Degree 0
+// sums the colour gradient in registers; above it every pair adds its
+// coefficient gradients to the gradient array directly (in slot order, the
+// same additions as a running sum into zeroed arrays).
 template <int D>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 0 ? 1 : 3))) void
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 3 ? 3 : 1))) void
 k_project_bwd(
     Params P, GradPtrs Gr, const int64_t* __restrict__ pair_offset,
     const int64_t* __restrict__ gauss_offset, const gs_camera* __restrict__ cams, int n_slots,
@@ -476,10 +482,8 @@ k_project_bwd(
     const float* __restrict__ d_rec) {
   int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (g >= P.n) return;
-  constexpr int NC = ColourAcc<D>::NC;
-  __shared__ float s_gcol[D == 0 ? 1 : NC * 256];
-  ColourAcc<D> gcol;
-  gcol.init(s_gcol);
+  const int64_t n = P.n;
+  float acc0[3] = {0.f, 0.f, 0.f};
   float mu[3], ls[3], q[4], ol;
   load_gaussian(P, g, mu, ls, q, ol);
   float gmu[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
@@ -499,18 +503,27 @@ k_project_bwd(
     for (int k = 0; k < 9; ++k) dr[k] = d_rec[p * GS_DREC_STRIDE + k];
     project_bwd_core(S, cams[s], dr, gmu, gls, gq, gol);
     // the colour last, so its coefficients are live only here
-    colour_bwd<D, ColourAcc<D>::STRIDE>(P.col, P.n, g, S, dr + 6, gcol.ptr(), gmu);
+    float gc[3];
+    colour_bwd<D>(P.col, n, g, S, dr + 6, gc, gmu);
+    if constexpr (D == 0) {
+      colour_coef_grads<0>(S.dir, gc, [&](int r, float x) { acc0[r] += x; });
+    } else {
+      float* gp = Gr.col + g;
+      asm volatile("" : "+v"(gp));
+      colour_coef_grads<D>(S.dir, gc, [&](int r, float x) { gp[(int64_t)r * n] += x; });
+    }
     any = true;
   }
   if (!any) return;
-  const int64_t n = P.n;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     Gr.mean[k * n + g] += gmu[k];
     Gr.ls[k * n + g] += gls[k];
   }
+  if constexpr (D == 0) {
 #pragma unroll
-  for (int k = 0; k < NC; ++k) Gr.col[k * n + g] += gcol.get(k);
+    for (int k = 0; k < 3; ++k) Gr.col[k * n + g] += acc0[k];
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) Gr.quat[k * n + g] += gq[k];
   Gr.ol[g] += gol;
@@ -526,15 +539,20 @@ struct AdamFused {
   float* m[5];
   float* v[5];
   int col_rows;           // rows of the colour arrays (>= 3 (D+1)^2)
+  int visible_only;       // sparse Adam: Gaussians drawn by no pair are left as they are
   float lr[5], lr_final[5];
   int decay_steps;
   float b1, b2, eps;
   const int32_t* step_dev;
 };
 
-template <int D>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D == 0 ? 1 : 3))) void
-k_project_bwd_adam(
+// ONE (degree > 0, calls with a single slot): the Gaussian's colour
+// gradient is Y(d) gc of its one pair, so only d and gc are kept and the
+// sums are made in the update loop; otherwise above degree 0 the sums live
+// in LDS, which allows 3 blocks per CU, and registers are capped to match.
+template <int D, bool ONE>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(D == 0 || (ONE && D < 3) ? 1 : 3))) void k_project_bwd_adam(
     Params P, AdamFused A, const int64_t* __restrict__ pair_offset,
     const int64_t* __restrict__ gauss_offset, const gs_camera* __restrict__ cams, int n_slots,
     int W, int H, int tw, int th, const int32_t* __restrict__ n_tiles,
@@ -553,10 +571,23 @@ k_project_bwd_adam(
   __syncthreads();
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (g >= P.n) return;
+  if (A.visible_only) {
+    // sparse Adam: a Gaussian drawn by no pair keeps parameters and moments,
+    // so nothing of it is read or written
+    bool drawn = false;
+    for (int s = 0; s < n_slots && !drawn; ++s) {
+      const int64_t g0 = gauss_offset[s];
+      if (g < g0 || g >= g0 + (pair_offset[s + 1] - pair_offset[s])) continue;
+      drawn = n_tiles[pair_offset[s] + (g - g0)] > 0;
+    }
+    if (!drawn) return;
+  }
   constexpr int NC = ColourAcc<D>::NC;
-  __shared__ float s_gcol[D == 0 ? 1 : NC * 256];
+  constexpr bool kLds = D > 0 && !ONE;
+  __shared__ float s_gcol[kLds ? NC * 256 : 1];
   ColourAcc<D> gcol;
-  gcol.init(s_gcol);
+  if constexpr (!ONE) gcol.init(s_gcol);
+  float one_dir[3] = {0.f, 0.f, 1.f}, one_gc[3] = {0.f, 0.f, 0.f};
   float mu[3], ls[3], q[4], ol;
   load_gaussian(P, g, mu, ls, q, ol);
   float gmu[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f};
@@ -575,7 +606,17 @@ k_project_bwd_adam(
     for (int k = 0; k < 9; ++k) dr[k] = d_rec[p * GS_DREC_STRIDE + k];
     project_bwd_core(S, cams[s], dr, gmu, gls, gq, gol);
     // the colour last, so its coefficients are live only here
-    colour_bwd<D, ColourAcc<D>::STRIDE>(P.col, P.n, g, S, dr + 6, gcol.ptr(), gmu);
+    float gc[3];
+    colour_bwd<D>(P.col, P.n, g, S, dr + 6, gc, gmu);
+    if constexpr (ONE) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        one_dir[j] = S.dir[j];
+        one_gc[j] = gc[j];
+      }
+    } else {
+      colour_coef_grads<D>(S.dir, gc, [&](int r, float x) { gcol.at(r) += x; });
+    }
   }
   // the gradient a separate pass would add to zeroed arrays
   const float G[11] = {0.f + gmu[0], 0.f + gmu[1], 0.f + gmu[2], 0.f + gls[0], 0.f + gls[1],
@@ -602,16 +643,21 @@ k_project_bwd_adam(
   float* cm = A.m[4] + g;
   float* cv = A.v[4] + g;
   if constexpr (D >= 1) asm volatile("" : "+v"(cp), "+v"(cm), "+v"(cv));
-#pragma unroll
-  for (int r = 0; r < NC; ++r) {
+  auto colour_row = [&](float grad) {
     float pv = *cp, m = *cm, v = *cv;
-    adam_update(pv, 0.f + gcol.get(r), m, v, s_lr[4], ibc1, ibc2, A.b1, A.b2, A.eps);
+    adam_update(pv, 0.f + grad, m, v, s_lr[4], ibc1, ibc2, A.b1, A.b2, A.eps);
     *cp = pv;
     *cm = m;
     *cv = v;
     cp += n;
     cm += n;
     cv += n;
+  };
+  if constexpr (ONE) {
+    colour_coef_grads<D>(one_dir, one_gc, [&](int, float x) { colour_row(x); });
+  } else {
+#pragma unroll
+    for (int r = 0; r < NC; ++r) colour_row(gcol.at(r));
   }
   for (int r = NC; r < A.col_rows; ++r) {
     float pv = *cp, m = *cm, v = *cv;
@@ -710,7 +756,8 @@ gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
                               const gs_tiling* tiling, const gs_projected* proj,
                               const float* d_rec, const gs_adam_group* groups,
                               const float* lr_final, int32_t decay_steps, float beta1,
-                              float beta2, float eps, int32_t* step_dev, void* stream) {
+                              float beta2, float eps, int32_t visible_only, int32_t* step_dev,
+                              void* stream) {
   clear_error();
   GS_REQUIRE(g && proj && groups && step_dev, "gs_project_bwd_adam: NULL argument");
   gs_status st = check_views(views, tiling, "gs_project_bwd_adam");
@@ -736,6 +783,7 @@ gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
   const int rows[5] = {3, 3, 4, 1, col_rows};
   AdamFused A;
   A.col_rows = col_rows;
+  A.visible_only = visible_only ? 1 : 0;
   for (int i = 0; i < 5; ++i) {
     GS_REQUIRE(groups[i].param == arrays[i] && groups[i].count == rows[i] * g->n,
                "gs_project_bwd_adam: group %d must be the Gaussians' array %d (%d x n elements)",
@@ -762,12 +810,20 @@ gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
                    (proj->m == 0 || (d_rec && proj->n_tiles)),
                "gs_project_bwd_adam: arrays must not be NULL");
     Params P{g->mean, g->log_scale, g->quat, g->opacity_logit, g->color, g->n};
+    const dim3 grid((unsigned)ceil_div(g->n, 256));
     sh_dispatch(g->sh_degree, [&](auto D) {
-      hipLaunchKernelGGL(k_project_bwd_adam<decltype(D)::value>,
-                         dim3((unsigned)ceil_div(g->n, 256)), dim3(256), 0, s, P, A,
-                         views->pair_offset, views->gauss_offset, views->cams, views->n_slots,
-                         tiling->width, tiling->height, tiling->tile_w, tiling->tile_h,
-                         proj->n_tiles, d_rec);
+      constexpr int kD = decltype(D)::value;
+      auto launch = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, grid, dim3(256), 0, s, P, A, views->pair_offset,
+                           views->gauss_offset, views->cams, views->n_slots, tiling->width,
+                           tiling->height, tiling->tile_w, tiling->tile_h, proj->n_tiles, d_rec);
+      };
+      if constexpr (kD > 0) {
+        if (views->n_slots == 1) launch(k_project_bwd_adam<kD, true>);
+        else launch(k_project_bwd_adam<kD, false>);
+      } else {
+        launch(k_project_bwd_adam<0, false>);
+      }
     });
     GS_LAUNCH_CHECK("gs_project_bwd_adam");
   }

@@ -296,14 +296,15 @@ class RasterBuffers:
              C.byref(self.tiling), C.byref(self.proj), _ptr(self.d_rec),
              C.byref(grads_struct_), s)
 
-    def project_bwd_adam(self, gstruct, adam, stream=None):
+    def project_bwd_adam(self, gstruct, adam, visible_only=False, stream=None):
         """gs_project_bwd_adam: projection backward and the DeviceAdam step
-        `adam` in one pass (gradient arrays untouched)."""
+        `adam` in one pass (gradient arrays untouched); visible_only selects
+        the sparse step (Gaussians the views do not draw stay as they are)."""
         s = stream or stream_handle()
         call("gs_project_bwd_adam", C.byref(gstruct), C.byref(self.views.struct),
              C.byref(self.tiling), C.byref(self.proj), _ptr(self.d_rec), adam.groups,
              adam.lr_final, adam.decay_steps, adam.betas[0], adam.betas[1], adam.betas[2],
-             _ptr(adam.step_dev), s)
+             int(bool(visible_only)), _ptr(adam.step_dev), s)
 
     def zero_d_rec(self, stream=None):
         s = stream or stream_handle()

@@ -67,8 +67,12 @@ class PlainTrainer:
     def __init__(self, params, cams_np, targets, masks, tile=(16, 16), lam=0.2,
                  bg=(0.0, 0.0, 0.0), stored=True, extent=2.75, lrs=None, dup_capacity=None,
                  schedule="default", chunk=0, fwd_waves=1, deterministic=False, fused_adam=True,
-                 density=None, sh_degree=0, sh_up_every=1000, device="cuda"):
+                 density=None, sh_degree=0, sh_up_every=1000, sparse_adam=False,
+                 device="cuda"):
         self.device = device
+        if sparse_adam and not fused_adam:
+            raise ValueError("sparse_adam needs fused_adam (the fused call makes the step)")
+        self.sparse_adam = bool(sparse_adam)
         self.V = len(cams_np)
         self.W, self.H = int(cams_np[0]["width"]), int(cams_np[0]["height"])
         self.cams_np = cams_np
@@ -94,14 +98,15 @@ class PlainTrainer:
              if not torch.is_tensor(v) else v.contiguous().to(device) for k, v in params.items()}
         # view-dependent colour: coefficients up to sh_degree (the higher
         # ones start at zero); the active degree starts at 0 and rises by
-        # one every sh_up_every steps (the 3D-GS schedule)
+        # one every sh_up_every steps (the 3D-GS schedule), or is sh_degree
+        # from the start when sh_up_every <= 0
         self.sh_degree, self.sh_up_every = int(sh_degree), int(sh_up_every)
         rows = 3 * (self.sh_degree + 1) ** 2
         if p["color"].shape[0] < rows:
             pad = torch.zeros((rows - p["color"].shape[0], p["color"].shape[1]),
                               dtype=p["color"].dtype, device=device)
             p["color"] = torch.cat([p["color"], pad]).contiguous()
-        self.active_sh = 0
+        self.active_sh = 0 if self.sh_up_every > 0 else self.sh_degree
         self._bind(p, {k: torch.zeros_like(v) for k, v in p.items()},
                    {k: torch.zeros_like(v) for k, v in p.items()}, dup_capacity)
         if density is not None:
@@ -183,7 +188,7 @@ class PlainTrainer:
         """One training step on view vi (asynchronous; no host sync)."""
         b = self.bufs
         if (self.active_sh < self.sh_degree and self.step_count > 0
-                and self.step_count % self.sh_up_every == 0):
+                and self.sh_up_every > 0 and self.step_count % self.sh_up_every == 0):
             self.active_sh += 1
             self.gst = ops.gaussians_struct(self.params, sh_degree=self.active_sh)
         self.views.use_cameras(self.cams[vi:vi + 1])
@@ -207,7 +212,7 @@ class PlainTrainer:
         self._ev("project_bwd")
         self.step_count += 1
         if self.fused_adam:
-            b.project_bwd_adam(self.gst, self.dev_adam)
+            b.project_bwd_adam(self.gst, self.dev_adam, visible_only=self.sparse_adam)
             self._ev("adam")
         else:
             b.project_bwd(self.gst, self.grst)
@@ -299,9 +304,12 @@ class BatchedTrainer:
     def __init__(self, parts, cams_np, views_per_part=4, tile=(16, 16), schedule="lpt",
                  chunk=64, stored=True, lam=0.2, bg=(0.0, 0.0, 0.0), extent=2.75, lrs=None,
                  order_seed=0, graphs=True, dup_capacity=None, fwd_waves=1, deterministic=False,
-                 fused_adam=True, device="cuda"):
+                 fused_adam=True, sparse_adam=False, device="cuda"):
         from .scene import concat_params
         self.device = device
+        if sparse_adam and not fused_adam:
+            raise ValueError("sparse_adam needs fused_adam (the fused call makes the step)")
+        self.sparse_adam = bool(sparse_adam)
         self.P = len(parts)
         self.vpp = views_per_part
         self.counts = [int(p["params"]["opacity_logit"].shape[-1]) for p in parts]
@@ -373,7 +381,7 @@ class BatchedTrainer:
         b.zero_d_rec()
         b.raster_bwd(self.loss.d_image, self.bg, self.mode)
         if self.fused_adam:
-            b.project_bwd_adam(self.gst, self.adam)
+            b.project_bwd_adam(self.gst, self.adam, visible_only=self.sparse_adam)
         else:
             b.project_bwd(self.gst, self.grst)
             self.adam(zero_grad=True)

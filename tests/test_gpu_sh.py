@@ -162,12 +162,15 @@ def test_lower_active_degree_draws_the_leading_rows(ops):
         ops.gaussians_struct(dict(dp, color=dp["color"][:12].contiguous()), sh_degree=2)
 
 
-@pytest.mark.parametrize("D,active", [(3, 3), (3, 1), (1, 1)])
-def test_fused_projection_backward_adam_bitwise_with_sh(ops, D, active):
-    say("project_bwd + adam fused, sh", D, active)
+@pytest.mark.parametrize("D,active,V", [(3, 3, 3), (3, 1, 3), (1, 1, 3), (3, 3, 1), (3, 2, 1),
+                                        (1, 1, 1)])
+def test_fused_projection_backward_adam_bitwise_with_sh(ops, D, active, V):
+    """Fused against unfused, several slots (LDS sums) and one slot (the
+    kernel that keeps only the pair's direction and colour gradient)."""
+    say("project_bwd + adam fused, sh", D, active, V)
     W, H, n = 200, 150, 4000
     params = sh_params(n, 95, D)
-    cams = scene.orbit_cameras(3, W, H)
+    cams = scene.orbit_cameras(V, W, H)
     lrs = {"mean": 4.4e-4, "log_scale": 5e-3, "quat": 1e-3, "opacity_logit": 5e-2,
            "color": 2.5e-3}
     runs = []
@@ -183,8 +186,8 @@ def test_fused_projection_backward_adam_bitwise_with_sh(ops, D, active):
         rng = np.random.default_rng(6)
         for step in range(3):
             bufs.project(gst)
-            drec = rng.normal(size=(3 * n, 9)).astype(np.float32)
-            drec[rng.uniform(size=3 * n) < 0.3] = 0.0
+            drec = rng.normal(size=(V * n, 9)).astype(np.float32)
+            drec[rng.uniform(size=V * n) < 0.3] = 0.0
             bufs.d_rec.copy_(torch.as_tensor(drec))
             if fused:
                 bufs.project_bwd_adam(gst, adam)

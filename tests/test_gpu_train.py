@@ -26,12 +26,12 @@ def tiny(gpu):
     return wl, targets, masks
 
 
-@pytest.mark.parametrize("stored", [True, False])
-def test_tiny_training_improves_psnr(tiny, stored):
-    say("train tiny stored=%s" % stored)
+@pytest.mark.parametrize("stored,sparse", [(True, False), (False, False), (True, True)])
+def test_tiny_training_improves_psnr(tiny, stored, sparse):
+    say("train tiny stored=%s sparse=%s" % (stored, sparse))
     from paper_2509_12138_amd.train import PlainTrainer
     wl, targets, masks = tiny
-    tr = PlainTrainer(wl["params"], wl["cams"], targets, masks, stored=stored)
+    tr = PlainTrainer(wl["params"], wl["cams"], targets, masks, stored=stored, sparse_adam=sparse)
     tr.fit_capacity()
     p0 = tr.evaluate()
     hist = tr.train(100, order_seed=1001, eval_every=50, check_every=25)
