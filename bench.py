@@ -63,6 +63,12 @@ def parse():
     ap.add_argument("--sh-degree", type=int, default=0,
                     help="view-dependent colour of this degree, active from the first step "
                          "(the headline workload is degree 0)")
+    ap.add_argument("--fov", type=float, default=50.0,
+                    help="horizontal field of view of the orbit in degrees (the workload: 50); "
+                         "narrower views draw part of the partition")
+    ap.add_argument("--order", choices=["morton", "sampled"], default="morton",
+                    help="storage order of the Gaussians: Z-order of their means, or the order "
+                         "they were sampled in")
     ap.add_argument("--sparse-adam", action="store_true",
                     help="visible-only Adam (the headline workload uses the dense step)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -138,7 +144,9 @@ def main():
     from paper_2509_12138_amd import _lib, workloads
     from paper_2509_12138_amd.train import PlainTrainer
     _lib.load()
-    cfg = dict(n=20000, n_ref=80000, views=8, width=320, height=180) if args.small else None
+    cfg = dict(n=20000, n_ref=80000, views=8, width=320, height=180) if args.small else {}
+    cfg["fov"] = args.fov
+    cfg["order"] = args.order
     t0 = time.perf_counter()
     wl = workloads.realistic_partition(cfg)
     log(f"scene built in {time.perf_counter() - t0:.1f}s")
@@ -209,6 +217,7 @@ def main():
     tr.bufs.render_checked(tr.gst, tr.bg)
     import torch as _t
     blended = float(tr.bufs.count_blended()[0].to(_t.int64).sum())
+    drawn = float((tr.bufs.n_tiles > 0).float().mean())
     evals_fwd = evals_bwd = blended
     # list positions visited before each pixel stops (what a rasteriser with
     # no culling below the tile evaluates), reported beside it
@@ -261,9 +270,11 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"single partition: mixing-layer isosurface, {cfgd['n']} Gaussians "
-                        f"(SH {args.sh_degree}), {cfgd['views']} orbital views at {W}x{H}, masks, "
-                        f"batch 1 view",
+                        f"(SH {args.sh_degree}), {cfgd['views']} orbital views at {W}x{H}"
+                        + (f" (field of view {args.fov:g} deg)" if args.fov != 50.0 else "")
+                        + ", masks, batch 1 view",
             "optimizer": "sparse adam" if args.sparse_adam else "adam",
+            "gaussian_order": args.order,
             "tile": f"{tile[0]}x{tile[1]}",
             "schedule": sched,
             "backward_chunk": chunk,
@@ -274,7 +285,7 @@ def main():
             "duplicates_per_view": need,
         },
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "pairs": {"blended": blended, "list_positions": list_pairs},
+        "pairs": {"blended": blended, "list_positions": list_pairs, "drawn_gaussians": drawn},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

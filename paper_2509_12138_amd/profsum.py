@@ -24,7 +24,7 @@ def short(name):
 
 
 def timed_window(rows, steps):
-    proj = [r for r in rows if short(r["Kernel_Name"]) == "k_project"]
+    proj = [r for r in rows if short(r["Kernel_Name"]).split("<")[0] == "k_project"]
     if len(proj) < steps + 1:
         raise SystemExit(f"only {len(proj)} k_project dispatches; need {steps + 1}")
     t0 = int(proj[-steps - 1]["Start_Timestamp"])

@@ -54,6 +54,24 @@ def look_at(center, target=(0.0, 0.0, 0.0), up=(0.0, 0.0, 1.0)):
     return R, -R @ c
 
 
+def morton_order(points, bits=10):
+    """Permutation that sorts points along a Z-order (Morton) curve of their
+    positions quantised to 2^bits cells per axis over their bounding box
+    (stable on equal codes).  Stored in this order, Gaussians that are close
+    in space are close in memory: a view's visible set then covers whole
+    wavefronts and cache lines, and a tile's list gathers neighbouring
+    records."""
+    p = np.asarray(points, np.float64)
+    lo, hi = p.min(0), p.max(0)
+    q = np.floor((p - lo) / np.maximum(hi - lo, 1e-30) * ((1 << bits) - 1) + 0.5)
+    q = np.clip(q, 0, (1 << bits) - 1).astype(np.uint64)
+    code = np.zeros(len(p), np.uint64)
+    for b in range(bits):
+        for a in range(3):
+            code |= ((q[:, a] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + (2 - a))
+    return np.argsort(code, kind="stable")
+
+
 def orbit_cameras(n_views, width, height, fov_x_deg=50.0, radius=2.5, znear=0.2):
     """Fibonacci-sphere orbit: z_i = 1 - (2i+1)/V, golden-angle azimuth."""
     cams = np.zeros(n_views, CAMERA_DTYPE)

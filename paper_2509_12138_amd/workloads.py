@@ -42,8 +42,12 @@ def realistic_partition(cfg=None, with_reference=True):
     cfg = dict(REALISTIC, **(cfg or {}))
     mi = scene.MixingInterface(seed=cfg["seed"])
     pts, nrm = _chunked_sample(mi, cfg["n"], cfg["seed"] + 10)
+    if cfg.get("order", "morton") == "morton":
+        perm = scene.morton_order(pts)
+        pts, nrm = pts[perm], nrm[perm]
     params = init_gaussians(pts, nrm)
-    cams = scene.orbit_cameras(cfg["views"], cfg["width"], cfg["height"])
+    cams = scene.orbit_cameras(cfg["views"], cfg["width"], cfg["height"],
+                               fov_x_deg=cfg.get("fov", 50.0))
     out = dict(params=params, cams=cams, cfg=cfg, points=pts, normals=nrm)
     if with_reference:
         rp, rn = _chunked_sample(mi, cfg["n_ref"], cfg["seed"] + 100)

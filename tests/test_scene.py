@@ -48,3 +48,17 @@ def test_views_table():
     po, go = scene.views_table([5, 3], 2)
     np.testing.assert_array_equal(po, [0, 5, 10, 13, 16])
     np.testing.assert_array_equal(go, [0, 0, 5, 5])
+
+
+def test_morton_order_is_a_permutation_that_keeps_neighbours_close():
+    rng = np.random.default_rng(3)
+    p = rng.uniform(-1, 1, (20000, 3))
+    o = scene.morton_order(p)
+    assert np.array_equal(np.sort(o), np.arange(len(p)))
+    step = np.linalg.norm(np.diff(p[o], axis=0), axis=1)
+    rand = np.linalg.norm(np.diff(p, axis=0), axis=1)
+    assert np.median(step) < 0.1 * np.median(rand)
+    # the 8 octant corners: each bit triple is (x, y, z), x the highest
+    c = np.array([[x, y, z] for z in (0, 1) for y in (0, 1) for x in (0, 1)], float)
+    code = 4 * c[:, 0] + 2 * c[:, 1] + c[:, 2]
+    assert np.array_equal(scene.morton_order(c), np.argsort(code, kind="stable"))
