@@ -237,12 +237,17 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
 // count[0] = m.  Depths of visible pairs are positive, so their bits order
 // as the floats; the passes sort the low 32 bits only, the pair's tile count
 // and slot ride along for the scan and the emission.
+// Also clears the n_range_words words of the tile ranges (grid-stride), so
+// the bin/sort needs no separate fill before k_ranges writes them.
 __global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ rec,
                                                    const int32_t* __restrict__ n_tiles, int64_t m,
                                                    uint64_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals,
-                                                   int64_t* __restrict__ count) {
+                                                   int64_t* __restrict__ count,
+                                                   uint32_t* __restrict__ ranges,
+                                                   int64_t n_range_words) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (int64_t w = i; w < n_range_words; w += (int64_t)gridDim.x * 256) ranges[w] = 0u;
   if (i == 0) count[0] = m;
   if (i >= m) return;
   const uint64_t nt = (uint64_t)max(n_tiles[i], 0);
@@ -464,9 +469,9 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   uint32_t* e0 = emit_out ? ((passes % 2 == 0) ? emit_out : emit_alt) : nullptr;
   uint32_t* e1 = emit_out ? ((passes % 2 == 0) ? emit_alt : emit_out) : nullptr;
 
-  st = gs_zero(tile_ranges, sizeof(uint32_t) * 2 * (size_t)n_tiles_all, stream);
-  if (st != GS_OK) return st;
   if (m == 0) {
+    st = gs_zero(tile_ranges, sizeof(uint32_t) * 2 * (size_t)n_tiles_all, stream);
+    if (st != GS_OK) return st;
     st = gs_zero(count, sizeof(int64_t) * 2, stream);
     if (st != GS_OK) return st;
     if (status) {
@@ -482,7 +487,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   uint32_t* pv[2] = {(uint32_t*)(w + L.off_pvals[0]), (uint32_t*)(w + L.off_pvals[1])};
   int64_t* count_pairs = count + 1;
   hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, proj->rec,
-                     proj->n_tiles, m, pk[0], pv[0], count_pairs);
+                     proj->n_tiles, m, pk[0], pv[0], count_pairs, tile_ranges, 2 * n_tiles_all);
   GS_LAUNCH_CHECK("gs_bin_sort/depth_keys");
   for (int p = 0; p < 4; ++p) {
     const int shift = p * kRadixBits;

@@ -857,44 +857,70 @@ __global__ __launch_bounds__(kOrderThreads) void k_order_scatter(const uint32_t*
   if (t < n_tiles) order[base[b] + local] = (uint32_t)t;
 }
 
+// The same order from one work-group, for up to kOrderOneMax tiles: bucket
+// counts in LDS, the descending-cost starts, then every tile's slot from an
+// LDS cursor per bucket (no workspace, one launch).
+constexpr int kOrderOneThreads = 1024;
+constexpr int64_t kOrderOneMax = 65536;
+
+__global__ __launch_bounds__(kOrderOneThreads) void k_order_one(const uint32_t* __restrict__ ranges,
+                                                                int n_tiles,
+                                                                uint32_t* __restrict__ order) {
+  __shared__ uint32_t h[kOrderBuckets], cur[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += kOrderOneThreads)
+    atomicAdd(&h[len_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = kOrderBuckets - 1; b >= 0; --b) {   // descending cost
+      cur[b] = run;
+      run += h[b];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += kOrderOneThreads)
+    order[atomicAdd(&cur[len_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u)] = (uint32_t)t;
+}
+
 __global__ void k_reset_queue(uint32_t* q) {
   if (threadIdx.x == 0) q[0] = 0u;
 }
 
 // ---------------------------------------------------------------- chunk items
 
-// offset[t] = ceil(len(t) / chunk); then an exclusive scan over n_tiles + 1
-// entries; then items[offset[t] + c] = t.
-__global__ __launch_bounds__(256) void k_chunk_count(const uint32_t* __restrict__ ranges,
-                                                     int64_t n_tiles, int chunk,
-                                                     uint32_t* __restrict__ offset) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t < n_tiles) offset[t] = (ranges[2 * t + 1] - ranges[2 * t] + chunk - 1) / chunk;
-  if (t == n_tiles) offset[t] = 0;
-}
+// offset[t] = exclusive scan of ceil(len(t) / chunk) over n_tiles + 1
+// entries, from one work-group (thread j owns a contiguous segment of tiles;
+// the ranges it reads are small); then a grid of threads, one per tile,
+// writes items[offset[t] + c] = t (items past max_items are dropped).  The
+// fill stays a grid: from one work-group, one CU's memory pipeline would
+// issue every scattered item store.
+constexpr int kChunkThreads = 1024;
 
-// single work-group exclusive scan of n entries in place (n up to a few 1e5)
-__global__ __launch_bounds__(1024) void k_scan_small(uint32_t* __restrict__ v, int64_t n) {
-  __shared__ uint32_t part[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t b0 = t * per, b1 = min(b0 + per, n);
-  uint32_t s = 0;
-  for (int64_t i = b0; i < b1; ++i) s += v[i];
-  part[t] = s;
+__global__ __launch_bounds__(kChunkThreads) void k_chunk_scan(const uint32_t* __restrict__ ranges,
+                                                              int64_t n_tiles, int chunk,
+                                                              uint32_t* __restrict__ offset) {
+  __shared__ uint32_t part[kChunkThreads];
+  const int j = threadIdx.x;
+  const int64_t per = (n_tiles + kChunkThreads - 1) / kChunkThreads;
+  const int64_t b0 = min((int64_t)j * per, n_tiles), b1 = min(b0 + per, n_tiles);
+  uint32_t sum = 0;
+  for (int64_t t = b0; t < b1; ++t) sum += (ranges[2 * t + 1] - ranges[2 * t] + chunk - 1) / chunk;
+  part[j] = sum;
   __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    uint32_t x = t >= d ? part[t - d] : 0u;
+  for (int d = 1; d < kChunkThreads; d <<= 1) {
+    const uint32_t x = j >= d ? part[j - d] : 0u;
     __syncthreads();
-    part[t] += x;
+    part[j] += x;
     __syncthreads();
   }
-  uint32_t run = t > 0 ? part[t - 1] : 0u;
-  for (int64_t i = b0; i < b1; ++i) {
-    const uint32_t x = v[i];
-    v[i] = run;
-    run += x;
+  uint32_t run = j > 0 ? part[j - 1] : 0u;
+  for (int64_t t = b0; t < b1; ++t) {
+    offset[t] = run;
+    run += (ranges[2 * t + 1] - ranges[2 * t] + chunk - 1) / chunk;
   }
+  if (j == kChunkThreads - 1) offset[n_tiles] = part[kChunkThreads - 1];
 }
 
 __global__ __launch_bounds__(256) void k_chunk_items(const uint32_t* __restrict__ offset,
@@ -1083,6 +1109,12 @@ gs_status gs_tile_order(const uint32_t* tile_ranges, int64_t n_tiles, void* ws, 
   uint32_t* start = hist + kOrderBuckets;
   uint32_t* cursor = start + kOrderBuckets;
   hipStream_t s = as_stream(stream);
+  if (n_tiles <= kOrderOneMax) {
+    hipLaunchKernelGGL(k_order_one, dim3(1), dim3(kOrderOneThreads), 0, s, tile_ranges,
+                       (int)n_tiles, order);
+    GS_LAUNCH_CHECK("gs_tile_order/one");
+    return GS_OK;
+  }
   gs_status st = gs_zero(ws, 3 * kOrderBuckets * sizeof(uint32_t), stream);
   if (st != GS_OK) return st;
   const unsigned blocks = (unsigned)ceil_div(n_tiles, kOrderThreads);
@@ -1111,15 +1143,14 @@ gs_status gs_chunk_items(const uint32_t* tile_ranges, int64_t n_tiles, int32_t c
   GS_REQUIRE(tile_ranges && chunk_offset && chunk_items, "gs_chunk_items: NULL argument");
   GS_REQUIRE(max_items > 0, "gs_chunk_items: max_items must be positive");
   hipStream_t s = as_stream(stream);
-  const unsigned blocks = (unsigned)ceil_div(n_tiles + 1, 256);
-  hipLaunchKernelGGL(k_chunk_count, dim3(blocks), dim3(256), 0, s, tile_ranges, n_tiles, chunk,
+  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kChunkThreads), 0, s, tile_ranges, n_tiles, chunk,
                      chunk_offset);
-  GS_LAUNCH_CHECK("gs_chunk_items/count");
-  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, chunk_offset, n_tiles + 1);
   GS_LAUNCH_CHECK("gs_chunk_items/scan");
-  hipLaunchKernelGGL(k_chunk_items, dim3(blocks), dim3(256), 0, s, chunk_offset, n_tiles, max_items,
-                     chunk_items);
-  GS_LAUNCH_CHECK("gs_chunk_items/items");
+  if (n_tiles > 0) {
+    hipLaunchKernelGGL(k_chunk_items, dim3((unsigned)ceil_div(n_tiles, 256)), dim3(256), 0, s,
+                       chunk_offset, n_tiles, max_items, chunk_items);
+    GS_LAUNCH_CHECK("gs_chunk_items/items");
+  }
   return GS_OK;
 }
 
