@@ -384,7 +384,11 @@ gs_status gs_adam_dev(const gs_adam_group* groups, int32_t n_groups, const float
  *   their m, v and lr; rows is a multiple of 3 from 3 (D+1)^2 (D =
  *   g->sh_degree) to 48: stored rows past the active degree are updated with
  *   a zero gradient, as a dense gs_adam_dev would.  grad pointers are not
- *   used.
+ *   used.  n_groups = 6 gives the colour rows from 3 on their own learning
+ *   rate (3D-GS steps the higher spherical-harmonic bands at 1/20 of the
+ *   plain colour's): group 4 is then the first 3 rows (count 3n) and group
+ *   5 the rest of the same arrays (param, m and v at group 4's plus 3n,
+ *   count (rows - 3) x n); lr_final has n_groups entries.
  *   visible_only != 0: sparse Adam, the optimiser form that updates only the
  *   Gaussians a step draws: a Gaussian with no pair of `views` whose n_tiles
  *   is > 0 keeps its parameters, m and v unchanged (and none of them is
@@ -395,7 +399,8 @@ gs_status gs_adam_dev(const gs_adam_group* groups, int32_t n_groups, const float
 gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
                               const gs_tiling* tiling, const gs_projected* proj,
                               const float* d_rec, const gs_adam_group* groups,
-                              const float* lr_final, int32_t decay_steps, float beta1,
+                              int32_t n_groups, const float* lr_final,
+                              int32_t decay_steps, float beta1,
                               float beta2, float eps, int32_t visible_only, int32_t* step_dev,
                               void* stream);
 

@@ -101,7 +101,7 @@ SIGNATURES = {
     "gs_adam": (i32, [P(gs_adam_group), i32, f32, f32, f32, i32, i32, vp]),
     "gs_adam_dev": (i32, [P(gs_adam_group), i32, P(f32), i32, f32, f32, f32, vp, i32, vp]),
     "gs_project_bwd_adam": (i32, [P(gs_gaussians), P(gs_views), P(gs_tiling), P(gs_projected),
-                                  vp, P(gs_adam_group), P(f32), i32, f32, f32, f32, i32, vp,
+                                  vp, P(gs_adam_group), i32, P(f32), i32, f32, f32, f32, i32, vp,
                                   vp]),
     "gs_densify_stats": (i32, [P(gs_views), P(gs_tiling), P(gs_projected), vp, i64, vp, vp, vp]),
     "gs_densify_workspace_bytes": (sz, [i64]),

@@ -540,7 +540,7 @@ struct AdamFused {
   float* v[5];
   int col_rows;           // rows of the colour arrays (>= 3 (D+1)^2)
   int visible_only;       // sparse Adam: Gaussians drawn by no pair are left as they are
-  float lr[5], lr_final[5];
+  float lr[6], lr_final[6];   // [5]: colour rows from 3 on (= [4] with five groups)
   int decay_steps;
   float b1, b2, eps;
   const int32_t* step_dev;
@@ -557,8 +557,8 @@ __attribute__((amdgpu_waves_per_eu(D == 0 || (ONE && D < 3) ? 1 : 3))) void k_pr
     const int64_t* __restrict__ gauss_offset, const gs_camera* __restrict__ cams, int n_slots,
     int W, int H, int tw, int th, const int32_t* __restrict__ n_tiles,
     const float* __restrict__ d_rec) {
-  __shared__ float s_lr[5], s_ibc[2];
-  if (threadIdx.x < 5) {
+  __shared__ float s_lr[6], s_ibc[2];
+  if (threadIdx.x < 6) {
     float lr, ibc1, ibc2;
     adam_schedule(A.step_dev[0] + 1, A.b1, A.b2, A.lr[threadIdx.x], A.lr_final[threadIdx.x],
                   A.decay_steps, lr, ibc1, ibc2);
@@ -643,9 +643,10 @@ __attribute__((amdgpu_waves_per_eu(D == 0 || (ONE && D < 3) ? 1 : 3))) void k_pr
   float* cm = A.m[4] + g;
   float* cv = A.v[4] + g;
   if constexpr (D >= 1) asm volatile("" : "+v"(cp), "+v"(cm), "+v"(cv));
-  auto colour_row = [&](float grad) {
+  const float lr_dc = s_lr[4], lr_rest = s_lr[5];
+  auto colour_row = [&](float grad, float lr) {
     float pv = *cp, m = *cm, v = *cv;
-    adam_update(pv, 0.f + grad, m, v, s_lr[4], ibc1, ibc2, A.b1, A.b2, A.eps);
+    adam_update(pv, 0.f + grad, m, v, lr, ibc1, ibc2, A.b1, A.b2, A.eps);
     *cp = pv;
     *cm = m;
     *cv = v;
@@ -654,14 +655,15 @@ __attribute__((amdgpu_waves_per_eu(D == 0 || (ONE && D < 3) ? 1 : 3))) void k_pr
     cv += n;
   };
   if constexpr (ONE) {
-    colour_coef_grads<D>(one_dir, one_gc, [&](int, float x) { colour_row(x); });
+    colour_coef_grads<D>(one_dir, one_gc,
+                         [&](int r, float x) { colour_row(x, r < 3 ? lr_dc : lr_rest); });
   } else {
 #pragma unroll
-    for (int r = 0; r < NC; ++r) colour_row(gcol.at(r));
+    for (int r = 0; r < NC; ++r) colour_row(gcol.at(r), r < 3 ? lr_dc : lr_rest);
   }
   for (int r = NC; r < A.col_rows; ++r) {
     float pv = *cp, m = *cm, v = *cv;
-    adam_update(pv, 0.f, m, v, s_lr[4], ibc1, ibc2, A.b1, A.b2, A.eps);
+    adam_update(pv, 0.f, m, v, r < 3 ? lr_dc : lr_rest, ibc1, ibc2, A.b1, A.b2, A.eps);
     *cp = pv;
     *cm = m;
     *cv = v;
@@ -755,11 +757,13 @@ gs_status gs_project_bwd(const gs_gaussians* g, const gs_views* views, const gs_
 gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
                               const gs_tiling* tiling, const gs_projected* proj,
                               const float* d_rec, const gs_adam_group* groups,
-                              const float* lr_final, int32_t decay_steps, float beta1,
-                              float beta2, float eps, int32_t visible_only, int32_t* step_dev,
-                              void* stream) {
+                              int32_t n_groups, const float* lr_final, int32_t decay_steps,
+                              float beta1, float beta2, float eps, int32_t visible_only,
+                              int32_t* step_dev, void* stream) {
   clear_error();
   GS_REQUIRE(g && proj && groups && step_dev, "gs_project_bwd_adam: NULL argument");
+  GS_REQUIRE(n_groups == 5 || n_groups == 6, "gs_project_bwd_adam: n_groups=%d (5 or 6)",
+             n_groups);
   gs_status st = check_views(views, tiling, "gs_project_bwd_adam");
   if (st != GS_OK) return st;
   GS_REQUIRE(proj->m == views->total_pairs, "gs_project_bwd_adam: proj->m != total_pairs");
@@ -772,15 +776,25 @@ gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
   const int nc = 3 * (g->sh_degree + 1) * (g->sh_degree + 1);
   int col_rows = nc;
   if (g->n > 0) {
-    GS_REQUIRE(groups[4].count % g->n == 0 && groups[4].count / g->n >= nc &&
-                   (groups[4].count / g->n) % 3 == 0 &&
-                   groups[4].count / g->n <= 3 * (GS_SH_MAX_DEGREE + 1) * (GS_SH_MAX_DEGREE + 1),
-               "gs_project_bwd_adam: colour group count %lld must be 3k x n, k >= (D+1)^2 = %d, "
+    // the colour rows: group 4's, plus group 5's when given
+    int64_t col_count = groups[4].count;
+    if (n_groups == 6) {
+      const int64_t off = 3 * g->n;
+      GS_REQUIRE(groups[4].count == off && groups[5].param == groups[4].param + off &&
+                     (groups[4].m == nullptr ||
+                      (groups[5].m == groups[4].m + off && groups[5].v == groups[4].v + off)),
+                 "gs_project_bwd_adam: with 6 groups, group 4 must be colour rows 0-2 and "
+                 "group 5 the rows after them in the same arrays");
+      col_count += groups[5].count;
+    }
+    GS_REQUIRE(col_count % g->n == 0 && col_count / g->n >= nc && (col_count / g->n) % 3 == 0 &&
+                   col_count / g->n <= 3 * (GS_SH_MAX_DEGREE + 1) * (GS_SH_MAX_DEGREE + 1),
+               "gs_project_bwd_adam: colour count %lld must be 3k x n, k >= (D+1)^2 = %d, "
                "k <= %d",
-               (long long)groups[4].count, nc / 3, (GS_SH_MAX_DEGREE + 1) * (GS_SH_MAX_DEGREE + 1));
-    col_rows = (int)(groups[4].count / g->n);
+               (long long)col_count, nc / 3, (GS_SH_MAX_DEGREE + 1) * (GS_SH_MAX_DEGREE + 1));
+    col_rows = (int)(col_count / g->n);
   }
-  const int rows[5] = {3, 3, 4, 1, col_rows};
+  const int rows[5] = {3, 3, 4, 1, n_groups == 6 ? 3 : col_rows};
   AdamFused A;
   A.col_rows = col_rows;
   A.visible_only = visible_only ? 1 : 0;
@@ -798,6 +812,14 @@ gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
     A.v[i] = groups[i].v;
     A.lr[i] = groups[i].lr;
     A.lr_final[i] = lf;
+  }
+  A.lr[5] = A.lr[4];
+  A.lr_final[5] = A.lr_final[4];
+  if (n_groups == 6) {
+    const float lf = lr_final ? lr_final[5] : 0.0f;
+    GS_REQUIRE(!(lf > 0.0f) || groups[5].lr > 0.0f, "gs_project_bwd_adam: decay needs lr > 0 (group 5)");
+    A.lr[5] = groups[5].lr;
+    A.lr_final[5] = lf;
   }
   A.decay_steps = decay_steps;
   A.b1 = beta1;

@@ -303,7 +303,7 @@ class RasterBuffers:
         s = stream or stream_handle()
         call("gs_project_bwd_adam", C.byref(gstruct), C.byref(self.views.struct),
              C.byref(self.tiling), C.byref(self.proj), _ptr(self.d_rec), adam.groups,
-             adam.lr_final, adam.decay_steps, adam.betas[0], adam.betas[1], adam.betas[2],
+             len(adam.groups), adam.lr_final, adam.decay_steps, adam.betas[0], adam.betas[1], adam.betas[2],
              int(bool(visible_only)), _ptr(adam.step_dev), s)
 
     def zero_d_rec(self, stream=None):
@@ -362,10 +362,24 @@ class LossBuffers:
 
 
 def adam_groups(params, grads, m, v, lrs):
-    arr = (_lib.gs_adam_group * len(PARAM_NAMES))()
+    """gs_adam_group array over the five parameter arrays.  With an lrs
+    entry "color_rest" and more than 3 colour rows, a sixth group takes the
+    colour rows from 3 on (the higher spherical-harmonic bands) at that
+    rate and group 4 keeps rows 0-2."""
+    rest = "color_rest" in lrs and params["color"].shape[0] > 3
+    arr = (_lib.gs_adam_group * (len(PARAM_NAMES) + int(rest)))()
     for i, k in enumerate(PARAM_NAMES):
+        cnt = params[k].numel()
+        if rest and k == "color":
+            cnt = 3 * params[k].shape[-1]
         arr[i] = _lib.gs_adam_group(params[k].data_ptr(), grads[k].data_ptr(), m[k].data_ptr(),
-                                    v[k].data_ptr(), params[k].numel(), float(lrs[k]))
+                                    v[k].data_ptr(), cnt, float(lrs[k]))
+    if rest:
+        off = 3 * params["color"].shape[-1] * 4           # bytes
+        c = params["color"]
+        arr[5] = _lib.gs_adam_group(c.data_ptr() + off, grads["color"].data_ptr() + off,
+                                    m["color"].data_ptr() + off, v["color"].data_ptr() + off,
+                                    c.numel() - 3 * c.shape[-1], float(lrs["color_rest"]))
     return arr
 
 
@@ -382,7 +396,8 @@ class DeviceAdam:
                  eps=1e-15, device="cuda"):
         self.groups = groups
         n = len(groups)
-        self.lr_final = (_lib.f32 * n)(*([0.0] * n if lr_final is None else lr_final))
+        lf = [0.0] * n if lr_final is None else list(lr_final)[:n]
+        self.lr_final = (_lib.f32 * n)(*(lf + [0.0] * (n - len(lf))))
         self.decay_steps = int(decay_steps)
         self.betas = (beta1, beta2, eps)
         self.step_dev = torch.zeros(1, dtype=torch.int32, device=device)

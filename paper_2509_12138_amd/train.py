@@ -23,7 +23,9 @@ import torch
 from . import _lib
 from . import ops
 
-DEFAULT_LR = dict(mean=1.6e-4, log_scale=5e-3, quat=1e-3, opacity_logit=5e-2, color=2.5e-3)
+# color_rest: the colour rows above degree 0 (spherical-harmonic bands 1-3)
+DEFAULT_LR = dict(mean=1.6e-4, log_scale=5e-3, quat=1e-3, opacity_logit=5e-2, color=2.5e-3,
+                  color_rest=2.5e-3 / 20)
 
 
 @dataclasses.dataclass
@@ -304,7 +306,8 @@ class BatchedTrainer:
     def __init__(self, parts, cams_np, views_per_part=4, tile=(16, 16), schedule="lpt",
                  chunk=64, stored=True, lam=0.2, bg=(0.0, 0.0, 0.0), extent=2.75, lrs=None,
                  order_seed=0, graphs=True, dup_capacity=None, fwd_waves=1, deterministic=False,
-                 fused_adam=True, sparse_adam=False, device="cuda"):
+                 fused_adam=True, sparse_adam=False, sh_degree=0, sh_up_every=1000,
+                 device="cuda"):
         from .scene import concat_params
         self.device = device
         if sparse_adam and not fused_adam:
@@ -317,6 +320,17 @@ class BatchedTrainer:
                              for p in parts])
         self.params = {k: torch.as_tensor(v).to(device) for k, v in cat.items()}
         self.n = sum(self.counts)
+        # view-dependent colour as in the plain trainer (higher bands start
+        # at zero; the active degree rises every sh_up_every steps, or is
+        # sh_degree from the start when sh_up_every <= 0)
+        self.sh_degree, self.sh_up_every = int(sh_degree), int(sh_up_every)
+        rows = 3 * (self.sh_degree + 1) ** 2
+        c = self.params["color"]
+        if c.shape[0] < rows:
+            self.params["color"] = torch.cat(
+                [c, torch.zeros((rows - c.shape[0], c.shape[1]), dtype=c.dtype, device=device)]
+            ).contiguous()
+        self.active_sh = 0 if self.sh_up_every > 0 else self.sh_degree
         self.grads = {k: torch.zeros_like(v) for k, v in self.params.items()}
         self.m = {k: torch.zeros_like(v) for k, v in self.params.items()}
         self.v = {k: torch.zeros_like(v) for k, v in self.params.items()}
@@ -350,7 +364,7 @@ class BatchedTrainer:
                                deterministic=deterministic)
         self.mode = _lib.GS_BWD_STORED if stored else _lib.GS_BWD_RECOMPUTE
         self.loss = ops.LossBuffers(self.S, self.H, self.W, device)
-        self.gst = ops.gaussians_struct(self.params)
+        self.gst = ops.gaussians_struct(self.params, sh_degree=self.active_sh)
         self.grst = ops.grads_struct(self.grads, self.n)
         self.groups = ops.adam_groups(self.params, self.grads, self.m, self.v, self.lrs)
         self.adam = ops.DeviceAdam(self.groups, lr_final=[1.6e-6 * extent, 0, 0, 0, 0],
@@ -388,6 +402,12 @@ class BatchedTrainer:
 
     def step(self, g):
         """One batched step on view group g (graph replay after the first)."""
+        if (self.active_sh < self.sh_degree and self.steps_done > 0 and self.sh_up_every > 0
+                and self.steps_done % self.sh_up_every == 0):
+            # the degree is a kernel argument baked into the captured graphs
+            self.active_sh += 1
+            self.gst = ops.gaussians_struct(self.params, sh_degree=self.active_sh)
+            self.graphs = {}
         if not self.use_graphs or g not in self._warm:
             # eager (also the first time, so every kernel is loaded before capture)
             self._step_body(g)

@@ -133,3 +133,35 @@ def test_prepare_captures_without_training(parts):
         torch.cuda.synchronize()
         np.testing.assert_allclose(bt.loss.loss.cpu().numpy(), ref.loss.loss.cpu().numpy(),
                                    rtol=2e-4, atol=1e-7)
+
+
+def test_graph_replay_with_rising_colour_degree(parts):
+    """View-dependent colour in the batched trainer: the active degree rises
+    (0 -> 1 -> 2) during training, the captured graphs are re-captured with
+    the new degree, and the replayed steps match eager ones."""
+    say("graph replay, rising sh degree")
+    from paper_2509_12138_amd.train import BatchedTrainer
+    prts, cams = parts
+    runs = {}
+    for graphs in (False, True):
+        bt = BatchedTrainer(prts, cams, views_per_part=2, graphs=graphs, order_seed=3,
+                            sh_degree=2, sh_up_every=3)
+        bt.fit_capacity()
+        assert bt.params["color"].shape[0] == 27 and len(bt.groups) == 6
+        losses, degrees = [], []
+        for s in range(9):
+            bt.step(s % bt.G)
+            torch.cuda.synchronize()
+            losses.append(bt.loss.loss.cpu().numpy().copy())
+            degrees.append(bt.active_sh)
+            _ = (bt.params["mean"] * 2).sum().item()
+        bt.check()
+        col = bt.params["color"].cpu().numpy()
+        runs[graphs] = (np.array(losses), degrees, col)
+        for k, v in bt.params.items():
+            assert torch.isfinite(v).all(), k
+    assert runs[True][1] == runs[False][1] == [0, 0, 0, 1, 1, 1, 2, 2, 2]
+    np.testing.assert_allclose(runs[True][0], runs[False][0], rtol=2e-4, atol=1e-7)
+    # bands 1 and 2 moved once active
+    col = runs[True][2]
+    assert np.abs(col[3:12]).max() > 0 and np.abs(col[12:27]).max() > 0

@@ -162,17 +162,21 @@ def test_lower_active_degree_draws_the_leading_rows(ops):
         ops.gaussians_struct(dict(dp, color=dp["color"][:12].contiguous()), sh_degree=2)
 
 
-@pytest.mark.parametrize("D,active,V", [(3, 3, 3), (3, 1, 3), (1, 1, 3), (3, 3, 1), (3, 2, 1),
-                                        (1, 1, 1)])
-def test_fused_projection_backward_adam_bitwise_with_sh(ops, D, active, V):
+@pytest.mark.parametrize("D,active,V,rest", [(3, 3, 3, False), (3, 1, 3, False), (1, 1, 3, False),
+                                             (3, 3, 1, False), (3, 2, 1, False), (1, 1, 1, False),
+                                             (3, 3, 1, True), (3, 3, 3, True), (2, 1, 1, True)])
+def test_fused_projection_backward_adam_bitwise_with_sh(ops, D, active, V, rest):
     """Fused against unfused, several slots (LDS sums) and one slot (the
-    kernel that keeps only the pair's direction and colour gradient)."""
-    say("project_bwd + adam fused, sh", D, active, V)
+    kernel that keeps only the pair's direction and colour gradient); with
+    rest, six Adam groups step the higher bands at their own rate."""
+    say("project_bwd + adam fused, sh", D, active, V, rest)
     W, H, n = 200, 150, 4000
     params = sh_params(n, 95, D)
     cams = scene.orbit_cameras(V, W, H)
     lrs = {"mean": 4.4e-4, "log_scale": 5e-3, "quat": 1e-3, "opacity_logit": 5e-2,
            "color": 2.5e-3}
+    if rest:
+        lrs["color_rest"] = 2.5e-3 / 20
     runs = []
     for fused in (False, True):
         bufs = make_bufs(ops, n, cams, W, H)
@@ -203,3 +207,8 @@ def test_fused_projection_backward_adam_bitwise_with_sh(ops, D, active, V):
     moved = runs[1][0]["color"] != params["color"]
     assert moved[:3 * K].any()
     assert not moved[3 * K:].any()          # rows above the active degree stay put
+    if rest:
+        # three Adam steps move a parameter by at most about 3 lr
+        step = np.abs(runs[1][0]["color"].astype(np.float64) - params["color"])
+        assert step[3:3 * K].max() <= 3.05 * lrs["color_rest"]
+        assert step[:3].max() > 3.05 * lrs["color_rest"]
