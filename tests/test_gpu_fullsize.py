@@ -219,3 +219,92 @@ def test_fullsize_raster_matches_oracle_windows(big, tile, sched, chunk, fwd_wav
         for c in range(9):
             nr = np.linalg.norm(drec[sl][:, c] - grad[:, c]) / max(np.linalg.norm(grad[:, c]), 1e-30)
             assert nr <= 1e-3, (c, nr)
+
+
+def test_fullsize_sh3_colour_and_gradients_on_sampled_gaussians(big):
+    """Degree-3 view-dependent colour at full size: the projection's colours
+    and the projection backward's gradients of 20,000 sampled Gaussians
+    (the oracle computes each Gaussian on its own) for two views, and the
+    fused backward + Adam of one view (the bench's one-slot kernel, six Adam
+    groups) bit for bit against the two separate calls."""
+    from paper_2509_12138_amd import ops
+    from paper_2509_12138_amd.train import DEFAULT_LR
+    params, cams = big
+    n = params["opacity_logit"].shape[0]
+    say(f"full-size sh3 n={n}")
+    rng = np.random.default_rng(31)
+    p3 = dict(params)
+    col = np.zeros((48, n), np.float32)
+    col[:3] = params["color"]
+    col[3:] = 0.2 * rng.normal(size=(45, n))
+    p3["color"] = col
+    dp = to_dev(p3, torch)
+    views = ops.Views.single(n, cams)
+    bufs = ops.RasterBuffers(views, W, H, (16, 16), dup_capacity=1024)
+    gst = ops.gaussians_struct(dp)
+    assert gst.sh_degree == 3
+    bufs.project(gst)
+    torch.cuda.synchronize()
+    rec = bufs.rec.cpu().numpy()
+    sample = np.sort(rng.choice(n, 20000, replace=False))
+    sub = {k: (v[..., sample] if v.ndim == 2 else v[sample]) for k, v in p3.items()}
+    drec = np.zeros((len(cams) * n, 9), np.float32)
+    for v in range(len(cams)):
+        o = oracle.project(sub, scene.camera_dict(cams[v]))
+        r = rec[v * n:(v + 1) * n][sample]
+        kappa = 2 * np.log(np.maximum(255 * o["opacity"], 1e-300))
+        hx = np.sqrt(np.maximum(kappa, 0) * o["cov2d"][0])
+        hy = np.sqrt(np.maximum(kappa, 0) * o["cov2d"][2])
+        edges = np.stack([o["mean2d"][0] - hx, o["mean2d"][0] + hx,
+                          o["mean2d"][1] - hy, o["mean2d"][1] + hy])
+        near = np.any(np.abs(edges - np.round(edges)) < 2e-4, axis=0) | \
+            (np.abs(255 * o["opacity"] - 1) < 1e-4)
+        ok = (o["n_tiles"] > 0) & ~near
+        assert ok.sum() > 5000
+        np.testing.assert_allclose(r[ok, 6:9], o["rgb"].T[ok], rtol=1e-5, atol=2e-6)
+        d = rng.normal(size=(len(sample), 9)) * ok[:, None]
+        d[:, 6:9] *= (o["rgb"].T > 1e-4)
+        drec[v * n + sample] = d
+    bufs.d_rec.copy_(torch.as_tensor(drec))
+    grads = {k: torch.zeros_like(v) for k, v in dp.items()}
+    bufs.project_bwd(gst, ops.grads_struct(grads, n))
+    torch.cuda.synchronize()
+    ref = {k: np.zeros(np.shape(v)) for k, v in sub.items()}
+    for v in range(len(cams)):
+        d = drec[v * n + sample].astype(np.float64)
+        g = oracle.project_bwd(sub, scene.camera_dict(cams[v]),
+                               dict(d_mean2d=d[:, 0:2].T, d_conic=d[:, 2:5].T, d_opacity=d[:, 5],
+                                    d_rgb=d[:, 6:9].T))
+        for k in ref:
+            ref[k] += g[k]
+    for k in ref:
+        got = grads[k].cpu().numpy()
+        got = (got[..., sample] if got.ndim == 2 else got[sample]).astype(np.float64)
+        r = ref[k]
+        nr = np.linalg.norm(got - r) / max(np.linalg.norm(r), 1e-30)
+        assert nr <= 1e-4, (k, nr)
+        assert np.all(np.abs(got - r) <= 1e-3 * np.abs(r) + 1e-5 * np.abs(r).max()), k
+    # fused one-view step against the separate calls, all 1M Gaussians
+    one = ops.Views.single(n, cams[:1])
+    b1 = ops.RasterBuffers(one, W, H, (16, 16), dup_capacity=1024)
+    runs = []
+    for fused in (False, True):
+        q = to_dev(p3, torch)
+        gq = ops.gaussians_struct(q)
+        m = {k: torch.zeros_like(v) for k, v in q.items()}
+        vv = {k: torch.zeros_like(v) for k, v in q.items()}
+        gr = {k: torch.zeros_like(v) for k, v in q.items()}
+        adam = ops.DeviceAdam(ops.adam_groups(q, gr, m, vv, DEFAULT_LR))
+        assert len(adam.groups) == 6
+        b1.project(gq)
+        b1.d_rec.copy_(torch.as_tensor(drec[:n]))
+        if fused:
+            b1.project_bwd_adam(gq, adam)
+        else:
+            b1.project_bwd(gq, ops.grads_struct(gr, n))
+            adam(zero_grad=True)
+        torch.cuda.synchronize()
+        runs.append({k: (q[k].cpu().numpy(), m[k].cpu().numpy()) for k in q})
+    for k in runs[0]:
+        np.testing.assert_array_equal(runs[0][k][0], runs[1][k][0], err_msg=k)
+        np.testing.assert_array_equal(runs[0][k][1], runs[1][k][1], err_msg=k)
