@@ -106,6 +106,7 @@ __global__ __launch_bounds__(kLThreads) void k_ssim(
   // if it lies outside, so all loads of a thread are in flight together.
   constexpr int kStage = kLS * kLS;
   constexpr int kStageQ = (kStage + kLThreads - 1) / kLThreads;
+  bool fg = false;      // a foreground pixel among the inputs of the tile's SSIM terms
   {
     float iv[kStageQ], gv[kStageQ];
     uint8_t mv[kStageQ];
@@ -129,9 +130,35 @@ __global__ __launch_bounds__(kLThreads) void k_ssim(
       const float mk = (ok[q] && mv[q] != 0) ? 1.0f : 0.0f;
       s_x[r * kLSs + c] = mk * iv[q];
       s_y[r * kLSs + c] = mk * gv[q];
+      fg = fg || (mk != 0.0f && r >= kLR && r < kLS - kLR && c >= kLR && c < kLS - kLR);
     }
   }
-  __syncthreads();
+  if (!__syncthreads_or(fg)) {
+    // background tile: the mask is zero over the 42x42 inputs of the tile's
+    // SSIM terms, so both masked images are zero there: each term is 1 (the
+    // blurs of zeros are zero), the L1 terms are 0 and so is the gradient
+    // (the mask is zero at the tile's own pixels).  Write that directly.
+    float* D = d_image + ic * HW;
+    float cnt = 0.f;
+    for (int i = t; i < kLT * kLT; i += kLThreads) {
+      const int y = oy + i / kLT, x = ox + i % kLT;
+      if (x < W && y < H) {
+        D[(int64_t)y * W + x] = 0.0f;
+        cnt += 1.0f;
+      }
+    }
+    cnt = wave_sum(cnt);
+    if ((t & 63) == 0) s_red[0][t >> 6] = cnt;
+    __syncthreads();
+    if (t == 0) {
+      float a0 = 0.f;
+#pragma unroll
+      for (int w = 0; w < kLThreads / 64; ++w) a0 += s_red[0][w];
+      part[2 * blockIdx.x] = a0;
+      part[2 * blockIdx.x + 1] = 0.0f;
+    }
+    return;
+  }
 
   // moments, horizontal: staged row r, positions c0 .. c0 + kH1 - 1
   constexpr int kItems1 = kLS * (kLM / kH1);

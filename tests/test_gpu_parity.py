@@ -378,6 +378,34 @@ def test_loss_matches_oracle(ops, S, H, W, lam):
     assert int(status[0]) == 0
 
 
+@pytest.mark.parametrize("S,H,W", [(2, 150, 230), (1, 97, 64)])
+def test_loss_with_background_tiles_matches_oracle(ops, S, H, W):
+    """A mask with wide empty areas (a disc of foreground, an empty image),
+    so that whole 32x32 tiles are background with and without a margin of
+    foreground pixels within the SSIM window."""
+    say("loss, background tiles", S, H, W)
+    rng = np.random.default_rng(19)
+    img = rng.uniform(0, 1, (S, 3, H, W)).astype(np.float32)
+    tgt = np.clip(img + rng.normal(0, 0.2, img.shape), 0, 1).astype(np.float32)
+    yy, xx = np.mgrid[0:H, 0:W]
+    mask = np.zeros((S, H, W), np.uint8)
+    mask[0] = ((yy - 0.45 * H) ** 2 + (xx - 0.4 * W) ** 2 < (0.3 * min(H, W)) ** 2)
+    mask[0, :, -3:] = 1                     # a foreground strip at the ragged right edge
+    L = ops.LossBuffers(S, H, W)
+    status = torch.zeros(4, dtype=torch.int64, device="cuda")
+    loss, dI = L(torch.as_tensor(img).cuda(), torch.as_tensor(tgt).cuda(),
+                 torch.as_tensor(mask).cuda(), lam=0.2, grad_scale=1.0, status=status)
+    torch.cuda.synchronize()
+    loss = loss.cpu().numpy(); dI = dI.cpu().numpy()
+    for s in range(S):
+        o = oracle.loss(img[s], tgt[s], mask[s], lam=0.2)
+        assert abs(loss[s] - o["loss"]) <= 1e-5 * max(abs(o["loss"]), 1e-6), (s, loss[s], o["loss"])
+        r = o["d_image"]
+        assert np.abs(dI[s] - r).max() <= 1e-5 * max(np.abs(r).max(), 1e-6) + 1e-12
+        assert np.all(dI[s][:, mask[s] == 0] == 0)
+    assert int(status[0]) == 0
+
+
 def test_adam_matches_oracle(ops):
     say("adam")
     rng = np.random.default_rng(10)
