@@ -653,6 +653,9 @@ __device__ __forceinline__ void bwd_tile(const RasterDev& a, int64_t tile, Splat
     dI[k][1] = L.inside[k] ? dimg[HW + o] : 0.0f;
     dI[k][2] = L.inside[k] ? dimg[2 * HW + o] : 0.0f;
     dIacc[k] = T[k] * (dI[k][0] * a.bg0 + dI[k][1] * a.bg1 + dI[k][2] * a.bg2);
+    // a pixel with a zero image gradient (a masked one) adds exactly zero
+    // to every gradient: it takes no part in the reverse pass
+    if (dI[k][0] == 0.0f && dI[k][1] == 0.0f && dI[k][2] == 0.0f) last[k] = 0;
   }
   int lmax = 0;
 #pragma unroll
@@ -699,10 +702,19 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd_chunked(
   const LanePixels<TW, TH> L(a, tile);
   const int64_t HW = (int64_t)a.H * a.W;
   int last[PX];
+  float T[PX], dI[PX][3], dIacc[PX];
+  const float* dimg = d_image + (int64_t)L.slot * 3 * HW;
   int lmax = 0;
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
-    last[k] = L.inside[k] ? n_contrib[(int64_t)L.slot * HW + L.offset(a, k)] : 0;
+    const int64_t o = L.offset(a, k);
+    last[k] = L.inside[k] ? n_contrib[(int64_t)L.slot * HW + o] : 0;
+    dI[k][0] = L.inside[k] ? dimg[o] : 0.0f;
+    dI[k][1] = L.inside[k] ? dimg[HW + o] : 0.0f;
+    dI[k][2] = L.inside[k] ? dimg[2 * HW + o] : 0.0f;
+    // a pixel with a zero image gradient (a masked one) adds exactly zero
+    // to every gradient: it takes no part in the reverse pass
+    if (dI[k][0] == 0.0f && dI[k][1] == 0.0f && dI[k][2] == 0.0f) last[k] = 0;
     lmax = max(lmax, last[k]);
   }
   const int hi = min(wave_max_int(lmax), hi_pos);
@@ -711,14 +723,9 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd_chunked(
     return;
   }
   const float4* ck = ch.ck + ((int64_t)ch.offset[tile] + c) * (TW * TH);
-  float T[PX], dI[PX][3], dIacc[PX];
-  const float* dimg = d_image + (int64_t)L.slot * 3 * HW;
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     const int64_t o = L.offset(a, k);
-    dI[k][0] = L.inside[k] ? dimg[o] : 0.0f;
-    dI[k][1] = L.inside[k] ? dimg[HW + o] : 0.0f;
-    dI[k][2] = L.inside[k] ? dimg[2 * HW + o] : 0.0f;
     if (!L.inside[k] || last[k] <= hi_pos) {
       // nothing blended after this chunk: final state, I - C_final = bg T_final
       T[k] = L.inside[k] ? T_final[(int64_t)L.slot * HW + o] : 1.0f;

@@ -28,6 +28,15 @@ def ops(gpu):
     return _ops
 
 
+def masked_image_gradient(rng, H, W, S=2):
+    """Seeded image gradient that is exactly zero where a loss mask would
+    cut it: on 30% of the pixels and on a solid block (whole tiles)."""
+    dI = rng.normal(size=(S, 3, H, W)).astype(np.float32)
+    zero = rng.uniform(size=(S, 1, H, W)) < 0.3
+    zero[:, :, H // 8:H // 2, W // 6:W // 2] = True
+    return np.where(zero, np.float32(0), dI)
+
+
 def make_bufs(ops, params, cams, W, H, tile=(16, 16), cap=None, store=True):
     n = params["opacity_logit"].shape[0]
     views = ops.Views.single(n, cams)
@@ -248,7 +257,7 @@ def test_raster_bwd_matches_oracle(ops, mode, tile, det):
         bufs.set_schedule("default", deterministic=True)
     raster_records(bufs, rec, tb, nt, bg, torch)
     rng = np.random.default_rng(7)
-    dI = rng.normal(size=(2, 3, H, W)).astype(np.float32)
+    dI = masked_image_gradient(rng, H, W)
     bufs.zero_d_rec()
     bufs.raster_bwd(torch.as_tensor(dI).cuda(), bg=bg, mode=mode)
     torch.cuda.synchronize()
@@ -472,7 +481,7 @@ def test_chunked_backward_matches_oracle(ops, chunk, sched, det):
     bg = (0.05, 0.1, 0.2)
     rec, tb, nt, views = oracle_records(params, cams, W, H, (16, 16))
     rng = np.random.default_rng(3)
-    dI = rng.normal(size=(2, 3, H, W)).astype(np.float32)
+    dI = masked_image_gradient(rng, H, W)
     res = {}
     for c in (0, chunk):
         bufs = make_bufs(ops, params, cams, W, H, (16, 16))
