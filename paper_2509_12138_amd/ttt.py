@@ -56,10 +56,17 @@ def slab_part(x0, x1, n, seed, ref_factor=2.0, grid=GRID, ghost_voxels=GHOST_VOX
     ref_factor-denser reference."""
     ghost = ghost_voxels * 2.0 / grid
     box = ((x0 - ghost, -1.0, -1.0), (x1 + ghost, 1.0, 1.0))
-    pts, nrm = scene.sample_surface(scene.field_sphere_sines, int(n), grid, seed=seed, box=box)
+    pts, nrm = _z_order(*scene.sample_surface(scene.field_sphere_sines, int(n), grid, seed=seed,
+                                              box=box))
     rp, rn = scene.sample_surface(scene.field_sphere_sines, int(n * ref_factor), grid,
                                   seed=seed + 50, box=box)
     return dict(points=pts, normals=nrm, ref_points=rp, ref_normals=rn, x_range=(x0, x1))
+
+
+def _z_order(pts, nrm):
+    """The sampled points (the future Gaussians) in Z-order of position."""
+    perm = scene.morton_order(pts)
+    return pts[perm], nrm[perm]
 
 
 def slab_partitions(counts=SLAB_COUNTS, seed=4, ref_factor=2.0, grid=GRID,
@@ -294,7 +301,8 @@ def octant_partition(n, seed, ref_factor=2.0, grid=GRID):
     margin across its three internal faces (one of eight partitions)."""
     ghost = GHOST_VOXELS * 2.0 / grid
     box = ((-ghost, -ghost, -ghost), (1.0, 1.0, 1.0))
-    pts, nrm = scene.sample_surface(scene.field_sphere_sines, int(n), grid, seed=seed, box=box)
+    pts, nrm = _z_order(*scene.sample_surface(scene.field_sphere_sines, int(n), grid, seed=seed,
+                                              box=box))
     rp, rn = scene.sample_surface(scene.field_sphere_sines, int(n * ref_factor), grid,
                                   seed=seed + 100, box=box)
     return dict(points=pts, normals=nrm, ref_points=rp, ref_normals=rn)
@@ -365,12 +373,17 @@ def cmd_learned(a):
     out = dict(experiment="learned_vs_plain", n=tgt["n"], target=a.target,
                mlp_train_seconds=mlp_seconds, mlp_history=hist, mlp_heldout_loss=held,
                plain_heldout_loss=held_plain)
+    # both initialisations once, untimed, so neither arm's clock includes a
+    # kernel's first load or the first allocation of its buffers
+    _, pts_w, nrm_w = plain_params(tgt)
+    learned_init.choose_init(mlp, pts_w, nrm_w)
+    torch.cuda.synchronize()
+    del pts_w, nrm_w
     for arm in ("plain", "learned"):
         init = arm if use_mlp else "plain"
         r = run_plain(tgt, cams, a.target, a.steps, a.eval_every, init=init, mlp=mlp, plan=a.plan,
                       seed=99)
         del r["trainer"]
-        torch.cuda.empty_cache()
         log(f"{arm}: {r['seconds']} s, {r['steps']} steps, psnr {r['psnr']}, init {r['init_kind']}")
         out[arm] = r
     print(json.dumps(out), flush=True)
