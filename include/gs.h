@@ -405,6 +405,31 @@ gs_status gs_project_bwd_adam(const gs_gaussians* g, const gs_views* views,
                               void* stream);
 
 /* ------------------------------------------------------------------------
+ * Microbenchmarks of the units the rooflines price (measurement helpers, not
+ * part of the training step).  The caller times each launch with events on
+ * `stream`; all buffers are device memory it owns.
+ *   gs_peak_copy:   dst = src, `bytes` (multiple of 16, 16-byte aligned): HBM
+ *                   bandwidth = 2 bytes / time.
+ *   gs_peak_fma:    blocks x 256 lanes x iters x 16 FP32 fused multiply-adds
+ *                   (no packed FP32 instructions); out [blocks * 256].
+ *   gs_peak_exp:    the same count of hardware base-2 exponentials.
+ *   gs_peak_lds:    blocks x 256 lanes x iters x 4 LDS reads of 16 bytes.
+ *   gs_peak_atomic: blocks x 256 lanes x iters FP32 atomic adds of 1 to
+ *                   hashed addresses of dst [n_addr >= 64]: one hash per
+ *                   lane, or (contiguous != 0) one per wave with its lanes
+ *                   on 64 consecutive floats.
+ *   gs_peak_mfma:   blocks x 4 waves x iters x 8 BF16 16x16x32 matrix
+ *                   multiply-accumulates (16384 flops each); out [blocks*256].
+ * Errors: GS_ERR_ARG on NULL buffers or non-positive counts.               */
+gs_status gs_peak_copy(const void* src, void* dst, int64_t bytes, void* stream);
+gs_status gs_peak_fma(float* out, int32_t blocks, int32_t iters, void* stream);
+gs_status gs_peak_exp(float* out, int32_t blocks, int32_t iters, void* stream);
+gs_status gs_peak_lds(float* out, int32_t blocks, int32_t iters, void* stream);
+gs_status gs_peak_atomic(float* dst, int64_t n_addr, int32_t blocks, int32_t iters,
+                         int32_t contiguous, void* stream);
+gs_status gs_peak_mfma(float* out, int32_t blocks, int32_t iters, void* stream);
+
+/* ------------------------------------------------------------------------
  * Adaptive density control of the 3D-GS method each partition is trained
  * with (Sec. II "Parallel Training"; the paper keeps its defaults): every
  * few hundred steps, Gaussians whose mean screen-space position gradient is

@@ -103,6 +103,12 @@ SIGNATURES = {
     "gs_project_bwd_adam": (i32, [P(gs_gaussians), P(gs_views), P(gs_tiling), P(gs_projected),
                                   vp, P(gs_adam_group), i32, P(f32), i32, f32, f32, f32, i32, vp,
                                   vp]),
+    "gs_peak_copy": (i32, [vp, vp, i64, vp]),
+    "gs_peak_fma": (i32, [vp, i32, i32, vp]),
+    "gs_peak_exp": (i32, [vp, i32, i32, vp]),
+    "gs_peak_lds": (i32, [vp, i32, i32, vp]),
+    "gs_peak_atomic": (i32, [vp, i64, i32, i32, i32, vp]),
+    "gs_peak_mfma": (i32, [vp, i32, i32, vp]),
     "gs_densify_stats": (i32, [P(gs_views), P(gs_tiling), P(gs_projected), vp, i64, vp, vp, vp]),
     "gs_densify_workspace_bytes": (sz, [i64]),
     "gs_densify_select": (i32, [P(gs_gaussian_state), vp, vp, f32, f32, f32, f32, f32, vp, sz,

@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgsmi.so")
 
 SOURCES = ["capi.hip", "project.hip", "binsort.hip", "raster.hip", "loss.hip", "adam.hip",
-           "knn.hip", "mlp.hip", "density.hip"]
+           "knn.hip", "mlp.hip", "density.hip", "peaks.hip"]
 
 ARCH = os.environ.get("GSMI_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
