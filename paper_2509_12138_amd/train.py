@@ -307,7 +307,7 @@ class BatchedTrainer:
                  chunk=64, stored=True, lam=0.2, bg=(0.0, 0.0, 0.0), extent=2.75, lrs=None,
                  order_seed=0, graphs=True, dup_capacity=None, fwd_waves=1, deterministic=False,
                  fused_adam=True, sparse_adam=False, sh_degree=0, sh_up_every=1000,
-                 device="cuda"):
+                 density=None, device="cuda"):
         from .scene import concat_params
         self.device = device
         if sparse_adam and not fused_adam:
@@ -331,9 +331,6 @@ class BatchedTrainer:
                 [c, torch.zeros((rows - c.shape[0], c.shape[1]), dtype=c.dtype, device=device)]
             ).contiguous()
         self.active_sh = 0 if self.sh_up_every > 0 else self.sh_degree
-        self.grads = {k: torch.zeros_like(v) for k, v in self.params.items()}
-        self.m = {k: torch.zeros_like(v) for k, v in self.params.items()}
-        self.v = {k: torch.zeros_like(v) for k, v in self.params.items()}
         self.V = len(cams_np)
         assert self.V % views_per_part == 0, "the orbit must split into whole view groups"
         self.G = self.V // views_per_part
@@ -357,23 +354,83 @@ class BatchedTrainer:
         self.bg, self.lam, self.extent = tuple(bg), lam, extent
         self.lrs = dict(DEFAULT_LR if lrs is None else lrs)
         self.lrs["mean"] = self.lrs["mean"] * extent
-        self.views = ops.Views.batch(self.counts, views_per_part, self.cams_g[0], device)
-        self.bufs = ops.RasterBuffers(self.views, self.W, self.H, tile, dup_capacity=dup_capacity,
-                                      store_state=stored)
-        self.bufs.set_schedule(schedule, chunk=chunk, fwd_waves=fwd_waves,
-                               deterministic=deterministic)
+        self.device = device
+        self.plan = dict(tile=tuple(tile), stored=stored, schedule=schedule, chunk=chunk,
+                         fwd_waves=fwd_waves, deterministic=deterministic)
         self.mode = _lib.GS_BWD_STORED if stored else _lib.GS_BWD_RECOMPUTE
         self.loss = ops.LossBuffers(self.S, self.H, self.W, device)
-        self.gst = ops.gaussians_struct(self.params, sh_degree=self.active_sh)
-        self.grst = ops.grads_struct(self.grads, self.n)
-        self.groups = ops.adam_groups(self.params, self.grads, self.m, self.v, self.lrs)
-        self.adam = ops.DeviceAdam(self.groups, lr_final=[1.6e-6 * extent, 0, 0, 0, 0],
-                                   decay_steps=30000, device=device)
+        # adaptive density control over all partitions at once (the outputs
+        # keep input order, so every partition stays one contiguous range)
+        self.density = density
+        self.densifier = None
+        if density is not None:
+            self.gen = torch.Generator(device=device).manual_seed(int(density.seed))
+        self.adam = None
+        self._bind(self.params, {k: torch.zeros_like(v) for k, v in self.params.items()},
+                   {k: torch.zeros_like(v) for k, v in self.params.items()}, dup_capacity)
         self.fused_adam = fused_adam
         self.use_graphs = graphs
         self.graphs = {}
         self._warm = set()
         self.steps_done = 0
+        self._graph_stats = self._stats_on()    # whether the step body gathers statistics
+
+    def _bind(self, params, m, v, dup_capacity=None):
+        """Point every buffer, call structure and the optimiser at a (new) set
+        of Gaussians in self.counts partitions; the device step count carries
+        over and captured graphs are dropped (they hold the old pointers)."""
+        self.params, self.m, self.v = params, m, v
+        self.n = sum(self.counts)
+        self.grads = {k: torch.zeros_like(t) for k, t in self.params.items()}
+        pl = self.plan
+        self.views = ops.Views.batch(self.counts, self.vpp, self.cams_g[0], self.device)
+        self.bufs = ops.RasterBuffers(self.views, self.W, self.H, pl["tile"],
+                                      dup_capacity=dup_capacity, store_state=pl["stored"])
+        self.bufs.set_schedule(pl["schedule"], chunk=pl["chunk"], fwd_waves=pl["fwd_waves"],
+                               deterministic=pl["deterministic"])
+        self.gst = ops.gaussians_struct(self.params, sh_degree=self.active_sh)
+        self.grst = ops.grads_struct(self.grads, self.n)
+        self.groups = ops.adam_groups(self.params, self.grads, self.m, self.v, self.lrs)
+        step_dev = self.adam.step_dev if self.adam is not None else None
+        self.adam = ops.DeviceAdam(self.groups, lr_final=[1.6e-6 * self.extent, 0, 0, 0, 0],
+                                   decay_steps=30000, device=self.device)
+        if step_dev is not None:
+            self.adam.step_dev = step_dev
+        if self.density is not None:
+            if self.densifier is None:
+                self.densifier = ops.Densifier(self.n, self.device)
+            else:
+                self.densifier.resize(self.n)
+        self.graphs = {}
+
+    def _stats_on(self):
+        c = self.density
+        return c is not None and self.steps_done < c.until
+
+    def densify(self):
+        """Clone / split / prune every partition from the statistics gathered
+        since the last call; the partitions' new counts come from the
+        actions (one host synchronisation).  Returns the new total."""
+        c = self.density
+        big = (math.log(c.max_world_scale * self.extent) if self.steps_done > c.reset_interval
+               else float("inf"))
+        log_split = math.log(c.split_divisor)
+        n_out = self.densifier.select(self.params, self.m, self.v, c.grad_threshold,
+                                      math.log(c.percent_dense * self.extent),
+                                      math.log(c.min_opacity / (1.0 - c.min_opacity)), big,
+                                      log_split)
+        act = self.densifier.action[:self.n].cpu().numpy()
+        outs = np.select([act == 1, act == 2, act == 3], [1, 2, 2], 0)
+        bounds = np.cumsum([0] + list(self.counts))
+        counts = [int(outs[bounds[p]:bounds[p + 1]].sum()) for p in range(self.P)]
+        assert sum(counts) == n_out
+        z = torch.randn((self.n, 2, 3), generator=self.gen, device=self.device)
+        P, M, V = self.densifier.apply(self.params, self.m, self.v, n_out, z, log_split)
+        per_gauss = self.bufs.dup_capacity / max(self.n, 1)
+        self.counts = counts
+        self._bind(P, M, V, dup_capacity=int(per_gauss * max(n_out, 1) * 1.2) + 4096)
+        self.densifier.reset_stats()
+        return n_out
 
     def fit_capacity(self, margin=1.3):
         need = 0
@@ -394,6 +451,8 @@ class BatchedTrainer:
         self.loss(b.image, self.targets_g[g], self.masks_g[g], self.lam, 1.0 / self.vpp, b.status)
         b.zero_d_rec()
         b.raster_bwd(self.loss.d_image, self.bg, self.mode)
+        if self._graph_stats:
+            self.densifier.stats(b)
         if self.fused_adam:
             b.project_bwd_adam(self.gst, self.adam, visible_only=self.sparse_adam)
         else:
@@ -407,6 +466,10 @@ class BatchedTrainer:
             # the degree is a kernel argument baked into the captured graphs
             self.active_sh += 1
             self.gst = ops.gaussians_struct(self.params, sh_degree=self.active_sh)
+            self.graphs = {}
+        if self._stats_on() != self._graph_stats:
+            # the density statistics leave (or join) the captured step
+            self._graph_stats = self._stats_on()
             self.graphs = {}
         if not self.use_graphs or g not in self._warm:
             # eager (also the first time, so every kernel is loaded before capture)
@@ -423,6 +486,13 @@ class BatchedTrainer:
                 self.graphs[g] = graph
             graph.replay()
         self.steps_done += 1
+        c = self.density
+        if c is not None and self.steps_done < c.until:
+            t = self.steps_done
+            if t > c.start and t % c.interval == 0:
+                self.densify()
+            if t % c.reset_interval == 0:
+                ops.Densifier.opacity_reset(self.params, self.m, self.v, math.log(0.01 / 0.99))
 
     def check(self):
         st, req = self.bufs.check()

@@ -165,3 +165,38 @@ def test_graph_replay_with_rising_colour_degree(parts):
     # bands 1 and 2 moved once active
     col = runs[True][2]
     assert np.abs(col[3:12]).max() > 0 and np.abs(col[12:27]).max() > 0
+
+
+def test_batched_density_control_keeps_partitions_apart(parts):
+    """Density control in the graph-captured batched trainer: the
+    densifications change every partition's count, the graphs are
+    re-captured on the new arrays, and afterwards each partition's slots of
+    a batched render still equal that partition rendered alone (so the
+    per-partition ranges followed the new Gaussians)."""
+    say("batched density control")
+    from paper_2509_12138_amd import ops
+    from paper_2509_12138_amd.train import BatchedTrainer, DensityControl
+    prts, cams = parts
+    dc = DensityControl(start=2, until=12, interval=3, grad_threshold=1e-5, reset_interval=1000,
+                        seed=2)
+    bt = BatchedTrainer(prts, cams, views_per_part=2, graphs=True, order_seed=4, density=dc)
+    bt.fit_capacity()
+    counts0 = list(bt.counts)
+    for s in range(14):
+        bt.step(s % bt.G)
+        _ = (bt.params["mean"] * 2).sum().item()
+    bt.check()
+    assert bt.counts != counts0 and sum(bt.counts) == bt.n
+    for k, v in bt.params.items():
+        assert torch.isfinite(v).all() and v.shape[-1] == bt.n, k
+    assert bt.views.struct.total_pairs == bt.n * bt.vpp
+    bt.views.use_cameras(bt.cams_g[1])
+    bt.bufs.render_checked(bt.gst)
+    torch.cuda.synchronize()
+    got = bt.bufs.image.cpu().numpy()
+    for p in range(3):
+        prm = bt.partition_params(p)
+        single = ops.RasterBuffers(ops.Views.single(bt.counts[p], cams[bt.group_views[1]]), W, H)
+        single.render_checked(ops.gaussians_struct({k: v.contiguous() for k, v in prm.items()}))
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got[2 * p:2 * p + 2], single.image.cpu().numpy())
