@@ -517,6 +517,8 @@ class BatchedTrainer:
                 t.copy_(saved[i])
                 i += 1
         self.adam.step_dev.copy_(step0)
+        if self.densifier is not None:
+            self.densifier.reset_stats()      # the undone step's statistics too
         for g in range(self.G):
             if g not in self.graphs:
                 torch.cuda.synchronize()
