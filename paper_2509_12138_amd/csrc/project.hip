@@ -4,7 +4,9 @@
 // Forward: one thread per (Gaussian, slot) pair; planar SoA parameter loads
 // are coalesced, the 48-byte record goes out as three 16-byte stores.
 // Backward: one thread per Gaussian that loops over the slots drawing it, so
-// gradients summed over views need no atomics and are deterministic.
+// gradients summed over views need no atomics and are deterministic.  The
+// view-dependent colour (spherical harmonics up to degree 3) is a template
+// parameter of every kernel.
 #include <type_traits>
 
 #include "gs_device.h"
@@ -530,10 +532,11 @@ k_project_bwd(
 }
 
 // gs_project_bwd and one Adam step in a single pass: a thread owns a
-// Gaussian, sums its gradient over its pairs in registers (the same
-// arithmetic as k_project_bwd) and applies the update to its 14 parameters,
-// reading and writing m and v once.  Gaussians drawn by no pair get a zero
-// gradient (dense Adam).
+// Gaussian, sums its gradient over its pairs (the same arithmetic as
+// k_project_bwd) and applies the update to its parameters (11 plus the
+// colour rows), reading and writing m and v once.  Gaussians drawn by no
+// pair get a zero gradient (dense Adam) or, with visible_only, are left as
+// they are (sparse Adam).
 struct AdamFused {
   float* p[5];            // mean, log_scale, quat, opacity_logit, colour (planar)
   float* m[5];
