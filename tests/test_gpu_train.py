@@ -150,3 +150,29 @@ def test_view_dependent_targets_need_spherical_harmonics(gpu):
             assert torch.isfinite(v).all(), (D, k)
     say(f"psnr degree 0 {psnr[0]:.2f}, degree 1 {psnr[1]:.2f}")
     assert psnr[1] > psnr[0] + 1.0
+
+
+def test_all_training_options_together(tiny):
+    """Degree-3 colour raised on a schedule, density control and sparse Adam
+    in one run of the plain trainer: the colour rows follow every
+    densification, the active degree reaches 3, parameters stay finite and
+    the fit improves."""
+    say("sh + density + sparse adam")
+    from paper_2509_12138_amd.train import DensityControl, PlainTrainer
+    wl, targets, masks = tiny
+    dc = DensityControl(start=10, until=90, interval=15, grad_threshold=1e-4,
+                        reset_interval=1000, seed=6)
+    tr = PlainTrainer(wl["params"], wl["cams"], targets, masks, density=dc, sh_degree=3,
+                      sh_up_every=25, sparse_adam=True)
+    tr.fit_capacity()
+    p0 = tr.evaluate()
+    n0 = tr.n
+    tr.train(100, order_seed=1003, check_every=10, grow=True)
+    p1 = tr.evaluate()
+    say(f"psnr {p0:.2f} -> {p1:.2f}, n {n0} -> {tr.n}, degree {tr.active_sh}")
+    assert tr.active_sh == 3 and tr.n != n0
+    assert tr.params["color"].shape == (48, tr.n) and tr.m["color"].shape == (48, tr.n)
+    assert len(tr.dev_adam.groups) == 6
+    for k, v in tr.params.items():
+        assert torch.isfinite(v).all(), k
+    assert p1 > p0 + 2.0
