@@ -13,6 +13,12 @@ image over the summed durations of the two rasteriser launches, HIP events
 on the launch stream); ms_per_step / iters_per_s cover the whole step.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+--workload highres times the high-resolution partition instead: the octant
+(with 2-voxel ghost cells) of the bumpy-sphere isosurface on a 2048^3 grid,
+13.3M Gaussians, 64 orbital views at 3840x2160; run it with and without
+--recompute to compare the stored and recomputed backward (the line reports
+the step's peak device memory and the bytes of stored raster state).
 """
 from __future__ import annotations
 
@@ -60,6 +66,9 @@ def parse():
                     help="reuse the plan the autotuner cached for this workload (no re-tuning)")
     ap.add_argument("--recompute", action="store_true")
     ap.add_argument("--small", action="store_true", help="tiny config (smoke use)")
+    ap.add_argument("--workload", choices=["realistic", "highres"], default="realistic",
+                    help="realistic: 1M-Gaussian mixing layer at 1920x1080 (the headline); "
+                         "highres: 13.3M-Gaussian octant at 3840x2160")
     ap.add_argument("--sh-degree", type=int, default=0,
                     help="view-dependent colour of this degree, active from the first step "
                          "(the headline workload is degree 0)")
@@ -123,7 +132,7 @@ def cpu_baseline(params, cam, target_seconds):
         "cores": oracle.max_threads(),
         "kind": "oracle",
         "sample": f"raster fwd+bwd of a {side}x{side} pixel window at the centre of view 0 "
-                  f"(1920x1080, all {params['opacity_logit'].shape[0]} Gaussians; "
+                  f"({W}x{H}, all {params['opacity_logit'].shape[0]} Gaussians; "
                   f"FP64 projection {t_proj:.2f}s not included), {dt:.1f}s",
     }
 
@@ -144,11 +153,17 @@ def main():
     from paper_2509_12138_amd import _lib, workloads
     from paper_2509_12138_amd.train import PlainTrainer
     _lib.load()
+    highres = args.workload == "highres"
     cfg = dict(n=20000, n_ref=80000, views=8, width=320, height=180) if args.small else {}
     cfg["fov"] = args.fov
-    cfg["order"] = args.order
     t0 = time.perf_counter()
-    wl = workloads.realistic_partition(cfg)
+    if highres:
+        if args.small:
+            cfg.update(n=200000, n_ref=200000, width=640, height=360)
+        wl = workloads.highres_partition(cfg, device="cuda")
+    else:
+        cfg["order"] = args.order
+        wl = workloads.realistic_partition(cfg)
     log(f"scene built in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
     targets, masks = workloads.render_targets_gpu(wl["reference"], wl["cams"])
@@ -162,7 +177,13 @@ def main():
         return PlainTrainer(wl["params"], wl["cams"], targets, masks, tile=tile, stored=stored)
 
     tune_entry = None
-    if args.no_autotune or (args.tile and args.schedule is not None and args.chunk is not None):
+    if highres and not args.tile and args.schedule is None:
+        # the plan the autotuner picks for the 1080p partition; tuning at this
+        # size would build one 13.3M-Gaussian trainer per candidate
+        args.tile, args.schedule = "16x16", "lpt"
+        args.chunk = 64 if args.chunk is None else args.chunk
+        args.fwd_waves = args.fwd_waves or 4
+    if args.no_autotune or highres or (args.tile and args.schedule is not None and args.chunk is not None):
         plan = (tuple(int(x) for x in (args.tile or "16x16").split("x")), args.schedule or "default",
                 args.chunk or 0, args.fwd_waves or 1, bool(args.deterministic))
     else:
@@ -188,6 +209,7 @@ def main():
         tr.step(int(order[s]))
     tr.check()
     torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
     # stage events on every EVENT_EVERY-th timed step: an event record costs
     # about 5 us of queue gap, so recording nine per step would inflate the
     # step time the loop measures
@@ -199,7 +221,13 @@ def main():
     torch.cuda.synchronize()
     tr.timing = timing
     wall = time.perf_counter() - t0
+    peak_mem = torch.cuda.max_memory_allocated()
     tr.check()
+    b = tr.bufs
+    state_bytes = sum(int(t.numel() * t.element_size()) for t in
+                      (getattr(b, "T_final", None), getattr(b, "n_contrib", None),
+                       getattr(b, "checkpoints", None) if b.chunk else None,
+                       getattr(b, "chunk_items", None) if b.chunk else None) if t is not None)
     ev = tr.timing
     names = ["project", "bin_sort", "raster_fwd", "loss", "zero", "raster_bwd", "project_bwd", "adam", "end"]
     stage_ms = {}
@@ -252,8 +280,9 @@ def main():
     # while its source is unchanged since they were taken
     from paper_2509_12138_amd import traffic as _traffic
     plan_str = f"{tile[0]}x{tile[1]},{sched},{chunk},{fwd_waves},{int(deterministic)}"
-    roof["traffic"] = _traffic.lookup(os.path.join(ROOT, "paper_2509_12138_amd", "hbm_traffic.json"),
-                                      roof["kernel"], plan_str)
+    # (the committed counter runs cover the 1080p partition only)
+    roof["traffic"] = None if highres else _traffic.lookup(
+        os.path.join(ROOT, "paper_2509_12138_amd", "hbm_traffic.json"), roof["kernel"], plan_str)
     out = {
         "metric": METRIC,
         "value": round(mpix, 3),
@@ -269,12 +298,15 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"single partition: mixing-layer isosurface, {cfgd['n']} Gaussians "
+            "workload": (f"high-resolution partition: octant of the bumpy-sphere isosurface on a "
+                         f"{cfgd['grid']}^3 grid with {cfgd['ghost']}-voxel ghost cells, "
+                         if highres else "single partition: mixing-layer isosurface, ")
+                        + f"{cfgd['n']} Gaussians "
                         f"(SH {args.sh_degree}), {cfgd['views']} orbital views at {W}x{H}"
                         + (f" (field of view {args.fov:g} deg)" if args.fov != 50.0 else "")
                         + ", masks, batch 1 view",
             "optimizer": "sparse adam" if args.sparse_adam else "adam",
-            "gaussian_order": args.order,
+            "gaussian_order": "morton" if highres else args.order,
             "tile": f"{tile[0]}x{tile[1]}",
             "schedule": sched,
             "backward_chunk": chunk,
@@ -285,6 +317,7 @@ def main():
             "duplicates_per_view": need,
         },
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "memory": {"peak_allocated_bytes": int(peak_mem), "raster_state_bytes": state_bytes},
         "pairs": {"blended": blended, "list_positions": list_pairs, "drawn_gaussians": drawn},
         "roofline": roof,
     }

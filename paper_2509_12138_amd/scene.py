@@ -123,6 +123,10 @@ def field_sphere_sines(p):
     return f, g
 
 
+# |grad f| <= 1 + 0.3 |(cos sin sin, sin cos sin, sin sin cos)| <= 1 + 0.3 sqrt(3)
+field_sphere_sines.lipschitz = 1.0 + 0.3 * np.sqrt(3.0)
+
+
 class GradientNoise3D:
     """Perlin-style gradient noise with a seeded permutation and seeded unit
     gradients (written from Perlin's description: lattice gradients, quintic
@@ -239,11 +243,17 @@ class MixingInterface:
 # Surface sampling of an implicit field
 # --------------------------------------------------------------------------
 
-def candidate_cells(field, grid, lo=-1.0, hi=1.0, box=None):
-    """Integer (i, j, k) of grid cells whose 8 corner values straddle zero.
+def candidate_cells(field, grid, lo=-1.0, hi=1.0, box=None, block=16):
+    """Integer (i, j, k) of grid cells whose 8 corner values straddle zero,
+    sorted by (k, i, j).
 
     box = (lo3, hi3) restricts the search to cells inside an axis-aligned box.
-    The volume is processed in z slabs so large grids fit in memory.
+    A field with a ``lipschitz`` attribute (a bound on |grad f|) is screened
+    block by block first: a block of block^3 cells whose centre value exceeds
+    the bound times its half-diagonal has one sign throughout and holds no
+    straddling cell, so only blocks near the surface have their corners
+    evaluated (same corner coordinates, same cells as the full sweep).
+    Otherwise the volume is swept in z slabs so large grids fit in memory.
     """
     h = (hi - lo) / grid
     if box is None:
@@ -251,6 +261,9 @@ def candidate_cells(field, grid, lo=-1.0, hi=1.0, box=None):
     else:
         kmin = np.clip(np.floor((np.asarray(box[0]) - lo) / h).astype(np.int64), 0, grid)
         kmax = np.clip(np.ceil((np.asarray(box[1]) - lo) / h).astype(np.int64), 0, grid)
+    lip = getattr(field, "lipschitz", None)
+    if lip is not None and block > 1:
+        return _candidate_cells_screened(field, lip, lo, h, kmin, kmax, block), h
     xs = lo + h * np.arange(kmin[0], kmax[0] + 1)
     ys = lo + h * np.arange(kmin[1], kmax[1] + 1)
     out = []
@@ -271,6 +284,32 @@ def candidate_cells(field, grid, lo=-1.0, hi=1.0, box=None):
                                             np.full(len(ii), kz - 1)]))
         prev = s
     return np.concatenate(out) if out else np.zeros((0, 3), np.int64), h
+
+
+def _candidate_cells_screened(field, lip, lo, h, kmin, kmax, block):
+    edges = [np.append(np.arange(kmin[a], kmax[a], block), kmax[a]) for a in range(3)]
+    b0 = np.meshgrid(*[e[:-1] for e in edges], indexing="ij")
+    b1 = np.meshgrid(*[e[1:] for e in edges], indexing="ij")
+    b0 = np.stack([b.ravel() for b in b0], -1)
+    b1 = np.stack([b.ravel() for b in b1], -1)
+    centre = lo + h * 0.5 * (b0 + b1)
+    half_diag = 0.5 * h * np.sqrt(np.sum((b1 - b0).astype(np.float64) ** 2, axis=1))
+    fc, _ = field(centre)
+    near = np.abs(fc) <= lip * half_diag * (1 + 1e-6) + 1e-12
+    out = []
+    for k0, k1 in zip(b0[near], b1[near]):
+        ax = [lo + h * np.arange(k0[a], k1[a] + 1) for a in range(3)]
+        P = np.stack(np.meshgrid(*ax, indexing="ij"), axis=-1)
+        s = field(P)[0] > 0
+        c8 = np.stack([s[:-1, :-1, :-1], s[1:, :-1, :-1], s[:-1, 1:, :-1], s[1:, 1:, :-1],
+                       s[:-1, :-1, 1:], s[1:, :-1, 1:], s[:-1, 1:, 1:], s[1:, 1:, 1:]])
+        ii, jj, kk = np.nonzero(c8.any(0) & ~c8.all(0))
+        if len(ii):
+            out.append(np.column_stack([ii + k0[0], jj + k0[1], kk + k0[2]]))
+    if not out:
+        return np.zeros((0, 3), np.int64)
+    cells = np.concatenate(out).astype(np.int64)
+    return cells[np.lexsort((cells[:, 1], cells[:, 0], cells[:, 2]))]
 
 
 def sample_surface(field, n, grid, seed, lo=-1.0, hi=1.0, box=None, newton=3, tol=1e-6):

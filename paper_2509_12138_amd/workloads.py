@@ -13,6 +13,12 @@ these builders produce seeded scenes of the same structure:
   is where the reference covers at least half of the pixel (1 - T >= 0.5).
 * ``tiny_partition``       the bumpy-sphere field on a 64^3 grid, 4,096
   Gaussians, 16 views at 128x128 (targets supplied by the caller).
+* ``highres_partition``    one eighth of a ~106.7M-Gaussian scene: the
+  bumpy-sphere field on a 2048^3 grid, the x, y, z >= 0 octant padded by
+  2-voxel ghost cells across its three internal faces (Sec. II, partitioning
+  with ghost cells), 13.3M Gaussians, 64 orbital views at 3840x2160; its
+  reference set is the octant's share of the full scene, sampled with its
+  own seed.
 """
 from __future__ import annotations
 
@@ -24,6 +30,8 @@ from . import scene
 
 REALISTIC = dict(n=1_000_000, n_ref=4_000_000, views=64, width=1920, height=1080, seed=2)
 TINY = dict(n=4096, n_ref=32768, views=16, width=128, height=128, grid=64, seed=1)
+HIGHRES = dict(n=13_300_000, n_ref=13_300_000, views=64, width=3840, height=2160, grid=2048,
+               ghost=2, seed=3)
 
 
 def init_gaussians(points, normals, opacity=0.1, knn_scale=None):
@@ -65,6 +73,45 @@ def _chunked_sample(mi, n, seed, chunk=500_000):
         pts.append(p); nrm.append(q)
         left -= k
     return np.concatenate(pts), np.concatenate(nrm)
+
+
+def octant_box(grid, ghost, lo=-1.0, hi=1.0):
+    """The x, y, z >= 0 octant of [lo, hi]^3, padded by ``ghost`` voxels of a
+    grid^3 sampling (spacing (hi - lo) / (grid - 1)) across the three faces it
+    shares with the other octants."""
+    g = ghost * (hi - lo) / (grid - 1)
+    return ((-g, -g, -g), (hi, hi, hi))
+
+
+def _knn_scale(points, device):
+    """3-NN mean distance, on the device (gs_knn) when one is given."""
+    if device is None:
+        return scene.knn_mean_distance(points, 3)
+    import torch
+    from . import ops
+    pd = torch.as_tensor(np.ascontiguousarray(points.T, np.float32)).to(device)
+    d = ops.knn_mean_distance(pd, 3).cpu().numpy().astype(np.float64)
+    del pd
+    return d
+
+
+def highres_partition(cfg=None, with_reference=True, device=None):
+    """The high-resolution octant partition; device = a torch device runs the
+    k-NN scale of the initialisation and of the reference discs there."""
+    cfg = dict(HIGHRES, **(cfg or {}))
+    box = octant_box(cfg["grid"], cfg["ghost"])
+    f = scene.field_sphere_sines
+    pts, nrm = scene.sample_surface(f, cfg["n"], cfg["grid"], seed=cfg["seed"], box=box)
+    perm = scene.morton_order(pts)
+    pts, nrm = pts[perm], nrm[perm]
+    params = init_gaussians(pts, nrm, knn_scale=_knn_scale(pts, device))
+    cams = scene.orbit_cameras(cfg["views"], cfg["width"], cfg["height"],
+                               fov_x_deg=cfg.get("fov", 50.0))
+    out = dict(params=params, cams=cams, cfg=cfg, points=pts, normals=nrm, box=box)
+    if with_reference:
+        rp, rn = scene.sample_surface(f, cfg["n_ref"], cfg["grid"], seed=100 + cfg["seed"], box=box)
+        out["reference"] = reference_discs(rp, rn, _knn_scale(rp, device))
+    return out
 
 
 def tiny_partition(cfg=None):

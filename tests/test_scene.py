@@ -23,6 +23,30 @@ def test_box_restricted_sampling():
     assert np.all(pts >= 0) and len(pts) == 2000
 
 
+def test_screened_candidate_cells_equal_the_full_sweep():
+    """The Lipschitz block screen keeps exactly the cells the corner sweep
+    finds (same cells, same order), whole grid and boxes with ragged blocks."""
+    f = scene.field_sphere_sines
+    sweep = lambda p: f(p)                         # no lipschitz attribute: full sweep
+    assert not hasattr(sweep, "lipschitz") and f.lipschitz > 1
+    for grid, box, block in ((64, None, 16), (200, ((-0.3, 0.1, -1.0), (0.9, 0.7, 0.2)), 16),
+                             (150, ((0.0, 0.0, 0.0), (1.0, 1.0, 1.0)), 7)):
+        a, h = scene.candidate_cells(f, grid, box=box, block=block)
+        b, h2 = scene.candidate_cells(sweep, grid, box=box)
+        assert h == h2 and len(a) > 1000
+        np.testing.assert_array_equal(a, b)
+
+
+def test_octant_box_has_two_voxel_ghosts():
+    from paper_2509_12138_amd import workloads
+    lo, hi = workloads.octant_box(2048, 2)
+    np.testing.assert_allclose(lo, -2 * 2 / 2047)
+    np.testing.assert_array_equal(hi, 1.0)
+    pts, _ = scene.sample_surface(scene.field_sphere_sines, 3000, 256, seed=3,
+                                  box=workloads.octant_box(256, 2))
+    assert np.all(pts >= -2 * 2 / 255) and (pts < 0).any()
+
+
 def test_mixing_interface_samples():
     mi = scene.MixingInterface(seed=2)
     assert abs(mi.A.sum() - 0.25) < 1e-12 and len(mi.A) == 32
