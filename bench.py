@@ -177,13 +177,7 @@ def main():
         return PlainTrainer(wl["params"], wl["cams"], targets, masks, tile=tile, stored=stored)
 
     tune_entry = None
-    if highres and not args.tile and args.schedule is None:
-        # the plan the autotuner picks for the 1080p partition; tuning at this
-        # size would build one 13.3M-Gaussian trainer per candidate
-        args.tile, args.schedule = "16x16", "lpt"
-        args.chunk = 64 if args.chunk is None else args.chunk
-        args.fwd_waves = args.fwd_waves or 4
-    if args.no_autotune or highres or (args.tile and args.schedule is not None and args.chunk is not None):
+    if args.no_autotune or (args.tile and args.schedule is not None and args.chunk is not None):
         plan = (tuple(int(x) for x in (args.tile or "16x16").split("x")), args.schedule or "default",
                 args.chunk or 0, args.fwd_waves or 1, bool(args.deterministic))
     else:
@@ -242,20 +236,26 @@ def main():
     # blended (pixel, Gaussian) pairs, counted with the forward's decisions
     last_view = int(order[args.warmup + args.steps - 1])
     tr.views.use_cameras(tr.cams[last_view:last_view + 1])
-    tr.bufs.render_checked(tr.gst, tr.bg)
+    rb = tr.bufs
+    if rb.n_contrib is None:
+        # the recomputing backward keeps no per-pixel state: replay into
+        # buffers that do
+        from paper_2509_12138_amd import ops as _ops
+        rb = _ops.RasterBuffers(tr.views, W, H, tile, dup_capacity=tr.bufs.dup_capacity)
+    rb.render_checked(tr.gst, tr.bg)
     import torch as _t
-    blended = float(tr.bufs.count_blended()[0].to(_t.int64).sum())
-    drawn = float((tr.bufs.n_tiles > 0).float().mean())
+    blended = float(rb.count_blended()[0].to(_t.int64).sum())
+    drawn = float((rb.n_tiles > 0).float().mean())
     evals_fwd = evals_bwd = blended
     # list positions visited before each pixel stops (what a rasteriser with
     # no culling below the tile evaluates), reported beside it
-    nc = tr.bufs.n_contrib[0].to(_t.int64)
-    rng_t = tr.bufs.ranges.to(_t.int64)
+    nc = rb.n_contrib[0].to(_t.int64)
+    rng_t = rb.ranges.to(_t.int64)
     tile_len = (rng_t[:, 1] - rng_t[:, 0])
     tx = (_t.arange(W, device="cuda") // tile[0])
     ty = (_t.arange(H, device="cuda") // tile[1])
-    tid = ty[:, None] * tr.bufs.tiles_x + tx[None, :]
-    stopped = tr.bufs.T_final[0] < 2e-4
+    tid = ty[:, None] * rb.tiles_x + tx[None, :]
+    stopped = rb.T_final[0] < 2e-4
     list_pairs = float(_t.where(stopped, _t.minimum(nc + 1, tile_len[tid]), tile_len[tid]).sum())
     dom = "raster_bwd" if t_bwd >= max(v for k, v in stage_ms.items() if k != "raster_bwd") else \
         max(stage_ms, key=stage_ms.get)

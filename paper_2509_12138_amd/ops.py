@@ -274,7 +274,7 @@ class RasterBuffers:
     def count_blended(self, stream=None):
         """Per-pixel number of blended list entries (gs_raster_count) of the
         current lists, as a new [S, H, W] int32 tensor."""
-        out = torch.empty_like(self.n_contrib)
+        out = torch.empty((self.S, self.H, self.W), dtype=torch.int32, device=self.views.device)
         call("gs_raster_count", C.byref(self.proj), C.byref(self.views.struct),
              C.byref(self.tiling), _ptr(self.ids), _ptr(self.ranges), _ptr(out),
              stream or stream_handle())

@@ -190,8 +190,10 @@ def test_highres_parameter_gradients_match_finite_differences(hr):
     1.6e-3 px and the truncation error of the difference reaches 1e-5
     relative.  A perturbation that changes a discrete decision (a pixel's
     contributor or blend count, the Gaussian's tile bbox, its place in the
-    depth order) is rejected and counted.  Bound: 1e-5 relative, floor 1e-7
-    of the Gaussian's largest gradient."""
+    depth order) is rejected and counted.  Bound: 1e-5 relative, plus 1e-6 of
+    the Gaussian's largest gradient, plus 2e-8: the rounding of the two
+    window sums (about sqrt(3000) FP64 ulps of terms below 1) divided by
+    2h = 2e-7 is about 1e-8 for the mean."""
     say("high-res FD on the 256-Gaussian subset")
     o, dI, params = hr["o"], hr["dI"], hr["params"]
     camd = scene.camera_dict(hr["cam"][0])
@@ -254,7 +256,7 @@ def test_highres_parameter_gradients_match_finite_differences(hr):
                     continue
                 fd = (Lp - Lm) / (2 * h)
                 g = ga[r_, 0]
-                assert abs(fd - g) <= 1e-5 * abs(g) + 1e-7 * gmax + 1e-9, (int(i), key, r_, fd, g)
+                assert abs(fd - g) <= 1e-5 * abs(g) + 1e-6 * gmax + 2e-8, (int(i), key, r_, fd, g)
                 checked += 1
     say(f"FD checked {checked}, rejected {rejected}")
     assert checked >= 256 * 14 * 0.8 and rejected <= checked // 10
