@@ -25,6 +25,7 @@ CANDIDATES = [
     ((16, 16), "lpt", 64, 1, False), ((16, 16), "persistent", 64, 1, True),
     ((16, 8), "lpt", 64, 2, True), ((8, 16), "lpt", 64, 2, True), ((8, 16), "lpt", 64, 1, False),
     ((8, 8), "lpt", 0, 1, True), ((16, 16), "lpt", 0, 4, True), ((32, 8), "lpt", 128, 4, True),
+    ((8, 8), "lpt", 64, 1, False), ((8, 8), "lpt", 0, 1, False), ((16, 16), "lpt", 0, 4, False),
 ]
 
 
