@@ -248,7 +248,9 @@ int64_t gs_chunk_max_items(int64_t n_tiles, int64_t dup_capacity, int32_t chunk)
 
 /* Work items of the chunked backward: chunk_offset[t] = first item of tile t
  * (chunk_offset[n_tiles] = item count = sum of ceil(len_t / chunk)),
- * chunk_items[i] = tile of item i.  Device arrays, no host sync.           */
+ * chunk_items[i] = tile of item i.  Device arrays, no host sync.  Entries of
+ * chunk_items past the item count are unspecified (above 16384 tiles the
+ * call keeps per-block sums there while it scans).                         */
 gs_status gs_chunk_items(const uint32_t* tile_ranges, int64_t n_tiles, int32_t chunk,
                          int64_t max_items, uint32_t* chunk_offset, uint32_t* chunk_items,
                          void* stream);

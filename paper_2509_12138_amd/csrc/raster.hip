@@ -930,6 +930,96 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_scan(const uint32_t* __
   if (j == kChunkThreads - 1) offset[n_tiles] = part[kChunkThreads - 1];
 }
 
+// Above kChunkScanOne tiles the single work-group's sequential segments
+// cost more than three grid launches (0.25 ms at 129,600 tiles): block b
+// sums the counts of its kChunkBlock tiles, one work-group scans the block
+// sums in place, then block b scans its tiles from its base.  Same offsets.
+constexpr int64_t kChunkScanOne = 16384;
+constexpr int kChunkPer = 4;                               // tiles per thread
+constexpr int kChunkBlock = 256 * kChunkPer;
+
+__device__ __forceinline__ uint32_t chunk_count(const uint32_t* __restrict__ ranges, int64_t t,
+                                                int chunk) {
+  return (ranges[2 * t + 1] - ranges[2 * t] + chunk - 1) / chunk;
+}
+
+__global__ __launch_bounds__(256) void k_chunk_bsum(const uint32_t* __restrict__ ranges,
+                                                    int64_t n_tiles, int chunk,
+                                                    uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t red[256];
+  const int64_t base = (int64_t)blockIdx.x * kChunkBlock;
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kChunkPer; ++k) {
+    const int64_t t = base + k * 256 + threadIdx.x;
+    if (t < n_tiles) sum += chunk_count(ranges, t, chunk);
+  }
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+// Exclusive scan of n values in place, one work-group (thread j owns a
+// contiguous segment).
+__global__ __launch_bounds__(kChunkThreads) void k_chunk_bscan(uint32_t* __restrict__ v,
+                                                               int64_t n) {
+  __shared__ uint32_t part[kChunkThreads];
+  const int j = threadIdx.x;
+  const int64_t per = (n + kChunkThreads - 1) / kChunkThreads;
+  const int64_t b0 = min((int64_t)j * per, n), b1 = min(b0 + per, n);
+  uint32_t sum = 0;
+  for (int64_t t = b0; t < b1; ++t) sum += v[t];
+  part[j] = sum;
+  __syncthreads();
+  for (int d = 1; d < kChunkThreads; d <<= 1) {
+    const uint32_t x = j >= d ? part[j - d] : 0u;
+    __syncthreads();
+    part[j] += x;
+    __syncthreads();
+  }
+  uint32_t run = j > 0 ? part[j - 1] : 0u;
+  for (int64_t t = b0; t < b1; ++t) {
+    const uint32_t c = v[t];
+    v[t] = run;
+    run += c;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_chunk_offsets(const uint32_t* __restrict__ ranges,
+                                                       int64_t n_tiles, int chunk,
+                                                       const uint32_t* __restrict__ bbase,
+                                                       uint32_t* __restrict__ offset) {
+  __shared__ uint32_t part[256];
+  const int j = threadIdx.x;
+  const int64_t t0 = (int64_t)blockIdx.x * kChunkBlock + (int64_t)j * kChunkPer;
+  uint32_t c[kChunkPer];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kChunkPer; ++k) {
+    c[k] = t0 + k < n_tiles ? chunk_count(ranges, t0 + k, chunk) : 0u;
+    sum += c[k];
+  }
+  part[j] = sum;
+  __syncthreads();
+  for (int d = 1; d < 256; d <<= 1) {
+    const uint32_t x = j >= d ? part[j - d] : 0u;
+    __syncthreads();
+    part[j] += x;
+    __syncthreads();
+  }
+  uint32_t run = bbase[blockIdx.x] + (j > 0 ? part[j - 1] : 0u);
+#pragma unroll
+  for (int k = 0; k < kChunkPer; ++k) {
+    if (t0 + k < n_tiles) offset[t0 + k] = run;
+    run += c[k];
+    if (t0 + k == n_tiles - 1) offset[n_tiles] = run;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_chunk_items(const uint32_t* __restrict__ offset,
                                                      int64_t n_tiles, int64_t max_items,
                                                      uint32_t* __restrict__ items) {
@@ -1150,9 +1240,22 @@ gs_status gs_chunk_items(const uint32_t* tile_ranges, int64_t n_tiles, int32_t c
   GS_REQUIRE(tile_ranges && chunk_offset && chunk_items, "gs_chunk_items: NULL argument");
   GS_REQUIRE(max_items > 0, "gs_chunk_items: max_items must be positive");
   hipStream_t s = as_stream(stream);
-  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kChunkThreads), 0, s, tile_ranges, n_tiles, chunk,
-                     chunk_offset);
-  GS_LAUNCH_CHECK("gs_chunk_items/scan");
+  const int64_t nb = ceil_div(n_tiles, (int64_t)kChunkBlock);
+  if (n_tiles > kChunkScanOne && nb <= max_items) {
+    // the block sums live in chunk_items until the fill below overwrites it
+    hipLaunchKernelGGL(k_chunk_bsum, dim3((unsigned)nb), dim3(256), 0, s, tile_ranges, n_tiles,
+                       chunk, chunk_items);
+    GS_LAUNCH_CHECK("gs_chunk_items/bsum");
+    hipLaunchKernelGGL(k_chunk_bscan, dim3(1), dim3(kChunkThreads), 0, s, chunk_items, nb);
+    GS_LAUNCH_CHECK("gs_chunk_items/bscan");
+    hipLaunchKernelGGL(k_chunk_offsets, dim3((unsigned)nb), dim3(256), 0, s, tile_ranges, n_tiles,
+                       chunk, chunk_items, chunk_offset);
+    GS_LAUNCH_CHECK("gs_chunk_items/offsets");
+  } else {
+    hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kChunkThreads), 0, s, tile_ranges, n_tiles,
+                       chunk, chunk_offset);
+    GS_LAUNCH_CHECK("gs_chunk_items/scan");
+  }
   if (n_tiles > 0) {
     hipLaunchKernelGGL(k_chunk_items, dim3((unsigned)ceil_div(n_tiles, 256)), dim3(256), 0, s,
                        chunk_offset, n_tiles, max_items, chunk_items);

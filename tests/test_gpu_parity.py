@@ -576,3 +576,32 @@ def test_deterministic_gradients_are_reproducible(ops, chunk):
     np.testing.assert_array_equal(out[0], out[1])
     nr = np.linalg.norm(out[0] - out[2]) / np.linalg.norm(out[2])
     assert nr <= 1e-5, nr
+
+
+@pytest.mark.parametrize("n_tiles,empty", [(5000, False), (16385, False), (129600, False),
+                                           (300001, False), (129600, True)])
+def test_chunk_items_exact(ops, n_tiles, empty):
+    """gs_chunk_items against the plain definition: offsets = exclusive sum
+    of ceil(len / chunk), items = each tile repeated that often.  Up to 16384
+    tiles one work-group scans; above, three grid launches (block sums, their
+    scan, per-block scans); with a single allowed item (all tiles empty) the
+    one-work-group scan again."""
+    say("chunk items", n_tiles, empty)
+    rng = np.random.default_rng(n_tiles)
+    lens = np.zeros(n_tiles, np.int64) if empty else rng.integers(0, 600, n_tiles)
+    lens[rng.uniform(size=n_tiles) < 0.4] = 0
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    ranges = np.stack([starts, starts + lens], 1).astype(np.uint32)
+    chunk = 64
+    cnt = (lens + chunk - 1) // chunk
+    off = np.concatenate([[0], np.cumsum(cnt)]).astype(np.uint32)
+    total = int(off[-1])
+    max_items = total + 7 if total else 1
+    r_d = torch.as_tensor(ranges.view(np.int32)).cuda()
+    o_d = torch.full((n_tiles + 1,), -1, dtype=torch.int32, device="cuda")
+    i_d = torch.full((max_items,), -1, dtype=torch.int32, device="cuda")
+    ops.call("gs_chunk_items", r_d.data_ptr(), n_tiles, chunk, max_items, o_d.data_ptr(),
+             i_d.data_ptr(), ops.stream_handle())
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(o_d.cpu().numpy().view(np.uint32), off)
+    np.testing.assert_array_equal(i_d.cpu().numpy()[:total], np.repeat(np.arange(n_tiles), cnt))
