@@ -299,6 +299,43 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ hi
   if (threadIdx.x == 0) row_tot[blockIdx.x] = total;
 }
 
+// Rows of up to kRowLds block counts: the row is staged in LDS with
+// coalesced loads, each thread scans its segment there, and the row goes
+// back with coalesced stores.  (In the plain version above every global
+// access of a wave touches 64 lines: 43 us per pass at 17K blocks.)
+constexpr int kRowLds = 32768;                      // 128 KB of the 160 KB LDS
+
+__global__ __launch_bounds__(256) void k_radix_rowscan_lds(uint32_t* __restrict__ hist, int64_t nb,
+                                                           uint32_t* __restrict__ row_tot) {
+  __shared__ uint32_t r[kRowLds];
+  __shared__ uint32_t sm[4];
+  uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+  const int n = (int)nb;
+  for (int i = threadIdx.x; i < n; i += 256) r[i] = row[i];
+  __syncthreads();
+  const int seg = (n + 255) / 256;
+  const int b0 = min((int)threadIdx.x * seg, n), b1 = min(b0 + seg, n);
+  uint32_t s = 0;
+  for (int b = b0; b < b1; ++b) s += r[b];
+  uint32_t total;
+  uint32_t ex = block_exclusive_scan<uint32_t>(s, sm, total);
+  for (int b = b0; b < b1; ++b) {
+    const uint32_t x = r[b];
+    r[b] = ex;
+    ex += x;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) row[i] = r[i];
+  if (threadIdx.x == 0) row_tot[blockIdx.x] = total;
+}
+
+static void launch_rowscan(uint32_t* hist, int64_t nb, uint32_t* row_tot, hipStream_t s) {
+  if (nb <= kRowLds)
+    hipLaunchKernelGGL(k_radix_rowscan_lds, dim3(kRadix), dim3(256), 0, s, hist, nb, row_tot);
+  else
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, nb, row_tot);
+}
+
 // vin2 / vout2 (may be NULL): a second value carried along.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
@@ -495,7 +532,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)L.nb_pairs), dim3(kSortThreads), 0, s, pk[a],
                        count_pairs, shift, L.nb_pairs, hist);
     GS_LAUNCH_CHECK("gs_bin_sort/depth_hist");
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, L.nb_pairs, rowtot);
+    launch_rowscan(hist, L.nb_pairs, rowtot, s);
     GS_LAUNCH_CHECK("gs_bin_sort/depth_rowscan");
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)L.nb_pairs), dim3(kSortThreads), 0, s,
                        pk[a], pv[a], pk[b], pv[b], count_pairs, shift, L.nb_pairs, hist, rowtot,
@@ -524,7 +561,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
     hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)L.nb_sort), dim3(kSortThreads), 0, s, kin,
                        count, shift, L.nb_sort, hist);
     GS_LAUNCH_CHECK("gs_bin_sort/radix_hist");
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, L.nb_sort, rowtot);
+    launch_rowscan(hist, L.nb_sort, rowtot, s);
     GS_LAUNCH_CHECK("gs_bin_sort/radix_rowscan");
     hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)L.nb_sort), dim3(kSortThreads), 0, s, kin,
                        vin, kout, vout, count, shift, L.nb_sort, hist, rowtot, ein, eout);
