@@ -185,7 +185,7 @@ def main():
         t0 = time.perf_counter()
         plan, tune_entry = autotune.tune(make, W, H, 1, cfgd["n"], stored=stored,
                                          views=list(range(0, cfgd["views"], max(1, cfgd["views"] // 8))),
-                                         cache_path=os.path.join(ROOT, "gpurun_out", "autotune.json"),
+                                         cache_path=os.path.join(ROOT, "_build", "autotune.json"),
                                          force=not args.cached_plan, log=log)
         log(f"autotuned plan {plan} in {time.perf_counter() - t0:.1f}s")
     tile, sched, chunk, fwd_waves, deterministic = plan
