@@ -80,6 +80,13 @@ def parse():
                          "they were sampled in")
     ap.add_argument("--sparse-adam", action="store_true",
                     help="visible-only Adam (the headline workload uses the dense step)")
+    ap.add_argument("--trained-steps", type=int, default=None,
+                    help="also time the partition after this many training steps (default 2000 "
+                         "for the headline workload, 0 = skip)")
+    ap.add_argument("--ttt", type=int, default=None,
+                    help="1: also measure the plain trainer's time to 35 dB masked PSNR from the "
+                         "plain initialisation (default on for the headline workload)")
+    ap.add_argument("--ttt-steps", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device copy 5 times (HBM counter scale)")
     return ap.parse_args()
@@ -137,6 +144,120 @@ def cpu_baseline(params, cam, target_seconds):
     }
 
 
+STAGES = ["project", "bin_sort", "raster_fwd", "loss", "zero", "raster_bwd", "project_bwd",
+          "adam", "end"]
+
+
+def timed_steps(tr, order, first, steps):
+    """Time `steps` training steps on views order[first:first + steps].
+    Stage events (HIP events on the launch stream) are recorded on every
+    EVENT_EVERY-th step only: an event record costs about 5 us of queue gap,
+    so nine per step would inflate the step time the wall clock measures.
+    Returns (ms per step, mean stage ms, summed stage ms over the event
+    steps, the views of the event steps)."""
+    import torch
+    timing = {}
+    event_views = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ev = s % EVENT_EVERY == 0
+        tr.timing = timing if ev else None
+        v = int(order[first + s])
+        if ev:
+            event_views.append(v)
+        tr.step(v)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tr.timing = None
+    mean, total = {}, {}
+    for a, b in zip(STAGES[:-1], STAGES[1:]):
+        d = [x.elapsed_time(y) for x, y in zip(timing[a], timing[b])]
+        mean[a], total[a] = float(np.mean(d)), float(np.sum(d))
+    return wall * 1000.0 / steps, mean, total, event_views
+
+
+def count_work(tr, views, W, H, tile):
+    """Blended (pixel, Gaussian) pairs of each view, summed, with the
+    forward's decisions (gs_raster_count) on the trainer's current state;
+    also the list positions each pixel visits before it stops (the work of a
+    rasteriser with no culling below the tile) and the drawn fraction."""
+    import torch
+    from paper_2509_12138_amd import ops as _ops
+    rb = tr.bufs
+    if rb.n_contrib is None:
+        # the recomputing backward keeps no per-pixel state: render into
+        # buffers that do
+        rb = _ops.RasterBuffers(tr.views, W, H, tile, dup_capacity=tr.bufs.dup_capacity)
+    blended = lists = drawn = 0.0
+    tx = torch.arange(W, device="cuda") // tile[0]
+    ty = torch.arange(H, device="cuda") // tile[1]
+    tid = ty[:, None] * rb.tiles_x + tx[None, :]
+    for v in views:
+        tr.views.use_cameras(tr.cams[v:v + 1])
+        rb.render_checked(tr.gst, tr.bg)
+        blended += float(rb.count_blended()[0].to(torch.int64).sum())
+        drawn += float((rb.n_tiles > 0).float().mean())
+        nc = rb.n_contrib[0].to(torch.int64)
+        rng_t = rb.ranges.to(torch.int64)
+        tile_len = rng_t[:, 1] - rng_t[:, 0]
+        stopped = rb.T_final[0] < 2e-4
+        lists += float(torch.where(stopped, torch.minimum(nc + 1, tile_len[tid]),
+                                   tile_len[tid]).sum())
+    return dict(blended=blended, list_positions=lists, drawn=drawn / max(len(views), 1),
+                views=len(views))
+
+
+def trained_state(tr, order, first, steps, total, W, H, tile, ops_per_eval):
+    """Train on to `total` steps (untimed), then time `steps` more steps the
+    same way as at initialisation: the throughput of a trained partition,
+    whose pixels stop earlier."""
+    import torch
+    n = total - first
+    for s in range(max(n, 0)):
+        tr.step(int(order[first + s]))
+        if (s + 1) % 200 == 0:
+            tr.check()
+    tr.check()
+    psnr = tr.evaluate()
+    ms, stage, sums, views = timed_steps(tr, order, max(total, first), steps)
+    tr.check()
+    work = count_work(tr, views, W, H, tile)
+    k = "raster_bwd" if ops_per_eval[0] == "bwd" else "raster_fwd"
+    per = OPS_PER_EVAL_BWD if k == "raster_bwd" else OPS_PER_EVAL_FWD
+    frac = work["blended"] * per / (sums[k] * 1e-3) / PEAK_VALU_OPS
+    return {"after_steps": int(max(total, first)), "masked_psnr": round(psnr, 3),
+            "value": round(W * H / ((stage["raster_fwd"] + stage["raster_bwd"]) * 1e-3) / 1e6, 3),
+            "ms_per_step": round(ms, 4), "iters_per_s": round(1000.0 / ms, 3),
+            "stage_ms": {a: round(b, 4) for a, b in stage.items()},
+            "blended": work["blended"], "list_positions": work["list_positions"],
+            "roofline_frac": round(frac, 4)}
+
+
+def time_to_target(wl, targets, masks, plan, target=35.0, max_steps=2000, eval_every=50):
+    """The plain trainer from the plain initialisation on the device (k-NN
+    scale; its time counts) until the mean masked PSNR over all views
+    reaches the target, evaluated every eval_every steps with the clock
+    paused; at most max_steps steps."""
+    import torch
+    from paper_2509_12138_amd import ttt
+    part = dict(points=wl["points"], normals=wl["normals"], targets=targets, masks=masks,
+                n=len(wl["points"]))
+    # the initialisation's kernels run once untimed on a subset, so that the
+    # clock does not include their first load
+    sub = dict(points=wl["points"][:4096], normals=wl["normals"][:4096])
+    ttt.plain_params(sub)
+    torch.cuda.synchronize()
+    r = ttt.run_plain(part, wl["cams"], target, max_steps, eval_every, plan=plan, seed=2)
+    del r["trainer"]
+    hist = r["history"]
+    return {"target_db": target, "seconds": None if r["seconds"] is None else round(r["seconds"], 3),
+            "steps": int(r["steps"]), "init_seconds": round(r["init_seconds"], 4),
+            "final_psnr": round(hist[-1][2], 3) if hist else None,
+            "max_steps": max_steps, "eval_every": eval_every,
+            "curve": [(int(s), round(t, 3), round(p, 2)) for s, t, p in hist[:: max(1, len(hist) // 10)]]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -154,6 +275,10 @@ def main():
     from paper_2509_12138_amd.train import PlainTrainer
     _lib.load()
     highres = args.workload == "highres"
+    if args.trained_steps is None:
+        args.trained_steps = 0 if (highres or args.small) else 2000
+    if args.ttt is None:
+        args.ttt = 0 if (highres or args.small) else 1
     cfg = dict(n=20000, n_ref=80000, views=8, width=320, height=180) if args.small else {}
     cfg["fov"] = args.fov
     t0 = time.perf_counter()
@@ -204,17 +329,7 @@ def main():
     tr.check()
     torch.cuda.synchronize()
     torch.cuda.reset_peak_memory_stats()
-    # stage events on every EVENT_EVERY-th timed step: an event record costs
-    # about 5 us of queue gap, so recording nine per step would inflate the
-    # step time the loop measures
-    timing = {}
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        tr.timing = timing if s % EVENT_EVERY == 0 else None
-        tr.step(int(order[args.warmup + s]))
-    torch.cuda.synchronize()
-    tr.timing = timing
-    wall = time.perf_counter() - t0
+    ms_per_step, stage_ms, sums, timed_views = timed_steps(tr, order, args.warmup, args.steps)
     peak_mem = torch.cuda.max_memory_allocated()
     tr.check()
     b = tr.bufs
@@ -222,59 +337,36 @@ def main():
                       (getattr(b, "T_final", None), getattr(b, "n_contrib", None),
                        getattr(b, "checkpoints", None) if b.chunk else None,
                        getattr(b, "chunk_items", None) if b.chunk else None) if t is not None)
-    ev = tr.timing
-    names = ["project", "bin_sort", "raster_fwd", "loss", "zero", "raster_bwd", "project_bwd", "adam", "end"]
-    stage_ms = {}
-    for a, b in zip(names[:-1], names[1:]):
-        stage_ms[a] = float(np.mean([x.elapsed_time(y) for x, y in zip(ev[a], ev[b])]))
-    tr.timing = None
     t_fwd, t_bwd = stage_ms["raster_fwd"], stage_ms["raster_bwd"]
-    ms_per_step = wall * 1000.0 / args.steps
     mpix = W * H / ((t_fwd + t_bwd) * 1e-3) / 1e6
 
-    # algorithmic work of the last step's view (replayed once, untimed): the
-    # blended (pixel, Gaussian) pairs, counted with the forward's decisions
-    last_view = int(order[args.warmup + args.steps - 1])
-    tr.views.use_cameras(tr.cams[last_view:last_view + 1])
-    rb = tr.bufs
-    if rb.n_contrib is None:
-        # the recomputing backward keeps no per-pixel state: replay into
-        # buffers that do
-        from paper_2509_12138_amd import ops as _ops
-        rb = _ops.RasterBuffers(tr.views, W, H, tile, dup_capacity=tr.bufs.dup_capacity)
-    rb.render_checked(tr.gst, tr.bg)
-    import torch as _t
-    blended = float(rb.count_blended()[0].to(_t.int64).sum())
-    drawn = float((rb.n_tiles > 0).float().mean())
-    evals_fwd = evals_bwd = blended
-    # list positions visited before each pixel stops (what a rasteriser with
-    # no culling below the tile evaluates), reported beside it
-    nc = rb.n_contrib[0].to(_t.int64)
-    rng_t = rb.ranges.to(_t.int64)
-    tile_len = (rng_t[:, 1] - rng_t[:, 0])
-    tx = (_t.arange(W, device="cuda") // tile[0])
-    ty = (_t.arange(H, device="cuda") // tile[1])
-    tid = ty[:, None] * rb.tiles_x + tx[None, :]
-    stopped = rb.T_final[0] < 2e-4
-    list_pairs = float(_t.where(stopped, _t.minimum(nc + 1, tile_len[tid]), tile_len[tid]).sum())
+    # algorithmic work of exactly the steps whose raster launches were
+    # event-timed: their views' blended (pixel, Gaussian) pairs, counted with
+    # the forward's decisions on the state the timed region ended in
+    work = count_work(tr, timed_views, W, H, tile)
+    coverage = float(masks[timed_views].float().mean())
+    blended = work["blended"]
+    drawn = work["drawn"]
+    list_pairs = work["list_positions"]
     dom = "raster_bwd" if t_bwd >= max(v for k, v in stage_ms.items() if k != "raster_bwd") else \
         max(stage_ms, key=stage_ms.get)
+    evals_fwd = evals_bwd = blended
     if dom == "raster_bwd":
-        achieved = evals_bwd * OPS_PER_EVAL_BWD / (t_bwd * 1e-3)
+        achieved = evals_bwd * OPS_PER_EVAL_BWD / (sums["raster_bwd"] * 1e-3)
         kname = (f"k_raster_bwd_chunked<{tile[0]}, {tile[1]}>" if chunk else
                  f"k_raster_bwd<{tile[0]}, {tile[1]}, {'true' if args.recompute else 'false'}>")
         if deterministic:
             kname += "+k_dup_reduce"          # both run inside the timed gs_raster_bwd call
         roof = {"kernel": kname, "bound": "alu", "achieved": achieved / 1e12,
                 "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
-                "traffic": None, "units_per_launch": evals_bwd,
+                "traffic": None, "units_per_launch": evals_bwd / len(timed_views),
                 "unit_desc": f"{OPS_PER_EVAL_BWD} FP32 VALU issue slots per blended (pixel, Gaussian)"}
     else:
-        achieved = evals_fwd * OPS_PER_EVAL_FWD / (t_fwd * 1e-3)
+        achieved = evals_fwd * OPS_PER_EVAL_FWD / (sums["raster_fwd"] * 1e-3)
         roof = {"kernel": f"k_raster_fwd<{tile[0]}, {tile[1]}, {fwd_waves}>", "bound": "alu",
                 "achieved": achieved / 1e12,
                 "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
-                "traffic": None, "units_per_launch": evals_fwd,
+                "traffic": None, "units_per_launch": evals_fwd / len(timed_views),
                 "unit_desc": f"{OPS_PER_EVAL_FWD} FP32 VALU issue slots per blended (pixel, Gaussian)"}
     # HBM traffic of the dominant kernel from committed counter runs, only
     # while its source is unchanged since they were taken
@@ -283,6 +375,9 @@ def main():
     # (the committed counter runs cover the 1080p partition only)
     roof["traffic"] = None if highres else _traffic.lookup(
         os.path.join(ROOT, "paper_2509_12138_amd", "hbm_traffic.json"), roof["kernel"], plan_str)
+    roof["launches"] = len(timed_views)
+    roof["launch_ms"] = round(sums[dom] / len(timed_views), 4)
+    roof["views"] = timed_views
     out = {
         "metric": METRIC,
         "value": round(mpix, 3),
@@ -318,9 +413,23 @@ def main():
         },
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "memory": {"peak_allocated_bytes": int(peak_mem), "raster_state_bytes": state_bytes},
-        "pairs": {"blended": blended, "list_positions": list_pairs, "drawn_gaussians": drawn},
+        "pairs": {"blended": blended, "list_positions": list_pairs, "drawn_gaussians": drawn,
+                  "views": len(timed_views)},
+        "mask_coverage": round(coverage, 4),
         "roofline": roof,
     }
+    if args.trained_steps > 0:
+        log(f"training on to {args.trained_steps} steps for the trained-state measurement ...")
+        out["trained"] = trained_state(tr, order, args.warmup + args.steps, args.steps,
+                                       args.trained_steps, W, H, tile,
+                                       ("bwd" if dom == "raster_bwd" else "fwd",))
+    if args.ttt:
+        del tr
+        torch.cuda.empty_cache()
+        log("time to 35 dB of the plain trainer from the plain initialisation ...")
+        out["time_to_35db"] = time_to_target(wl, targets, masks,
+                                             (tile, sched, chunk, fwd_waves, deterministic),
+                                             max_steps=args.ttt_steps)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(wl["params"], wl["cams"][0], args.cpu_seconds)

@@ -329,6 +329,30 @@ gs_status gs_loss(const float* image, const float* target,
                   size_t ws_bytes, float* loss_out, float* d_image,
                   int64_t* status, void* stream);
 
+/* Workspace for gs_masked_psnr on S images of H x W.                      */
+size_t gs_psnr_workspace_bytes(int32_t S, int32_t H, int32_t W);
+
+/* Masked PSNR of each image s, the reconstruction metric the trainers stop
+ * on (PSNR, Sec. III; restricted to the object by the background mask of
+ * Sec. II "Image Rendering and Masking"):
+ *   se = sum over pixels p with mask[s][p] != 0 of
+ *        sum_c (clamp(image[s][c][p], 0, 1) - target[s][c][p])^2,
+ *   cnt = 3 x (number of such pixels),
+ *   psnr_out[s] = 10 log10(cnt / se)  (images in [0, 1], peak 1),
+ *   +inf when se = 0 < cnt, NaN when cnt = 0 (an empty mask).
+ * image, target [S][3][H][W] f32, mask [S][H][W] u8 (NULL = all pixels),
+ * psnr_out [S] f32: device.  Sums in FP64 in a fixed order (reproducible).
+ * ws: gs_psnr_workspace_bytes, 8-byte aligned.                             */
+gs_status gs_masked_psnr(const float* image, const float* target, const uint8_t* mask,
+                         int32_t S, int32_t H, int32_t W, void* ws, size_t ws_bytes,
+                         float* psnr_out, void* stream);
+
+/* x[r][i] *= scale[r] for rows r < rows and i < row_len (device arrays): the
+ * chain rule of the per-image loss of gs_loss through an upstream gradient
+ * (autograd).                                                              */
+gs_status gs_scale_rows(float* x, const float* scale, int64_t rows, int64_t row_len,
+                        void* stream);
+
 /* One parameter group of gs_adam: count fp32 elements at param/grad/m/v.  */
 typedef struct {
   float* param;
@@ -359,11 +383,33 @@ size_t gs_knn_workspace_bytes(int64_t n, int32_t k);
  * Sec. II "Isosurface Extraction").
  *   pts [3][n] device (planar x, y, z); idx [n][k] i32 and dist [n][k] f32
  *   device outputs sorted by (distance, index); missing neighbours (n <= k)
- *   are -1 / +inf.  1 <= k <= 32, n < 2^31.  ws: gs_knn_workspace_bytes,
- *   256-byte aligned.  Uniform grid + shell search with an exact stopping
- *   bound; no host synchronisation.                                        */
+ *   are -1 / +inf.  mean_dist [n] f32 device output: the arithmetic mean of
+ *   the distances to the neighbours found, summed nearest first (0 when
+ *   n = 1).  Each of idx, dist and mean_dist may be NULL (not written); at
+ *   least one must be given.  1 <= k <= 32, n < 2^31.  ws:
+ *   gs_knn_workspace_bytes, 256-byte aligned.  Uniform grid + shell search
+ *   with an exact stopping bound; no host synchronisation.                 */
 gs_status gs_knn(const float* pts, int64_t n, int32_t k, void* ws, size_t ws_bytes,
-                 int32_t* idx, float* dist, void* stream);
+                 int32_t* idx, float* dist, float* mean_dist, void* stream);
+
+/* Workspace for gs_plain_init on n points.                                 */
+size_t gs_plain_init_workspace_bytes(int64_t n);
+
+/* The plain initialisation of the Gaussians of n isosurface points (one
+ * Gaussian per extracted point, Sec. II "Isosurface Extraction"; shape from
+ * the 3D-GS default the paper trains with):
+ *   mean = pts, color [3][n] = sqrt(pi) normals (degree-0 colour (n+1)/2
+ *   for unit normals), and, when log_scale is not NULL:
+ *   log_scale [3][n] = log(max(d, 1e-6)) with d the mean distance to the 3
+ *   nearest other points (gs_knn), quat [4][n] = (1, 0, 0, 0),
+ *   opacity_logit [n] = log(opacity / (1 - opacity)), 0 < opacity < 1.
+ * With log_scale NULL only mean and colour are written (ws, quat and
+ * opacity_logit unused): the learned initialisation takes the shape from
+ * gs_mlp_apply.  pts, normals [3][n] device; outputs planar device arrays.
+ * ws: gs_plain_init_workspace_bytes(n), 256-byte aligned.                  */
+gs_status gs_plain_init(const float* pts, const float* normals, int64_t n, float opacity,
+                        void* ws, size_t ws_bytes, float* mean, float* log_scale, float* quat,
+                        float* opacity_logit, float* color, void* stream);
 
 /* gs_adam with the step count on the device, so that a captured HIP graph
  * can replay training steps unchanged: the kernels use t = step_dev[0] + 1

@@ -264,6 +264,29 @@ def loss(image, target, mask=None, lam=0.2):
     return dict(loss=L.value, l1=l1.value, ssim=ss.value, d_image=dI, ssim_map=smap)
 
 
+def masked_psnr(image, target, mask=None):
+    """Masked PSNR of one image [3,H,W] against its target, in dB (FP64).
+
+    The paper reports reconstruction quality as PSNR (Sec. III, Tables II,
+    V, VI) of images whose background is removed by a mask (Sec. II "Image
+    Rendering and Masking").  Reading taken here: the rendered image is
+    clamped to [0, 1] (the displayable range, peak value 1), the squared
+    error is averaged over the three channels of the masked pixels only,
+    and PSNR = 10 log10(1 / MSE).  An exact match gives +inf; an empty
+    mask leaves the value undefined (NaN) and such a view is left out of a
+    mean over views."""
+    img = np.clip(np.asarray(image, np.float64), 0.0, 1.0)
+    tgt = np.asarray(target, np.float64)
+    m = np.ones(img.shape[1:], bool) if mask is None else np.asarray(mask) != 0
+    count = 3 * int(m.sum())
+    if count == 0:
+        return float("nan")
+    se = float(((img - tgt) ** 2)[:, m].sum())
+    if se == 0.0:
+        return float("inf")
+    return 10.0 * np.log10(count / se)
+
+
 # --------------------------------------------------------------------------
 # Adam (dense, bias-corrected)
 # --------------------------------------------------------------------------

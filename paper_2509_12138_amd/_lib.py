@@ -120,7 +120,12 @@ SIGNATURES = {
     "gs_last_error": (C.c_char_p, []),
     "gs_version": (C.c_char_p, []),
     "gs_knn_workspace_bytes": (sz, [i64, i32]),
-    "gs_knn": (i32, [vp, i64, i32, vp, sz, vp, vp, vp]),
+    "gs_knn": (i32, [vp, i64, i32, vp, sz, vp, vp, vp, vp]),
+    "gs_plain_init_workspace_bytes": (sz, [i64]),
+    "gs_plain_init": (i32, [vp, vp, i64, f32, vp, sz, vp, vp, vp, vp, vp, vp]),
+    "gs_psnr_workspace_bytes": (sz, [i32, i32, i32]),
+    "gs_masked_psnr": (i32, [vp, vp, vp, i32, i32, i32, vp, sz, vp, vp]),
+    "gs_scale_rows": (i32, [vp, vp, i64, i64, vp]),
     "gs_mlp_features": (i32, [vp, vp, i64, vp, vp, vp, vp, vp]),
     "gs_mlp_fwd": (i32, [vp, i64, P(gs_mlp), vp, vp]),
     "gs_mlp_bwd_workspace_bytes": (sz, [i64]),

@@ -237,7 +237,8 @@ __global__ __launch_bounds__(kKnnThreads) void k_query(const float4* __restrict_
                                                        int k, const GridParams* __restrict__ P,
                                                        const uint32_t* __restrict__ start,
                                                        int32_t* __restrict__ idx,
-                                                       float* __restrict__ dist) {
+                                                       float* __restrict__ dist,
+                                                       float* __restrict__ mean_dist) {
   const int64_t s = (int64_t)blockIdx.x * kKnnThreads + threadIdx.x;
   if (s >= n) return;
   const GridParams G = *P;
@@ -290,12 +291,48 @@ __global__ __launch_bounds__(kKnnThreads) void k_query(const float4* __restrict_
     for (int t = 1; t < K; ++t) kth = (t == k - 1) ? bd[t] : kth;
     if (kth <= wall * wall * 0.9999f || wall == INFINITY) break;
   }
+  float dsum = 0.0f;
+  int found = 0;
 #pragma unroll
   for (int t = 0; t < K; ++t)
     if (t < k) {
-      idx[(int64_t)qi * k + t] = bi[t] == 0x7fffffff ? -1 : bi[t];
-      dist[(int64_t)qi * k + t] = sqrtf(bd[t]);
+      const float d = sqrtf(bd[t]);
+      if (idx) idx[(int64_t)qi * k + t] = bi[t] == 0x7fffffff ? -1 : bi[t];
+      if (dist) dist[(int64_t)qi * k + t] = d;
+      if (bi[t] != 0x7fffffff) {
+        dsum += d;
+        ++found;
+      }
     }
+  // mean over the neighbours found, in ascending order of distance
+  if (mean_dist) mean_dist[qi] = found ? dsum / (float)found : 0.0f;
+}
+
+// Plain initialisation of the Gaussians of surface points (one thread per
+// point): mean = point, colour coefficient sqrt(pi) n (so that the degree-0
+// colour max(0, C0 f + 1/2) is (n + 1)/2), and, when the k-NN mean distances
+// d are given, an isotropic log-scale log(max(d, 1e-6)), the identity
+// rotation and a fixed opacity logit.
+__global__ __launch_bounds__(kKnnThreads) void k_plain_init(
+    const float* __restrict__ pts, const float* __restrict__ nrm, int64_t n,
+    const float* __restrict__ d, float logit, float* __restrict__ mean,
+    float* __restrict__ log_scale, float* __restrict__ quat, float* __restrict__ opacity_logit,
+    float* __restrict__ color) {
+  const int64_t i = (int64_t)blockIdx.x * kKnnThreads + threadIdx.x;
+  if (i >= n) return;
+  const float kSqrtPi = 1.7724538509055160f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    mean[a * n + i] = pts[a * n + i];
+    color[a * n + i] = kSqrtPi * nrm[a * n + i];
+  }
+  if (!d) return;
+  const float ls = logf(fmaxf(d[i], 1e-6f));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) log_scale[a * n + i] = ls;
+  quat[i] = 1.0f;
+  quat[n + i] = quat[2 * n + i] = quat[3 * n + i] = 0.0f;
+  opacity_logit[i] = logit;
 }
 
 }  // namespace gsmi
@@ -311,12 +348,13 @@ size_t gs_knn_workspace_bytes(int64_t n, int32_t k) {
 }
 
 gs_status gs_knn(const float* pts, int64_t n, int32_t k, void* ws, size_t ws_bytes, int32_t* idx,
-                 float* dist, void* stream) {
+                 float* dist, float* mean_dist, void* stream) {
   clear_error();
   GS_REQUIRE(k >= 1 && k <= 32, "gs_knn: k=%d outside [1, 32]", k);
   GS_REQUIRE(n >= 0 && n < (int64_t(1) << 31), "gs_knn: n=%lld outside [0, 2^31)", (long long)n);
   if (n == 0) return GS_OK;
-  GS_REQUIRE(pts && ws && idx && dist, "gs_knn: NULL argument");
+  GS_REQUIRE(pts && ws, "gs_knn: NULL points or workspace");
+  GS_REQUIRE(idx || dist || mean_dist, "gs_knn: no output requested");
   const KnnLayout L = knn_layout(n);
   GS_REQUIRE(ws_bytes >= L.total, "gs_knn: workspace %zu < required %zu", ws_bytes, L.total);
   GS_REQUIRE(((uintptr_t)ws & 255) == 0, "gs_knn: workspace must be 256-byte aligned");
@@ -354,13 +392,49 @@ gs_status gs_knn(const float* pts, int64_t n, int32_t k, void* ws, size_t ws_byt
   GS_LAUNCH_CHECK("gs_knn/scatter");
 #define GS_KNN_Q(KK)                                                                        \
   hipLaunchKernelGGL(k_query<KK>, dim3(nb), dim3(kKnnThreads), 0, s, sorted, n, k, P, count, \
-                     idx, dist)
+                     idx, dist, mean_dist)
   if (k <= 4) GS_KNN_Q(4);
   else if (k <= 8) GS_KNN_Q(8);
   else if (k <= 16) GS_KNN_Q(16);
   else GS_KNN_Q(32);
 #undef GS_KNN_Q
   GS_LAUNCH_CHECK("gs_knn/query");
+  return GS_OK;
+}
+
+size_t gs_plain_init_workspace_bytes(int64_t n) {
+  if (n < 0) return 0;
+  return a256(knn_layout(n).total) + a256(sizeof(float) * (size_t)(n > 0 ? n : 1));
+}
+
+gs_status gs_plain_init(const float* pts, const float* normals, int64_t n, float opacity,
+                        void* ws, size_t ws_bytes, float* mean, float* log_scale, float* quat,
+                        float* opacity_logit, float* color, void* stream) {
+  clear_error();
+  GS_REQUIRE(n >= 0 && n < (int64_t(1) << 31), "gs_plain_init: n=%lld outside [0, 2^31)",
+             (long long)n);
+  if (n == 0) return GS_OK;
+  GS_REQUIRE(pts && normals && mean && color, "gs_plain_init: NULL points, normals, mean or colour");
+  const bool shape = log_scale != nullptr;
+  GS_REQUIRE(!shape || (quat && opacity_logit && ws),
+             "gs_plain_init: log_scale given without quat, opacity_logit or workspace");
+  GS_REQUIRE(!shape || (opacity > 0.f && opacity < 1.f), "gs_plain_init: opacity %f outside (0, 1)",
+             (double)opacity);
+  float* d = nullptr;
+  if (shape) {
+    const size_t need = gs_plain_init_workspace_bytes(n);
+    GS_REQUIRE(ws_bytes >= need, "gs_plain_init: workspace %zu < required %zu", ws_bytes, need);
+    GS_REQUIRE(((uintptr_t)ws & 255) == 0, "gs_plain_init: workspace must be 256-byte aligned");
+    const size_t off = a256(knn_layout(n).total);
+    d = (float*)((char*)ws + off);
+    gs_status st = gs_knn(pts, n, 3, ws, off, nullptr, nullptr, d, stream);
+    if (st != GS_OK) return st;
+  }
+  const float logit = shape ? logf(opacity / (1.0f - opacity)) : 0.0f;
+  hipLaunchKernelGGL(k_plain_init, dim3((unsigned)ceil_div(n, kKnnThreads)), dim3(kKnnThreads), 0,
+                     as_stream(stream), pts, normals, n, d, logit, mean, log_scale, quat,
+                     opacity_logit, color);
+  GS_LAUNCH_CHECK("gs_plain_init");
   return GS_OK;
 }
 

@@ -372,6 +372,101 @@ __global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ pa
   }
 }
 
+// ------------------------------------------------------------ masked PSNR
+
+// Evaluation metric of the trainers (the paper judges reconstructions by
+// PSNR, Sec. III; the background mask restricts it to the object):
+// per image, se = sum over pixels of m sum_c (clamp(I, 0, 1) - G)^2 and
+// cnt = 3 sum m, accumulated in FP64 per thread, per work-group in a fixed
+// tree order, then over the work-groups of an image in a fixed order.
+constexpr int kPsnrThreads = 256;
+constexpr int64_t kPsnrMaxBlocks = 256;     // work-groups per image
+
+static int64_t psnr_blocks(int64_t HW) {
+  const int64_t b = ceil_div(HW, (int64_t)kPsnrThreads * 16);
+  return b < 1 ? 1 : (b > kPsnrMaxBlocks ? kPsnrMaxBlocks : b);
+}
+
+__device__ __forceinline__ void block_sum2(double& a, double& b, double (*sm)[kPsnrThreads]) {
+  const int t = threadIdx.x;
+  sm[0][t] = a;
+  sm[1][t] = b;
+  __syncthreads();
+  for (int d = kPsnrThreads / 2; d > 0; d >>= 1) {
+    if (t < d) {
+      sm[0][t] += sm[0][t + d];
+      sm[1][t] += sm[1][t + d];
+    }
+    __syncthreads();
+  }
+  a = sm[0][0];
+  b = sm[1][0];
+}
+
+__global__ __launch_bounds__(kPsnrThreads) void k_psnr_partial(
+    const float* __restrict__ image, const float* __restrict__ target,
+    const uint8_t* __restrict__ mask, int64_t HW, int64_t blocks_per_img,
+    double* __restrict__ part) {
+  __shared__ double sm[2][kPsnrThreads];
+  const int64_t img = blockIdx.x / blocks_per_img, b = blockIdx.x - img * blocks_per_img;
+  const float* I = image + img * 3 * HW;
+  const float* G = target + img * 3 * HW;
+  const uint8_t* M = mask ? mask + img * HW : nullptr;
+  double se = 0.0, cnt = 0.0;
+  for (int64_t p = b * kPsnrThreads + threadIdx.x; p < HW; p += blocks_per_img * kPsnrThreads) {
+    if (M && M[p] == 0) continue;
+    double e = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double d = (double)fminf(fmaxf(I[c * HW + p], 0.0f), 1.0f) - (double)G[c * HW + p];
+      e = fma(d, d, e);
+    }
+    se += e;
+    cnt += 3.0;
+  }
+  block_sum2(se, cnt, sm);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = se;
+    part[2 * blockIdx.x + 1] = cnt;
+  }
+}
+
+__global__ __launch_bounds__(kPsnrThreads) void k_psnr_final(const double* __restrict__ part,
+                                                             int64_t blocks_per_img,
+                                                             float* __restrict__ psnr) {
+  __shared__ double sm[2][kPsnrThreads];
+  const int64_t img = blockIdx.x;
+  double se = 0.0, cnt = 0.0;
+  for (int64_t b = threadIdx.x; b < blocks_per_img; b += kPsnrThreads) {
+    se += part[2 * (img * blocks_per_img + b)];
+    cnt += part[2 * (img * blocks_per_img + b) + 1];
+  }
+  block_sum2(se, cnt, sm);
+  if (threadIdx.x == 0) {
+    float r;
+    if (cnt == 0.0) r = __builtin_nanf("");
+    else if (se == 0.0) r = INFINITY;
+    else r = (float)(10.0 * log10(cnt / se));
+    psnr[img] = r;
+  }
+}
+
+// x[r][i] *= scale[r] for r < rows, i < row_len (the chain rule of a loss
+// through an upstream gradient per image).
+__global__ __launch_bounds__(256) void k_scale_rows(float* __restrict__ x,
+                                                    const float* __restrict__ scale, int64_t rows,
+                                                    int64_t row_len) {
+  const int64_t total = rows * row_len;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256)
+    x[i] *= scale[i / row_len];
+}
+
+static gs_status launch_loss(const float* image, const float* target, const uint8_t* mask,
+                             int32_t S, int32_t H, int32_t W, float lambda_dssim,
+                             float grad_scale, float* part, float* loss_out, float* d_image,
+                             int64_t* status, void* stream);
+
 }  // namespace gsmi
 
 using namespace gsmi;
@@ -395,7 +490,19 @@ gs_status gs_loss(const float* image, const float* target, const uint8_t* mask, 
   LossLayout L = loss_layout(S, H, W);
   GS_REQUIRE(ws_bytes >= L.total, "gs_loss: workspace %zu < required %zu", ws_bytes, L.total);
   GS_REQUIRE(((uintptr_t)ws & 255) == 0, "gs_loss: workspace must be 256-byte aligned");
-  float* part = (float*)((char*)ws + L.off_part);
+  return launch_loss(image, target, mask, S, H, W, lambda_dssim, grad_scale,
+                     (float*)((char*)ws + L.off_part), loss_out, d_image, status, stream);
+}
+
+}  // extern "C"
+
+namespace gsmi {
+
+static gs_status launch_loss(const float* image, const float* target, const uint8_t* mask,
+                             int32_t S, int32_t H, int32_t W, float lambda_dssim,
+                             float grad_scale, float* part, float* loss_out, float* d_image,
+                             int64_t* status, void* stream) {
+  const LossLayout L = loss_layout(S, H, W);
   const Window win = ssim_window();
   const int64_t blocks = (int64_t)S * 3 * L.blocks_per_img;
   hipStream_t s = as_stream(stream);
@@ -414,6 +521,52 @@ gs_status gs_loss(const float* image, const float* target, const uint8_t* mask, 
   hipLaunchKernelGGL(k_loss_final, dim3((unsigned)S), dim3(256), 0, s, part, L.blocks_per_img,
                      1.0 / N, lambda_dssim, loss_out, status);
   GS_LAUNCH_CHECK("gs_loss/final");
+  return GS_OK;
+}
+
+}  // namespace gsmi
+
+extern "C" {
+
+size_t gs_psnr_workspace_bytes(int32_t S, int32_t H, int32_t W) {
+  if (S < 0 || H < 0 || W < 0) return 0;
+  const size_t b = (size_t)psnr_blocks((int64_t)H * W);
+  return ((sizeof(double) * 2 * b * (size_t)(S > 0 ? S : 1)) + 255) & ~size_t(255);
+}
+
+gs_status gs_masked_psnr(const float* image, const float* target, const uint8_t* mask, int32_t S,
+                         int32_t H, int32_t W, void* ws, size_t ws_bytes, float* psnr_out,
+                         void* stream) {
+  clear_error();
+  GS_REQUIRE(S >= 1 && H >= 1 && W >= 1, "gs_masked_psnr: bad shape S=%d H=%d W=%d", S, H, W);
+  GS_REQUIRE(image && target && ws && psnr_out, "gs_masked_psnr: NULL argument");
+  const size_t need = gs_psnr_workspace_bytes(S, H, W);
+  GS_REQUIRE(ws_bytes >= need, "gs_masked_psnr: workspace %zu < required %zu", ws_bytes, need);
+  GS_REQUIRE(((uintptr_t)ws & 7) == 0, "gs_masked_psnr: workspace must be 8-byte aligned");
+  const int64_t HW = (int64_t)H * W;
+  const int64_t B = psnr_blocks(HW);
+  hipStream_t s = as_stream(stream);
+  hipLaunchKernelGGL(k_psnr_partial, dim3((unsigned)(B * S)), dim3(kPsnrThreads), 0, s, image,
+                     target, mask, HW, B, (double*)ws);
+  GS_LAUNCH_CHECK("gs_masked_psnr/partial");
+  hipLaunchKernelGGL(k_psnr_final, dim3((unsigned)S), dim3(kPsnrThreads), 0, s,
+                     (const double*)ws, B, psnr_out);
+  GS_LAUNCH_CHECK("gs_masked_psnr/final");
+  return GS_OK;
+}
+
+gs_status gs_scale_rows(float* x, const float* scale, int64_t rows, int64_t row_len,
+                        void* stream) {
+  clear_error();
+  GS_REQUIRE(rows >= 0 && row_len >= 0, "gs_scale_rows: negative size");
+  if (rows == 0 || row_len == 0) return GS_OK;
+  GS_REQUIRE(x && scale, "gs_scale_rows: NULL argument");
+  int64_t blocks = ceil_div(rows * row_len, 256);
+  const int64_t cap = (int64_t)device_cu_count() * 16;
+  if (blocks > cap) blocks = cap;
+  hipLaunchKernelGGL(k_scale_rows, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), x,
+                     scale, rows, row_len);
+  GS_LAUNCH_CHECK("gs_scale_rows");
   return GS_OK;
 }
 

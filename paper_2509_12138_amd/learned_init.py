@@ -148,15 +148,7 @@ def plain_init(points, normals, opacity=PLAIN_OPACITY):
     """The plain k-NN initialisation on the device: isotropic scale = mean
     distance to the 3 nearest neighbours, identity rotation, fixed opacity,
     colour from the normal."""
-    n = points.shape[1]
-    d = ops.knn_mean_distance(points, 3).clamp_min(1e-6)
-    dev = points.device
-    quat = torch.zeros((4, n), dtype=torch.float32, device=dev)
-    quat[0] = 1.0
-    return dict(mean=points.clone(), log_scale=d.log().expand(3, n).contiguous(), quat=quat,
-                opacity_logit=torch.full((n,), math.log(opacity / (1 - opacity)),
-                                         dtype=torch.float32, device=dev),
-                color=(normals * SQRT_PI).contiguous())
+    return ops.plain_init(points.contiguous(), normals.contiguous(), opacity)
 
 
 def learned_params(mlp, points, normals, x=None, dbar=None):
@@ -167,7 +159,8 @@ def learned_params(mlp, points, normals, x=None, dbar=None):
     if not bool(torch.isfinite(y).all()):
         return None
     g = apply(y, normals, dbar)
-    g.update(mean=points.clone(), color=(normals * SQRT_PI).contiguous())
+    mc = ops.plain_init(points.contiguous(), normals.contiguous(), PLAIN_OPACITY, shape=False)
+    g.update(mean=mc["mean"], color=mc["color"])
     return {k: g[k].contiguous() for k in ops.PARAM_NAMES}
 
 

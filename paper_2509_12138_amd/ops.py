@@ -157,12 +157,22 @@ class RasterBuffers:
         self.chunk = 0
         self.fwd_waves = 1
         self.dup_capacity = 0
+        # bumped whenever a buffer that launches point at is reallocated, so
+        # that holders of captured graphs know to re-capture them
+        self.generation = 0
+        # a failure status read (and cleared) by render_checked before a
+        # trainer's own check saw it
+        self._pending = None
         self.ensure_capacity(dup_capacity or max(4 * m, 1024))
 
     def ensure_capacity(self, cap):
+        """Grow the duplicate buffers to at least cap entries; returns True
+        if they were reallocated (graphs holding the old pointers are then
+        stale: ``generation`` changes)."""
         cap = int(min(max(cap, 1024), 0xFFFFFFFF))
         if cap <= self.dup_capacity:
-            return
+            return False
+        self.generation += 1
         dev = self.views.device
         self.dup_capacity = cap
         self.keys = torch.empty(cap, dtype=torch.int64, device=dev)
@@ -175,6 +185,7 @@ class RasterBuffers:
             self._alloc_chunks()
         if self.deterministic:
             self._alloc_dup_grads()
+        return True
 
     # ---------------------------------------------------------- the calls
 
@@ -310,18 +321,35 @@ class RasterBuffers:
         s = stream or stream_handle()
         call("gs_zero", _ptr(self.d_rec), self.d_rec.numel() * 4, s)
 
-    def check(self, stream=None):
-        """Synchronise and report (status, required duplicates)."""
+    def _read_status(self, stream=None):
         s = stream or stream_handle()
         req = C.c_int64(0)
         st = _lib.load().gs_check_status(_ptr(self.status), s, C.byref(req))
         return st, int(req.value)
 
+    def check(self, stream=None):
+        """Synchronise and report (status, required duplicates), including a
+        failure that render_checked read before this call."""
+        st, req = self._read_status(stream)
+        if self._pending is not None:
+            pst, preq = self._pending
+            self._pending = None
+            if st == _lib.GS_OK or st == pst:
+                st, req = pst, max(req, preq)
+        return st, req
+
     def clear_status(self, stream=None):
         call("gs_zero", _ptr(self.status), self.status.numel() * 8, stream or stream_handle())
 
     def render_checked(self, gstruct, bg=(0.0, 0.0, 0.0), max_retry=3):
-        """project + bin_sort (+ capacity growth on overflow) + raster_fwd."""
+        """project + bin_sort (+ capacity growth on overflow) + raster_fwd.
+        A failure flagged by earlier asynchronous steps is kept for the next
+        check() before the status is cleared."""
+        st, req = self._read_status()
+        if st != _lib.GS_OK:
+            if self._pending is not None and self._pending[0] == st:
+                req = max(req, self._pending[1])
+            self._pending = (st, req)
         for _ in range(max_retry + 1):
             self.clear_status()
             self.project(gstruct)
@@ -462,33 +490,103 @@ class LossFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, d_loss):
         (d_image,) = ctx.saved_tensors
-        return d_image * d_loss.view(-1, 1, 1, 1), None, None, None, None
+        out = d_image.clone()
+        S = out.shape[0]
+        call("gs_scale_rows", _ptr(out), _ptr(d_loss.contiguous().float()), S,
+             out.numel() // max(S, 1), stream_handle())
+        return out, None, None, None, None
+
+
+class PsnrBuffers:
+    """Workspace and output of gs_masked_psnr for S images of H x W."""
+
+    def __init__(self, S, H, W, device="cuda"):
+        self.S, self.H, self.W = S, H, W
+        nbytes = _lib.load().gs_psnr_workspace_bytes(S, H, W)
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        self.psnr = torch.empty(S, dtype=torch.float32, device=device)
+
+    def __call__(self, image, target, mask=None, out=None, stream=None):
+        """Masked PSNR of each image (device [S] tensor; `out` may be a
+        slice of a longer device array to write into)."""
+        _check_f32(image, "image"); _check_f32(target, "target")
+        if mask is not None and (mask.dtype != torch.uint8 or not mask.is_contiguous()):
+            raise ValueError("mask must be a contiguous uint8 tensor")
+        dst = self.psnr if out is None else out
+        if dst.dtype != torch.float32 or dst.numel() < self.S or not dst.is_contiguous():
+            raise ValueError("psnr output must be a contiguous float32 tensor of S entries")
+        call("gs_masked_psnr", _ptr(image), _ptr(target), _ptr(mask), self.S, self.H, self.W,
+             _ptr(self.ws), self.ws.numel(), _ptr(dst), stream or stream_handle())
+        return dst
+
+
+def masked_psnr(image, target, mask=None):
+    """Masked PSNR of a stack of images [S, 3, H, W] (gs_masked_psnr):
+    device tensor [S]; NaN for an empty mask, +inf for an exact match."""
+    if image.dim() == 3:
+        image, target = image.unsqueeze(0), target.unsqueeze(0)
+        mask = mask.unsqueeze(0) if mask is not None else None
+    S, _, H, W = image.shape
+    return PsnrBuffers(S, H, W, image.device)(image.contiguous(), target.contiguous(),
+                                              mask.contiguous() if mask is not None else None)
 
 
 # --------------------------------------------------------------------------
 # k nearest neighbours
 # --------------------------------------------------------------------------
 
-def knn(points, k):
+def knn(points, k, with_mean=False):
     """Exact k-NN of device points [3, n] (gs_knn); returns (idx [n,k] int32,
-    dist [n,k] float32) sorted by (distance, index)."""
+    dist [n,k] float32) sorted by (distance, index), and with_mean also the
+    mean distance [n]."""
     _check_f32(points, "points")
     n = points.shape[1]
     idx = torch.empty((n, k), dtype=torch.int32, device=points.device)
     dist = torch.empty((n, k), dtype=torch.float32, device=points.device)
-    if n == 0:
-        return idx, dist
-    nbytes = _lib.load().gs_knn_workspace_bytes(n, k)
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=points.device)
-    call("gs_knn", _ptr(points), n, int(k), _ptr(ws), nbytes, _ptr(idx), _ptr(dist),
-         stream_handle())
-    return idx, dist
+    mean = torch.empty(n, dtype=torch.float32, device=points.device) if with_mean else None
+    if n > 0:
+        nbytes = _lib.load().gs_knn_workspace_bytes(n, k)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=points.device)
+        call("gs_knn", _ptr(points), n, int(k), _ptr(ws), nbytes, _ptr(idx), _ptr(dist),
+             _ptr(mean), stream_handle())
+    return (idx, dist, mean) if with_mean else (idx, dist)
 
 
 def knn_mean_distance(points, k=3):
-    """Mean distance to the k nearest neighbours of each device point."""
-    _, d = knn(points, k)
-    return d.mean(dim=1)
+    """Mean distance to the k nearest neighbours of each device point
+    (computed by gs_knn; the neighbour lists are not written)."""
+    _check_f32(points, "points")
+    n = points.shape[1]
+    mean = torch.empty(n, dtype=torch.float32, device=points.device)
+    if n > 0:
+        nbytes = _lib.load().gs_knn_workspace_bytes(n, k)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=points.device)
+        call("gs_knn", _ptr(points), n, int(k), _ptr(ws), nbytes, None, None, _ptr(mean),
+             stream_handle())
+    return mean
+
+
+def plain_init(points, normals, opacity, shape=True):
+    """gs_plain_init: Gaussians of device surface points [3, n] with unit
+    normals [3, n]; shape=False writes only mean and colour (the other
+    arrays are returned uninitialised)."""
+    _check_f32(points, "points"); _check_f32(normals, "normals")
+    n = points.shape[1]
+    dev = points.device
+    out = dict(mean=torch.empty((3, n), dtype=torch.float32, device=dev),
+               log_scale=torch.empty((3, n), dtype=torch.float32, device=dev),
+               quat=torch.empty((4, n), dtype=torch.float32, device=dev),
+               opacity_logit=torch.empty(n, dtype=torch.float32, device=dev),
+               color=torch.empty((3, n), dtype=torch.float32, device=dev))
+    if n == 0:
+        return out
+    nbytes = _lib.load().gs_plain_init_workspace_bytes(n) if shape else 0
+    ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+    call("gs_plain_init", _ptr(points), _ptr(normals), n, float(opacity), _ptr(ws), nbytes,
+         _ptr(out["mean"]), _ptr(out["log_scale"]) if shape else None,
+         _ptr(out["quat"]) if shape else None, _ptr(out["opacity_logit"]) if shape else None,
+         _ptr(out["color"]), stream_handle())
+    return out
 
 
 # --------------------------------------------------------------------------

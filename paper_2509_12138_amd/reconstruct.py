@@ -32,14 +32,16 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import sys
 import time
 
 import numpy as np
 import torch
 
-from . import scene, workloads
+from . import ops, scene, workloads
 from . import ttt
+from .train import mean_over_views
 
 WHITE = (1.0, 1.0, 1.0)
 BLACK = (0.0, 0.0, 0.0)
@@ -85,23 +87,25 @@ def render_views(params, cams, bg, tile=(16, 16), device="cuda"):
         yield v, bufs.image[0], bufs.T_final[0]
 
 
-def _psnr(se, cnt):
-    return float(10.0 * torch.log10(cnt / se.clamp_min(1e-20))) if cnt > 0 else None
-
-
 def evaluate(model, cams, glob, band):
-    """PSNR of a merged model against the global reference renders over the
-    foreground, the seam band and the background (clamped images)."""
-    acc = {k: [torch.zeros((), dtype=torch.float64, device="cuda"), 0.0]
-           for k in ("foreground", "seam", "background")}
+    """Masked PSNR (gs_masked_psnr, clamped images) of a merged model against
+    the global reference renders over three regions of every view: the
+    foreground, the seam band and the background; each region's value is the
+    mean over the views in which it is not empty."""
+    W, H = int(cams[0]["width"]), int(cams[0]["height"])
+    psnr = ops.PsnrBuffers(1, H, W)
+    vals = {k: [] for k in ("foreground", "seam", "background")}
     for v, img, _ in render_views(model, cams, WHITE):
-        se = ((img.clamp(0, 1) - glob["targets"][v]) ** 2).sum(0).double()
-        regions = dict(foreground=glob["masks"][v].bool(), seam=glob["seam"][v],
-                       background=~glob["masks"][v].bool())
+        fg = glob["masks"][v:v + 1].contiguous()
+        regions = dict(foreground=fg, seam=glob["seam"][v:v + 1].to(torch.uint8).contiguous(),
+                       background=(fg == 0).to(torch.uint8))
         for k, m in regions.items():
-            acc[k][0] += se[m].sum()
-            acc[k][1] += 3.0 * float(m.sum())
-    return {k: _psnr(s, c) for k, (s, c) in acc.items()}
+            vals[k].append(float(psnr(img.unsqueeze(0), glob["targets"][v:v + 1], m)[0]))
+    out = {}
+    for k, vs in vals.items():
+        r = mean_over_views(vs)
+        out[k] = None if math.isnan(r) else r
+    return out
 
 
 def global_reference(n_ref, cams, band, seed=977):

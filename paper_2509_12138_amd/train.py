@@ -55,12 +55,12 @@ def mean_lr(step, extent, lr0=1.6e-4, lr1=1.6e-6, total=30000):
     return extent * math.exp(math.log(lr0) * (1 - t) + math.log(lr1) * t)
 
 
-def masked_psnr(image, target, mask):
-    """10 log10(1/MSE) over masked pixels of clamped images (evaluation only)."""
-    m = mask.to(image.dtype).unsqueeze(-3)
-    se = ((image.clamp(0, 1) - target) ** 2 * m).sum(dim=(-3, -2, -1))
-    cnt = 3.0 * m.sum(dim=(-3, -2, -1)).clamp_min(1.0)
-    return 10.0 * torch.log10(1.0 / (se / cnt).clamp_min(1e-20))
+def mean_over_views(psnr):
+    """Mean of per-view masked PSNRs (host array); views with an empty mask
+    (NaN) are left out."""
+    v = np.asarray(psnr, np.float64)
+    v = v[~np.isnan(v)]
+    return float(v.mean()) if v.size else float("nan")
 
 
 class PlainTrainer:
@@ -245,14 +245,19 @@ class PlainTrainer:
         return req
 
     def evaluate(self, views=None):
-        """Mean masked PSNR over views (renders each; evaluation only)."""
-        views = range(self.V) if views is None else views
-        ps = []
-        for vi in views:
+        """Mean masked PSNR over views (gs_masked_psnr of each rendered view;
+        evaluation only, views with an empty mask left out)."""
+        views = list(range(self.V) if views is None else views)
+        if getattr(self, "_psnr", None) is None:
+            self._psnr = ops.PsnrBuffers(1, self.H, self.W, self.device)
+            self._psnr_views = torch.empty(self.V, dtype=torch.float32, device=self.device)
+        for i, vi in enumerate(views):
             self.views.use_cameras(self.cams[vi:vi + 1])
             self.bufs.render_checked(self.gst, self.bg)
-            ps.append(masked_psnr(self.bufs.image[0], self.targets[vi], self.masks[vi]))
-        return float(torch.stack(ps).mean())
+            self._psnr(self.bufs.image, self.targets[vi:vi + 1],
+                       self.masks[vi:vi + 1] if self.masks is not None else None,
+                       out=self._psnr_views[i:i + 1])
+        return mean_over_views(self._psnr_views[:len(views)].cpu().numpy())
 
     def train(self, steps, order_seed=0, eval_every=0, target_psnr=None, check_every=50,
               log=None, grow=False):
@@ -371,6 +376,7 @@ class BatchedTrainer:
         self.fused_adam = fused_adam
         self.use_graphs = graphs
         self.graphs = {}
+        self._graph_gen = self.bufs.generation
         self._warm = set()
         self.steps_done = 0
         self._graph_stats = self._stats_on()    # whether the step body gathers statistics
@@ -402,6 +408,7 @@ class BatchedTrainer:
             else:
                 self.densifier.resize(self.n)
         self.graphs = {}
+        self._graph_gen = self.bufs.generation
 
     def _stats_on(self):
         c = self.density
@@ -439,6 +446,7 @@ class BatchedTrainer:
             need = max(need, self.bufs.render_checked(self.gst, self.bg))
         self.bufs.ensure_capacity(int(need * margin) + 4096)
         self.graphs = {}
+        self._graph_gen = self.bufs.generation
         return need
 
     def _step_body(self, g):
@@ -459,8 +467,16 @@ class BatchedTrainer:
             b.project_bwd(self.gst, self.grst)
             self.adam(zero_grad=True)
 
+    def _drop_stale_graphs(self):
+        """Captured graphs hold the buffers' pointers: drop them when a
+        buffer was reallocated (capacity growth, e.g. inside evaluate)."""
+        if self.bufs.generation != self._graph_gen:
+            self.graphs = {}
+            self._graph_gen = self.bufs.generation
+
     def step(self, g):
         """One batched step on view group g (graph replay after the first)."""
+        self._drop_stale_graphs()
         if (self.active_sh < self.sh_degree and self.steps_done > 0 and self.sh_up_every > 0
                 and self.steps_done % self.sh_up_every == 0):
             # the degree is a kernel argument baked into the captured graphs
@@ -507,6 +523,7 @@ class BatchedTrainer:
         captured (capturing does not run it)."""
         if not self.use_graphs:
             return
+        self._drop_stale_graphs()
         saved = [t.clone() for d in (self.params, self.m, self.v) for t in d.values()]
         step0 = self.adam.step_dev.clone()
         self._step_body(0)
@@ -530,16 +547,19 @@ class BatchedTrainer:
         torch.cuda.synchronize()
 
     def evaluate(self):
-        """Masked PSNR per partition (mean over its views); evaluation only."""
-        ps = torch.zeros((self.P, self.V), device=self.device)
+        """Masked PSNR per partition (gs_masked_psnr of every slot, mean over
+        the partition's views); evaluation only."""
+        if getattr(self, "_psnr", None) is None:
+            self._psnr = ops.PsnrBuffers(self.S, self.H, self.W, self.device)
+        ps = np.zeros((self.P, self.V))
         for g in range(self.G):
             self.views.use_cameras(self.cams_g[g])
             self.bufs.render_checked(self.gst, self.bg)
-            pv = masked_psnr(self.bufs.image, self.targets_g[g], self.masks_g[g])
+            pv = self._psnr(self.bufs.image, self.targets_g[g], self.masks_g[g]).cpu().numpy()
             for p in range(self.P):
                 for j in range(self.vpp):
                     ps[p, self.group_views[g][j]] = pv[p * self.vpp + j]
-        return ps.mean(dim=1).cpu().numpy()
+        return np.array([mean_over_views(ps[p]) for p in range(self.P)])
 
     def partition_params(self, p):
         o = sum(self.counts[:p])

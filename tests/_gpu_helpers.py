@@ -27,13 +27,14 @@ def rec_to_oracle(rec, tile_bbox, n_tiles):
                 tile_bbox=np.ascontiguousarray(tb.T), valid=(np.asarray(n_tiles) > 0).astype(np.int32))
 
 
-def grad_tolerance_check(g, r, term_mass, amb_mass, rel=1e-3, floor=0.1):
+def grad_tolerance_check(g, r, term_mass, amb_mass, rel=1e-3, floor=0.01):
     """|g - r| <= rel * max(|r|, floor * A) + A_amb per element, where A is the
-    oracle's term mass (sum over pixels of the magnitudes of the terms before
-    they cancel) and A_amb the contribution of ambiguous pixels.  The floor
-    1e-4 A is the FP32 evaluation error of such sums when the transmittance
-    is recovered over blend chains of a few hundred entries (about 1.5 ulp
-    per entry); returns (ok, worst ratio)."""
+    oracle's term mass (sum over pixels of the magnitudes of the terms of
+    dL/dalpha before they cancel) and A_amb the contribution of ambiguous
+    pixels.  The floor is relative to the terms, not to the cancelled
+    result: an exact FP32 replay of the kernels' transmittance recovery and
+    accumulation (test_fp32_gradient_bound) uses about a tenth of this bound
+    and breaks one relative to the result; returns (ok, worst ratio)."""
     bound = rel * np.maximum(np.abs(r), floor * term_mass) + amb_mass + 1e-12
     ratio = np.abs(g - r) / bound
     worst = float(ratio.max(initial=0.0))
@@ -43,6 +44,15 @@ def grad_tolerance_check(g, r, term_mass, amb_mass, rel=1e-3, floor=0.1):
                                    term_mass=float(term_mass[i]), amb_mass=float(amb_mass[i]),
                                    n_bad=int((ratio > 1).sum())))
     return True, worst
+
+
+def masked_image_gradient(rng, H, W, S=2):
+    """Seeded image gradient that is exactly zero where a loss mask would
+    cut it: on 30% of the pixels and on a solid block (whole tiles)."""
+    dI = rng.normal(size=(S, 3, H, W)).astype(np.float32)
+    zero = rng.uniform(size=(S, 1, H, W)) < 0.3
+    zero[:, :, H // 8:H // 2, W // 6:W // 2] = True
+    return np.where(zero, np.float32(0), dI)
 
 
 def surface_scene(n, seed, opacity=0.1):

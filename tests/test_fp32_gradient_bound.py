@@ -1,0 +1,243 @@
+"""What FP32 arithmetic can promise for the rasteriser's gradients (no GPU).
+
+The reverse replay of the compositing recovers each blend's transmittance
+from the pixel's final one, T_k = T_{k+1} / (1 - alpha_k), and forms
+dL/dalpha_k = T_k (dI . c_k) - (dI . colour behind k) / (1 - alpha_k): a
+difference of two terms that cancel where a Gaussian's colour matches what
+lies behind it.  Each division and each accumulation adds a rounding of
+about 2^-24 relative to the *terms*, so over blend chains of a few hundred
+entries the absolute error of such an element grows like (entries x 2^-24)
+times the sum of its term magnitudes, however small the result.
+
+This module replays that arithmetic exactly as the kernels order it, in
+numpy float32, on the scene of the chunked-backward parity test (20,000
+perturbed surface Gaussians, 112x80, two views, a masked image gradient): the
+stored form (division from the final transmittance through the whole list)
+and the chunked form (per-64-entry checkpoints of the transmittance and of
+the normalised colour behind, built by the recursion
+U_c = L_{c+1} + P_{c+1} U_{c+1}).  Against the FP64 oracle it shows
+* that the bound the GPU tests use, |g - r| <= 1e-3 max(|r|, 0.01 A) + A_amb
+  with A the oracle's term mass, holds for a correct FP32 evaluation with a
+  margin (about a tenth of the bound is used);
+* that a bound relative to the cancelled result, 1e-3 max(|r|, 0.01 |c|_1)
+  (|c|_1 = sum over pixels of |contribution|), is broken by the same correct
+  FP32 evaluation, so no FP32 kernel could be held to it;
+* that the term-mass bound still catches plausible mistakes (a dropped
+  background term, the transmittance behind instead of in front of a blend,
+  a lost opacity factor).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_12138_amd import scene
+from _gpu_helpers import masked_image_gradient, oracle_records, perturbed, surface_scene
+
+f32 = np.float32
+LOG2E = f32(1.4426950408889634)
+LN2 = f32(0.6931471805599453)
+SAME_RECORD_BITS = 1 | 2 | 4 | 8
+TILE = 16
+W, H = 112, 80
+BG = (0.05, 0.1, 0.2)
+
+
+def fma(a, b, c):
+    """Fused multiply-add rounded once to FP32 (the product of two floats is
+    exact in FP64)."""
+    return (np.asarray(a, np.float64) * np.asarray(b, np.float64)
+            + np.asarray(c, np.float64)).astype(f32)
+
+
+class Splats:
+    """The records of one view as the rasterisers stage them: mean, the
+    log2-scaled conic (A, B, C), opacity, colour, skip threshold."""
+
+    def __init__(self, rec):
+        rec = np.asarray(rec, f32)
+        self.mx, self.my = rec[:, 0], rec[:, 1]
+        self.A = f32(-0.5) * LOG2E * rec[:, 2]
+        self.B = -LOG2E * rec[:, 3]
+        self.C = f32(-0.5) * LOG2E * rec[:, 4]
+        self.o = rec[:, 5]
+        self.rgb = rec[:, 6:9]
+        with np.errstate(divide="ignore"):
+            self.thr = -np.log2(f32(255.0) * self.o).astype(f32)
+
+    def p2(self, g, fx, fy):
+        dx = (fx - self.mx[g]).astype(f32)
+        dy = (fy - self.my[g]).astype(f32)
+        adx2 = (self.A[g] * dx).astype(f32) * dx
+        bdx = (self.B[g] * dx).astype(f32)
+        return fma(dy, fma(self.C[g], dy, bdx), adx2), dx, dy
+
+
+def tile_pixels(t, tiles_x):
+    ty, tx = divmod(t, tiles_x)
+    yy, xx = np.divmod(np.arange(TILE * TILE), TILE)
+    px, py = tx * TILE + xx, ty * TILE + yy
+    inside = (px < W) & (py < H)
+    return px, py, inside
+
+
+def emulate(rec, ids, ranges, dI, chunk=0, mistake=None):
+    """FP32 replay of forward + reverse pass over every tile of one view;
+    returns d_rec [m, 9] in FP64 (the per-pair sums are FP32)."""
+    sp = Splats(rec)
+    m = rec.shape[0]
+    d_rec = np.zeros((m, 9), f32)
+    tiles_x = math.ceil(W / TILE)
+    scale = np.array([-LN2, -LN2, -0.5, -1.0, -0.5, 1, 1, 1, 1], f32)
+    bg = np.array(BG, f32)
+    for t in range(ranges.shape[0]):
+        start, end = int(ranges[t, 0]), int(ranges[t, 1])
+        if start >= end:
+            continue
+        lst = ids[start:end].astype(np.int64)
+        px, py, inside = tile_pixels(t, tiles_x)
+        fx, fy = (px + 0.5).astype(f32), (py + 0.5).astype(f32)
+        npx = len(px)
+        # ---- forward (with the chunk checkpoints when chunked)
+        T = np.ones(npx, f32)
+        alive = inside.copy()
+        last = np.zeros(npx, np.int64)
+        Tl = np.ones(npx, f32)
+        Lc = np.zeros((npx, 3), f32)
+        ck = {}
+        for j, g in enumerate(lst):
+            p2, _, _ = sp.p2(g, fx, fy)
+            ok = alive & (p2 <= 0) & (p2 >= sp.thr[g])
+            alpha = np.minimum(f32(0.99), (sp.o[g] * np.exp2(p2).astype(f32)).astype(f32))
+            Tn = (T * (f32(1) - alpha)).astype(f32)
+            stop = ok & (Tn < f32(1e-4))
+            alive &= ~stop
+            blend = ok & ~stop
+            if chunk:
+                wl = (alpha * Tl).astype(f32)
+                for c in range(3):
+                    Lc[:, c] = np.where(blend, fma(sp.rgb[g, c], wl, Lc[:, c]), Lc[:, c])
+                Tl = np.where(blend, (Tl * (f32(1) - alpha)).astype(f32), Tl)
+            T = np.where(blend, Tn, T)
+            last = np.where(blend, j + 1, last)
+            if chunk and (j + 1) % chunk == 0:
+                ck[(j + 1) // chunk - 1] = (Tl.copy(), Lc.copy())
+                Tl = np.ones(npx, f32)
+                Lc = np.zeros((npx, 3), f32)
+        if chunk:
+            n_ch = (len(lst) + chunk - 1) // chunk
+            if len(lst) % chunk:
+                ck[n_ch - 1] = (Tl.copy(), Lc.copy())
+            # checkpoint c: transmittance and normalised colour behind the
+            # end of chunk c, from the chunk-local (P, L) of chunk c + 1
+            Tn_, U = T.copy(), np.tile(bg, (npx, 1)).astype(f32)
+            state = {}
+            for c in range(n_ch - 2, -1, -1):
+                P, L = ck[c + 1]
+                Te = (Tn_ / P).astype(f32)
+                U = fma(P[:, None], U, L)
+                state[c] = (Te, U.copy())
+                Tn_ = Te
+        # ---- reverse pass
+        dIt = dI[:, py.clip(0, H - 1), px.clip(0, W - 1)].T.astype(f32) * inside[:, None]
+        live = inside & np.any(dIt != 0, axis=1)
+        last = np.where(live, last, 0)
+        segments = ([(c * chunk, min((c + 1) * chunk, len(lst))) for c in range(n_ch)]
+                    if chunk else [(0, len(lst))])
+        for ci, (lo, hi_pos) in enumerate(segments):
+            Tf = T.copy()
+            bgterm = (dIt[:, 0] * bg[0] + dIt[:, 1] * bg[1] + dIt[:, 2] * bg[2]).astype(f32)
+            if mistake == "no_bg":
+                bgterm = np.zeros_like(bgterm)
+            Tk = Tf
+            acc = (Tf * bgterm).astype(f32)
+            if chunk and ci < len(segments) - 1:
+                Te, U = state[ci]
+                use = last > hi_pos
+                Tk = np.where(use, Te, Tf)
+                acc = np.where(use, (Te * (dIt[:, 0] * U[:, 0] + dIt[:, 1] * U[:, 1]
+                                          + dIt[:, 2] * U[:, 2]).astype(f32)).astype(f32), acc)
+            for j in range(hi_pos - 1, lo - 1, -1):
+                g = lst[j]
+                p2, dx, dy = sp.p2(g, fx, fy)
+                ok = (j + 1 <= last) & (p2 <= 0) & (p2 >= sp.thr[g])
+                if not ok.any():
+                    continue
+                gss = np.exp2(p2).astype(f32)
+                aa = (sp.o[g] * gss).astype(f32)
+                alpha = np.minimum(f32(0.99), aa)
+                inv = (f32(1) / (f32(1) - alpha)).astype(f32)
+                Tb = (Tk * inv).astype(f32)
+                w = (alpha * (Tk if mistake == "behind" else Tb)).astype(f32)
+                dIc = fma(dIt[:, 2], sp.rgb[g, 2], fma(dIt[:, 1], sp.rgb[g, 1],
+                                                        dIt[:, 0] * sp.rgb[g, 0]))
+                dLda = fma(Tb, dIc, (-inv * acc).astype(f32))
+                acc = np.where(ok, fma(w, dIc, acc), acc)
+                Tk = np.where(ok, Tb, Tk)
+                geo = ok & (aa < f32(0.99))
+                G = np.where(geo, (dLda * alpha).astype(f32), f32(0))
+                if mistake == "no_opacity":
+                    G = np.where(geo, dLda, f32(0))
+                Gdy = (G * dy).astype(f32)
+                comp = np.stack([
+                    fma((f32(2) * sp.A[g] * dx).astype(f32), G, (sp.B[g] * Gdy).astype(f32)),
+                    fma((f32(2) * sp.C[g]).astype(f32), Gdy, (sp.B[g] * dx * G).astype(f32)),
+                    (dx * dx * G).astype(f32),
+                    (dx * Gdy).astype(f32),
+                    (Gdy * dy).astype(f32),
+                    np.where(geo, (dLda * gss).astype(f32), f32(0)),
+                    np.where(ok, dIt[:, 0] * w, f32(0)),
+                    np.where(ok, dIt[:, 1] * w, f32(0)),
+                    np.where(ok, dIt[:, 2] * w, f32(0))], axis=1).astype(f32)
+                d_rec[g] += (scale * comp.sum(axis=0, dtype=f32)).astype(f32)
+    return d_rec.astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def case():
+    params = perturbed(surface_scene(20000, 81), 81, amount=0.2)
+    cams = scene.orbit_cameras(2, W, H)
+    rec, tb, nt, views = oracle_records(params, cams, W, H, (TILE, TILE))
+    dI = masked_image_gradient(np.random.default_rng(3), H, W)
+    n = 20000
+    tiles_x, tiles_y = math.ceil(W / TILE), math.ceil(H / TILE)
+    out = []
+    for v in range(2):
+        sl = slice(v * n, (v + 1) * n)
+        tbv = (tb[sl].view(np.uint16).astype(np.int32))
+        _, ids, ranges = oracle.bin_sort(tbv, nt[sl], rec[sl, 9], np.zeros(n, np.int32),
+                                         tiles_x, tiles_x * tiles_y, 1)
+        o = oracle.render_bwd(views[v], W, H, dI[v].astype(np.float64), bg=BG,
+                              amb_bits=SAME_RECORD_BITS)
+        ref = np.concatenate([o["d_mean2d"], o["d_conic"], o["d_opacity"][None], o["d_rgb"]]).T
+        out.append(dict(rec=rec[sl], ids=ids, ranges=ranges, dI=dI[v], ref=ref,
+                        term=o["term_mass"].T, amb=o["amb_mass"].T, abs=o["abs_mass"].T))
+    return out
+
+
+def worst_ratio(g, c, floor, mass):
+    bound = 1e-3 * np.maximum(np.abs(c["ref"]), floor * mass) + c["amb"] + 1e-12
+    return float((np.abs(g - c["ref"]) / bound).max())
+
+
+@pytest.mark.parametrize("chunk", [0, 64])
+def test_fp32_replay_meets_term_mass_bound_but_not_a_cancelled_one(case, chunk):
+    lens = [int((c["ranges"][:, 1] - c["ranges"][:, 0]).max()) for c in case]
+    assert max(lens) > 3 * 64                  # long chains, several chunks per tile
+    new, old = [], []
+    for c in case:
+        g = emulate(c["rec"], c["ids"], c["ranges"], c["dI"], chunk)
+        new.append(worst_ratio(g, c, 0.01, c["term"]))
+        old.append(worst_ratio(g, c, 0.01, c["abs"]))
+    print(f"chunk {chunk}: term-mass bound worst ratio {max(new):.3f}, "
+          f"cancelled-result bound worst ratio {max(old):.3f}")
+    assert max(new) <= 0.5            # a correct FP32 evaluation uses at most half the bound
+    assert max(old) > 1.0             # ... and cannot meet a bound relative to the result
+
+
+@pytest.mark.parametrize("mistake", ["no_bg", "behind", "no_opacity"])
+def test_term_mass_bound_catches_plausible_mistakes(case, mistake):
+    c = case[0]
+    g = emulate(c["rec"], c["ids"], c["ranges"], c["dI"], 0, mistake=mistake)
+    assert worst_ratio(g, c, 0.01, c["term"]) > 10.0

@@ -200,3 +200,82 @@ def test_batched_density_control_keeps_partitions_apart(parts):
         single.render_checked(ops.gaussians_struct({k: v.contiguous() for k, v in prm.items()}))
         torch.cuda.synchronize()
         np.testing.assert_array_equal(got[2 * p:2 * p + 2], single.image.cpu().numpy())
+
+
+def _unambiguous_masks(prts, cams, views):
+    """Copies of the partitions whose masks also cut every pixel the oracle
+    marks ambiguous for the partition's own Gaussians in the given views
+    (there FP32 and FP64 decisions may differ), with the oracle's
+    projections and renders of those views."""
+    out, orc = [], []
+    for part in prts:
+        masks = part["masks"].clone()
+        per = {}
+        for vi in views:
+            cam = scene.camera_dict(cams[vi])
+            pr = oracle.project(part["params"], cam)
+            r = oracle.render(pr, W, H)
+            amb = torch.as_tensor(r["ambiguous"].astype(bool)).cuda()
+            masks[vi] = masks[vi] * (~amb).to(torch.uint8)
+            per[vi] = (cam, pr, r)
+        out.append(dict(part, masks=masks))
+        orc.append(per)
+    return out, orc
+
+
+def test_batched_step_matches_oracle(parts):
+    """One batched step of three uneven partitions stored back to back
+    (slots with gauss_offset != 0), four views each, in one launch per stage:
+    every slot's image, every pair's record gradient and every partition's
+    parameter gradient (the mean over its four views, read back from Adam's
+    first moment m = (1 - beta1) g after the first step) against the oracle
+    run partition by partition and view by view."""
+    say("batched step vs oracle")
+    from paper_2509_12138_amd.train import BatchedTrainer
+    from _gpu_helpers import grad_tolerance_check
+    prts, cams = parts
+    vpp = 4
+    bt0 = BatchedTrainer(prts, cams, views_per_part=vpp, graphs=False, order_seed=11)
+    views = [int(v) for v in bt0.group_views[0]]
+    mod, orc = _unambiguous_masks(prts, cams, views)
+    bt = BatchedTrainer(mod, cams, views_per_part=vpp, graphs=False, order_seed=11)
+    assert [int(v) for v in bt.group_views[0]] == views
+    bt.fit_capacity()
+    bt.step(0)
+    bt.check()
+    torch.cuda.synchronize()
+    assert int(bt.views.gauss_offset[vpp].item()) == bt.counts[0] > 0
+    img = bt.bufs.image.cpu().numpy()
+    drec = bt.bufs.d_rec.cpu().numpy().astype(np.float64)
+    po = bt.views.pair_offset_host
+    b1 = np.float32(0.9)
+    inv = np.float32(1.0) / (np.float32(1.0) - b1)
+    gpu_g = {k: (v.cpu().numpy() * inv).astype(np.float64) for k, v in bt.m.items()}
+    off = 0
+    for p, part in enumerate(mod):
+        n = bt.counts[p]
+        g_ref = {k: np.zeros_like(np.asarray(v, np.float64)) for k, v in part["params"].items()}
+        for j, vi in enumerate(views):
+            s = p * vpp + j
+            cam, pr, r = orc[p][vi]
+            ok = ~r["ambiguous"].astype(bool)
+            err = np.abs(img[s] - r["image"])[:, ok]
+            assert err.max() <= 1e-4, (p, j, err.max())
+            lo = oracle.loss(r["image"], part["targets"][vi].cpu().numpy(),
+                             part["masks"][vi].cpu().numpy())
+            rb = oracle.render_bwd(pr, W, H, lo["d_image"] / vpp)
+            ref = np.concatenate([rb["d_mean2d"], rb["d_conic"], rb["d_opacity"][None],
+                                  rb["d_rgb"]]).T
+            okg, worst = grad_tolerance_check(drec[po[s]:po[s + 1]], ref, rb["term_mass"].T,
+                                              rb["amb_mass"].T)
+            assert okg, (p, j, worst)
+            gp = oracle.project_bwd(part["params"], cam, rb)
+            for k in g_ref:
+                g_ref[k] += gp[k]
+        for k, ref in g_ref.items():
+            got = gpu_g[k][..., off:off + n]
+            scale = np.abs(ref).max()
+            assert np.all(np.abs(got - ref) <= 1e-3 * np.abs(ref) + 1e-4 * scale), (p, k)
+            nr = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
+            assert nr <= 1e-3, (p, k, nr)
+        off += n

@@ -200,7 +200,8 @@ def test_fullsize_raster_matches_oracle_windows(big, tile, sched, chunk, fwd_wav
         grad = np.zeros((n, 9)); term = np.zeros((n, 9)); amb_m = np.zeros((n, 9))
         for w_i, ((x0, y0, x1, y1), f, b) in enumerate(per):
             amb = ((f["ambiguity"] & SAME_RECORD_BITS) != 0)[y0:y1, x0:x1]
-            assert amb.mean() <= 1e-2
+            # measured on these windows: at most 2 of 1,024 pixels
+            assert amb.mean() <= 5e-3
             err = np.abs(img[v][:, y0:y1, x0:x1] - f["image"][:, y0:y1, x0:x1])[:, ~amb]
             assert err.max() <= 1e-4, ((x0, y0), err.max())
             if stored:

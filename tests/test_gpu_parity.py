@@ -13,8 +13,8 @@ import pytest
 
 import oracle
 from paper_2509_12138_amd import scene
-from _gpu_helpers import (grad_tolerance_check, oracle_records, perturbed, raster_records, say,
-                          surface_scene, to_dev)
+from _gpu_helpers import (grad_tolerance_check, masked_image_gradient, oracle_records, perturbed,
+                          raster_records, say, surface_scene, to_dev)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -26,15 +26,6 @@ SAME_RECORD_BITS = 1 | 2 | 4 | 8      # oracle ambiguity reasons other than dept
 def ops(gpu):
     from paper_2509_12138_amd import ops as _ops
     return _ops
-
-
-def masked_image_gradient(rng, H, W, S=2):
-    """Seeded image gradient that is exactly zero where a loss mask would
-    cut it: on 30% of the pixels and on a solid block (whole tiles)."""
-    dI = rng.normal(size=(S, 3, H, W)).astype(np.float32)
-    zero = rng.uniform(size=(S, 1, H, W)) < 0.3
-    zero[:, :, H // 8:H // 2, W // 6:W // 2] = True
-    return np.where(zero, np.float32(0), dI)
 
 
 def make_bufs(ops, params, cams, W, H, tile=(16, 16), cap=None, store=True):
@@ -190,7 +181,8 @@ def test_raster_fwd_matches_oracle_on_same_records(ops, tile):
         # both sides sort the same FP32 depths, so near-equal depths are not
         # ambiguous here: only the alpha / power / cut-off guard bands count
         amb = (o["ambiguity"] & SAME_RECORD_BITS) != 0
-        assert amb.mean() <= 1e-3
+        # measured on this scene: 1-3 pixels of 16,500 (at most 1.8e-4)
+        assert amb.mean() <= 5e-4
         ok = ~amb
         err = np.abs(img[v] - o["image"])[:, ok]
         assert err.max() <= 1e-4, err.max()
@@ -224,8 +216,9 @@ def test_end_to_end_image_matches_fp64_oracle(ops):
         o = oracle.render(oracle.project(params, scene.camera_dict(cams[v])), W, H)
         amb = o["ambiguous"]
         # near-equal depths of neighbouring surface Gaussians dominate the
-        # ambiguous set (their FP32 order may differ from FP64)
-        assert amb.mean() <= 1e-2
+        # ambiguous set (their FP32 order may differ from FP64); measured on
+        # these four views: 0.05-0.39% of the pixels
+        assert amb.mean() <= 5e-3
         err = np.abs(img[v] - o["image"])[:, ~amb]
         assert err.max() <= 1e-4, err.max()
 

@@ -43,40 +43,47 @@ def test_tiny_training_improves_psnr(tiny, stored, sparse):
 
 
 def test_training_step_matches_oracle_step(tiny):
-    """One full step (loss gradient, backward, Adam) against the oracle fed the
-    same state (per-step parity; long trajectories diverge chaotically)."""
+    """One full step of the plain trainer (projection, bin/sort, compositing,
+    masked loss, backward, projection backward fused with Adam) against the
+    oracle fed the same state (per-step parity; long trajectories diverge
+    chaotically).  The step's parameter gradient is read back from Adam's
+    first moment (m = (1 - beta1) g after the first step) and compared per
+    element; the update is then checked against the oracle's Adam applied
+    to that gradient.  Pixels the oracle marks ambiguous are cut from the
+    loss mask, so FP32 and FP64 take the same decisions everywhere else."""
     say("one-step parity")
     from paper_2509_12138_amd.train import PlainTrainer, mean_lr
     wl, targets, masks = tiny
-    tr = PlainTrainer(wl["params"], wl["cams"], targets, masks)
-    tr.fit_capacity()
     v = 3
-    before = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in wl["params"].items()}
+    cam = scene.camera_dict(wl["cams"][v])
+    before = {k: np.asarray(x, np.float32).astype(np.float64) for k, x in wl["params"].items()}
+    W, H = wl["cfg"]["width"], wl["cfg"]["height"]
+    p = oracle.project(before, cam)
+    r = oracle.render(p, W, H)
+    mk = masks.clone()
+    mk[v] = mk[v] * torch.as_tensor(~r["ambiguous"].astype(bool)).cuda().to(torch.uint8)
+    tr = PlainTrainer(wl["params"], wl["cams"], targets, mk)
+    tr.fit_capacity()
     tr.step(v)
     torch.cuda.synchronize()
     after = {k: t.detach().cpu().numpy().astype(np.float64) for k, t in tr.params.items()}
-    cam = scene.camera_dict(wl["cams"][v])
-    W, H = tr.W, tr.H
-    p = oracle.project(before, cam)
-    r = oracle.render(p, W, H)
-    lo = oracle.loss(r["image"], targets[v].cpu().numpy(), masks[v].cpu().numpy())
+    inv = np.float32(1.0) / (np.float32(1.0) - np.float32(0.9))
+    g_gpu = {k: (t.cpu().numpy() * inv).astype(np.float64) for k, t in tr.m.items()}
+    lo = oracle.loss(r["image"], targets[v].cpu().numpy(), mk[v].cpu().numpy())
     g = oracle.project_bwd(before, cam, oracle.render_bwd(p, W, H, lo["d_image"]))
     lrs = dict(tr.lrs); lrs["mean"] = mean_lr(1, tr.extent, tr.lrs["mean"])
     for k in before:
-        ref, _, _ = oracle.adam(before[k], g[k], 0 * before[k], 0 * before[k], lrs[k], 1)
-        step_ref = ref - before[k]
-        step_got = after[k] - before[k]
-        # first Adam step = -lr sign(g): compare where the gradient is clearly non-zero
-        scale = max(np.abs(g[kk]).max() for kk in g)
-        big = np.abs(g[k]) > 1e-3 * np.abs(g[k]).max()
-        if np.abs(g[k]).max() <= 1e-9 * scale:
-            # zero in exact arithmetic (isotropic Gaussians have no rotation
-            # gradient); FP32 round-off may still give an Adam step <= lr
-            assert np.all(np.abs(step_got) <= lrs[k] * 1.001), k
+        ref = g[k]
+        scale = np.abs(ref).max()
+        if scale == 0.0:
             continue
-        agree = np.mean(np.sign(step_got[big]) == np.sign(step_ref[big]))
-        assert agree > 0.995, (k, agree)
-        np.testing.assert_allclose(np.abs(step_got[big]), lrs[k], rtol=1e-3)
+        assert np.all(np.abs(g_gpu[k] - ref) <= 1e-3 * np.abs(ref) + 1e-4 * scale), k
+        nr = np.linalg.norm(g_gpu[k] - ref) / np.linalg.norm(ref)
+        assert nr <= 1e-3, (k, nr)
+        # the update of the step: the oracle's Adam on the GPU's gradient
+        upd, _, _ = oracle.adam(before[k], g_gpu[k], 0 * before[k], 0 * before[k], lrs[k], 1)
+        np.testing.assert_allclose(after[k], upd, rtol=2e-6, atol=2e-6 * lrs[k]), k
+
 
 
 def test_density_control_changes_the_model_and_keeps_training(tiny):
