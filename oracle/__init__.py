@@ -150,7 +150,7 @@ def _proj_arrays(proj):
             _f64(proj["opacity"]), _f64(proj["rgb"]), tb, valid)
 
 
-def render(proj, W, H, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None):
+def render(proj, W, H, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None, band=1e-5):
     """Composite every pixel front to back (3D-GS rasteriser definition).
 
     proj holds SoA mean2d [2,n], conic [3,n], depth, opacity, rgb [3,n],
@@ -159,6 +159,10 @@ def render(proj, W, H, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None):
     pixels outside the window are left zero.  ``ambiguity`` holds the reason
     bits of an ambiguous pixel: 1 power near 0, 2 alpha near 1/255, 4 alpha
     near 0.99, 8 transmittance near the cut-off, 16 near-equal depths.
+    ``band`` is the relative half-width of the alpha and cut-off guard bands
+    (1e-5 for records given to both sides in the same FP32 values; wider
+    where the other side computes its records itself, to the projection's
+    own tolerance).  It only classifies pixels.
     """
     lib = _load()
     n, m2, cn, dp, op, rgb, tb, valid = _proj_arrays(proj)
@@ -168,13 +172,13 @@ def render(proj, W, H, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None):
     bgv = _f64(bg)
     lib.or_render(ctypes.c_int64(n), _p(m2), _p(cn), _p(dp), _p(op), _p(rgb), _p(tb), _p(valid),
                   W, H, tile[0], tile[1], _p(bgv), x0, y0, x1, y1, _p(img), _p(T), _p(nc),
-                  _p(nb), _p(amb))
+                  _p(nb), _p(amb), ctypes.c_double(band))
     return dict(image=img, T_final=T, n_contrib=nc, n_blended=nb, ambiguous=amb.astype(bool),
                 ambiguity=amb)
 
 
 def render_bwd(proj, W, H, d_image, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None,
-               amb_bits=31):
+               amb_bits=31, band=1e-5):
     """Analytic backward of ``render`` with all decisions held fixed.
 
     Returns per-Gaussian SoA gradients d_mean2d [2,n], d_conic [3,n],
@@ -182,7 +186,8 @@ def render_bwd(proj, W, H, d_image, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=No
     per-pixel contributions, all pixels / ambiguous pixels only; amb_bits
     selects which ambiguity reasons of ``render`` count) and term_mass [9,n]
     (the same sums over the magnitudes of the terms before they cancel inside
-    dL/dalpha, a condition measure for FP32 comparisons).
+    dL/dalpha, a condition measure for FP32 comparisons).  ``band`` as in
+    ``render``.
     """
     lib = _load()
     n, m2, cn, dp, op, rgb, tb, valid = _proj_arrays(proj)
@@ -196,7 +201,7 @@ def render_bwd(proj, W, H, d_image, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=No
                       _p(valid), W, H, tile[0], tile[1], _p(bgv), x0, y0, x1, y1, _p(dI),
                       _p(out["d_mean2d"]), _p(out["d_conic"]), _p(out["d_opacity"]),
                       _p(out["d_rgb"]), _p(out["abs_mass"]), _p(out["amb_mass"]),
-                      ctypes.c_int(amb_bits), _p(out["term_mass"]))
+                      ctypes.c_int(amb_bits), _p(out["term_mass"]), ctypes.c_double(band))
     return out
 
 

@@ -327,45 +327,62 @@ typedef struct {
 
 /* Composite one pixel.  Inputs are SoA per Gaussian; `order` lists the valid
  * Gaussians sorted by (depth, index).  If `rec` is non-NULL the blended
- * entries are recorded (capacity n).  Returns the number blended.          */
+ * entries are recorded (capacity n).  Returns the number blended.
+ * band_rel is the relative half-width of the guard bands around the alpha
+ * thresholds (1/255 and 0.99) and the least relative half-width of the one
+ * around the transmittance cut-off, inside which a pixel is marked
+ * ambiguous: an input given to FP32 to within that relative error may take
+ * the other branch there.  It classifies pixels only; the composite itself
+ * does not depend on it.                                                   */
 static int64_t composite_pixel(int px, int py, int tw, int th, int64_t n, int64_t cnt,
                                const int64_t* order, const double* mean2d, const double* conic,
                                const double* depth, const double* opacity, const double* rgb,
                                const int32_t* tile_bbox, const double* bg, double out[3],
                                double* T_out, int32_t* ncontrib_out, uint8_t* amb_out,
-                               or_blend* rec) {
+                               or_blend* rec, double band_rel) {
   double T = 1.0, C[3] = {0, 0, 0};
   int tx = px / tw, ty = py / th;
   double cxp = px + 0.5, cyp = py + 0.5;
   int64_t pos = 0, last = 0, nb = 0;
   int amb = 0;
+  /* depth of the previous entry that passed the alpha test: two such entries
+   * at near-equal depths may be sorted either way from FP32 depths, which
+   * matters when either is blended or stops the pixel; after the stop, the
+   * next passing entry is the one that could take the stopping one's place */
   double prev_depth = -1.0;
+  int stopped = 0;
   for (int64_t k = 0; k < cnt; ++k) {
     int64_t g = order[k];
     if (tx < tile_bbox[g] || ty < tile_bbox[n + g] || tx > tile_bbox[2 * n + g] ||
         ty > tile_bbox[3 * n + g])
       continue;                                   /* not in this tile's list */
+    /* entries are in ascending depth: past the band nothing can tie */
+    if (stopped && depth[g] - prev_depth > 5e-7 * fabs(depth[g])) break;
     ++pos;
     double dx = cxp - mean2d[g], dy = cyp - mean2d[n + g];
     double q11 = conic[g], q12 = conic[n + g], q22 = conic[2 * n + g];
     double qf = q11 * dx * dx + 2.0 * q12 * dx * dy + q22 * dy * dy;
     double qabs = fabs(q11 * dx * dx) + fabs(2.0 * q12 * dx * dy) + fabs(q22 * dy * dy);
-    if (qabs > 0 && fabs(qf) <= 1e-5 * qabs) amb |= 1;
+    if (!stopped && qabs > 0 && fabs(qf) <= 1e-5 * qabs) amb |= 1;
     double power = -0.5 * qf;
     if (power > 0) continue;
     double e = exp(power);
     double a = opacity[g] * e;
-    if (fabs(a - OR_ALPHA_MIN) <= 1e-5 * OR_ALPHA_MIN) amb |= 2;
-    if (fabs(a - OR_ALPHA_MAX) <= 1e-5 * OR_ALPHA_MAX) amb |= 4;
+    if (!stopped && fabs(a - OR_ALPHA_MIN) <= band_rel * OR_ALPHA_MIN) amb |= 2;
+    if (!stopped && fabs(a - OR_ALPHA_MAX) <= band_rel * OR_ALPHA_MAX) amb |= 4;
     double alpha = a < OR_ALPHA_MAX ? a : OR_ALPHA_MAX;
     if (alpha < OR_ALPHA_MIN) continue;
-    double Tn = T * (1.0 - alpha);
-    double band = 8.0 * (double)(nb + 1) * 5.9604644775390625e-08;  /* 8 n 2^-24 */
-    if (band < 1e-5) band = 1e-5;
-    if (fabs(Tn - OR_T_MIN) <= band * OR_T_MIN) amb |= 8;
-    if (Tn < OR_T_MIN) break;
     if (prev_depth >= 0 && fabs(depth[g] - prev_depth) <= 5e-7 * fabs(depth[g])) amb |= 16;
     prev_depth = depth[g];
+    if (stopped) break;
+    double Tn = T * (1.0 - alpha);
+    double band = 8.0 * (double)(nb + 1) * 5.9604644775390625e-08;  /* 8 n 2^-24 */
+    if (band < band_rel) band = band_rel;
+    if (fabs(Tn - OR_T_MIN) <= band * OR_T_MIN) amb |= 8;
+    if (Tn < OR_T_MIN) {
+      stopped = 1;
+      continue;
+    }
     if (rec) {
       rec[nb].g = g; rec[nb].alpha = alpha; rec[nb].a = a; rec[nb].e = e;
       rec[nb].T = T; rec[nb].dx = dx; rec[nb].dy = dy;
@@ -389,7 +406,7 @@ void or_render(int64_t n, const double* mean2d, const double* conic, const doubl
                const double* opacity, const double* rgb, const int32_t* tile_bbox,
                const int32_t* valid, int W, int H, int tw, int th, const double* bg, int x0,
                int y0, int x1, int y1, double* image, double* T_final, int32_t* n_contrib,
-               int32_t* n_blended, uint8_t* ambiguous) {
+               int32_t* n_blended, uint8_t* ambiguous, double band_rel) {
   int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
   int64_t cnt = sorted_order(n, depth, valid, order);
   int64_t npix = (int64_t)(x1 - x0) * (y1 - y0);
@@ -399,7 +416,7 @@ void or_render(int64_t n, const double* mean2d, const double* conic, const doubl
     int64_t o = (int64_t)py * W + px;
     double out[3], T; int32_t nc; uint8_t amb;
     int64_t nb = composite_pixel(px, py, tw, th, n, cnt, order, mean2d, conic, depth, opacity,
-                                 rgb, tile_bbox, bg, out, &T, &nc, &amb, NULL);
+                                 rgb, tile_bbox, bg, out, &T, &nc, &amb, NULL, band_rel);
     for (int ch = 0; ch < 3; ++ch) image[(int64_t)ch * W * H + o] = out[ch];
     if (T_final) T_final[o] = T;
     if (n_contrib) n_contrib[o] = nc;
@@ -424,7 +441,7 @@ void or_render_bwd(int64_t n, const double* mean2d, const double* conic, const d
                    const int32_t* valid, int W, int H, int tw, int th, const double* bg, int x0,
                    int y0, int x1, int y1, const double* d_image, double* d_mean2d,
                    double* d_conic, double* d_opacity, double* d_rgb, double* abs_mass,
-                   double* amb_mass, int amb_bits, double* term_mass) {
+                   double* amb_mass, int amb_bits, double* term_mass, double band_rel) {
   int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
   int64_t cnt = sorted_order(n, depth, valid, order);
   int64_t npix = (int64_t)(x1 - x0) * (y1 - y0);
@@ -437,7 +454,7 @@ void or_render_bwd(int64_t n, const double* mean2d, const double* conic, const d
       int64_t o = (int64_t)py * W + px;
       double out[3], Tf; int32_t nc; uint8_t amb;
       int64_t nb = composite_pixel(px, py, tw, th, n, cnt, order, mean2d, conic, depth, opacity,
-                                   rgb, tile_bbox, bg, out, &Tf, &nc, &amb, rec);
+                                   rgb, tile_bbox, bg, out, &Tf, &nc, &amb, rec, band_rel);
       double dI[3];
       for (int ch = 0; ch < 3; ++ch) dI[ch] = d_image[(int64_t)ch * W * H + o];
       double acc[3];                      /* sum_{j>k} c_j a_j T_j + bg T_final */

@@ -27,6 +27,14 @@ def rec_to_oracle(rec, tile_bbox, n_tiles):
                 tile_bbox=np.ascontiguousarray(tb.T), valid=(np.asarray(n_tiles) > 0).astype(np.int32))
 
 
+# Relative half-width of the oracle's decision bands (alpha thresholds,
+# transmittance cut-off) where the GPU computes the projected records itself:
+# the projection matches FP64 to 1e-5 relative on the conic and about 1e-4 px
+# on the mean, which moves the exponent -q^T Q q / 2 of a footprint about a
+# pixel wide by up to about 1e-3 near the 1/255 contour.
+BAND_E2E = 1e-3
+
+
 def grad_tolerance_check(g, r, term_mass, amb_mass, rel=1e-3, floor=0.01):
     """|g - r| <= rel * max(|r|, floor * A) + A_amb per element, where A is the
     oracle's term mass (sum over pixels of the magnitudes of the terms of
@@ -115,3 +123,17 @@ def raster_records(bufs, rec, tb, nt, bg, torch):
     bufs.order_tiles()
     bufs.raster_fwd(bg)
     torch.cuda.synchronize()
+
+
+def decision_safe_mask(mask, r, target, tol=1e-4):
+    """A loss mask [H,W] (uint8) with the pixels cut where FP32 and FP64 may
+    take different discrete decisions: those the oracle's render marks
+    ambiguous, and those where some channel of the oracle image lies within
+    the image tolerance (1e-4) of the target, since there the sign of the
+    L1 term's derivative is not fixed by an image that matches to 1e-4.
+    Built from the oracle's render and the target only."""
+    img = np.asarray(r["image"], np.float64)
+    tgt = np.asarray(target, np.float64)
+    near = (np.abs(img - tgt) <= tol).any(axis=0)
+    keep = ~(np.asarray(r["ambiguous"]).astype(bool) | near)
+    return (np.asarray(mask) != 0) & keep

@@ -203,42 +203,42 @@ def test_batched_density_control_keeps_partitions_apart(parts):
 
 
 def _unambiguous_masks(prts, cams, views):
-    """Copies of the partitions whose masks also cut every pixel the oracle
-    marks ambiguous for the partition's own Gaussians in the given views
-    (there FP32 and FP64 decisions may differ), with the oracle's
-    projections and renders of those views."""
+    """Copies of the partitions made anisotropic, rotated and varied (so that
+    no gradient vanishes identically, as the rotation's does for isotropic
+    Gaussians) whose masks also cut every pixel where FP32 and FP64
+    decisions may differ for the partition's own Gaussians in the given
+    views (render ambiguity, or an L1 sign within the image tolerance),
+    with the oracle's projections and renders of those views.  The GPU
+    projects the Gaussians itself, so the decision bands are those of its
+    projection's tolerance (BAND_E2E), not of FP32 rounding alone."""
+    from _gpu_helpers import BAND_E2E, decision_safe_mask
     out, orc = [], []
-    for part in prts:
+    for i, part in enumerate(prts):
+        prm = perturbed(part["params"], 40 + i)
         masks = part["masks"].clone()
         per = {}
         for vi in views:
             cam = scene.camera_dict(cams[vi])
-            pr = oracle.project(part["params"], cam)
-            r = oracle.render(pr, W, H)
-            amb = torch.as_tensor(r["ambiguous"].astype(bool)).cuda()
-            masks[vi] = masks[vi] * (~amb).to(torch.uint8)
+            pr = oracle.project(prm, cam)
+            r = oracle.render(pr, W, H, band=BAND_E2E)
+            keep = decision_safe_mask(masks[vi].cpu().numpy(), r,
+                                      part["targets"][vi].cpu().numpy())
+            masks[vi] = torch.as_tensor(keep.astype(np.uint8)).cuda()
             per[vi] = (cam, pr, r)
-        out.append(dict(part, masks=masks))
+        out.append(dict(part, params=prm, masks=masks))
         orc.append(per)
     return out, orc
 
 
-def test_batched_step_matches_oracle(parts):
-    """One batched step of three uneven partitions stored back to back
-    (slots with gauss_offset != 0), four views each, in one launch per stage:
-    every slot's image, every pair's record gradient and every partition's
-    parameter gradient (the mean over its four views, read back from Adam's
-    first moment m = (1 - beta1) g after the first step) against the oracle
-    run partition by partition and view by view."""
-    say("batched step vs oracle")
+def _batched_step_vs_oracle(parts, lam, per_pair):
     from paper_2509_12138_amd.train import BatchedTrainer
-    from _gpu_helpers import grad_tolerance_check
+    from _gpu_helpers import BAND_E2E, grad_tolerance_check
     prts, cams = parts
     vpp = 4
     bt0 = BatchedTrainer(prts, cams, views_per_part=vpp, graphs=False, order_seed=11)
     views = [int(v) for v in bt0.group_views[0]]
     mod, orc = _unambiguous_masks(prts, cams, views)
-    bt = BatchedTrainer(mod, cams, views_per_part=vpp, graphs=False, order_seed=11)
+    bt = BatchedTrainer(mod, cams, views_per_part=vpp, graphs=False, order_seed=11, lam=lam)
     assert [int(v) for v in bt.group_views[0]] == views
     bt.fit_capacity()
     bt.step(0)
@@ -262,13 +262,14 @@ def test_batched_step_matches_oracle(parts):
             err = np.abs(img[s] - r["image"])[:, ok]
             assert err.max() <= 1e-4, (p, j, err.max())
             lo = oracle.loss(r["image"], part["targets"][vi].cpu().numpy(),
-                             part["masks"][vi].cpu().numpy())
-            rb = oracle.render_bwd(pr, W, H, lo["d_image"] / vpp)
-            ref = np.concatenate([rb["d_mean2d"], rb["d_conic"], rb["d_opacity"][None],
-                                  rb["d_rgb"]]).T
-            okg, worst = grad_tolerance_check(drec[po[s]:po[s + 1]], ref, rb["term_mass"].T,
-                                              rb["amb_mass"].T)
-            assert okg, (p, j, worst)
+                             part["masks"][vi].cpu().numpy(), lam=lam)
+            rb = oracle.render_bwd(pr, W, H, lo["d_image"] / vpp, band=BAND_E2E)
+            if per_pair:
+                ref = np.concatenate([rb["d_mean2d"], rb["d_conic"], rb["d_opacity"][None],
+                                      rb["d_rgb"]]).T
+                okg, worst = grad_tolerance_check(drec[po[s]:po[s + 1]], ref,
+                                                  rb["term_mass"].T, rb["amb_mass"].T)
+                assert okg, f"slot {p},{j}: {worst}"
             gp = oracle.project_bwd(part["params"], cam, rb)
             for k in g_ref:
                 g_ref[k] += gp[k]
@@ -279,3 +280,28 @@ def test_batched_step_matches_oracle(parts):
             nr = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
             assert nr <= 1e-3, (p, k, nr)
         off += n
+
+
+def test_batched_step_matches_oracle(parts):
+    """One batched step of three uneven partitions stored back to back
+    (slots with gauss_offset != 0), four views each, in one launch per stage,
+    with the L1 loss alone: every slot's image, every pair's record gradient
+    (per element, term-mass bound) and every partition's parameter gradient
+    (the mean over its four views, read back from Adam's first moment
+    m = (1 - beta1) g after the first step) against the oracle run partition
+    by partition and view by view.  With the L1 sign decided the same way on
+    both sides the image gradient is identical, so every difference comes
+    from the launch itself."""
+    say("batched step vs oracle (L1)")
+    _batched_step_vs_oracle(parts, lam=0.0, per_pair=True)
+
+
+def test_batched_step_with_dssim_matches_oracle(parts):
+    """The same step with the configured 0.8 L1 + 0.2 D-SSIM loss: images and
+    per-partition parameter gradients against the oracle (per element
+    1e-3 |r| + 1e-4 max |r|, normwise 1e-3).  The D-SSIM gradient moves by
+    about 40x the image's own FP32 error relative to its largest value, so a
+    pair whose gradient cancels across pixels of both signs is compared at
+    the parameter level only; the loss's own parity is tested by itself."""
+    say("batched step vs oracle (L1 + D-SSIM)")
+    _batched_step_vs_oracle(parts, lam=0.2, per_pair=False)

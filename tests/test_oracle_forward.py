@@ -269,3 +269,44 @@ def test_window_matches_full_render():
     full = oracle.render(p, 48, 40)
     win = oracle.render(p, 48, 40, window=(5, 7, 30, 33))
     np.testing.assert_array_equal(win["image"][:, 7:33, 5:30], full["image"][:, 7:33, 5:30])
+
+
+def test_decision_bands_classify_only():
+    """The guard-band width marks which pixels sit near a threshold (an
+    opacity of 1/255 (1 + 5e-4) at the pixel centre is outside a 1e-5 band
+    and inside a 1e-3 one; likewise 0.99 (1 - 5e-4) for the clamp) and
+    never changes the composite."""
+    cx = 0.5 * 2 / F
+    for o, bit in (((1 / 255) * (1 + 5e-4), 2), (0.99 * (1 - 5e-4), 4)):
+        g = one((cx, cx, 2), 0.1, opacity=o, color=rgb_to_sh([1, 1, 1]))
+        _, narrow = render_scene(g)
+        _, wide = render_scene(g, band=1e-3)
+        np.testing.assert_array_equal(narrow["image"], wide["image"])
+        np.testing.assert_array_equal(narrow["T_final"], wide["T_final"])
+        assert not narrow["ambiguity"][16, 16] & bit
+        assert wide["ambiguity"][16, 16] & bit
+        assert np.all(wide["ambiguous"] >= narrow["ambiguous"])
+
+
+def test_depth_tie_at_the_stopping_entry_is_ambiguous():
+    """The pixel of the transmittance-cut-off stack stops at its 14th
+    Gaussian; a further Gaussian that passes the alpha test at a depth
+    within 5e-7 (relative) of that stopping one could be sorted before it
+    from FP32 depths and then be blended, so the pixel is marked (reason
+    16); at a clearly larger depth it is not, and the composite is the same
+    either way at that pixel."""
+    mu_x = (16.5 - 16) * 2.0 / F
+
+    def g_at(z):
+        return one((mu_x * z / 2.0, mu_x * z / 2.0, z), 0.01, color=rgb_to_sh([1, 1, 1]))
+
+    base = [g_at(2 + 0.1 * i) for i in range(14)]
+    z_stop = 2 + 0.1 * 13
+    _, r0 = render_scene(cat(*base))
+    _, r_far = render_scene(cat(*base, g_at(z_stop * (1 + 1e-3))))
+    _, r_tie = render_scene(cat(*base, g_at(z_stop * (1 + 1e-7))))
+    assert r0["n_blended"][16, 16] == 13 and r_tie["n_blended"][16, 16] == 13
+    assert not r0["ambiguity"][16, 16] & 16
+    assert not r_far["ambiguity"][16, 16] & 16
+    assert r_tie["ambiguity"][16, 16] & 16
+    np.testing.assert_array_equal(r_tie["image"][:, 16, 16], r0["image"][:, 16, 16])
