@@ -329,6 +329,21 @@ gs_status gs_loss(const float* image, const float* target,
                   size_t ws_bytes, float* loss_out, float* d_image,
                   int64_t* status, void* stream);
 
+/* gs_loss without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, outputs and errors as gs_loss, minus
+ * ws / ws_bytes: the partial sums live in a 4 MiB array inside the library,
+ * one per device, held until the process ends (S x ceil(H/32) x ceil(W/32)
+ * x 24 bytes must fit: e.g. up to 85 images of 1920x1080).  Larger requests
+ * fail with GS_ERR_ARG and enqueue nothing.  The call allocates nothing.
+ * Every call on a device shares that device's array, so calls that overlap
+ * on one device (other streams, other threads) race; calls ordered on one
+ * stream do not.                                                           */
+gs_status gs_loss_noalloc(const float* image, const float* target,
+                          const uint8_t* mask, int32_t S, int32_t H, int32_t W,
+                          float lambda_dssim, float grad_scale, float* loss_out,
+                          float* d_image, int64_t* status, void* stream);
+
 /* Workspace for gs_masked_psnr on S images of H x W.                      */
 size_t gs_psnr_workspace_bytes(int32_t S, int32_t H, int32_t W);
 

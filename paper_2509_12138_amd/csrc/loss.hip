@@ -16,6 +16,9 @@
 // once per thread rather than once per tap.
 #include <math.h>
 
+#include <mutex>
+#include <vector>
+
 #include "gs_device.h"
 
 namespace gsmi {
@@ -467,11 +470,64 @@ static gs_status launch_loss(const float* image, const float* target, const uint
                              float grad_scale, float* part, float* loss_out, float* d_image,
                              int64_t* status, void* stream);
 
+// Allocation-free form of the loss: its partial sums (8 bytes per image,
+// channel and 32x32 tile, every one written by k_ssim before k_loss_final
+// reads it, so nothing needs clearing) live in this file-scope array, one
+// copy per device, held until the process ends.  Host code never passes the
+// array's name to a kernel: it looks up the array's device address once per
+// device with hipGetSymbolAddress and passes that.
+constexpr size_t kLossScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kLossScratchBytes];
+
+static gs_status loss_scratch_address(void** out) {
+  static std::mutex mu;
+  static std::vector<void*> addr;           // per device, from hipGetSymbolAddress
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    set_error("gs_loss_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+    return GS_ERR_HIP;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (addr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      set_error("gs_loss_noalloc: hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      return GS_ERR_HIP;
+    }
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return GS_OK;
+}
+
 }  // namespace gsmi
 
 using namespace gsmi;
 
 extern "C" {
+
+gs_status gs_loss_noalloc(const float* image, const float* target, const uint8_t* mask,
+                          int32_t S, int32_t H, int32_t W, float lambda_dssim, float grad_scale,
+                          float* loss_out, float* d_image, int64_t* status, void* stream) {
+  clear_error();
+  GS_REQUIRE(S >= 1 && H >= 1 && W >= 1, "gs_loss_noalloc: bad shape S=%d H=%d W=%d", S, H, W);
+  GS_REQUIRE(image && target && loss_out && d_image, "gs_loss_noalloc: NULL argument");
+  GS_REQUIRE(lambda_dssim >= 0.f && lambda_dssim <= 1.f,
+             "gs_loss_noalloc: lambda %f outside [0,1]", (double)lambda_dssim);
+  const LossLayout L = loss_layout(S, H, W);
+  GS_REQUIRE(L.total <= kLossScratchBytes,
+             "gs_loss_noalloc: S=%d images of %dx%d need %zu bytes of scratch, above the "
+             "%zu-byte maximum (use gs_loss with a workspace)",
+             S, W, H, L.total, kLossScratchBytes);
+  void* ws = nullptr;
+  const gs_status st = loss_scratch_address(&ws);
+  if (st != GS_OK) return st;
+  return launch_loss(image, target, mask, S, H, W, lambda_dssim, grad_scale,
+                     (float*)((char*)ws + L.off_part), loss_out, d_image, status, stream);
+}
 
 size_t gs_loss_workspace_bytes(int32_t S, int32_t H, int32_t W) {
   if (S < 0 || H < 0 || W < 0) return 0;
