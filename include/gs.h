@@ -675,6 +675,30 @@ gs_status gs_zero(void* ptr, size_t bytes, void* stream);
 gs_status gs_check_status(const int64_t* status, void* stream,
                           int64_t* required_out);
 
+/* HIP-graph handles of a whole training step (the batched, persistent step
+ * of one or more partitions and views that Sec. II "Parallel Training" runs
+ * per partition, replayed so the step costs one launch).
+ *
+ * gs_graph_begin starts capturing `stream` (a created stream, not the null
+ * stream; thread-local capture mode, so an unsafe call such as a device
+ * allocation made by this thread during the capture invalidates it).  The
+ * library's calls enqueued on `stream` until gs_graph_end are recorded, not
+ * run.  Every library call is capturable: data-dependent sizes stay on the
+ * device and clears are kernels (gs_zero), never memset nodes.
+ * gs_graph_end stops the capture, instantiates it and returns a
+ * library-owned handle in *out (NULL on failure: GS_ERR_HIP when the capture
+ * was invalidated or instantiation failed).
+ * gs_graph_launch enqueues one replay on `stream` (any stream, the null
+ * stream included).  A replay reads the device buffers the captured calls
+ * named, at their current contents, so those buffers must stay allocated
+ * while the handle is used.  gs_graph_destroy frees the handle (NULL is a
+ * no-op); work already launched is unaffected.                            */
+typedef struct gs_graph gs_graph;
+gs_status gs_graph_begin(void* stream);
+gs_status gs_graph_end(void* stream, gs_graph** out);
+gs_status gs_graph_launch(gs_graph* graph, void* stream);
+void gs_graph_destroy(gs_graph* graph);
+
 /* Thread-local text of the last error ("" if none).                        */
 const char* gs_last_error(void);
 

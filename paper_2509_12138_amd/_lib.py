@@ -99,6 +99,10 @@ SIGNATURES = {
     "gs_loss_workspace_bytes": (sz, [i32, i32, i32]),
     "gs_loss": (i32, [vp, vp, vp, i32, i32, i32, f32, f32, vp, sz, vp, vp, vp, vp]),
     "gs_loss_noalloc": (i32, [vp, vp, vp, i32, i32, i32, f32, f32, vp, vp, vp, vp]),
+    "gs_graph_begin": (i32, [vp]),
+    "gs_graph_end": (i32, [vp, P(vp)]),
+    "gs_graph_launch": (i32, [vp, vp]),
+    "gs_graph_destroy": (None, [vp]),
     "gs_adam": (i32, [P(gs_adam_group), i32, f32, f32, f32, i32, i32, vp]),
     "gs_adam_dev": (i32, [P(gs_adam_group), i32, P(f32), i32, f32, f32, f32, vp, i32, vp]),
     "gs_project_bwd_adam": (i32, [P(gs_gaussians), P(gs_views), P(gs_tiling), P(gs_projected),

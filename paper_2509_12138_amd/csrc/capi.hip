@@ -1,8 +1,9 @@
-// capi.hip — error reporting, status checks, argument validation and the
-// graph-safe zero fill of libgsmi.
+// capi.hip — error reporting, status checks, argument validation, the
+// graph-safe zero fill and the HIP-graph handles of libgsmi.
 #include <string.h>
 
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "gs_device.h"
@@ -62,6 +63,12 @@ __global__ void k_zero(uint32_t* __restrict__ p, int64_t n_words) {
 
 }  // namespace gsmi
 
+// A captured and instantiated step: the graph and its executable form.
+struct gs_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
 using namespace gsmi;
 
 extern "C" {
@@ -106,6 +113,68 @@ gs_status gs_check_status(const int64_t* status, void* stream, int64_t* required
     return GS_ERR_NONFINITE;
   }
   return GS_OK;
+}
+
+gs_status gs_graph_begin(void* stream) {
+  clear_error();
+  GS_REQUIRE(stream != nullptr,
+             "gs_graph_begin: capture needs a created stream (not the null stream)");
+  // thread-local mode: an unsafe call (e.g. a device allocation) made by this
+  // thread during the capture fails and invalidates it
+  hipError_t e = hipStreamBeginCapture(as_stream(stream), hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    set_error("gs_graph_begin: hipStreamBeginCapture: %s", hipGetErrorString(e));
+    return GS_ERR_HIP;
+  }
+  return GS_OK;
+}
+
+gs_status gs_graph_end(void* stream, gs_graph** out) {
+  clear_error();
+  GS_REQUIRE(stream != nullptr && out != nullptr, "gs_graph_end: NULL argument");
+  *out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(as_stream(stream), &graph);
+  if (e != hipSuccess || graph == nullptr) {
+    set_error("gs_graph_end: hipStreamEndCapture: %s (the capture was invalidated)",
+              hipGetErrorString(e));
+    if (graph) (void)hipGraphDestroy(graph);
+    return GS_ERR_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    set_error("gs_graph_end: hipGraphInstantiate: %s", hipGetErrorString(e));
+    (void)hipGraphDestroy(graph);
+    return GS_ERR_HIP;
+  }
+  gs_graph* g = new (std::nothrow) gs_graph{graph, exec};
+  if (!g) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    set_error("gs_graph_end: out of host memory");
+    return GS_ERR_HIP;
+  }
+  *out = g;
+  return GS_OK;
+}
+
+gs_status gs_graph_launch(gs_graph* g, void* stream) {
+  clear_error();
+  GS_REQUIRE(g != nullptr, "gs_graph_launch: NULL graph");
+  hipError_t e = hipGraphLaunch(g->exec, as_stream(stream));
+  if (e != hipSuccess) {
+    set_error("gs_graph_launch: %s", hipGetErrorString(e));
+    return GS_ERR_HIP;
+  }
+  return GS_OK;
+}
+
+void gs_graph_destroy(gs_graph* g) {
+  if (!g) return;
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  delete g;
 }
 
 }  // extern "C"

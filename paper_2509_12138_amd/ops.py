@@ -370,6 +370,40 @@ class RasterBuffers:
 # Loss and optimiser
 # --------------------------------------------------------------------------
 
+class StepGraph:
+    """A sequence of library calls captured into a HIP graph through the C
+    ABI (gs_graph_begin / gs_graph_end on a stream of its own, default
+    priority) and replayed with gs_graph_launch.  body() must enqueue only
+    library calls on the current stream and allocate nothing; the buffers it
+    names must outlive the graph."""
+
+    def __init__(self, body, device=None):
+        self._h = None
+        lib = _lib.load()
+        self._stream = torch.cuda.Stream(device=device)
+        self._stream.wait_stream(torch.cuda.current_stream(device))
+        h = C.c_void_p(self._stream.cuda_stream)
+        out = C.c_void_p()
+        with torch.cuda.stream(self._stream):
+            call("gs_graph_begin", h)
+            try:
+                body()
+            except BaseException:
+                if lib.gs_graph_end(h, C.byref(out)) == _lib.GS_OK:
+                    lib.gs_graph_destroy(out)
+                raise
+            call("gs_graph_end", h, C.byref(out))
+        self._h = out
+
+    def replay(self, stream=None):
+        call("gs_graph_launch", self._h, stream or stream_handle())
+
+    def __del__(self):
+        if self._h:
+            _lib.load().gs_graph_destroy(self._h)
+            self._h = None
+
+
 class LossBuffers:
     def __init__(self, S, H, W, device="cuda"):
         self.S, self.H, self.W = S, H, W

@@ -299,8 +299,9 @@ class BatchedTrainer:
     through ONE launch per stage, and each stage's work is balanced by the
     longest-first tile order (and the chunked backward).  The views are cut
     into fixed groups (a seeded permutation of the orbit); each group's step
-    is captured once in a HIP graph (through torch.cuda.CUDAGraph) and then
-    replayed: the step count and the position-lr decay live on the device.
+    is captured once in a HIP graph (gs_graph_begin / gs_graph_end through
+    ops.StepGraph) and then replayed with gs_graph_launch: the step count
+    and the position-lr decay live on the device.
 
     parts: list of dicts with params (planar SoA arrays), targets [V,3,H,W]
     float32 and masks [V,H,W] uint8 on the device, all seen from cams_np.
@@ -496,9 +497,7 @@ class BatchedTrainer:
             if graph is None:
                 # capture; the capture itself does not execute the work
                 torch.cuda.synchronize()
-                graph = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(graph):
-                    self._step_body(g)
+                graph = ops.StepGraph(lambda: self._step_body(g), self.device)
                 self.graphs[g] = graph
             graph.replay()
         self.steps_done += 1
@@ -539,10 +538,7 @@ class BatchedTrainer:
         for g in range(self.G):
             if g not in self.graphs:
                 torch.cuda.synchronize()
-                graph = torch.cuda.CUDAGraph()
-                with torch.cuda.graph(graph):
-                    self._step_body(g)
-                self.graphs[g] = graph
+                self.graphs[g] = ops.StepGraph(lambda: self._step_body(g), self.device)
             self._warm.add(g)
         torch.cuda.synchronize()
 

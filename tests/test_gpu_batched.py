@@ -305,3 +305,66 @@ def test_batched_step_with_dssim_matches_oracle(parts):
     the parameter level only; the loss's own parity is tested by itself."""
     say("batched step vs oracle (L1 + D-SSIM)")
     _batched_step_vs_oracle(parts, lam=0.2, per_pair=False)
+
+
+def test_captured_step_replays_bit_identically_to_eager(parts):
+    """The batched step captured through the C ABI (gs_graph_begin /
+    gs_graph_end, replayed by gs_graph_launch) with deterministic gradient
+    sums: ten steps over alternating view groups, with the program's own
+    eager work and synchronisations between replays, give bit-identical
+    losses, parameters and Adam moments to the same steps run eagerly."""
+    say("graph replay bit-identical")
+    from paper_2509_12138_amd.train import BatchedTrainer
+    prts, cams = parts
+    runs = {}
+    for graphs in (False, True):
+        bt = BatchedTrainer(prts, cams, views_per_part=2, graphs=graphs, order_seed=3,
+                            deterministic=True)
+        bt.fit_capacity()
+        if graphs:
+            bt.prepare()
+            assert len(bt.graphs) == bt.G
+        losses = []
+        for s in range(10):
+            bt.step(s % bt.G)
+            torch.cuda.synchronize()
+            losses.append(bt.loss.loss.cpu().numpy().copy())
+            _ = (bt.params["mean"] * 2).sum().item()          # eager work between replays
+        bt.check()
+        runs[graphs] = (np.array(losses), {k: v.cpu().numpy() for k, v in bt.params.items()},
+                        {k: v.cpu().numpy() for k, v in bt.m.items()},
+                        int(bt.adam.step_dev.item()))
+    assert runs[True][3] == runs[False][3] == 10
+    np.testing.assert_array_equal(runs[True][0], runs[False][0])
+    for k in runs[False][1]:
+        np.testing.assert_array_equal(runs[True][1][k], runs[False][1][k])
+        np.testing.assert_array_equal(runs[True][2][k], runs[False][2][k])
+
+
+def test_graph_handles_through_the_c_abi(gpu):
+    """gs_graph_* directly: capture two library fills on a created stream,
+    replay the graph three times with eager writes in between (each replay
+    restores the captured effect), and refuse capture on the null stream."""
+    import ctypes as C
+    lib = gpu.load()
+    say("graph handles")
+    buf = torch.full((1 << 16,), 7.0, device="cuda")
+    s = torch.cuda.Stream()
+    h = C.c_void_p(s.cuda_stream)
+    torch.cuda.synchronize()
+    assert lib.gs_graph_begin(h) == 0, lib.gs_last_error()
+    assert lib.gs_zero(C.c_void_p(buf.data_ptr()), 4 * 4096, h) == 0
+    assert lib.gs_zero(C.c_void_p(buf.data_ptr() + 4 * 8192), 4 * 4096, h) == 0
+    g = C.c_void_p()
+    assert lib.gs_graph_end(h, C.byref(g)) == 0, lib.gs_last_error()
+    torch.cuda.synchronize()
+    assert float(buf[0]) == 7.0                # capturing ran nothing
+    for r in range(3):
+        buf.fill_(float(r + 1))
+        assert lib.gs_graph_launch(g, C.c_void_p(torch.cuda.current_stream().cuda_stream)) == 0
+        torch.cuda.synchronize()
+        host = buf.cpu().numpy()
+        assert np.all(host[:4096] == 0) and np.all(host[8192:12288] == 0)
+        assert np.all(host[4096:8192] == r + 1) and np.all(host[12288:] == r + 1)
+    lib.gs_graph_destroy(g)
+    assert lib.gs_graph_begin(None) == -1
