@@ -77,7 +77,9 @@ static LossLayout loss_layout(int S, int H, int W) {
 // region B the horizontal moment sums, later the horizontal pass of the
 // partials.
 constexpr int kLRegionA = (2 * kLS * kLSs > 3 * kLM * kLMs) ? 2 * kLS * kLSs : 3 * kLM * kLMs;
-constexpr int kLRegionB = (5 * kLS * kLMs > 3 * kLM * kLTs) ? 5 * kLS * kLMs : 3 * kLM * kLTs;
+constexpr int kLMom = 6;              // blurred moments: x, y, xx, yy, xy, foreground
+constexpr int kLRegionB = (kLMom * kLS * kLMs > 3 * kLM * kLTs) ? kLMom * kLS * kLMs
+                                                                 : 3 * kLM * kLTs;
 
 template <bool MASK>
 __global__ __launch_bounds__(kLThreads) void k_ssim(
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(kLThreads) void k_ssim(
     float* __restrict__ part) {
   __shared__ float sA[kLRegionA];
   __shared__ float sB[kLRegionB];
-  __shared__ float s_red[2][kLThreads / 64];
+  __shared__ float s_red[3][kLThreads / 64];
   const int64_t ic = blockIdx.x / blocks_per_img;          // image * 3 + channel
   const int64_t img = ic / 3;
   const int64_t b = blockIdx.x - ic * blocks_per_img;
@@ -104,12 +106,19 @@ __global__ __launch_bounds__(kLThreads) void k_ssim(
   float* s_p = sA;                  // [3][kLM][kLMs], position row r = image row oy - 5 + r
   float* s_g = sB;                  // [3][kLM][kLTs]
 
-  // stage the masked image and target (zero outside the image).  Every
-  // load reads a clamped, valid address and the value is dropped afterwards
-  // if it lies outside, so all loads of a thread are in flight together.
+  // stage the masked image and target with their foreground pixels shifted
+  // by the foreground means (x'' = M (x - sx)): variances and the covariance
+  // follow from moments of the shifted values and the blurred mask without
+  // the cancellation of E[x^2] - mu^2 where the images are smooth.  A
+  // background pixel (mask 0 or outside the image: zero padding) is staged
+  // as -0.0, a foreground one never is ((x - sx) + 0 is +0 when x = sx), so
+  // the sign bit of a staged zero carries the mask.  Every load reads a
+  // clamped, valid address and the value is dropped afterwards if it lies
+  // outside, so all loads of a thread are in flight together.
   constexpr int kStage = kLS * kLS;
   constexpr int kStageQ = (kStage + kLThreads - 1) / kLThreads;
   bool fg = false;      // a foreground pixel among the inputs of the tile's SSIM terms
+  float shx, shy;       // the shifts of image and target
   {
     float iv[kStageQ], gv[kStageQ];
     uint8_t mv[kStageQ];
@@ -119,21 +128,49 @@ __global__ __launch_bounds__(kLThreads) void k_ssim(
       const int i = min(t + q * kLThreads, kStage - 1);
       const int r = i / kLS, c = i - r * kLS;
       const int y = oy - 2 * kLR + r, x = ox - 2 * kLR + c;
-      ok[q] = x >= 0 && x < W && y >= 0 && y < H;
+      ok[q] = x >= 0 && x < W && y >= 0 && y < H && t + q * kLThreads < kStage;
       const int64_t o = (int64_t)min(max(y, 0), H - 1) * W + min(max(x, 0), W - 1);
       mv[q] = MASK ? Mk[o] : (uint8_t)1;
       iv[q] = I[o];
       gv[q] = G[o];
     }
+    float sx = 0.f, sy = 0.f, sn = 0.f;
+#pragma unroll
+    for (int q = 0; q < kStageQ; ++q) {
+      const float mk = (ok[q] && mv[q] != 0) ? 1.0f : 0.0f;
+      iv[q] *= mk;
+      gv[q] *= mk;
+      sx += iv[q];
+      sy += gv[q];
+      sn += mk;
+    }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    sn = wave_sum(sn);
+    if ((t & 63) == 0) {
+      s_red[0][t >> 6] = sx;
+      s_red[1][t >> 6] = sy;
+      s_red[2][t >> 6] = sn;
+    }
+    __syncthreads();
+    float tx_ = 0.f, ty_ = 0.f, tn = 0.f;
+#pragma unroll
+    for (int w = 0; w < kLThreads / 64; ++w) {
+      tx_ += s_red[0][w];
+      ty_ += s_red[1][w];
+      tn += s_red[2][w];
+    }
+    shx = tn > 0.f ? tx_ / tn : 0.f;
+    shy = tn > 0.f ? ty_ / tn : 0.f;
 #pragma unroll
     for (int q = 0; q < kStageQ; ++q) {
       const int i = t + q * kLThreads;
       if (i >= kStage) continue;
       const int r = i / kLS, c = i - r * kLS;
-      const float mk = (ok[q] && mv[q] != 0) ? 1.0f : 0.0f;
-      s_x[r * kLSs + c] = mk * iv[q];
-      s_y[r * kLSs + c] = mk * gv[q];
-      fg = fg || (mk != 0.0f && r >= kLR && r < kLS - kLR && c >= kLR && c < kLS - kLR);
+      const bool f = ok[q] && mv[q] != 0;
+      s_x[r * kLSs + c] = f ? (iv[q] - shx) + 0.0f : -0.0f;
+      s_y[r * kLSs + c] = f ? (gv[q] - shy) + 0.0f : -0.0f;
+      fg = fg || (f && r >= kLR && r < kLS - kLR && c >= kLR && c < kLS - kLR);
     }
   }
   if (!__syncthreads_or(fg)) {
@@ -167,15 +204,16 @@ __global__ __launch_bounds__(kLThreads) void k_ssim(
   constexpr int kItems1 = kLS * (kLM / kH1);
   for (int it = t; it < kItems1; it += kLThreads) {
     const int r = it / (kLM / kH1), c0 = (it - r * (kLM / kH1)) * kH1;
-    float acc[kH1][5];
+    float acc[kH1][kLMom];
 #pragma unroll
     for (int u = 0; u < kH1; ++u)
 #pragma unroll
-      for (int q = 0; q < 5; ++q) acc[u][q] = 0.f;
+      for (int q = 0; q < kLMom; ++q) acc[u][q] = 0.f;
 #pragma unroll
     for (int j = 0; j < kH1 + 2 * kLR; ++j) {
       const float xv = s_x[r * kLSs + c0 + j], yv = s_y[r * kLSs + c0 + j];
       const float xx = xv * xv, yy = yv * yv, xy = xv * yv;
+      const float mk = __float_as_uint(xv) == 0x80000000u ? 0.f : 1.f;
 #pragma unroll
       for (int u = 0; u < kH1; ++u) {
         const int k = j - u;
@@ -186,12 +224,13 @@ __global__ __launch_bounds__(kLThreads) void k_ssim(
         acc[u][2] = fmaf(w, xx, acc[u][2]);
         acc[u][3] = fmaf(w, yy, acc[u][3]);
         acc[u][4] = fmaf(w, xy, acc[u][4]);
+        acc[u][5] = fmaf(w, mk, acc[u][5]);
       }
     }
 #pragma unroll
     for (int u = 0; u < kH1; ++u)
 #pragma unroll
-      for (int q = 0; q < 5; ++q) s_h[(q * kLS + r) * kLMs + c0 + u] = acc[u][q];
+      for (int q = 0; q < kLMom; ++q) s_h[(q * kLS + r) * kLMs + c0 + u] = acc[u][q];
   }
   __syncthreads();
 
@@ -199,22 +238,22 @@ __global__ __launch_bounds__(kLThreads) void k_ssim(
   float ssum = 0.f;
   if (t < (kLM / kV1) * kLM) {
     const int c = t % kLM, r0 = (t / kLM) * kV1;
-    float m[kV1][5];
+    float m[kV1][kLMom];
 #pragma unroll
     for (int u = 0; u < kV1; ++u)
 #pragma unroll
-      for (int q = 0; q < 5; ++q) m[u][q] = 0.f;
+      for (int q = 0; q < kLMom; ++q) m[u][q] = 0.f;
 #pragma unroll
     for (int j = 0; j < kV1 + 2 * kLR; ++j) {
-      float h[5];
+      float h[kLMom];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) h[q] = s_h[(q * kLS + r0 + j) * kLMs + c];
+      for (int q = 0; q < kLMom; ++q) h[q] = s_h[(q * kLS + r0 + j) * kLMs + c];
 #pragma unroll
       for (int u = 0; u < kV1; ++u) {
         const int k = j - u;
         if (k < 0 || k > 2 * kLR) continue;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) m[u][q] = fmaf(win.w[k], h[q], m[u][q]);
+        for (int q = 0; q < kLMom; ++q) m[u][q] = fmaf(win.w[k], h[q], m[u][q]);
       }
     }
     const int x = ox - kLR + c;
@@ -225,20 +264,39 @@ __global__ __launch_bounds__(kLThreads) void k_ssim(
     for (int u = 0; u < kV1; ++u) {
       const int y = oy - kLR + r0 + u;
       const float C1 = 0.01f * 0.01f, C2 = 0.03f * 0.03f;
-      const float mx = m[u][0], my = m[u][1];
+      // moments of the shifted values (mu', E') and the blurred mask wt,
+      // om = 1 - wt (x = x'' + s M with M^2 = M and x'' M = x''):
+      //   mu = mu' + s wt,  var = E'xx - mu'^2 + om (2 s mu' + s^2 wt),
+      //   cov = E'xy - mu'x mu'y + om (sy mu'x + sx mu'y + sx sy wt)
+      const float wt = m[u][5], om = 1.f - wt;
+      const float ux = m[u][0], uy = m[u][1];
+      const float mx = fmaf(shx, wt, ux), my = fmaf(shy, wt, uy);
+      const float vx = (m[u][2] - ux * ux) + om * (2.f * shx * ux + shx * shx * wt);
+      const float vy = (m[u][3] - uy * uy) + om * (2.f * shy * uy + shy * shy * wt);
+      const float cv = (m[u][4] - ux * uy) + om * (shy * ux + shx * uy + shx * shy * wt);
       const float A1 = 2.f * mx * my + C1;
-      const float A2 = 2.f * (m[u][4] - mx * my) + C2;
+      const float A2 = 2.f * cv + C2;
       const float B1 = mx * mx + my * my + C1;
-      const float B2 = (m[u][2] - mx * mx) + (m[u][3] - my * my) + C2;
+      const float B2 = vx + vy + C2;
       // B1, B2 >= C1, C2 > 0: hardware reciprocals (1 ulp) suffice
       const float iB1 = __builtin_amdgcn_rcpf(B1), iB2 = __builtin_amdgcn_rcpf(B2);
       const float iB = iB1 * iB2;
       const float S = A1 * A2 * iB;
       const bool in = colin && y >= 0 && y < H;
       if (in && colc && r0 + u >= kLR && r0 + u < kLR + kLT) ssum += S;
-      P[u][0] = in ? 2.f * my * (A2 - A1) * iB - 2.f * mx * S * (iB1 - iB2) : 0.f;
-      P[u][1] = in ? -S * iB2 : 0.f;
-      P[u][2] = in ? 2.f * A1 * iB : 0.f;
+      // partials of S in (mu, var, cov), folded so that, at a foreground
+      // pixel p, dS/dx_p = sum_q w_qp (Q0_q + 2 x''_p Q1_q + y''_p Q2_q)
+      // since there x_p - mu_q = x''_p - mu'_q + sx om_q
+      // dS/dmu_x = 2 A2 / (B1^2 B2) (my - mx) (my (mx + my) + C1), the
+      // factored form of 2 my A2 / (B1 B2) - 2 mx A1 A2 / (B1^2 B2), whose
+      // two terms cancel where the means agree; my - mx from the shifted means
+      const float dm = (uy - ux) + (shy - shx) * wt;
+      const float Pm = 2.f * A2 * iB2 * iB1 * iB1 * dm * fmaf(my, mx + my, C1);
+      const float Pv = -S * iB2;                                  // dS/dvar_x
+      const float Pc = 2.f * A1 * iB;                             // dS/dcov
+      P[u][0] = in ? Pm + 2.f * (shx * om - ux) * Pv + (shy * om - uy) * Pc : 0.f;
+      P[u][1] = in ? Pv : 0.f;
+      P[u][2] = in ? Pc : 0.f;
     }
     // region A (the staged images) is free once every thread is past the
     // horizontal pass, which the barrier above guarantees
@@ -320,7 +378,7 @@ __global__ __launch_bounds__(kLThreads) void k_ssim(
     if (x >= W || y >= H) continue;
     const float xv = xo[u], yv = yo[u];
     l1sum += fabsf(xv - yv);
-    const float gs = g[u][0] + 2.f * xv * g[u][1] + yv * g[u][2];
+    const float gs = g[u][0] + 2.f * (xv - shx) * g[u][1] + (yv - shy) * g[u][2];
     const float diff = xv - yv;
     const float sg = diff > 0.f ? 1.f : (diff < 0.f ? -1.f : 0.f);
     D[(int64_t)y * W + x] = mo[u] * (l1_coef * sg - ssim_coef * gs);

@@ -450,23 +450,38 @@ class BatchedTrainer:
         self._graph_gen = self.bufs.generation
         return need
 
-    def _step_body(self, g):
+    def _ev(self, name, timing):
+        if timing is None:
+            return
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        timing.setdefault(name, []).append(e)
+
+    def _step_body(self, g, timing=None):
         b = self.bufs
         self.views.use_cameras(self.cams_g[g])
+        self._ev("project", timing)
         b.project(self.gst)
+        self._ev("bin_sort", timing)
         b.bin_sort()
         b.order_tiles()
+        self._ev("raster_fwd", timing)
         b.raster_fwd(self.bg)
+        self._ev("loss", timing)
         self.loss(b.image, self.targets_g[g], self.masks_g[g], self.lam, 1.0 / self.vpp, b.status)
+        self._ev("zero", timing)
         b.zero_d_rec()
+        self._ev("raster_bwd", timing)
         b.raster_bwd(self.loss.d_image, self.bg, self.mode)
         if self._graph_stats:
             self.densifier.stats(b)
+        self._ev("project_bwd", timing)
         if self.fused_adam:
             b.project_bwd_adam(self.gst, self.adam, visible_only=self.sparse_adam)
         else:
             b.project_bwd(self.gst, self.grst)
             self.adam(zero_grad=True)
+        self._ev("end", timing)
 
     def _drop_stale_graphs(self):
         """Captured graphs hold the buffers' pointers: drop them when a
@@ -475,8 +490,10 @@ class BatchedTrainer:
             self.graphs = {}
             self._graph_gen = self.bufs.generation
 
-    def step(self, g):
-        """One batched step on view group g (graph replay after the first)."""
+    def step(self, g, timing=None):
+        """One batched step on view group g (graph replay after the first).
+        With a timing dict the step runs eagerly with HIP events around its
+        stages (on the launch stream), appended to timing[stage]."""
         self._drop_stale_graphs()
         if (self.active_sh < self.sh_degree and self.steps_done > 0 and self.sh_up_every > 0
                 and self.steps_done % self.sh_up_every == 0):
@@ -488,9 +505,9 @@ class BatchedTrainer:
             # the density statistics leave (or join) the captured step
             self._graph_stats = self._stats_on()
             self.graphs = {}
-        if not self.use_graphs or g not in self._warm:
+        if timing is not None or not self.use_graphs or g not in self._warm:
             # eager (also the first time, so every kernel is loaded before capture)
-            self._step_body(g)
+            self._step_body(g, timing)
             self._warm.add(g)
         else:
             graph = self.graphs.get(g)

@@ -79,8 +79,12 @@ def slab_partitions(counts=SLAB_COUNTS, seed=4, ref_factor=2.0, grid=GRID,
     points / normals / ref_points / ref_normals ([n,3] float64)."""
     P = len(counts)
     edges = np.linspace(-SURFACE_EXTENT, SURFACE_EXTENT, P + 1)
-    return [slab_part(float(edges[p]), float(edges[p + 1]), counts[p], seed * 100 + p,
-                      ref_factor, grid, ghost_voxels) for p in range(P)]
+    out = []
+    for p in range(P):
+        out.append(slab_part(float(edges[p]), float(edges[p + 1]), counts[p], seed * 100 + p,
+                             ref_factor, grid, ghost_voxels))
+        log(f"slab {p}: {counts[p]} points sampled")
+    return out
 
 
 def slab_faces(P):
@@ -89,9 +93,13 @@ def slab_faces(P):
 
 
 def prepare(parts, cams, device="cuda", bg=(0.0, 0.0, 0.0)):
-    """Reference discs -> targets and masks on the device, per partition."""
+    """Reference discs -> targets and masks on the device, per partition
+    (disc spacing from the library's k-NN on the device)."""
+    from . import ops
     for part in parts:
-        d = scene.knn_mean_distance(part["ref_points"], 3)
+        rp = torch.as_tensor(np.ascontiguousarray(part["ref_points"].T, np.float32)).to(device)
+        d = ops.knn_mean_distance(rp, 3).cpu().numpy().astype(np.float64)
+        del rp
         ref = workloads.reference_discs(part["ref_points"], part["ref_normals"], d)
         part["targets"], part["masks"] = workloads.render_targets_gpu(ref, cams, device=device,
                                                                       bg=bg)
@@ -128,7 +136,12 @@ def run_plain(part, cams, target, max_steps, eval_every, init="plain", mlp=None,
     tr = PlainTrainer(params, cams, part["targets"], part["masks"], tile=tile, schedule=sched,
                       chunk=chunk, fwd_waves=nw, deterministic=det)
     tr.fit_capacity(views=range(0, len(cams), max(1, len(cams) // 8)))
-    hist = tr.train(max_steps, order_seed=1000 + seed, eval_every=eval_every, target_psnr=target)
+    def progress(step, t, p):
+        if (step // eval_every) % 10 == 0 or p >= target:
+            log(f"plain step {step}: {t:.2f} s, psnr {p:.2f}")
+
+    hist = tr.train(max_steps, order_seed=1000 + seed, eval_every=eval_every, target_psnr=target,
+                    log=progress)
     reached = [h for h in hist if h[2] is not None and h[2] >= target]
     last = [h for h in hist if h[2] is not None]
     out = dict(init_seconds=t_init, init_kind=kind,

@@ -598,3 +598,49 @@ def test_chunk_items_exact(ops, n_tiles, empty):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(o_d.cpu().numpy().view(np.uint32), off)
     np.testing.assert_array_equal(i_d.cpu().numpy()[:total], np.repeat(np.arange(n_tiles), cnt))
+
+
+def _blob_mask(rng, H, W, coverage=0.65):
+    """A foreground mask shaped like an object's silhouette: a thresholded
+    sum of a few dozen wide Gaussian blobs, cut to about `coverage` of the
+    image, with whole background tiles around it."""
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    f = np.zeros((H, W))
+    for _ in range(40):
+        cy, cx = rng.uniform(0.2, 0.8) * H, rng.uniform(0.15, 0.85) * W
+        r = rng.uniform(0.05, 0.2) * min(H, W)
+        f += np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * r * r))
+    return (f >= np.quantile(f, 1.0 - coverage)).astype(np.uint8)
+
+
+def test_loss_at_1080p_matches_oracle(ops):
+    """The loss at the bench's image size (1920x1080, two slots, a batch
+    weight of 1/4) with silhouette masks of the bench's coverage (about 65%),
+    smooth targets and noisy renders (a quarter of the pixels exactly equal
+    to the target, so the L1 sign is 0 there)."""
+    say("loss 1080p")
+    S, H, W = 2, 1080, 1920
+    rng = np.random.default_rng(23)
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    tgt = np.empty((S, 3, H, W), np.float32)
+    for s in range(S):
+        for c in range(3):
+            a, b, ph = rng.uniform(2, 9), rng.uniform(2, 9), rng.uniform(0, 6.3)
+            tgt[s, c] = 0.5 + 0.4 * np.sin(a * xx / W + ph) * np.cos(b * yy / H)
+    img = np.clip(tgt + rng.normal(0, 0.05, tgt.shape), 0, 1).astype(np.float32)
+    same = rng.uniform(size=(S, 1, H, W)) < 0.25
+    img = np.where(same, tgt, img).astype(np.float32)
+    mask = np.stack([_blob_mask(rng, H, W) for _ in range(S)])
+    L = ops.LossBuffers(S, H, W)
+    status = torch.zeros(4, dtype=torch.int64, device="cuda")
+    loss, dI = L(torch.as_tensor(img).cuda(), torch.as_tensor(tgt).cuda(),
+                 torch.as_tensor(mask).cuda(), lam=0.2, grad_scale=0.25, status=status)
+    torch.cuda.synchronize()
+    loss = loss.cpu().numpy(); dI = dI.cpu().numpy()
+    for s in range(S):
+        o = oracle.loss(img[s], tgt[s], mask[s], lam=0.2)
+        assert abs(loss[s] - o["loss"]) <= 1e-5 * abs(o["loss"]), (s, loss[s], o["loss"])
+        r = 0.25 * o["d_image"]
+        assert np.abs(dI[s] - r).max() <= 1e-5 * np.abs(r).max() + 1e-12
+        assert np.all(dI[s][:, mask[s] == 0] == 0)
+    assert int(status[0]) == 0
