@@ -268,6 +268,14 @@ def time_to_target(wl, targets, masks, plan, target=35.0, max_steps=2000, eval_e
             "curve": [(int(s), round(t, 3), round(p, 2)) for s, t, p in hist[:: max(1, len(hist) // 10)]]}
 
 
+# plans tried for the batched workload (tile, schedule, backward chunk,
+# forward waves, deterministic gradient sums)
+BATCHED_CANDIDATES = [
+    ((16, 16), "lpt", 64, 4, False), ((8, 8), "lpt", 64, 1, False), ((16, 8), "lpt", 64, 2, False),
+    ((8, 16), "lpt", 64, 2, False), ((32, 8), "lpt", 128, 4, False), ((16, 16), "lpt", 128, 4, False),
+]
+
+
 def batched_main(args):
     """The batched-partition workload: graph-replayed steps timed by the wall
     clock; stage times (and the raster rate) from eager steps of the same
@@ -295,6 +303,40 @@ def batched_main(args):
     tr = BatchedTrainer(bp, cams, views_per_part=vpp, tile=tile, schedule=sched, chunk=chunk,
                         stored=not args.recompute, fwd_waves=fwd_waves, deterministic=det,
                         order_seed=7)
+    plan_source = "fixed"
+    if not args.no_autotune and args.tile is None:
+        # the plan of the batched step, timed on eager steps of every candidate
+        # (the step count and parameters are restored after each)
+        saved = [t.clone() for d in (tr.params, tr.m, tr.v) for t in d.values()]
+        step0 = tr.adam.step_dev.clone()
+        best = None
+        for cand in BATCHED_CANDIDATES:
+            if args.recompute and cand[2]:
+                continue
+            tr.set_plan(*cand)
+            for s in range(2):
+                tr.step(s % tr.G, timing={})
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in range(4):
+                tr.step((2 + s) % tr.G, timing={})
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 250.0
+            tr.check()
+            log(f"batched plan {cand}: {ms:.2f} ms/step (eager)")
+            if best is None or ms < best[0]:
+                best = (ms, cand)
+        i = 0
+        for d in (tr.params, tr.m, tr.v):
+            for t in d.values():
+                t.copy_(saved[i])
+                i += 1
+        tr.adam.step_dev.copy_(step0)
+        tr.steps_done = 0
+        del saved
+        tile, sched, chunk, fwd_waves, det = best[1]
+        tr.set_plan(*best[1])
+        plan_source = "autotuner"
     need = tr.fit_capacity()
     tr.prepare()
     log(f"{tr.S} slots, {tr.G} view groups, max duplicates per step {need}; graphs captured")
@@ -359,7 +401,7 @@ def batched_main(args):
                          f"{V} orbital views at {W}x{H}, masks, {tr.S} image slots per step, "
                          f"one launch per stage, graph-replayed steps"),
             "tile": f"{tile[0]}x{tile[1]}", "schedule": sched, "backward_chunk": chunk,
-            "fwd_waves": fwd_waves, "deterministic_gradients": det,
+            "fwd_waves": fwd_waves, "deterministic_gradients": det, "plan_source": plan_source,
             "backward": "recompute" if args.recompute else "stored",
             "duplicates_per_step": need,
         },

@@ -313,7 +313,7 @@ class BatchedTrainer:
                  chunk=64, stored=True, lam=0.2, bg=(0.0, 0.0, 0.0), extent=2.75, lrs=None,
                  order_seed=0, graphs=True, dup_capacity=None, fwd_waves=1, deterministic=False,
                  fused_adam=True, sparse_adam=False, sh_degree=0, sh_up_every=1000,
-                 density=None, device="cuda"):
+                 density=None, batch_scaling=True, device="cuda"):
         from .scene import concat_params
         self.device = device
         if sparse_adam and not fused_adam:
@@ -360,6 +360,14 @@ class BatchedTrainer:
         self.bg, self.lam, self.extent = tuple(bg), lam, extent
         self.lrs = dict(DEFAULT_LR if lrs is None else lrs)
         self.lrs["mean"] = self.lrs["mean"] * extent
+        # a step averages views_per_part views: with batch_scaling the Adam
+        # rates grow by sqrt(B) and the moment decays become beta^B (B the
+        # views per partition), so B views move the parameters about as far
+        # as B one-view steps would
+        B = views_per_part if batch_scaling else 1
+        self.lr_scale = math.sqrt(B)
+        self.betas = (0.9 ** B, 0.999 ** B)
+        self.lrs = {k: v * self.lr_scale for k, v in self.lrs.items()}
         self.device = device
         self.plan = dict(tile=tuple(tile), stored=stored, schedule=schedule, chunk=chunk,
                          fwd_waves=fwd_waves, deterministic=deterministic)
@@ -399,7 +407,9 @@ class BatchedTrainer:
         self.grst = ops.grads_struct(self.grads, self.n)
         self.groups = ops.adam_groups(self.params, self.grads, self.m, self.v, self.lrs)
         step_dev = self.adam.step_dev if self.adam is not None else None
-        self.adam = ops.DeviceAdam(self.groups, lr_final=[1.6e-6 * self.extent, 0, 0, 0, 0],
+        self.adam = ops.DeviceAdam(self.groups,
+                                   lr_final=[1.6e-6 * self.extent * self.lr_scale, 0, 0, 0, 0],
+                                   beta1=self.betas[0], beta2=self.betas[1],
                                    decay_steps=30000, device=self.device)
         if step_dev is not None:
             self.adam.step_dev = step_dev
@@ -410,6 +420,15 @@ class BatchedTrainer:
                 self.densifier.resize(self.n)
         self.graphs = {}
         self._graph_gen = self.bufs.generation
+
+    def set_plan(self, tile, schedule, chunk, fwd_waves=1, deterministic=False):
+        """Rebind the raster buffers to another plan (tile shape, schedule,
+        backward chunk, forward waves, deterministic sums); parameters,
+        moments and the step count are kept, captured graphs dropped."""
+        self.plan.update(tile=tuple(tile), schedule=schedule, chunk=int(chunk),
+                         fwd_waves=int(fwd_waves), deterministic=bool(deterministic))
+        self._bind(self.params, self.m, self.v)
+        self.fit_capacity()
 
     def _stats_on(self):
         c = self.density

@@ -156,8 +156,9 @@ def run_plain(part, cams, target, max_steps, eval_every, init="plain", mlp=None,
 
 def run_batched(parts, cams, target, max_steps, eval_every, views_per_part=4, plan=None,
                 device="cuda"):
-    """All partitions in one batched trainer until every one reaches the
-    target; per partition the time of its first evaluation at the target."""
+    """All partitions in one batched trainer until every one reaches its
+    target (a number, or one per partition); per partition the time of its
+    first evaluation at the target."""
     from .train import BatchedTrainer
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -172,6 +173,7 @@ def run_batched(parts, cams, target, max_steps, eval_every, views_per_part=4, pl
     tr.fit_capacity()
     tr.prepare()                  # graph capture is set-up, outside the clock
     P = len(parts)
+    targets = list(target) if np.ndim(target) else [float(target)] * P
     reached = [None] * P
     hist = []
     train_time = 0.0
@@ -192,7 +194,7 @@ def run_batched(parts, cams, target, max_steps, eval_every, views_per_part=4, pl
             log(f"batched step {s + 1}: {train_time:.2f} s, psnr min {ps.min():.2f} "
                 f"mean {ps.mean():.2f}")
             for p in range(P):
-                if reached[p] is None and ps[p] >= target:
+                if reached[p] is None and ps[p] >= targets[p]:
                     reached[p] = (s + 1, t_init + train_time, float(ps[p]))
             if all(r is not None for r in reached):
                 break
@@ -229,37 +231,51 @@ def cmd_probe(a):
 
 
 def cmd_batched(a):
+    """Batched vs plain on the uneven slabs.  The plain arm runs first: each
+    partition alone, one view per step, until 35 dB or the step cap, with the
+    batched arm's rasteriser plan ("same") and/or the untuned one-work-group-
+    per-tile plan ("default").  A partition that does not reach the target
+    within the cap in the first plain arm gets the target (its final PSNR -
+    0.5 dB) in every arm.  The batched arm then trains all partitions
+    together until each reaches its target."""
     counts = [int(c * a.scale) for c in SLAB_COUNTS]
     cams = _cams(a.views, a.width, a.height)
     log(f"sampling slabs {counts}")
     parts = prepare(slab_partitions(counts, ref_factor=a.ref_factor), cams)
     log("targets ready: " + ", ".join(str(p["n"]) for p in parts))
-    rb = run_batched(parts, cams, a.target, a.steps, a.eval_every, a.vpp, plan=a.plan)
+    plans = {"same": a.plan, "default": ((16, 16), "default", 0, 1, False)}
+    arms, goals = {}, None
+    for name in a.plain_plan.split(","):
+        plain = []
+        for i, part in enumerate(parts):
+            goal = a.target if goals is None else goals[i]
+            r = run_plain(part, cams, goal, a.plain_steps, a.eval_every * a.vpp,
+                          plan=plans[name], seed=i)
+            del r["trainer"]
+            torch.cuda.empty_cache()
+            if goals is None and r["seconds"] is None:
+                goal = r["history"][-1][2] - 0.5
+            t_goal = next((r["init_seconds"] + t for s_, t, p in r["history"] if p >= goal), None)
+            r.update(goal=goal, seconds_to_goal=t_goal)
+            log(f"plain ({name} plan) partition {i} (n={part['n']}): goal {goal:.2f} dB at "
+                f"{t_goal} s")
+            plain.append(r)
+        if goals is None:
+            goals = [r["goal"] for r in plain]
+        tp = [r["seconds_to_goal"] for r in plain]
+        arms[name] = dict(plan=list(plans[name]), partitions=plain,
+                          seconds_all=sum(tp) if all(t is not None for t in tp) else None)
+    rb = run_batched(parts, cams, goals, a.steps, a.eval_every, a.vpp, plan=a.plan)
     del rb["trainer"]
     torch.cuda.empty_cache()
-    plain = []
-    # the plain arm: one partition after another, one view per step; by
-    # default with the same rasteriser plan, --plain-plan default gives it the
-    # untuned one-work-group-per-tile plan
-    plain_plan = ((16, 16), "default", 0, 1, False) if a.plain_plan == "default" else a.plan
-    for i, part in enumerate(parts):
-        r = run_plain(part, cams, a.target, a.steps * a.vpp, a.eval_every * a.vpp, plan=plain_plan,
-                      seed=i)
-        del r["trainer"]
-        torch.cuda.empty_cache()
-        log(f"plain partition {i} (n={part['n']}): {r['seconds']} s, {r['steps']} steps, "
-            f"psnr {r['psnr']}")
-        plain.append(r)
-    res = dict(experiment="batched_vs_plain", counts=[p["n"] for p in parts], target=a.target,
-               plan=list(a.plan), plain_plan=list(plain_plan),
-               views=a.views, width=a.width, height=a.height, views_per_part=a.vpp,
-               batched=dict(init_seconds=rb["init_seconds"], reached=rb["reached"],
-                            history=rb["history"]),
-               plain=[{k: v for k, v in r.items()} for r in plain])
     tb = [r[1] for r in rb["reached"]] if all(rb["reached"]) else None
-    tp = [r["seconds"] for r in plain]
-    res["batched_seconds_all"] = max(tb) if tb else None
-    res["plain_seconds_all"] = sum(tp) if all(t is not None for t in tp) else None
+    res = dict(experiment="batched_vs_plain", counts=[p["n"] for p in parts], target=a.target,
+               goals=goals, plan=list(a.plan), views=a.views, width=a.width, height=a.height,
+               views_per_part=a.vpp, eval_every=a.eval_every,
+               plain_steps_cap=a.plain_steps, batched_steps_cap=a.steps,
+               batched=dict(init_seconds=rb["init_seconds"], reached=rb["reached"],
+                            history=rb["history"], seconds_all=max(tb) if tb else None),
+               plain=arms)
     print(json.dumps(res), flush=True)
 
 
@@ -354,11 +370,23 @@ def cmd_learned(a):
                                    ((16, 16), "lpt", 64, 1, True), 1)
     xs.append(x); ts.append(t); ys.append(yp)
     log(f"tiny fitted: psnr {ps}")
-    src = prepare([octant_partition(int(a.scale * 13_300_000), seed=3, ref_factor=a.ref_factor)],
-                  cams)[0]
-    x, t, yp, ps = fitted_examples(src, cams, a.fit_steps, a.plan, 3)
+    if a.fit_source == "highres":
+        # the high-resolution partition: the octant of the field on a 2048^3
+        # grid with ghost cells, 13.3M Gaussians, its own 64 views at 3840x2160
+        n_hr = int(a.scale * workloads.HIGHRES["n"])
+        hr = workloads.highres_partition(dict(n=n_hr, n_ref=n_hr), device="cuda")
+        src = dict(points=hr["points"], normals=hr["normals"], n=len(hr["points"]))
+        src["targets"], src["masks"] = workloads.render_targets_gpu(hr["reference"], hr["cams"])
+        src_cams = hr["cams"]
+        del hr
+    else:
+        src = prepare([octant_partition(int(a.scale * 13_300_000), seed=3,
+                                        ref_factor=a.ref_factor)], cams)[0]
+        src_cams = cams
+    x, t, yp, ps = fitted_examples(src, src_cams, a.fit_steps, a.plan, 3)
     xs.append(x); ts.append(t); ys.append(yp)
-    log(f"octant fitted (n={src['n']}): psnr {ps}")
+    log(f"{a.fit_source} partition fitted (n={src['n']}, "
+        f"{src_cams[0]['width']}x{src_cams[0]['height']}): psnr {ps}")
     del src
     x = torch.cat(xs); t = torch.cat(ts); yp = torch.cat(ys)
     # held-out tenth for the fallback rule
@@ -408,6 +436,8 @@ def main(argv=None):
     ap.add_argument("--scale", type=float, default=1.0, help="multiplies every Gaussian count")
     ap.add_argument("--target", type=float, default=35.0)
     ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--plain-steps", type=int, default=5000,
+                    help="batched experiment: step cap of each partition's plain run")
     ap.add_argument("--eval-every", type=int, default=100)
     ap.add_argument("--views", type=int, default=64)
     ap.add_argument("--width", type=int, default=1920)
@@ -415,8 +445,13 @@ def main(argv=None):
     ap.add_argument("--vpp", type=int, default=4)
     ap.add_argument("--ref-factor", type=float, default=2.0)
     ap.add_argument("--field", choices=["sphere", "mixing"], default="sphere")
-    ap.add_argument("--plain-plan", choices=["same", "default"], default="same")
+    ap.add_argument("--plain-plan", default="same",
+                    help="batched experiment: plain arms to run, 'same', 'default' or "
+                         "'same,default'")
     ap.add_argument("--fit-steps", type=int, default=2000)
+    ap.add_argument("--fit-source", choices=["highres", "octant"], default="highres",
+                    help="learned experiment: the second fitted partition, the 4K octant on a "
+                         "2048^3 grid or an octant at the experiment's views")
     ap.add_argument("--mlp-steps", type=int, default=2000)
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--schedule", default="lpt")

@@ -248,7 +248,7 @@ def _batched_step_vs_oracle(parts, lam, per_pair):
     img = bt.bufs.image.cpu().numpy()
     drec = bt.bufs.d_rec.cpu().numpy().astype(np.float64)
     po = bt.views.pair_offset_host
-    b1 = np.float32(0.9)
+    b1 = np.float32(bt.adam.betas[0])           # 0.9^4 with the batch-size rule
     inv = np.float32(1.0) / (np.float32(1.0) - b1)
     gpu_g = {k: (v.cpu().numpy() * inv).astype(np.float64) for k, v in bt.m.items()}
     off = 0
@@ -288,7 +288,7 @@ def test_batched_step_matches_oracle(parts):
     with the L1 loss alone: every slot's image, every pair's record gradient
     (per element, term-mass bound) and every partition's parameter gradient
     (the mean over its four views, read back from Adam's first moment
-    m = (1 - beta1) g after the first step) against the oracle run partition
+    m = (1 - beta1) g after the first step, beta1 = 0.9^4) against the oracle run partition
     by partition and view by view.  With the L1 sign decided the same way on
     both sides the image gradient is identical, so every difference comes
     from the launch itself."""
