@@ -549,6 +549,21 @@ def main():
     roof["launches"] = len(timed_views)
     roof["launch_ms"] = round(sums[dom] / len(timed_views), 4)
     roof["views"] = timed_views
+    roof["mask_coverage"] = round(coverage, 4)
+    if roof["traffic"]:
+        # HBM rate of the dominant kernel: its counted bytes over this run's launch time
+        roof["hbm_tbps"] = roof["traffic"] / (roof["launch_ms"] * 1e-3) / 1e12
+        roof["hbm_frac"] = roof["hbm_tbps"] * 1e12 / PEAK_HBM
+    # VALU, LDS and HBM rates from the committed counter passes of this plan
+    # (per-dispatch counters over the same dispatches' durations), reported
+    # while the kernel's source is unchanged
+    from paper_2509_12138_amd import kcounters as _kc
+    kc = None if highres else _kc.lookup(
+        os.path.join(ROOT, "paper_2509_12138_amd", "kernel_counters.json"), roof["kernel"], plan_str)
+    if kc:
+        roof["counters"] = {k: kc.get(k) for k in ("mean_us", "valu_busy", "valu_lanes", "lds_tbps",
+                                                   "lds_frac", "lds_busy", "lds_conflict",
+                                                   "hbm_tbps", "hbm_frac")}
     out = {
         "metric": METRIC,
         "value": round(mpix, 3),

@@ -2,9 +2,9 @@
 
     python -m paper_2509_12138_amd.profsum <kernel_trace.csv> --steps K [--pmc <counter.csv> ...]
 
-bench.py launches one k_project per training step and one more afterwards
-(the untimed replay that counts evaluations), so the timed window is the
-K steps that precede the last k_project dispatch.  Prints per-kernel
+The timed window is the last K training steps of the run (a step runs from
+its k_project to its projection backward + Adam); the renders bench.py runs
+afterwards to count the work are left out.  Prints per-kernel
 dispatch counts, mean durations and share of the step, as Markdown.  With
 --pmc, adds per-dispatch FETCH_SIZE / WRITE_SIZE (KiB, raw counter values) averaged
 over the dispatches of each kernel in counter-collection CSVs.
@@ -24,12 +24,22 @@ def short(name):
 
 
 def timed_window(rows, steps):
-    proj = [r for r in rows if short(r["Kernel_Name"]).split("<")[0] == "k_project"]
-    if len(proj) < steps + 1:
-        raise SystemExit(f"only {len(proj)} k_project dispatches; need {steps + 1}")
-    t0 = int(proj[-steps - 1]["Start_Timestamp"])
-    t1 = int(proj[-1]["Start_Timestamp"])
-    return t0, t1
+    """The last `steps` training steps: each ends with the projection
+    backward (fused with Adam) and begins at the projection before it;
+    renders after training (bench.py's work count) are left out."""
+    ends = [i for i, r in enumerate(rows)
+            if short(r["Kernel_Name"]).split("<")[0] in ("k_project_bwd_adam", "k_project_bwd")]
+    if len(ends) < steps:
+        raise SystemExit(f"only {len(ends)} training steps in the trace; need {steps}")
+    first = ends[-steps]
+    start = max(i for i in range(first) if short(rows[i]["Kernel_Name"]).split("<")[0] ==
+                "k_project")
+    last = ends[-1]
+    # the step's closing kernels (Adam step counter) run right after
+    while last + 1 < len(rows) and short(rows[last + 1]["Kernel_Name"]).split("<")[0] in (
+            "k_adam_step_inc", "k_adam"):
+        last += 1
+    return int(rows[start]["Start_Timestamp"]), int(rows[last]["End_Timestamp"]) + 1
 
 
 def summarise(trace, steps):
@@ -65,7 +75,7 @@ def main():
     dur, total, wall = summarise(args.trace, args.steps)
     pmc = counters(args.pmc)
     print(f"Timed window: {args.steps} steps, {wall / 1e3:.1f} us per step (first k_project to "
-          f"the next step's), kernels busy {total / args.steps / 1e3:.1f} us per step\n")
+          f"the last step's end), kernels busy {total / args.steps / 1e3:.1f} us per step\n")
     head = "| kernel | dispatches/step | mean us | us/step | share |"
     rule = "|---|---:|---:|---:|---:|"
     if pmc:
