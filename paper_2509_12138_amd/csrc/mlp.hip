@@ -2,18 +2,23 @@
 // maps 16-nearest-neighbour features of an isosurface point (the points of
 // Sec. II "Isosurface Extraction") to the initial log-scale, rotation and
 // opacity of its Gaussian.  BF16 weights and activations on the MFMA matrix
-// cores (v_mfma_f32_16x16x16_bf16), FP32 accumulation and biases; the FP32
-// master weights are rounded to bf16 when a work-group stages them in LDS.
+// cores, FP32 accumulation and biases; the FP32 master weights are rounded to
+// bf16 when a work-group stages them in LDS.
 //
-// MFMA 16x16x16 operand layout (wave64, lane l, j = 0..3):
+// Products whose K runs over features or hidden units (the layers, and the
+// backward's dZ W^T) use v_mfma_f32_16x16x32_bf16, lane l, j = 0..7:
+//   A[m][k]: m = l % 16, k = 8 (l / 16) + j      (8 consecutive k per lane)
+//   B[k][n]: n = l % 16, k = 8 (l / 16) + j
+// The weight gradients, whose K runs over a tile's 16 points, and dY W3^T
+// (K = 8 outputs) use v_mfma_f32_16x16x16_bf16, lane l, j = 0..3:
 //   A[m][k]: m = l % 16, k = 4 (l / 16) + j      (4 consecutive k per lane)
 //   B[k][n]: n = l % 16, k = 4 (l / 16) + j
-//   C[m][n]: n = l % 16, m = 4 (l / 16) + j
-// A C-layout fragment over 16 points is therefore, unchanged, the A operand
-// of the transposed matrix with K = those 16 points, and also a B operand
-// with K = those points: the weight-gradient products H^T dZ take both
-// operands straight from registers; only the layer-to-layer hand-offs go
-// through LDS.  One wave owns one 16-point tile at a time.
+// Both write C[m][n]: n = l % 16, m = 4 (l / 16) + j.  A C-layout fragment
+// over 16 points is therefore, unchanged, the A operand of the transposed
+// matrix with K = those 16 points, and also a B operand with K = those
+// points: the weight-gradient products H^T dZ take both operands straight
+// from registers; only the layer-to-layer hand-offs go through LDS.  One
+// wave owns one 16-point tile at a time.
 //
 //   gs_mlp_features  16-NN offsets (divided by their mean distance) and
 //                    neighbour normals in the point's local frame -> bf16 x
@@ -46,8 +51,22 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Eight consecutive bf16 of row (row0 + l%16), columns k0 + 8(l/16) .. +7 of
+// a row-major bf16 matrix in LDS with `stride` elements per row (16-B loads:
+// stride and k0 are multiples of 8).
+__device__ __forceinline__ bf16x8 frag8(const uint16_t* m, int stride, int row0, int k0) {
+  const int l = threadIdx.x & 63;
+  return *reinterpret_cast<const bf16x8*>(m + (row0 + (l & 15)) * stride + k0 + 8 * (l >> 4));
 }
 
 // Four consecutive bf16 of row (row0 + l%16), columns k0 + 4(l/16) .. +3 of a
@@ -168,10 +187,10 @@ __device__ __forceinline__ void tile_forward(const MlpLds& L, WaveLds& Wv, f32x4
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) z1[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int kt = 0; kt < kIn / 16; ++kt) {
-    const bf16x4 a = frag(Wv.x, kIn, 0, 16 * kt);
+  for (int kt = 0; kt < kIn / 32; ++kt) {
+    const bf16x8 a = frag8(Wv.x, kIn, 0, 32 * kt);
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) z1[nt] = mfma(a, frag(L.w1t, kIn, 16 * nt, 16 * kt), z1[nt]);
+    for (int nt = 0; nt < 4; ++nt) z1[nt] = mfma32(a, frag8(L.w1t, kIn, 16 * nt, 32 * kt), z1[nt]);
   }
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
@@ -186,10 +205,10 @@ __device__ __forceinline__ void tile_forward(const MlpLds& L, WaveLds& Wv, f32x4
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) z2[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int kt = 0; kt < kHid / 16; ++kt) {
-    const bf16x4 a = frag(Wv.h1, kHid, 0, 16 * kt);
+  for (int kt = 0; kt < kHid / 32; ++kt) {
+    const bf16x8 a = frag8(Wv.h1, kHid, 0, 32 * kt);
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) z2[nt] = mfma(a, frag(L.w2t, kHid, 16 * nt, 16 * kt), z2[nt]);
+    for (int nt = 0; nt < 4; ++nt) z2[nt] = mfma32(a, frag8(L.w2t, kHid, 16 * nt, 32 * kt), z2[nt]);
   }
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
@@ -203,8 +222,8 @@ __device__ __forceinline__ void tile_forward(const MlpLds& L, WaveLds& Wv, f32x4
   wave_lds_sync();
   y = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int kt = 0; kt < kHid / 16; ++kt)
-    y = mfma(frag(Wv.h2, kHid, 0, 16 * kt), frag(L.w3t, kHid, 0, 16 * kt), y);
+  for (int kt = 0; kt < kHid / 32; ++kt)
+    y = mfma32(frag8(Wv.h2, kHid, 0, 32 * kt), frag8(L.w3t, kHid, 0, 32 * kt), y);
 #pragma unroll
   for (int j = 0; j < 4; ++j) y[j] += L.b3[l & 15];
 }
@@ -332,8 +351,8 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_bwd(const uint16_t* __restr
     for (int nt = 0; nt < 4; ++nt) {
       f32x4 d = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kt = 0; kt < 4; ++kt)
-        d = mfma(frag(S.dz2, kHid, 0, 16 * kt), frag(L.w2n, kHid, 16 * nt, 16 * kt), d);
+      for (int kt = 0; kt < kHid / 32; ++kt)
+        d = mfma32(frag8(S.dz2, kHid, 0, 32 * kt), frag8(L.w2n, kHid, 16 * nt, 32 * kt), d);
       float v[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) v[j] = z1[nt][j] > 0.f ? d[j] : 0.f;
@@ -361,12 +380,13 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_bwd(const uint16_t* __restr
       for (int nt = 0; nt < 6; ++nt) {
         f32x4 d = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt) {
-          bf16x4 b;
+        for (int kt = 0; kt < kHid / 32; ++kt) {
+          bf16x8 b;
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            b[j] = (short)L.w1t[(16 * kt + 4 * (l >> 4) + j) * kIn + 16 * nt + (l & 15)];
-          d = mfma(frag(S.h1, kHid, 0, 16 * kt), b, d);
+          for (int j = 0; j < 8; ++j)
+            b[j] = __builtin_bit_cast(
+                __bf16, L.w1t[(32 * kt + 8 * (l >> 4) + j) * kIn + 16 * nt + (l & 15)]);
+          d = mfma32(frag8(S.h1, kHid, 0, 32 * kt), b, d);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {

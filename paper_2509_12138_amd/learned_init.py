@@ -245,3 +245,39 @@ def choose_init(mlp, points, normals, held_x=None, held_dbar=None, held_t=None,
     if p is None:
         return plain_init(points, normals), "plain"
     return p, "learned"
+
+
+def mlp_bench(n=4_000_000, reps=10, seed=0):
+    """Time the network's forward and backward kernels on n seeded bf16
+    feature rows (the size of the learned partition): mean ms per call of
+    gs_mlp_fwd and gs_mlp_bwd (no dx), HIP events on the launch stream."""
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    x = (torch.randn((n, 96), generator=g, device="cuda") * 0.5).to(torch.bfloat16)
+    x = x.view(torch.int16).contiguous()
+    mlp = InitMLP.random(seed=seed)
+    dy = torch.randn((n, 8), generator=g, device="cuda") * 1e-3
+    grads = {k: torch.zeros_like(v) for k, v in mlp.w.items()}
+    y = mlp.forward(x)
+    mlp.backward(x, dy, grads)
+    torch.cuda.synchronize()
+    out = {}
+    for name, fn in (("fwd", lambda: mlp.forward(x, y)), ("bwd", lambda: mlp.backward(x, dy, grads))):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = e0.elapsed_time(e1) / reps
+    out["n"] = n
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="time the initialisation network's kernels")
+    ap.add_argument("--n", type=int, default=4_000_000)
+    ap.add_argument("--reps", type=int, default=10)
+    a = ap.parse_args()
+    print(json.dumps(mlp_bench(a.n, a.reps)), flush=True)
