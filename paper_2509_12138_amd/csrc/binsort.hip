@@ -14,7 +14,8 @@
 //                  then one thread per duplicate (coalesced writes) finds its
 //                  pair by binary search in LDS and writes key / pair index
 //   k_radix_hist / k_radix_rowscan / k_radix_scatter   LSD radix passes on
-//                  8-bit digits over the tile bits of the keys only (the
+//                  8-bit digits (9-bit when that saves a pass: 17-18 tile
+//                  bits) over the tile bits of the keys only (the
 //                  emission is already in (depth, pair) order and the passes
 //                  are stable); the scatter ranks stably with wave64 ballots
 //                  and stages the block in LDS so global writes are runs per
@@ -30,11 +31,13 @@ constexpr int kScanItems = kScanThreads * kScanPer;   // pairs per scan/emit blo
 constexpr int kSortThreads = 256;
 constexpr int kSortPer = 8;
 constexpr int kSortItems = kSortThreads * kSortPer;   // keys per radix block
-constexpr int kRadixBits = 8;
+constexpr int kRadixBits = 8;      // digit width of the depth passes and of most tile passes
+constexpr int kRadixBitsMax = 9;   // tile keys of 17-18 bits: two 9-bit passes instead of three
 // presort key fields: depth bits 0-31, slot 32-41, tile count 42-63
 constexpr int kKeySlotShift = 32, kKeyTilesShift = 42;
 constexpr uint64_t kKeySlotMask = (1ull << (kKeyTilesShift - kKeySlotShift)) - 1;
 constexpr int kRadix = 1 << kRadixBits;
+constexpr int kRadixMax = 1 << kRadixBitsMax;
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -57,8 +60,8 @@ static BinSortLayout layout(int64_t m, int64_t cap) {
   L.off_keys_alt = o; o += align256(sizeof(uint64_t) * (size_t)(cap > 0 ? cap : 1));
   L.off_vals_alt = o; o += align256(sizeof(uint32_t) * (size_t)(cap > 0 ? cap : 1));
   L.off_emit_alt = o; o += align256(sizeof(uint32_t) * (size_t)(cap > 0 ? cap : 1));
-  L.off_hist = o; o += align256(sizeof(uint32_t) * (size_t)kRadix * (size_t)nb_hist);
-  L.off_rowtot = o; o += align256(sizeof(uint32_t) * kRadix);
+  L.off_hist = o; o += align256(sizeof(uint32_t) * (size_t)kRadixMax * (size_t)nb_hist);
+  L.off_rowtot = o; o += align256(sizeof(uint32_t) * kRadixMax);
   for (int b = 0; b < 2; ++b) {
     L.off_pkeys[b] = o; o += align256(sizeof(uint64_t) * mm);
     L.off_pvals[b] = o; o += align256(sizeof(uint32_t) * mm);
@@ -259,13 +262,18 @@ __global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ re
 
 // ------------------------------------------------------------ radix sort
 
+// Digit counts of one block of keys: hist[digit][block].  RB-bit digits,
+// 1 << RB of them (each thread owns 1 << RB / 256).
+template <int RB>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys,
                                                              const int64_t* __restrict__ count,
                                                              int shift, int64_t nb,
                                                              uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[kRadix];
+  constexpr int R = 1 << RB, DPT = R / kSortThreads;
+  __shared__ uint32_t h[R];
   const int t = threadIdx.x;
-  h[t] = 0;
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) h[t + q * kSortThreads] = 0;
   __syncthreads();
   const int64_t n = count[0];
   const int64_t base = (int64_t)blockIdx.x * kSortItems;
@@ -273,11 +281,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
 #pragma unroll 4
     for (int k = 0; k < kSortPer; ++k) {
       int64_t i = base + k * kSortThreads + t;
-      if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (kRadix - 1)], 1u);
+      if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (R - 1)], 1u);
     }
   }
   __syncthreads();
-  hist[(int64_t)t * nb + blockIdx.x] = h[t];
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int d = t + q * kSortThreads;
+    hist[(int64_t)d * nb + blockIdx.x] = h[d];
+  }
 }
 
 // One workgroup per digit: exclusive scan of that digit's per-block counts.
@@ -329,26 +341,32 @@ __global__ __launch_bounds__(256) void k_radix_rowscan_lds(uint32_t* __restrict_
   if (threadIdx.x == 0) row_tot[blockIdx.x] = total;
 }
 
-static void launch_rowscan(uint32_t* hist, int64_t nb, uint32_t* row_tot, hipStream_t s) {
+static void launch_rowscan(uint32_t* hist, int64_t nb, uint32_t* row_tot, int digits,
+                           hipStream_t s) {
   if (nb <= kRowLds)
-    hipLaunchKernelGGL(k_radix_rowscan_lds, dim3(kRadix), dim3(256), 0, s, hist, nb, row_tot);
+    hipLaunchKernelGGL(k_radix_rowscan_lds, dim3(digits), dim3(256), 0, s, hist, nb, row_tot);
   else
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(kRadix), dim3(256), 0, s, hist, nb, row_tot);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(digits), dim3(256), 0, s, hist, nb, row_tot);
 }
 
-// vin2 / vout2 (may be NULL): a second value carried along.
+// One stable LSD pass over RB-bit digits (1 << RB of them; each thread owns
+// 1 << RB / 256 consecutive digits).  vin2 / vout2 (may be NULL): a second
+// value carried along.
+template <int RB>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, const int64_t* __restrict__ count,
     int shift, int64_t nb, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ row_tot,
     const uint32_t* __restrict__ vin2, uint32_t* __restrict__ vout2) {
+  constexpr int R = 1 << RB, DPT = R / kSortThreads;
+  static_assert(DPT >= 1 && R % kSortThreads == 0, "digits per thread");
   // LDS: per (round, wave, digit) counts; staging of the block's items
-  __shared__ uint16_t s_cnt[kSortPer][4][kRadix];   // 16 KB
+  __shared__ uint16_t s_cnt[kSortPer][4][R];         // 16 KB (8-bit), 32 KB (9-bit)
   __shared__ uint64_t s_key[kSortItems];             // 16 KB
   __shared__ uint32_t s_val[kSortItems];             // 8 KB
   __shared__ uint32_t s_val2[kSortItems];            // 8 KB
-  __shared__ uint32_t s_dstart[kRadix];              // local digit starts
-  __shared__ uint32_t s_gbase[kRadix];               // global digit base of this block
+  __shared__ uint32_t s_dstart[R];                   // local digit starts
+  __shared__ uint32_t s_gbase[R];                    // global digit base of this block
   __shared__ uint32_t s_w[4];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t n = count[0];
@@ -357,14 +375,24 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   // global base per digit = sum of all row totals of smaller digits + this
   // block's exclusive prefix within the digit's row
   {
-    uint32_t rt = row_tot[t];
+    uint32_t rt[DPT], sum = 0;
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      rt[q] = row_tot[t * DPT + q];
+      sum += rt[q];
+    }
     uint32_t tot;
-    uint32_t ex = block_exclusive_scan<uint32_t>(rt, s_w, tot);
-    s_gbase[t] = ex + hist[(int64_t)t * nb + blockIdx.x];
+    uint32_t ex = block_exclusive_scan<uint32_t>(sum, s_w, tot);
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      const int d = t * DPT + q;
+      s_gbase[d] = ex + hist[(int64_t)d * nb + blockIdx.x];
+      ex += rt[q];
+    }
   }
   {
     uint32_t* z = reinterpret_cast<uint32_t*>(&s_cnt[0][0][0]);
-    for (int i = t; i < kSortPer * 4 * kRadix / 2; i += kSortThreads) z[i] = 0u;
+    for (int i = t; i < kSortPer * 4 * R / 2; i += kSortThreads) z[i] = 0u;
   }
   __syncthreads();
   uint64_t key[kSortPer];
@@ -379,10 +407,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     key[r] = valid ? kin[i] : 0ull;
     val[r] = valid ? vin[i] : 0u;
     val2[r] = (valid && two) ? vin2[i] : 0u;
-    uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+    uint32_t d = (uint32_t)(key[r] >> shift) & (R - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int bit = 0; bit < kRadixBits; ++bit) {
+    for (int bit = 0; bit < RB; ++bit) {
       uint64_t b = __ballot((d >> bit) & 1u);
       peers &= ((d >> bit) & 1u) ? b : ~b;
     }
@@ -390,27 +418,37 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     if (valid && wrank[r] == 0) s_cnt[r][wave][d] = (uint16_t)__popcll(peers);
   }
   __syncthreads();
-  // thread t owns digit t: exclusive scan over (round, wave) in index order
+  // thread t owns its digits: exclusive scan over (round, wave) in index order
   {
-    uint32_t run = 0;
+    uint32_t run[DPT], sum = 0;
 #pragma unroll
-    for (int r = 0; r < kSortPer; ++r)
+    for (int q = 0; q < DPT; ++q) {
+      const int d = t * DPT + q;
+      run[q] = 0;
 #pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        uint32_t c = s_cnt[r][w][t];
-        s_cnt[r][w][t] = (uint16_t)run;
-        run += c;
-      }
+      for (int r = 0; r < kSortPer; ++r)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          uint32_t c = s_cnt[r][w][d];
+          s_cnt[r][w][d] = (uint16_t)run[q];
+          run[q] += c;
+        }
+      sum += run[q];
+    }
     uint32_t tot;
-    uint32_t ex = block_exclusive_scan<uint32_t>(run, s_w, tot);
-    s_dstart[t] = ex;
+    uint32_t ex = block_exclusive_scan<uint32_t>(sum, s_w, tot);
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      s_dstart[t * DPT + q] = ex;
+      ex += run[q];
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortPer; ++r) {
     int64_t i = base + r * kSortThreads + t;
     if (i < n) {
-      uint32_t d = (uint32_t)(key[r] >> shift) & (kRadix - 1);
+      uint32_t d = (uint32_t)(key[r] >> shift) & (R - 1);
       uint32_t pos = s_dstart[d] + s_cnt[r][wave][d] + wrank[r];
       s_key[pos] = key[r];
       s_val[pos] = val[r];
@@ -424,7 +462,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     int li = r * kSortThreads + t;
     if (li < nloc) {
       uint64_t k = s_key[li];
-      uint32_t d = (uint32_t)(k >> shift) & (kRadix - 1);
+      uint32_t d = (uint32_t)(k >> shift) & (R - 1);
       int64_t dst = (int64_t)s_gbase[d] + (li - (int64_t)s_dstart[d]);
       kout[dst] = k;
       vout[dst] = s_val[li];
@@ -496,7 +534,11 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   // presort of the pairs)
   int tile_bits = 0;
   while ((int64_t(1) << tile_bits) < n_tiles_all) ++tile_bits;
-  const int passes = (tile_bits + kRadixBits - 1) / kRadixBits;
+  // 17-18 tile bits (e.g. 8x8 tiles of one 3840x2160 image): two 9-bit passes
+  // instead of three 8-bit ones
+  const int rb = (tile_bits > 2 * kRadixBits && tile_bits <= 2 * kRadixBitsMax) ? kRadixBitsMax
+                                                                                : kRadixBits;
+  const int passes = (tile_bits + rb - 1) / rb;
   // emit into the buffer that the last pass will not overwrite
   uint64_t* k0 = (passes % 2 == 0) ? keys_out : keys_alt;
   uint32_t* v0 = (passes % 2 == 0) ? ids_out : vals_alt;
@@ -529,14 +571,14 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   for (int p = 0; p < 4; ++p) {
     const int shift = p * kRadixBits;
     const int a = p & 1, b = a ^ 1;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)L.nb_pairs), dim3(kSortThreads), 0, s, pk[a],
-                       count_pairs, shift, L.nb_pairs, hist);
+    hipLaunchKernelGGL(k_radix_hist<kRadixBits>, dim3((unsigned)L.nb_pairs), dim3(kSortThreads),
+                       0, s, pk[a], count_pairs, shift, L.nb_pairs, hist);
     GS_LAUNCH_CHECK("gs_bin_sort/depth_hist");
-    launch_rowscan(hist, L.nb_pairs, rowtot, s);
+    launch_rowscan(hist, L.nb_pairs, rowtot, kRadix, s);
     GS_LAUNCH_CHECK("gs_bin_sort/depth_rowscan");
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)L.nb_pairs), dim3(kSortThreads), 0, s,
-                       pk[a], pv[a], pk[b], pv[b], count_pairs, shift, L.nb_pairs, hist, rowtot,
-                       (const uint32_t*)nullptr, (uint32_t*)nullptr);
+    hipLaunchKernelGGL(k_radix_scatter<kRadixBits>, dim3((unsigned)L.nb_pairs),
+                       dim3(kSortThreads), 0, s, pk[a], pv[a], pk[b], pv[b], count_pairs, shift,
+                       L.nb_pairs, hist, rowtot, (const uint32_t*)nullptr, (uint32_t*)nullptr);
     GS_LAUNCH_CHECK("gs_bin_sort/depth_scatter");
   }
   // duplicates in depth order, then stable passes over the tile bits only
@@ -551,20 +593,30 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
                      tiles_x, (int)tiles_per_slot, k0, v0, pair_first, e0);
   GS_LAUNCH_CHECK("gs_bin_sort/emit");
   for (int p = 0; p < passes; ++p) {
-    const int shift = 32 + p * kRadixBits;
+    const int shift = 32 + p * rb;
     const uint64_t* kin = (p % 2 == 0) ? k0 : k1;
     const uint32_t* vin = (p % 2 == 0) ? v0 : v1;
     uint64_t* kout = (p % 2 == 0) ? k1 : k0;
     uint32_t* vout = (p % 2 == 0) ? v1 : v0;
     const uint32_t* ein = (p % 2 == 0) ? e0 : e1;
     uint32_t* eout = (p % 2 == 0) ? e1 : e0;
-    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)L.nb_sort), dim3(kSortThreads), 0, s, kin,
-                       count, shift, L.nb_sort, hist);
+    if (rb == kRadixBitsMax)
+      hipLaunchKernelGGL(k_radix_hist<kRadixBitsMax>, dim3((unsigned)L.nb_sort),
+                         dim3(kSortThreads), 0, s, kin, count, shift, L.nb_sort, hist);
+    else
+      hipLaunchKernelGGL(k_radix_hist<kRadixBits>, dim3((unsigned)L.nb_sort), dim3(kSortThreads),
+                         0, s, kin, count, shift, L.nb_sort, hist);
     GS_LAUNCH_CHECK("gs_bin_sort/radix_hist");
-    launch_rowscan(hist, L.nb_sort, rowtot, s);
+    launch_rowscan(hist, L.nb_sort, rowtot, 1 << rb, s);
     GS_LAUNCH_CHECK("gs_bin_sort/radix_rowscan");
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)L.nb_sort), dim3(kSortThreads), 0, s, kin,
-                       vin, kout, vout, count, shift, L.nb_sort, hist, rowtot, ein, eout);
+    if (rb == kRadixBitsMax)
+      hipLaunchKernelGGL(k_radix_scatter<kRadixBitsMax>, dim3((unsigned)L.nb_sort),
+                         dim3(kSortThreads), 0, s, kin, vin, kout, vout, count, shift, L.nb_sort,
+                         hist, rowtot, ein, eout);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<kRadixBits>, dim3((unsigned)L.nb_sort),
+                         dim3(kSortThreads), 0, s, kin, vin, kout, vout, count, shift, L.nb_sort,
+                         hist, rowtot, ein, eout);
     GS_LAUNCH_CHECK("gs_bin_sort/radix_scatter");
   }
   hipLaunchKernelGGL(k_ranges, dim3((unsigned)ceil_div(dup_capacity, 256)), dim3(256), 0, s,

@@ -112,7 +112,7 @@ def global_reference(n_ref, cams, band, seed=977):
     """Targets, masks and seam bands of a reference set sampled over the
     whole surface (white background)."""
     rp, rn = scene.sample_surface(scene.field_sphere_sines, int(n_ref), ttt.GRID, seed=seed)
-    d = scene.knn_mean_distance(rp, 3)
+    d = workloads._knn_scale(rp, "cuda")
     ref = workloads.reference_discs(rp, rn, d)
     targets, masks = workloads.render_targets_gpu(ref, cams, bg=WHITE)
     # x of the visible surface per pixel: render x as grey level, divide out

@@ -118,6 +118,9 @@ def run_binsort(ops, tb, nt, depth, slot, W, H, tile, S, cap):
     (5000, 1, (16, 16), 300, 200, 0),        # several scan blocks, one slot
     (9000, 3, (8, 8), 130, 75, 1),           # ragged tiles, three slots
     (300000, 2, (16, 16), 1920, 1080, 2),    # many radix blocks, 1080p tiles
+    (400000, 1, (8, 8), 3840, 2160, 3),      # 129,600 tiles: 17 tile bits, two 9-bit passes
+    (400000, 2, (8, 8), 3840, 2160, 4),      # 259,200 tiles: 18 tile bits, two 9-bit passes
+    (200000, 3, (8, 8), 3840, 2160, 6),      # 388,800 tiles: 19 tile bits, three 8-bit passes
 ])
 def test_bin_sort_bit_exact(ops, m, S, tile, W, H, seed):
     say("bin_sort", m, S, tile, W, H)
