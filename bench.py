@@ -526,8 +526,9 @@ def main():
     blended = work["blended"]
     drawn = work["drawn"]
     list_pairs = work["list_positions"]
-    dom = "raster_bwd" if t_bwd >= max(v for k, v in stage_ms.items() if k != "raster_bwd") else \
-        max(stage_ms, key=stage_ms.get)
+    # the dominant single kernel is one of the two raster passes: the bin/sort
+    # stage can take longer in all, but it is a chain of ~20 shorter launches
+    dom = "raster_bwd" if t_bwd >= t_fwd else "raster_fwd"
     evals_fwd = evals_bwd = blended
     if dom == "raster_bwd":
         achieved = evals_bwd * OPS_PER_EVAL_BWD / (sums["raster_bwd"] * 1e-3)
