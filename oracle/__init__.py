@@ -150,7 +150,8 @@ def _proj_arrays(proj):
             _f64(proj["opacity"]), _f64(proj["rgb"]), tb, valid)
 
 
-def render(proj, W, H, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None, band=1e-5):
+def render(proj, W, H, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None, band=1e-5,
+           support=True):
     """Composite every pixel front to back (3D-GS rasteriser definition).
 
     proj holds SoA mean2d [2,n], conic [3,n], depth, opacity, rgb [3,n],
@@ -158,11 +159,16 @@ def render(proj, W, H, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None, band=1e-5
     Returns image [3,H,W], T_final, n_contrib, n_blended, ambiguous ([H,W]);
     pixels outside the window are left zero.  ``ambiguity`` holds the reason
     bits of an ambiguous pixel: 1 power near 0, 2 alpha near 1/255, 4 alpha
-    near 0.99, 8 transmittance near the cut-off, 16 near-equal depths.
+    near 0.99, 8 transmittance near the cut-off, 16 near-equal depths, 32 a
+    pair listed on the pixel's tile by an ambiguous decision before its last
+    blended entry (only n_contrib, a list position, can differ there).
     ``band`` is the relative half-width of the alpha and cut-off guard bands
     (1e-5 for records given to both sides in the same FP32 values; wider
     where the other side computes its records itself, to the projection's
-    own tolerance).  It only classifies pixels.
+    own tolerance).  It only classifies pixels.  ``support`` lists a pair on
+    the tiles that meet its widened support (``support_tiles``, the binning
+    the method uses); False lists it on every tile of its bbox.  Images,
+    T_final and n_blended do not depend on it.
     """
     lib = _load()
     n, m2, cn, dp, op, rgb, tb, valid = _proj_arrays(proj)
@@ -172,7 +178,7 @@ def render(proj, W, H, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None, band=1e-5
     bgv = _f64(bg)
     lib.or_render(ctypes.c_int64(n), _p(m2), _p(cn), _p(dp), _p(op), _p(rgb), _p(tb), _p(valid),
                   W, H, tile[0], tile[1], _p(bgv), x0, y0, x1, y1, _p(img), _p(T), _p(nc),
-                  _p(nb), _p(amb), ctypes.c_double(band))
+                  _p(nb), _p(amb), ctypes.c_double(band), ctypes.c_int(1 if support else 0))
     return dict(image=img, T_final=T, n_contrib=nc, n_blended=nb, ambiguous=amb.astype(bool),
                 ambiguity=amb)
 
@@ -229,12 +235,49 @@ def project_bwd(params, cam, grads2d, tile=(16, 16)):
 # Binning + sort
 # --------------------------------------------------------------------------
 
-def bin_sort(tile_bbox, n_tiles, depth_f32, slot, tiles_x, tiles_per_slot, n_slots):
+LIST_BAND = 2e-4   # relative band of the single-precision listing decisions
+
+
+def support_tiles(mean2d, conic, opacity, tile_bbox, valid, tile=(16, 16), band=LIST_BAND):
+    """Tiles of each pair's tile bbox that meet its widened support.
+
+    SoA inputs mean2d [2,n], conic [3,n], opacity [n], tile_bbox [4,n] and
+    valid [n].  A tile is listed when its pixel-centre rectangle meets
+    {d : d^T conic d <= 2 ln(255 o) + 0.02 + 1e-5 M} (M bounds the terms of
+    the quadratic form over the bbox): outside it no pixel centre passes the
+    alpha >= 1/255 test.  Returns (mask, amb) uint64 [n]: bit (ty - ty0) *
+    span + (tx - tx0) of mask is set for a listed tile (mask 0 for a bbox of
+    more than 64 tiles, all listed), of amb for a decision within ``band``
+    of the threshold.
+    """
+    lib = _load()
+    n = np.asarray(opacity).shape[0]
+    m2 = _f64(mean2d); cn = _f64(conic); op = _f64(opacity)
+    tb = np.ascontiguousarray(tile_bbox, dtype=np.int32)
+    va = np.ascontiguousarray(valid, dtype=np.int32)
+    mask = np.zeros(n, np.uint64); amb = np.zeros(n, np.uint64)
+    lib.or_support_tiles(ctypes.c_int64(n), _p(m2), _p(cn), _p(op), _p(tb), _p(va),
+                         tile[0], tile[1], ctypes.c_double(band), _p(mask), _p(amb))
+    return mask, amb
+
+
+def sup_from_records(rec):
+    """The listing inputs of pair-major FP32 records [m,12]: mean x, y, conic
+    a, b, c and opacity, as FP64 [m,6]."""
+    return np.ascontiguousarray(np.asarray(rec, np.float32)[:, 0:6], dtype=np.float64)
+
+
+def bin_sort(tile_bbox, n_tiles, depth_f32, slot, tiles_x, tiles_per_slot, n_slots, sup=None,
+             tile=(16, 16), band=LIST_BAND, details=False):
     """Emit (tile, depth) keys per pair and sort them stably (plain definition).
 
     tile_bbox [m,4] pair-major (tx0, ty0, tx1, ty1); depth_f32 float32 [m]
-    (its raw bits form the low key word).  Returns keys u64, ids u32 and
-    ranges u32 [n_slots*tiles_per_slot, 2].
+    (its raw bits form the low key word).  sup [m,6] (mean x, y, conic a, b,
+    c, opacity; see ``sup_from_records``) lists each pair on the tiles of
+    ``support_tiles``; None lists it on every bbox tile.  Returns keys u64,
+    ids u32 and ranges u32 [n_slots*tiles_per_slot, 2]; with details=True
+    also the entry count of every pair and whether any of its listing
+    decisions is ambiguous (within ``band``).
     """
     lib = _load()
     tb = np.ascontiguousarray(tile_bbox, dtype=np.int32).reshape(-1, 4)
@@ -242,13 +285,17 @@ def bin_sort(tile_bbox, n_tiles, depth_f32, slot, tiles_x, tiles_per_slot, n_slo
     nt = np.ascontiguousarray(n_tiles, dtype=np.int32)
     db = np.ascontiguousarray(np.asarray(depth_f32, dtype=np.float32).view(np.uint32))
     sl = np.ascontiguousarray(slot, dtype=np.int32)
-    total = int(np.maximum(nt, 0).sum())
+    sp = None if sup is None else np.ascontiguousarray(sup, dtype=np.float64).reshape(-1, 6)
+    count = np.zeros(max(m, 1), np.int32); amb = np.zeros(max(m, 1), np.uint8)
+    args = (ctypes.c_int64(m), _p(tb), _p(nt), None if sp is None else _p(sp), tile[0], tile[1],
+            ctypes.c_double(band), _p(db), _p(sl), tiles_x, tiles_per_slot, n_slots)
+    total = int(lib.or_bin_sort(*args, ctypes.c_int64(-1), None, None, None, _p(count), _p(amb)))
     keys = np.zeros(max(total, 1), np.uint64); ids = np.zeros(max(total, 1), np.uint32)
     ranges = np.zeros((n_slots * tiles_per_slot, 2), np.uint32)
-    got = lib.or_bin_sort(ctypes.c_int64(m), _p(tb), _p(nt), _p(db), _p(sl), tiles_x,
-                          tiles_per_slot, n_slots, ctypes.c_int64(total), _p(keys), _p(ids),
-                          _p(ranges))
+    got = lib.or_bin_sort(*args, ctypes.c_int64(total), _p(keys), _p(ids), _p(ranges), None, None)
     assert got == total
+    if details:
+        return keys[:total], ids[:total], ranges, count[:m], amb[:m].astype(bool)
     return keys[:total], ids[:total], ranges
 
 

@@ -16,8 +16,8 @@
  * tie-break, colour model) are listed with the design notes.  Every number is
  * FP64.  There is no tiling, blocking or reordering beyond what a definition
  * states: the per-pixel loop runs over ALL Gaussians in (depth, index) order
- * and only consults a Gaussian's tile bbox because the method's own binning
- * defines the per-pixel list that way.
+ * and only consults a Gaussian's tile set (or_support_tiles) because the
+ * method's own binning defines the per-pixel list that way.
  *
  * Build: gcc -O2 -fopenmp -fPIC -shared gs_oracle.c -o liboracle.so -lm
  */
@@ -320,6 +320,113 @@ static int64_t sorted_order(int64_t n, const double* depth, const int32_t* valid
   return cnt;
 }
 
+/* ---------------------------------------------------------------------- */
+/* Tiles a pair is binned to                                                */
+/* ---------------------------------------------------------------------- */
+
+/* A pair is listed on the tiles of its tile bbox whose pixel-centre
+ * rectangle [tx tw + 1/2, tx tw + tw - 1/2] x [ty th + 1/2, ty th + th - 1/2]
+ * meets its support (alpha >= 1/255: Q(d) = d^T conic d <= 2 ln(255 o)),
+ * widened by a margin mu = 0.02 + 1e-5 M that absorbs single-precision
+ * rounding (M = a X^2 + 2|b| X Y + c Y^2 bounds the magnitudes of the terms
+ * of Q over the bbox, X and Y the largest |dx|, |dy| to its pixel-centre
+ * extents).  A tile whose rectangle misses the widened support holds no
+ * pixel centre where the pair can pass the alpha test, so leaving it out
+ * changes no image.  Pairs whose bbox has more than OR_MASK_TILES tiles are
+ * listed on all of them.                                                   */
+#define OR_MASK_TILES 64
+
+/* min over the rectangle [dx0,dx1] x [dy0,dy1] of a dx^2 + 2 b dx dy + c dy^2
+ * (positive definite): zero if the rectangle holds the origin, else the
+ * least of the four edge minima, each at the clamped stationary point.     */
+static double rect_min_quad(double dx0, double dx1, double dy0, double dy1, double a, double b,
+                            double c) {
+  if (dx0 <= 0 && dx1 >= 0 && dy0 <= 0 && dy1 >= 0) return 0.0;
+  double best = INFINITY;
+  for (int e = 0; e < 2; ++e) {
+    double dx = e ? dx1 : dx0;                       /* vertical edge     */
+    double dy = -b * dx / c;
+    dy = dy < dy0 ? dy0 : (dy > dy1 ? dy1 : dy);
+    double q = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy;
+    if (q < best) best = q;
+    dy = e ? dy1 : dy0;                              /* horizontal edge   */
+    dx = -b * dy / a;
+    dx = dx < dx0 ? dx0 : (dx > dx1 ? dx1 : dx);
+    q = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy;
+    if (q < best) best = q;
+  }
+  return best;
+}
+
+/* Tile set of one pair with mean (mx, my), conic (a, b, c), opacity o and
+ * tile bbox (tx0, ty0, tx1, ty1): bit (ty - ty0) * span + (tx - tx0) of
+ * *mask is set when tile (tx, ty) is listed; *mask = 0 when the bbox has
+ * more than OR_MASK_TILES tiles (all are listed).  *amb marks the tiles
+ * whose decision lies within band * threshold + 1e-6 M of the threshold,
+ * where a single-precision evaluation may decide the other way.           */
+static void support_mask(double mx, double my, double a, double b, double c, double o, int tx0,
+                         int ty0, int tx1, int ty1, int tw, int th, double band, uint64_t* mask,
+                         uint64_t* amb) {
+  *mask = 0; *amb = 0;
+  int span = tx1 - tx0 + 1;
+  if ((int64_t)span * (ty1 - ty0 + 1) > OR_MASK_TILES) return;
+  double X0 = fabs(tx0 * (double)tw + 0.5 - mx), X1 = fabs(tx1 * (double)tw + tw - 0.5 - mx);
+  double Y0 = fabs(ty0 * (double)th + 0.5 - my), Y1 = fabs(ty1 * (double)th + th - 0.5 - my);
+  double X = X0 > X1 ? X0 : X1, Y = Y0 > Y1 ? Y0 : Y1;
+  double M = a * X * X + 2.0 * fabs(b) * X * Y + c * Y * Y;
+  double thr = 2.0 * log(255.0 * o) + 0.02 + 1e-5 * M;
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      double q = rect_min_quad(tx * (double)tw + 0.5 - mx, tx * (double)tw + tw - 0.5 - mx,
+                               ty * (double)th + 0.5 - my, ty * (double)th + th - 0.5 - my, a,
+                               b, c);
+      uint64_t bit = 1ull << ((ty - ty0) * span + (tx - tx0));
+      if (q <= thr) *mask |= bit;
+      if (fabs(q - thr) <= band * thr + 1e-6 * M) *amb |= bit;
+    }
+}
+
+/* support_mask of every pair p (SoA mean2d [2][n], conic [3][n], opacity
+ * [n], tile_bbox [4][n]); pairs with valid[p] == 0 get zero masks.         */
+void or_support_tiles(int64_t n, const double* mean2d, const double* conic,
+                      const double* opacity, const int32_t* tile_bbox, const int32_t* valid,
+                      int tw, int th, double band, uint64_t* mask, uint64_t* amb) {
+  for (int64_t p = 0; p < n; ++p) {
+    mask[p] = 0; amb[p] = 0;
+    if (!valid[p]) continue;
+    support_mask(mean2d[p], mean2d[n + p], conic[p], conic[n + p], conic[2 * n + p], opacity[p],
+                 tile_bbox[p], tile_bbox[n + p], tile_bbox[2 * n + p], tile_bbox[3 * n + p], tw,
+                 th, band, &mask[p], &amb[p]);
+  }
+}
+
+/* Is tile (tx, ty) on pair g's list: 0 no, 1 yes; 2 no and 3 yes where the
+ * decision is ambiguous.                                                   */
+static int listed(int64_t n, int64_t g, int tx, int ty, const int32_t* tile_bbox,
+                  const uint64_t* mask, const uint64_t* amb) {
+  int tx0 = tile_bbox[g], ty0 = tile_bbox[n + g], tx1 = tile_bbox[2 * n + g],
+      ty1 = tile_bbox[3 * n + g];
+  if (tx < tx0 || ty < ty0 || tx > tx1 || ty > ty1) return 0;
+  int span = tx1 - tx0 + 1;
+  if (!mask || (int64_t)span * (ty1 - ty0 + 1) > OR_MASK_TILES) return 1;
+  uint64_t bit = 1ull << ((ty - ty0) * span + (tx - tx0));
+  int on = (mask[g] & bit) ? 1 : 0;
+  return (amb && (amb[g] & bit)) ? 2 + on : on;
+}
+
+/* Tile sets of a render call (NULL masks when use_support is 0: every
+ * bbox tile).                                                              */
+static void render_masks(int64_t n, const double* mean2d, const double* conic,
+                         const double* opacity, const int32_t* tile_bbox, const int32_t* valid,
+                         int tw, int th, int use_support, double band, uint64_t** mask,
+                         uint64_t** amb) {
+  *mask = *amb = NULL;
+  if (!use_support) return;
+  *mask = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+  *amb = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+  or_support_tiles(n, mean2d, conic, opacity, tile_bbox, valid, tw, th, band, *mask, *amb);
+}
+
 typedef struct {
   int64_t g;
   double alpha, a, e, T, dx, dy;
@@ -337,7 +444,8 @@ typedef struct {
 static int64_t composite_pixel(int px, int py, int tw, int th, int64_t n, int64_t cnt,
                                const int64_t* order, const double* mean2d, const double* conic,
                                const double* depth, const double* opacity, const double* rgb,
-                               const int32_t* tile_bbox, const double* bg, double out[3],
+                               const int32_t* tile_bbox, const uint64_t* mask,
+                               const uint64_t* mamb, const double* bg, double out[3],
                                double* T_out, int32_t* ncontrib_out, uint8_t* amb_out,
                                or_blend* rec, double band_rel) {
   double T = 1.0, C[3] = {0, 0, 0};
@@ -351,11 +459,14 @@ static int64_t composite_pixel(int px, int py, int tw, int th, int64_t n, int64_
    * next passing entry is the one that could take the stopping one's place */
   double prev_depth = -1.0;
   int stopped = 0;
+  int64_t first_amb = 0;      /* list position of the first ambiguous listing */
   for (int64_t k = 0; k < cnt; ++k) {
     int64_t g = order[k];
-    if (tx < tile_bbox[g] || ty < tile_bbox[n + g] || tx > tile_bbox[2 * n + g] ||
-        ty > tile_bbox[3 * n + g])
-      continue;                                   /* not in this tile's list */
+    int on = listed(n, g, tx, ty, tile_bbox, mask, mamb);
+    /* an entry whose listing is ambiguous cannot blend here (it lies outside
+     * the widened support) but shifts the list positions after it */
+    if (on >= 2 && first_amb == 0 && !stopped) first_amb = pos + 1;
+    if (on == 0 || on == 2) continue;             /* not in this tile's list */
     /* entries are in ascending depth: past the band nothing can tie */
     if (stopped && depth[g] - prev_depth > 5e-7 * fabs(depth[g])) break;
     ++pos;
@@ -392,6 +503,7 @@ static int64_t composite_pixel(int px, int py, int tw, int th, int64_t n, int64_
     last = pos;
     ++nb;
   }
+  if (first_amb > 0 && first_amb < last) amb |= 32;   /* n_contrib may differ */
   for (int ch = 0; ch < 3; ++ch) out[ch] = C[ch] + T * bg[ch];
   if (T_out) *T_out = T;
   if (ncontrib_out) *ncontrib_out = (int32_t)last;
@@ -399,24 +511,35 @@ static int64_t composite_pixel(int px, int py, int tw, int th, int64_t n, int64_
   return nb;
 }
 
+/* Minimum relative band of the listing decisions (single-precision
+ * evaluation of the tile test on the same records).                       */
+#define OR_LIST_BAND 2e-4
+
 /* Render the pixel window [x0,x1) x [y0,y1) of one W x H image.  image is a
  * full [3][H][W] buffer; T_final, n_contrib, n_blended, ambiguous are full
- * [H][W] buffers (each may be NULL).  tile_bbox is SoA [4][n].            */
+ * [H][W] buffers (each may be NULL).  tile_bbox is SoA [4][n].  Tile lists
+ * hold the pairs binned there (or_support_tiles), or every pair whose bbox
+ * covers the tile when use_support is 0; only n_contrib, a list position,
+ * depends on it.                                                           */
 void or_render(int64_t n, const double* mean2d, const double* conic, const double* depth,
                const double* opacity, const double* rgb, const int32_t* tile_bbox,
                const int32_t* valid, int W, int H, int tw, int th, const double* bg, int x0,
                int y0, int x1, int y1, double* image, double* T_final, int32_t* n_contrib,
-               int32_t* n_blended, uint8_t* ambiguous, double band_rel) {
+               int32_t* n_blended, uint8_t* ambiguous, double band_rel, int use_support) {
   int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
   int64_t cnt = sorted_order(n, depth, valid, order);
   int64_t npix = (int64_t)(x1 - x0) * (y1 - y0);
+  uint64_t *mask, *mamb;
+  render_masks(n, mean2d, conic, opacity, tile_bbox, valid, tw, th, use_support,
+               band_rel > OR_LIST_BAND ? band_rel : OR_LIST_BAND, &mask, &mamb);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t pi = 0; pi < npix; ++pi) {
     int px = x0 + (int)(pi % (x1 - x0)), py = y0 + (int)(pi / (x1 - x0));
     int64_t o = (int64_t)py * W + px;
     double out[3], T; int32_t nc; uint8_t amb;
     int64_t nb = composite_pixel(px, py, tw, th, n, cnt, order, mean2d, conic, depth, opacity,
-                                 rgb, tile_bbox, bg, out, &T, &nc, &amb, NULL, band_rel);
+                                 rgb, tile_bbox, mask, mamb, bg, out, &T, &nc, &amb, NULL,
+                                 band_rel);
     for (int ch = 0; ch < 3; ++ch) image[(int64_t)ch * W * H + o] = out[ch];
     if (T_final) T_final[o] = T;
     if (n_contrib) n_contrib[o] = nc;
@@ -424,6 +547,8 @@ void or_render(int64_t n, const double* mean2d, const double* conic, const doubl
     if (ambiguous) ambiguous[o] = amb;
   }
   free(order);
+  free(mask);
+  free(mamb);
 }
 
 /* Analytic backward of or_render over the window, decisions held fixed.
@@ -453,8 +578,11 @@ void or_render_bwd(int64_t n, const double* mean2d, const double* conic, const d
       int px = x0 + (int)(pi % (x1 - x0)), py = y0 + (int)(pi / (x1 - x0));
       int64_t o = (int64_t)py * W + px;
       double out[3], Tf; int32_t nc; uint8_t amb;
+      /* the gradients do not depend on which tiles list a pair that never
+       * blends there, so the backward walks every bbox tile */
       int64_t nb = composite_pixel(px, py, tw, th, n, cnt, order, mean2d, conic, depth, opacity,
-                                   rgb, tile_bbox, bg, out, &Tf, &nc, &amb, rec, band_rel);
+                                   rgb, tile_bbox, NULL, NULL, bg, out, &Tf, &nc, &amb, rec,
+                                   band_rel);
       double dI[3];
       for (int ch = 0; ch < 3; ++ch) dI[ch] = d_image[(int64_t)ch * W * H + o];
       double acc[3];                      /* sum_{j>k} c_j a_j T_j + bg T_final */
@@ -667,27 +795,53 @@ static int cmp_dup(const void* A, const void* B) {
   return (a->seq < b->seq) ? -1 : (a->seq > b->seq);
 }
 
-/* Emit every (pair, tile of its tile bbox) entry in pair order with key
- * ((slot * tiles_per_slot + ty * tiles_x + tx) << 32) | depth_bits, then
- * sort stably by key.  tile_bbox is pair-major [m][4] (tx0, ty0, tx1, ty1),
- * pairs with n_tiles[p] == 0 emit nothing.  Writes up to cap entries to
- * keys/ids and the [start, end) ranges of every tile ([n_slots *
- * tiles_per_slot][2], zero for empty tiles).  Returns the total count; if
- * it exceeds cap nothing is written.                                       */
+/* Emit every (pair, listed tile) entry in pair order, each pair's tiles
+ * row-major over its bbox, with key ((slot * tiles_per_slot + ty * tiles_x
+ * + tx) << 32) | depth_bits, then sort stably by key.  tile_bbox is
+ * pair-major [m][4] (tx0, ty0, tx1, ty1), sup pair-major [m][6] (mean x, y,
+ * conic a, b, c, opacity) decides the listed tiles (support_mask; NULL:
+ * every bbox tile); pairs with n_tiles[p] == 0 emit nothing.  Writes up to cap entries to keys/ids
+ * and the [start, end) ranges of every tile ([n_slots * tiles_per_slot][2],
+ * zero for empty tiles), and per pair its entry count (count, may be NULL)
+ * and whether any of its decisions is ambiguous at relative band `band`
+ * (amb, may be NULL).  Returns the total count; if it exceeds cap nothing
+ * is written to keys, ids and ranges.                                      */
 int64_t or_bin_sort(int64_t m, const int32_t* tile_bbox, const int32_t* n_tiles,
+                    const double* sup, int tw, int th, double band,
                     const uint32_t* depth_bits, const int32_t* slot, int tiles_x,
                     int tiles_per_slot, int n_slots, int64_t cap, uint64_t* keys, uint32_t* ids,
-                    uint32_t* ranges) {
+                    uint32_t* ranges, int32_t* count, uint8_t* amb) {
+  uint64_t* mask = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1));
   int64_t total = 0;
-  for (int64_t p = 0; p < m; ++p) total += n_tiles[p] > 0 ? n_tiles[p] : 0;
-  if (total > cap) return total;
+  for (int64_t p = 0; p < m; ++p) {
+    const int32_t* bb = tile_bbox + 4 * p;
+    uint64_t am = 0;
+    int64_t np = 0;
+    mask[p] = 0;
+    if (n_tiles[p] > 0) {
+      int64_t area = (int64_t)(bb[2] - bb[0] + 1) * (bb[3] - bb[1] + 1);
+      if (sup) {
+        const double* r = sup + 6 * p;
+        support_mask(r[0], r[1], r[2], r[3], r[4], r[5], bb[0], bb[1], bb[2], bb[3], tw, th,
+                     band, &mask[p], &am);
+      }
+      np = (!sup || area > OR_MASK_TILES) ? area : (int64_t)__builtin_popcountll(mask[p]);
+    }
+    if (count) count[p] = (int32_t)np;
+    if (amb) amb[p] = am != 0;
+    total += np;
+  }
+  if (total > cap) { free(mask); return total; }
   or_dup* d = (or_dup*)malloc(sizeof(or_dup) * (size_t)(total > 0 ? total : 1));
   int64_t k = 0;
   for (int64_t p = 0; p < m; ++p) {
     if (n_tiles[p] <= 0) continue;
     const int32_t* bb = tile_bbox + 4 * p;
+    int span = bb[2] - bb[0] + 1;
+    int all = !sup || (int64_t)span * (bb[3] - bb[1] + 1) > OR_MASK_TILES;
     for (int ty = bb[1]; ty <= bb[3]; ++ty)
       for (int tx = bb[0]; tx <= bb[2]; ++tx) {
+        if (!all && !(mask[p] >> ((ty - bb[1]) * span + (tx - bb[0])) & 1)) continue;
         uint64_t tile = (uint64_t)slot[p] * (uint64_t)tiles_per_slot + (uint64_t)(ty * tiles_x + tx);
         d[k].key = (tile << 32) | (uint64_t)depth_bits[p];
         d[k].seq = k;
@@ -706,6 +860,7 @@ int64_t or_bin_sort(int64_t m, const int32_t* tile_bbox, const int32_t* n_tiles,
     if (j == total - 1 || (d[j + 1].key >> 32) != tile) ranges[2 * tile + 1] = (uint32_t)(j + 1);
   }
   free(d);
+  free(mask);
   return total;
 }
 
