@@ -173,18 +173,28 @@ gs_status gs_project(const gs_gaussians* g, const gs_views* views,
 size_t gs_bin_sort_workspace_bytes(int64_t m, int64_t dup_capacity,
                                    const gs_tiling* tiling, int32_t n_slots);
 
-/* Tile binning and sorting.  Each pair emits one entry per tile of its tile
- * bbox with key ((slot * tiles_per_slot + ty * tiles_x + tx) << 32) |
- * bits(depth) and value = pair index; entries are sorted stably by key, so
- * equal keys keep ascending pair index.  Outputs (device):
+/* Tile binning and sorting (the 3D-GS per-tile, depth-ordered lists).  Each
+ * pair emits one entry per listed tile with key ((slot * tiles_per_slot +
+ * ty * tiles_x + tx) << 32) | bits(depth) and value = pair index; entries
+ * are sorted stably by key, so equal keys keep ascending pair index.  The
+ * listed tiles of a pair with n_tiles > 0 are those of its tile bbox whose
+ * pixel-centre rectangle [tx tile_w + 1/2, tx tile_w + tile_w - 1/2] x
+ * [ty tile_h + 1/2, ty tile_h + tile_h - 1/2] meets its support widened by a
+ * rounding margin: d^T conic d <= 2 ln(255 o) + 0.02 + 1e-5 M, with M =
+ * a X^2 + 2|b| X Y + c Y^2 for the largest |dx| = X and |dy| = Y from the
+ * mean to the bbox's pixel-centre extents (conic (a, b, c), opacity o and
+ * mean read from rec).  No pixel centre of another bbox tile reaches
+ * alpha >= 1/255, so images do not depend on it.  A bbox of more than 64
+ * tiles is listed whole.  Outputs (device):
  *   keys_out [dup_capacity] u64, ids_out [dup_capacity] u32 (sorted),
  *   tile_ranges [n_slots * tiles_per_slot][2] u32: [start, end) into ids_out
  *   (start = end = 0 for an empty tile),
- *   pair_first [m] u32 (optional, may be NULL): the emission index of each
- *   pair's first entry.  Entries are emitted pair by pair in ascending
- *   (depth bits, pair index) order, each pair's tiles row-major over its tile
- *   bbox, so pair p's entries are emission indices pair_first[p] ..
- *   pair_first[p] + n_tiles[p] - 1 (unspecified when n_tiles[p] = 0),
+ *   pair_first [m][2] u32 (optional, may be NULL): per pair, the emission
+ *   index of its first entry and its entry count.  Entries are emitted pair
+ *   by pair in ascending (depth bits, pair index) order, each pair's tiles
+ *   row-major over its tile bbox, so pair p's entries are emission indices
+ *   pair_first[p][0] .. pair_first[p][0] + pair_first[p][1] - 1 (word 0 is
+ *   unspecified when the count is 0),
  *   emit_out [dup_capacity] u32 (optional, may be NULL): the emission index
  *   of each sorted entry (aligned with ids_out).
  * The true duplicate count is written to status[1]; when it exceeds
@@ -218,7 +228,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views,
  * shortens the longest tiles; must divide tile_w * tile_h / 64; not with a
  * queue).
  * Deterministic gradients: with dup_grads ([dup_capacity][9] f32 device
- * workspace; dup_capacity as passed to gs_bin_sort), pair_first and
+ * workspace; dup_capacity as passed to gs_bin_sort), pair_first ([m][2]) and
  * emit_idx (pair_first and emit_out of gs_bin_sort of the same step) set,
  * the backward writes each (tile, pair) entry's 9 gradient components into
  * the slot of its emission index instead of adding them atomically, then

@@ -156,8 +156,8 @@ def render(proj, W, H, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None, band=1e-5
 
     proj holds SoA mean2d [2,n], conic [3,n], depth, opacity, rgb [3,n],
     tile_bbox [4,n] and valid (or n_tiles).  window = (x0, y0, x1, y1).
-    Returns image [3,H,W], T_final, n_contrib, n_blended, ambiguous ([H,W]);
-    pixels outside the window are left zero.  ``ambiguity`` holds the reason
+    Returns image [3,H,W], T_final, n_contrib, n_blended, ambiguous ([H,W],
+    reasons 1-16); pixels outside the window are left zero.  ``ambiguity`` holds the reason
     bits of an ambiguous pixel: 1 power near 0, 2 alpha near 1/255, 4 alpha
     near 0.99, 8 transmittance near the cut-off, 16 near-equal depths, 32 a
     pair listed on the pixel's tile by an ambiguous decision before its last
@@ -179,8 +179,9 @@ def render(proj, W, H, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None, band=1e-5
     lib.or_render(ctypes.c_int64(n), _p(m2), _p(cn), _p(dp), _p(op), _p(rgb), _p(tb), _p(valid),
                   W, H, tile[0], tile[1], _p(bgv), x0, y0, x1, y1, _p(img), _p(T), _p(nc),
                   _p(nb), _p(amb), ctypes.c_double(band), ctypes.c_int(1 if support else 0))
-    return dict(image=img, T_final=T, n_contrib=nc, n_blended=nb, ambiguous=amb.astype(bool),
-                ambiguity=amb)
+    # ``ambiguous`` covers what images, T_final and n_blended depend on
+    return dict(image=img, T_final=T, n_contrib=nc, n_blended=nb,
+                ambiguous=(amb & 31).astype(bool), ambiguity=amb)
 
 
 def render_bwd(proj, W, H, d_image, tile=(16, 16), bg=(0.0, 0.0, 0.0), window=None,

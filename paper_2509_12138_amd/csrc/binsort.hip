@@ -6,13 +6,17 @@
 // call can be captured in a HIP graph):
 //   k_depth_keys + 4 radix passes   the m pairs sorted stably by depth bits
 //                  (ties by pair index): the depth order is sorted once per
-//                  pair instead of once per duplicate
-//   k_scan_reduce  per-block sums of n_tiles, in depth order
+//                  pair instead of once per duplicate; k_depth_keys also
+//                  decides which tiles of each pair's bbox meet its support
+//                  (a 64-bit row-major mask over bboxes of up to 64 tiles)
+//   k_scan_reduce  per-block sums of the pairs' tile counts, in depth order
 //   k_scan_top     exclusive scan of the block sums, total -> status[1],
 //                  overflow flag, clamped count
-//   k_emit         per block of depth-ordered pairs: local scan of n_tiles,
-//                  then one thread per duplicate (coalesced writes) finds its
-//                  pair by binary search in LDS and writes key / pair index
+//   k_emit         per block of depth-ordered pairs: local scan of the tile
+//                  counts, an LDS map from duplicate to pair, then one
+//                  thread per duplicate (coalesced writes) finds its tile as
+//                  the k-th set bit of the pair's mask and writes key / pair
+//                  index
 //   k_radix_hist / k_radix_rowscan / k_radix_scatter   LSD radix passes on
 //                  8-bit digits (9-bit when that saves a pass: 17-18 tile
 //                  bits) over the tile bits of the keys only (the
@@ -26,8 +30,9 @@
 namespace gsmi {
 
 constexpr int kScanThreads = 256;
-constexpr int kScanPer = 8;
+constexpr int kScanPer = 4;
 constexpr int kScanItems = kScanThreads * kScanPer;   // pairs per scan/emit block
+constexpr int kEmitRound = 2048;   // duplicates a k_emit block expands at a time
 constexpr int kSortThreads = 256;
 constexpr int kSortPer = 8;
 constexpr int kSortItems = kSortThreads * kSortPer;   // keys per radix block
@@ -43,7 +48,8 @@ static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct BinSortLayout {
   int64_t nb_scan, nb_sort, nb_pairs;
-  size_t off_block_sums, off_count, off_keys_alt, off_vals_alt, off_emit_alt, off_hist, off_rowtot;
+  size_t off_block_sums, off_count, off_keys_alt, off_vals_alt, off_emit_alt, off_hist, off_rowtot,
+      off_erec;
   size_t off_pkeys[2], off_pvals[2], total;
 };
 
@@ -62,12 +68,87 @@ static BinSortLayout layout(int64_t m, int64_t cap) {
   L.off_emit_alt = o; o += align256(sizeof(uint32_t) * (size_t)(cap > 0 ? cap : 1));
   L.off_hist = o; o += align256(sizeof(uint32_t) * (size_t)kRadixMax * (size_t)nb_hist);
   L.off_rowtot = o; o += align256(sizeof(uint32_t) * kRadixMax);
+  L.off_erec = o; o += align256(sizeof(uint32_t) * 4 * mm);
   for (int b = 0; b < 2; ++b) {
     L.off_pkeys[b] = o; o += align256(sizeof(uint64_t) * mm);
     L.off_pvals[b] = o; o += align256(sizeof(uint32_t) * mm);
   }
   L.total = o;
   return L;
+}
+
+// ------------------------------------------------------------ tile listing
+
+constexpr int kMaskTiles = 64;   // bboxes of more tiles are listed whole
+
+// Tiles of one pair's tile bbox (tx0, ty0)-(tx1, ty1) whose pixel-centre
+// rectangle [tx tw + 1/2, tx tw + tw - 1/2] x [ty th + 1/2, ty th + th - 1/2]
+// meets the pair's support (alpha >= 1/255, d^T Q d <= 2 ln(255 o)) widened
+// by 0.02 + 1e-5 M, M = a X^2 + 2|b| X Y + c Y^2 over the bbox's pixel-centre
+// extents: no pixel centre outside it passes the alpha test, and the margin
+// exceeds the single-precision rounding of this test and of the per-pixel
+// one.  The support is convex, so inside one tile row's pixel-centre band
+// its x-extent is an interval [L, R]: the rightmost point of the whole
+// ellipse (dx = xmax at dy = -b xmax / c) when that dy lies in the band, else
+// the larger of the two band edges' right ends (the right boundary is
+// concave in dy), and the same for the left end.  Bit (ty - ty0) * span +
+// (tx - tx0) of the result is set for each tile column meeting [L, R].
+// Call only for bboxes of at most kMaskTiles tiles.
+__device__ __forceinline__ uint64_t support_tile_mask(const float* __restrict__ r, int tx0,
+                                                      int ty0, int tx1, int ty1, int tw, int th) {
+  const float mx = r[0], my = r[1], a = r[2], b = r[3], c = r[4], o = r[5];
+  const int span = tx1 - tx0 + 1, rows = ty1 - ty0 + 1;
+  const float X = fmaxf(fabsf((float)(tx0 * tw) + 0.5f - mx),
+                        fabsf((float)(tx1 * tw + tw) - 0.5f - mx));
+  const float Y = fmaxf(fabsf((float)(ty0 * th) + 0.5f - my),
+                        fabsf((float)(ty1 * th + th) - 0.5f - my));
+  const float M = fmaf(a * X, X, fmaf(2.0f * fabsf(b) * X, Y, c * Y * Y));
+  const float thr = fmaf(1e-5f, M, fmaf(2.0f, logf(255.0f * o), 0.02f));
+  // det = a c - b^2 with the rounding error of b^2 carried (thin supports
+  // have det << a c)
+  const float bb = b * b;
+  const float det = fmaf(a, c, -bb) - fmaf(b, b, -bb);
+  const int area = span * rows;
+  const uint64_t all = area >= 64 ? ~0ull : ((1ull << area) - 1ull);
+  if (!(det > 0.0f) || !(thr > 0.0f)) return all;         // degenerate form: list all
+  const float ymax = sqrtf(a * thr / det), xmax = sqrtf(c * thr / det);
+  const float dyr = -b * xmax / c;                         // dy of the rightmost point
+  const float at = a * thr;
+  uint64_t mask = 0;
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    const float y0 = (float)(ty * th) + 0.5f - my;
+    const float u0 = fmaxf(y0, -ymax), u1 = fminf(y0 + (float)(th - 1), ymax);
+    if (!(u0 <= u1)) continue;
+    const float h0 = sqrtf(fmaxf(fmaf(-det * u0, u0, at), 0.0f));
+    const float h1 = sqrtf(fmaxf(fmaf(-det * u1, u1, at), 0.0f));
+    const float R = (u0 <= dyr && dyr <= u1) ? xmax : fmaxf(fmaf(-b, u0, h0), fmaf(-b, u1, h1)) / a;
+    const float L = (u0 <= -dyr && -dyr <= u1) ? -xmax
+                                                 : fminf(fmaf(-b, u0, -h0), fmaf(-b, u1, -h1)) / a;
+    // columns with tx tw + tw - 1/2 >= mx + L and tx tw + 1/2 <= mx + R
+    const float f0 = fmaxf(ceilf((mx + L + 0.5f) / (float)tw - 1.0f), (float)tx0);
+    const float f1 = fminf(floorf((mx + R - 0.5f) / (float)tw), (float)tx1);
+    if (!(f0 <= f1)) continue;
+    const int c0 = (int)f0, n = (int)f1 - c0 + 1;
+    const uint64_t run = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+    mask |= run << ((ty - ty0) * span + (c0 - tx0));
+  }
+  return mask;
+}
+
+// Position of the k-th set bit (from 0) of v, which has more than k.
+__device__ __forceinline__ int select_bit(uint64_t v, uint32_t k) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const uint64_t low = v & ((1ull << w) - 1ull);
+    const uint32_t cnt = (uint32_t)__popcll(low);
+    if (k >= cnt) {
+      k -= cnt;
+      v >>= w;
+      pos += w;
+    }
+  }
+  return pos;
 }
 
 // ------------------------------------------------------------ block scans
@@ -130,14 +211,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t* __restrict__
                                                            int64_t* __restrict__ status,
                                                            int64_t* __restrict__ count) {
   __shared__ int64_t sm[4];
-  int64_t carry = 0;
-  for (int64_t c0 = 0; c0 < nb; c0 += kScanThreads) {
-    int64_t i = c0 + threadIdx.x;
-    int64_t v = i < nb ? block_sums[i] : 0;
-    int64_t total;
-    int64_t ex = block_exclusive_scan<int64_t>(v, sm, total);
-    if (i < nb) block_sums[i] = carry + ex;
-    carry += total;
+  // thread t owns the contiguous segment [t * seg, (t + 1) * seg): sum it,
+  // scan the 256 segment sums, then rewrite the segment as prefixes
+  const int64_t seg = (nb + kScanThreads - 1) / kScanThreads;
+  const int64_t s0 = min(nb, (int64_t)threadIdx.x * seg), s1 = min(nb, s0 + seg);
+  int64_t sum = 0;
+  for (int64_t i = s0; i < s1; ++i) sum += block_sums[i];
+  int64_t carry;
+  int64_t run = block_exclusive_scan<int64_t>(sum, sm, carry);
+  for (int64_t i = s0; i < s1; ++i) {
+    const int64_t v = block_sums[i];
+    block_sums[i] = run;
+    run += v;
   }
   if (threadIdx.x == 0) {
     if (status) {
@@ -151,19 +236,29 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t* __restrict__
 // ------------------------------------------------------------ emit
 
 // Block b handles depth-ordered positions b*kScanItems ...: pair perm[i]
-// with presorted key pkey[i] = (n_tiles << 42) | (slot << 32) | depth bits.
+// with presorted key pkey[i] = (tiles << 42) | (slot << 32) | depth bits and
+// emission record erec[perm[i]] (k_depth_keys): one 16-byte gather per pair.
+// pair_first (optional) is [m][2]: word 0 of a pair with tiles > 0 receives
+// the emission index of its first entry.
+// The block's duplicates are expanded kEmitRound at a time: each thread
+// marks, in an LDS owner map, the duplicates of its own pairs that fall in
+// the round, then one thread per duplicate reads its pair from the map
+// (coalesced key and value writes, no search).
 __global__ __launch_bounds__(kScanThreads) void k_emit(
-    const uint2* __restrict__ tile_bbox,
-    const uint64_t* __restrict__ pkey, const uint32_t* __restrict__ perm, int64_t m,
+    const uint4* __restrict__ erec, const uint64_t* __restrict__ pkey, const uint32_t* __restrict__ perm, int64_t m,
     const int64_t* __restrict__ block_offsets, int64_t cap, int tiles_x, int tiles_per_slot,
     uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ pair_first,
     uint32_t* __restrict__ emit) {
   __shared__ uint32_t s_off[kScanItems + 1];
-  __shared__ uint2 s_bbox[kScanItems];
+  __shared__ uint32_t s_base[kScanItems];     // tile index of the bbox's first tile
+  __shared__ uint32_t s_span[kScanItems];     // bbox width in tiles
+  __shared__ uint64_t s_mask[kScanItems];
   __shared__ uint32_t s_depth[kScanItems];
-  __shared__ uint32_t s_slot[kScanItems];
   __shared__ uint32_t s_pair[kScanItems];
+  __shared__ uint16_t s_owner[kEmitRound];
   __shared__ uint32_t s_w[4];
+  static_assert(kScanItems <= 65536, "owner map holds 16-bit pair slots");
+  (void)tiles_per_slot;
   const int64_t base = (int64_t)blockIdx.x * kScanItems;
   const int t = threadIdx.x;
   // stage the block's pairs (striped, coalesced) ...
@@ -177,16 +272,18 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
       nt = (int)(key >> kKeyTilesShift);
       if (nt > 0) {
         const uint32_t p = perm[i];
-        s_bbox[li] = tile_bbox[p];
+        const uint4 e = erec[p];
+        s_base[li] = e.x;
+        s_span[li] = e.y;
+        s_mask[li] = ((uint64_t)e.w << 32) | e.z;
         s_depth[li] = (uint32_t)key;
-        s_slot[li] = (uint32_t)((key >> kKeySlotShift) & kKeySlotMask);
         s_pair[li] = p;
       }
     }
     s_off[li] = (uint32_t)nt;
   }
   __syncthreads();
-  // ... then scan them in blocked order (thread t owns items t*8 .. t*8+7)
+  // ... then scan them in blocked order (thread t owns items t*kScanPer ...)
   uint32_t v[kScanPer], run = 0;
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
@@ -208,44 +305,61 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
     for (int k = 0; k < kScanPer; ++k) {
       const int li = k * kScanThreads + t;
       const int64_t i = base + li;
-      if (i < m && s_off[li + 1] > s_off[li]) pair_first[s_pair[li]] = (uint32_t)(gbase + s_off[li]);
+      if (i < m && s_off[li + 1] > s_off[li])
+        pair_first[2 * (int64_t)s_pair[li]] = (uint32_t)(gbase + s_off[li]);
     }
   }
-  for (uint32_t j = t; j < total; j += kScanThreads) {
-    int64_t dst = gbase + j;
-    if (dst >= cap) break;
-    // last local pair whose offset <= j (pairs with zero tiles are skipped
-    // because their successor shares the offset)
-    int lo = 0, hi = kScanItems - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (s_off[mid] <= j) lo = mid;
-      else hi = mid - 1;
+  for (uint32_t r0 = 0; r0 < total; r0 += kEmitRound) {
+    const uint32_t r1 = min(total, r0 + (uint32_t)kEmitRound);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const int li = t * kScanPer + k;
+      const uint32_t q0 = max(s_off[li], r0), q1 = min(s_off[li + 1], r1);
+      for (uint32_t q = q0; q < q1; ++q) s_owner[q - r0] = (uint16_t)li;
     }
-    uint32_t k = j - s_off[lo];
-    uint2 bb = s_bbox[lo];
-    int tx0 = bb.x & 0xffff, ty0 = bb.x >> 16, tx1 = bb.y & 0xffff;
-    int span = tx1 - tx0 + 1;
-    int ty = ty0 + (int)(k / span), tx = tx0 + (int)(k % span);
-    uint64_t tile = (uint64_t)s_slot[lo] * (uint64_t)tiles_per_slot + (uint64_t)(ty * tiles_x + tx);
-    keys[dst] = (tile << 32) | (uint64_t)s_depth[lo];
-    vals[dst] = s_pair[lo];
-    if (emit) emit[dst] = (uint32_t)dst;
+    __syncthreads();
+    for (uint32_t j = r0 + t; j < r1; j += kScanThreads) {
+      const int64_t dst = gbase + j;
+      if (dst >= cap) break;
+      const int li = s_owner[j - r0];
+      uint32_t k = j - s_off[li];
+      // the k-th listed tile: k-th set bit of the mask, or the k-th bbox tile
+      const uint64_t mk = s_mask[li];
+      if (mk) k = (uint32_t)select_bit(mk, k);
+      const uint32_t span = s_span[li];
+      const uint32_t ky = k / span;
+      const uint64_t tile = (uint64_t)(s_base[li] + ky * (uint32_t)tiles_x + (k - ky * span));
+      keys[dst] = (tile << 32) | (uint64_t)s_depth[li];
+      vals[dst] = s_pair[li];
+      if (emit) emit[dst] = (uint32_t)dst;
+    }
+    __syncthreads();
   }
 }
 
 // ------------------------------------------------------------ depth presort
 
-// key = (n_tiles << 42) | (slot << 32) | depth bits, value = pair index;
+// key = (tiles << 42) | (slot << 32) | depth bits, value = pair index;
 // count[0] = m.  Depths of visible pairs are positive, so their bits order
 // as the floats; the passes sort the low 32 bits only, the pair's tile count
-// and slot ride along for the scan and the emission.
+// and slot ride along for the scan and the emission.  tiles is the number of
+// listed tiles: the set bits of support_tile_mask for a bbox of up to
+// kMaskTiles tiles, else the whole bbox (mask 0 in the emission record).
+// pair_count (optional) receives the same count per pair.  A pair with
+// tiles > 0 gets its emission record erec[i] = (index of its bbox's first
+// tile slot * tiles_per_slot + ty0 * tiles_x + tx0, bbox width, mask low
+// and high words).
 // Also clears the n_range_words words of the tile ranges (grid-stride), so
 // the bin/sort needs no separate fill before k_ranges writes them.
 __global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ rec,
-                                                   const int32_t* __restrict__ n_tiles, int64_t m,
+                                                   const int32_t* __restrict__ n_tiles,
+                                                   const uint2* __restrict__ tile_bbox, int tw,
+                                                   int th, int tiles_x, int tiles_per_slot,
+                                                   int64_t m,
                                                    uint64_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals,
+                                                   uint4* __restrict__ erec,
+                                                   uint32_t* __restrict__ pair_count,
                                                    int64_t* __restrict__ count,
                                                    uint32_t* __restrict__ ranges,
                                                    int64_t n_range_words) {
@@ -253,10 +367,23 @@ __global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ re
   for (int64_t w = i; w < n_range_words; w += (int64_t)gridDim.x * 256) ranges[w] = 0u;
   if (i == 0) count[0] = m;
   if (i >= m) return;
-  const uint64_t nt = (uint64_t)max(n_tiles[i], 0);
-  keys[i] = (nt << kKeyTilesShift) |
-            ((uint64_t)__float_as_uint(rec[i * GS_REC_STRIDE + 10]) << kKeySlotShift) |
-            (uint64_t)__float_as_uint(rec[i * GS_REC_STRIDE + 9]);
+  const float* r = rec + i * GS_REC_STRIDE;
+  uint64_t nt = (uint64_t)max(n_tiles[i], 0);
+  const uint32_t slot = __float_as_uint(r[10]);
+  if (nt > 0) {
+    const uint2 bb = tile_bbox[i];
+    const int tx0 = (int)(bb.x & 0xffff), ty0 = (int)(bb.x >> 16), tx1 = (int)(bb.y & 0xffff);
+    uint64_t mask = 0;
+    if (nt <= (uint64_t)kMaskTiles) {
+      mask = support_tile_mask(r, tx0, ty0, tx1, (int)(bb.y >> 16), tw, th);
+      nt = (uint64_t)__popcll(mask);
+    }
+    erec[i] = make_uint4(slot * (uint32_t)tiles_per_slot + (uint32_t)(ty0 * tiles_x + tx0),
+                         (uint32_t)(tx1 - tx0 + 1), (uint32_t)mask, (uint32_t)(mask >> 32));
+  }
+  if (pair_count) pair_count[2 * i + 1] = (uint32_t)nt;
+  keys[i] = (nt << kKeyTilesShift) | ((uint64_t)slot << kKeySlotShift) |
+            (uint64_t)__float_as_uint(r[9]);
   vals[i] = (uint32_t)i;
 }
 
@@ -565,8 +692,11 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   uint64_t* pk[2] = {(uint64_t*)(w + L.off_pkeys[0]), (uint64_t*)(w + L.off_pkeys[1])};
   uint32_t* pv[2] = {(uint32_t*)(w + L.off_pvals[0]), (uint32_t*)(w + L.off_pvals[1])};
   int64_t* count_pairs = count + 1;
+  uint4* erec = (uint4*)(w + L.off_erec);
   hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, proj->rec,
-                     proj->n_tiles, m, pk[0], pv[0], count_pairs, tile_ranges, 2 * n_tiles_all);
+                     proj->n_tiles, (const uint2*)proj->tile_bbox, tiling->tile_w,
+                     tiling->tile_h, tiles_x, (int)tiles_per_slot, m, pk[0], pv[0], erec,
+                     pair_first, count_pairs, tile_ranges, 2 * n_tiles_all);
   GS_LAUNCH_CHECK("gs_bin_sort/depth_keys");
   for (int p = 0; p < 4; ++p) {
     const int shift = p * kRadixBits;
@@ -589,7 +719,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
                      dup_capacity, status, count);
   GS_LAUNCH_CHECK("gs_bin_sort/scan_top");
   hipLaunchKernelGGL(k_emit, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s,
-                     (const uint2*)proj->tile_bbox, pk[0], pv[0], m, block_sums, dup_capacity,
+                     (const uint4*)erec, pk[0], pv[0], m, block_sums, dup_capacity,
                      tiles_x, (int)tiles_per_slot, k0, v0, pair_first, e0);
   GS_LAUNCH_CHECK("gs_bin_sort/emit");
   for (int p = 0; p < passes; ++p) {

@@ -1032,18 +1032,18 @@ __global__ __launch_bounds__(256) void k_chunk_items(const uint32_t* __restrict_
 
 // d_rec[p][c] += sum over pair p's emission slots of component c, in
 // emission order; one thread per (pair, component), so the 9 threads of a
-// pair read its slots' 36-byte records together.
-__global__ __launch_bounds__(256) void k_dup_reduce(const int32_t* __restrict__ n_tiles,
-                                                    const uint32_t* __restrict__ pair_first,
+// pair read its slots' 36-byte records together.  pair_first [m][2] holds
+// each pair's first emission index and its entry count.
+__global__ __launch_bounds__(256) void k_dup_reduce(const uint32_t* __restrict__ pair_first,
                                                     int64_t m, const float* __restrict__ dup,
                                                     int64_t dup_cap, float* __restrict__ d_rec) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t p = i / GS_DREC_STRIDE;
   const int c = (int)(i - p * GS_DREC_STRIDE);
   if (p >= m) return;
-  const int nt = n_tiles[p];
+  const int64_t nt = pair_first[2 * p + 1];
   if (nt <= 0) return;
-  const int64_t e0 = pair_first[p];
+  const int64_t e0 = pair_first[2 * p];
   if (e0 + nt > dup_cap) return;
   const float* g = dup + e0 * GS_DREC_STRIDE + c;
   float acc = 0.0f;
@@ -1305,8 +1305,8 @@ gs_status gs_raster_bwd(const gs_projected* proj, const gs_views* views, const g
   hipStream_t s = as_stream(stream);
   const bool det = plan && plan->dup_grads;
   if (det) {
-    GS_REQUIRE(plan->pair_first && plan->emit_idx && plan->dup_capacity > 0 && proj->n_tiles,
-               "gs_raster_bwd: deterministic mode needs pair_first, emit_idx, dup_capacity, n_tiles");
+    GS_REQUIRE(plan->pair_first && plan->emit_idx && plan->dup_capacity > 0,
+               "gs_raster_bwd: deterministic mode needs pair_first, emit_idx, dup_capacity");
     a.emit = plan->emit_idx;
     a.dup_grads = plan->dup_grads;
     a.dup_cap = plan->dup_capacity;
@@ -1324,7 +1324,7 @@ gs_status gs_raster_bwd(const gs_projected* proj, const gs_views* views, const g
   if (det && proj->m > 0) {
     hipLaunchKernelGGL(k_dup_reduce, dim3((unsigned)ceil_div(proj->m * GS_DREC_STRIDE, 256)),
                        dim3(256), 0, s,
-                       proj->n_tiles, plan->pair_first, proj->m, plan->dup_grads,
+                       plan->pair_first, proj->m, plan->dup_grads,
                        plan->dup_capacity, d_rec);
     GS_LAUNCH_CHECK("gs_raster_bwd/reduce");
   }

@@ -147,7 +147,7 @@ class RasterBuffers:
         else:
             self.T_final = self.n_contrib = None
         self.d_rec = torch.zeros((max(m, 1), 9), dtype=torch.float32, device=dev)
-        self.pair_first = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+        self.pair_first = torch.empty(2 * max(m, 1), dtype=torch.int32, device=dev)   # (first, count)
         self.status = torch.zeros(4, dtype=torch.int64, device=dev)
         self.keys = self.ids = self.ws = None
         self.dup_grads = None

@@ -119,10 +119,27 @@ def raster_records(bufs, rec, tb, nt, bg, torch):
     bufs.clear_status()
     bufs.bin_sort()
     st, req = bufs.check()
-    assert st == 0 and req == int(nt.astype(np.int64).sum()), (st, req)
+    # the support listing keeps at most the bbox tiles
+    assert st == 0 and req <= int(nt.astype(np.int64).sum()), (st, req)
     bufs.order_tiles()
     bufs.raster_fwd(bg)
     torch.cuda.synchronize()
+
+
+def oracle_lists(rec, tb, nt, slot, tile, W, H, S):
+    """The oracle's sorted tile lists of FP32 records (rec [m,12], tb [m,4]
+    u16 bits, nt [m]) with the pairs whose tile listing is ambiguous culled:
+    returns (nt with those pairs at 0, keys, ids, ranges).  Give the GPU the
+    returned nt so that both sides list the same pairs."""
+    tx, ty = math.ceil(W / tile[0]), math.ceil(H / tile[1])
+    tbi = np.asarray(tb).astype(np.int32).reshape(-1, 4) & 0xFFFF
+    sup = oracle.sup_from_records(rec)
+    *_, amb = oracle.bin_sort(tbi, nt, rec[:, 9], slot, tx, tx * ty, S, sup=sup, tile=tile,
+                              details=True)
+    nt = np.where(amb, 0, nt).astype(np.int32)
+    keys, ids, ranges = oracle.bin_sort(tbi, nt, rec[:, 9], slot, tx, tx * ty, S, sup=sup,
+                                        tile=tile)
+    return nt, keys, ids, ranges
 
 
 def decision_safe_mask(mask, r, target, tol=1e-4):

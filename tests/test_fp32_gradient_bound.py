@@ -207,7 +207,8 @@ def case():
         sl = slice(v * n, (v + 1) * n)
         tbv = (tb[sl].view(np.uint16).astype(np.int32))
         _, ids, ranges = oracle.bin_sort(tbv, nt[sl], rec[sl, 9], np.zeros(n, np.int32),
-                                         tiles_x, tiles_x * tiles_y, 1)
+                                         tiles_x, tiles_x * tiles_y, 1,
+                                         sup=oracle.sup_from_records(rec[sl]), tile=(TILE, TILE))
         o = oracle.render_bwd(views[v], W, H, dI[v].astype(np.float64), bg=BG,
                               amb_bits=SAME_RECORD_BITS)
         ref = np.concatenate([o["d_mean2d"], o["d_conic"], o["d_opacity"][None], o["d_rgb"]]).T
