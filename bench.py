@@ -187,6 +187,20 @@ def timed_steps(tr, order, first, steps):
     return wall * 1000.0 / steps, mean, total, event_views
 
 
+def fwd_kernel_name(tile, fwd_waves):
+    """The forward kernel the library launches for this plan."""
+    return f"k_raster_fwd<{tile[0]}, {tile[1]}, {fwd_waves}>"
+
+
+def bwd_kernel_name(tile, chunk, recompute, deterministic):
+    """The backward kernel the library launches for this plan."""
+    if chunk and not recompute:
+        if tuple(tile) == (8, 8) and not deterministic:
+            return f"k_raster_bwd_chunked_q<{tile[0]}, {tile[1]}>"   # quadrant lane groups
+        return f"k_raster_bwd_chunked<{tile[0]}, {tile[1]}>"
+    return f"k_raster_bwd<{tile[0]}, {tile[1]}, {'true' if recompute else 'false'}>"
+
+
 def count_work(tr, views, W, H, tile):
     """Blended (pixel, Gaussian) pairs of each view, summed, with the
     forward's decisions (gs_raster_count) on the trainer's current state;
@@ -383,9 +397,8 @@ def batched_main(args):
     k = "raster_bwd" if mean["raster_bwd"] >= mean["raster_fwd"] else "raster_fwd"
     per = OPS_PER_EVAL_BWD if k == "raster_bwd" else OPS_PER_EVAL_FWD
     achieved = blended * per / (total[k] * 1e-3)
-    kname = (f"k_raster_bwd_chunked<{tile[0]}, {tile[1]}>" if k == "raster_bwd" and chunk else
-             f"k_raster_bwd<{tile[0]}, {tile[1]}, {'true' if args.recompute else 'false'}>"
-             if k == "raster_bwd" else f"k_raster_fwd<{tile[0]}, {tile[1]}, {fwd_waves}>")
+    kname = (bwd_kernel_name(tile, chunk, args.recompute, False) if k == "raster_bwd"
+             else fwd_kernel_name(tile, fwd_waves))
     mpix = tr.S * W * H / ((mean["raster_fwd"] + mean["raster_bwd"]) * 1e-3) / 1e6
     out = {
         "metric": METRIC,
@@ -532,8 +545,7 @@ def main():
     evals_fwd = evals_bwd = blended
     if dom == "raster_bwd":
         achieved = evals_bwd * OPS_PER_EVAL_BWD / (sums["raster_bwd"] * 1e-3)
-        kname = (f"k_raster_bwd_chunked<{tile[0]}, {tile[1]}>" if chunk else
-                 f"k_raster_bwd<{tile[0]}, {tile[1]}, {'true' if args.recompute else 'false'}>")
+        kname = bwd_kernel_name(tile, chunk, args.recompute, deterministic)
         if deterministic:
             kname += "+k_dup_reduce"          # both run inside the timed gs_raster_bwd call
         roof = {"kernel": kname, "bound": "alu", "achieved": achieved / 1e12,
@@ -542,7 +554,7 @@ def main():
                 "unit_desc": f"{OPS_PER_EVAL_BWD} FP32 VALU issue slots per blended (pixel, Gaussian)"}
     else:
         achieved = evals_fwd * OPS_PER_EVAL_FWD / (sums["raster_fwd"] * 1e-3)
-        roof = {"kernel": f"k_raster_fwd<{tile[0]}, {tile[1]}, {fwd_waves}>", "bound": "alu",
+        roof = {"kernel": fwd_kernel_name(tile, fwd_waves), "bound": "alu",
                 "achieved": achieved / 1e12,
                 "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
                 "traffic": None, "units_per_launch": evals_fwd / len(timed_views),

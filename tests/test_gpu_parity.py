@@ -490,23 +490,26 @@ def test_schedules_give_identical_results(ops, sched):
     assert nr <= 1e-5, nr
 
 
-@pytest.mark.parametrize("chunk,sched,det", [(64, "default", False), (128, "lpt", False),
-                                             (64, "persistent", False), (64, "lpt", True),
-                                             (128, "default", True)])
-def test_chunked_backward_matches_oracle(ops, chunk, sched, det):
+@pytest.mark.parametrize("chunk,sched,det,tile", [
+    (64, "default", False, (16, 16)), (128, "lpt", False, (16, 16)),
+    (64, "persistent", False, (16, 16)), (64, "lpt", True, (16, 16)),
+    (128, "default", True, (16, 16)),
+    # 8x8 atomic: the quadrant-group backward
+    (64, "lpt", False, (8, 8)), (64, "default", False, (8, 8)), (64, "lpt", True, (8, 8))])
+def test_chunked_backward_matches_oracle(ops, chunk, sched, det, tile):
     """Tile lists cut into chunk-entry work items (forward checkpoints of T and
     C) give the oracle's gradients; the image is unchanged."""
-    say("chunked bwd", chunk, sched)
+    say("chunked bwd", chunk, sched, tile)
     W, H = 112, 80
     params = perturbed(surface_scene(20000, 81), 81, amount=0.2)
     cams = scene.orbit_cameras(2, W, H)
     bg = (0.05, 0.1, 0.2)
-    rec, tb, nt, views = oracle_records(params, cams, W, H, (16, 16))
+    rec, tb, nt, views = oracle_records(params, cams, W, H, tile)
     rng = np.random.default_rng(3)
     dI = masked_image_gradient(rng, H, W)
     res = {}
     for c in (0, chunk):
-        bufs = make_bufs(ops, params, cams, W, H, (16, 16))
+        bufs = make_bufs(ops, params, cams, W, H, tile)
         bufs.set_schedule(sched if c else "default", persistent_waves=29, chunk=c,
                           deterministic=det)
         raster_records(bufs, rec, tb, nt, bg, torch)
@@ -527,7 +530,7 @@ def test_chunked_backward_matches_oracle(ops, chunk, sched, det):
     n = 20000
     for v in range(2):
         sl = slice(v * n, (v + 1) * n)
-        o = oracle.render_bwd(views[v], W, H, dI[v], bg=bg, amb_bits=SAME_RECORD_BITS)
+        o = oracle.render_bwd(views[v], W, H, dI[v], tile=tile, bg=bg, amb_bits=SAME_RECORD_BITS)
         ref = np.concatenate([o["d_mean2d"], o["d_conic"], o["d_opacity"][None], o["d_rgb"]]).T
         ok0, worst0 = grad_tolerance_check(res[0][1][sl], ref, o["term_mass"].T, o["amb_mass"].T)
         ok, worst = grad_tolerance_check(res[chunk][1][sl], ref, o["term_mass"].T, o["amb_mass"].T)
