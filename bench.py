@@ -187,8 +187,10 @@ def timed_steps(tr, order, first, steps):
     return wall * 1000.0 / steps, mean, total, event_views
 
 
-def fwd_kernel_name(tile, fwd_waves):
-    """The forward kernel the library launches for this plan."""
+def fwd_kernel_name(tile, fwd_waves, sched="default", chunk=0):
+    """The forward kernel(s) the library launches for this plan."""
+    if sched.endswith("+split") and chunk:
+        return f"k_raster_fwd_part<{tile[0]}, {tile[1]}>+k_raster_fwd_join<{tile[0]}, {tile[1]}>"
     return f"k_raster_fwd<{tile[0]}, {tile[1]}, {fwd_waves}>"
 
 
@@ -398,7 +400,7 @@ def batched_main(args):
     per = OPS_PER_EVAL_BWD if k == "raster_bwd" else OPS_PER_EVAL_FWD
     achieved = blended * per / (total[k] * 1e-3)
     kname = (bwd_kernel_name(tile, chunk, args.recompute, False) if k == "raster_bwd"
-             else fwd_kernel_name(tile, fwd_waves))
+             else fwd_kernel_name(tile, fwd_waves, sched, chunk))
     mpix = tr.S * W * H / ((mean["raster_fwd"] + mean["raster_bwd"]) * 1e-3) / 1e6
     out = {
         "metric": METRIC,
@@ -554,7 +556,7 @@ def main():
                 "unit_desc": f"{OPS_PER_EVAL_BWD} FP32 VALU issue slots per blended (pixel, Gaussian)"}
     else:
         achieved = evals_fwd * OPS_PER_EVAL_FWD / (sums["raster_fwd"] * 1e-3)
-        roof = {"kernel": fwd_kernel_name(tile, fwd_waves), "bound": "alu",
+        roof = {"kernel": fwd_kernel_name(tile, fwd_waves, sched, chunk), "bound": "alu",
                 "achieved": achieved / 1e12,
                 "peak": PEAK_VALU_OPS / 1e12, "unit": "TOP/s", "frac": achieved / PEAK_VALU_OPS,
                 "traffic": None, "units_per_launch": evals_fwd / len(timed_views),

@@ -227,6 +227,16 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views,
  * 4 split the tile's pixels over that many waves of one work-group, which
  * shortens the longest tiles; must divide tile_w * tile_h / 64; not with a
  * queue).
+ * Split forward (fwd_split = 1, chunked STORED mode only): the forward
+ * composites every chunk item in parallel from a local transmittance of 1
+ * (one wave per item; chunk_last [max_items][tile_w*tile_h] u16 device
+ * workspace receives each item's chunk-local position of the last blend per
+ * pixel), then one wave per tile joins its chunks in list order, composites
+ * again with the stop rule the chunk in which a pixel's transmittance
+ * reaches the cut-off, and writes the image, T_final, n_contrib and the
+ * backward's checkpoints.  Long tile lists then no longer run on one wave
+ * each; the results equal the sequential forward's up to FP32 rounding of
+ * the transmittance products and colour sums.
  * Deterministic gradients: with dup_grads ([dup_capacity][9] f32 device
  * workspace; dup_capacity as passed to gs_bin_sort), pair_first ([m][2]) and
  * emit_idx (pair_first and emit_out of gs_bin_sort of the same step) set,
@@ -246,11 +256,12 @@ typedef struct {
   float* checkpoints;
   int64_t max_items;
   int32_t fwd_waves;
-  int32_t reserved;
+  int32_t fwd_split;
   float* dup_grads;
   const uint32_t* pair_first;
   int64_t dup_capacity;
   const uint32_t* emit_idx;
+  uint16_t* chunk_last;
 } gs_raster_plan;
 
 /* Upper bound on the work items of gs_chunk_items for a duplicate capacity. */

@@ -53,9 +53,9 @@ class gs_projected(C.Structure):
 class gs_raster_plan(C.Structure):
     _fields_ = [("tile_order", vp), ("queue", vp), ("persistent_waves", i32), ("chunk", i32),
                 ("chunk_offset", vp), ("chunk_items", vp), ("checkpoints", vp),
-                ("max_items", i64), ("fwd_waves", i32), ("reserved", i32),
+                ("max_items", i64), ("fwd_waves", i32), ("fwd_split", i32),
                 ("dup_grads", vp), ("pair_first", vp), ("dup_capacity", i64),
-                ("emit_idx", vp)]
+                ("emit_idx", vp), ("chunk_last", vp)]
 
 
 class gs_adam_group(C.Structure):

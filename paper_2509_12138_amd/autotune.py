@@ -26,6 +26,8 @@ CANDIDATES = [
     ((16, 8), "lpt", 64, 2, True), ((8, 16), "lpt", 64, 2, True), ((8, 16), "lpt", 64, 1, False),
     ((8, 8), "lpt", 0, 1, True), ((16, 16), "lpt", 0, 4, True), ((32, 8), "lpt", 128, 4, True),
     ((8, 8), "lpt", 64, 1, False), ((8, 8), "lpt", 0, 1, False), ((16, 16), "lpt", 0, 4, False),
+    # split forward (chunk items composited in parallel, joined per tile)
+    ((8, 8), "lpt+split", 64, 1, False), ((16, 16), "lpt+split", 64, 1, False),
 ]
 
 

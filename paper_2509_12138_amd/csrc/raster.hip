@@ -944,6 +944,303 @@ __global__ __launch_bounds__(kRasterWave) void k_raster_bwd_chunked_q(
   }
 }
 
+// ---------------------------------------------------------------- split forward
+
+// Forward of long tile lists in parallel (stored mode with chunk items).
+// Part 1: one wave per chunk item (tile, c) composites the chunk's entries
+// for the tile's pixels from a local transmittance of 1, ignoring the stop
+// rule: P = prod(1 - alpha) and L = sum rgb alpha T_local over the chunk
+// (the arithmetic of the sequential forward's chunk composites), and the
+// chunk-local position of the last blend.  The (P, L) of chunk c >= 1 go to
+// checkpoint slot c - 1, those of chunk 0 to slot nc - 1 (nc = the tile's
+// chunks; the backward never reads that slot, the last chunk starting from
+// the final state).
+template <int TW, int TH>
+__global__ __launch_bounds__(kRasterWave) void k_raster_fwd_part(RasterDev a, ChunkDev ch,
+                                                                uint16_t* __restrict__ clast) {
+  constexpr int PX = TileGeom<TW, TH>::PX;
+  __shared__ Splat s_splat[kRasterWave];
+  const uint32_t item = blockIdx.x;
+  if (item >= ch.offset[a.n_tiles]) return;
+  const int64_t tile = ch.items[item];
+  const uint32_t c0 = ch.offset[tile];
+  const int c = (int)(item - c0), nc = (int)(ch.offset[tile + 1] - c0);
+  const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+  const int len = (int)(end - start);
+  const int lo = c * ch.chunk, hi_pos = min(lo + ch.chunk, len);
+  const LanePixels<TW, TH> L(a, tile);
+  const PixBox box{(float)(L.tx * TW) + 0.5f, (float)(L.tx * TW + TW - 1) + 0.5f,
+                   (float)(L.ty * TH) + 0.5f, (float)(L.ty * TH + TH - 1) + 0.5f};
+  const int lane = threadIdx.x;
+  float fyk[PX], Tl[PX], Lc[PX][3];
+  int lastl[PX];
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    fyk[k] = L.inside[k] ? L.fy[k] : __builtin_nanf("");
+    Tl[k] = 1.0f;
+    Lc[k][0] = Lc[k][1] = Lc[k][2] = 0.0f;
+    lastl[k] = 0;
+  }
+  for (int b0 = lo; b0 < hi_pos; b0 += kRasterWave) {
+    const int n = min(kRasterWave, hi_pos - b0);
+    wave_sync();
+    bool hit = false;
+    if (lane < n) {
+      const Splat s = load_splat(a.rec, a.ids[start + b0 + lane]);
+      hit = splat_may_hit(s, box.x0, box.x1, box.y0, box.y1);
+      s_splat[lane] = s;
+    }
+    uint64_t todo = __ballot(hit);
+    wave_sync();
+    while (todo) {
+      const int j = (int)__builtin_ctzll(todo);
+      todo &= todo - 1;
+      const Splat sp = s_splat[j];
+      const float dx = __fsub_rn(L.fx, sp.mx);
+      float p2[PX];
+      splat_p2_column<PX>(sp, dx, fyk, p2);
+      bool pass[PX], any = false;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        pass[k] = splat_pass(sp, p2[k]);
+        any = any || pass[k];
+      }
+      if (!__any(any)) continue;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        if (!pass[k]) continue;
+        const float alpha = fminf(kAlphaMax, sp.o * splat_gauss(p2[k]));
+        const float wl = alpha * Tl[k];
+        Lc[k][0] = fmaf(sp.r, wl, Lc[k][0]);
+        Lc[k][1] = fmaf(sp.g, wl, Lc[k][1]);
+        Lc[k][2] = fmaf(sp.b, wl, Lc[k][2]);
+        Tl[k] = Tl[k] * (1.0f - alpha);
+        lastl[k] = b0 - lo + j + 1;
+      }
+    }
+  }
+  float4* ck = ch.ck + ((int64_t)c0 + (c >= 1 ? c - 1 : nc - 1)) * (TW * TH);
+  uint16_t* cl = clast + ((int64_t)c0 + c) * (TW * TH);
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    ck[lane + k * kRasterWave] = make_float4(Tl[k], Lc[k][0], Lc[k][1], Lc[k][2]);
+    cl[lane + k * kRasterWave] = (uint16_t)lastl[k];
+  }
+}
+
+// Part 2: one wave per tile joins its chunks in list order.  A pixel whose
+// transmittance stays at or above the cut-off through chunk c (T P_c >=
+// T_min: the partial products only fall, so no entry of the chunk stops
+// it) takes C += T L_c, T = T P_c; where T P_c < T_min the chunk is
+// composited again entry by entry from T with the stop rule (all lanes stage
+// it, the pixels concerned composite), and the pixel ends there.  Then the
+// image, T_final and n_contrib are written, and the checkpoints become the
+// (T_c, U_c) the backward reads, by the recursion of the sequential forward
+// over the chunks' (P, L) (identity after a pixel's stop, the partial
+// composite up to it in the stopping chunk).  Both walks over the chunks
+// keep D chunks' loads in flight: a long list's join is a chain of
+// dependent loads otherwise.
+template <int TW, int TH>
+__global__ __launch_bounds__(kRasterWave) void k_raster_fwd_join(
+    RasterDev a, TileSched sch, ChunkDev ch, const uint16_t* __restrict__ clast,
+    float* __restrict__ image, float* __restrict__ T_final, int32_t* __restrict__ n_contrib) {
+  constexpr int PX = TileGeom<TW, TH>::PX, NP = TW * TH;
+  constexpr int D = PX >= 4 ? 1 : 4 / PX;
+  __shared__ Splat s_splat[kRasterWave];
+  for_each_tile(sch, a.n_tiles, [&](int64_t tile) {
+    const LanePixels<TW, TH> L(a, tile);
+    const int lane = threadIdx.x;
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const int len = (int)(end - start);
+    const uint32_t c0 = ch.offset[tile];
+    const int nc = (int)(ch.offset[tile + 1] - c0);
+    float4* ck = ch.ck + (int64_t)c0 * NP;
+    const uint16_t* cl = clast + (int64_t)c0 * NP;
+    const PixBox box{(float)(L.tx * TW) + 0.5f, (float)(L.tx * TW + TW - 1) + 0.5f,
+                     (float)(L.ty * TH) + 0.5f, (float)(L.ty * TH + TH - 1) + 0.5f};
+    float T[PX], C[PX][3], Ps[PX], Ls[PX][3];
+    int last[PX], cs[PX];
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      T[k] = 1.0f;
+      C[k][0] = C[k][1] = C[k][2] = 0.0f;
+      last[k] = 0;
+      cs[k] = nc;                       // chunk of the stop (nc: none)
+      Ps[k] = 1.0f;
+      Ls[k][0] = Ls[k][1] = Ls[k][2] = 0.0f;
+    }
+    // chunk c's (P, L) sit in slot c - 1, chunk 0's in slot nc - 1
+    auto load_chunk = [&](int c, float4 (&pl)[PX], int (&ll)[PX]) {
+      const int sl = c >= 1 ? c - 1 : nc - 1;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        pl[k] = ck[(int64_t)sl * NP + lane + k * kRasterWave];
+        ll[k] = cl[(int64_t)c * NP + lane + k * kRasterWave];
+      }
+    };
+    auto join_chunk = [&](int c, const float4 (&pl)[PX], const int (&ll)[PX]) {
+      bool fix[PX], any_fix = false;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        fix[k] = false;
+        if (cs[k] < nc || !L.inside[k]) continue;
+        const float Tn = T[k] * pl[k].x;
+        if (Tn < kTMin) {
+          fix[k] = true;
+          any_fix = true;
+          continue;
+        }
+        C[k][0] = fmaf(T[k], pl[k].y, C[k][0]);
+        C[k][1] = fmaf(T[k], pl[k].z, C[k][1]);
+        C[k][2] = fmaf(T[k], pl[k].w, C[k][2]);
+        T[k] = Tn;
+        if (ll[k]) last[k] = c * ch.chunk + ll[k];
+      }
+      if (!__any(any_fix)) return;
+      // composite chunk c again, entry by entry with the stop rule, for the
+      // pixels whose transmittance reaches the cut-off inside it
+      float fyk[PX], Tl[PX], Lc[PX][3];
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        fyk[k] = fix[k] ? L.fy[k] : __builtin_nanf("");
+        Tl[k] = 1.0f;
+        Lc[k][0] = Lc[k][1] = Lc[k][2] = 0.0f;
+      }
+      const int lo = c * ch.chunk, hi_pos = min(lo + ch.chunk, len);
+      for (int b0 = lo; b0 < hi_pos; b0 += kRasterWave) {
+        const int n = min(kRasterWave, hi_pos - b0);
+        wave_sync();
+        bool hit = false;
+        if (lane < n) {
+          const Splat s = load_splat(a.rec, a.ids[start + b0 + lane]);
+          hit = splat_may_hit(s, box.x0, box.x1, box.y0, box.y1);
+          s_splat[lane] = s;
+        }
+        uint64_t todo = __ballot(hit);
+        wave_sync();
+        while (todo) {
+          const int j = (int)__builtin_ctzll(todo);
+          todo &= todo - 1;
+          const Splat sp = s_splat[j];
+          const float dx = __fsub_rn(L.fx, sp.mx);
+          float p2[PX];
+          splat_p2_column<PX>(sp, dx, fyk, p2);
+          bool pass[PX], any = false;
+#pragma unroll
+          for (int k = 0; k < PX; ++k) {
+            pass[k] = splat_pass(sp, p2[k]);
+            any = any || pass[k];
+          }
+          if (!__any(any)) continue;
+#pragma unroll
+          for (int k = 0; k < PX; ++k) {
+            if (!pass[k]) continue;
+            const float alpha = fminf(kAlphaMax, sp.o * splat_gauss(p2[k]));
+            const float Tn = T[k] * (1.0f - alpha);
+            if (Tn < kTMin) {              // the pixel stops; this entry is not blended
+              fyk[k] = __builtin_nanf("");
+              cs[k] = c;
+              continue;
+            }
+            const float w = alpha * T[k];
+            C[k][0] = fmaf(sp.r, w, C[k][0]);
+            C[k][1] = fmaf(sp.g, w, C[k][1]);
+            C[k][2] = fmaf(sp.b, w, C[k][2]);
+            const float wl = alpha * Tl[k];
+            Lc[k][0] = fmaf(sp.r, wl, Lc[k][0]);
+            Lc[k][1] = fmaf(sp.g, wl, Lc[k][1]);
+            Lc[k][2] = fmaf(sp.b, wl, Lc[k][2]);
+            Tl[k] = Tl[k] * (1.0f - alpha);
+            T[k] = Tn;
+            last[k] = b0 + j + 1;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < PX; ++k) {
+        if (cs[k] != c) continue;
+        Ps[k] = Tl[k];
+        Ls[k][0] = Lc[k][0];
+        Ls[k][1] = Lc[k][1];
+        Ls[k][2] = Lc[k][2];
+      }
+    };
+    float4 buf[D][PX];
+    int lbuf[D][PX];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+      if (d < nc) load_chunk(d, buf[d], lbuf[d]);
+    for (int cb = 0; cb < nc; cb += D) {
+      // every pixel stopped (or outside the image): the rest blends nothing
+      bool done = true;
+#pragma unroll
+      for (int k = 0; k < PX; ++k) done = done && (cs[k] < nc || !L.inside[k]);
+      if (__all(done)) break;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const int c = cb + d;
+        if (c >= nc) break;
+        float4 pl[PX];
+        int ll[PX];
+#pragma unroll
+        for (int k = 0; k < PX; ++k) {
+          pl[k] = buf[d][k];
+          ll[k] = lbuf[d][k];
+        }
+        if (c + D < nc) load_chunk(c + D, buf[d], lbuf[d]);
+        join_chunk(c, pl, ll);
+      }
+    }
+    const int64_t HW = (int64_t)a.H * a.W;
+    float* img = image + (int64_t)L.slot * 3 * HW;
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      if (!L.inside[k]) continue;
+      const int64_t o = L.offset(a, k);
+      img[o] = C[k][0] + T[k] * a.bg0;
+      img[HW + o] = C[k][1] + T[k] * a.bg1;
+      img[2 * HW + o] = C[k][2] + T[k] * a.bg2;
+      T_final[(int64_t)L.slot * HW + o] = T[k];
+      n_contrib[(int64_t)L.slot * HW + o] = last[k];
+    }
+    // checkpoints: slot c <- (T_c, U_c) from chunk c+1's (P, L), last first.
+    // The backward reads slot c only for pixels that blend after chunk c, so
+    // the walk starts below the last chunk holding a blend of any pixel
+    // (after it T_c = T_final and U_c = bg exactly).
+    int lc = 0;
+#pragma unroll
+    for (int k = 0; k < PX; ++k) lc = max(lc, (last[k] + ch.chunk - 1) / ch.chunk);
+    const int c_top = min(nc - 2, wave_max_int(lc) - 2);
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      float Tn = T[k], U[3] = {a.bg0, a.bg1, a.bg2};
+      float4* col = ck + lane + k * kRasterWave;
+      for (int cb = c_top; cb >= 0; cb -= D) {
+        float4 v[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+          if (cb - d >= 0) v[d] = col[(int64_t)(cb - d) * NP];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const int c = cb - d;
+          if (c < 0) break;
+          const int e = c + 1;
+          const float4 pl = e > cs[k] ? make_float4(1.0f, 0.0f, 0.0f, 0.0f)
+                                      : (e == cs[k] ? make_float4(Ps[k], Ls[k][0], Ls[k][1],
+                                                                  Ls[k][2])
+                                                    : v[d]);
+          const float Te = Tn / pl.x;
+          U[0] = fmaf(pl.x, U[0], pl.y);
+          U[1] = fmaf(pl.x, U[1], pl.z);
+          U[2] = fmaf(pl.x, U[2], pl.w);
+          col[(int64_t)c * NP] = make_float4(Te, U[0], U[1], U[2]);
+          Tn = Te;
+        }
+      }
+    }
+  });
+}
+
 // ---------------------------------------------------------------- support count
 
 // Per pixel, the number of list entries it blends (alpha test passed,
@@ -1308,6 +1605,15 @@ static void launch_fwd(const RasterDev& a, const Launch& L, float* image, float*
 }
 
 template <int TW, int TH>
+static void launch_fwd_split(const RasterDev& a, const Launch& L, uint16_t* chunk_last,
+                             float* image, float* T_final, int32_t* n_contrib, hipStream_t s) {
+  hipLaunchKernelGGL((k_raster_fwd_part<TW, TH>), dim3((unsigned)L.max_items), dim3(kRasterWave),
+                     0, s, a, L.ch, chunk_last);
+  hipLaunchKernelGGL((k_raster_fwd_join<TW, TH>), dim3(L.blocks), dim3(kRasterWave), 0, s, a,
+                     L.sch, L.ch, chunk_last, image, T_final, n_contrib);
+}
+
+template <int TW, int TH>
 static void launch_bwd(const RasterDev& a, const Launch& L, const float* T_final,
                        const int32_t* n_contrib, const float* d_image, int mode, float* d_rec,
                        hipStream_t s) {
@@ -1490,10 +1796,16 @@ gs_status gs_raster_fwd(const gs_projected* proj, const gs_views* views, const g
   st = plan_prepare(plan, tiling, s, "gs_raster_fwd");
   if (st != GS_OK) return st;
   const Launch L = make_launch(a, plan);
-#define GS_FWD_CASE(a_, b_)                                              \
-  if (tiling->tile_w == a_ && tiling->tile_h == b_)                      \
-    launch_fwd<a_, b_>(a, L, image, T_final, n_contrib, s);              \
-  else
+  const bool split = plan && plan->fwd_split && L.ch.ck != nullptr;
+  GS_REQUIRE(!split || (plan->chunk_last && T_final),
+             "gs_raster_fwd: fwd_split needs chunk_last and the stored state (T_final, n_contrib)");
+#define GS_FWD_CASE(a_, b_)                                                          \
+  if (tiling->tile_w == a_ && tiling->tile_h == b_) {                                \
+    if (split)                                                                       \
+      launch_fwd_split<a_, b_>(a, L, plan->chunk_last, image, T_final, n_contrib, s); \
+    else                                                                             \
+      launch_fwd<a_, b_>(a, L, image, T_final, n_contrib, s);                        \
+  } else
   GS_RASTER_SHAPES(GS_FWD_CASE) {}
 #undef GS_FWD_CASE
   GS_LAUNCH_CHECK("gs_raster_fwd");

@@ -204,7 +204,7 @@ class RasterBuffers:
     # ---------------------------------------------------------- tile schedule
 
     def set_schedule(self, mode="default", persistent_waves=0, chunk=0, fwd_waves=1,
-                     deterministic=False):
+                     deterministic=False, split=False):
         """How the rasterisers walk the tiles: "default" (XCD-aware order, one
         work-group per tile), "lpt" (longest tile lists first) or "persistent"
         (longest first, pulled from an atomic queue by a persistent grid).
@@ -212,12 +212,18 @@ class RasterBuffers:
         chunk-entry work items (stored mode), using forward checkpoints.
         fwd_waves (1, 2, 4) splits each tile's pixels over that many waves in
         the forward.  deterministic: per-entry gradient slots summed per pair
-        instead of atomics (bitwise reproducible gradients)."""
+        instead of atomics (bitwise reproducible gradients).  split (chunked
+        plans; also a "+split" suffix of the mode, e.g. "lpt+split"): the
+        forward composites the chunk items in parallel and joins them per
+        tile."""
         dev = self.views.device
+        if mode.endswith("+split"):
+            mode, split = mode[:-len("+split")], True
         self.schedule = mode
         self.chunk = int(chunk) if self.store_state else 0
         self.fwd_waves = int(fwd_waves)
         self.deterministic = bool(deterministic)
+        self.split = bool(split) and self.chunk > 0
         n = self.S * self.tiles_per_slot
         self.plan = _lib.gs_raster_plan()
         self.plan.fwd_waves = self.fwd_waves
@@ -259,6 +265,11 @@ class RasterBuffers:
         self.plan.chunk_items = self.chunk_items.data_ptr()
         self.plan.checkpoints = self.checkpoints.data_ptr()
         self.plan.max_items = self.max_items
+        if getattr(self, "split", False):
+            self.chunk_last = torch.empty((self.max_items, self.tile[0] * self.tile[1]),
+                                          dtype=torch.int16, device=dev)
+            self.plan.fwd_split = 1
+            self.plan.chunk_last = self.chunk_last.data_ptr()
 
     def order_tiles(self, stream=None):
         """Per-step plan inputs that depend on the sorted lists."""

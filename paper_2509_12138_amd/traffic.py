@@ -23,7 +23,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {"k_raster_bwd_chunked": "raster.hip", "k_raster_bwd": "raster.hip",
                   "k_raster_fwd": "raster.hip", "k_dup_reduce": "raster.hip",
-                  "k_raster_bwd_chunked_q": "raster.hip",
+                  "k_raster_bwd_chunked_q": "raster.hip", "k_raster_fwd_part": "raster.hip",
+                  "k_raster_fwd_join": "raster.hip",
                   "k_project_bwd_adam": "project.hip", "k_project": "project.hip",
                   "k_ssim": "loss.hip", "k_adam": "adam.hip", "k_radix_scatter": "binsort.hip",
                   "k_emit": "binsort.hip"}

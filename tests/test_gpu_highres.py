@@ -146,14 +146,15 @@ def oracle_subset(hr):
     return _oracle_windows
 
 
-@pytest.mark.parametrize("stored", [True, False], ids=["stored", "recompute"])
-def test_highres_raster_on_subset_footprints_matches_oracle(hr, stored):
+@pytest.mark.parametrize("stored,sched", [(True, "lpt"), (False, "lpt"), (True, "lpt+split")],
+                         ids=["stored", "recompute", "split"])
+def test_highres_raster_on_subset_footprints_matches_oracle(hr, stored, sched):
     from paper_2509_12138_amd import ops
     n = hr["n"]
-    say(f"high-res raster, subset footprints, stored={stored}")
+    say(f"high-res raster, subset footprints, stored={stored} {sched}")
     bufs = ops.RasterBuffers(ops.Views.single(n, hr["cam"]), W, H, TILE, dup_capacity=1024,
                              store_state=stored)
-    bufs.set_schedule("lpt", chunk=64 if stored else 0, fwd_waves=4)
+    bufs.set_schedule(sched, chunk=64 if stored else 0, fwd_waves=4)
     raster_records(bufs, hr["rec"], hr["tb"], hr["nt"], (0.0, 0.0, 0.0), torch)
     bufs.zero_d_rec()
     bufs.raster_bwd(torch.as_tensor(hr["dI"][None].astype(np.float32)).cuda())

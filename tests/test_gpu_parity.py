@@ -537,6 +537,61 @@ def test_chunked_backward_matches_oracle(ops, chunk, sched, det, tile):
         assert ok0 and ok, (worst0, worst)
 
 
+@pytest.mark.parametrize("tile,shift,sched", [((8, 8), 0.0, "lpt"), ((8, 8), 3.0, "lpt"),
+                                              ((16, 16), 3.0, "default"), ((8, 16), 1.5, "lpt")])
+def test_split_forward_matches_sequential_and_oracle(ops, tile, shift, sched):
+    """The split forward (chunk items composited in parallel, joined per
+    tile, stopping chunks composited again with the stop rule) gives the
+    sequential forward's image, T_final and n_contrib up to FP32 rounding,
+    the oracle's within the usual bands, and checkpoints from which the
+    chunked backward reaches the oracle's gradients.  shift raises the
+    opacities so that many pixels stop inside a chunk."""
+    say("split forward", tile, shift, sched)
+    W, H = 112, 80
+    params = perturbed(surface_scene(20000, 81), 81, amount=0.2)
+    params["opacity_logit"] = (params["opacity_logit"] + shift).astype(np.float32)
+    cams = scene.orbit_cameras(2, W, H)
+    bg = (0.05, 0.1, 0.2)
+    rec, tb, nt, views = oracle_records(params, cams, W, H, tile)
+    dI = masked_image_gradient(np.random.default_rng(3), H, W)
+    res = {}
+    for split in (False, True):
+        bufs = make_bufs(ops, params, cams, W, H, tile)
+        bufs.set_schedule(sched + ("+split" if split else ""), chunk=64)
+        raster_records(bufs, rec, tb, nt, bg, torch)
+        bufs.zero_d_rec()
+        bufs.raster_bwd(torch.as_tensor(dI).cuda(), bg=bg)
+        torch.cuda.synchronize()
+        res[split] = (bufs.image.cpu().numpy(), bufs.T_final.cpu().numpy(),
+                      bufs.n_contrib.cpu().numpy(), bufs.d_rec.cpu().numpy().astype(np.float64))
+        lens = (bufs.ranges.cpu().numpy()[:, 1] - bufs.ranges.cpu().numpy()[:, 0]).astype(np.int64)
+        assert lens.max() > 3 * 64                             # several chunks per long tile
+    (i0, t0, n0, g0), (i1, t1, n1, g1) = res[False], res[True]
+    # the colour sums and transmittance products round in another order
+    assert np.abs(i1 - i0).max() <= 1e-5
+    assert np.all(np.abs(t1 - t0) <= 1e-4 * np.maximum(t0, 1e-4))
+    same = n1 == n0
+    assert same.mean() >= 0.999, same.mean()
+    n = 20000
+    stopped = 0
+    for v in range(2):
+        o = oracle.render(views[v], W, H, tile=tile, bg=bg)
+        amb = (o["ambiguity"] & SAME_RECORD_BITS) != 0
+        assert amb.mean() <= 5e-3
+        ok = ~amb
+        assert np.abs(i1[v] - o["image"])[:, ok].max() <= 1e-4
+        okp = ok & ((o["ambiguity"] & 32) == 0)            # list positions
+        np.testing.assert_array_equal(n1[v][okp], o["n_contrib"][okp])
+        stopped += int(((o["T_final"] * 0.5 < 1e-4) & ok).sum())
+        sl = slice(v * n, (v + 1) * n)
+        b = oracle.render_bwd(views[v], W, H, dI[v], tile=tile, bg=bg, amb_bits=SAME_RECORD_BITS)
+        ref = np.concatenate([b["d_mean2d"], b["d_conic"], b["d_opacity"][None], b["d_rgb"]]).T
+        ok1, worst = grad_tolerance_check(g1[sl], ref, b["term_mass"].T, b["amb_mass"].T)
+        assert ok1, worst
+    if shift > 0:
+        assert stopped > 100, stopped                         # the stop path is exercised
+
+
 @pytest.mark.parametrize("tile,fwd_waves", [((16, 16), 2), ((16, 16), 4), ((8, 16), 2),
                                             ((32, 16), 4)])
 def test_forward_waves_give_identical_results(ops, tile, fwd_waves):
