@@ -18,7 +18,9 @@ import numpy as np
 import torch
 
 # (tile, schedule, backward chunk, forward waves per tile, deterministic
-# gradients); every tile shape here has a compiled rasteriser
+# gradients); every tile shape here has a compiled rasteriser.  A fixed set
+# of plans (the full-size parity tests run each); the tuner itself searches
+# the plan space in stages (staged_search)
 CANDIDATES = [
     ((16, 16), "lpt", 64, 4, True), ((16, 16), "lpt", 64, 4, False),
     ((16, 16), "lpt", 128, 4, True), ((16, 16), "lpt", 64, 2, True),
@@ -27,7 +29,8 @@ CANDIDATES = [
     ((8, 8), "lpt", 0, 1, True), ((16, 16), "lpt", 0, 4, True), ((32, 8), "lpt", 128, 4, True),
     ((8, 8), "lpt", 64, 1, False), ((8, 8), "lpt", 0, 1, False), ((16, 16), "lpt", 0, 4, False),
     # split forward (chunk items composited in parallel, joined per tile)
-    ((8, 8), "lpt+split", 64, 1, False), ((16, 16), "lpt+split", 64, 1, False),
+    ((8, 8), "lpt+split", 64, 1, False), ((8, 8), "lpt+split", 128, 1, False),
+    ((16, 16), "lpt+split", 64, 1, False),
 ]
 
 
@@ -83,10 +86,61 @@ def time_plan(make_trainer, plan, views, steps=8, warmup=2):
     return ms
 
 
+TILES = [(16, 16), (8, 8), (16, 8), (8, 16), (32, 8), (32, 16), (16, 32)]
+SCHEDULES = ["lpt", "default", "persistent", "lpt+split"]
+
+
+def valid_waves(tile):
+    """Forward waves per tile that divide the tile's pixels per lane."""
+    px = tile[0] * tile[1] // 64
+    return [w for w in (1, 2, 4) if px % w == 0]
+
+
+def valid(plan):
+    tile, sched, chunk, nw, det = plan
+    if sched == "persistent" and nw > 1:
+        return False                                   # the queue takes one wave per tile
+    if sched.endswith("+split") and (chunk == 0 or nw != 1):
+        return False                                   # split: chunked, joined by one wave
+    return nw in valid_waves(tile)
+
+
+def staged_search(measure, stored):
+    """Coordinate search over the plan space: every tile shape with a
+    representative plan (LPT order, 64-entry chunks, the most forward waves
+    the shape allows, atomic sums), then, for the two fastest shapes, one
+    parameter at a time from the best plan so far: schedule (LPT, XCD-aware,
+    persistent, split forward), backward chunk (64, 128, whole tiles),
+    forward waves, deterministic sums."""
+    first = {}
+    for tile in TILES:
+        plan = (tile, "lpt", 64 if stored else 0, max(valid_waves(tile)), False)
+        ms = measure(plan)
+        if ms is not None:
+            first[tile] = (ms, plan)
+    for tile in sorted(first, key=lambda t: first[t][0])[:2]:
+        best_ms, best = first[tile]
+        axes = [lambda p, v: (p[0], v, p[2], 1 if v.endswith("+split") or v == "persistent"
+                               else p[3], p[4]),
+                lambda p, v: (p[0], p[1], v, p[3], p[4]),
+                lambda p, v: (p[0], p[1], p[2], v, p[4]),
+                lambda p, v: (p[0], p[1], p[2], p[3], v)]
+        values = [SCHEDULES, [64, 128, 0] if stored else [0], valid_waves(tile), [False, True]]
+        for axis, vals in zip(axes, values):
+            for v in vals:
+                plan = axis(best, v)
+                if not valid(plan):
+                    continue
+                ms = measure(plan)
+                if ms is not None and ms < best_ms:
+                    best_ms, best = ms, plan
+
+
 def tune(make_trainer, width, height, n_slots, n_gauss, stored=True, views=None,
          candidates=None, cache_path=DEFAULT_CACHE, force=False, log=None):
     """Return the fastest (tile, schedule, chunk, fwd_waves, deterministic)
-    for this workload.
+    for this workload: the given candidate plans, or the staged search over
+    the plan space (staged_search).
 
     make_trainer(tile) builds a fresh trainer (with .bufs, .step(view),
     .fit_capacity(views=...), .check()).  The choice is cached unless force.
@@ -99,14 +153,24 @@ def tune(make_trainer, width, height, n_slots, n_gauss, stored=True, views=None,
                           e.get("deterministic", False))), e
     views = list(views if views is not None else range(8))
     results = []
-    for plan in (candidates or CANDIDATES):
+    timed = {}
+
+    def measure(plan):
         plan = normalize(plan)
         if not stored and plan[2]:
-            continue                                   # chunking needs stored state
-        ms = time_plan(make_trainer, plan, views)
-        results.append((ms, plan))
-        if log:
-            log(f"autotune {plan}: {ms:.3f} ms/step")
+            return None                                # chunking needs stored state
+        if plan not in timed:
+            timed[plan] = time_plan(make_trainer, plan, views)
+            results.append((timed[plan], plan))
+            if log:
+                log(f"autotune {plan}: {timed[plan]:.3f} ms/step")
+        return timed[plan]
+
+    if candidates is not None:
+        for plan in candidates:
+            measure(plan)
+    else:
+        staged_search(measure, stored)
     ms, best = min(results, key=lambda r: r[0])
     entry = dict(tile=list(best[0]), schedule=best[1], chunk=best[2], fwd_waves=best[3],
                  deterministic=best[4], ms_per_step=ms,

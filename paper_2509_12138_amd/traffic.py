@@ -27,7 +27,7 @@ KERNEL_SOURCES = {"k_raster_bwd_chunked": "raster.hip", "k_raster_bwd": "raster.
                   "k_raster_fwd_join": "raster.hip",
                   "k_project_bwd_adam": "project.hip", "k_project": "project.hip",
                   "k_ssim": "loss.hip", "k_adam": "adam.hip", "k_radix_scatter": "binsort.hip",
-                  "k_emit": "binsort.hip"}
+                  "k_emit": "binsort.hip", "k_depth_keys": "binsort.hip"}
 COPY_BYTES = 512 * 1024 * 1024
 
 
