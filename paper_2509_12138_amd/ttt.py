@@ -44,7 +44,8 @@ GHOST_VOXELS = 2
 
 
 def log(*a):
-    print("[ttt]", *a, flush=True)
+    # progress goes to stderr: stdout carries the JSON results only
+    print("[ttt]", *a, file=sys.stderr, flush=True)
 
 
 SURFACE_EXTENT = 0.56    # the isosurface |x| = 0.5 +- 0.05 lies inside [-0.56, 0.56]^3
