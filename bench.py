@@ -296,6 +296,7 @@ def time_to_target(wl, targets, masks, plan, target=35.0, max_steps=2000, eval_e
 BATCHED_CANDIDATES = [
     ((16, 16), "lpt", 64, 4, False), ((8, 8), "lpt", 64, 1, False), ((16, 8), "lpt", 64, 2, False),
     ((8, 16), "lpt", 64, 2, False), ((32, 8), "lpt", 128, 4, False), ((16, 16), "lpt", 128, 4, False),
+    ((8, 8), "lpt+split", 64, 1, False), ((8, 8), "lpt+split", 128, 1, False),
 ]
 
 
