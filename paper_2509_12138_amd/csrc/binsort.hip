@@ -459,7 +459,7 @@ static void launch_hist(const uint64_t* keys, const int64_t* count, int shift, i
   constexpr int G = 8;
   // (for 8-bit digits the grouped kernel measured slower: 49 vs 41 us a pass
   // over 13.3M keys; for 9-bit digits 84 against 164 us over 20.7M)
-  if (RB > kRadixBits && nb >= 2048)
+  if ((RB > kRadixBits && nb >= 2048) || nb >= 16384)
     hipLaunchKernelGGL((k_radix_hist_g<RB, G>), dim3((unsigned)((nb + G - 1) / G)),
                        dim3(kSortThreads), 0, s, keys, count, shift, nb, hist);
   else
@@ -467,29 +467,12 @@ static void launch_hist(const uint64_t* keys, const int64_t* count, int shift, i
                        count, shift, nb, hist);
 }
 
-// One workgroup per digit: exclusive scan of that digit's per-block counts.
-__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* __restrict__ hist, int64_t nb,
-                                                       uint32_t* __restrict__ row_tot) {
-  __shared__ uint32_t sm[4];
-  uint32_t* row = hist + (int64_t)blockIdx.x * nb;
-  const int64_t seg = ceil_div(nb, 256);
-  const int64_t b0 = threadIdx.x * seg, b1 = min(b0 + seg, nb);
-  uint32_t s = 0;
-  for (int64_t b = b0; b < b1; ++b) s += row[b];
-  uint32_t total;
-  uint32_t ex = block_exclusive_scan<uint32_t>(s, sm, total);
-  for (int64_t b = b0; b < b1; ++b) {
-    uint32_t x = row[b];
-    row[b] = ex;
-    ex += x;
-  }
-  if (threadIdx.x == 0) row_tot[blockIdx.x] = total;
-}
-
-// Rows of up to kRowLds block counts: the row is staged in LDS with
-// coalesced loads, each thread scans its segment there, and the row goes
-// back with coalesced stores.  (In the plain version above every global
-// access of a wave touches 64 lines: 43 us per pass at 17K blocks.)
+// The row of a digit's block counts is scanned in segments of up to kRowLds
+// counts staged in LDS with coalesced loads (each thread scans its part
+// there) and written back with coalesced stores, the running total carried
+// from segment to segment.  (Scanning per-thread segments in global memory
+// instead, every access of a wave touched 64 lines: 43 us per pass at 17K
+// blocks, 475 us at 50K.)
 constexpr int kRowLds = 32768;                      // 128 KB of the 160 KB LDS
 
 __global__ __launch_bounds__(256) void k_radix_rowscan_lds(uint32_t* __restrict__ hist, int64_t nb,
@@ -497,31 +480,34 @@ __global__ __launch_bounds__(256) void k_radix_rowscan_lds(uint32_t* __restrict_
   __shared__ uint32_t r[kRowLds];
   __shared__ uint32_t sm[4];
   uint32_t* row = hist + (int64_t)blockIdx.x * nb;
-  const int n = (int)nb;
-  for (int i = threadIdx.x; i < n; i += 256) r[i] = row[i];
-  __syncthreads();
-  const int seg = (n + 255) / 256;
-  const int b0 = min((int)threadIdx.x * seg, n), b1 = min(b0 + seg, n);
-  uint32_t s = 0;
-  for (int b = b0; b < b1; ++b) s += r[b];
-  uint32_t total;
-  uint32_t ex = block_exclusive_scan<uint32_t>(s, sm, total);
-  for (int b = b0; b < b1; ++b) {
-    const uint32_t x = r[b];
-    r[b] = ex;
-    ex += x;
+  uint32_t carry = 0;
+  for (int64_t s0 = 0; s0 < nb; s0 += kRowLds) {
+    const int n = (int)min((int64_t)kRowLds, nb - s0);
+    uint32_t* seg = row + s0;
+    for (int i = threadIdx.x; i < n; i += 256) r[i] = seg[i];
+    __syncthreads();
+    const int per = (n + 255) / 256;
+    const int b0 = min((int)threadIdx.x * per, n), b1 = min(b0 + per, n);
+    uint32_t sum = 0;
+    for (int b = b0; b < b1; ++b) sum += r[b];
+    uint32_t total;
+    uint32_t ex = carry + block_exclusive_scan<uint32_t>(sum, sm, total);
+    for (int b = b0; b < b1; ++b) {
+      const uint32_t x = r[b];
+      r[b] = ex;
+      ex += x;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += 256) seg[i] = r[i];
+    carry += total;
+    __syncthreads();                                 // LDS reused by the next segment
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += 256) row[i] = r[i];
-  if (threadIdx.x == 0) row_tot[blockIdx.x] = total;
+  if (threadIdx.x == 0) row_tot[blockIdx.x] = carry;
 }
 
 static void launch_rowscan(uint32_t* hist, int64_t nb, uint32_t* row_tot, int digits,
                            hipStream_t s) {
-  if (nb <= kRowLds)
-    hipLaunchKernelGGL(k_radix_rowscan_lds, dim3(digits), dim3(256), 0, s, hist, nb, row_tot);
-  else
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(digits), dim3(256), 0, s, hist, nb, row_tot);
+  hipLaunchKernelGGL(k_radix_rowscan_lds, dim3(digits), dim3(256), 0, s, hist, nb, row_tot);
 }
 
 // One stable LSD pass over RB-bit digits (1 << RB of them; each thread owns

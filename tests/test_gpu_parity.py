@@ -161,19 +161,23 @@ def test_bin_sort_bit_exact(ops, m, S, tile, W, H, seed, span):
     np.testing.assert_array_equal(gr, ranges)
 
 
-@pytest.mark.parametrize("m,tile,W,H,S", [(1100000, (8, 8), 3840, 2160, 1),
-                                          (600000, (16, 16), 1920, 1080, 3)])
-def test_bin_sort_large_capacity_bit_exact(ops, m, tile, W, H, S):
-    """A duplicate capacity of 5M keys (2442 radix blocks): the tile passes
-    count digits with the grouped-block histogram.  (The depth presort uses
-    it above 4M pairs, which the high-resolution sort test covers.)"""
+@pytest.mark.parametrize("m,tile,W,H,S,cap", [(1100000, (8, 8), 3840, 2160, 1, 5_000_000),
+                                              (600000, (16, 16), 1920, 1080, 3, 5_000_000),
+                                              (300000, (16, 16), 1920, 1080, 2, 70_000_000)])
+def test_bin_sort_large_capacity_bit_exact(ops, m, tile, W, H, S, cap):
+    """Large duplicate capacities: 5M keys (2442 radix blocks), where the
+    9-bit tile passes count digits with the grouped-block histogram (the
+    depth presort uses it above 4M pairs, which the high-resolution sort test
+    covers), and 70M keys (34K blocks), where every digit's row of block
+    counts is scanned in two LDS segments and the 8-bit passes count with
+    the grouped histogram too."""
     say("bin_sort large capacity", m, tile)
     tx, ty = math.ceil(W / tile[0]), math.ceil(H / tile[1])
     tb, nt, depth, slot, sup = synthetic_pairs(m, tx, ty, S, 7, tile)
     keys, ids, ranges = oracle.bin_sort(tb, nt, depth, slot, tx, tx * ty, S,
                                         sup=sup.astype(np.float64), tile=tile)
     K = len(ids)
-    bufs, st, req = run_binsort(ops, tb, nt, depth, slot, sup, W, H, tile, S, cap=5_000_000)
+    bufs, st, req = run_binsort(ops, tb, nt, depth, slot, sup, W, H, tile, S, cap=cap)
     assert st == 0 and req == K
     np.testing.assert_array_equal(bufs.keys[:K].cpu().numpy().view(np.uint64), keys)
     np.testing.assert_array_equal(bufs.ids[:K].cpu().numpy().view(np.uint32), ids)
