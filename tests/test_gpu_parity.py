@@ -560,16 +560,19 @@ def test_chunked_backward_matches_oracle(ops, chunk, sched, det, tile):
         assert ok0 and ok, (worst0, worst)
 
 
-@pytest.mark.parametrize("tile,shift,sched", [((8, 8), 0.0, "lpt"), ((8, 8), 3.0, "lpt"),
-                                              ((16, 16), 3.0, "default"), ((8, 16), 1.5, "lpt")])
-def test_split_forward_matches_sequential_and_oracle(ops, tile, shift, sched):
+@pytest.mark.parametrize("tile,shift,sched,det", [((8, 8), 0.0, "lpt", False),
+                                                  ((8, 8), 3.0, "lpt", False),
+                                                  ((16, 16), 3.0, "default", False),
+                                                  ((8, 16), 1.5, "lpt", False),
+                                                  ((8, 8), 3.0, "persistent", True)])
+def test_split_forward_matches_sequential_and_oracle(ops, tile, shift, sched, det):
     """The split forward (chunk items composited in parallel, joined per
     tile, stopping chunks composited again with the stop rule) gives the
     sequential forward's image, T_final and n_contrib up to FP32 rounding,
     the oracle's within the usual bands, and checkpoints from which the
     chunked backward reaches the oracle's gradients.  shift raises the
     opacities so that many pixels stop inside a chunk."""
-    say("split forward", tile, shift, sched)
+    say("split forward", tile, shift, sched, "deterministic" if det else "atomic")
     W, H = 112, 80
     params = perturbed(surface_scene(20000, 81), 81, amount=0.2)
     params["opacity_logit"] = (params["opacity_logit"] + shift).astype(np.float32)
@@ -580,7 +583,7 @@ def test_split_forward_matches_sequential_and_oracle(ops, tile, shift, sched):
     res = {}
     for split in (False, True):
         bufs = make_bufs(ops, params, cams, W, H, tile)
-        bufs.set_schedule(sched + ("+split" if split else ""), chunk=64)
+        bufs.set_schedule(sched + ("+split" if split else ""), chunk=64, deterministic=det)
         raster_records(bufs, rec, tb, nt, bg, torch)
         bufs.zero_d_rec()
         bufs.raster_bwd(torch.as_tensor(dI).cuda(), bg=bg)
