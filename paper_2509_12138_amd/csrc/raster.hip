@@ -120,16 +120,27 @@ __device__ __forceinline__ void tile_forward(const float* __restrict__ rec,
     }
   }
   uint32_t reached = 0;     // list entries processed (CHUNKED bookkeeping)
+  // the next batch's records and the id of the one after are loaded while a
+  // batch is composited, so a batch boundary does not wait on the two
+  // dependent loads (id, then record)
+  RawSplat nraw{};
+  uint32_t nid2 = 0;
+  if (start + lane < end) nraw = fetch_splat(rec, ids[start + lane]);
+  if (start + kRasterWave + lane < end) nid2 = ids[start + kRasterWave + lane];
   for (uint32_t b0 = start; b0 < end; b0 += kRasterWave) {
     bool lane_done = true;
 #pragma unroll
     for (int k = 0; k < PX; ++k) lane_done = lane_done && (fyk[k] != fyk[k]);
     if (__all(lane_done)) break;
     const int n = (int)min((uint32_t)kRasterWave, end - b0);
+    const RawSplat raw = nraw;
+    const uint32_t nid = nid2;
+    if (b0 + kRasterWave + lane < end) nraw = fetch_splat(rec, nid);
+    if (b0 + 2 * kRasterWave + lane < end) nid2 = ids[b0 + 2 * kRasterWave + lane];
     wave_sync();
     bool hit = false;
     if (lane < n) {
-      const Splat s = load_splat(rec, ids[b0 + lane]);
+      const Splat s = make_splat(raw);
       hit = splat_may_hit(s, box.x0, box.x1, box.y0, box.y1);
       s_splat[lane] = s;
     }
