@@ -405,12 +405,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
   __syncthreads();
   const int64_t n = count[0];
   const int64_t base = (int64_t)blockIdx.x * kSortItems;
-  if (base < n) {
+  // blocks past the count are never read (the row scans and the scatter
+  // stop at the last block that holds keys)
+  if (base >= n) return;
 #pragma unroll 4
-    for (int k = 0; k < kSortPer; ++k) {
-      int64_t i = base + k * kSortThreads + t;
-      if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (R - 1)], 1u);
-    }
+  for (int k = 0; k < kSortPer; ++k) {
+    int64_t i = base + k * kSortThreads + t;
+    if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (R - 1)], 1u);
   }
   __syncthreads();
 #pragma unroll
@@ -436,6 +437,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist_g(const uint64_t* _
   __syncthreads();
   const int64_t n = count[0];
   const int64_t b0 = (int64_t)blockIdx.x * G;
+  const int64_t nb_used = min(nb, (n + kSortItems - 1) / kSortItems);
+  if (b0 >= nb_used) return;
   for (int g = 0; g < G; ++g) {
     const int64_t base = (b0 + g) * kSortItems;
     if (base >= n) break;
@@ -448,7 +451,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist_g(const uint64_t* _
   __syncthreads();
   for (int idx = t; idx < G * R; idx += kSortThreads) {
     const int d = idx / G, g = idx - d * G;
-    if (b0 + g < nb) hist[(int64_t)d * nb + b0 + g] = h[g * RP + d];
+    if (b0 + g < nb_used) hist[(int64_t)d * nb + b0 + g] = h[g * RP + d];
   }
 }
 
@@ -476,13 +479,16 @@ static void launch_hist(const uint64_t* keys, const int64_t* count, int shift, i
 constexpr int kRowLds = 32768;                      // 128 KB of the 160 KB LDS
 
 __global__ __launch_bounds__(256) void k_radix_rowscan_lds(uint32_t* __restrict__ hist, int64_t nb,
+                                                           const int64_t* __restrict__ count,
                                                            uint32_t* __restrict__ row_tot) {
   __shared__ uint32_t r[kRowLds];
   __shared__ uint32_t sm[4];
   uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+  // the row's first nb_used counts: the blocks that hold keys
+  const int64_t nb_used = min(nb, (count[0] + kSortItems - 1) / kSortItems);
   uint32_t carry = 0;
-  for (int64_t s0 = 0; s0 < nb; s0 += kRowLds) {
-    const int n = (int)min((int64_t)kRowLds, nb - s0);
+  for (int64_t s0 = 0; s0 < nb_used; s0 += kRowLds) {
+    const int n = (int)min((int64_t)kRowLds, nb_used - s0);
     uint32_t* seg = row + s0;
     for (int i = threadIdx.x; i < n; i += 256) r[i] = seg[i];
     __syncthreads();
@@ -505,15 +511,21 @@ __global__ __launch_bounds__(256) void k_radix_rowscan_lds(uint32_t* __restrict_
   if (threadIdx.x == 0) row_tot[blockIdx.x] = carry;
 }
 
-static void launch_rowscan(uint32_t* hist, int64_t nb, uint32_t* row_tot, int digits,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_radix_rowscan_lds, dim3(digits), dim3(256), 0, s, hist, nb, row_tot);
+static void launch_rowscan(uint32_t* hist, int64_t nb, const int64_t* count, uint32_t* row_tot,
+                           int digits, hipStream_t s) {
+  hipLaunchKernelGGL(k_radix_rowscan_lds, dim3(digits), dim3(256), 0, s, hist, nb, count,
+                     row_tot);
 }
 
 // One stable LSD pass over RB-bit digits (1 << RB of them; each thread owns
-// 1 << RB / 256 consecutive digits).  vin2 / vout2 (may be NULL): a second
-// value carried along.
-template <int RB>
+// 1 << RB / 256 consecutive digits).  TWO: a second value vin2 -> vout2 is
+// carried along.  The block's 2048 items are ranked in 8 rounds of 256 (item
+// base + r * 256 + t in round r): within a wave by ballots over the digit
+// bits, then per round the owner of each digit turns the 4 waves' counts
+// into offsets after the items of earlier rounds and waves, so the LDS holds
+// one round's counts (double-buffered) instead of all 32 (round, wave) rows
+// and more blocks fit on a CU.
+template <int RB, bool TWO>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, const int64_t* __restrict__ count,
@@ -521,13 +533,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t* __restrict__ vin2, uint32_t* __restrict__ vout2) {
   constexpr int R = 1 << RB, DPT = R / kSortThreads;
   static_assert(DPT >= 1 && R % kSortThreads == 0, "digits per thread");
-  // LDS: per (round, wave, digit) counts; staging of the block's items
-  __shared__ uint16_t s_cnt[kSortPer][4][R];         // 16 KB (8-bit), 32 KB (9-bit)
-  __shared__ uint64_t s_key[kSortItems];             // 16 KB
-  __shared__ uint32_t s_val[kSortItems];             // 8 KB
-  __shared__ uint32_t s_val2[kSortItems];            // 8 KB
-  __shared__ uint32_t s_dstart[R];                   // local digit starts
-  __shared__ uint32_t s_gbase[R];                    // global digit base of this block
+  __shared__ uint16_t s_cnt[2][4][R];               // one round's (wave, digit) counts
+  __shared__ uint32_t s_run[R];                     // items of earlier rounds per digit
+  __shared__ uint64_t s_key[kSortItems];            // 16 KB
+  __shared__ uint32_t s_val[kSortItems];            // 8 KB
+  __shared__ uint32_t s_val2[TWO ? kSortItems : 1];
+  __shared__ uint32_t s_dstart[R];                  // local digit starts
+  __shared__ uint32_t s_gbase[R];                   // global digit base of this block
   __shared__ uint32_t s_w[4];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t n = count[0];
@@ -551,49 +563,60 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
       ex += rt[q];
     }
   }
-  {
-    uint32_t* z = reinterpret_cast<uint32_t*>(&s_cnt[0][0][0]);
-    for (int i = t; i < kSortPer * 4 * R / 2; i += kSortThreads) z[i] = 0u;
+#pragma unroll
+  for (int q = 0; q < DPT; ++q) {
+    const int d = t * DPT + q;
+    s_run[d] = 0u;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) s_cnt[0][w][d] = 0;
   }
   __syncthreads();
   uint64_t key[kSortPer];
   uint32_t val[kSortPer], val2[kSortPer];
-  const bool two = vin2 != nullptr;
-  uint32_t wrank[kSortPer];
+  uint32_t rank[kSortPer];                 // position among the block's items of its digit
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
   for (int r = 0; r < kSortPer; ++r) {
-    int64_t i = base + r * kSortThreads + t;
-    bool valid = i < n;
+    const int b = r & 1;
+    const int64_t i = base + r * kSortThreads + t;
+    const bool valid = i < n;
     key[r] = valid ? kin[i] : 0ull;
     val[r] = valid ? vin[i] : 0u;
-    val2[r] = (valid && two) ? vin2[i] : 0u;
-    uint32_t d = (uint32_t)(key[r] >> shift) & (R - 1);
+    if (TWO) val2[r] = valid ? vin2[i] : 0u;
+    const uint32_t d = (uint32_t)(key[r] >> shift) & (R - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < RB; ++bit) {
-      uint64_t b = __ballot((d >> bit) & 1u);
-      peers &= ((d >> bit) & 1u) ? b : ~b;
+      const uint64_t m = __ballot((d >> bit) & 1u);
+      peers &= ((d >> bit) & 1u) ? m : ~m;
     }
-    wrank[r] = (uint32_t)__popcll(peers & lt_mask);
-    if (valid && wrank[r] == 0) s_cnt[r][wave][d] = (uint16_t)__popcll(peers);
+    const uint32_t wrank = (uint32_t)__popcll(peers & lt_mask);
+    if (valid && wrank == 0) s_cnt[b][wave][d] = (uint16_t)__popcll(peers);
+    __syncthreads();
+    // digit owners: counts -> offsets; clear the other buffer for round r + 1
+    // (its offsets of round r - 1 were read before the barrier above)
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      const int dd = t * DPT + q;
+      uint32_t run = s_run[dd];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const uint32_t c = s_cnt[b][w][dd];
+        s_cnt[b][w][dd] = (uint16_t)run;
+        run += c;
+        s_cnt[b ^ 1][w][dd] = 0;
+      }
+      s_run[dd] = run;
+    }
+    __syncthreads();
+    rank[r] = (uint32_t)s_cnt[b][wave][d] + wrank;
   }
-  __syncthreads();
-  // thread t owns its digits: exclusive scan over (round, wave) in index order
+  // s_run: the block's count per digit; exclusive scan over digits
   {
     uint32_t run[DPT], sum = 0;
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {
-      const int d = t * DPT + q;
-      run[q] = 0;
-#pragma unroll
-      for (int r = 0; r < kSortPer; ++r)
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          uint32_t c = s_cnt[r][w][d];
-          s_cnt[r][w][d] = (uint16_t)run[q];
-          run[q] += c;
-        }
+      run[q] = s_run[t * DPT + q];
       sum += run[q];
     }
     uint32_t tot;
@@ -607,27 +630,27 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kSortPer; ++r) {
-    int64_t i = base + r * kSortThreads + t;
+    const int64_t i = base + r * kSortThreads + t;
     if (i < n) {
-      uint32_t d = (uint32_t)(key[r] >> shift) & (R - 1);
-      uint32_t pos = s_dstart[d] + s_cnt[r][wave][d] + wrank[r];
+      const uint32_t d = (uint32_t)(key[r] >> shift) & (R - 1);
+      const uint32_t pos = s_dstart[d] + rank[r];
       s_key[pos] = key[r];
       s_val[pos] = val[r];
-      s_val2[pos] = val2[r];
+      if (TWO) s_val2[pos] = val2[r];
     }
   }
   __syncthreads();
   const int64_t nloc = min((int64_t)kSortItems, n - base);
 #pragma unroll 4
   for (int r = 0; r < kSortPer; ++r) {
-    int li = r * kSortThreads + t;
+    const int li = r * kSortThreads + t;
     if (li < nloc) {
-      uint64_t k = s_key[li];
-      uint32_t d = (uint32_t)(k >> shift) & (R - 1);
-      int64_t dst = (int64_t)s_gbase[d] + (li - (int64_t)s_dstart[d]);
+      const uint64_t k = s_key[li];
+      const uint32_t d = (uint32_t)(k >> shift) & (R - 1);
+      const int64_t dst = (int64_t)s_gbase[d] + (li - (int64_t)s_dstart[d]);
       kout[dst] = k;
       vout[dst] = s_val[li];
-      if (two) vout2[dst] = s_val2[li];
+      if (TWO) vout2[dst] = s_val2[li];
     }
   }
 }
@@ -641,8 +664,12 @@ static void launch_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* k
   // (G consecutive blocks per work-group, so that their prefixes within a
   // digit's row share a cache line, measured slower: 162 vs 127 us for an
   // 8-bit pass over 13.3M keys at G = 4)
-  hipLaunchKernelGGL((k_radix_scatter<RB>), dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin,
-                     vin, kout, vout, count, shift, nb, hist, row_tot, vin2, vout2);
+  if (vin2 != nullptr)
+    hipLaunchKernelGGL((k_radix_scatter<RB, true>), dim3((unsigned)nb), dim3(kSortThreads), 0, s,
+                       kin, vin, kout, vout, count, shift, nb, hist, row_tot, vin2, vout2);
+  else
+    hipLaunchKernelGGL((k_radix_scatter<RB, false>), dim3((unsigned)nb), dim3(kSortThreads), 0,
+                       s, kin, vin, kout, vout, count, shift, nb, hist, row_tot, vin2, vout2);
 }
 
 __global__ __launch_bounds__(256) void k_ranges(const uint64_t* __restrict__ keys,
@@ -750,7 +777,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
     const int a = p & 1, b = a ^ 1;
     launch_hist<kRadixBits>(pk[a], count_pairs, shift, L.nb_pairs, hist, s);
     GS_LAUNCH_CHECK("gs_bin_sort/depth_hist");
-    launch_rowscan(hist, L.nb_pairs, rowtot, kRadix, s);
+    launch_rowscan(hist, L.nb_pairs, count_pairs, rowtot, kRadix, s);
     GS_LAUNCH_CHECK("gs_bin_sort/depth_rowscan");
     launch_scatter<kRadixBits>(pk[a], pv[a], pk[b], pv[b], count_pairs, shift, L.nb_pairs, hist,
                                rowtot, (const uint32_t*)nullptr, (uint32_t*)nullptr, s);
@@ -780,7 +807,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
     else
       launch_hist<kRadixBits>(kin, count, shift, L.nb_sort, hist, s);
     GS_LAUNCH_CHECK("gs_bin_sort/radix_hist");
-    launch_rowscan(hist, L.nb_sort, rowtot, 1 << rb, s);
+    launch_rowscan(hist, L.nb_sort, count, rowtot, 1 << rb, s);
     GS_LAUNCH_CHECK("gs_bin_sort/radix_rowscan");
     if (rb == kRadixBitsMax)
       launch_scatter<kRadixBitsMax>(kin, vin, kout, vout, count, shift, L.nb_sort, hist, rowtot,
