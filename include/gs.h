@@ -186,7 +186,9 @@ size_t gs_bin_sort_workspace_bytes(int64_t m, int64_t dup_capacity,
  * mean read from rec).  No pixel centre of another bbox tile reaches
  * alpha >= 1/255, so images do not depend on it.  A bbox of more than 64
  * tiles is listed whole.  Outputs (device):
- *   keys_out [dup_capacity] u64, ids_out [dup_capacity] u32 (sorted),
+ *   keys_out [dup_capacity] u64 (optional, may be NULL: the sort then
+ *   carries 32-bit tile indices instead of the 64-bit keys, with the same
+ *   ids_out and tile_ranges), ids_out [dup_capacity] u32 (sorted),
  *   tile_ranges [n_slots * tiles_per_slot][2] u32: [start, end) into ids_out
  *   (start = end = 0 for an empty tile),
  *   pair_first [m][2] u32 (optional, may be NULL): per pair, the emission

@@ -25,6 +25,9 @@
 //                  and stages the block in LDS so global writes are runs per
 //                  digit
 //   k_ranges       [start, end) per tile from the sorted keys
+// When the caller does not ask for the sorted (tile, depth) keys, the tile
+// phase (emission, tile passes, ranges) carries 32-bit tile indices as keys
+// instead of 64-bit keys.
 #include "gs_device.h"
 
 namespace gsmi {
@@ -244,11 +247,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t* __restrict__
 // marks, in an LDS owner map, the duplicates of its own pairs that fall in
 // the round, then one thread per duplicate reads its pair from the map
 // (coalesced key and value writes, no search).
+template <typename K>
 __global__ __launch_bounds__(kScanThreads) void k_emit(
     const uint4* __restrict__ erec, const uint64_t* __restrict__ pkey,
     const uint32_t* __restrict__ perm, int64_t m,
     const int64_t* __restrict__ block_offsets, int64_t cap, int tiles_x, int tiles_per_slot,
-    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ pair_first,
+    K* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ pair_first,
     uint32_t* __restrict__ emit) {
   __shared__ uint32_t s_off[kScanItems + 1];
   __shared__ uint32_t s_base[kScanItems];     // tile index of the bbox's first tile
@@ -330,7 +334,10 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
       const uint32_t span = s_span[li];
       const uint32_t ky = k / span;
       const uint64_t tile = (uint64_t)(s_base[li] + ky * (uint32_t)tiles_x + (k - ky * span));
-      keys[dst] = (tile << 32) | (uint64_t)s_depth[li];
+      if constexpr (sizeof(K) == 8)
+        keys[dst] = (tile << 32) | (uint64_t)s_depth[li];
+      else
+        keys[dst] = (K)tile;
       vals[dst] = s_pair[li];
       if (emit) emit[dst] = (uint32_t)dst;
     }
@@ -392,8 +399,8 @@ __global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ re
 
 // Digit counts of one block of keys: hist[digit][block].  RB-bit digits,
 // 1 << RB of them (each thread owns 1 << RB / 256).
-template <int RB>
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __restrict__ keys,
+template <int RB, typename K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict__ keys,
                                                              const int64_t* __restrict__ count,
                                                              int shift, int64_t nb,
                                                              uint32_t* __restrict__ hist) {
@@ -425,8 +432,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
 // one digit are adjacent in the digit-major table, so the writes go out in
 // G-word runs instead of one scattered word per (block, digit).  For large
 // sorts, where the scattered writes of k_radix_hist dominate its time.
-template <int RB, int G>
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist_g(const uint64_t* __restrict__ keys,
+template <int RB, int G, typename K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist_g(const K* __restrict__ keys,
                                                                const int64_t* __restrict__ count,
                                                                int shift, int64_t nb,
                                                                uint32_t* __restrict__ hist) {
@@ -456,17 +463,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist_g(const uint64_t* _
 }
 
 // Launch the digit counts of one pass: grouped blocks for large sorts.
-template <int RB>
-static void launch_hist(const uint64_t* keys, const int64_t* count, int shift, int64_t nb,
+template <int RB, typename K>
+static void launch_hist(const K* keys, const int64_t* count, int shift, int64_t nb,
                         uint32_t* hist, hipStream_t s) {
   constexpr int G = 8;
   // (for 8-bit digits the grouped kernel measured slower: 49 vs 41 us a pass
   // over 13.3M keys; for 9-bit digits 84 against 164 us over 20.7M)
   if ((RB > kRadixBits && nb >= 2048) || nb >= 16384)
-    hipLaunchKernelGGL((k_radix_hist_g<RB, G>), dim3((unsigned)((nb + G - 1) / G)),
+    hipLaunchKernelGGL((k_radix_hist_g<RB, G, K>), dim3((unsigned)((nb + G - 1) / G)),
                        dim3(kSortThreads), 0, s, keys, count, shift, nb, hist);
   else
-    hipLaunchKernelGGL(k_radix_hist<RB>, dim3((unsigned)nb), dim3(kSortThreads), 0, s, keys,
+    hipLaunchKernelGGL((k_radix_hist<RB, K>), dim3((unsigned)nb), dim3(kSortThreads), 0, s, keys,
                        count, shift, nb, hist);
 }
 
@@ -525,17 +532,17 @@ static void launch_rowscan(uint32_t* hist, int64_t nb, const int64_t* count, uin
 // into offsets after the items of earlier rounds and waves, so the LDS holds
 // one round's counts (double-buffered) instead of all 32 (round, wave) rows
 // and more blocks fit on a CU.
-template <int RB, bool TWO>
+template <int RB, bool TWO, typename K>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, const int64_t* __restrict__ count,
+    const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+    K* __restrict__ kout, uint32_t* __restrict__ vout, const int64_t* __restrict__ count,
     int shift, int64_t nb, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ row_tot,
     const uint32_t* __restrict__ vin2, uint32_t* __restrict__ vout2) {
   constexpr int R = 1 << RB, DPT = R / kSortThreads;
   static_assert(DPT >= 1 && R % kSortThreads == 0, "digits per thread");
   __shared__ uint16_t s_cnt[2][4][R];               // one round's (wave, digit) counts
   __shared__ uint32_t s_run[R];                     // items of earlier rounds per digit
-  __shared__ uint64_t s_key[kSortItems];            // 16 KB
+  __shared__ K s_key[kSortItems];                   // 16 KB (64-bit keys), 8 KB
   __shared__ uint32_t s_val[kSortItems];            // 8 KB
   __shared__ uint32_t s_val2[TWO ? kSortItems : 1];
   __shared__ uint32_t s_dstart[R];                  // local digit starts
@@ -571,7 +578,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     for (int w = 0; w < 4; ++w) s_cnt[0][w][d] = 0;
   }
   __syncthreads();
-  uint64_t key[kSortPer];
+  K key[kSortPer];
   uint32_t val[kSortPer], val2[kSortPer];
   uint32_t rank[kSortPer];                 // position among the block's items of its digit
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -580,7 +587,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const int b = r & 1;
     const int64_t i = base + r * kSortThreads + t;
     const bool valid = i < n;
-    key[r] = valid ? kin[i] : 0ull;
+    key[r] = valid ? kin[i] : (K)0;
     val[r] = valid ? vin[i] : 0u;
     if (TWO) val2[r] = valid ? vin2[i] : 0u;
     const uint32_t d = (uint32_t)(key[r] >> shift) & (R - 1);
@@ -645,7 +652,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   for (int r = 0; r < kSortPer; ++r) {
     const int li = r * kSortThreads + t;
     if (li < nloc) {
-      const uint64_t k = s_key[li];
+      const K k = s_key[li];
       const uint32_t d = (uint32_t)(k >> shift) & (R - 1);
       const int64_t dst = (int64_t)s_gbase[d] + (li - (int64_t)s_dstart[d]);
       kout[dst] = k;
@@ -656,8 +663,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 }
 
 // One scatter pass, one block per work-group.
-template <int RB>
-static void launch_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+template <int RB, typename K>
+static void launch_scatter(const K* kin, const uint32_t* vin, K* kout,
                            uint32_t* vout, const int64_t* count, int shift, int64_t nb,
                            const uint32_t* hist, const uint32_t* row_tot, const uint32_t* vin2,
                            uint32_t* vout2, hipStream_t s) {
@@ -665,23 +672,95 @@ static void launch_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* k
   // digit's row share a cache line, measured slower: 162 vs 127 us for an
   // 8-bit pass over 13.3M keys at G = 4)
   if (vin2 != nullptr)
-    hipLaunchKernelGGL((k_radix_scatter<RB, true>), dim3((unsigned)nb), dim3(kSortThreads), 0, s,
+    hipLaunchKernelGGL((k_radix_scatter<RB, true, K>), dim3((unsigned)nb), dim3(kSortThreads), 0, s,
                        kin, vin, kout, vout, count, shift, nb, hist, row_tot, vin2, vout2);
   else
-    hipLaunchKernelGGL((k_radix_scatter<RB, false>), dim3((unsigned)nb), dim3(kSortThreads), 0,
+    hipLaunchKernelGGL((k_radix_scatter<RB, false, K>), dim3((unsigned)nb), dim3(kSortThreads), 0,
                        s, kin, vin, kout, vout, count, shift, nb, hist, row_tot, vin2, vout2);
 }
 
-__global__ __launch_bounds__(256) void k_ranges(const uint64_t* __restrict__ keys,
+// Tile index of a sorted key: the high word of a 64-bit (tile, depth) key, or
+// the whole 32-bit tile key.
+template <typename K>
+__device__ __forceinline__ uint32_t key_tile(K k) {
+  if constexpr (sizeof(K) == 8)
+    return (uint32_t)(k >> 32);
+  else
+    return (uint32_t)k;
+}
+
+// Each thread takes kRangePer consecutive sorted keys and the one before
+// them, and marks the tile boundaries among them.
+constexpr int kRangePer = 4;
+
+template <typename K>
+__global__ __launch_bounds__(256) void k_ranges(const K* __restrict__ keys,
                                                 const int64_t* __restrict__ count,
                                                 uint32_t* __restrict__ ranges) {
   const int64_t n = count[0];
-  int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  uint32_t tile = (uint32_t)(keys[j] >> 32);
-  if (j == 0 || (uint32_t)(keys[j - 1] >> 32) != tile) ranges[2 * (int64_t)tile] = (uint32_t)j;
-  if (j == n - 1 || (uint32_t)(keys[j + 1] >> 32) != tile)
-    ranges[2 * (int64_t)tile + 1] = (uint32_t)(j + 1);
+  const int64_t j0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * kRangePer;
+  if (j0 >= n) return;
+  uint32_t prev = j0 > 0 ? key_tile(keys[j0 - 1]) : 0u;
+  uint32_t tk[kRangePer];
+#pragma unroll
+  for (int q = 0; q < kRangePer; ++q) tk[q] = j0 + q < n ? key_tile(keys[j0 + q]) : 0u;
+#pragma unroll
+  for (int q = 0; q < kRangePer; ++q) {
+    const int64_t j = j0 + q;
+    if (j >= n) break;
+    if (j == 0 || prev != tk[q]) {
+      ranges[2 * (int64_t)tk[q]] = (uint32_t)j;
+      if (j > 0) ranges[2 * (int64_t)prev + 1] = (uint32_t)j;
+    }
+    if (j == n - 1) ranges[2 * (int64_t)tk[q] + 1] = (uint32_t)n;
+    prev = tk[q];
+  }
+}
+
+// The tile phase after the depth presort: emission of the duplicates in
+// (depth, pair) order into (k0, v0, e0), `passes` stable passes of rb-bit
+// digits over the tile bits (from bit key_shift) ping-ponging with
+// (k1, v1, e1), and the tile ranges.  K = uint64_t: (tile << 32) | depth
+// keys; K = uint32_t: the tile index only (half the key traffic).
+template <typename K>
+static gs_status tile_phase(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t* e0, uint32_t* e1,
+                            int key_shift, int rb, int passes, const uint4* erec,
+                            const uint64_t* pkey, const uint32_t* pval, int64_t m,
+                            const int64_t* block_sums, int64_t cap, int tiles_x,
+                            int tiles_per_slot, uint32_t* pair_first, const int64_t* count,
+                            const BinSortLayout& L, uint32_t* hist, uint32_t* rowtot,
+                            uint32_t* tile_ranges, hipStream_t s) {
+  hipLaunchKernelGGL(k_emit<K>, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s, erec, pkey,
+                     pval, m, block_sums, cap, tiles_x, tiles_per_slot, k0, v0, pair_first, e0);
+  GS_LAUNCH_CHECK("gs_bin_sort/emit");
+  for (int p = 0; p < passes; ++p) {
+    const int shift = key_shift + p * rb;
+    const K* kin = (p % 2 == 0) ? k0 : k1;
+    const uint32_t* vin = (p % 2 == 0) ? v0 : v1;
+    K* kout = (p % 2 == 0) ? k1 : k0;
+    uint32_t* vout = (p % 2 == 0) ? v1 : v0;
+    const uint32_t* ein = (p % 2 == 0) ? e0 : e1;
+    uint32_t* eout = (p % 2 == 0) ? e1 : e0;
+    if (rb == kRadixBitsMax)
+      launch_hist<kRadixBitsMax>(kin, count, shift, L.nb_sort, hist, s);
+    else
+      launch_hist<kRadixBits>(kin, count, shift, L.nb_sort, hist, s);
+    GS_LAUNCH_CHECK("gs_bin_sort/radix_hist");
+    launch_rowscan(hist, L.nb_sort, count, rowtot, 1 << rb, s);
+    GS_LAUNCH_CHECK("gs_bin_sort/radix_rowscan");
+    if (rb == kRadixBitsMax)
+      launch_scatter<kRadixBitsMax>(kin, vin, kout, vout, count, shift, L.nb_sort, hist, rowtot,
+                                    ein, eout, s);
+    else
+      launch_scatter<kRadixBits>(kin, vin, kout, vout, count, shift, L.nb_sort, hist, rowtot, ein,
+                                 eout, s);
+    GS_LAUNCH_CHECK("gs_bin_sort/radix_scatter");
+  }
+  const K* sorted = (passes % 2 == 0) ? k0 : k1;
+  hipLaunchKernelGGL(k_ranges<K>, dim3((unsigned)ceil_div(ceil_div(cap, kRangePer), 256)),
+                     dim3(256), 0, s, sorted, count, tile_ranges);
+  GS_LAUNCH_CHECK("gs_bin_sort/ranges");
+  return GS_OK;
 }
 
 }  // namespace gsmi
@@ -709,7 +788,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   GS_REQUIRE(proj->m == views->total_pairs, "gs_bin_sort: proj->m != total_pairs");
   GS_REQUIRE(dup_capacity >= 1 && dup_capacity <= (int64_t)0xFFFFFFFFll,
              "gs_bin_sort: dup_capacity=%lld outside [1, 2^32-1]", (long long)dup_capacity);
-  GS_REQUIRE(keys_out && ids_out && tile_ranges && ws, "gs_bin_sort: NULL output/workspace");
+  GS_REQUIRE(ids_out && tile_ranges && ws, "gs_bin_sort: NULL output/workspace");
   const int64_t m = proj->m;
   GS_REQUIRE(m == 0 || (proj->rec && proj->tile_bbox && proj->n_tiles),
              "gs_bin_sort: NULL projected arrays");
@@ -741,9 +820,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
                                                                                 : kRadixBits;
   const int passes = (tile_bits + rb - 1) / rb;
   // emit into the buffer that the last pass will not overwrite
-  uint64_t* k0 = (passes % 2 == 0) ? keys_out : keys_alt;
   uint32_t* v0 = (passes % 2 == 0) ? ids_out : vals_alt;
-  uint64_t* k1 = (passes % 2 == 0) ? keys_alt : keys_out;
   uint32_t* v1 = (passes % 2 == 0) ? vals_alt : ids_out;
   uint32_t* emit_alt = (uint32_t*)(w + L.off_emit_alt);
   uint32_t* e0 = emit_out ? ((passes % 2 == 0) ? emit_out : emit_alt) : nullptr;
@@ -790,37 +867,19 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, block_sums, L.nb_scan,
                      dup_capacity, status, count);
   GS_LAUNCH_CHECK("gs_bin_sort/scan_top");
-  hipLaunchKernelGGL(k_emit, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s,
-                     (const uint4*)erec, pk[0], pv[0], m, block_sums, dup_capacity,
-                     tiles_x, (int)tiles_per_slot, k0, v0, pair_first, e0);
-  GS_LAUNCH_CHECK("gs_bin_sort/emit");
-  for (int p = 0; p < passes; ++p) {
-    const int shift = 32 + p * rb;
-    const uint64_t* kin = (p % 2 == 0) ? k0 : k1;
-    const uint32_t* vin = (p % 2 == 0) ? v0 : v1;
-    uint64_t* kout = (p % 2 == 0) ? k1 : k0;
-    uint32_t* vout = (p % 2 == 0) ? v1 : v0;
-    const uint32_t* ein = (p % 2 == 0) ? e0 : e1;
-    uint32_t* eout = (p % 2 == 0) ? e1 : e0;
-    if (rb == kRadixBitsMax)
-      launch_hist<kRadixBitsMax>(kin, count, shift, L.nb_sort, hist, s);
-    else
-      launch_hist<kRadixBits>(kin, count, shift, L.nb_sort, hist, s);
-    GS_LAUNCH_CHECK("gs_bin_sort/radix_hist");
-    launch_rowscan(hist, L.nb_sort, count, rowtot, 1 << rb, s);
-    GS_LAUNCH_CHECK("gs_bin_sort/radix_rowscan");
-    if (rb == kRadixBitsMax)
-      launch_scatter<kRadixBitsMax>(kin, vin, kout, vout, count, shift, L.nb_sort, hist, rowtot,
-                                    ein, eout, s);
-    else
-      launch_scatter<kRadixBits>(kin, vin, kout, vout, count, shift, L.nb_sort, hist, rowtot, ein,
-                                 eout, s);
-    GS_LAUNCH_CHECK("gs_bin_sort/radix_scatter");
+  if (keys_out) {
+    uint64_t* k0 = (passes % 2 == 0) ? keys_out : keys_alt;
+    uint64_t* k1 = (passes % 2 == 0) ? keys_alt : keys_out;
+    return tile_phase<uint64_t>(k0, k1, v0, v1, e0, e1, 32, rb, passes, erec, pk[0], pv[0], m,
+                                block_sums, dup_capacity, tiles_x, (int)tiles_per_slot,
+                                pair_first, count, L, hist, rowtot, tile_ranges, s);
   }
-  hipLaunchKernelGGL(k_ranges, dim3((unsigned)ceil_div(dup_capacity, 256)), dim3(256), 0, s,
-                     keys_out, count, tile_ranges);
-  GS_LAUNCH_CHECK("gs_bin_sort/ranges");
-  return GS_OK;
+  // no keys asked for: 32-bit tile keys in the two halves of keys_alt
+  uint32_t* t0 = reinterpret_cast<uint32_t*>(keys_alt);
+  uint32_t* t1 = t0 + dup_capacity;
+  return tile_phase<uint32_t>(t0, t1, v0, v1, e0, e1, 0, rb, passes, erec, pk[0], pv[0], m,
+                              block_sums, dup_capacity, tiles_x, (int)tiles_per_slot, pair_first,
+                              count, L, hist, rowtot, tile_ranges, s);
 }
 
 }  // extern "C"

@@ -120,10 +120,12 @@ def tiling_struct(width, height, tile=(16, 16)):
 class RasterBuffers:
     """All device buffers one (views, tiling) configuration needs.
 
-    dup_capacity grows on overflow (see ``ensure_capacity``)."""
+    dup_capacity grows on overflow (see ``ensure_capacity``).  keep_keys: also
+    keep the sorted 64-bit (tile, depth) keys in ``keys`` (the rasterisers
+    need only ids and ranges; without it the sort carries 32-bit tile keys)."""
 
     def __init__(self, views: Views, width, height, tile=(16, 16), dup_capacity=None,
-                 store_state=True):
+                 store_state=True, keep_keys=False):
         dev = views.device
         self.views = views
         self.W, self.H, self.tile = width, height, tuple(tile)
@@ -150,6 +152,7 @@ class RasterBuffers:
         self.pair_first = torch.empty(2 * max(m, 1), dtype=torch.int32, device=dev)   # (first, count)
         self.status = torch.zeros(4, dtype=torch.int64, device=dev)
         self.keys = self.ids = self.ws = None
+        self.keep_keys = bool(keep_keys)
         self.dup_grads = None
         self.deterministic = False
         self.plan = None
@@ -175,7 +178,7 @@ class RasterBuffers:
         self.generation += 1
         dev = self.views.device
         self.dup_capacity = cap
-        self.keys = torch.empty(cap, dtype=torch.int64, device=dev)
+        self.keys = torch.empty(cap, dtype=torch.int64, device=dev) if self.keep_keys else None
         self.ids = torch.empty(cap, dtype=torch.int32, device=dev)
         self.emit = torch.empty(cap, dtype=torch.int32, device=dev)
         nbytes = _lib.load().gs_bin_sort_workspace_bytes(self.m, cap, C.byref(self.tiling),
@@ -197,7 +200,8 @@ class RasterBuffers:
     def bin_sort(self, stream=None):
         s = stream or stream_handle()
         call("gs_bin_sort", C.byref(self.proj), C.byref(self.views.struct), C.byref(self.tiling),
-             self.dup_capacity, _ptr(self.ws), self.ws.numel(), _ptr(self.keys), _ptr(self.ids),
+             self.dup_capacity, _ptr(self.ws), self.ws.numel(),
+             _ptr(self.keys) if self.keep_keys else None, _ptr(self.ids),
              _ptr(self.ranges), _ptr(self.pair_first) if self.deterministic else None,
              _ptr(self.emit) if self.deterministic else None, _ptr(self.status), s)
 

@@ -166,13 +166,17 @@ def test_fullsize_bin_sort_bit_exact(big):
         rec, tb, nt, _ = records(big, tile)
         slot = np.repeat(np.arange(len(cams), dtype=np.int32), n)
         nt, keys, ids, ranges = oracle_lists(rec, tb, nt, slot, tile, W, H, len(cams))
-        bufs = ops.RasterBuffers(ops.Views.single(n, cams), W, H, tile, dup_capacity=1024)
-        raster_records(bufs, rec, tb, nt, (0.0, 0.0, 0.0), torch)
         K = len(ids)
-        assert int(bufs.check()[1]) == K and K < 0.9 * int(nt.astype(np.int64).sum())
-        np.testing.assert_array_equal(bufs.keys[:K].cpu().numpy().view(np.uint64), keys)
-        np.testing.assert_array_equal(bufs.ids[:K].cpu().numpy().view(np.uint32), ids)
-        np.testing.assert_array_equal(bufs.ranges.cpu().numpy().view(np.uint32), ranges)
+        for keep in (True, False):      # 64-bit (tile, depth) keys, or 32-bit tile keys
+            bufs = ops.RasterBuffers(ops.Views.single(n, cams), W, H, tile, dup_capacity=1024,
+                                     keep_keys=keep)
+            raster_records(bufs, rec, tb, nt, (0.0, 0.0, 0.0), torch)
+            assert int(bufs.check()[1]) == K and K < 0.9 * int(nt.astype(np.int64).sum())
+            if keep:
+                np.testing.assert_array_equal(bufs.keys[:K].cpu().numpy().view(np.uint64), keys)
+            np.testing.assert_array_equal(bufs.ids[:K].cpu().numpy().view(np.uint32), ids)
+            np.testing.assert_array_equal(bufs.ranges.cpu().numpy().view(np.uint32), ranges)
+            del bufs
 
 
 def _plans():

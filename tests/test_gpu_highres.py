@@ -112,14 +112,18 @@ def test_highres_bin_sort_bit_exact(hr):
     n, rec, tb, nt = hr["n"], hr["rec"], hr["tb"], hr["nt"]
     say("high-res bin/sort")
     nt, keys, ids, ranges = oracle_lists(rec, tb, nt, np.zeros(n, np.int32), TILE, W, H, 1)
-    bufs = ops.RasterBuffers(ops.Views.single(n, hr["cam"]), W, H, TILE, dup_capacity=1024)
-    raster_records(bufs, rec, tb, nt, (0.0, 0.0, 0.0), torch)
     K = len(ids)
-    assert int(bufs.check()[1]) == K and K < 0.9 * int(nt.astype(np.int64).sum())
     assert K > 2 * 10 ** 6
-    np.testing.assert_array_equal(bufs.keys[:K].cpu().numpy().view(np.uint64), keys)
-    np.testing.assert_array_equal(bufs.ids[:K].cpu().numpy().view(np.uint32), ids)
-    np.testing.assert_array_equal(bufs.ranges.cpu().numpy().view(np.uint32), ranges)
+    for keep in (True, False):          # 64-bit (tile, depth) keys, or 32-bit tile keys
+        bufs = ops.RasterBuffers(ops.Views.single(n, hr["cam"]), W, H, TILE, dup_capacity=1024,
+                                 keep_keys=keep)
+        raster_records(bufs, rec, tb, nt, (0.0, 0.0, 0.0), torch)
+        assert int(bufs.check()[1]) == K and K < 0.9 * int(nt.astype(np.int64).sum())
+        if keep:
+            np.testing.assert_array_equal(bufs.keys[:K].cpu().numpy().view(np.uint64), keys)
+        np.testing.assert_array_equal(bufs.ids[:K].cpu().numpy().view(np.uint32), ids)
+        np.testing.assert_array_equal(bufs.ranges.cpu().numpy().view(np.uint32), ranges)
+        del bufs
 
 
 _oracle_windows = {}

@@ -115,13 +115,15 @@ def synthetic_pairs(m, tiles_x, tiles_y, S, seed, tile, zero_frac=0.2, max_span=
     return tb, nt, depth, slot, sup
 
 
-def run_binsort(ops, tb, nt, depth, slot, sup, W, H, tile, S, cap):
+def run_binsort(ops, tb, nt, depth, slot, sup, W, H, tile, S, cap, keep_keys=True):
+    """keep_keys=False: the product path's sort, which carries 32-bit tile
+    keys and writes no (tile, depth) keys; ids and ranges must not change."""
     m = len(nt)
     counts = [int((slot == s).sum()) for s in range(S)]
     po = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
     cams = scene.orbit_cameras(S, W, H)
     views = ops.Views(po, np.zeros(S, np.int64), ops.Views.cams_to_device(cams, "cuda"), "cuda")
-    bufs = ops.RasterBuffers(views, W, H, tile, dup_capacity=cap)
+    bufs = ops.RasterBuffers(views, W, H, tile, dup_capacity=cap, keep_keys=keep_keys)
     rec = np.zeros((m, 12), np.float32)
     rec[:, 0:6] = sup
     rec[:, 9] = depth
@@ -151,14 +153,14 @@ def test_bin_sort_bit_exact(ops, m, S, tile, W, H, seed, span):
                                         sup=sup.astype(np.float64), tile=tile)
     K = len(ids)
     assert K < 0.95 * int(nt.sum())               # the listing drops bbox tiles
-    bufs, st, req = run_binsort(ops, tb, nt, depth, slot, sup, W, H, tile, S, cap=K + 17)
-    assert st == 0 and req == K
-    gk = bufs.keys[:K].cpu().numpy().view(np.uint64)
-    gi = bufs.ids[:K].cpu().numpy().view(np.uint32)
-    gr = bufs.ranges.cpu().numpy().view(np.uint32)
-    np.testing.assert_array_equal(gk, keys)
-    np.testing.assert_array_equal(gi, ids)
-    np.testing.assert_array_equal(gr, ranges)
+    for keep in (True, False):
+        bufs, st, req = run_binsort(ops, tb, nt, depth, slot, sup, W, H, tile, S, cap=K + 17,
+                                    keep_keys=keep)
+        assert st == 0 and req == K
+        if keep:
+            np.testing.assert_array_equal(bufs.keys[:K].cpu().numpy().view(np.uint64), keys)
+        np.testing.assert_array_equal(bufs.ids[:K].cpu().numpy().view(np.uint32), ids)
+        np.testing.assert_array_equal(bufs.ranges.cpu().numpy().view(np.uint32), ranges)
 
 
 @pytest.mark.parametrize("m,tile,W,H,S,cap", [(1100000, (8, 8), 3840, 2160, 1, 5_000_000),
@@ -177,11 +179,15 @@ def test_bin_sort_large_capacity_bit_exact(ops, m, tile, W, H, S, cap):
     keys, ids, ranges = oracle.bin_sort(tb, nt, depth, slot, tx, tx * ty, S,
                                         sup=sup.astype(np.float64), tile=tile)
     K = len(ids)
-    bufs, st, req = run_binsort(ops, tb, nt, depth, slot, sup, W, H, tile, S, cap=cap)
-    assert st == 0 and req == K
-    np.testing.assert_array_equal(bufs.keys[:K].cpu().numpy().view(np.uint64), keys)
-    np.testing.assert_array_equal(bufs.ids[:K].cpu().numpy().view(np.uint32), ids)
-    np.testing.assert_array_equal(bufs.ranges.cpu().numpy().view(np.uint32), ranges)
+    for keep in (True, False):
+        bufs, st, req = run_binsort(ops, tb, nt, depth, slot, sup, W, H, tile, S, cap=cap,
+                                    keep_keys=keep)
+        assert st == 0 and req == K
+        if keep:
+            np.testing.assert_array_equal(bufs.keys[:K].cpu().numpy().view(np.uint64), keys)
+        np.testing.assert_array_equal(bufs.ids[:K].cpu().numpy().view(np.uint32), ids)
+        np.testing.assert_array_equal(bufs.ranges.cpu().numpy().view(np.uint32), ranges)
+        del bufs
 
 
 def test_bin_sort_overflow_and_empty(ops):
