@@ -208,24 +208,41 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint64_t* __
 }
 
 // Single workgroup: exclusive scan of nb block sums in place; writes the
-// true total to status[1] and min(total, cap) to count[0].
+// true total to status[1] and min(total, cap) to count[0].  The sums are
+// staged in LDS kTopLds at a time with coalesced loads (one padding slot
+// after every 32, so the per-thread runs below start in different banks),
+// thread t scans its run of consecutive sums there, and the prefixes go back
+// with coalesced stores; the running total carries from segment to segment.
+constexpr int kTopLds = 8192;
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t* __restrict__ block_sums,
                                                            int64_t nb, int64_t cap,
                                                            int64_t* __restrict__ status,
                                                            int64_t* __restrict__ count) {
+  __shared__ int64_t r[kTopLds + kTopLds / 32];
   __shared__ int64_t sm[4];
-  // thread t owns the contiguous segment [t * seg, (t + 1) * seg): sum it,
-  // scan the 256 segment sums, then rewrite the segment as prefixes
-  const int64_t seg = (nb + kScanThreads - 1) / kScanThreads;
-  const int64_t s0 = min(nb, (int64_t)threadIdx.x * seg), s1 = min(nb, s0 + seg);
-  int64_t sum = 0;
-  for (int64_t i = s0; i < s1; ++i) sum += block_sums[i];
-  int64_t carry;
-  int64_t run = block_exclusive_scan<int64_t>(sum, sm, carry);
-  for (int64_t i = s0; i < s1; ++i) {
-    const int64_t v = block_sums[i];
-    block_sums[i] = run;
-    run += v;
+  auto at = [](int i) { return i + (i >> 5); };
+  int64_t carry = 0;
+  for (int64_t s0 = 0; s0 < nb; s0 += kTopLds) {
+    const int n = (int)min((int64_t)kTopLds, nb - s0);
+    int64_t* seg = block_sums + s0;
+    for (int i = threadIdx.x; i < n; i += kScanThreads) r[at(i)] = seg[i];
+    __syncthreads();
+    const int per = (n + kScanThreads - 1) / kScanThreads;
+    const int b0 = min((int)threadIdx.x * per, n), b1 = min(b0 + per, n);
+    int64_t sum = 0;
+    for (int b = b0; b < b1; ++b) sum += r[at(b)];
+    int64_t total;
+    int64_t ex = carry + block_exclusive_scan<int64_t>(sum, sm, total);
+    for (int b = b0; b < b1; ++b) {
+      const int64_t x = r[at(b)];
+      r[at(b)] = ex;
+      ex += x;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += kScanThreads) seg[i] = r[at(i)];
+    carry += total;
+    __syncthreads();                                 // LDS reused by the next segment
   }
   if (threadIdx.x == 0) {
     if (status) {
@@ -347,7 +364,8 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
 
 // ------------------------------------------------------------ depth presort
 
-// key = (tiles << 42) | (slot << 32) | depth bits, value = pair index;
+// key = (tiles << 42) | (slot << 32) | depth bits (the first radix pass
+// takes the pair index i as its value);
 // count[0] = m.  Depths of visible pairs are positive, so their bits order
 // as the floats; the passes sort the low 32 bits only, the pair's tile count
 // and slot ride along for the scan and the emission.  tiles is the number of
@@ -365,7 +383,6 @@ __global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ re
                                                    int th, int tiles_x, int tiles_per_slot,
                                                    int64_t m,
                                                    uint64_t* __restrict__ keys,
-                                                   uint32_t* __restrict__ vals,
                                                    uint4* __restrict__ erec,
                                                    uint32_t* __restrict__ pair_count,
                                                    int64_t* __restrict__ count,
@@ -392,7 +409,6 @@ __global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ re
   if (pair_count) pair_count[2 * i + 1] = (uint32_t)nt;
   keys[i] = (nt << kKeyTilesShift) | ((uint64_t)slot << kKeySlotShift) |
             (uint64_t)__float_as_uint(r[9]);
-  vals[i] = (uint32_t)i;
 }
 
 // ------------------------------------------------------------ radix sort
@@ -480,15 +496,17 @@ static void launch_hist(const K* keys, const int64_t* count, int shift, int64_t 
 // The row of a digit's block counts is scanned in segments of up to kRowLds
 // counts staged in LDS with coalesced loads (each thread scans its part
 // there) and written back with coalesced stores, the running total carried
-// from segment to segment.  (Scanning per-thread segments in global memory
+// from segment to segment; one padding slot after every 32 counts starts the
+// threads' runs in different LDS banks.  (Scanning per-thread segments in global memory
 // instead, every access of a wave touched 64 lines: 43 us per pass at 17K
 // blocks, 475 us at 50K.)
-constexpr int kRowLds = 32768;                      // 128 KB of the 160 KB LDS
+constexpr int kRowLds = 32768;                      // 132 KB of LDS with the padding
 
 __global__ __launch_bounds__(256) void k_radix_rowscan_lds(uint32_t* __restrict__ hist, int64_t nb,
                                                            const int64_t* __restrict__ count,
                                                            uint32_t* __restrict__ row_tot) {
-  __shared__ uint32_t r[kRowLds];
+  __shared__ uint32_t r[kRowLds + kRowLds / 32];   // one padding slot after every 32
+  auto at = [](int i) { return i + (i >> 5); };
   __shared__ uint32_t sm[4];
   uint32_t* row = hist + (int64_t)blockIdx.x * nb;
   // the row's first nb_used counts: the blocks that hold keys
@@ -497,21 +515,21 @@ __global__ __launch_bounds__(256) void k_radix_rowscan_lds(uint32_t* __restrict_
   for (int64_t s0 = 0; s0 < nb_used; s0 += kRowLds) {
     const int n = (int)min((int64_t)kRowLds, nb_used - s0);
     uint32_t* seg = row + s0;
-    for (int i = threadIdx.x; i < n; i += 256) r[i] = seg[i];
+    for (int i = threadIdx.x; i < n; i += 256) r[at(i)] = seg[i];
     __syncthreads();
     const int per = (n + 255) / 256;
     const int b0 = min((int)threadIdx.x * per, n), b1 = min(b0 + per, n);
     uint32_t sum = 0;
-    for (int b = b0; b < b1; ++b) sum += r[b];
+    for (int b = b0; b < b1; ++b) sum += r[at(b)];
     uint32_t total;
     uint32_t ex = carry + block_exclusive_scan<uint32_t>(sum, sm, total);
     for (int b = b0; b < b1; ++b) {
-      const uint32_t x = r[b];
-      r[b] = ex;
+      const uint32_t x = r[at(b)];
+      r[at(b)] = ex;
       ex += x;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += 256) seg[i] = r[i];
+    for (int i = threadIdx.x; i < n; i += 256) seg[i] = r[at(i)];
     carry += total;
     __syncthreads();                                 // LDS reused by the next segment
   }
@@ -525,8 +543,8 @@ static void launch_rowscan(uint32_t* hist, int64_t nb, const int64_t* count, uin
 }
 
 // One stable LSD pass over RB-bit digits (1 << RB of them; each thread owns
-// 1 << RB / 256 consecutive digits).  TWO: a second value vin2 -> vout2 is
-// carried along.  The block's 2048 items are ranked in 8 rounds of 256 (item
+// 1 << RB / 256 consecutive digits).  vin NULL: the value of item i is i.
+// TWO: a second value vin2 -> vout2 is carried along.  The block's 2048 items are ranked in 8 rounds of 256 (item
 // base + r * 256 + t in round r): within a wave by ballots over the digit
 // bits, then per round the owner of each digit turns the 4 waves' counts
 // into offsets after the items of earlier rounds and waves, so the LDS holds
@@ -588,7 +606,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const int64_t i = base + r * kSortThreads + t;
     const bool valid = i < n;
     key[r] = valid ? kin[i] : (K)0;
-    val[r] = valid ? vin[i] : 0u;
+    val[r] = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
     if (TWO) val2[r] = valid ? vin2[i] : 0u;
     const uint32_t d = (uint32_t)(key[r] >> shift) & (R - 1);
     uint64_t peers = __ballot(valid);
@@ -846,7 +864,7 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   uint4* erec = (uint4*)(w + L.off_erec);
   hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, proj->rec,
                      proj->n_tiles, (const uint2*)proj->tile_bbox, tiling->tile_w,
-                     tiling->tile_h, tiles_x, (int)tiles_per_slot, m, pk[0], pv[0], erec,
+                     tiling->tile_h, tiles_x, (int)tiles_per_slot, m, pk[0], erec,
                      pair_first, count_pairs, tile_ranges, 2 * n_tiles_all);
   GS_LAUNCH_CHECK("gs_bin_sort/depth_keys");
   for (int p = 0; p < 4; ++p) {
@@ -856,8 +874,10 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
     GS_LAUNCH_CHECK("gs_bin_sort/depth_hist");
     launch_rowscan(hist, L.nb_pairs, count_pairs, rowtot, kRadix, s);
     GS_LAUNCH_CHECK("gs_bin_sort/depth_rowscan");
-    launch_scatter<kRadixBits>(pk[a], pv[a], pk[b], pv[b], count_pairs, shift, L.nb_pairs, hist,
-                               rowtot, (const uint32_t*)nullptr, (uint32_t*)nullptr, s);
+    // (the first pass numbers the pairs itself: values in = NULL)
+    launch_scatter<kRadixBits>(pk[a], p == 0 ? nullptr : pv[a], pk[b], pv[b], count_pairs, shift,
+                               L.nb_pairs, hist, rowtot, (const uint32_t*)nullptr,
+                               (uint32_t*)nullptr, s);
     GS_LAUNCH_CHECK("gs_bin_sort/depth_scatter");
   }
   // duplicates in depth order, then stable passes over the tile bits only
