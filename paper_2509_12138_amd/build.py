@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgsmi.so")
 
-SOURCES = ["capi.hip", "project.hip", "binsort.hip", "raster.hip", "loss.hip", "adam.hip",
+SOURCES = ["capi.hip", "project.hip", "binsort.hip", "raster.hip", "schedule.hip", "loss.hip", "adam.hip",
            "knn.hip", "mlp.hip", "density.hip", "peaks.hip"]
 
 ARCH = os.environ.get("GSMI_ARCH", "gfx950")

@@ -726,6 +726,32 @@ def test_chunk_items_exact(ops, n_tiles, empty):
     np.testing.assert_array_equal(i_d.cpu().numpy()[:total], np.repeat(np.arange(n_tiles), cnt))
 
 
+@pytest.mark.parametrize("n_tiles", [1, 5000, 65536, 70001])
+def test_tile_order_is_longest_first_permutation(ops, n_tiles):
+    """gs_tile_order: a permutation of the tiles whose cost classes
+    floor(log2(len + 1)) never increase along it (one work-group up to 65536
+    tiles, three grid launches above)."""
+    say("tile order", n_tiles)
+    rng = np.random.default_rng(n_tiles + 3)
+    lens = rng.integers(0, 3000, n_tiles)
+    lens[rng.uniform(size=n_tiles) < 0.3] = 0
+    lens[rng.uniform(size=n_tiles) < 0.01] = 200000
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    ranges = np.stack([starts, starts + lens], 1).astype(np.uint32)
+    r_d = torch.as_tensor(ranges.view(np.int32)).cuda()
+    o_d = torch.full((n_tiles,), -1, dtype=torch.int32, device="cuda")
+    lib = ops._lib.load()
+    ws = torch.empty(int(lib.gs_tile_order_workspace_bytes(n_tiles)), dtype=torch.uint8,
+                     device="cuda")
+    ops.call("gs_tile_order", r_d.data_ptr(), n_tiles, ws.data_ptr(), ws.numel(),
+             o_d.data_ptr(), ops.stream_handle())
+    torch.cuda.synchronize()
+    order = o_d.cpu().numpy()
+    np.testing.assert_array_equal(np.sort(order), np.arange(n_tiles))
+    cls = np.floor(np.log2(lens[order] + 1.0)).astype(np.int64)
+    assert np.all(np.diff(cls) <= 0)
+
+
 def _blob_mask(rng, H, W, coverage=0.65):
     """A foreground mask shaped like an object's silhouette: a thresholded
     sum of a few dozen wide Gaussian blobs, cut to about `coverage` of the
