@@ -41,9 +41,12 @@ constexpr int kSortPer = 8;
 constexpr int kSortItems = kSortThreads * kSortPer;   // keys per radix block
 constexpr int kRadixBits = 8;      // digit width of the depth passes and of most tile passes
 constexpr int kRadixBitsMax = 9;   // tile keys of 17-18 bits: two 9-bit passes instead of three
-// presort key fields: depth bits 0-31, slot 32-41, tile count 42-63
-constexpr int kKeySlotShift = 32, kKeyTilesShift = 42;
-constexpr uint64_t kKeySlotMask = (1ull << (kKeyTilesShift - kKeySlotShift)) - 1;
+// emission record word 1: bbox width in tiles, and this flag when the whole
+// bbox is listed (word 2 then holds the tile count instead of a mask)
+constexpr uint32_t kWholeBbox = 1u << 31;
+// per-pair tile counts kept as one byte; kNtEscape: look the count up in the
+// emission record
+constexpr uint32_t kNtEscape = 255;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kRadixMax = 1 << kRadixBitsMax;
 
@@ -53,7 +56,7 @@ struct BinSortLayout {
   int64_t nb_scan, nb_sort, nb_pairs;
   size_t off_block_sums, off_count, off_keys_alt, off_vals_alt, off_emit_alt, off_hist, off_rowtot,
       off_erec;
-  size_t off_pkeys[2], off_pvals[2], total;
+  size_t off_pkeys[2], off_pvals[2], off_nt8, total;
 };
 
 static BinSortLayout layout(int64_t m, int64_t cap) {
@@ -73,9 +76,10 @@ static BinSortLayout layout(int64_t m, int64_t cap) {
   L.off_rowtot = o; o += align256(sizeof(uint32_t) * kRadixMax);
   L.off_erec = o; o += align256(sizeof(uint32_t) * 4 * mm);
   for (int b = 0; b < 2; ++b) {
-    L.off_pkeys[b] = o; o += align256(sizeof(uint64_t) * mm);
+    L.off_pkeys[b] = o; o += align256(sizeof(uint32_t) * mm);
     L.off_pvals[b] = o; o += align256(sizeof(uint32_t) * mm);
   }
+  L.off_nt8 = o; o += align256(mm);
   L.total = o;
   return L;
 }
@@ -189,9 +193,12 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* sm_waves /*[4]*/, T& t
 
 // ------------------------------------------------------------ scan of n_tiles
 
-// Pairs in depth order: their tile counts are the top bits of the presorted
-// keys.
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint64_t* __restrict__ pkey,
+// Pairs in depth order (perm: pair index at each depth-ordered position):
+// their tile counts from the one-byte copies (a random gather from a small
+// array), the emission record for the rare count of kNtEscape or more.
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t* __restrict__ perm,
+                                                              const uint8_t* __restrict__ nt8,
+                                                              const uint4* __restrict__ erec,
                                                               int64_t m,
                                                               int64_t* __restrict__ block_sums) {
   __shared__ int64_t sm[4];
@@ -200,7 +207,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint64_t* __
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
     int64_t i = base + k * kScanThreads + threadIdx.x;
-    if (i < m) sum += (int64_t)(pkey[i] >> kKeyTilesShift);
+    if (i < m) {
+      const uint32_t p = perm[i];
+      uint32_t c = nt8[p];
+      if (c == kNtEscape) c = erec[p].z;
+      sum += (int64_t)c;
+    }
   }
   int64_t total;
   block_exclusive_scan<int64_t>(sum, sm, total);
@@ -256,8 +268,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t* __restrict__
 // ------------------------------------------------------------ emit
 
 // Block b handles depth-ordered positions b*kScanItems ...: pair perm[i]
-// with presorted key pkey[i] = (tiles << 42) | (slot << 32) | depth bits and
-// emission record erec[perm[i]] (k_depth_keys): one 16-byte gather per pair.
+// with depth bits pkey[i] and emission record erec[perm[i]] (k_depth_keys),
+// which also gives its tile count: one 16-byte gather per pair.
 // pair_first (optional) is [m][2]: word 0 of a pair with tiles > 0 receives
 // the emission index of its first entry.
 // The block's duplicates are expanded kEmitRound at a time: each thread
@@ -266,7 +278,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t* __restrict__
 // (coalesced key and value writes, no search).
 template <typename K>
 __global__ __launch_bounds__(kScanThreads) void k_emit(
-    const uint4* __restrict__ erec, const uint64_t* __restrict__ pkey,
+    const uint4* __restrict__ erec, const uint32_t* __restrict__ pkey,
     const uint32_t* __restrict__ perm, int64_t m,
     const int64_t* __restrict__ block_offsets, int64_t cap, int tiles_x, int tiles_per_slot,
     K* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ pair_first,
@@ -290,15 +302,16 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
     int64_t i = base + li;
     int nt = 0;
     if (i < m) {
-      const uint64_t key = pkey[i];
-      nt = (int)(key >> kKeyTilesShift);
+      const uint32_t p = perm[i];
+      const uint4 e = erec[p];
+      const bool whole = (e.y & kWholeBbox) != 0u;
+      const uint64_t mask = whole ? 0ull : (((uint64_t)e.w << 32) | e.z);
+      nt = whole ? (int)e.z : __popcll(mask);
       if (nt > 0) {
-        const uint32_t p = perm[i];
-        const uint4 e = erec[p];
         s_base[li] = e.x;
-        s_span[li] = e.y;
-        s_mask[li] = ((uint64_t)e.w << 32) | e.z;
-        s_depth[li] = (uint32_t)key;
+        s_span[li] = e.y & ~kWholeBbox;
+        s_mask[li] = mask;
+        s_depth[li] = pkey[i];
         s_pair[li] = p;
       }
     }
@@ -364,17 +377,15 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
 
 // ------------------------------------------------------------ depth presort
 
-// key = (tiles << 42) | (slot << 32) | depth bits (the first radix pass
-// takes the pair index i as its value);
-// count[0] = m.  Depths of visible pairs are positive, so their bits order
-// as the floats; the passes sort the low 32 bits only, the pair's tile count
-// and slot ride along for the scan and the emission.  tiles is the number of
-// listed tiles: the set bits of support_tile_mask for a bbox of up to
-// kMaskTiles tiles, else the whole bbox (mask 0 in the emission record).
-// pair_count (optional) receives the same count per pair.  A pair with
-// tiles > 0 gets its emission record erec[i] = (index of its bbox's first
-// tile slot * tiles_per_slot + ty0 * tiles_x + tx0, bbox width, mask low
-// and high words).
+// key = depth bits (the first radix pass takes the pair index i as its
+// value); count[0] = m.  Depths of visible pairs are positive, so their bits
+// order as the floats.  Every pair gets its emission record erec[i] =
+// (index of its bbox's first tile: slot * tiles_per_slot + ty0 * tiles_x +
+// tx0, bbox width, mask low and high words): the listed tiles are the set
+// bits of support_tile_mask for a bbox of up to kMaskTiles tiles; a larger
+// bbox is listed whole (width | kWholeBbox, tile count, 0); a pair that lists
+// no tile gets zeros.  nt8[i] = min(tile count, kNtEscape); pair_count
+// (optional) receives the count.
 // Also clears the n_range_words words of the tile ranges (grid-stride), so
 // the bin/sort needs no separate fill before k_ranges writes them.
 __global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ rec,
@@ -382,7 +393,8 @@ __global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ re
                                                    const uint2* __restrict__ tile_bbox, int tw,
                                                    int th, int tiles_x, int tiles_per_slot,
                                                    int64_t m,
-                                                   uint64_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ keys,
+                                                   uint8_t* __restrict__ nt8,
                                                    uint4* __restrict__ erec,
                                                    uint32_t* __restrict__ pair_count,
                                                    int64_t* __restrict__ count,
@@ -393,22 +405,26 @@ __global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ re
   if (i == 0) count[0] = m;
   if (i >= m) return;
   const float* r = rec + i * GS_REC_STRIDE;
-  uint64_t nt = (uint64_t)max(n_tiles[i], 0);
-  const uint32_t slot = __float_as_uint(r[10]);
+  uint32_t nt = (uint32_t)max(n_tiles[i], 0);
+  uint4 e = make_uint4(0u, 0u, 0u, 0u);
   if (nt > 0) {
+    const uint32_t slot = __float_as_uint(r[10]);
     const uint2 bb = tile_bbox[i];
     const int tx0 = (int)(bb.x & 0xffff), ty0 = (int)(bb.x >> 16), tx1 = (int)(bb.y & 0xffff);
-    uint64_t mask = 0;
-    if (nt <= (uint64_t)kMaskTiles) {
-      mask = support_tile_mask(r, tx0, ty0, tx1, (int)(bb.y >> 16), tw, th);
-      nt = (uint64_t)__popcll(mask);
+    const uint32_t first = slot * (uint32_t)tiles_per_slot + (uint32_t)(ty0 * tiles_x + tx0);
+    const uint32_t span = (uint32_t)(tx1 - tx0 + 1);
+    if (nt <= (uint32_t)kMaskTiles) {
+      const uint64_t mask = support_tile_mask(r, tx0, ty0, tx1, (int)(bb.y >> 16), tw, th);
+      nt = (uint32_t)__popcll(mask);
+      if (nt > 0) e = make_uint4(first, span, (uint32_t)mask, (uint32_t)(mask >> 32));
+    } else {
+      e = make_uint4(first, span | kWholeBbox, nt, 0u);
     }
-    erec[i] = make_uint4(slot * (uint32_t)tiles_per_slot + (uint32_t)(ty0 * tiles_x + tx0),
-                         (uint32_t)(tx1 - tx0 + 1), (uint32_t)mask, (uint32_t)(mask >> 32));
   }
-  if (pair_count) pair_count[2 * i + 1] = (uint32_t)nt;
-  keys[i] = (nt << kKeyTilesShift) | ((uint64_t)slot << kKeySlotShift) |
-            (uint64_t)__float_as_uint(r[9]);
+  erec[i] = e;
+  nt8[i] = (uint8_t)min(nt, kNtEscape);
+  if (pair_count) pair_count[2 * i + 1] = nt;
+  keys[i] = __float_as_uint(r[9]);
 }
 
 // ------------------------------------------------------------ radix sort
@@ -743,7 +759,7 @@ __global__ __launch_bounds__(256) void k_ranges(const K* __restrict__ keys,
 template <typename K>
 static gs_status tile_phase(K* k0, K* k1, uint32_t* v0, uint32_t* v1, uint32_t* e0, uint32_t* e1,
                             int key_shift, int rb, int passes, const uint4* erec,
-                            const uint64_t* pkey, const uint32_t* pval, int64_t m,
+                            const uint32_t* pkey, const uint32_t* pval, int64_t m,
                             const int64_t* block_sums, int64_t cap, int tiles_x,
                             int tiles_per_slot, uint32_t* pair_first, const int64_t* count,
                             const BinSortLayout& L, uint32_t* hist, uint32_t* rowtot,
@@ -825,8 +841,8 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   const int tiles_y = (int)ceil_div(tiling->height, tiling->tile_h);
   const int64_t tiles_per_slot = (int64_t)tiles_x * tiles_y;
   const int64_t n_tiles_all = tiles_per_slot * views->n_slots;
-  GS_REQUIRE(tiles_per_slot < (int64_t(1) << (64 - kKeyTilesShift)) && views->n_slots <= (int)kKeySlotMask + 1,
-             "gs_bin_sort: %lld tiles per slot or %d slots exceed the key fields",
+  GS_REQUIRE(n_tiles_all <= (int64_t)0xFFFFFFFFll,
+             "gs_bin_sort: %lld tiles per slot x %d slots exceed 32-bit tile indices",
              (long long)tiles_per_slot, views->n_slots);
   // passes over the tile bits of the keys (the depth order comes from the
   // presort of the pairs)
@@ -858,13 +874,14 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   }
   // depth presort of the m pairs: 4 stable passes over the depth bits,
   // ping-pong ending in buffer 0
-  uint64_t* pk[2] = {(uint64_t*)(w + L.off_pkeys[0]), (uint64_t*)(w + L.off_pkeys[1])};
+  uint32_t* pk[2] = {(uint32_t*)(w + L.off_pkeys[0]), (uint32_t*)(w + L.off_pkeys[1])};
+  uint8_t* nt8 = (uint8_t*)(w + L.off_nt8);
   uint32_t* pv[2] = {(uint32_t*)(w + L.off_pvals[0]), (uint32_t*)(w + L.off_pvals[1])};
   int64_t* count_pairs = count + 1;
   uint4* erec = (uint4*)(w + L.off_erec);
   hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)ceil_div(m, 256)), dim3(256), 0, s, proj->rec,
                      proj->n_tiles, (const uint2*)proj->tile_bbox, tiling->tile_w,
-                     tiling->tile_h, tiles_x, (int)tiles_per_slot, m, pk[0], erec,
+                     tiling->tile_h, tiles_x, (int)tiles_per_slot, m, pk[0], nt8, erec,
                      pair_first, count_pairs, tile_ranges, 2 * n_tiles_all);
   GS_LAUNCH_CHECK("gs_bin_sort/depth_keys");
   for (int p = 0; p < 4; ++p) {
@@ -881,8 +898,8 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
     GS_LAUNCH_CHECK("gs_bin_sort/depth_scatter");
   }
   // duplicates in depth order, then stable passes over the tile bits only
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s, pk[0], m,
-                     block_sums);
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)L.nb_scan), dim3(kScanThreads), 0, s, pv[0],
+                     (const uint8_t*)nt8, (const uint4*)erec, m, block_sums);
   GS_LAUNCH_CHECK("gs_bin_sort/scan_reduce");
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, block_sums, L.nb_scan,
                      dup_capacity, status, count);
