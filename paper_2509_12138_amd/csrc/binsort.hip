@@ -52,6 +52,28 @@ constexpr int kRadixMax = 1 << kRadixBitsMax;
 
 static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Stages src[0, n) into LDS at dst[at(i)] with 256 threads, kStageBatch
+// loads per thread in flight at a time (a plain loop waits for each load
+// before its LDS store).
+constexpr int kStageBatch = 8;
+
+template <typename T, typename At>
+__device__ __forceinline__ void stage_to_lds(const T* __restrict__ src, int n, T* dst, At at) {
+  for (int i0 = threadIdx.x; i0 < n; i0 += 256 * kStageBatch) {
+    T v[kStageBatch];
+#pragma unroll
+    for (int q = 0; q < kStageBatch; ++q) {
+      const int i = i0 + q * 256;
+      v[q] = i < n ? src[i] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < kStageBatch; ++q) {
+      const int i = i0 + q * 256;
+      if (i < n) dst[at(i)] = v[q];
+    }
+  }
+}
+
 struct BinSortLayout {
   int64_t nb_scan, nb_sort, nb_pairs;
   size_t off_block_sums, off_count, off_keys_alt, off_vals_alt, off_emit_alt, off_hist, off_rowtot,
@@ -238,7 +260,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t* __restrict__
   for (int64_t s0 = 0; s0 < nb; s0 += kTopLds) {
     const int n = (int)min((int64_t)kTopLds, nb - s0);
     int64_t* seg = block_sums + s0;
-    for (int i = threadIdx.x; i < n; i += kScanThreads) r[at(i)] = seg[i];
+    stage_to_lds(seg, n, r, at);
     __syncthreads();
     const int per = (n + kScanThreads - 1) / kScanThreads;
     const int b0 = min((int)threadIdx.x * per, n), b1 = min(b0 + per, n);
@@ -531,7 +553,7 @@ __global__ __launch_bounds__(256) void k_radix_rowscan_lds(uint32_t* __restrict_
   for (int64_t s0 = 0; s0 < nb_used; s0 += kRowLds) {
     const int n = (int)min((int64_t)kRowLds, nb_used - s0);
     uint32_t* seg = row + s0;
-    for (int i = threadIdx.x; i < n; i += 256) r[at(i)] = seg[i];
+    stage_to_lds(seg, n, r, at);
     __syncthreads();
     const int per = (n + 255) / 256;
     const int b0 = min((int)threadIdx.x * per, n), b1 = min(b0 + per, n);

@@ -117,8 +117,20 @@ __global__ __launch_bounds__(kChunkThreads) void k_chunk_scan(const uint32_t* __
   for (int64_t s0 = 0; s0 < n_tiles; s0 += kChunkScanOne) {
     const int n = (int)min(kChunkScanOne, n_tiles - s0);
     const uint32_t* rg = ranges + 2 * s0;
-    for (int t = j; t < n; t += kChunkThreads)
-      cnt[at(t)] = (rg[2 * t + 1] - rg[2 * t] + chunk - 1) / chunk;
+    // 8 loads per thread in flight at a time (a plain loop waits for each)
+    for (int t0 = j; t0 < n; t0 += kChunkThreads * 8) {
+      uint2 rr[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int t = t0 + q * kChunkThreads;
+        rr[q] = t < n ? reinterpret_cast<const uint2*>(rg)[t] : make_uint2(0u, 0u);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int t = t0 + q * kChunkThreads;
+        if (t < n) cnt[at(t)] = (rr[q].y - rr[q].x + chunk - 1) / chunk;
+      }
+    }
     __syncthreads();
     const int per = (n + kChunkThreads - 1) / kChunkThreads;
     const int b0 = min(j * per, n), b1 = min(b0 + per, n);
