@@ -91,7 +91,8 @@ static BinSortLayout layout(int64_t m, int64_t cap) {
   size_t o = 0;
   L.off_block_sums = o; o += align256(sizeof(int64_t) * (size_t)L.nb_scan);
   L.off_count = o; o += align256(sizeof(int64_t) * 2);
-  L.off_keys_alt = o; o += align256(sizeof(uint64_t) * (size_t)(cap > 0 ? cap : 1));
+  // 64-bit keys, or two 32-bit key arrays each starting 256-byte aligned
+  L.off_keys_alt = o; o += 2 * align256(sizeof(uint32_t) * (size_t)(cap > 0 ? cap : 1));
   L.off_vals_alt = o; o += align256(sizeof(uint32_t) * (size_t)(cap > 0 ? cap : 1));
   L.off_emit_alt = o; o += align256(sizeof(uint32_t) * (size_t)(cap > 0 ? cap : 1));
   L.off_hist = o; o += align256(sizeof(uint32_t) * (size_t)kRadixMax * (size_t)nb_hist);
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
         s_base[li] = e.x;
         s_span[li] = e.y & ~kWholeBbox;
         s_mask[li] = mask;
-        s_depth[li] = pkey[i];
+        if constexpr (sizeof(K) == 8) s_depth[li] = pkey[i];   // only 64-bit keys hold it
         s_pair[li] = p;
       }
     }
@@ -451,6 +452,49 @@ __global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ re
 
 // ------------------------------------------------------------ radix sort
 
+// Adds the RB-bit digits (key >> shift) of the keys [b0, min(b0 + kSortItems,
+// n)) to the LDS counts h (256 threads).  The counts do not depend on which
+// thread reads which key, so a 16-byte aligned array is read in whole
+// 16-byte words, all of a thread's loads issued before its first count.
+template <int RB, typename K>
+__device__ __forceinline__ void count_block(const K* __restrict__ keys, int64_t b0, int64_t n,
+                                            int shift, uint32_t* h) {
+  constexpr int KP = 16 / (int)sizeof(K);                  // keys per word
+  constexpr int WPT = kSortItems / KP / kSortThreads;     // words per thread
+  constexpr uint32_t R = 1u << RB;
+  const int t = threadIdx.x;
+  union Word {
+    uint4 v;
+    K k[KP];
+  };
+  if ((reinterpret_cast<uintptr_t>(keys) & 15) == 0) {
+    Word w[WPT];
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      const int64_t e0 = b0 + (int64_t)(q * kSortThreads + t) * KP;
+      if (e0 + KP <= n) {
+        w[q].v = *reinterpret_cast<const uint4*>(keys + e0);
+      } else {
+#pragma unroll
+        for (int k = 0; k < KP; ++k) w[q].k[k] = e0 + k < n ? keys[e0 + k] : K(0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < WPT; ++q) {
+      const int64_t e0 = b0 + (int64_t)(q * kSortThreads + t) * KP;
+#pragma unroll
+      for (int k = 0; k < KP; ++k)
+        if (e0 + k < n) atomicAdd(&h[(uint32_t)(w[q].k[k] >> shift) & (R - 1)], 1u);
+    }
+  } else {
+#pragma unroll 4
+    for (int k = 0; k < kSortPer; ++k) {
+      const int64_t i = b0 + k * kSortThreads + t;
+      if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (R - 1)], 1u);
+    }
+  }
+}
+
 // Digit counts of one block of keys: hist[digit][block].  RB-bit digits,
 // 1 << RB of them (each thread owns 1 << RB / 256).
 template <int RB, typename K>
@@ -469,11 +513,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K* __restrict
   // blocks past the count are never read (the row scans and the scatter
   // stop at the last block that holds keys)
   if (base >= n) return;
-#pragma unroll 4
-  for (int k = 0; k < kSortPer; ++k) {
-    int64_t i = base + k * kSortThreads + t;
-    if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (R - 1)], 1u);
-  }
+  count_block<RB>(keys, base, n, shift, h);
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < DPT; ++q) {
@@ -503,11 +543,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist_g(const K* __restri
   for (int g = 0; g < G; ++g) {
     const int64_t base = (b0 + g) * kSortItems;
     if (base >= n) break;
-#pragma unroll 4
-    for (int k = 0; k < kSortPer; ++k) {
-      const int64_t i = base + k * kSortThreads + t;
-      if (i < n) atomicAdd(&h[g * RP + ((uint32_t)(keys[i] >> shift) & (R - 1))], 1u);
-    }
+    count_block<RB>(keys, base, n, shift, h + g * RP);
   }
   __syncthreads();
   for (int idx = t; idx < G * R; idx += kSortThreads) {
@@ -638,14 +674,20 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   uint32_t val[kSortPer], val2[kSortPer];
   uint32_t rank[kSortPer];                 // position among the block's items of its digit
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // all rounds' loads first: the barriers of the ranking below would
+  // otherwise hold each round's load until the round before it is ranked
 #pragma unroll
   for (int r = 0; r < kSortPer; ++r) {
-    const int b = r & 1;
     const int64_t i = base + r * kSortThreads + t;
     const bool valid = i < n;
     key[r] = valid ? kin[i] : (K)0;
     val[r] = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
     if (TWO) val2[r] = valid ? vin2[i] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kSortPer; ++r) {
+    const int b = r & 1;
+    const bool valid = base + r * kSortThreads + t < n;
     const uint32_t d = (uint32_t)(key[r] >> shift) & (R - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -935,7 +977,8 @@ gs_status gs_bin_sort(const gs_projected* proj, const gs_views* views, const gs_
   }
   // no keys asked for: 32-bit tile keys in the two halves of keys_alt
   uint32_t* t0 = reinterpret_cast<uint32_t*>(keys_alt);
-  uint32_t* t1 = t0 + dup_capacity;
+  uint32_t* t1 = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(keys_alt) +
+                                             align256(sizeof(uint32_t) * (size_t)dup_capacity));
   return tile_phase<uint32_t>(t0, t1, v0, v1, e0, e1, 0, rb, passes, erec, pk[0], pv[0], m,
                               block_sums, dup_capacity, tiles_x, (int)tiles_per_slot, pair_first,
                               count, L, hist, rowtot, tile_ranges, s);
