@@ -59,8 +59,12 @@ def test_graph_replay_matches_eager(parts):
     from paper_2509_12138_amd.train import BatchedTrainer
     prts, cams = parts
     runs = {}
-    for graphs in (False, True):
-        bt = BatchedTrainer(prts, cams, views_per_part=2, graphs=graphs, order_seed=3)
+    # (graphs, deterministic): the atomic step eager and replayed, and the
+    # eager step with fixed-order gradient sums as the measure of the atomic
+    # sums' summation-order noise
+    for graphs, det in ((False, False), (True, False), ("det", True)):
+        bt = BatchedTrainer(prts, cams, views_per_part=2, graphs=graphs is True, order_seed=3,
+                            deterministic=det)
         bt.fit_capacity()
         losses, m1 = [], None
         for s in range(10):
@@ -77,9 +81,17 @@ def test_graph_replay_matches_eager(parts):
     le, lg = runs[False][0], runs[True][0]
     np.testing.assert_allclose(lg, le, rtol=2e-4, atol=1e-7)
     assert runs[True][2] == runs[False][2] == 10
+    # first Adam moments after step 1 (0.1 x the gradient): the atomic sums'
+    # order differs from run to run, so the replay may differ from the eager
+    # run by that noise, which the eager run's distance from the fixed-order
+    # run measures (it dominates in the rotation gradients, sums of terms
+    # that nearly cancel); a wrong replay would differ at the gradients' own
+    # scale
     for k in runs[False][1]:
-        a, b = runs[False][1][k], runs[True][1][k]
-        assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a) + 1e-12, k
+        a, b, d = runs[False][1][k], runs[True][1][k], runs["det"][1][k]
+        noise = np.linalg.norm(a - d)
+        assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(a) + 1e-12 + 2.0 * noise, k
+        assert noise <= np.linalg.norm(a) + 1e-12, k
 
 
 def test_device_adam_schedule_matches_oracle(gpu):
