@@ -557,9 +557,10 @@ template <int RB, typename K>
 static void launch_hist(const K* keys, const int64_t* count, int shift, int64_t nb,
                         uint32_t* hist, hipStream_t s) {
   constexpr int G = 8;
-  // (for 8-bit digits the grouped kernel measured slower: 49 vs 41 us a pass
-  // over 13.3M keys; for 9-bit digits 84 against 164 us over 20.7M)
-  if ((RB > kRadixBits && nb >= 2048) || nb >= 16384)
+  // (grouped from 2048 blocks: with the 16-byte key loads also for 8-bit
+  // digits, 4 passes over 13.3M depth keys 0.121 -> 0.105 ms; 9-bit digits
+  // over 20.7M keys 0.164 -> 0.084 ms before those loads)
+  if (nb >= 2048)
     hipLaunchKernelGGL((k_radix_hist_g<RB, G, K>), dim3((unsigned)((nb + G - 1) / G)),
                        dim3(kSortThreads), 0, s, keys, count, shift, nb, hist);
   else
