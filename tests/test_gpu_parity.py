@@ -163,6 +163,28 @@ def test_bin_sort_bit_exact(ops, m, S, tile, W, H, seed, span):
         np.testing.assert_array_equal(bufs.ranges.cpu().numpy().view(np.uint32), ranges)
 
 
+@pytest.mark.parametrize("S", [1, 2])
+def test_bin_sort_one_tile_per_slot(ops, S):
+    """Images of a single tile: one slot needs no radix pass over tile bits
+    (the emission is the result), two slots need one 1-bit pass; with and
+    without the 64-bit keys."""
+    say("bin_sort one tile per slot", S)
+    m = 3000 * S
+    tb, nt, depth, slot, sup = synthetic_pairs(m, 1, 1, S, 11 + S, (16, 16))
+    keys, ids, ranges = oracle.bin_sort(tb, nt, depth, slot, 1, 1, S,
+                                        sup=sup.astype(np.float64), tile=(16, 16))
+    K = len(ids)
+    assert K > 0
+    for keep in (True, False):
+        bufs, st, req = run_binsort(ops, tb, nt, depth, slot, sup, 16, 16, (16, 16), S,
+                                    cap=K + 5, keep_keys=keep)
+        assert st == 0 and req == K
+        if keep:
+            np.testing.assert_array_equal(bufs.keys[:K].cpu().numpy().view(np.uint64), keys)
+        np.testing.assert_array_equal(bufs.ids[:K].cpu().numpy().view(np.uint32), ids)
+        np.testing.assert_array_equal(bufs.ranges.cpu().numpy().view(np.uint32), ranges)
+
+
 @pytest.mark.parametrize("m,tile,W,H,S,cap", [(1100000, (8, 8), 3840, 2160, 1, 5_000_000),
                                               (600000, (16, 16), 1920, 1080, 3, 5_000_000),
                                               (300000, (16, 16), 1920, 1080, 2, 70_000_000)])
