@@ -310,7 +310,7 @@ __global__ __launch_bounds__(kScanThreads) void k_emit(
   __shared__ uint32_t s_base[kScanItems];     // tile index of the bbox's first tile
   __shared__ uint32_t s_span[kScanItems];     // bbox width in tiles
   __shared__ uint64_t s_mask[kScanItems];
-  __shared__ uint32_t s_depth[kScanItems];
+  __shared__ uint32_t s_depth[sizeof(K) == 8 ? kScanItems : 1];   // only 64-bit keys use it
   __shared__ uint32_t s_pair[kScanItems];
   __shared__ uint16_t s_owner[kEmitRound];
   __shared__ uint32_t s_w[4];
